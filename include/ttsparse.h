@@ -1,0 +1,187 @@
+/*
+ * ttsparse -- sparse tensor-train decomposition on AMD Instinct MI355X (gfx950).
+ *
+ * C-ABI of libttsparse.so.  Implements the method of arXiv 1908.02721
+ * ("Faster Tensor Train Decomposition for Sparse Data"):
+ *   - an exact sparse TT built by parallel-vector rounding of each mode's sparse
+ *     unfolding: the TT-SVD sweep (Algorithm 1) with every truncated SVD replaced
+ *     by Deparallelisation (Algorithm 3, Sec. 2.4);
+ *   - TT-rounding of that TT (Algorithm 2, run mirrored: a left-to-right QR sweep,
+ *     then a right-to-left delta-truncated SVD sweep; fixed-rank truncation as in
+ *     Sec. 3.4);
+ *   - evaluation of TT entries at given coordinates (Sec. 2.3, entry formula) and
+ *     its gradient with respect to every core.
+ *
+ * Conventions.
+ *   Indices are 0-based.  Tensors are linearised row-major, last mode fastest (the
+ *   vectorisation definition of Sec. 2.2).  Core k (1..d) is a dense row-major
+ *   array [r_{k-1}][n_k][r_k] with r_0 = r_d = 1, i.e. unfold_2 of the core stored
+ *   row-major.  "Device" pointers are HIP device memory; "host" pointers are
+ *   ordinary memory.  `stream` is a hipStream_t (NULL = the null stream).
+ *
+ * Errors.  Every call returns a tt_status; no exception crosses the ABI.  On error
+ * no result is returned (*out = NULL) and nothing leaks.  Argument errors are found
+ * on the host before any launch; data errors (index out of range, non-finite value,
+ * repeated coordinate) are found on the device.  tt_last_error() returns a message
+ * for the calling thread's most recent failure.
+ */
+#ifndef TTSPARSE_H
+#define TTSPARSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAX_D 64
+
+typedef enum {
+  TT_OK = 0,
+  TT_ERR_ARG = 1,        /* invalid argument (host check) */
+  TT_ERR_INDEX = 2,      /* a coordinate is outside [0, n_k) */
+  TT_ERR_DUPLICATE = 3,  /* the same coordinate appears twice among the nonzeros */
+  TT_ERR_NONFINITE = 4,  /* a value is NaN or infinite */
+  TT_ERR_EMPTY = 5,      /* no nonzero is left after dropping explicit zeros */
+  TT_ERR_TOO_LARGE = 6,  /* a size limit of this implementation is exceeded */
+  TT_ERR_NOMEM = 7,      /* device allocation failed or device_mem_budget exceeded */
+  TT_ERR_DEVICE = 8      /* a HIP runtime call failed */
+} tt_status;
+
+typedef enum {
+  TT_FP64 = 0,          /* every step in binary64 */
+  TT_FP32 = 1,          /* dense contractions in binary32 (MFMA, FP32 accumulate);
+                           R factors, Gram and SVD steps in binary64 */
+  TT_BF16_FP32ACC = 2   /* dense contractions with bfloat16 operands on MFMA,
+                           FP32 accumulate; R factors, Gram and SVD in binary64 */
+} tt_precision;
+
+typedef enum { TT_DTYPE_F64 = 0, TT_DTYPE_F32 = 1 } tt_dtype;
+
+typedef struct {
+  int32_t precision;          /* tt_precision */
+  int32_t max_rank;           /* 0: truncate by eps; > 0: fixed-rank truncation
+                                 (keep min(max_rank, #nonzero sigma)), eps ignored */
+  int32_t keep_intermediates; /* 1: keep per-level maps for tt_get_level */
+  int32_t sparse_only;        /* 1: stop after the exact sparse TT (no rounding);
+                                 tt_get_core then returns the exact cores */
+  uint64_t device_mem_budget; /* 0: unlimited; else TT_ERR_NOMEM when the working
+                                 set of a stage would exceed it */
+  /* Optional device allocator.  NULL: stream-ordered hipMallocAsync from the
+     device's default pool.  alloc returns NULL on failure. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} tt_options;
+
+typedef struct tt_result_s* tt_result; /* opaque, owned by the library */
+
+/* Fill *opt with the defaults: FP64, eps truncation, no intermediates, full
+   rounding, no budget, the library's own allocator. */
+void tt_options_default(tt_options* opt);
+
+/*
+ * Decompose the sparse tensor given in COO form.
+ *   d     : order, 2 <= d <= TT_MAX_D
+ *   dims  : host int64[d], 1 <= n_k <= 2^31-1; the packed coordinate
+ *           sum_k ceil(log2 n_k) must not exceed 63 bits (else TT_ERR_TOO_LARGE)
+ *   nnz   : number of stored entries, 0 <= nnz < 2^31
+ *   idx   : device int32[nnz][d], row-major, 0-based (borrowed, not modified)
+ *   val   : device double[nnz] (borrowed, not modified).  Explicit zeros (+-0) are
+ *           dropped; NaN/Inf -> TT_ERR_NONFINITE; repeated coordinate among the
+ *           nonzeros -> TT_ERR_DUPLICATE; out of range -> TT_ERR_INDEX (checked in
+ *           that order of precedence).
+ *   eps   : relative Frobenius tolerance, 0 <= eps < 1.  The result B satisfies
+ *           ||A - B||_F <= eps ||A||_F (Algorithm 2, Theorem 9), up to round-off;
+ *           eps = 0 drops only zero singular values.
+ *   opt   : NULL for the defaults
+ *   out   : receives the result handle; release it with tt_free
+ * All work is enqueued on `stream`; the call waits for its own small device-to-
+ * host counts (one or two per level and per bond) and returns when the result
+ * is complete.
+ */
+tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
+                              const double* val, double eps, const tt_options* opt, void* stream,
+                              tt_result* out);
+
+/* Final TT-ranks, host int64[d+1] (r_0 = r_d = 1). */
+tt_status tt_get_ranks(tt_result r, int64_t* ranks);
+
+/* Core k (1..d): a device pointer to [r_{k-1}][n_k][r_k], borrowed until tt_free,
+   and its dtype (tt_dtype; FP64 in TT_FP64 mode, FP32 otherwise). */
+tt_status tt_get_core(tt_result r, int32_t k, const void** dev_ptr, int32_t* dtype);
+
+/* Summary: host_info[0] = nonzeros kept, [1] = rounded (0/1), [2] = d;
+   norm = ||A||_F; delta = per-bond threshold eps*||A||_F/sqrt(d-1). */
+tt_status tt_get_info(tt_result r, int64_t* host_info, double* norm, double* delta);
+
+/* Ranks of the exact sparse TT (beta_k, host int64[d+1]) and the ranks after the
+   left-to-right QR sweep (host int64[d+1]); either pointer may be NULL. */
+tt_status tt_get_sparse_ranks(tt_result r, int64_t* betas, int64_t* qr_ranks);
+
+/* Singular values met at bond b (1..d-1) in the right-to-left sweep, sorted
+   non-ascending (host, borrowed until tt_free), their count, and the discarded
+   sum of squares.  Not available with sparse_only. */
+tt_status tt_get_sigma(tt_result r, int32_t b, int64_t* count, const double** host_sigma,
+                       double* tail);
+
+/* Stage times in milliseconds (host_ms[TT_NUM_STAGES]), measured with HIP events
+   on the call's stream: ingest, sort, sparse levels, QR sweep, SVD sweep, total. */
+#define TT_NUM_STAGES 6
+tt_status tt_get_times(tt_result r, double* host_ms);
+
+/*
+ * Level k (1..d-1) of the exact sparse stage (needs keep_intermediates):
+ *   ncols      : number of unfolding columns (nnz_{k+1})
+ *   beta       : number of distinct (non-parallel) columns, i.e. beta_k
+ *   col        : device int64[ncols], row-major linear index of each column's
+ *                suffix (i_{k+1},...,i_d); the column order is unspecified
+ *   g          : device int32[ncols], group of each column (transfer-matrix row);
+ *                groups are numbered by first occurrence in row-major column order
+ *   s          : device double[ncols], prefactor: column = s * N_k[:, g]
+ *   n_colptr   : device int64[beta+1]; n_row: device int32[]; n_val: device double[]
+ *                N_k in CSC form, rows rho = g_{k-1}*n_k + i_k ascending within a
+ *                column; the entry at the smallest row of every column is 1.
+ * All pointers are borrowed until tt_free.
+ */
+tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, const int64_t** col,
+                       const int32_t** g, const double** s, const int64_t** n_colptr,
+                       const int32_t** n_row, const double** n_val);
+
+/* Release a result (NULL is ignored). */
+void tt_free(tt_result r);
+
+/*
+ * Entries of a TT at m coordinates (entry formula of Sec. 2.3):
+ *   y_n = G1[0, i1, :] G2[:, i2, :] ... Gd[:, id, 0].
+ *   dims, ranks : host int64[d], int64[d+1] (ranks[0] = ranks[d] = 1, each <= 256)
+ *   cores       : host array of d device pointers, core k [r_{k-1}][n_k][r_k]
+ *   dtype       : tt_dtype of the cores and of y_out (FP32 or FP64)
+ *   idx         : device int32[m][d];  y_out: device [m] (caller-owned, written)
+ * Coordinates out of range -> TT_ERR_INDEX (checked on the device, y_out then
+ * undefined).
+ */
+tt_status tt_eval_entries(int32_t d, const int64_t* dims, const int64_t* ranks,
+                          const void* const* cores, int32_t dtype, int64_t m, const int32_t* idx,
+                          void* y_out, void* stream);
+
+/*
+ * Gradient of L = sum_n grad_y[n] * y_n with respect to every core:
+ *   dL/dG_k[a, i, b] = sum_{n: i_k^n = i} grad_y[n] * l_{k-1}^n[a] * r_{k+1}^n[b],
+ * l and r being the left and right partial products.  grad_cores: host array of d
+ * device pointers shaped like the cores (caller-owned, overwritten).  The result is
+ * deterministic (fixed-order reduction).
+ */
+tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                   const void* const* cores, int32_t dtype, int64_t m,
+                                   const int32_t* idx, const void* grad_y, void* const* grad_cores,
+                                   void* stream);
+
+const char* tt_status_string(tt_status s);
+const char* tt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTSPARSE_H */

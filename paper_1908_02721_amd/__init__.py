@@ -1,0 +1,226 @@
+"""Sparse tensor-train decomposition on MI355X (gfx950): Python binding of libttsparse.
+
+Method: arXiv 1908.02721, "Faster Tensor Train Decomposition for Sparse Data".
+Every step runs in the library's HIP kernels; this module only marshals
+arguments (PyTorch provides device memory and streams).
+
+    tt = decompose(idx, val, dims, eps)          # idx int32 [nnz, d], val float64 [nnz] on cuda
+    tt.ranks, tt.cores                            # cores [r_{k-1}, n_k, r_k]
+    y = EvalEntries.apply(idx, *cores)            # TT entries at idx, differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import STAGES, TTError
+
+__all__ = ["decompose", "TT", "eval_entries", "eval_entries_backward", "EvalEntries", "TTError", "library_path"]
+
+library_path = _lib.LIB_PATH
+
+
+def _stream_handle(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _CAI:
+    """A borrowed device buffer exposed through __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(int(x) for x in shape),
+                                         "typestr": typestr, "version": 2, "strides": None}
+
+
+_TYPESTR = {torch.float64: "<f8", torch.float32: "<f4", torch.int64: "<i8", torch.int32: "<i4"}
+
+
+def _copy_from_device(ptr: int, shape, dtype) -> torch.Tensor:
+    """Owning torch copy of a library-owned device buffer."""
+    n = 1
+    for x in shape:
+        n *= int(x)
+    if n == 0 or not ptr:
+        return torch.empty(tuple(shape), dtype=dtype, device="cuda")
+    view = torch.as_tensor(_CAI(ptr, shape, _TYPESTR[dtype]), device="cuda")
+    return view.clone()
+
+
+class TT:
+    """Result of ``decompose``: owns the library handle until garbage-collected."""
+
+    def __init__(self, handle: ctypes.c_void_p, dims):
+        self._h = handle
+        self.dims = tuple(int(x) for x in dims)
+        self.d = len(self.dims)
+        L = _lib.load()
+        r = (ctypes.c_int64 * (self.d + 1))()
+        _lib.check(L.tt_get_ranks(self._h, r))
+        self.ranks = [int(x) for x in r]
+        info = (ctypes.c_int64 * 3)()
+        nrm, dl = ctypes.c_double(), ctypes.c_double()
+        _lib.check(L.tt_get_info(self._h, info, ctypes.byref(nrm), ctypes.byref(dl)))
+        self.nnz, self.rounded = int(info[0]), bool(info[1])
+        self.norm, self.delta = nrm.value, dl.value
+        b = (ctypes.c_int64 * (self.d + 1))()
+        q = (ctypes.c_int64 * (self.d + 1))()
+        _lib.check(L.tt_get_sparse_ranks(self._h, b, q if self.rounded else None))
+        self.betas = [int(x) for x in b]
+        self.qr_ranks = [int(x) for x in q] if self.rounded else None
+        t = (ctypes.c_double * _lib.NUM_STAGES)()
+        _lib.check(L.tt_get_times(self._h, t))
+        self.times_ms = dict(zip(STAGES, (float(x) for x in t)))
+        self._cores = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().tt_free(h)
+            except Exception:  # interpreter shutdown
+                pass
+            self._h = None
+
+    @property
+    def cores(self):
+        """Owning torch copies of the cores, [r_{k-1}, n_k, r_k] each."""
+        if self._cores is None:
+            L = _lib.load()
+            out = []
+            for k in range(1, self.d + 1):
+                p = ctypes.c_void_p()
+                dt = ctypes.c_int32()
+                _lib.check(L.tt_get_core(self._h, k, ctypes.byref(p), ctypes.byref(dt)))
+                dtype = torch.float64 if dt.value == _lib.DTYPE_F64 else torch.float32
+                shape = (self.ranks[k - 1], self.dims[k - 1], self.ranks[k])
+                out.append(_copy_from_device(p.value, shape, dtype))
+            self._cores = out
+        return self._cores
+
+    def sigma(self, b: int):
+        """Singular values at bond b (1..d-1) and the discarded sum of squares."""
+        L = _lib.load()
+        cnt = ctypes.c_int64()
+        ptr = ctypes.POINTER(ctypes.c_double)()
+        tail = ctypes.c_double()
+        _lib.check(L.tt_get_sigma(self._h, b, ctypes.byref(cnt), ctypes.byref(ptr), ctypes.byref(tail)))
+        import numpy as np
+
+        sig = np.ctypeslib.as_array(ptr, shape=(cnt.value,)).copy() if cnt.value else np.zeros(0)
+        return sig, tail.value
+
+    def level(self, k: int):
+        """Level k (1..d-1) of the sparse stage (needs keep_intermediates=True)."""
+        L = _lib.load()
+        ncols, beta = ctypes.c_int64(), ctypes.c_int64()
+        ptrs = [ctypes.c_void_p() for _ in range(6)]
+        _lib.check(L.tt_get_level(self._h, k, ctypes.byref(ncols), ctypes.byref(beta),
+                                  *[ctypes.byref(p) for p in ptrs]))
+        nc, bt = ncols.value, beta.value
+        colptr = _copy_from_device(ptrs[3].value, (bt + 1,), torch.int64)
+        nnz_n = int(colptr[-1].item()) if bt else 0
+        return {
+            "ncols": nc,
+            "beta": bt,
+            "col": _copy_from_device(ptrs[0].value, (nc,), torch.int64),
+            "g": _copy_from_device(ptrs[1].value, (nc,), torch.int32),
+            "s": _copy_from_device(ptrs[2].value, (nc,), torch.float64),
+            "n_colptr": colptr,
+            "n_row": _copy_from_device(ptrs[4].value, (nnz_n,), torch.int32),
+            "n_val": _copy_from_device(ptrs[5].value, (nnz_n,), torch.float64),
+        }
+
+
+def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision: str = "fp64",
+              max_rank: int = 0, keep_intermediates: bool = False, sparse_only: bool = False,
+              device_mem_budget: int = 0, stream=None) -> TT:
+    """Sparse TT decomposition of the COO tensor (idx int32 [nnz, d], val float64 [nnz], on cuda)."""
+    L = _lib.load()
+    if not (idx.is_cuda and val.is_cuda):
+        raise ValueError("idx and val must be cuda tensors")
+    if idx.dtype != torch.int32 or val.dtype != torch.float64:
+        raise TypeError("idx must be int32 and val float64")
+    idx = idx.contiguous()
+    val = val.contiguous()
+    d = len(dims)
+    nnz = int(val.numel())
+    if idx.numel() != nnz * d:
+        raise ValueError("idx must have shape [nnz, d]")
+    opt = _lib.tt_options()
+    L.tt_options_default(ctypes.byref(opt))
+    opt.precision = _lib.PRECISION[precision]
+    opt.max_rank = int(max_rank)
+    opt.keep_intermediates = int(bool(keep_intermediates))
+    opt.sparse_only = int(bool(sparse_only))
+    opt.device_mem_budget = int(device_mem_budget)
+    dims_a = (ctypes.c_int64 * d)(*[int(x) for x in dims])
+    h = ctypes.c_void_p()
+    st = L.tt_sparse_decompose(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                               float(eps), ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h))
+    _lib.check(st)
+    return TT(h, dims)
+
+
+def _core_args(cores):
+    d = len(cores)
+    dims = (ctypes.c_int64 * d)(*[int(c.shape[1]) for c in cores])
+    ranks = (ctypes.c_int64 * (d + 1))(*([int(c.shape[0]) for c in cores] + [int(cores[-1].shape[2])]))
+    ptrs = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+    return d, dims, ranks, ptrs
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.DTYPE_F64
+    if t.dtype == torch.float32:
+        return _lib.DTYPE_F32
+    raise TypeError("cores must be float32 or float64")
+
+
+def eval_entries(cores, idx: torch.Tensor, stream=None) -> torch.Tensor:
+    """y[n] = G1[0, i1, :] G2[:, i2, :] ... Gd[:, id, 0] for idx int32 [m, d] (cuda)."""
+    L = _lib.load()
+    cores = [c.contiguous() for c in cores]
+    dt = _dtype_code(cores[0])
+    if any(c.dtype != cores[0].dtype for c in cores):
+        raise TypeError("all cores must share one dtype")
+    idx = idx.contiguous()
+    m = idx.shape[0]
+    y = torch.empty(m, dtype=cores[0].dtype, device=cores[0].device)
+    d, dims, ranks, ptrs = _core_args(cores)
+    _lib.check(L.tt_eval_entries(d, dims, ranks, ptrs, dt, m, ctypes.c_void_p(idx.data_ptr()),
+                                 ctypes.c_void_p(y.data_ptr()), _stream_handle(stream)))
+    return y
+
+
+def eval_entries_backward(cores, idx: torch.Tensor, grad_y: torch.Tensor, stream=None):
+    """Gradients of sum_n grad_y[n] * y_n with respect to every core."""
+    L = _lib.load()
+    cores = [c.contiguous() for c in cores]
+    dt = _dtype_code(cores[0])
+    idx = idx.contiguous()
+    grad_y = grad_y.contiguous().to(cores[0].dtype)
+    grads = [torch.empty_like(c) for c in cores]
+    d, dims, ranks, ptrs = _core_args(cores)
+    gptrs = (ctypes.c_void_p * d)(*[g.data_ptr() for g in grads])
+    _lib.check(L.tt_eval_entries_backward(d, dims, ranks, ptrs, dt, idx.shape[0], ctypes.c_void_p(idx.data_ptr()),
+                                          ctypes.c_void_p(grad_y.data_ptr()), gptrs, _stream_handle(stream)))
+    return grads
+
+
+class EvalEntries(torch.autograd.Function):
+    """Differentiable sampled-entry evaluation: EvalEntries.apply(idx, *cores) -> y."""
+
+    @staticmethod
+    def forward(ctx, idx, *cores):
+        ctx.save_for_backward(idx, *cores)
+        return eval_entries(cores, idx)
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        idx, *cores = ctx.saved_tensors
+        grads = eval_entries_backward(cores, idx, grad_y)
+        return (None, *grads)

@@ -1,0 +1,564 @@
+// C-ABI of libttsparse: argument checks, the host loop over levels and bonds, and
+// result ownership.  Every step of the decomposition runs in the library's HIP
+// kernels; the host only sequences launches and reads back small counts.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "prim.hpp"
+#include "sparse.hpp"
+
+namespace tts {
+
+namespace {
+thread_local std::string g_last_error;
+thread_local DevStatus* g_host_status = nullptr;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+DevStatus* host_status() {
+  if (!g_host_status) {
+    void* p = nullptr;
+    TTS_HIP(hipHostMalloc(&p, sizeof(DevStatus), hipHostMallocDefault));
+    g_host_status = static_cast<DevStatus*>(p);
+  }
+  return g_host_status;
+}
+
+void configure_pool_once() {
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = std::numeric_limits<uint64_t>::max();
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  done[dev] = true;
+}
+
+uint32_t bits_for(uint64_t n) {  // bits to hold values 0..n-1
+  uint32_t b = 0;
+  while (b < 64 && (n - 1) >> b) ++b;
+  return b;
+}
+
+}  // namespace
+
+void fail(tt_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void* Allocator::get(size_t bytes) {
+  if (budget && in_use + bytes > budget)
+    fail(TT_ERR_NOMEM, "device_mem_budget exceeded (" + std::to_string(in_use + bytes) + " bytes needed)");
+  void* p = nullptr;
+  if (hook_alloc) {
+    p = hook_alloc(bytes, ctx);
+    if (!p) fail(TT_ERR_NOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    const hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      fail(TT_ERR_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
+    }
+  }
+  in_use += bytes;
+  peak = std::max(peak, in_use);
+  return p;
+}
+
+void Allocator::put(void* p, size_t bytes) {
+  if (!p) return;
+  if (hook_free)
+    hook_free(p, ctx);
+  else
+    (void)hipFreeAsync(p, stream);
+  in_use -= bytes;
+}
+
+struct LevelData {
+  uint32_t ncols = 0, beta = 0, nnz_n = 0;
+  DBuf<int64_t> col;
+  DBuf<int32_t> g;
+  DBuf<double> s;
+  DBuf<int64_t> colptr;
+  DBuf<int32_t> row;
+  DBuf<double> val;
+};
+
+}  // namespace tts
+
+struct tt_result_s {
+  tts::Allocator al;
+  int32_t d = 0;
+  std::vector<int64_t> dims;
+  int64_t nnz = 0;
+  double norm = 0.0, delta = 0.0;
+  int32_t rounded = 0;
+  std::vector<tts::LevelData> lev;
+  tts::DBuf<double> last_exact;
+  std::vector<int64_t> betas, qr_ranks, ranks;
+  std::vector<tts::DBuf<char>> cores;
+  int32_t dtype = TT_DTYPE_F64;
+  std::vector<std::vector<double>> sigma;
+  std::vector<double> tail;
+  double ms[TT_NUM_STAGES] = {};
+};
+
+namespace tts {
+namespace {
+
+struct Events {
+  hipEvent_t e[TT_NUM_STAGES + 1] = {};
+  Events() {
+    for (auto& x : e) TTS_HIP(hipEventCreate(&x));
+  }
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+void sync_status(DevStatus* d_st, hipStream_t s) {
+  DevStatus* h = host_status();
+  TTS_HIP(hipMemcpyAsync(h, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+  TTS_HIP(hipStreamSynchronize(s));
+}
+
+// Exact sparse TT: ingest, sort, and parallel-vector rounding level by level.
+void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
+                  int total_bits, bool keep, hipStream_t s, Events& ev) {
+  Allocator* al = &R->al;
+  const int d = mi.d;
+  DBuf<DevStatus> st(al, 1);
+  TTS_HIP(hipMemsetAsync(st.get(), 0, sizeof(DevStatus), s));
+
+  // a1: ingest
+  DBuf<uint64_t> keys(al, nnz), vals(al, nnz);
+  launch_ingest(idx, val, nnz, mi, keys.get(), vals.get(), st.get(), s);
+  sync_status(st.get(), s);
+  {
+    const DevStatus* h = host_status();
+    if (h->err & kErrIndex) fail(TT_ERR_INDEX, "a coordinate is outside its mode range");
+    if (h->err & kErrNonfinite) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");
+    if (h->kept == 0) fail(TT_ERR_EMPTY, "no nonzero left after dropping explicit zeros");
+  }
+  const uint32_t kept = host_status()->kept;
+  R->nnz = kept;
+  TTS_HIP(hipEventRecord(ev.e[1], s));
+
+  // a2: one global stable sort by packed key; dropped entries (key ~0) go last
+  {
+    DBuf<uint64_t> kt(al, nnz), vt(al, nnz);
+    const int sort_bits = total_bits + (kept < nnz ? 1 : 0);
+    radix_sort_pairs(al, keys.get(), vals.get(), kt.get(), vt.get(), nnz, sort_bits, s);
+  }
+  TTS_HIP(hipEventRecord(ev.e[2], s));
+
+  // a3..a7: levels
+  DBuf<uint64_t> ekey = std::move(keys);
+  DBuf<uint32_t> erho;
+  DBuf<double> evals;
+  const double* evp = reinterpret_cast<const double*>(vals.get());
+  uint32_t nE = kept;
+  R->lev.resize(d - 1);
+  R->betas.assign(d + 1, 1);
+  for (int k = 1; k <= d - 1; ++k) {
+    const int kidx = k;           // first suffix mode, 0-based
+    const int sh = static_cast<int>(mi.bits[k - 1]);
+    const bool level1 = (k == 1);
+    DBuf<uint32_t> flag(al, nE), pos(al, nE), col_start(al, static_cast<size_t>(nE) + 1);
+    DBuf<double> norm_part;
+    if (level1) norm_part.reset(al, norm_partials_count(nE));
+    TTS_HIP(hipMemsetAsync(&st.get()->longcol, 0, sizeof(uint32_t), s));
+    launch_col_flags(ekey.get(), nE, sh, level1, !level1, evp, flag.get(), norm_part.get(), st.get(), s);
+    exclusive_scan_u32(al, flag.get(), pos.get(), nE, &st.get()->ncols, s);
+    launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), st.get(), s);
+    if (level1) launch_norm_final(norm_part.get(), norm_partials_count(nE), st.get(), s);
+    sync_status(st.get(), s);
+    const DevStatus hs = *host_status();
+    if (level1) {
+      if (hs.err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
+      R->norm = std::sqrt(hs.norm2);
+    }
+    const uint32_t ncols = hs.ncols;
+    bool sort_rows = !level1;
+    if (!level1 && hs.longcol) {
+      // long columns: order entries by (column, rho) with one composite sort
+      const uint64_t maxrho = static_cast<uint64_t>(R->betas[k - 1]) * mi.n[k - 1];
+      const int rbits = static_cast<int>(bits_for(maxrho));
+      const int cbits = static_cast<int>(bits_for(ncols));
+      if (rbits + cbits > 64) fail(TT_ERR_TOO_LARGE, "composite (column, row) key exceeds 64 bits");
+      DBuf<uint64_t> ck(al, nE), cv(al, nE), ckt(al, nE), cvt(al, nE);
+      launch_make_composite(flag.get(), pos.get(), erho.get(), nE, rbits, ck.get(), cv.get(), s);
+      radix_sort_pairs(al, ck.get(), cv.get(), ckt.get(), cvt.get(), nE, rbits + cbits, s);
+      DBuf<uint64_t> ek2(al, nE);
+      DBuf<uint32_t> er2(al, nE);
+      DBuf<double> ev2(al, nE);
+      launch_permute_entries(cv.get(), nE, ekey.get(), erho.get(), evp, ek2.get(), er2.get(), ev2.get(), s);
+      ekey = std::move(ek2);
+      erho = std::move(er2);
+      evals = std::move(ev2);
+      evp = evals.get();
+      sort_rows = false;
+    }
+    flag.release();
+    // a4: canonicalise
+    DBuf<uint32_t> crho(al, nE);
+    DBuf<double> cval(al, nE), cols(al, ncols);
+    DBuf<uint64_t> colhash(al, ncols), colsuf(al, ncols), rmkey(al, ncols);
+    CanonArgs ca{};
+    ca.ekey = ekey.get();
+    ca.erho = level1 ? nullptr : erho.get();
+    ca.ev = evp;
+    ca.col_start = col_start.get();
+    ca.ncols = ncols;
+    ca.sh = sh;
+    ca.rho_mask = (mi.bits[0] >= 64) ? ~0ull : ((1ull << mi.bits[0]) - 1ull);
+    ca.kidx = kidx;
+    ca.sort_rows = sort_rows;
+    ca.crho = crho.get();
+    ca.cval = cval.get();
+    ca.colhash = colhash.get();
+    ca.cols = cols.get();
+    ca.colsuf = colsuf.get();
+    ca.rmkey = rmkey.get();
+    launch_canon(ca, mi, st.get(), s);
+    // a5: group
+    uint32_t tsize = 1;
+    while (tsize < 2u * ncols + 2u) tsize <<= 1;
+    DBuf<uint64_t> table(al, tsize), slotmin(al, tsize);
+    TTS_HIP(hipMemsetAsync(table.get(), 0, sizeof(uint64_t) * tsize, s));
+    TTS_HIP(hipMemsetAsync(slotmin.get(), 0xff, sizeof(uint64_t) * tsize, s));
+    DBuf<uint32_t> slot(al, ncols), isrep(al, ncols);
+    launch_group(colhash.get(), crho.get(), cval.get(), col_start.get(), rmkey.get(), ncols, table.get(),
+                 slotmin.get(), tsize - 1, slot.get(), isrep.get(), s);
+    DBuf<uint32_t> reppos(al, ncols);
+    exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, &st.get()->beta, s);
+    sync_status(st.get(), s);
+    const uint32_t beta = host_status()->beta;
+    if (static_cast<uint64_t>(beta) * (k < d ? mi.n[k] : 1) > static_cast<uint64_t>(INT32_MAX))
+      fail(TT_ERR_TOO_LARGE, "rank times mode size exceeds 2^31");
+    int rm_bits = 0;
+    for (int j = kidx; j < d; ++j) rm_bits += static_cast<int>(mi.bits[j]);
+    DBuf<uint64_t> lkey(al, beta), lslot(al, beta);
+    launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, lkey.get(), lslot.get(), s);
+    {
+      DBuf<uint64_t> kt(al, beta), vt(al, beta);
+      radix_sort_pairs(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s);
+    }
+    DBuf<uint32_t> slot_gid(al, tsize), nlen(al, beta), npos(al, beta);
+    launch_group_ids(lslot.get(), beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
+    exclusive_scan_u32(al, nlen.get(), npos.get(), beta, &st.get()->nnz_n, s);
+    sync_status(st.get(), s);
+    const uint32_t nnz_n = host_status()->nnz_n;
+    LevelData& L = R->lev[k - 1];
+    L.ncols = ncols;
+    L.beta = beta;
+    L.nnz_n = nnz_n;
+    R->betas[k] = beta;
+    // a6: N_k
+    L.colptr.reset(al, static_cast<size_t>(beta) + 1);
+    L.row.reset(al, nnz_n);
+    L.val.reset(al, nnz_n);
+    launch_emit_n(lslot.get(), beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
+                  L.colptr.get(), L.row.get(), L.val.get(), st.get(), s);
+    // a7: next level (or the last core)
+    EmitArgs ea{};
+    ea.ncols = ncols;
+    ea.slot = slot.get();
+    ea.slot_gid = slot_gid.get();
+    ea.colsuf = colsuf.get();
+    ea.cols = cols.get();
+    ea.kidx = kidx;
+    ea.last = (k == d - 1);
+    if (keep) {
+      L.col.reset(al, ncols);
+      L.g.reset(al, ncols);
+      L.s.reset(al, ncols);
+      ea.out_col = L.col.get();
+      ea.out_g = L.g.get();
+      ea.out_s = L.s.get();
+    }
+    DBuf<uint64_t> nk;
+    DBuf<uint32_t> nr;
+    DBuf<double> nv;
+    if (!ea.last) {
+      nk.reset(al, ncols);
+      nr.reset(al, ncols);
+      nv.reset(al, ncols);
+      ea.next_ekey = nk.get();
+      ea.next_rho = nr.get();
+      ea.next_v = nv.get();
+    } else {
+      const size_t sz = static_cast<size_t>(beta) * mi.n[d - 1];
+      R->last_exact.reset(al, sz);
+      TTS_HIP(hipMemsetAsync(R->last_exact.get(), 0, sizeof(double) * sz, s));
+      ea.last_core = R->last_exact.get();
+    }
+    launch_emit_next(ea, mi, s);
+    if (!ea.last) {
+      ekey = std::move(nk);
+      erho = std::move(nr);
+      evals = std::move(nv);
+      evp = evals.get();
+      vals.release();
+      nE = ncols;
+    }
+  }
+  TTS_HIP(hipEventRecord(ev.e[3], s));
+}
+
+}  // namespace
+}  // namespace tts
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+using namespace tts;
+
+extern "C" {
+
+void tt_options_default(tt_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = TT_FP64;
+}
+
+const char* tt_status_string(tt_status s) {
+  switch (s) {
+    case TT_OK: return "TT_OK";
+    case TT_ERR_ARG: return "TT_ERR_ARG";
+    case TT_ERR_INDEX: return "TT_ERR_INDEX";
+    case TT_ERR_DUPLICATE: return "TT_ERR_DUPLICATE";
+    case TT_ERR_NONFINITE: return "TT_ERR_NONFINITE";
+    case TT_ERR_EMPTY: return "TT_ERR_EMPTY";
+    case TT_ERR_TOO_LARGE: return "TT_ERR_TOO_LARGE";
+    case TT_ERR_NOMEM: return "TT_ERR_NOMEM";
+    case TT_ERR_DEVICE: return "TT_ERR_DEVICE";
+  }
+  return "TT_ERR_UNKNOWN";
+}
+
+const char* tt_last_error(void) { return g_last_error.c_str(); }
+
+tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                              double eps, const tt_options* opt, void* stream, tt_result* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return TT_ERR_ARG;
+  }
+  *out = nullptr;
+  tt_options o;
+  tt_options_default(&o);
+  if (opt) o = *opt;
+  // host-side argument checks, before any launch
+  std::string why;
+  if (d < 2 || d > TT_MAX_D) why = "d must be in [2, 64]";
+  else if (!dims) why = "dims is NULL";
+  else if (nnz < 0 || nnz >= (int64_t(1) << 31)) why = "nnz must be in [0, 2^31)";
+  else if (nnz > 0 && (!idx || !val)) why = "idx/val is NULL";
+  else if (!(eps >= 0.0 && eps < 1.0)) why = "eps must satisfy 0 <= eps < 1";
+  else if (o.precision < TT_FP64 || o.precision > TT_BF16_FP32ACC) why = "unknown precision";
+  else if (o.max_rank < 0) why = "max_rank must be >= 0";
+  else if ((o.alloc == nullptr) != (o.free == nullptr)) why = "alloc and free hooks must be given together";
+  if (why.empty())
+    for (int k = 0; k < d; ++k)
+      if (dims[k] < 1 || dims[k] > INT32_MAX) why = "every n_k must be in [1, 2^31-1]";
+  if (!why.empty()) {
+    set_error(why);
+    return TT_ERR_ARG;
+  }
+  ModeInfo mi{};
+  mi.d = d;
+  int total_bits = 0;
+  for (int k = 0; k < d; ++k) {
+    mi.n[k] = static_cast<uint32_t>(dims[k]);
+    mi.bits[k] = bits_for(static_cast<uint64_t>(dims[k]));
+    mi.off[k] = static_cast<uint32_t>(total_bits);
+    total_bits += static_cast<int>(mi.bits[k]);
+  }
+  if (total_bits > 63) {
+    set_error("packed coordinate needs more than 63 bits");
+    return TT_ERR_TOO_LARGE;
+  }
+  if (nnz == 0) {
+    set_error("no nonzero given");
+    return TT_ERR_EMPTY;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tt_result_s* R = nullptr;
+  try {
+    configure_pool_once();
+    R = new tt_result_s();
+    R->al.stream = s;
+    R->al.hook_alloc = o.alloc;
+    R->al.hook_free = o.free;
+    R->al.ctx = o.alloc_ctx;
+    R->al.budget = o.device_mem_budget;
+    R->d = d;
+    R->dims.assign(dims, dims + d);
+    Events ev;
+    TTS_HIP(hipEventRecord(ev.e[0], s));
+    sparse_stage(R, idx, val, static_cast<uint32_t>(nnz), mi, total_bits, o.keep_intermediates != 0, s, ev);
+    R->delta = eps * R->norm / std::sqrt(static_cast<double>(d - 1));
+    RoundInput in{};
+    in.d = d;
+    in.dims = R->dims;
+    in.betas = R->betas;
+    in.eps = eps;
+    in.delta = R->delta;
+    in.norm = R->norm;
+    in.max_rank = o.max_rank;
+    in.precision = o.precision;
+    for (int k = 1; k <= d - 1; ++k) {
+      const LevelData& L = R->lev[k - 1];
+      in.n_colptr.push_back(L.colptr.get());
+      in.n_row.push_back(L.row.get());
+      in.n_val.push_back(L.val.get());
+      in.n_nnz.push_back(L.nnz_n);
+    }
+    in.last_core = R->last_exact.get();
+    if (o.sparse_only) {
+      densify_exact_cores(R->al, in, R->cores, s);
+      R->ranks = R->betas;
+      R->dtype = TT_DTYPE_F64;
+      TTS_HIP(hipEventRecord(ev.e[4], s));
+      TTS_HIP(hipEventRecord(ev.e[5], s));
+    } else {
+      RoundOutput ro;
+      round_tt(R->al, in, ro, s, ev.e[4]);
+      R->qr_ranks = ro.qr_ranks;
+      R->ranks = ro.ranks;
+      R->cores = std::move(ro.cores);
+      R->dtype = ro.dtype;
+      R->sigma = std::move(ro.sigma);
+      R->tail = std::move(ro.tail);
+      R->rounded = 1;
+      TTS_HIP(hipEventRecord(ev.e[5], s));
+    }
+    TTS_HIP(hipEventRecord(ev.e[6], s));
+    TTS_HIP(hipEventSynchronize(ev.e[6]));
+    for (int i = 0; i < TT_NUM_STAGES - 1; ++i) {
+      float ms = 0.f;
+      TTS_HIP(hipEventElapsedTime(&ms, ev.e[i], ev.e[i + 1]));
+      R->ms[i] = ms;
+    }
+    float tot = 0.f;
+    TTS_HIP(hipEventElapsedTime(&tot, ev.e[0], ev.e[6]));
+    R->ms[TT_NUM_STAGES - 1] = tot;
+    if (!o.keep_intermediates) {
+      for (auto& L : R->lev) {
+        L.colptr.release();
+        L.row.release();
+        L.val.release();
+      }
+    }
+    *out = R;
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return TT_ERR_NOMEM;
+  }
+}
+
+void tt_free(tt_result r) {
+  if (!r) return;
+  r->al.stream = nullptr;
+  delete r;
+}
+
+tt_status tt_get_ranks(tt_result r, int64_t* ranks) {
+  if (!r || !ranks) return TT_ERR_ARG;
+  std::copy(r->ranks.begin(), r->ranks.end(), ranks);
+  return TT_OK;
+}
+
+tt_status tt_get_sparse_ranks(tt_result r, int64_t* betas, int64_t* qr_ranks) {
+  if (!r) return TT_ERR_ARG;
+  if (betas) std::copy(r->betas.begin(), r->betas.end(), betas);
+  if (qr_ranks) {
+    if (!r->rounded) return TT_ERR_ARG;
+    std::copy(r->qr_ranks.begin(), r->qr_ranks.end(), qr_ranks);
+  }
+  return TT_OK;
+}
+
+tt_status tt_get_core(tt_result r, int32_t k, const void** dev_ptr, int32_t* dtype) {
+  if (!r || !dev_ptr || k < 1 || k > r->d) return TT_ERR_ARG;
+  if (r->cores.size() != static_cast<size_t>(r->d)) {
+    set_error("cores not available (sparse_only result too large to densify)");
+    return TT_ERR_TOO_LARGE;
+  }
+  *dev_ptr = r->cores[k - 1].get();
+  if (dtype) *dtype = r->dtype;
+  return TT_OK;
+}
+
+tt_status tt_get_info(tt_result r, int64_t* host_info, double* norm, double* delta) {
+  if (!r) return TT_ERR_ARG;
+  if (host_info) {
+    host_info[0] = r->nnz;
+    host_info[1] = r->rounded;
+    host_info[2] = r->d;
+  }
+  if (norm) *norm = r->norm;
+  if (delta) *delta = r->delta;
+  return TT_OK;
+}
+
+tt_status tt_get_sigma(tt_result r, int32_t b, int64_t* count, const double** host_sigma, double* tail) {
+  if (!r || b < 1 || b >= r->d) return TT_ERR_ARG;
+  if (!r->rounded) {
+    set_error("no singular values: sparse_only result");
+    return TT_ERR_ARG;
+  }
+  if (count) *count = static_cast<int64_t>(r->sigma[b - 1].size());
+  if (host_sigma) *host_sigma = r->sigma[b - 1].data();
+  if (tail) *tail = r->tail[b - 1];
+  return TT_OK;
+}
+
+tt_status tt_get_times(tt_result r, double* host_ms) {
+  if (!r || !host_ms) return TT_ERR_ARG;
+  std::copy(r->ms, r->ms + TT_NUM_STAGES, host_ms);
+  return TT_OK;
+}
+
+tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, const int64_t** col, const int32_t** g,
+                       const double** s, const int64_t** n_colptr, const int32_t** n_row, const double** n_val) {
+  if (!r || k < 1 || k >= r->d) return TT_ERR_ARG;
+  const LevelData& L = r->lev[k - 1];
+  if (ncols) *ncols = L.ncols;
+  if (beta) *beta = L.beta;
+  const bool have = L.g.get() != nullptr || L.ncols == 0;
+  if ((col || g || s || n_colptr || n_row || n_val) && !have) {
+    set_error("level data not kept (set keep_intermediates)");
+    return TT_ERR_ARG;
+  }
+  if (col) *col = L.col.get();
+  if (g) *g = L.g.get();
+  if (s) *s = L.s.get();
+  if (n_colptr) *n_colptr = L.colptr.get();
+  if (n_row) *n_row = L.row.get();
+  if (n_val) *n_val = L.val.get();
+  return TT_OK;
+}
+
+}  // extern "C"

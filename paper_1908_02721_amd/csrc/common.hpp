@@ -1,0 +1,151 @@
+// Shared host/device helpers of libttsparse (HIP, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "ttsparse.h"
+
+namespace tts {
+
+// ---------------------------------------------------------------------------
+// Host-side error handling: internal code throws tts::Error, the C-ABI entry
+// points catch it and turn it into a tt_status (nothing crosses the ABI).
+// ---------------------------------------------------------------------------
+struct Error {
+  tt_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(tt_status s, const std::string& msg);
+
+#define TTS_HIP(x)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      ::tts::fail(TT_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define TTS_LAUNCH_CHECK() TTS_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Device memory: stream-ordered allocations from the caller's hooks or from the
+// device's default pool, with an optional budget.
+// ---------------------------------------------------------------------------
+struct Allocator {
+  hipStream_t stream = nullptr;
+  void* (*hook_alloc)(size_t, void*) = nullptr;
+  void (*hook_free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  uint64_t peak = 0;
+
+  void* get(size_t bytes);
+  void put(void* p, size_t bytes);
+};
+
+template <class T>
+class DBuf {
+ public:
+  DBuf() = default;
+  DBuf(Allocator* a, size_t n) { reset(a, n); }
+  ~DBuf() { release(); }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { swap(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      swap(o);
+    }
+    return *this;
+  }
+  void reset(Allocator* a, size_t n) {
+    release();
+    al_ = a;
+    n_ = n;
+    p_ = n ? static_cast<T*>(a->get(n * sizeof(T))) : nullptr;
+  }
+  void release() {
+    if (p_ && al_) al_->put(p_, n_ * sizeof(T));
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  void swap(DBuf& o) noexcept {
+    std::swap(al_, o.al_);
+    std::swap(p_, o.p_);
+    std::swap(n_, o.n_);
+  }
+
+ private:
+  Allocator* al_ = nullptr;
+  T* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+inline unsigned grid_for(size_t n, unsigned block) {
+  size_t g = (n + block - 1) / block;
+  return static_cast<unsigned>(g == 0 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// Device helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const unsigned l = __lane_id();
+  return (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  const unsigned lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= static_cast<unsigned>(o)) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Exclusive scan of one value per thread over a block of NT threads.
+// `lds` must hold NT/64 words.  Returns the exclusive prefix; *total = block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t* lds, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const unsigned lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan_u32(x);
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t v = (lane < NW) ? lds[lane] : 0u;
+    v = wave_incl_scan_u32(v);
+    if (lane < NW) lds[lane] = v;
+  }
+  __syncthreads();
+  const uint32_t wbase = (w > 0) ? lds[w - 1] : 0u;
+  *total = lds[NW - 1];
+  __syncthreads();
+  return wbase + inc - x;
+}
+
+// 64-bit mixing step (SplitMix64 finaliser).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace tts

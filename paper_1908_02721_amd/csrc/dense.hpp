@@ -1,0 +1,40 @@
+// Dense stage: TT-rounding of the exact sparse TT (QR sweep, truncated-SVD sweep).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace tts {
+
+struct RoundInput {
+  int d = 0;
+  std::vector<int64_t> dims;
+  std::vector<int64_t> betas;              // ranks of the exact sparse TT, d+1
+  double eps = 0.0, delta = 0.0, norm = 0.0;
+  int max_rank = 0;
+  int precision = TT_FP64;
+  // N_k (k = 1..d-1), CSC, rows rho = g_{k-1} * n_k + i_k
+  std::vector<const int64_t*> n_colptr;
+  std::vector<const int32_t*> n_row;
+  std::vector<const double*> n_val;
+  std::vector<uint32_t> n_nnz;
+  const double* last_core = nullptr;       // G^(d): [beta_{d-1}][n_d]
+};
+
+struct RoundOutput {
+  std::vector<int64_t> qr_ranks, ranks;
+  std::vector<DBuf<char>> cores;
+  int32_t dtype = TT_DTYPE_F64;
+  std::vector<std::vector<double>> sigma;  // sigma[b-1]
+  std::vector<double> tail;                // discarded sum of sigma^2 per bond
+};
+
+// Rounds the exact TT.  Records `mid` on the stream between the QR sweep and the
+// truncated-SVD sweep.
+void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid);
+
+// Dense exact cores [beta_{k-1}][n_k][beta_k] from N_k and the last core.
+void densify_exact_cores(Allocator& al, const RoundInput& in, std::vector<DBuf<char>>& cores, hipStream_t s);
+
+}  // namespace tts

@@ -1,0 +1,244 @@
+// Device-wide exclusive scan and stable LSD radix sort, hand-written for gfx950.
+//
+// Radix sort: 8-bit digits, one pass per digit, three kernels per pass:
+//   k_rs_hist    -- per-tile digit histogram (wave-aggregated with a ballot match,
+//                   one LDS histogram per wave), written digit-major.
+//   scan         -- exclusive scan of the digit-major counts = global offsets.
+//   k_rs_scatter -- stable per-tile ranking (ballot match inside each wave, wave
+//                   prefix over the tile), staging through LDS so that the global
+//                   writes of one digit run are contiguous.
+// No inter-block waiting anywhere: every kernel only reads what earlier launches
+// wrote.
+#include "prim.hpp"
+
+namespace tts {
+
+namespace {
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = SCAN_NT * SCAN_IPT;
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
+                                                         uint32_t* __restrict__ part) {
+  __shared__ uint32_t lds[SCAN_NT / 64];
+  const size_t base = static_cast<size_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_IPT;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const size_t j = base + i;
+    if (j < n) s += in[j];
+  }
+  uint32_t tot;
+  block_excl_scan_u32<SCAN_NT>(s, lds, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ part, uint32_t nb,
+                                                        uint32_t* __restrict__ d_total) {
+  __shared__ uint32_t lds[1024 / 64];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nb; base += 1024) {
+    const uint32_t j = base + threadIdx.x;
+    const uint32_t x = (j < nb) ? part[j] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_u32<1024>(x, lds, &tot);
+    if (j < nb) part[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && d_total) *d_total = carry;
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                        const uint32_t* __restrict__ part) {
+  __shared__ uint32_t lds[SCAN_NT / 64];
+  const size_t base = static_cast<size_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_IPT;
+  uint32_t v[SCAN_IPT];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const size_t j = base + i;
+    v[i] = (j < n) ? in[j] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = block_excl_scan_u32<SCAN_NT>(s, lds, &tot) + part[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) {
+    const size_t j = base + i;
+    if (j < n) out[j] = run;
+    run += v[i];
+  }
+}
+
+// ----------------------------------------------------------------------------
+constexpr int RS_NT = 256;
+constexpr int RS_NW = RS_NT / 64;
+constexpr int RS_IPT = 16;
+constexpr int RS_TILE = RS_NT * RS_IPT;  // 4096 items per tile
+
+// Mask of the lanes of this wave that hold the same 8-bit digit (all lanes must
+// be active).
+__device__ __forceinline__ uint64_t match_digit(unsigned dig) {
+  uint64_t m = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (dig >> b) & 1u;
+    const uint64_t bal = __ballot(bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
+                                                   uint32_t* __restrict__ counts, uint32_t ntiles) {
+  __shared__ uint32_t h[RS_NW][256];
+  for (int i = threadIdx.x; i < RS_NW * 256; i += RS_NT) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t base = static_cast<size_t>(blockIdx.x) * RS_TILE + static_cast<size_t>(w) * 64 * RS_IPT;
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
+    const bool valid = i < n;
+    const unsigned dig = valid ? static_cast<unsigned>((keys[i] >> shift) & 255u) : 0u;
+    const uint64_t peers = match_digit(dig) & __ballot(valid);
+    if (valid && (peers & lanemask_lt()) == 0) h[w][dig] += static_cast<uint32_t>(__popcll(peers));
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  const unsigned t = threadIdx.x;
+  uint32_t c = 0;
+#pragma unroll
+  for (int ww = 0; ww < RS_NW; ++ww) c += h[ww][t];
+  counts[static_cast<size_t>(t) * ntiles + blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                      const uint64_t* __restrict__ vin,
+                                                      uint64_t* __restrict__ kout,
+                                                      uint64_t* __restrict__ vout, uint32_t n, int shift,
+                                                      const uint32_t* __restrict__ offs, uint32_t ntiles) {
+  __shared__ uint32_t wcnt[RS_NW][256];
+  __shared__ uint32_t toff[256];
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t scan_lds[RS_NW];
+  __shared__ uint64_t stage[RS_TILE];
+  __shared__ uint8_t sdig[RS_TILE];
+
+  for (int i = threadIdx.x; i < RS_NW * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+  goff[threadIdx.x] = offs[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x];
+  __syncthreads();
+
+  const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t tile0 = static_cast<size_t>(blockIdx.x) * RS_TILE;
+  const size_t base = tile0 + static_cast<size_t>(w) * 64 * RS_IPT;
+  uint64_t k[RS_IPT], v[RS_IPT];
+  uint32_t rk[RS_IPT];
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
+    const bool valid = i < n;
+    k[r] = valid ? kin[i] : 0ull;
+    v[r] = valid ? vin[i] : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
+    const bool valid = i < n;
+    const unsigned dig = static_cast<unsigned>((k[r] >> shift) & 255u);
+    const uint64_t peers = match_digit(dig) & __ballot(valid);
+    const uint32_t pre = static_cast<uint32_t>(__popcll(peers & lanemask_lt()));
+    const uint32_t old = valid ? wcnt[w][dig] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && pre == 0) wcnt[w][dig] = old + static_cast<uint32_t>(__popcll(peers));
+    __builtin_amdgcn_wave_barrier();
+    rk[r] = old + pre;
+  }
+  __syncthreads();
+  {
+    const unsigned t = threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int ww = 0; ww < RS_NW; ++ww) {
+      const uint32_t c = wcnt[ww][t];
+      wcnt[ww][t] = s;
+      s += c;
+    }
+    uint32_t tot;
+    toff[t] = block_excl_scan_u32<RS_NT>(s, scan_lds, &tot);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
+    if (i < n) {
+      const unsigned dig = static_cast<unsigned>((k[r] >> shift) & 255u);
+      const uint32_t pos = toff[dig] + wcnt[w][dig] + rk[r];
+      stage[pos] = k[r];
+      sdig[pos] = static_cast<uint8_t>(dig);
+    }
+  }
+  __syncthreads();
+  const uint32_t cnt = static_cast<uint32_t>(min(static_cast<size_t>(RS_TILE), n - tile0));
+  for (uint32_t j = threadIdx.x; j < cnt; j += RS_NT) {
+    const unsigned dig = sdig[j];
+    kout[goff[dig] + (j - toff[dig])] = stage[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
+    if (i < n) {
+      const unsigned dig = static_cast<unsigned>((k[r] >> shift) & 255u);
+      stage[toff[dig] + wcnt[w][dig] + rk[r]] = v[r];
+    }
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < cnt; j += RS_NT) {
+    const unsigned dig = sdig[j];
+    vout[goff[dig] + (j - toff[dig])] = stage[j];
+  }
+}
+
+}  // namespace
+
+void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
+                        hipStream_t s) {
+  if (n == 0) {
+    if (d_total) TTS_HIP(hipMemsetAsync(d_total, 0, sizeof(uint32_t), s));
+    return;
+  }
+  const uint32_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  DBuf<uint32_t> part(al, nb);
+  k_scan_reduce<<<nb, SCAN_NT, 0, s>>>(in, n, part.get());
+  TTS_LAUNCH_CHECK();
+  k_scan_partials<<<1, 1024, 0, s>>>(part.get(), nb, d_total);
+  TTS_LAUNCH_CHECK();
+  k_scan_apply<<<nb, SCAN_NT, 0, s>>>(in, out, n, part.get());
+  TTS_LAUNCH_CHECK();
+}
+
+void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
+                      uint32_t n, int nbits, hipStream_t s) {
+  if (n <= 1 || nbits <= 0) return;
+  const uint32_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+  const int passes = (nbits + 7) / 8;
+  DBuf<uint32_t> counts(al, static_cast<size_t>(256) * ntiles);
+  uint64_t *ki = keys, *vi = vals, *ko = ktmp, *vo = vtmp;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, counts.get(), ntiles);
+    TTS_LAUNCH_CHECK();
+    exclusive_scan_u32(al, counts.get(), counts.get(), 256u * ntiles, nullptr, s);
+    k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, counts.get(), ntiles);
+    TTS_LAUNCH_CHECK();
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  if (ki != keys) {
+    TTS_HIP(hipMemcpyAsync(keys, ki, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    TTS_HIP(hipMemcpyAsync(vals, vi, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace tts

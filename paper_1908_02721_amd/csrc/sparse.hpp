@@ -1,0 +1,111 @@
+// Sparse stage of the decomposition: parallel-vector rounding of sparse unfoldings.
+#pragma once
+
+#include "common.hpp"
+
+namespace tts {
+
+// Bit layout of the packed coordinate key: the field of mode j (0-based) sits at
+// bit off[j] with width bits[j]; mode 0 is least significant, so the last mode is
+// most significant and every suffix (i_{k+1},...,i_d) is a contiguous high part.
+struct ModeInfo {
+  int32_t d;
+  uint32_t bits[TT_MAX_D];
+  uint32_t off[TT_MAX_D];
+  uint32_t n[TT_MAX_D];
+};
+
+// Small device-side status block, read back once or twice per level.
+struct DevStatus {
+  uint32_t err;       // bit 0: index out of range, bit 1: non-finite, bit 2: duplicate
+  uint32_t longcol;   // a level >= 2 column has more than kMaxLocal entries
+  uint32_t kept;      // nonzeros kept after dropping explicit zeros
+  uint32_t ncols;     // columns of the current level
+  uint32_t beta;      // groups of the current level
+  uint32_t nnz_n;     // entries of N_k
+  uint32_t pad0, pad1;
+  double norm2;       // ||A||_F^2
+};
+
+constexpr uint32_t kErrIndex = 1u, kErrNonfinite = 2u, kErrDuplicate = 4u;
+constexpr int kMaxLocal = 32;  // longest column canonicalised from registers
+
+// a1: validate, drop zeros (key := ~0), pack keys; values copied as raw bits.
+void launch_ingest(const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
+                   uint64_t* keys, uint64_t* vbits, DevStatus* st, hipStream_t s);
+
+// Column starts of a level: flag[e] = 1 where (ekey[e] >> sh) changes.  Level 1
+// also checks duplicates and accumulates ||A||^2 (fixed-order partial sums).
+void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, bool check_long,
+                      const double* ev, uint32_t* flag, double* norm_part, DevStatus* st, hipStream_t s);
+uint32_t norm_partials_count(uint32_t nE);
+void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s);
+void launch_col_starts(const uint32_t* flag, const uint32_t* pos, uint32_t nE, uint32_t* col_start,
+                       const DevStatus* st, hipStream_t s);
+
+// Long-column path: composite sort keys (column << rbits | rho) and a permutation.
+void launch_make_composite(const uint32_t* flag, const uint32_t* pos, const uint32_t* erho, uint32_t nE,
+                           int rbits, uint64_t* ckey, uint64_t* cval, hipStream_t s);
+void launch_permute_entries(const uint64_t* perm, uint32_t nE, const uint64_t* ekey_in, const uint32_t* erho_in,
+                            const double* ev_in, uint64_t* ekey_out, uint32_t* erho_out, double* ev_out,
+                            hipStream_t s);
+
+struct CanonArgs {
+  const uint64_t* ekey;
+  const uint32_t* erho;  // null at level 1 (rho = low field of ekey)
+  const double* ev;
+  const uint32_t* col_start;
+  uint32_t ncols;
+  int sh;               // bits of mode k-1 (0-based): column = ekey >> sh
+  uint64_t rho_mask;    // level 1: mask of the mode-0 field
+  int kidx;             // first suffix mode (0-based) = k
+  bool sort_rows;       // entries of a column still need ordering by rho
+  uint32_t* crho;       // out, per entry: rho in ascending order
+  double* cval;         // out, per entry: canonical value v / s
+  uint64_t* colhash;
+  double* cols;         // prefactor s
+  uint64_t* colsuf;     // colex-packed suffix (lowest field = mode k)
+  uint64_t* rmkey;      // row-major-ordered suffix key (numbering order)
+};
+// a4: canonicalise every column by its entry of smallest row, key and hash it.
+void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus* st, hipStream_t s);
+
+// a5: group identical canonical columns (open-addressing table with full-key
+// verification), leader = smallest row-major suffix key of each group.
+void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* cval, const uint32_t* col_start,
+                  const uint64_t* rmkey, uint32_t ncols, uint64_t* table, uint64_t* slotmin, uint32_t tmask,
+                  uint32_t* slot, uint32_t* isrep, hipStream_t s);
+void launch_rep_list(const uint32_t* isrep, const uint32_t* reppos, const uint32_t* slot, const uint64_t* slotmin,
+                     uint32_t ncols, uint64_t* lkey, uint64_t* lslot, hipStream_t s);
+// group id of each slot (= rank of its leader) and the length of each group's column
+void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
+                      uint32_t* slot_gid, uint32_t* nlen, hipStream_t s);
+
+// a6: N_k in CSC (one canonical column per group, in group order).
+void launch_emit_n(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
+                   const uint32_t* npos, const uint32_t* crho, const double* cval, int64_t* colptr,
+                   int32_t* nrow, double* nval, const DevStatus* st, hipStream_t s);
+
+struct EmitArgs {
+  uint32_t ncols;
+  const uint32_t* slot;
+  const uint32_t* slot_gid;
+  const uint64_t* colsuf;
+  const double* cols;
+  int kidx;            // first suffix mode (0-based)
+  bool last;           // k == d-1: write the last core
+  // keep_intermediates (may be null)
+  int64_t* out_col;
+  int32_t* out_g;
+  double* out_s;
+  // next level (k < d-1)
+  uint64_t* next_ekey;
+  uint32_t* next_rho;
+  double* next_v;
+  // last level: dense G^(d) [beta][n_d], zero-filled beforehand
+  double* last_core;
+};
+// a7: transfer matrix -> next level's entries (or the last core).
+void launch_emit_next(const EmitArgs& a, const ModeInfo& mi, hipStream_t s);
+
+}  // namespace tts

@@ -1,0 +1,87 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry
+point, and host-side argument errors are reported before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "ttsparse.h")) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tt_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1908_02721_amd import _lib
+
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "tt_sparse_decompose" in names and "tt_eval_entries_backward" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1908_02721_amd import _lib
+
+    assert sorted(_lib.EXPORTS) == names
+
+
+def _call(lib, d, dims, nnz, idx, val, eps, opt=None):
+    from paper_1908_02721_amd import _lib
+
+    o = _lib.tt_options()
+    lib.tt_options_default(ctypes.byref(o))
+    if opt:
+        for k, v in opt.items():
+            setattr(o, k, v)
+    dims_a = (ctypes.c_int64 * max(1, len(dims)))(*dims)
+    h = ctypes.c_void_p(123)
+    st = lib.tt_sparse_decompose(d, dims_a, nnz, idx, val, eps, ctypes.byref(o), None, ctypes.byref(h))
+    return st, h.value
+
+
+def test_host_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails on the host
+    cases = [
+        ((1, [4], 1, fake, fake, 0.1), 1),              # d < 2
+        ((65, [2] * 65, 1, fake, fake, 0.1), 1),        # d > 64
+        ((2, [4, 0], 1, fake, fake, 0.1), 1),           # n_k < 1
+        ((2, [4, 4], 1, None, fake, 0.1), 1),           # idx NULL
+        ((2, [4, 4], 1, fake, None, 0.1), 1),           # val NULL
+        ((2, [4, 4], 1, fake, fake, 1.0), 1),           # eps >= 1
+        ((2, [4, 4], 1, fake, fake, -0.1), 1),          # eps < 0
+        ((2, [4, 4], 1, fake, fake, float("nan")), 1),  # eps NaN
+        ((2, [4, 4], -1, fake, fake, 0.1), 1),          # nnz < 0
+        ((2, [4, 4], 0, fake, fake, 0.1), 5),           # nothing given -> EMPTY
+        ((8, [1 << 30] * 8, 1, fake, fake, 0.1), 6),    # packed key > 63 bits
+    ]
+    for args, expect in cases:
+        st, h = _call(lib, *args)
+        assert st == expect, (args, st)
+        assert h is None
+        assert len(lib.tt_last_error()) > 0
+    st, _ = _call(lib, 2, [4, 4], 1, fake, fake, 0.1, {"precision": 7})
+    assert st == 1
+    st, _ = _call(lib, 2, [4, 4], 1, fake, fake, 0.1, {"max_rank": -2})
+    assert st == 1
+
+
+def test_status_strings(lib):
+    from paper_1908_02721_amd import _lib
+
+    for code, name in _lib.STATUS.items():
+        assert lib.tt_status_string(code).decode() == name
+
+
+def test_null_handles(lib):
+    lib.tt_free(None)
+    r = (ctypes.c_int64 * 4)()
+    assert lib.tt_get_ranks(None, r) == 1
+    assert lib.tt_get_core(None, 1, ctypes.byref(ctypes.c_void_p()), None) == 1

@@ -1,0 +1,160 @@
+"""GPU parity of the sparse stage (parallel-vector rounding of the sparse unfoldings).
+
+Grouping, numbering, prefactors, distinct columns N_k and the last core must match
+the oracle bit for bit; ||A||_F within a few ulps (different summation order).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_02721_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _tt():
+    import paper_1908_02721_amd as tts
+
+    return tts
+
+
+def _to_gpu(idx, val):
+    return torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda(), \
+        torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).cuda()
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.int64)
+
+
+def check_sparse_parity(oracle_mod, idx, val, dims, label=""):
+    tts = _tt()
+    print(f"[sparse parity] {label} dims={tuple(dims)} nnz={len(val)}", flush=True)
+    res = oracle_mod.decompose(idx, val, dims, 0.0, do_round=False)
+    gi, gv = _to_gpu(idx, val)
+    tt = tts.decompose(gi, gv, dims, 0.0, sparse_only=True, keep_intermediates=True)
+    assert tt.nnz == res.nnz
+    assert tt.betas == res.betas, (tt.betas, res.betas)
+    assert abs(tt.norm - res.norm) <= 1e-13 * res.norm
+    d = len(dims)
+    for k in range(1, d):
+        L = tt.level(k)
+        O = res.levels[k - 1]
+        col = L["col"].cpu().numpy()
+        order = np.argsort(col, kind="stable")
+        assert np.array_equal(col[order], O.col), f"level {k}: columns"
+        assert np.array_equal(L["g"].cpu().numpy()[order], O.g), f"level {k}: groups"
+        assert np.array_equal(_bits(L["s"].cpu().numpy()[order]), _bits(O.s)), f"level {k}: prefactors"
+        assert np.array_equal(L["n_colptr"].cpu().numpy(), O.n_colptr), f"level {k}: N colptr"
+        assert np.array_equal(L["n_row"].cpu().numpy().astype(np.int64), O.n_row), f"level {k}: N rows"
+        assert np.array_equal(_bits(L["n_val"].cpu().numpy()), _bits(O.n_val)), f"level {k}: N values"
+    cores = tt.cores
+    ex = res.exact_cores()
+    for k in range(d):
+        assert np.array_equal(_bits(cores[k].cpu().numpy()), _bits(ex[k])), f"core {k + 1}"
+    return tt, res
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("kind", ["int", "normal"])
+def test_tiny_random(oracle_mod, seed, kind):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = [(3, 4, 2, 3), (2, 3, 3, 2, 2), (5, 4, 6), (7, 1, 5)][seed]
+    total = int(np.prod(dims))
+    nnz = max(1, total // 3)
+    lin = rng.choice(total, nnz, replace=False)
+    val = (rng.integers(1, 4, nnz) * rng.choice([-1, 1], nnz)).astype(float) if kind == "int" else rng.standard_normal(nnz)
+    check_sparse_parity(oracle_mod, synth.unravel(lin, dims), val, dims, f"tiny {kind} {seed}")
+
+
+def test_random4d_n20_nnz1k(oracle_mod):
+    idx, val, dims, _ = synth.workload("random4d_n20_nnz1k")
+    check_sparse_parity(oracle_mod, idx, val, dims, "random4d_n20_nnz1k")
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 7])
+def test_laplacian(oracle_mod, L):
+    idx, val, dims = synth.laplacian_qtt(L)
+    check_sparse_parity(oracle_mod, idx, val, dims, f"laplace L={L}")
+
+
+def test_kronecker_small(oracle_mod):
+    idx, val, dims = synth.kronecker_sum(5, 12, 10, 3, seed=9)
+    check_sparse_parity(oracle_mod, idx, val, dims, "kron d5")
+
+
+def test_long_columns_path(oracle_mod):
+    # level-2 columns with more than 32 entries take the composite-sort path
+    rng = np.random.Generator(np.random.PCG64(17))
+    dims = (3, 48, 4)
+    total = int(np.prod(dims))
+    lin = rng.choice(total, total // 2, replace=False)
+    val = rng.integers(1, 3, lin.size).astype(float)
+    check_sparse_parity(oracle_mod, synth.unravel(lin, dims), val, dims, "long columns")
+
+
+def test_wide_mode_and_unit_modes(oracle_mod):
+    idx, val, dims = synth.random_sparse((1, 300, 1, 7, 2), 500, 33)
+    check_sparse_parity(oracle_mod, idx, val, dims, "unit modes")
+
+
+def test_fdm_pattern(oracle_mod):
+    idx, val, dims = synth.fdm3d_mpo(10, "pattern")
+    check_sparse_parity(oracle_mod, idx, val, dims, "fdm n=10")
+
+
+def test_permutation_zeros_and_determinism(oracle_mod):
+    tts = _tt()
+    idx, val, dims = synth.random_sparse((9, 8, 7, 6), 900, 5)
+    rng = np.random.Generator(np.random.PCG64(1))
+    p = rng.permutation(len(val))
+    # append explicit zeros at fresh coordinates (they must be dropped)
+    lin = set((((idx[:, 0] * 8 + idx[:, 1]) * 7 + idx[:, 2]) * 6 + idx[:, 3]).tolist())
+    free = [x for x in range(9 * 8 * 7 * 6) if x not in lin][:5]
+    zi = synth.unravel(np.array(free), dims)
+    idx2 = np.concatenate([idx[p], zi])
+    val2 = np.concatenate([val[p], [0.0, -0.0, 0.0, 0.0, -0.0]])
+    t1, _ = check_sparse_parity(oracle_mod, idx2, val2, dims, "permuted+zeros")
+    gi, gv = _to_gpu(idx2, val2)
+    t2 = tts.decompose(gi, gv, dims, 0.0, sparse_only=True)
+    for a, b in zip(t1.cores, t2.cores):
+        assert torch.equal(a, b)
+
+
+def test_device_detected_errors():
+    tts = _tt()
+    dims = (4, 4, 4)
+    idx = np.array([[0, 1, 2], [3, 3, 3], [1, 0, 2]], dtype=np.int32)
+    val = np.array([1.0, 2.0, 3.0])
+
+    def run(i, v):
+        gi, gv = _to_gpu(i, v)
+        with pytest.raises(tts.TTError) as e:
+            tts.decompose(gi, gv, dims, 0.1, sparse_only=True)
+        return e.value.status
+
+    bad = idx.copy()
+    bad[1, 2] = 4
+    assert run(bad, val) == "TT_ERR_INDEX"
+    bad[1, 2] = -1
+    assert run(bad, val) == "TT_ERR_INDEX"
+    assert run(idx, np.array([1.0, np.nan, 3.0])) == "TT_ERR_NONFINITE"
+    assert run(idx, np.array([1.0, np.inf, 3.0])) == "TT_ERR_NONFINITE"
+    dup = idx.copy()
+    dup[2] = dup[0]
+    assert run(dup, val) == "TT_ERR_DUPLICATE"
+    assert run(idx, np.zeros(3)) == "TT_ERR_EMPTY"
+    # precedence: index before non-finite before duplicate
+    both = dup.copy()
+    both[1, 0] = 9
+    assert run(both, np.array([1.0, np.nan, 3.0])) == "TT_ERR_INDEX"
+    # a duplicate whose copy is an explicit zero is not a duplicate
+    gi, gv = _to_gpu(dup, np.array([1.0, 2.0, 0.0]))
+    tt = tts.decompose(gi, gv, dims, 0.1, sparse_only=True)
+    assert tt.nnz == 2
+
+
+@pytest.mark.parametrize("name", ["kron8d_n32_t64", "laplace2d_qtt_L10"])
+def test_full_size_sparse_stage(oracle_mod, name):
+    idx, val, dims, _ = synth.workload(name)
+    check_sparse_parity(oracle_mod, idx, val, dims, name)
