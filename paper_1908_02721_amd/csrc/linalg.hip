@@ -1,0 +1,998 @@
+// Dense FP64 kernels of the rounding stage (gfx950, wave64).
+#include "linalg.hpp"
+
+#include <algorithm>
+
+#include "prim.hpp"
+
+namespace tts {
+
+namespace {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------
+// GEMM: 64x64 output tile per 256-thread workgroup, 4x4 register tile per
+// thread (rows ty + 16r, columns tx + 16c), K staged through LDS in steps of 16.
+// ---------------------------------------------------------------------------
+constexpr int GT = 64, GK = 16;
+
+__global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k, double alpha,
+                                             const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                             int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
+                                             double* __restrict__ part) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(k, kb + kchunk);
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    for (int e = threadIdx.x; e < GT * GK; e += NT) {
+      int i, kk;
+      if (!ta) {
+        i = e % GT;
+        kk = e / GT;
+      } else {
+        kk = e % GK;
+        i = e / GK;
+      }
+      const int gi = m0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < ke) v = ta ? A[gk + static_cast<size_t>(gi) * lda] : A[gi + static_cast<size_t>(gk) * lda];
+      As[kk][i] = v;
+    }
+    for (int e = threadIdx.x; e < GT * GK; e += NT) {
+      int j, kk;
+      if (!tb) {
+        kk = e % GK;
+        j = e / GK;
+      } else {
+        j = e % GT;
+        kk = e / GT;
+      }
+      const int gj = n0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < n && gk < ke) v = tb ? B[gj + static_cast<size_t>(gk) * ldb] : B[gk + static_cast<size_t>(gj) * ldb];
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int gi = m0 + ty + 16 * r;
+    if (gi >= m) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gj = n0 + tx + 16 * c;
+      if (gj >= n) continue;
+      if (part) {
+        part[static_cast<size_t>(blockIdx.z) * m * n + gi + static_cast<size_t>(gj) * m] = acc[r][c];
+      } else {
+        double* cp = &C[gi + static_cast<size_t>(gj) * ldc];
+        *cp = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*cp));
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const double* __restrict__ part,
+                                                    double alpha, double beta, double* __restrict__ C, int ldc) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
+  const size_t mn = static_cast<size_t>(m) * n;
+  if (e >= mn) return;
+  double s = 0.0;
+  for (int z = 0; z < ns; ++z) s += part[static_cast<size_t>(z) * mn + e];
+  const int i = static_cast<int>(e % m), j = static_cast<int>(e / m);
+  double* cp = &C[i + static_cast<size_t>(j) * ldc];
+  *cp = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * (*cp));
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_spmm_left(const double* __restrict__ W, int r, int ldw,
+                                                  const int64_t* __restrict__ colptr, const int32_t* __restrict__ row,
+                                                  const double* __restrict__ val, int nk, double* __restrict__ X,
+                                                  int ldx) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  const int b = blockIdx.y;
+  if (a >= r) return;
+  double* xc = X + static_cast<size_t>(b) * ldx + static_cast<size_t>(a) * nk;
+  for (int64_t e = colptr[b]; e < colptr[b + 1]; ++e) {
+    const int rho = row[e];
+    const int g = rho / nk, i = rho - g * nk;
+    xc[i] = fma(W[a + static_cast<size_t>(g) * ldw], val[e], xc[i]);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_expand_cols(const int64_t* __restrict__ colptr, int ncols,
+                                                    const int32_t* __restrict__ row, uint64_t* __restrict__ key,
+                                                    uint64_t* __restrict__ ent, uint32_t* __restrict__ ecol) {
+  const int b = blockIdx.x * NT + threadIdx.x;
+  if (b >= ncols) return;
+  for (int64_t e = colptr[b]; e < colptr[b + 1]; ++e) {
+    key[e] = static_cast<uint64_t>(row[e]);
+    ent[e] = static_cast<uint64_t>(e);
+    ecol[e] = static_cast<uint32_t>(b);
+  }
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(NT) void k_group_weights(const uint64_t* __restrict__ skey,
+                                                      const uint64_t* __restrict__ sent, uint32_t nnz, int nk,
+                                                      int ngroups, const double* __restrict__ val,
+                                                      const uint32_t* __restrict__ ecol,
+                                                      const double* __restrict__ wnext, double* __restrict__ w) {
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= ngroups) return;
+  const uint32_t lo = lower_bound_u64(skey, nnz, static_cast<uint64_t>(g) * nk);
+  const uint32_t hi = lower_bound_u64(skey, nnz, static_cast<uint64_t>(g + 1) * nk);
+  double s = 0.0;
+  for (uint32_t t = lo; t < hi; ++t) {
+    const uint64_t e = sent[t];
+    const double c = val[e];
+    s = fma(c * c, wnext[ecol[e]], s);
+  }
+  w[g] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_row_sumsq(const double* __restrict__ G, int ngroups, int nk,
+                                                  double* __restrict__ w) {
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= ngroups) return;
+  double s = 0.0;
+  for (int i = 0; i < nk; ++i) {
+    const double x = G[static_cast<size_t>(g) * nk + i];
+    s = fma(x, x, s);
+  }
+  w[g] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_scale_cols(const double* __restrict__ X, int rows, int ldx,
+                                                   const int32_t* __restrict__ piv, const double* __restrict__ w,
+                                                   double* __restrict__ Y, int ldy) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int t = blockIdx.y;
+  if (i >= rows) return;
+  const int j = piv ? piv[t] : t;
+  const double sc = w ? sqrt(w[j]) : 1.0;
+  Y[i + static_cast<size_t>(t) * ldy] = X[i + static_cast<size_t>(j) * ldx] * sc;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide helpers for single-workgroup kernels (1024 threads).
+// ---------------------------------------------------------------------------
+constexpr int BT = 1024;
+
+__device__ double block_sum_1024(double x, double* red) {
+  x = wave_sum_f64(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = x;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < BT / 64; ++i) s += red[i];
+    red[16] = s;
+  }
+  __syncthreads();
+  s = red[16];
+  __syncthreads();
+  return s;
+}
+
+// argmax with lowest index on ties
+__device__ void block_argmax_1024(double v, int idx, double* redv, int* redi, double* outv, int* outi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    redv[w] = v;
+    redi[w] = idx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bv = redv[0];
+    int bi = redi[0];
+    for (int i = 1; i < BT / 64; ++i)
+      if (redv[i] > bv || (redv[i] == bv && redi[i] < bi)) {
+        bv = redv[i];
+        bi = redi[i];
+      }
+    redv[16] = bv;
+    redi[16] = bi;
+  }
+  __syncthreads();
+  *outv = redv[16];
+  *outi = redi[16];
+  __syncthreads();
+}
+
+// Left-looking pivoted Cholesky (dynamic LDS: n doubles for the Schur diagonal).
+__global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restrict__ G, int n, int ldg, int rmax,
+                                                         double theta, double* __restrict__ L,
+                                                         int32_t* __restrict__ piv, int32_t* __restrict__ d_r) {
+  extern __shared__ double sm[];
+  double* dg = sm;               // n
+  double* lp = sm + n;           // rmax (row p of L)
+  __shared__ double redv[17];
+  __shared__ int redi[17];
+  double gmax = 0.0;
+  for (int j = threadIdx.x; j < n; j += BT) {
+    dg[j] = G[j + static_cast<size_t>(j) * ldg];
+    gmax = fmax(gmax, dg[j]);
+  }
+  double mv;
+  int mi;
+  block_argmax_1024(gmax, 0, redv, redi, &mv, &mi);
+  const double thr = theta * mv;
+  int r = 0;
+  for (int t = 0; t < rmax; ++t) {
+    double v = -1.0;
+    int idx = n;
+    for (int j = threadIdx.x; j < n; j += BT)
+      if (dg[j] > v || (dg[j] == v && j < idx)) {
+        v = dg[j];
+        idx = j;
+      }
+    double pv;
+    int p;
+    block_argmax_1024(v, idx, redv, redi, &pv, &p);
+    if (!(pv > thr)) break;
+    if (threadIdx.x == 0) piv[t] = p;
+    for (int l = threadIdx.x; l < t; l += BT) lp[l] = L[p + static_cast<size_t>(l) * n];
+    __syncthreads();
+    const double inv = 1.0 / sqrt(pv);
+    for (int j = threadIdx.x; j < n; j += BT) {
+      double x;
+      if (j == p) {
+        x = sqrt(pv);
+        dg[j] = -1.0;
+      } else if (dg[j] < 0.0) {
+        x = 0.0;  // already a pivot: its Schur row is zero
+      } else {
+        double s = G[j + static_cast<size_t>(p) * ldg];
+        for (int l = 0; l < t; ++l) s = fma(-L[j + static_cast<size_t>(l) * n], lp[l], s);
+        x = s * inv;
+        dg[j] = dg[j] - x * x;
+      }
+      L[j + static_cast<size_t>(t) * n] = x;
+    }
+    __syncthreads();
+    r = t + 1;
+  }
+  if (threadIdx.x == 0) *d_r = r;
+}
+
+__global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ L, int n,
+                                                     const int32_t* __restrict__ piv, int r, double* __restrict__ U) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= r * r) return;
+  const int t = e % r, s = e / r;  // U[t, s] = L[piv[s], t] for t <= s
+  U[t + static_cast<size_t>(s) * r] = (t <= s) ? L[piv[s] + static_cast<size_t>(t) * n] : 0.0;
+}
+
+// Right-looking Cholesky, upper factor, in global memory, one workgroup.
+__global__ __launch_bounds__(BT) void k_cholesky_upper(double* __restrict__ A, int r, int lda, double max_ratio,
+                                                       int32_t* __restrict__ ok) {
+  __shared__ double piv, dmin, dmax;
+  __shared__ int bad;
+  if (threadIdx.x == 0) {
+    bad = 0;
+    dmin = INFINITY;
+    dmax = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    if (threadIdx.x == 0) {
+      const double a = A[j + static_cast<size_t>(j) * lda];
+      if (!(a > 0.0)) bad = 1;
+      piv = (a > 0.0) ? sqrt(a) : 1.0;
+      A[j + static_cast<size_t>(j) * lda] = piv;
+      dmin = fmin(dmin, piv);
+      dmax = fmax(dmax, piv);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double inv = 1.0 / piv;
+    for (int c = j + 1 + threadIdx.x; c < r; c += BT) A[j + static_cast<size_t>(c) * lda] *= inv;
+    __syncthreads();
+    // trailing update of the upper triangle: A[i, c] -= A[j, i] * A[j, c], j < i <= c
+    const int w = r - j - 1;
+    const long long tot = static_cast<long long>(w) * w;
+    for (long long e = threadIdx.x; e < tot; e += BT) {
+      const int i = j + 1 + static_cast<int>(e % w), c = j + 1 + static_cast<int>(e / w);
+      if (i <= c) A[i + static_cast<size_t>(c) * lda] -= A[j + static_cast<size_t>(i) * lda] * A[j + static_cast<size_t>(c) * lda];
+    }
+    __syncthreads();
+  }
+  // zero the strict lower part
+  for (long long e = threadIdx.x; e < static_cast<long long>(r) * r; e += BT) {
+    const int i = static_cast<int>(e % r), c = static_cast<int>(e / r);
+    if (i > c) A[i + static_cast<size_t>(c) * lda] = 0.0;
+  }
+  if (threadIdx.x == 0) *ok = (bad || dmax > max_ratio * dmin) ? 0 : 1;
+}
+
+// Inverse of an upper-triangular matrix: one thread per column of the inverse.
+__global__ __launch_bounds__(NT) void k_triu_inverse(const double* __restrict__ U, int r, int ldu,
+                                                     double* __restrict__ X, int ldx, int32_t* __restrict__ ok) {
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= r) return;
+  double* x = X + static_cast<size_t>(j) * ldx;
+  for (int i = j + 1; i < r; ++i) x[i] = 0.0;
+  const double ujj = U[j + static_cast<size_t>(j) * ldu];
+  if (ujj == 0.0) {
+    *ok = 0;
+    return;
+  }
+  x[j] = 1.0 / ujj;
+  for (int i = j - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int l = i + 1; l <= j; ++l) s = fma(U[i + static_cast<size_t>(l) * ldu], x[l], s);
+    const double uii = U[i + static_cast<size_t>(i) * ldu];
+    if (uii == 0.0) {
+      *ok = 0;
+      return;
+    }
+    x[i] = -s / uii;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_col_sumsq(const double* __restrict__ E, int rows, int lde,
+                                                  double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < rows; i += NT) {
+    const double x = E[i + static_cast<size_t>(j) * lde];
+    s = fma(x, x, s);
+  }
+  s = wave_sum_f64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    out[j] = t;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_weighted_total(const double* __restrict__ cs, const double* __restrict__ w,
+                                                       int cols, double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < cols; j += NT) s += (w ? w[j] : 1.0) * cs[j];
+  s = wave_sum_f64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < NT / 64; ++i) t += red[i];
+    *out = t;
+  }
+}
+
+// Householder QR, one workgroup, LAPACK geqr2/larfg conventions.
+__global__ __launch_bounds__(BT) void k_householder_qr(double* __restrict__ A, int m, int n, int lda,
+                                                       double* __restrict__ tau) {
+  __shared__ double red[17];
+  __shared__ double sh_tau, sh_beta, sh_scale;
+  const int p = min(m, n);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j < p; ++j) {
+    double* x = A + static_cast<size_t>(j) * lda;
+    double s = 0.0;
+    for (int i = j + 1 + threadIdx.x; i < m; i += BT) s = fma(x[i], x[i], s);
+    const double xn2 = block_sum_1024(s, red);
+    if (threadIdx.x == 0) {
+      const double alpha = x[j];
+      if (xn2 == 0.0) {
+        sh_tau = 0.0;
+        sh_beta = alpha;
+        sh_scale = 1.0;
+      } else {
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        sh_tau = (beta - alpha) / beta;
+        sh_scale = 1.0 / (alpha - beta);
+        sh_beta = beta;
+      }
+      tau[j] = sh_tau;
+    }
+    __syncthreads();
+    const double tj = sh_tau, sc = sh_scale;
+    for (int i = j + 1 + threadIdx.x; i < m; i += BT) x[i] *= sc;
+    __syncthreads();
+    if (threadIdx.x == 0) x[j] = sh_beta;
+    if (tj != 0.0) {
+      for (int c = j + 1 + wv; c < n; c += BT / 64) {
+        double* y = A + static_cast<size_t>(c) * lda;
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w = fma(x[i], y[i], w);
+        w = wave_sum_f64(w);
+        w = tj * (w + y[j]);
+        if (lane == 0) y[j] -= w;
+        for (int i = j + 1 + lane; i < m; i += 64) y[i] = fma(-w, x[i], y[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(BT) void k_householder_form_q(const double* __restrict__ A, int m, int p, int lda,
+                                                           const double* __restrict__ tau, double* __restrict__ Q,
+                                                           int ldq) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (long long e = threadIdx.x; e < static_cast<long long>(m) * p; e += BT) {
+    const int i = static_cast<int>(e % m), c = static_cast<int>(e / m);
+    Q[i + static_cast<size_t>(c) * ldq] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = p - 1; j >= 0; --j) {
+    const double tj = tau[j];
+    const double* v = A + static_cast<size_t>(j) * lda;
+    if (tj != 0.0) {
+      for (int c = j + wv; c < p; c += BT / 64) {
+        double* y = Q + static_cast<size_t>(c) * ldq;
+        double w = 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) w = fma(v[i], y[i], w);
+        w = wave_sum_f64(w);
+        w = tj * (w + y[j]);
+        if (lane == 0) y[j] -= w;
+        for (int i = j + 1 + lane; i < m; i += 64) y[i] = fma(-w, v[i], y[i]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_extract_r(const double* __restrict__ A, int p, int n, int lda,
+                                                  double* __restrict__ R, int ldr) {
+  const long long e = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= static_cast<long long>(p) * n) return;
+  const int i = static_cast<int>(e % p), c = static_cast<int>(e / p);
+  const double sg = (A[i + static_cast<size_t>(i) * lda] < 0.0) ? -1.0 : 1.0;
+  R[i + static_cast<size_t>(c) * ldr] = (c >= i) ? sg * A[i + static_cast<size_t>(c) * lda] : 0.0;
+}
+
+__global__ __launch_bounds__(NT) void k_flip_q(const double* __restrict__ A, int m, int p, int lda,
+                                               double* __restrict__ Q, int ldq) {
+  const long long e = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= static_cast<long long>(m) * p) return;
+  const int i = static_cast<int>(e % m), c = static_cast<int>(e / m);
+  if (A[c + static_cast<size_t>(c) * lda] < 0.0) Q[i + static_cast<size_t>(c) * ldq] = -Q[i + static_cast<size_t>(c) * ldq];
+}
+
+// One-sided (Hestenes) Jacobi, one workgroup of 1024 threads = 64 groups of 16
+// lanes, one column pair per group per step, circle-method pair ordering.
+// The matrix and V live in LDS when they fit (use_lds), else in global memory.
+__global__ __launch_bounds__(BT) void k_jacobi(double* __restrict__ Ag, int rows, int c, int lda,
+                                               double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
+                                               int use_lds) {
+  extern __shared__ double sm[];
+  __shared__ int rotated;
+  double* A = Ag;
+  double* V = Vg;
+  int la = lda, lv = ldv;
+  if (use_lds) {
+    A = sm;
+    V = sm + static_cast<size_t>(rows) * c;
+    la = rows;
+    lv = c;
+    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += BT) {
+      const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+      A[i + static_cast<size_t>(j) * la] = Ag[i + static_cast<size_t>(j) * lda];
+    }
+  }
+  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += BT) {
+    const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+    V[i + static_cast<size_t>(j) * lv] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  const int N = c + (c & 1);  // players (a virtual empty column when c is odd)
+  const double tol = sqrt(static_cast<double>(rows)) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      for (int k = grp; k < N / 2; k += BT / 16) {
+        int p, q;
+        if (k == 0) {
+          p = rd;
+          q = N - 1;
+        } else {
+          p = (rd + k) % (N - 1);
+          q = (rd - k + (N - 1)) % (N - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q >= c) continue;  // pair with the virtual column (uniform within the group)
+        double* ap = A + static_cast<size_t>(p) * la;
+        double* aq = A + static_cast<size_t>(q) * la;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = gl; i < rows; i += 16) {
+          const double x = ap[i], y = aq[i];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          g = fma(x, y, g);
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, 16);
+          b += __shfl_xor(b, o, 16);
+          g += __shfl_xor(g, o, 16);
+        }
+        if (a == 0.0 || b == 0.0) continue;
+        if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t);
+        const double sn = cs * t;
+        for (int i = gl; i < rows; i += 16) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = cs * x - sn * y;
+          aq[i] = sn * x + cs * y;
+        }
+        double* vp = V + static_cast<size_t>(p) * lv;
+        double* vq = V + static_cast<size_t>(q) * lv;
+        for (int i = gl; i < c; i += 16) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = cs * x - sn * y;
+          vq[i] = sn * x + cs * y;
+        }
+        if (gl == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // column norms
+  for (int j = grp; j < c; j += BT / 16) {
+    const double* aj = A + static_cast<size_t>(j) * la;
+    double s = 0.0;
+    for (int i = gl; i < rows; i += 16) s = fma(aj[i], aj[i], s);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    if (gl == 0) sigma[j] = sqrt(s);
+  }
+  if (use_lds) {
+    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += BT) {
+      const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+      Ag[i + static_cast<size_t>(j) * lda] = A[i + static_cast<size_t>(j) * la];
+    }
+    for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += BT) {
+      const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+      Vg[i + static_cast<size_t>(j) * ldv] = V[i + static_cast<size_t>(j) * lv];
+    }
+  }
+}
+
+// Block-pair step of a one-sided block Jacobi sweep for wide matrices: workgroup w
+// takes the pair of column blocks given by the circle method for round `rd`,
+// stages both blocks of A (rows x 2b) and of V (c x 2b) in LDS, runs inner Jacobi
+// sweeps over their 2b columns (8 pairs at a time, 32 lanes per pair) until no
+// rotation happens (at most 4), and writes them back.  *flag |= any rotation.
+constexpr int BJ_B = 8;
+__global__ __launch_bounds__(NT) void k_bjacobi_round(double* __restrict__ Ag, int rows, int c, int lda,
+                                                      double* __restrict__ Vg, int ldv, int nb, int rd,
+                                                      int32_t* __restrict__ flag) {
+  extern __shared__ double sm[];
+  __shared__ int cols_idx[2 * BJ_B];
+  __shared__ int rot_any, rot_sweep;
+  const int w = blockIdx.x;
+  int P, Qb;
+  if (w == 0) {
+    P = rd;
+    Qb = nb - 1;
+  } else {
+    P = (rd + w) % (nb - 1);
+    Qb = (rd - w + (nb - 1)) % (nb - 1);
+  }
+  double* As = sm;                                           // rows x 2b
+  double* Vs = sm + static_cast<size_t>(rows) * 2 * BJ_B;   // c x 2b
+  if (threadIdx.x < 2 * BJ_B) {
+    const int blk = (threadIdx.x < BJ_B) ? P : Qb;
+    const int col = blk * BJ_B + (threadIdx.x % BJ_B);
+    cols_idx[threadIdx.x] = (col < c) ? col : -1;
+  }
+  if (threadIdx.x == 0) rot_any = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * 2 * BJ_B; e += NT) {
+    const int i = e % rows, j = e / rows;
+    const int col = cols_idx[j];
+    As[e] = (col >= 0) ? Ag[i + static_cast<size_t>(col) * lda] : 0.0;
+  }
+  for (int e = threadIdx.x; e < c * 2 * BJ_B; e += NT) {
+    const int i = e % c, j = e / c;
+    const int col = cols_idx[j];
+    Vs[e] = (col >= 0) ? Vg[i + static_cast<size_t>(col) * ldv] : 0.0;
+  }
+  __syncthreads();
+  const int grp = threadIdx.x >> 5, gl = threadIdx.x & 31;
+  constexpr int NL = 2 * BJ_B;
+  const double tol = sqrt(static_cast<double>(rows)) * 2.220446049250313e-16;
+  for (int inner = 0; inner < 4; ++inner) {
+    if (threadIdx.x == 0) rot_sweep = 0;
+    __syncthreads();
+    for (int r2 = 0; r2 < NL - 1; ++r2) {
+      const int k = grp;  // NL/2 = 8 pairs, 8 groups of 32 lanes
+      int p, q;
+      if (k == 0) {
+        p = r2;
+        q = NL - 1;
+      } else {
+        p = (r2 + k) % (NL - 1);
+        q = (r2 - k + (NL - 1)) % (NL - 1);
+      }
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      if (cols_idx[p] >= 0 && cols_idx[q] >= 0) {
+        double* ap = As + static_cast<size_t>(p) * rows;
+        double* aq = As + static_cast<size_t>(q) * rows;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = gl; i < rows; i += 32) {
+          const double x = ap[i], y = aq[i];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          g = fma(x, y, g);
+        }
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, 32);
+          b += __shfl_xor(b, o, 32);
+          g += __shfl_xor(g, o, 32);
+        }
+        if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          const double zeta = (b - a) / (2.0 * g);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int i = gl; i < rows; i += 32) {
+            const double x = ap[i], y = aq[i];
+            ap[i] = cs * x - sn * y;
+            aq[i] = sn * x + cs * y;
+          }
+          double* vp = Vs + static_cast<size_t>(p) * c;
+          double* vq = Vs + static_cast<size_t>(q) * c;
+          for (int i = gl; i < c; i += 32) {
+            const double x = vp[i], y = vq[i];
+            vp[i] = cs * x - sn * y;
+            vq[i] = sn * x + cs * y;
+          }
+          if (gl == 0) {
+            rot_sweep = 1;
+            rot_any = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!rot_sweep) break;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < rows * 2 * BJ_B; e += NT) {
+    const int i = e % rows, j = e / rows;
+    const int col = cols_idx[j];
+    if (col >= 0) Ag[i + static_cast<size_t>(col) * lda] = As[e];
+  }
+  for (int e = threadIdx.x; e < c * 2 * BJ_B; e += NT) {
+    const int i = e % c, j = e / c;
+    const int col = cols_idx[j];
+    if (col >= 0) Vg[i + static_cast<size_t>(col) * ldv] = Vs[e];
+  }
+  if (threadIdx.x == 0 && rot_any) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(NT) void k_eye(double* __restrict__ V, int c, int ldv) {
+  const long long e = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= static_cast<long long>(c) * c) return;
+  const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+  V[i + static_cast<size_t>(j) * ldv] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(NT) void k_col_norms(const double* __restrict__ A, int rows, int c, int lda,
+                                                  double* __restrict__ sigma) {
+  __shared__ double red[NT / 64];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < rows; i += NT) s = fma(A[i + static_cast<size_t>(j) * lda], A[i + static_cast<size_t>(j) * lda], s);
+  s = wave_sum_f64(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    sigma[j] = sqrt(t);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ A, int rows, int cols, int lda,
+                                             double* __restrict__ B, int ldb) {
+  const long long e = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= static_cast<long long>(rows) * cols) return;
+  const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+  B[i + static_cast<size_t>(j) * ldb] = A[i + static_cast<size_t>(j) * lda];
+}
+
+__global__ __launch_bounds__(NT) void k_transpose(const double* __restrict__ A, int rows, int cols, int lda,
+                                                  double* __restrict__ B, int ldb) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int i = bx + tx, j = by + k;
+    tile[k][tx] = (i < rows && j < cols) ? A[i + static_cast<size_t>(j) * lda] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int j = by + tx, i = bx + k;  // B[j, i] = A[i, j]
+    if (i < rows && j < cols) B[j + static_cast<size_t>(i) * ldb] = tile[tx][k];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_permute_cols(const double* __restrict__ A, int rows, int lda,
+                                                     const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ scale, double* __restrict__ B,
+                                                     int ldb) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  const int t = blockIdx.y;
+  if (i >= rows) return;
+  const double sc = scale ? scale[t] : 1.0;
+  B[i + static_cast<size_t>(t) * ldb] = A[i + static_cast<size_t>(perm[t]) * lda] * sc;
+}
+
+// One wave per column: entry of largest magnitude (lowest index on ties) made positive.
+__global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int rows, int r, int ldu,
+                                                 double* __restrict__ VS, int vrows, int ldv) {
+  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= r) return;
+  double* u = U + static_cast<size_t>(j) * ldu;
+  double best = -1.0;
+  int bi = rows;
+  for (int i = lane; i < rows; i += 64) {
+    const double a = fabs(u[i]);
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (bi >= rows || u[bi] >= 0.0) return;
+  for (int i = lane; i < rows; i += 64) u[i] = -u[i];
+  double* v = VS + static_cast<size_t>(j) * ldv;
+  for (int i = lane; i < vrows; i += 64) v[i] = -v[i];
+}
+
+}  // namespace
+
+void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  const int tm = (m + GT - 1) / GT, tn = (n + GT - 1) / GT;
+  const int tiles = tm * tn;
+  int ns = 1;
+  if (tiles < 128 && k > 512) ns = std::min({(k + 255) / 256, std::max(1, 256 / tiles), 64});
+  int kchunk = (k + ns - 1) / ns;
+  kchunk = ((kchunk + GK - 1) / GK) * GK;
+  if (kchunk == 0) kchunk = GK;
+  ns = std::max(1, (k + kchunk - 1) / kchunk);
+  if (ns == 1) {
+    k_gemm<<<dim3(tm, tn, 1), NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk > k ? kchunk : k,
+                                          nullptr);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  DBuf<double> part(al, static_cast<size_t>(ns) * m * n);
+  k_gemm<<<dim3(tm, tn, ns), NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part.get());
+  TTS_LAUNCH_CHECK();
+  const size_t mn = static_cast<size_t>(m) * n;
+  k_gemm_reduce<<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+  TTS_LAUNCH_CHECK();
+}
+
+void spmm_left(const double* W, int r, int ldw, const int64_t* colptr, const int32_t* row, const double* val,
+               int ncols, int nk, double* X, int ldx, hipStream_t s) {
+  if (r <= 0 || ncols <= 0) return;
+  k_spmm_left<<<dim3(grid_for(r, NT), ncols), NT, 0, s>>>(W, r, ldw, colptr, row, val, nk, X, ldx);
+  TTS_LAUNCH_CHECK();
+}
+
+void right_weights(Allocator* al, const int64_t* colptr, const int32_t* row, const double* val, int ncols,
+                   uint32_t nnz, int nk, int ngroups, const double* wnext, double* w, hipStream_t s) {
+  DBuf<uint64_t> key(al, nnz), ent(al, nnz), kt(al, nnz), vt(al, nnz);
+  DBuf<uint32_t> ecol(al, nnz);
+  k_expand_cols<<<grid_for(ncols, NT), NT, 0, s>>>(colptr, ncols, row, key.get(), ent.get(), ecol.get());
+  TTS_LAUNCH_CHECK();
+  int bits = 0;
+  while (bits < 63 && (static_cast<uint64_t>(ngroups) * nk - 1) >> bits) ++bits;
+  radix_sort_pairs(al, key.get(), ent.get(), kt.get(), vt.get(), nnz, bits, s);
+  k_group_weights<<<grid_for(ngroups, NT), NT, 0, s>>>(key.get(), ent.get(), nnz, nk, ngroups, val, ecol.get(), wnext,
+                                                       w);
+  TTS_LAUNCH_CHECK();
+}
+
+void row_sumsq(const double* G, int ngroups, int nk, double* w, hipStream_t s) {
+  k_row_sumsq<<<grid_for(ngroups, NT), NT, 0, s>>>(G, ngroups, nk, w);
+  TTS_LAUNCH_CHECK();
+}
+
+void scale_cols_sqrt(const double* X, int rows, int cols, int ldx, const double* w, double* Y, int ldy,
+                     hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  k_scale_cols<<<dim3(grid_for(rows, NT), cols), NT, 0, s>>>(X, rows, ldx, nullptr, w, Y, ldy);
+  TTS_LAUNCH_CHECK();
+}
+
+void gather_cols(const double* X, int rows, int ldx, const int32_t* piv, int r, const double* w, double* Y, int ldy,
+                 hipStream_t s) {
+  if (rows <= 0 || r <= 0) return;
+  k_scale_cols<<<dim3(grid_for(rows, NT), r), NT, 0, s>>>(X, rows, ldx, piv, w, Y, ldy);
+  TTS_LAUNCH_CHECK();
+}
+
+void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, double* L, int32_t* piv, int32_t* d_r,
+                      hipStream_t s) {
+  const size_t shm = sizeof(double) * (static_cast<size_t>(n) + rmax);
+  if (shm > 150 * 1024) fail(TT_ERR_TOO_LARGE, "pivoted Cholesky: Gram matrix too large for one workgroup");
+  k_pivoted_cholesky<<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  TTS_LAUNCH_CHECK();
+}
+
+void pivot_factor(const double* L, int n, const int32_t* piv, int r, double* U, hipStream_t s) {
+  k_pivot_factor<<<grid_for(static_cast<size_t>(r) * r, NT), NT, 0, s>>>(L, n, piv, r, U);
+  TTS_LAUNCH_CHECK();
+}
+
+void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, hipStream_t s) {
+  k_cholesky_upper<<<1, BT, 0, s>>>(A, r, lda, max_ratio, d_ok);
+  TTS_LAUNCH_CHECK();
+}
+
+void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t* d_ok, hipStream_t s) {
+  k_triu_inverse<<<grid_for(r, NT), NT, 0, s>>>(U, r, ldu, Ui, ldi, d_ok);
+  TTS_LAUNCH_CHECK();
+}
+
+void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde, const double* w, double* d_out,
+                    hipStream_t s) {
+  DBuf<double> cs(al, std::max(cols, 1));
+  if (cols > 0) {
+    k_col_sumsq<<<cols, NT, 0, s>>>(E, rows, lde, cs.get());
+    TTS_LAUNCH_CHECK();
+  }
+  k_weighted_total<<<1, NT, 0, s>>>(cs.get(), w, cols, d_out);
+  TTS_LAUNCH_CHECK();
+}
+
+void householder_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  k_householder_qr<<<1, BT, 0, s>>>(A, m, n, lda, tau);
+  TTS_LAUNCH_CHECK();
+}
+
+void householder_form_q(const double* A, int m, int p, int lda, const double* tau, double* Q, int ldq, hipStream_t s) {
+  if (m <= 0 || p <= 0) return;
+  k_householder_form_q<<<1, BT, 0, s>>>(A, m, p, lda, tau, Q, ldq);
+  TTS_LAUNCH_CHECK();
+}
+
+void householder_extract_r(const double* A, int m, int n, int lda, double* R, int ldr, double* Q, int ldq,
+                           hipStream_t s) {
+  const int p = std::min(m, n);
+  if (p <= 0) return;
+  k_extract_r<<<grid_for(static_cast<size_t>(p) * n, NT), NT, 0, s>>>(A, p, n, lda, R, ldr);
+  TTS_LAUNCH_CHECK();
+  if (Q) {
+    k_flip_q<<<grid_for(static_cast<size_t>(m) * p, NT), NT, 0, s>>>(A, m, p, lda, Q, ldq);
+    TTS_LAUNCH_CHECK();
+  }
+}
+
+void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, hipStream_t s) {
+  if (c <= 0) return;
+  const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
+  if (shm <= 150 * 1024 || c <= 2 * BJ_B) {
+    const int use_lds = shm <= 150 * 1024;
+    k_jacobi<<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  // wide: block Jacobi, one launch per round of block pairs
+  const size_t bshm = sizeof(double) * 2 * BJ_B * (static_cast<size_t>(rows) + c);
+  if (bshm > 150 * 1024) fail(TT_ERR_TOO_LARGE, "Jacobi SVD: matrix too large for the block kernel");
+  int nb = (c + BJ_B - 1) / BJ_B;
+  nb += nb & 1;
+  k_eye<<<grid_for(static_cast<size_t>(c) * c, NT), NT, 0, s>>>(V, c, ldv);
+  TTS_LAUNCH_CHECK();
+  int32_t* flag = nullptr;
+  TTS_HIP(hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(int32_t), s));
+  int32_t hflag = 1;
+  for (int sweep = 0; sweep < 60 && hflag; ++sweep) {
+    TTS_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    for (int rd = 0; rd < nb - 1; ++rd) {
+      k_bjacobi_round<<<nb / 2, NT, bshm, s>>>(A, rows, c, lda, V, ldv, nb, rd, flag);
+      TTS_LAUNCH_CHECK();
+    }
+    TTS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipStreamSynchronize(s));
+  }
+  TTS_HIP(hipFreeAsync(flag, s));
+  k_col_norms<<<c, NT, 0, s>>>(A, rows, c, lda, sigma);
+  TTS_LAUNCH_CHECK();
+}
+
+void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  k_copy<<<grid_for(static_cast<size_t>(rows) * cols, NT), NT, 0, s>>>(A, rows, cols, lda, B, ldb);
+  TTS_LAUNCH_CHECK();
+}
+
+void transpose(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  k_transpose<<<dim3((rows + 31) / 32, (cols + 31) / 32), NT, 0, s>>>(A, rows, cols, lda, B, ldb);
+  TTS_LAUNCH_CHECK();
+}
+
+void permute_cols(const double* A, int rows, int lda, const int32_t* perm, const double* scale, int cols, double* B,
+                  int ldb, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  k_permute_cols<<<dim3(grid_for(rows, NT), cols), NT, 0, s>>>(A, rows, lda, perm, scale, B, ldb);
+  TTS_LAUNCH_CHECK();
+}
+
+void sign_fix(double* U, int rows, int r, int ldu, double* VS, int vrows, int ldv, hipStream_t s) {
+  if (r <= 0) return;
+  k_sign_fix<<<(r + 3) / 4, NT, 0, s>>>(U, rows, r, ldu, VS, vrows, ldv);
+  TTS_LAUNCH_CHECK();
+}
+
+}  // namespace tts

@@ -1,10 +1,288 @@
-// TT-rounding of the exact sparse TT (placeholder until the dense sweeps land).
+// TT-rounding of the exact sparse TT: a left-to-right orthogonalisation (QR) sweep,
+// then a right-to-left delta-truncated SVD sweep (Algorithm 2 run mirrored; at
+// p = d the second sweep is Algorithm 6's right-to-left SVD sweep).
+//
+// Structure used by the left-to-right sweep.  In the exact TT built by
+// parallel-vector rounding, every column of a transfer matrix T_k (one column per
+// suffix (i_{k+1},...,i_d)) has exactly one nonzero -- the prefactor of that
+// column in its group -- and the product of the later cores reproduces T_k
+// structurally.  Hence T_k T_k^T = diag(w_k) with w_k[g] the squared norm of row g,
+// and T_k = D_k Theta_k with D_k = diag(sqrt(w_k)) and Theta_k row-orthonormal.
+// With the left part already orthonormal, the bond-k unfolding of A is
+// (orthonormal) * (X_k D_k) * (orthonormal), X_k = W_{k-1} x_1 N_k.  So an
+// orthonormal basis Q_k of X_k D_k that leaves a residual ||X_k D_k - Q Q^T X_k D_k||_F
+// <= tau changes the represented tensor by exactly that residual.  The sweep uses
+// this to drop directions whose whole weight is below tau (numerically zero
+// directions of rank-deficient unfoldings) with a certified, exactly accounted
+// error, so the later sweep works on the numerical ranks instead of the larger
+// ranks of the exact sparse TT.  The basis comes from a pivoted Cholesky of the
+// Gram matrix of X_k D_k and two CholeskyQR passes over the pivot columns; when the
+// residual check fails (or tau = 0) the sweep falls back to an exact Householder QR.
+//
+// The truncated-SVD sweep orthogonalises unfold_1^T of each core (CholeskyQR2, or
+// Householder when the Gram factor is ill-conditioned), takes a one-sided Jacobi
+// SVD of the small R factor, keeps the smallest rank whose discarded sum of
+// sigma^2 is <= delta^2 (or max_rank), makes the largest entry of every kept left
+// singular vector positive and merges V*Sigma into the left neighbour.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
 #include "dense.hpp"
+#include "linalg.hpp"
 
 namespace tts {
 
-void round_tt(Allocator&, const RoundInput&, RoundOutput&, hipStream_t, hipEvent_t) {
-  fail(TT_ERR_ARG, "rounding not available in this build (use sparse_only)");
+namespace {
+
+constexpr double kTheta = 1e-12;   // pivot threshold relative to the largest Gram diagonal
+constexpr double kTauRel = 1e-13;  // per-bond deflation budget relative to ||A||_F
+
+__global__ void k_set_f64(double* p, double v) { *p = v; }
+__global__ void k_set_i32(int32_t* p, int n, int32_t v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+template <class T>
+void d2h(T* host, const T* dev, size_t n, hipStream_t s) {
+  TTS_HIP(hipMemcpyAsync(host, dev, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  TTS_HIP(hipStreamSynchronize(s));
+}
+
+template <class T>
+void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
+  TTS_HIP(hipMemcpyAsync(dev, host, sizeof(T) * n, hipMemcpyHostToDevice, s));
+}
+
+// CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
+// Returns false when a Cholesky factor breaks down or is too ill-conditioned.
+bool cholqr2(Allocator* al, const double* G, int m, int c, double* Q, double* R, hipStream_t s) {
+  DBuf<double> g1(al, static_cast<size_t>(c) * c), u1i(al, static_cast<size_t>(c) * c),
+      q1(al, static_cast<size_t>(m) * c), g2(al, static_cast<size_t>(c) * c), u2i(al, static_cast<size_t>(c) * c);
+  DBuf<int32_t> ok(al, 4);
+  k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
+  TTS_LAUNCH_CHECK();
+  gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
+  cholesky_upper(g1.get(), c, c, 1e7, ok.get() + 0, s);
+  triu_inverse(g1.get(), c, c, u1i.get(), c, ok.get() + 1, s);
+  gemm(al, false, false, m, c, c, 1.0, G, m, u1i.get(), c, 0.0, q1.get(), m, s);
+  gemm(al, true, false, c, c, m, 1.0, q1.get(), m, q1.get(), m, 0.0, g2.get(), c, s);
+  cholesky_upper(g2.get(), c, c, 10.0, ok.get() + 2, s);
+  triu_inverse(g2.get(), c, c, u2i.get(), c, ok.get() + 3, s);
+  gemm(al, false, false, m, c, c, 1.0, q1.get(), m, u2i.get(), c, 0.0, Q, m, s);
+  gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
+  int32_t h[4];
+  d2h(h, ok.get(), 4, s);
+  return h[0] && h[1] && h[2] && h[3];
+}
+
+}  // namespace
+
+void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid) {
+  if (in.precision != TT_FP64) fail(TT_ERR_ARG, "mixed-precision rounding is not available in this build");
+  const int d = in.d;
+  std::vector<int> n(d), beta(d + 1);
+  for (int k = 0; k < d; ++k) n[k] = static_cast<int>(in.dims[k]);
+  for (int k = 0; k <= d; ++k) beta[k] = static_cast<int>(in.betas[k]);
+  for (int k = 1; k <= d; ++k) {
+    const double sz = static_cast<double>(beta[k - 1]) * n[k - 1] * beta[k];
+    if (beta[k] > 16384 || static_cast<double>(beta[k - 1]) * n[k - 1] > 2.0e9 || sz > 4.0e9)
+      fail(TT_ERR_TOO_LARGE, "exact sparse TT too large to round on one device (bond " + std::to_string(k) + ")");
+  }
+  Allocator* A = &al;
+
+  // Row norms of the transfer matrices (right parts): w[k] for bonds k = 1..d-1.
+  std::vector<DBuf<double>> w(d);
+  w[d - 1].reset(A, beta[d - 1]);
+  row_sumsq(in.last_core, beta[d - 1], n[d - 1], w[d - 1].get(), s);
+  for (int k = d - 2; k >= 1; --k) {
+    w[k].reset(A, beta[k]);
+    right_weights(A, in.n_colptr[k], in.n_row[k], in.n_val[k], beta[k + 1], in.n_nnz[k], n[k], beta[k],
+                  w[k + 1].get(), w[k].get(), s);
+  }
+
+  const double tau = std::min(1e-2 * in.delta, kTauRel * in.norm);
+  std::vector<int64_t> r(d + 1, 1);
+  std::vector<DBuf<char>> cores(d);
+
+  // ---------------- left-to-right sweep ----------------
+  DBuf<double> W(A, 1);
+  k_set_f64<<<1, 1, 0, s>>>(W.get(), 1.0);
+  TTS_LAUNCH_CHECK();
+  int rp = 1;
+  for (int k = 1; k <= d - 1; ++k) {
+    const int nk = n[k - 1];
+    const int rows = rp * nk, cols = beta[k];
+    DBuf<double> X(A, static_cast<size_t>(rows) * cols);
+    TTS_HIP(hipMemsetAsync(X.get(), 0, sizeof(double) * rows * cols, s));
+    spmm_left(W.get(), rp, rp, in.n_colptr[k - 1], in.n_row[k - 1], in.n_val[k - 1], cols, nk, X.get(), rows, s);
+
+    DBuf<double> Q, Wn;
+    int rk = 0;
+    bool accepted = false;
+    if (tau > 0.0) {
+      DBuf<double> Y(A, static_cast<size_t>(rows) * cols), G(A, static_cast<size_t>(cols) * cols);
+      scale_cols_sqrt(X.get(), rows, cols, rows, w[k].get(), Y.get(), rows, s);
+      gemm(A, true, false, cols, cols, rows, 1.0, Y.get(), rows, Y.get(), rows, 0.0, G.get(), cols, s);
+      const int rmax = std::min(rows, cols);
+      DBuf<double> L(A, static_cast<size_t>(cols) * rmax);
+      DBuf<int32_t> piv(A, rmax), cnt(A, 1);
+      pivoted_cholesky(G.get(), cols, cols, rmax, kTheta, L.get(), piv.get(), cnt.get(), s);
+      int32_t rsel = 0;
+      d2h(&rsel, cnt.get(), 1, s);
+      if (rsel > 0) {
+        DBuf<double> Ys(A, static_cast<size_t>(rows) * rsel), U1(A, static_cast<size_t>(rsel) * rsel),
+            U1i(A, static_cast<size_t>(rsel) * rsel), Q1(A, static_cast<size_t>(rows) * rsel),
+            G2(A, static_cast<size_t>(rsel) * rsel), U2i(A, static_cast<size_t>(rsel) * rsel);
+        DBuf<int32_t> ok(A, 4);
+        DBuf<double> e2(A, 1);
+        k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
+        TTS_LAUNCH_CHECK();
+        gather_cols(X.get(), rows, rows, piv.get(), rsel, w[k].get(), Ys.get(), rows, s);
+        pivot_factor(L.get(), cols, piv.get(), rsel, U1.get(), s);
+        triu_inverse(U1.get(), rsel, rsel, U1i.get(), rsel, ok.get() + 1, s);
+        gemm(A, false, false, rows, rsel, rsel, 1.0, Ys.get(), rows, U1i.get(), rsel, 0.0, Q1.get(), rows, s);
+        gemm(A, true, false, rsel, rsel, rows, 1.0, Q1.get(), rows, Q1.get(), rows, 0.0, G2.get(), rsel, s);
+        cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
+        triu_inverse(G2.get(), rsel, rsel, U2i.get(), rsel, ok.get() + 3, s);
+        Q.reset(A, static_cast<size_t>(rows) * rsel);
+        gemm(A, false, false, rows, rsel, rsel, 1.0, Q1.get(), rows, U2i.get(), rsel, 0.0, Q.get(), rows, s);
+        Wn.reset(A, static_cast<size_t>(rsel) * cols);
+        gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
+        // residual of the basis, weighted by the right-part row norms
+        DBuf<double> E(A, static_cast<size_t>(rows) * cols);
+        copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s);
+        gemm(A, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s);
+        weighted_sumsq(A, E.get(), rows, cols, rows, w[k].get(), e2.get(), s);
+        int32_t okh[4];
+        double e2h = 0.0;
+        TTS_HIP(hipMemcpyAsync(okh, ok.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
+        d2h(&e2h, e2.get(), 1, s);
+        // fixed-rank truncation keeps min(max_rank, #nonzero sigma): deflating below
+        // max_rank would drop numerically tiny but nonzero directions it keeps
+        const bool rank_ok = in.max_rank <= 0 || rsel >= in.max_rank;
+        if (okh[1] && okh[2] && okh[3] && e2h <= tau * tau && rank_ok) {
+          accepted = true;
+          rk = rsel;
+        }
+      }
+    }
+    if (!accepted) {
+      // exact Householder QR of X_k
+      const int p = std::min(rows, cols);
+      DBuf<double> Af(A, static_cast<size_t>(rows) * cols), th(A, p);
+      copy_matrix(X.get(), rows, cols, rows, Af.get(), rows, s);
+      householder_qr(Af.get(), rows, cols, rows, th.get(), s);
+      Q.reset(A, static_cast<size_t>(rows) * p);
+      householder_form_q(Af.get(), rows, p, rows, th.get(), Q.get(), rows, s);
+      Wn.reset(A, static_cast<size_t>(p) * cols);
+      householder_extract_r(Af.get(), rows, cols, rows, Wn.get(), p, Q.get(), rows, s);
+      rk = p;
+    }
+    // core k = Q reshaped to [r_{k-1}][n_k][r_k] (row-major) = Q^T column-major
+    cores[k - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * rk);
+    transpose(Q.get(), rows, rk, rows, reinterpret_cast<double*>(cores[k - 1].get()), rk, s);
+    W = std::move(Wn);
+    rp = rk;
+    r[k] = rk;
+  }
+  {
+    // last core: W (r_{d-1} x beta_{d-1}) times the exact last core (beta_{d-1} x n_d)
+    const int nd = n[d - 1], bl = beta[d - 1];
+    DBuf<double> C(A, static_cast<size_t>(rp) * nd);
+    gemm(A, false, true, rp, nd, bl, 1.0, W.get(), rp, in.last_core, nd, 0.0, C.get(), rp, s);
+    cores[d - 1].reset(A, sizeof(double) * static_cast<size_t>(rp) * nd);
+    transpose(C.get(), rp, nd, rp, reinterpret_cast<double*>(cores[d - 1].get()), nd, s);
+  }
+  out.qr_ranks = r;
+  TTS_HIP(hipEventRecord(mid, s));
+
+  // ---------------- right-to-left truncated SVD sweep ----------------
+  out.sigma.assign(d - 1, {});
+  out.tail.assign(d - 1, 0.0);
+  const double delta2 = in.delta * in.delta;
+  for (int k = d; k >= 2; --k) {
+    const int rl = static_cast<int>(r[k - 1]), nk = n[k - 1], rr = static_cast<int>(r[k]);
+    const int m = nk * rr;
+    double* Gk = reinterpret_cast<double*>(cores[k - 1].get());  // column-major m x rl
+    DBuf<double> Qb, B;
+    int rowsB = m;
+    bool haveQ = false;
+    if (m > rl) {
+      Qb.reset(A, static_cast<size_t>(m) * rl);
+      B.reset(A, static_cast<size_t>(rl) * rl);
+      if (!cholqr2(A, Gk, m, rl, Qb.get(), B.get(), s)) {
+        DBuf<double> Af(A, static_cast<size_t>(m) * rl), th(A, rl);
+        copy_matrix(Gk, m, rl, m, Af.get(), m, s);
+        householder_qr(Af.get(), m, rl, m, th.get(), s);
+        householder_form_q(Af.get(), m, rl, m, th.get(), Qb.get(), m, s);
+        householder_extract_r(Af.get(), m, rl, m, B.get(), rl, Qb.get(), m, s);
+      }
+      rowsB = rl;
+      haveQ = true;
+    } else {
+      B.reset(A, static_cast<size_t>(m) * rl);
+      copy_matrix(Gk, m, rl, m, B.get(), m, s);
+    }
+    DBuf<double> V(A, static_cast<size_t>(rl) * rl), sig(A, rl);
+    jacobi_svd(B.get(), rowsB, rl, rowsB, V.get(), rl, sig.get(), s);
+    std::vector<double> sh(rl);
+    d2h(sh.data(), sig.get(), rl, s);
+    std::vector<int32_t> perm(rl);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return sh[x] > sh[y]; });
+    std::vector<double> ss(rl), tailsum(rl + 1, 0.0);
+    for (int j = 0; j < rl; ++j) ss[j] = sh[perm[j]];
+    for (int j = rl - 1; j >= 0; --j) tailsum[j] = tailsum[j + 1] + ss[j] * ss[j];
+    int rk;
+    if (in.max_rank > 0) {
+      int nz = 0;
+      for (double x : ss) nz += (x > 0.0);
+      rk = std::max(1, std::min(in.max_rank, nz));
+    } else {
+      rk = rl;
+      for (int c = 1; c <= rl; ++c)
+        if (tailsum[c] <= delta2) {
+          rk = c;
+          break;
+        }
+    }
+    out.sigma[k - 2] = ss;
+    out.tail[k - 2] = tailsum[rk];
+    std::vector<double> inv(rk), sc(rk);
+    for (int j = 0; j < rk; ++j) {
+      inv[j] = 1.0 / ss[j];
+      sc[j] = ss[j];
+    }
+    DBuf<int32_t> dperm(A, rk);
+    DBuf<double> dinv(A, rk), dsc(A, rk);
+    h2d(dperm.get(), perm.data(), rk, s);
+    h2d(dinv.get(), inv.data(), rk, s);
+    h2d(dsc.get(), sc.data(), rk, s);
+    DBuf<double> UR(A, static_cast<size_t>(rowsB) * rk), VS(A, static_cast<size_t>(rl) * rk);
+    permute_cols(B.get(), rowsB, rowsB, dperm.get(), dinv.get(), rk, UR.get(), rowsB, s);
+    permute_cols(V.get(), rl, rl, dperm.get(), dsc.get(), rk, VS.get(), rl, s);
+    DBuf<char> Unew(A, sizeof(double) * static_cast<size_t>(m) * rk);
+    double* U = reinterpret_cast<double*>(Unew.get());
+    if (haveQ)
+      gemm(A, false, false, m, rk, rl, 1.0, Qb.get(), m, UR.get(), rl, 0.0, U, m, s);
+    else
+      copy_matrix(UR.get(), m, rk, m, U, m, s);
+    sign_fix(U, m, rk, m, VS.get(), rl, rl, s);
+    // merge V*Sigma into core k-1: unfold_2(G_{k-1}) (rows2 x rl) * VS (rl x rk)
+    const int rows2 = static_cast<int>(r[k - 2]) * n[k - 2];
+    DBuf<char> Pnew(A, sizeof(double) * static_cast<size_t>(rows2) * rk);
+    gemm(A, true, false, rk, rows2, rl, 1.0, VS.get(), rl, reinterpret_cast<double*>(cores[k - 2].get()), rl, 0.0,
+         reinterpret_cast<double*>(Pnew.get()), rk, s);
+    cores[k - 1] = std::move(Unew);
+    cores[k - 2] = std::move(Pnew);
+    r[k - 1] = rk;
+    TTS_HIP(hipStreamSynchronize(s));  // host vectors above are read by the copies
+  }
+  out.ranks = r;
+  out.cores = std::move(cores);
+  out.dtype = TT_DTYPE_F64;
 }
 
 }  // namespace tts
