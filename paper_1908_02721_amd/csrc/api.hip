@@ -21,6 +21,11 @@ thread_local std::string g_last_error;
 thread_local DevStatus* g_host_status = nullptr;
 
 void set_error(const std::string& m) { g_last_error = m; }
+}  // namespace
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
 
 DevStatus* host_status() {
   if (!g_host_status) {

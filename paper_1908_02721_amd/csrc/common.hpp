@@ -21,6 +21,8 @@ struct Error {
 };
 
 [[noreturn]] void fail(tt_status s, const std::string& msg);
+// Message returned by tt_last_error() on the calling thread.
+void set_last_error(const std::string& msg);
 
 #define TTS_HIP(x)                                                                         \
   do {                                                                                     \

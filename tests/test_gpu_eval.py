@@ -1,0 +1,145 @@
+"""GPU parity of sampled-entry evaluation (forward) and its hand-written backward.
+
+FP64 kernels against the FP64 oracle: relative 1e-12 (different summation order
+only).  FP32 kernels against the FP64 oracle: relative L2 error <= 1e-5 (chains of
+d vector-matrix products with rank <= 64 in binary32, unit roundoff 6e-8).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _tts():
+    import paper_1908_02721_amd as tts
+
+    return tts
+
+
+def _rand_tt(rng, dims, ranks, scale=None):
+    r = [1] + list(ranks) + [1]
+    cores = []
+    for k, n in enumerate(dims):
+        s = scale if scale is not None else 1.0 / np.sqrt(r[k])
+        cores.append(rng.standard_normal((r[k], n, r[k + 1])) * s)
+    return cores
+
+
+def _idx(rng, dims, m):
+    return np.stack([rng.integers(0, n, m) for n in dims], 1).astype(np.int32)
+
+
+def _cuda(cores, dtype):
+    return [torch.from_numpy(np.ascontiguousarray(c)).to(dtype).cuda() for c in cores]
+
+
+CFGS = [
+    ("d4r5", (6, 7, 5, 4), (5, 3, 6), 3000),
+    ("d8r32", (32,) * 8, (32,) * 7, 20000),
+    ("d5r64", (9, 8, 7, 6, 5), (40, 64, 50, 20), 5000),
+    ("d3r200", (5, 6, 7), (150, 200), 2000),
+    ("d2", (11, 13), (9,), 1000),
+]
+
+
+@pytest.mark.parametrize("name,dims,ranks,m", CFGS)
+def test_forward_fp64_and_fp32(oracle_mod, name, dims, ranks, m):
+    tts = _tts()
+    print(f"[eval fwd] {name}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(len(name)))
+    cores = _rand_tt(rng, dims, ranks)
+    idx = _idx(rng, dims, m)
+    ref = oracle_mod.eval_entries(cores, idx)
+    gi = torch.from_numpy(idx).cuda()
+    y64 = tts.eval_entries(_cuda(cores, torch.float64), gi).cpu().numpy()
+    scale = np.linalg.norm(ref) / np.sqrt(m)
+    assert np.max(np.abs(y64 - ref)) <= 1e-12 * max(scale, 1.0)
+    y32 = tts.eval_entries(_cuda(cores, torch.float32), gi).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(y32 - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name,dims,ranks,m", CFGS)
+def test_backward_fp64_and_fp32(oracle_mod, name, dims, ranks, m):
+    tts = _tts()
+    print(f"[eval bwd] {name}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(100 + len(name)))
+    cores = _rand_tt(rng, dims, ranks)
+    m = min(m, 4000)
+    idx = _idx(rng, dims, m)
+    gy = rng.standard_normal(m)
+    ref = oracle_mod.eval_grad(cores, idx, gy)
+    gi = torch.from_numpy(idx).cuda()
+    g64 = tts.eval_entries_backward(_cuda(cores, torch.float64), gi, torch.from_numpy(gy).cuda())
+    for k, (a, b) in enumerate(zip(g64, ref)):
+        a = a.cpu().numpy()
+        assert np.max(np.abs(a - b)) <= 1e-12 * max(1.0, np.max(np.abs(b))), f"core {k}"
+    g32 = tts.eval_entries_backward(_cuda(cores, torch.float32), gi, torch.from_numpy(gy).float().cuda())
+    for k, (a, b) in enumerate(zip(g32, ref)):
+        a = a.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), f"core {k} fp32"
+
+
+def test_backward_finite_differences():
+    tts = _tts()
+    rng = np.random.Generator(np.random.PCG64(3))
+    dims, ranks = (5, 4, 6, 3), (3, 4, 2)
+    cores = _cuda(_rand_tt(rng, dims, ranks), torch.float64)
+    idx = torch.from_numpy(_idx(rng, dims, 300)).cuda()
+    a = torch.from_numpy(rng.standard_normal(300)).cuda()
+
+    def loss(cs):
+        return torch.sum((tts.eval_entries(cs, idx) - a) ** 2).item()
+
+    y = tts.eval_entries(cores, idx)
+    grads = tts.eval_entries_backward(cores, idx, 2.0 * (y - a))
+    checked = 0
+    for k in range(len(cores)):
+        flat = cores[k].view(-1)
+        for e in rng.choice(flat.numel(), min(flat.numel(), 24), replace=False):
+            h = 1e-6 * max(1.0, abs(flat[e].item()))
+            old = flat[e].item()
+            flat[e] = old + h
+            lp = loss(cores)
+            flat[e] = old - h
+            lm = loss(cores)
+            flat[e] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[k].view(-1)[e].item()
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+            checked += 1
+    assert checked >= 64
+
+
+def test_autograd_function_gradcheck():
+    tts = _tts()
+    rng = np.random.Generator(np.random.PCG64(4))
+    dims, ranks = (3, 4, 3), (2, 3)
+    cores = [c.requires_grad_() for c in _cuda(_rand_tt(rng, dims, ranks), torch.float64)]
+    idx = torch.from_numpy(_idx(rng, dims, 40)).cuda()
+    assert torch.autograd.gradcheck(lambda *cs: tts.EvalEntries.apply(idx, *cs), cores, eps=1e-6, atol=1e-8)
+
+
+def test_deterministic_backward_and_errors():
+    tts = _tts()
+    rng = np.random.Generator(np.random.PCG64(5))
+    dims, ranks = (32,) * 6, (16,) * 5
+    cores = _cuda(_rand_tt(rng, dims, ranks), torch.float32)
+    idx = torch.from_numpy(_idx(rng, dims, 50000)).cuda()
+    gy = torch.randn(50000, device="cuda")
+    g1 = tts.eval_entries_backward(cores, idx, gy)
+    g2 = tts.eval_entries_backward(cores, idx, gy)
+    for a, b in zip(g1, g2):
+        assert torch.equal(a, b)
+    bad = idx.clone()
+    bad[7, 3] = 32
+    with pytest.raises(tts.TTError) as e:
+        tts.eval_entries(cores, bad)
+    assert e.value.status == "TT_ERR_INDEX"
+    with pytest.raises(tts.TTError) as e:
+        tts.eval_entries_backward(cores, bad, gy)
+    assert e.value.status == "TT_ERR_INDEX"
+    empty = idx[:0]
+    assert tts.eval_entries(cores, empty).numel() == 0
+    gz = tts.eval_entries_backward(cores, empty, gy[:0])
+    assert all(float(g.abs().max()) == 0.0 for g in gz)
