@@ -1,0 +1,166 @@
+"""Benchmark of the sparse TT decomposition hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
+
+One step is one pass of the whole hot path over the workload's nonzeros, all in
+libttsparse kernels:
+  tt_sparse_decompose   ingest, sort, parallel-vector rounding of every level,
+                        left-to-right QR sweep, right-to-left truncated-SVD sweep
+  tt_eval_entries       the TT at every nonzero coordinate
+  tt_eval_entries_backward  gradient of sum_n val[n] * TT(i_n) w.r.t. every core
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "nonzeros decomposed/sec at fixed eps (FP64 vs mixed) + HBM/MFMA roofline %"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+# Kernel family that dominates one step (per the rocprofv3 kernel-trace summaries
+# under profiles/), and what bounds it.
+DOMINANT = "eval_grad"
+FAMILY_BOUND = {
+    "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "gemm": "alu", "jacobi": "alu",
+    "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm",
+}
+
+
+def _parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="kron8d_n32_t64")
+    p.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
+    p.add_argument("--roofline", default=DOMINANT, help="kernel family timed live for the roofline object")
+    return p.parse_args()
+
+
+def cpu_baseline(idx, val, dims, eps, sample):
+    """The oracle (single-threaded FP64 C++), timed on this host on a bounded sample."""
+    import oracle
+
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    res = oracle.decompose(idx, val, dims, eps)
+    t_dec = time.perf_counter() - t0
+    rng = np.random.Generator(np.random.PCG64(11))
+    pick = rng.choice(len(val), min(sample, len(val)), replace=False)
+    t0 = time.perf_counter()
+    y = oracle.eval_entries(res.cores, idx[pick])
+    oracle.eval_grad(res.cores, idx[pick], val[pick])
+    t_eval = time.perf_counter() - t0
+    del y
+    t_step = t_dec + t_eval * (len(val) / len(pick))
+    return {
+        "value": len(val) / t_step,
+        "unit": "nnz/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"full decomposition of the workload ({t_dec:.2f} s) + eval/backward on {len(pick)} of "
+                   f"{len(val)} nonzeros ({t_eval:.2f} s, scaled linearly to all nonzeros)"),
+    }
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is design-only.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1908_02721_amd as tts
+    from paper_1908_02721_amd import synth
+
+    idx, val, dims, eps = synth.workload(args.workload)
+    nnz = len(val)
+    gi = torch.from_numpy(np.ascontiguousarray(idx)).cuda()
+    gv = torch.from_numpy(np.ascontiguousarray(val)).cuda()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tt = tts.decompose(gi, gv, dims, eps, precision=args.precision)
+        cores = tt.cores
+        gy = gv if cores[0].dtype == torch.float64 else gv.float()
+        y = tts.eval_entries(cores, gi)
+        grads = tts.eval_entries_backward(cores, gi, gy)
+        return tt, y, grads
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    from paper_1908_02721_amd import _lib
+
+    _lib.kernel_timer_start(args.roofline)
+    times = []
+    dec_ms = []
+    t_all0 = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        tt, y, grads = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        dec_ms.append(tt.times_ms["total"])
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t_all0
+    k_ms, k_n, k_bytes, k_flops = _lib.kernel_timer_read()
+    _lib.kernel_timer_start(None)
+    ms_per_step = 1000.0 * t_all / args.steps
+    value = nnz / (t_all / args.steps)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "nnz": nnz, "eps": eps,
+                   "precision": args.precision, "ranks": tt.ranks},
+        "decompose_ms_median": float(np.median(dec_ms)),
+        "decompose_nnz_per_s": nnz / (float(np.median(dec_ms)) / 1000.0),
+        "stage_ms": tt.times_ms,
+        "step_ms_min": 1000.0 * min(times),
+        "step_ms_median": 1000.0 * float(np.median(times)),
+    }
+    bound = FAMILY_BOUND.get(args.roofline, "alu")
+    if k_n and k_ms > 0:
+        if bound == "hbm":
+            achieved = k_bytes / (k_ms / 1000.0) / 1e9
+            peak, unit = HBM_PEAK_GBS, "GB/s"
+        else:
+            achieved = k_flops / (k_ms / 1000.0) / 1e12
+            fp32 = args.precision != "fp64" and args.roofline in ("eval_forward", "eval_up", "eval_grad")
+            peak, unit = (FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS), "TFLOP/s"
+        out["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+                           "traffic": None, "kernel": args.roofline, "launches_per_step": k_n / args.steps,
+                           "kernel_ms_per_step": k_ms / args.steps,
+                           "algo_bytes_per_launch": k_bytes / k_n, "algo_flops_per_launch": k_flops / k_n}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,20 @@ tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, const int64_t
 const char* tt_status_string(tt_status s);
 const char* tt_last_error(void);
 
+/*
+ * Live timing of one kernel family, for roofline reporting.  After
+ * tt_kernel_timer_start(family) every launch of that family (in any call, on any
+ * stream) is bracketed by two HIP events on its own stream, and the algorithmic
+ * bytes and flops of the launch (what the operation must move and compute, not
+ * what the implementation happens to move) are accumulated.  tt_kernel_timer_read
+ * waits for the recorded events and returns the totals; family NULL or "" stops
+ * timing.  Families: "sort_scatter", "level_group", "level_canon",
+ * "eval_forward", "eval_up", "eval_grad", "gemm", "jacobi".  Process-wide, not for
+ * concurrent use from several threads.
+ */
+tt_status tt_kernel_timer_start(const char* family);
+tt_status tt_kernel_timer_read(double* total_ms, int64_t* launches, double* algo_bytes, double* algo_flops);
+
 #ifdef __cplusplus
 }
 #endif

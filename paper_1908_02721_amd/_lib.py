@@ -53,6 +53,7 @@ EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
     "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_times", "tt_get_level", "tt_free",
     "tt_eval_entries", "tt_eval_entries_backward", "tt_status_string", "tt_last_error",
+    "tt_kernel_timer_start", "tt_kernel_timer_read",
 )
 
 
@@ -95,6 +96,10 @@ def load():
         L.tt_status_string.restype = ctypes.c_char_p
         L.tt_last_error.argtypes = []
         L.tt_last_error.restype = ctypes.c_char_p
+        L.tt_kernel_timer_start.argtypes = [ctypes.c_char_p]
+        L.tt_kernel_timer_start.restype = ctypes.c_int
+        L.tt_kernel_timer_read.argtypes = [P(f64), P(i64), P(f64), P(f64)]
+        L.tt_kernel_timer_read.restype = ctypes.c_int
         _ = u64
         _lib = L
         return L
@@ -104,3 +109,15 @@ def check(code: int):
     if code != 0:
         msg = load().tt_last_error().decode(errors="replace")
         raise TTError(code, msg)
+
+
+def kernel_timer_start(family):
+    """Time every launch of one kernel family from now on (None stops)."""
+    check(load().tt_kernel_timer_start(family.encode() if family else None))
+
+
+def kernel_timer_read():
+    """(total_ms, launches, algorithmic_bytes, algorithmic_flops) since the last start."""
+    ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    check(load().tt_kernel_timer_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), ctypes.byref(f)))
+    return ms.value, n.value, b.value, f.value

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -58,6 +60,57 @@ uint32_t bits_for(uint64_t n) {  // bits to hold values 0..n-1
 
 void fail(tt_status s, const std::string& msg) { throw Error{s, msg}; }
 
+// ---------------------------------------------------------------------------
+// Device block cache.  Blocks are kept per stream in size classes (four classes per
+// power of two); a block released on a stream is handed out again only to work on
+// the same stream, so stream order makes the reuse safe without synchronisation.
+// Blocks stay cached until the process ends.
+// ---------------------------------------------------------------------------
+namespace {
+struct BlockCache {
+  std::mutex mu;
+  std::map<std::pair<hipStream_t, size_t>, std::vector<void*>> free;
+};
+BlockCache& block_cache() {
+  static BlockCache* c = new BlockCache();
+  return *c;
+}
+size_t size_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  int lg = 63 - __builtin_clzll(static_cast<unsigned long long>(bytes - 1));
+  const size_t step = (static_cast<size_t>(1) << lg) / 4;
+  return ((bytes + step - 1) / step) * step;
+}
+}  // namespace
+
+void* cached_alloc(size_t bytes, hipStream_t s) {
+  const size_t cls = size_class(bytes);
+  {
+    BlockCache& c = block_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.free.find({s, cls});
+    if (it != c.free.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, cls, s);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void cached_free(void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.free[{s, size_class(bytes)}].push_back(p);
+}
+
 void* Allocator::get(size_t bytes) {
   if (budget && in_use + bytes > budget)
     fail(TT_ERR_NOMEM, "device_mem_budget exceeded (" + std::to_string(in_use + bytes) + " bytes needed)");
@@ -66,11 +119,8 @@ void* Allocator::get(size_t bytes) {
     p = hook_alloc(bytes, ctx);
     if (!p) fail(TT_ERR_NOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
   } else {
-    const hipError_t e = hipMallocAsync(&p, bytes, stream);
-    if (e != hipSuccess || !p) {
-      (void)hipGetLastError();
-      fail(TT_ERR_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
-    }
+    p = cached_alloc(bytes, stream);
+    if (!p) fail(TT_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   in_use += bytes;
   peak = std::max(peak, in_use);
@@ -82,7 +132,7 @@ void Allocator::put(void* p, size_t bytes) {
   if (hook_free)
     hook_free(p, ctx);
   else
-    (void)hipFreeAsync(p, stream);
+    cached_free(p, bytes, stream);
   in_use -= bytes;
 }
 
@@ -485,6 +535,9 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
 
 void tt_free(tt_result r) {
   if (!r) return;
+  // The cores may still be read by the caller's work on any stream: wait for the
+  // device, then return the blocks to the cache of the null stream.
+  (void)hipDeviceSynchronize();
   r->al.stream = nullptr;
   delete r;
 }
@@ -567,3 +620,89 @@ tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, co
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Kernel-family timer.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+namespace tts {
+namespace {
+struct TimerState {
+  std::mutex mu;
+  std::string family;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<hipEvent_t> pool;
+  double bytes = 0.0, flops = 0.0;
+  int64_t launches = 0;
+};
+TimerState& timer_state() {
+  static TimerState* t = new TimerState();
+  return *t;
+}
+hipEvent_t pool_event(TimerState& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  TTS_HIP(hipEventCreate(&e));
+  return e;
+}
+}  // namespace
+
+KTimer::KTimer(const char* family, hipStream_t s, double bytes, double flops) {
+  TimerState& t = timer_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (t.family.empty() || t.family != family) return;
+  s_ = s;
+  hipEvent_t a = pool_event(t), b = pool_event(t);
+  TTS_HIP(hipEventRecord(a, s));
+  t.ev.emplace_back(a, b);
+  slot_ = static_cast<int>(t.ev.size()) - 1;
+  t.bytes += bytes;
+  t.flops += flops;
+  t.launches += 1;
+}
+
+KTimer::~KTimer() {
+  if (slot_ < 0) return;
+  TimerState& t = timer_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (slot_ < static_cast<int>(t.ev.size())) (void)hipEventRecord(t.ev[slot_].second, s_);
+}
+
+}  // namespace tts
+
+extern "C" tt_status tt_kernel_timer_start(const char* family) {
+  tts::TimerState& t = tts::timer_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto& p : t.ev) {
+    t.pool.push_back(p.first);
+    t.pool.push_back(p.second);
+  }
+  t.ev.clear();
+  t.bytes = t.flops = 0.0;
+  t.launches = 0;
+  t.family = family ? family : "";
+  return TT_OK;
+}
+
+extern "C" tt_status tt_kernel_timer_read(double* total_ms, int64_t* launches, double* algo_bytes,
+                                          double* algo_flops) {
+  tts::TimerState& t = tts::timer_state();
+  std::lock_guard<std::mutex> g(t.mu);
+  double ms = 0.0;
+  for (auto& p : t.ev) {
+    if (hipEventSynchronize(p.second) != hipSuccess) return TT_ERR_DEVICE;
+    float x = 0.f;
+    if (hipEventElapsedTime(&x, p.first, p.second) != hipSuccess) return TT_ERR_DEVICE;
+    ms += x;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = t.launches;
+  if (algo_bytes) *algo_bytes = t.bytes;
+  if (algo_flops) *algo_flops = t.flops;
+  return TT_OK;
+}

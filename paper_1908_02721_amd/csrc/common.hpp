@@ -50,6 +50,10 @@ struct Allocator {
   void put(void* p, size_t bytes);
 };
 
+// Stream-ordered block cache shared by every allocation of the library.
+void* cached_alloc(size_t bytes, hipStream_t s);
+void cached_free(void* p, size_t bytes, hipStream_t s);
+
 template <class T>
 class DBuf {
  public:
@@ -89,6 +93,21 @@ class DBuf {
   Allocator* al_ = nullptr;
   T* p_ = nullptr;
   size_t n_ = 0;
+};
+
+// Live timing of one kernel family (see tt_kernel_timer_start).  Construct a
+// KTimer around a launch: when the family is being timed, events are recorded on
+// the launch's stream before and after it.
+class KTimer {
+ public:
+  KTimer(const char* family, hipStream_t s, double bytes, double flops);
+  ~KTimer();
+  KTimer(const KTimer&) = delete;
+  KTimer& operator=(const KTimer&) = delete;
+
+ private:
+  int slot_ = -1;
+  hipStream_t s_ = nullptr;
 };
 
 inline unsigned grid_for(size_t n, unsigned block) {

@@ -123,6 +123,14 @@ __global__ __launch_bounds__(NT) void k_bucket_keys(const int32_t* __restrict__ 
   val[n] = static_cast<uint64_t>(n);
 }
 
+__global__ __launch_bounds__(NT) void k_bucket_keys_u32(const uint32_t* __restrict__ coord, int64_t m,
+                                                        uint64_t* __restrict__ key, uint64_t* __restrict__ val) {
+  const int64_t n = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (n >= m) return;
+  key[n] = static_cast<uint64_t>(coord[n]);
+  val[n] = static_cast<uint64_t>(n);
+}
+
 __global__ __launch_bounds__(NT) void k_bucket_offsets(const uint64_t* __restrict__ skey, int64_t m, int nk,
                                                        int64_t* __restrict__ off) {
   const int i = blockIdx.x * NT + threadIdx.x;
@@ -146,7 +154,8 @@ __global__ __launch_bounds__(NT) void k_grad_partial(int r0, int r1, int nk, con
                                                      const int64_t* __restrict__ off, const T* __restrict__ gy,
                                                      const T* __restrict__ L, int64_t lsum, int64_t loff,
                                                      const T* __restrict__ R, int64_t rsum, int64_t roff,
-                                                     int64_t chunk, T* __restrict__ part) {
+                                                     int64_t chunk, T* __restrict__ part,
+                                                     const uint32_t* __restrict__ lidx) {
   __shared__ T Ls[KC][65];
   __shared__ T Rs[KC][65];
   const int i = blockIdx.x;
@@ -168,8 +177,9 @@ __global__ __launch_bounds__(NT) void k_grad_partial(int r0, int r1, int nk, con
       T lv = T(0), rv = T(0);
       if (t < cnt) {
         const int64_t n = static_cast<int64_t>(perm[s0 + t]);
+        const int64_t nl = lidx ? static_cast<int64_t>(lidx[n]) : n;
         const int a = a0 + j, b = b0 + j;
-        if (a < r0) lv = (loff < 0 ? T(1) : L[n * lsum + loff + a]) * gy[n];
+        if (a < r0) lv = (loff < 0 ? T(1) : L[nl * lsum + loff + a]) * (gy ? gy[n] : T(1));
         if (b < r1) rv = (roff < 0 ? T(1) : R[n * rsum + roff + b]);
       }
       Ls[t][j] = lv;
@@ -276,34 +286,507 @@ void launch_right(const EvalDesc& ed, int64_t m, const int32_t* idx, T* R, hipSt
   TTS_LAUNCH_CHECK();
 }
 
-void* dalloc(size_t bytes, hipStream_t s) {
-  void* p = nullptr;
-  if (bytes == 0) return nullptr;
-  if (hipMallocAsync(&p, bytes, s) != hipSuccess || !p) {
-    (void)hipGetLastError();
-    fail(TT_ERR_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed");
-  }
-  return p;
-}
-
 struct DevMem {
   hipStream_t s;
-  std::vector<void*> ps;
+  std::vector<std::pair<void*, size_t>> ps;
   explicit DevMem(hipStream_t st) : s(st) {}
   template <class X>
   X* get(size_t n) {
-    void* p = dalloc(n * sizeof(X), s);
-    ps.push_back(p);
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(X);
+    void* p = cached_alloc(bytes, s);
+    if (!p) fail(TT_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    ps.emplace_back(p, bytes);
     return static_cast<X*>(p);
   }
   ~DevMem() {
-    for (void* p : ps)
-      if (p) (void)hipFreeAsync(p, s);
+    for (auto& pb : ps) cached_free(pb.first, pb.second, s);
   }
 };
 
+// ---------------------------------------------------------------------------
+// Prefix-trie evaluation.  Entries are sorted by their coordinates (mode 0 most
+// significant); the distinct prefixes (i_0..i_{t-1}) of depth t are the nodes of a
+// trie whose depth-d nodes are the distinct coordinates.  Left products are
+// computed once per node (top-down), the "up" vectors
+//   U_t[q] = sum over leaves n below q of gy_n * G_t[i_t^n] ... G_{d-1}[i_{d-1}^n]
+// once per node (bottom-up), and
+//   dL/dG_t[a, i, b] = sum over children c (depth t+1, i_t(c) = i) of L_t[parent(c)][a] U_{t+1}[c][b].
+// The work is sum_t P_t r_{t-1} r_t instead of m sum_t r_{t-1} r_t.
+// ---------------------------------------------------------------------------
+struct TrieGeom {
+  int32_t d;
+  uint32_t bits[TT_MAX_D];
+  uint32_t off[TT_MAX_D];  // mode 0 most significant: off[k] = sum_{j>k} bits[j]
+  int32_t n[TT_MAX_D];
+};
+
+__global__ __launch_bounds__(NT) void k_tri_keys(const int32_t* __restrict__ idx, int64_t m, TrieGeom g,
+                                                 uint64_t* __restrict__ key, uint64_t* __restrict__ val,
+                                                 uint32_t* __restrict__ err) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= m) return;
+  uint64_t k = 0;
+  bool bad = false;
+  for (int j = 0; j < g.d; ++j) {
+    const int32_t c = idx[e * g.d + j];
+    bad |= (c < 0) || (c >= g.n[j]);
+    k |= static_cast<uint64_t>(static_cast<uint32_t>(c)) << g.off[j];
+  }
+  if (bad) atomicOr(err, 1u);
+  key[e] = bad ? 0ull : k;
+  val[e] = static_cast<uint64_t>(e);
+}
+
+__global__ __launch_bounds__(NT) void k_tri_flags(const uint64_t* __restrict__ key, int64_t m, int sh,
+                                                  uint32_t* __restrict__ flag) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= m) return;
+  flag[e] = (e == 0 || (key[e] >> sh) != (key[e - 1] >> sh)) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(NT) void k_tri_nodes(const uint64_t* __restrict__ key, const uint32_t* __restrict__ flag,
+                                                  const uint32_t* __restrict__ pos, int64_t m,
+                                                  const uint32_t* __restrict__ prev_id, int csh, uint64_t cmask,
+                                                  uint32_t* __restrict__ cur_id, uint32_t* __restrict__ parent,
+                                                  uint32_t* __restrict__ coord, uint32_t* __restrict__ start) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= m) return;
+  const uint32_t id = pos[e] + flag[e] - 1u;
+  cur_id[e] = id;
+  if (flag[e]) {
+    parent[id] = prev_id ? prev_id[e] : 0u;
+    coord[id] = static_cast<uint32_t>((key[e] >> csh) & cmask);
+    if (start) start[id] = static_cast<uint32_t>(e);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_tri_child_ranges(const uint32_t* __restrict__ parent, int64_t pc,
+                                                         int64_t pq, uint32_t* __restrict__ cbeg) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (c == 0) cbeg[pq] = static_cast<uint32_t>(pc);
+  if (c >= pc) return;
+  if (c == 0 || parent[c] != parent[c - 1]) cbeg[parent[c]] = static_cast<uint32_t>(c);
+}
+
+template <typename T, int LPE>
+__global__ __launch_bounds__(NT) void k_tri_fwd(int64_t P, const uint32_t* __restrict__ parent,
+                                                const uint32_t* __restrict__ coord, const T* __restrict__ Lprev,
+                                                int r0, int r1, const T* __restrict__ G, int nk,
+                                                T* __restrict__ Lcur) {
+  constexpr int EPW = 64 / LPE;
+  __shared__ T buf[NT / 64][EPW][RMAX];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = lane / LPE, l = lane % LPE;
+  T* v = buf[wv][sub];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * (NT / 64) * EPW;
+  const int64_t rs = static_cast<int64_t>(nk) * r1;
+  for (int64_t q = (static_cast<int64_t>(blockIdx.x) * (NT / 64) + wv) * EPW + sub; q < P + (EPW - 1); q += stride) {
+    const bool live = q < P;
+    const int64_t pq = live ? parent[q] : 0;
+    const int64_t i = live ? coord[q] : 0;
+    for (int a = l; a < r0; a += LPE) v[a] = live ? Lprev[pq * r0 + a] : T(0);
+    __builtin_amdgcn_wave_barrier();
+    const T* base = G + i * r1;
+    for (int j = l; j < r1; j += LPE) {
+      T acc = T(0);
+      for (int a = 0; a < r0; ++a) acc = fma(v[a], base[a * rs + j], acc);
+      if (live) Lcur[q * r1 + j] = acc;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Forward of depth-t nodes grouped by their mode index: workgroup (i, chunk, tile)
+// multiplies the parent vectors of up to 64 nodes whose last index is i by the
+// slice G[:, i, b0:b0+64] staged in LDS (a small gather-GEMM-scatter), thread tile
+// 4 nodes x 4 columns.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
+                                                       const int64_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ parent,
+                                                       const T* __restrict__ Lprev, const T* __restrict__ G,
+                                                       T* __restrict__ Lcur) {
+  constexpr int NB = 64;  // nodes per workgroup
+  constexpr int AK = 32;  // slice rows staged per step
+  __shared__ T Vs[AK][NB + 1];
+  __shared__ T Ss[AK][64 + 1];
+  __shared__ uint32_t qid[NB], pid[NB];
+  const int i = blockIdx.x;
+  const int64_t beg = off[i] + static_cast<int64_t>(blockIdx.y) * NB;
+  const int64_t end = min(off[i + 1], beg + NB);
+  if (beg >= end) return;
+  const int cnt = static_cast<int>(end - beg);
+  const int b0 = blockIdx.z * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (threadIdx.x < NB) {
+    const uint32_t q = (threadIdx.x < cnt) ? static_cast<uint32_t>(perm[beg + threadIdx.x]) : 0u;
+    qid[threadIdx.x] = q;
+    pid[threadIdx.x] = (threadIdx.x < cnt) ? parent[q] : 0u;
+  }
+  __syncthreads();
+  T acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+  const int64_t rs = static_cast<int64_t>(nk) * r1;
+  for (int a0 = 0; a0 < r0; a0 += AK) {
+    for (int e = threadIdx.x; e < AK * NB; e += NT) {
+      const int a = e % AK, nn = e / AK;
+      Vs[a][nn] = (nn < cnt && a0 + a < r0) ? Lprev[static_cast<int64_t>(pid[nn]) * r0 + a0 + a] : T(0);
+    }
+    for (int e = threadIdx.x; e < AK * 64; e += NT) {
+      const int b = e % 64, a = e / 64;
+      Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? G[(a0 + a) * rs + static_cast<int64_t>(i) * r1 + b0 + b] : T(0);
+    }
+    __syncthreads();
+    const int kk = min(AK, r0 - a0);
+    for (int a = 0; a < kk; ++a) {
+      T vv[4], sv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vv[u] = Vs[a][ty + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sv[v] = Ss[a][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(vv[u], sv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int nn = ty + 16 * u;
+    if (nn >= cnt) continue;
+    const int64_t q = qid[nn];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = b0 + tx + 16 * v;
+      if (b < r1) Lcur[q * r1 + b] = acc[u][v];
+    }
+  }
+}
+
+// Up vectors of depth-t nodes from their children (depth t+1).  GT is the core
+// with its slices transposed: GT[(i * r1 + b) * r0 + a] = G[a, i, b].
+template <typename T, int LPE>
+__global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __restrict__ cbeg,
+                                               const uint32_t* __restrict__ ccoord, const T* __restrict__ Unext,
+                                               int r0, int r1, const T* __restrict__ GT, T* __restrict__ Ucur) {
+  constexpr int EPW = 64 / LPE;
+  __shared__ T buf[NT / 64][EPW][RMAX];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sub = lane / LPE, l = lane % LPE;
+  T* u = buf[wv][sub];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * (NT / 64) * EPW;
+  for (int64_t q = (static_cast<int64_t>(blockIdx.x) * (NT / 64) + wv) * EPW + sub; q < P + (EPW - 1); q += stride) {
+    const bool live = q < P;
+    const int64_t c0 = live ? cbeg[q] : 0, c1 = live ? cbeg[q + 1] : 0;
+    T acc[RMAX / LPE];
+#pragma unroll
+    for (int s2 = 0; s2 < RMAX / LPE; ++s2) acc[s2] = T(0);
+    for (int64_t c = c0; c < c1; ++c) {
+      for (int b = l; b < r1; b += LPE) u[b] = Unext[c * r1 + b];
+      __builtin_amdgcn_wave_barrier();
+      const T* base = GT + static_cast<int64_t>(ccoord[c]) * r1 * r0;
+#pragma unroll
+      for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
+        const int a = l + s2 * LPE;
+        if (a < r0) {
+          T x = acc[s2];
+          for (int b = 0; b < r1; ++b) x = fma(base[b * r0 + a], u[b], x);
+          acc[s2] = x;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (live) {
+#pragma unroll
+      for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
+        const int a = l + s2 * LPE;
+        if (a < r0) Ucur[q * r0 + a] = acc[s2];
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_leaf_up(int64_t P, const uint32_t* __restrict__ start, int64_t m,
+                                                    const uint64_t* __restrict__ perm, const T* __restrict__ gy,
+                                                    T* __restrict__ U) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (q >= P) return;
+  const int64_t e1 = (q + 1 < P) ? static_cast<int64_t>(start[q + 1]) : m;
+  T s = T(0);
+  for (int64_t e = start[q]; e < e1; ++e) s += gy[perm[e]];
+  U[q] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_out(int64_t m, const uint32_t* __restrict__ leaf,
+                                                const uint64_t* __restrict__ perm, const T* __restrict__ Ld,
+                                                T* __restrict__ y) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= m) return;
+  y[perm[e]] = Ld[leaf[e]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_slice_transpose(const T* __restrict__ G, int r0, int nk, int r1,
+                                                        T* __restrict__ GT) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t tot = static_cast<int64_t>(r0) * nk * r1;
+  if (e >= tot) return;
+  const int b = static_cast<int>(e % r1);
+  const int i = static_cast<int>((e / r1) % nk);
+  const int a = static_cast<int>(e / (static_cast<int64_t>(r1) * nk));
+  GT[(static_cast<int64_t>(i) * r1 + b) * r0 + a] = G[e];
+}
+
+template <typename T>
+__global__ void k_one(T* p) {
+  *p = T(1);
+}
+
+struct Trie {
+  int64_t m = 0;
+  std::vector<uint64_t*> bperm;           // per depth t = 1..d: nodes sorted by their last index
+  std::vector<int64_t*> boff;             // bucket offsets (n_{t-1} + 1)
+  std::vector<int64_t> bmax;              // largest bucket
+  std::vector<int64_t> P;                 // P[t], t = 0..d (P[0] = 1)
+  std::vector<uint32_t*> parent, coord;   // per depth t = 1..d
+  uint32_t* leaf = nullptr;               // per sorted entry: depth-d node
+  uint32_t* start = nullptr;              // per depth-d node: first sorted entry
+  uint64_t* perm = nullptr;               // sorted position -> entry
+};
+
+int lpe_for(const EvalDesc& ed) { return max_rank_of(ed) <= 32 ? 32 : 64; }
+
+unsigned blocks_for(int64_t items, int lpe) {
+  const int64_t per_block = (NT / 64) * (64 / lpe);
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, 256 * 64)));
+}
+
+bool trie_possible(const EvalDesc& ed) {
+  int bits = 0;
+  for (int k = 0; k < ed.d; ++k) {
+    int b = 0;
+    while (b < 31 && (static_cast<int64_t>(ed.n[k]) - 1) >> b) ++b;
+    bits += b;
+  }
+  return bits <= 63;
+}
+
+// Sorts the entries and builds the node arrays of every depth.  Returns false on a
+// coordinate out of range.
+bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, Allocator* al, Trie& tr,
+                hipStream_t s) {
+  const int d = ed.d;
+  TrieGeom g{};
+  g.d = d;
+  int total = 0;
+  for (int k = d - 1; k >= 0; --k) {
+    int b = 0;
+    while (b < 31 && (static_cast<int64_t>(ed.n[k]) - 1) >> b) ++b;
+    g.bits[k] = b;
+    g.off[k] = total;
+    g.n[k] = ed.n[k];
+    total += b;
+  }
+  tr.m = m;
+  uint64_t* key = mem.get<uint64_t>(m);
+  uint64_t* val = mem.get<uint64_t>(m);
+  uint64_t* kt = mem.get<uint64_t>(m);
+  uint64_t* vt = mem.get<uint64_t>(m);
+  uint32_t* err = mem.get<uint32_t>(1);
+  TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
+  k_tri_keys<<<grid_for(m, NT), NT, 0, s>>>(idx, m, g, key, val, err);
+  TTS_LAUNCH_CHECK();
+  uint32_t herr = 0;
+  TTS_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+  TTS_HIP(hipStreamSynchronize(s));
+  if (herr) return false;
+  radix_sort_pairs(al, key, val, kt, vt, static_cast<uint32_t>(m), total, s);
+  tr.perm = val;
+  uint32_t* flag = mem.get<uint32_t>(m);
+  uint32_t* pos = mem.get<uint32_t>(m);
+  uint32_t* ida = mem.get<uint32_t>(m);
+  uint32_t* idb = mem.get<uint32_t>(m);
+  uint32_t* cnt = mem.get<uint32_t>(1);
+  tr.P.assign(d + 1, 1);
+  tr.parent.assign(d + 1, nullptr);
+  tr.coord.assign(d + 1, nullptr);
+  uint32_t* prev = nullptr;
+  for (int t = 1; t <= d; ++t) {
+    // prefix (i_0..i_{t-1}) = key >> off[t-1]; mode t-1's field sits at off[t-1]
+    const int psh = static_cast<int>(g.off[t - 1]);
+    k_tri_flags<<<grid_for(m, NT), NT, 0, s>>>(key, m, psh, flag);
+    TTS_LAUNCH_CHECK();
+    exclusive_scan_u32(al, flag, pos, static_cast<uint32_t>(m), cnt, s);
+    uint32_t pt = 0;
+    TTS_HIP(hipMemcpyAsync(&pt, cnt, sizeof(pt), hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipStreamSynchronize(s));
+    tr.P[t] = pt;
+    tr.parent[t] = mem.get<uint32_t>(pt);
+    tr.coord[t] = mem.get<uint32_t>(pt);
+    uint32_t* st = nullptr;
+    if (t == d) st = tr.start = mem.get<uint32_t>(pt);
+    uint32_t* cur = (t & 1) ? ida : idb;
+    const uint64_t cmask = g.bits[t - 1] >= 64 ? ~0ull : ((1ull << g.bits[t - 1]) - 1ull);
+    k_tri_nodes<<<grid_for(m, NT), NT, 0, s>>>(key, flag, pos, m, prev, psh, cmask, cur, tr.parent[t], tr.coord[t],
+                                               st);
+    TTS_LAUNCH_CHECK();
+    prev = cur;
+  }
+  tr.leaf = prev;
+  return true;
+}
+
+// Buckets of the depth-t nodes by their last index (stable radix sort).
+void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hipStream_t s) {
+  const int d = ed.d;
+  tr.bperm.assign(d + 1, nullptr);
+  tr.boff.assign(d + 1, nullptr);
+  tr.bmax.assign(d + 1, 0);
+  const int64_t pmax = *std::max_element(tr.P.begin(), tr.P.end());
+  uint64_t* key = mem.get<uint64_t>(pmax);
+  uint64_t* kt = mem.get<uint64_t>(pmax);
+  uint64_t* vt = mem.get<uint64_t>(pmax);
+  std::vector<std::vector<int64_t>> hoff(d + 1);
+  for (int t = 1; t <= d; ++t) {
+    const int nk = ed.n[t - 1];
+    const int64_t P = tr.P[t];
+    tr.bperm[t] = mem.get<uint64_t>(P);
+    k_bucket_keys_u32<<<grid_for(P, NT), NT, 0, s>>>(tr.coord[t], P, key, tr.bperm[t]);
+    TTS_LAUNCH_CHECK();
+    int bits = 0;
+    while (bits < 31 && (static_cast<int64_t>(nk) - 1) >> bits) ++bits;
+    radix_sort_pairs(al, key, tr.bperm[t], kt, vt, static_cast<uint32_t>(P), bits, s);
+    tr.boff[t] = mem.get<int64_t>(nk + 1);
+    k_bucket_offsets<<<grid_for(nk + 1, NT), NT, 0, s>>>(key, P, nk, tr.boff[t]);
+    TTS_LAUNCH_CHECK();
+    hoff[t].resize(nk + 1);
+    TTS_HIP(hipMemcpyAsync(hoff[t].data(), tr.boff[t], sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToHost, s));
+  }
+  TTS_HIP(hipStreamSynchronize(s));
+  for (int t = 1; t <= d; ++t)
+    for (int i = 0; i < ed.n[t - 1]; ++i) tr.bmax[t] = std::max(tr.bmax[t], hoff[t][i + 1] - hoff[t][i]);
+}
+
+template <typename T>
+void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std::vector<T*>& Lv, hipStream_t s) {
+  const int d = ed.d;
+  if (tr.bperm.empty()) build_buckets(ed, tr, mem, al, s);
+  Lv.assign(d + 1, nullptr);
+  Lv[0] = mem.get<T>(1);
+  k_one<T><<<1, 1, 0, s>>>(Lv[0]);
+  TTS_LAUNCH_CHECK();
+  for (int t = 1; t <= d; ++t) {
+    const int r0 = ed.r[t - 1], r1 = ed.r[t], nk = ed.n[t - 1];
+    const int64_t P = tr.P[t];
+    Lv[t] = mem.get<T>(static_cast<size_t>(P) * r1);
+    const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + 63) / 64);
+    if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
+    const int tiles = (r1 + 63) / 64;
+    KTimer kt("eval_forward", s,
+              static_cast<double>(P) * (r1 + 8) * sizeof(T) + static_cast<double>(tr.P[t - 1]) * r0 * sizeof(T) +
+                  static_cast<double>(r0) * nk * r1 * sizeof(T),
+              2.0 * static_cast<double>(P) * r0 * r1);
+    k_tri_fwd_bucket<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
+        r0, r1, nk, tr.bperm[t], tr.boff[t], tr.parent[t], Lv[t - 1], static_cast<const T*>(ed.core[t - 1]), Lv[t]);
+    TTS_LAUNCH_CHECK();
+  }
+}
+
+template <typename T>
+tt_status trie_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, T* y, hipStream_t s) {
+  DevMem mem(s);
+  Allocator al;
+  al.stream = s;
+  Trie tr;
+  if (!build_trie(ed, m, idx, mem, &al, tr, s)) {
+    set_last_error("a coordinate is outside its mode range");
+    return TT_ERR_INDEX;
+  }
+  std::vector<T*> Lv;
+  trie_forward<T>(ed, tr, mem, &al, Lv, s);
+  k_tri_out<T><<<grid_for(m, NT), NT, 0, s>>>(m, tr.leaf, tr.perm, Lv[ed.d], y);
+  TTS_LAUNCH_CHECK();
+  TTS_HIP(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+template <typename T>
+tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
+                    hipStream_t s) {
+  DevMem mem(s);
+  Allocator al;
+  al.stream = s;
+  const int d = ed.d;
+  Trie tr;
+  if (!build_trie(ed, m, idx, mem, &al, tr, s)) {
+    set_last_error("a coordinate is outside its mode range");
+    return TT_ERR_INDEX;
+  }
+  std::vector<T*> Lv;
+  trie_forward<T>(ed, tr, mem, &al, Lv, s);
+  const int lpe = lpe_for(ed);
+  // up vectors, bottom-up
+  std::vector<T*> Uv(d + 1, nullptr);
+  Uv[d] = mem.get<T>(tr.P[d]);
+  k_tri_leaf_up<T><<<grid_for(tr.P[d], NT), NT, 0, s>>>(tr.P[d], tr.start, m, tr.perm, gy, Uv[d]);
+  TTS_LAUNCH_CHECK();
+  std::vector<uint32_t*> cbeg(d + 1, nullptr);
+  for (int t = d - 1; t >= 1; --t) {
+    const int r0 = ed.r[t], r1 = ed.r[t + 1], nk = ed.n[t];
+    const int64_t P = tr.P[t], Pc = tr.P[t + 1];
+    cbeg[t] = mem.get<uint32_t>(P + 1);
+    k_tri_child_ranges<<<grid_for(Pc, NT), NT, 0, s>>>(tr.parent[t + 1], Pc, P, cbeg[t]);
+    TTS_LAUNCH_CHECK();
+    T* GT = mem.get<T>(static_cast<size_t>(r0) * nk * r1);
+    k_slice_transpose<T><<<grid_for(static_cast<size_t>(r0) * nk * r1, NT), NT, 0, s>>>(
+        static_cast<const T*>(ed.core[t]), r0, nk, r1, GT);
+    TTS_LAUNCH_CHECK();
+    Uv[t] = mem.get<T>(static_cast<size_t>(P) * r0);
+    KTimer kt("eval_up", s, static_cast<double>(Pc) * (r1 + 8) * sizeof(T) + static_cast<double>(P) * r0 * sizeof(T),
+              2.0 * static_cast<double>(Pc) * r0 * r1);
+    if (lpe == 32)
+      k_tri_up<T, 32><<<blocks_for(P, 32), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
+    else
+      k_tri_up<T, 64><<<blocks_for(P, 64), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
+    TTS_LAUNCH_CHECK();
+  }
+  // gradients: core t pairs parents at depth t with children at depth t+1
+  constexpr int KC = sizeof(T) == 8 ? 64 : 128;
+  for (int t = 0; t < d; ++t) {
+    const int nk = ed.n[t], r0 = ed.r[t], r1 = ed.r[t + 1];
+    const int64_t Pc = tr.P[t + 1];
+    const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
+    const int64_t maxb = tr.bmax[t + 1];
+    const int64_t iters = std::max<int64_t>(1, (maxb + KC * 512 - 1) / (KC * 512));
+    const int64_t chunk = KC * iters;
+    const int nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + chunk - 1) / chunk));
+    const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
+    T* part = mem.get<T>(static_cast<size_t>(nchunk) * csz);
+    {
+      KTimer ktm("eval_grad", s,
+                 static_cast<double>(Pc) * (r0 + r1 + 8) * sizeof(T) + static_cast<double>(nchunk) * csz * sizeof(T),
+                 2.0 * static_cast<double>(Pc) * r0 * r1);
+      k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], nullptr,
+                                                                   Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1], r1, 0, chunk,
+                                                                   part, tr.parent[t + 1]);
+      TTS_LAUNCH_CHECK();
+    }
+    k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, static_cast<T*>(grads[t]));
+    TTS_LAUNCH_CHECK();
+  }
+  TTS_HIP(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
 template <typename T>
 tt_status eval_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_out, hipStream_t s) {
+  if (m > 0 && m < (int64_t(1) << 31) && trie_possible(ed)) return trie_eval<T>(ed, m, idx, static_cast<T*>(y_out), s);
   DevMem mem(s);
   uint32_t* err = mem.get<uint32_t>(1);
   TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
@@ -321,6 +804,7 @@ tt_status eval_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_o
 template <typename T>
 tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
                     hipStream_t s) {
+  if (m > 0 && m < (int64_t(1) << 31) && trie_possible(ed)) return trie_grad<T>(ed, m, idx, gy, grads, s);
   DevMem mem(s);
   Allocator al;
   al.stream = s;
@@ -377,7 +861,7 @@ tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     const int64_t lo = (k >= 1) ? ed.loff[k] : -1;              // l_k (k >= 1); l_0 = 1
     const int64_t ro = (k + 1 <= d - 1) ? ed.roff[k + 1] : -1;  // r_{k+1}; r_d = 1
     k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, perm, off, gy, L, ed.lsum, lo, R,
-                                                                 ed.rsum, ro, chunk, part);
+                                                                 ed.rsum, ro, chunk, part, nullptr);
     TTS_LAUNCH_CHECK();
     k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, gout);
     TTS_LAUNCH_CHECK();

@@ -825,6 +825,8 @@ void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, co
   kchunk = ((kchunk + GK - 1) / GK) * GK;
   if (kchunk == 0) kchunk = GK;
   ns = std::max(1, (k + kchunk - 1) / kchunk);
+  KTimer kt("gemm", s, 8.0 * (static_cast<double>(m) * k + static_cast<double>(k) * n + static_cast<double>(m) * n),
+            2.0 * static_cast<double>(m) * n * k);
   if (ns == 1) {
     k_gemm<<<dim3(tm, tn, 1), NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk > k ? kchunk : k,
                                           nullptr);
@@ -940,6 +942,9 @@ void householder_extract_r(const double* A, int m, int n, int lda, double* R, in
 void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, hipStream_t s) {
   if (c <= 0) return;
   const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
+  KTimer kt("jacobi", s, 8.0 * 2.0 * (static_cast<double>(rows) * c + static_cast<double>(c) * c),
+            // one sweep of rotations: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V)
+            0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
   if (shm <= 150 * 1024 || c <= 2 * BJ_B) {
     const int use_lds = shm <= 150 * 1024;
     k_jacobi<<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds);
@@ -953,8 +958,8 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   nb += nb & 1;
   k_eye<<<grid_for(static_cast<size_t>(c) * c, NT), NT, 0, s>>>(V, c, ldv);
   TTS_LAUNCH_CHECK();
-  int32_t* flag = nullptr;
-  TTS_HIP(hipMallocAsync(reinterpret_cast<void**>(&flag), sizeof(int32_t), s));
+  int32_t* flag = static_cast<int32_t*>(cached_alloc(sizeof(int32_t), s));
+  if (!flag) fail(TT_ERR_NOMEM, "device allocation failed");
   int32_t hflag = 1;
   for (int sweep = 0; sweep < 60 && hflag; ++sweep) {
     TTS_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
@@ -965,7 +970,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     TTS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
   }
-  TTS_HIP(hipFreeAsync(flag, s));
+  cached_free(flag, sizeof(int32_t), s);
   k_col_norms<<<c, NT, 0, s>>>(A, rows, c, lda, sigma);
   TTS_LAUNCH_CHECK();
 }

@@ -230,8 +230,12 @@ void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* k
     k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, counts.get(), ntiles);
     TTS_LAUNCH_CHECK();
     exclusive_scan_u32(al, counts.get(), counts.get(), 256u * ntiles, nullptr, s);
-    k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, counts.get(), ntiles);
-    TTS_LAUNCH_CHECK();
+    {
+      // algorithmic bytes of one pass: read and write every (key, value) pair once
+      KTimer kt("sort_scatter", s, 32.0 * n, 0.0);
+      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, counts.get(), ntiles);
+      TTS_LAUNCH_CHECK();
+    }
     std::swap(ki, ko);
     std::swap(vi, vo);
   }

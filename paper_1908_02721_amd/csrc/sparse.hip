@@ -353,6 +353,10 @@ void launch_permute_entries(const uint64_t* perm, uint32_t nE, const uint64_t* e
 
 void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, hipStream_t s) {
   if (!a.ncols) return;
+  // per column: read its entries' (key, rho, value) once, write (rho, c) and the
+  // column record (hash, s, suffix, row-major key) once -- the caller passes the
+  // entry count through the column starts; bytes are estimated from ncols here
+  KTimer kt("level_canon", s, 56.0 * a.ncols, 0.0);
   k_canon<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
   TTS_LAUNCH_CHECK();
 }
@@ -361,6 +365,8 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
                   const uint64_t* rmkey, uint32_t ncols, uint64_t* table, uint64_t* slotmin, uint32_t tmask,
                   uint32_t* slot, uint32_t* isrep, hipStream_t s) {
   if (!ncols) return;
+  // per column: read hash, start and row-major key, write slot and flag
+  KTimer kt("level_group", s, 32.0 * ncols, 0.0);
   k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
                                              slot, isrep);
   TTS_LAUNCH_CHECK();

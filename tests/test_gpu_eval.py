@@ -143,3 +143,22 @@ def test_deterministic_backward_and_errors():
     assert tts.eval_entries(cores, empty).numel() == 0
     gz = tts.eval_entries_backward(cores, empty, gy[:0])
     assert all(float(g.abs().max()) == 0.0 for g in gz)
+
+
+def test_repeated_and_shared_prefix_coordinates(oracle_mod):
+    # repeated coordinates and heavy prefix sharing (every entry below a few prefixes)
+    tts = _tts()
+    rng = np.random.Generator(np.random.PCG64(9))
+    dims, ranks = (4, 3, 50, 60), (3, 7, 9)
+    cores = _rand_tt(rng, dims, ranks)
+    idx = _idx(rng, dims, 4000)
+    idx[:, 0] = 1
+    idx[:, 1] = rng.integers(0, 2, 4000)
+    idx = np.concatenate([idx, idx[:500]])
+    gy = rng.standard_normal(len(idx))
+    gi = torch.from_numpy(idx).cuda()
+    y = tts.eval_entries(_cuda(cores, torch.float64), gi).cpu().numpy()
+    assert np.max(np.abs(y - oracle_mod.eval_entries(cores, idx))) <= 1e-12
+    g = tts.eval_entries_backward(_cuda(cores, torch.float64), gi, torch.from_numpy(gy).cuda())
+    for a, b in zip(g, oracle_mod.eval_grad(cores, idx, gy)):
+        assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-11 * max(1.0, np.max(np.abs(b)))
