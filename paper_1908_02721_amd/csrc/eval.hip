@@ -396,12 +396,16 @@ __global__ __launch_bounds__(NT) void k_tri_fwd(int64_t P, const uint32_t* __res
   }
 }
 
-// Forward of depth-t nodes grouped by their mode index: workgroup (i, chunk, tile)
-// multiplies the parent vectors of up to 64 nodes whose last index is i by the
-// slice G[:, i, b0:b0+64] staged in LDS (a small gather-GEMM-scatter), thread tile
-// 4 nodes x 4 columns.
+// Bucketed row-times-slice product over the nodes of one trie depth grouped by their
+// last mode index: workgroup (i, chunk, tile) takes up to 64 nodes q whose index is
+// i, gathers their input rows src[parent(q)] (forward; src[q] when parent is null),
+// multiplies them by the r0 x r1 slice S_i (S_i[a][b] = G[i*sI + a*sK + b], staged
+// in LDS 32 rows at a time) and writes dst[q][b0:b0+64]: a small gather-GEMM-scatter
+// with a 4 nodes x 4 columns thread tile.  Forward: S_i = G[:, i, :].  Up pass:
+// S_i = G[:, i, :]^T, rows = the children's up vectors.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
+__global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int64_t sK, int64_t sI,
+                                                       const uint64_t* __restrict__ perm,
                                                        const int64_t* __restrict__ off,
                                                        const uint32_t* __restrict__ parent,
                                                        const T* __restrict__ Lprev, const T* __restrict__ G,
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, c
   if (threadIdx.x < NB) {
     const uint32_t q = (threadIdx.x < cnt) ? static_cast<uint32_t>(perm[beg + threadIdx.x]) : 0u;
     qid[threadIdx.x] = q;
-    pid[threadIdx.x] = (threadIdx.x < cnt) ? parent[q] : 0u;
+    pid[threadIdx.x] = (threadIdx.x < cnt) ? (parent ? parent[q] : q) : 0u;
   }
   __syncthreads();
   T acc[4][4];
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, c
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-  const int64_t rs = static_cast<int64_t>(nk) * r1;
+  const T* Gi = G + static_cast<int64_t>(i) * sI;
   for (int a0 = 0; a0 < r0; a0 += AK) {
     for (int e = threadIdx.x; e < AK * NB; e += NT) {
       const int a = e % AK, nn = e / AK;
@@ -437,7 +441,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, c
     }
     for (int e = threadIdx.x; e < AK * 64; e += NT) {
       const int b = e % 64, a = e / 64;
-      Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? G[(a0 + a) * rs + static_cast<int64_t>(i) * r1 + b0 + b] : T(0);
+      Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? Gi[(a0 + a) * sK + b0 + b] : T(0);
     }
     __syncthreads();
     const int kk = min(AK, r0 - a0);
@@ -467,6 +471,74 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int nk, c
   }
 }
 
+// Forward for narrow outputs (r1 < 16): one thread per (node, output column); the
+// node's parent vector is read from global memory, the slice column from LDS.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_fwd_narrow(int r0, int r1, int64_t sK, int64_t sI,
+                                                       const uint64_t* __restrict__ perm,
+                                                       const int64_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ parent,
+                                                       const T* __restrict__ Lprev, const T* __restrict__ G,
+                                                       T* __restrict__ Lcur) {
+  __shared__ T Ss[RMAX * 16];
+  const int i = blockIdx.x;
+  const int per = NT / r1;  // nodes per pass
+  const int64_t beg = off[i] + static_cast<int64_t>(blockIdx.y) * per * 8;
+  const int64_t end = min(off[i + 1], beg + static_cast<int64_t>(per) * 8);
+  if (beg >= end) return;
+  const T* Gi = G + static_cast<int64_t>(i) * sI;
+  for (int e = threadIdx.x; e < r0 * r1; e += NT) {
+    const int a = e / r1, b = e % r1;
+    Ss[a * r1 + b] = Gi[a * sK + b];
+  }
+  __syncthreads();
+  const int b = threadIdx.x % r1, nn = threadIdx.x / r1;
+  if (nn >= per) return;
+  for (int64_t t = beg + nn; t < end; t += per) {
+    const int64_t q = static_cast<int64_t>(perm[t]);
+    const T* v = Lprev + (parent ? static_cast<int64_t>(parent[q]) : q) * r0;
+    T acc = T(0);
+    for (int a = 0; a < r0; ++a) acc = fma(v[a], Ss[a * r1 + b], acc);
+    Lcur[q * r1 + b] = acc;
+  }
+}
+
+// Gradient partial for small outputs (r0 * r1 <= 256): thread t owns output
+// o = t % O for the entries t / O, t / O + NT / O, ... of its chunk; the per-thread
+// sums are then added in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
+                                                   const int64_t* __restrict__ off, const T* __restrict__ L,
+                                                   int64_t loff, const T* __restrict__ R,
+                                                   const uint32_t* __restrict__ lidx, int64_t chunk,
+                                                   T* __restrict__ part) {
+  __shared__ T red[NT];
+  const int i = blockIdx.x;
+  const int c = blockIdx.y;
+  const int O = r0 * r1;
+  const int lanes = NT / O;
+  const int o = threadIdx.x % O, l = threadIdx.x / O;
+  const int a = o / r1, b = o % r1;
+  const int64_t beg = off[i] + static_cast<int64_t>(c) * chunk;
+  const int64_t end = min(off[i + 1], beg + chunk);
+  T acc = T(0);
+  if (l < lanes) {
+    for (int64_t t = beg + l; t < end; t += lanes) {
+      const int64_t n = static_cast<int64_t>(perm[t]);
+      const T lv = (loff < 0) ? T(1) : L[static_cast<int64_t>(lidx[n]) * r0 + a];
+      acc = fma(lv, R[n * r1 + b], acc);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < O) {
+    T s2 = T(0);
+    for (int ll = 0; ll < lanes; ++ll) s2 += red[ll * O + threadIdx.x];
+    const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
+    part[static_cast<int64_t>(c) * csz + (static_cast<int64_t>(a) * nk + i) * r1 + b] = s2;
+  }
+}
+
 // Up vectors of depth-t nodes from their children (depth t+1).  GT is the core
 // with its slices transposed: GT[(i * r1 + b) * r0 + a] = G[a, i, b].
 template <typename T, int LPE>
@@ -474,20 +546,16 @@ __global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __rest
                                                const uint32_t* __restrict__ ccoord, const T* __restrict__ Unext,
                                                int r0, int r1, const T* __restrict__ GT, T* __restrict__ Ucur) {
   constexpr int EPW = 64 / LPE;
-  __shared__ T buf[NT / 64][EPW][RMAX];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sub = lane / LPE, l = lane % LPE;
-  T* u = buf[wv][sub];
   const int64_t stride = static_cast<int64_t>(gridDim.x) * (NT / 64) * EPW;
-  for (int64_t q = (static_cast<int64_t>(blockIdx.x) * (NT / 64) + wv) * EPW + sub; q < P + (EPW - 1); q += stride) {
-    const bool live = q < P;
-    const int64_t c0 = live ? cbeg[q] : 0, c1 = live ? cbeg[q + 1] : 0;
+  for (int64_t q = (static_cast<int64_t>(blockIdx.x) * (NT / 64) + wv) * EPW + sub; q < P; q += stride) {
+    const int64_t c0 = cbeg[q], c1 = cbeg[q + 1];
     T acc[RMAX / LPE];
 #pragma unroll
     for (int s2 = 0; s2 < RMAX / LPE; ++s2) acc[s2] = T(0);
     for (int64_t c = c0; c < c1; ++c) {
-      for (int b = l; b < r1; b += LPE) u[b] = Unext[c * r1 + b];
-      __builtin_amdgcn_wave_barrier();
+      const T* u = Unext + c * r1;
       const T* base = GT + static_cast<int64_t>(ccoord[c]) * r1 * r0;
 #pragma unroll
       for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
@@ -498,16 +566,27 @@ __global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __rest
           acc[s2] = x;
         }
       }
-      __builtin_amdgcn_wave_barrier();
     }
-    if (live) {
 #pragma unroll
-      for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
-        const int a = l + s2 * LPE;
-        if (a < r0) Ucur[q * r0 + a] = acc[s2];
-      }
+    for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
+      const int a = l + s2 * LPE;
+      if (a < r0) Ucur[q * r0 + a] = acc[s2];
     }
   }
+}
+
+// Up vector of each parent as the fixed-order sum of its children's products:
+// U[q][a] = sum_{c in [cbeg[q], cbeg[q+1])} V[c][a].  One thread per (q, a).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_segsum(int64_t P, int r0, const uint32_t* __restrict__ cbeg,
+                                                   const T* __restrict__ V, T* __restrict__ U) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= P * r0) return;
+  const int64_t q = e / r0;
+  const int a = static_cast<int>(e - q * r0);
+  T acc = T(0);
+  for (int64_t c = cbeg[q]; c < cbeg[q + 1]; ++c) acc += V[c * r0 + a];
+  U[e] = acc;
 }
 
 template <typename T>
@@ -673,6 +752,27 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hip
     for (int i = 0; i < ed.n[t - 1]; ++i) tr.bmax[t] = std::max(tr.bmax[t], hoff[t][i + 1] - hoff[t][i]);
 }
 
+// dst[q] = src[parent(q) or q] * S_{coord(q)} for every depth-t node q (see
+// k_tri_fwd_bucket); K x O slices with strides sK (rows) and sI (index).
+template <typename T>
+void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int64_t sI, const uint32_t* parent,
+                    const T* src, const T* G, T* dst, hipStream_t s) {
+  if (O < 16) {
+    const int64_t per = (NT / O) * 8;
+    const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + per - 1) / per);
+    if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
+    k_tri_fwd_narrow<T><<<dim3(nk, static_cast<unsigned>(nchunk)), NT, 0, s>>>(K, O, sK, sI, tr.bperm[t], tr.boff[t],
+                                                                                parent, src, G, dst);
+  } else {
+    const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + 63) / 64);
+    if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
+    const int tiles = (O + 63) / 64;
+    k_tri_fwd_bucket<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
+        K, O, sK, sI, tr.bperm[t], tr.boff[t], parent, src, G, dst);
+  }
+  TTS_LAUNCH_CHECK();
+}
+
 template <typename T>
 void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std::vector<T*>& Lv, hipStream_t s) {
   const int d = ed.d;
@@ -685,16 +785,12 @@ void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std:
     const int r0 = ed.r[t - 1], r1 = ed.r[t], nk = ed.n[t - 1];
     const int64_t P = tr.P[t];
     Lv[t] = mem.get<T>(static_cast<size_t>(P) * r1);
-    const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + 63) / 64);
-    if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
-    const int tiles = (r1 + 63) / 64;
     KTimer kt("eval_forward", s,
               static_cast<double>(P) * (r1 + 8) * sizeof(T) + static_cast<double>(tr.P[t - 1]) * r0 * sizeof(T) +
                   static_cast<double>(r0) * nk * r1 * sizeof(T),
               2.0 * static_cast<double>(P) * r0 * r1);
-    k_tri_fwd_bucket<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
-        r0, r1, nk, tr.bperm[t], tr.boff[t], tr.parent[t], Lv[t - 1], static_cast<const T*>(ed.core[t - 1]), Lv[t]);
-    TTS_LAUNCH_CHECK();
+    bucket_product<T>(tr, t, nk, r0, r1, static_cast<int64_t>(nk) * r1, r1, tr.parent[t], Lv[t - 1],
+                      static_cast<const T*>(ed.core[t - 1]), Lv[t], s);
   }
 }
 
@@ -750,11 +846,21 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     Uv[t] = mem.get<T>(static_cast<size_t>(P) * r0);
     KTimer kt("eval_up", s, static_cast<double>(Pc) * (r1 + 8) * sizeof(T) + static_cast<double>(P) * r0 * sizeof(T),
               2.0 * static_cast<double>(Pc) * r0 * r1);
-    if (lpe == 32)
-      k_tri_up<T, 32><<<blocks_for(P, 32), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
-    else
-      k_tri_up<T, 64><<<blocks_for(P, 64), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
-    TTS_LAUNCH_CHECK();
+    if (r1 <= 4) {
+      // short contraction: each parent walks its children directly
+      if (lpe == 32)
+        k_tri_up<T, 32><<<blocks_for(P, 32), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
+      else
+        k_tri_up<T, 64><<<blocks_for(P, 64), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
+      TTS_LAUNCH_CHECK();
+    } else {
+      // children bucketed by index: V[c] = G[:, i_c, :] U[c] as gather-GEMMs, then the
+      // fixed-order sum over each parent's children
+      T* V = mem.get<T>(static_cast<size_t>(Pc) * r0);
+      bucket_product<T>(tr, t + 1, nk, r1, r0, r0, static_cast<int64_t>(r1) * r0, nullptr, Uv[t + 1], GT, V, s);
+      k_tri_segsum<T><<<grid_for(static_cast<size_t>(P) * r0, NT), NT, 0, s>>>(P, r0, cbeg[t], V, Uv[t]);
+      TTS_LAUNCH_CHECK();
+    }
   }
   // gradients: core t pairs parents at depth t with children at depth t+1
   constexpr int KC = sizeof(T) == 8 ? 64 : 128;
@@ -772,9 +878,13 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
       KTimer ktm("eval_grad", s,
                  static_cast<double>(Pc) * (r0 + r1 + 8) * sizeof(T) + static_cast<double>(nchunk) * csz * sizeof(T),
                  2.0 * static_cast<double>(Pc) * r0 * r1);
-      k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], nullptr,
-                                                                   Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1], r1, 0, chunk,
-                                                                   part, tr.parent[t + 1]);
+      if (r0 * r1 <= NT && (r0 < 16 || r1 < 16))
+        k_grad_small<T><<<dim3(nk, nchunk), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], Lv[t],
+                                                        t == 0 ? -1 : 0, Uv[t + 1], tr.parent[t + 1], chunk, part);
+      else
+        k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1],
+                                                                     nullptr, Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1],
+                                                                     r1, 0, chunk, part, tr.parent[t + 1]);
       TTS_LAUNCH_CHECK();
     }
     k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, static_cast<T*>(grads[t]));

@@ -17,21 +17,43 @@ constexpr int NT = 256;
 // ---------------------------------------------------------------------------
 constexpr int GT = 64, GK = 16;
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// C = alpha * op(A) op(B) + beta * C on the FP64 matrix cores (column-major, op = T
+// when ta / tb).  Workgroup = one 64 x 64 tile of C over the k range
+// [blockIdx.z * kchunk, ...), 4 waves each owning a 32 x 32 quarter as 2 x 2 blocks
+// of v_mfma_f64_16x16x4 (operand lanes: A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k; accumulator register v of lane l holds row 4v + l/16, column l%16).
+// Operand tiles go through LDS 16 k-steps at a time.  sym (C = A^T A): only tiles on
+// or above the diagonal are computed, each written to both halves.  With `part` set,
+// raw tile sums go to part[z] for a fixed-order split-K reduction.
 __global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k, double alpha,
                                              const double* __restrict__ A, int lda, const double* __restrict__ B,
                                              int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, int sym) {
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  int bi = blockIdx.x, bj = blockIdx.y;
+  if (sym) {  // blockIdx.x enumerates the tiles bi <= bj
+    int rem = blockIdx.x;
+    bj = 0;
+    while (rem > bj) {
+      rem -= bj + 1;
+      ++bj;
+    }
+    bi = rem;
+  }
+  const int m0 = bi * GT, n0 = bj * GT;
   const int kb = blockIdx.z * kchunk;
   const int ke = min(k, kb + kchunk);
-  double acc[4][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = kb; k0 < ke; k0 += GK) {
     for (int e = threadIdx.x; e < GT * GK; e += NT) {
       int i, kk;
@@ -63,35 +85,40 @@ __global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ty + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    for (int ks = 0; ks < GK; ks += 4) {
+      const double a0 = As[ks + lk][wm + li], a1 = As[ks + lk][wm + 16 + li];
+      const double b0 = Bs[ks + lk][wn + li], b1 = Bs[ks + lk][wn + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gi = m0 + ty + 16 * r;
-    if (gi >= m) continue;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int gj = n0 + tx + 16 * c;
-      if (gj >= n) continue;
-      if (part) {
-        part[static_cast<size_t>(blockIdx.z) * m * n + gi + static_cast<size_t>(gj) * m] = acc[r][c];
-      } else {
-        double* cp = &C[gi + static_cast<size_t>(gj) * ldc];
-        *cp = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*cp));
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm + 16 * x + 4 * v + lk;
+        const int gj = n0 + wn + 16 * y + li;
+        if (gi >= m || gj >= n) continue;
+        const double val = acc[x][y][v];
+        const bool mirror = sym && bi < bj;
+        if (part) {
+          double* pz = part + static_cast<size_t>(blockIdx.z) * m * n;
+          pz[gi + static_cast<size_t>(gj) * m] = val;
+          if (mirror) pz[gj + static_cast<size_t>(gi) * m] = val;
+        } else {
+          double* cp = &C[gi + static_cast<size_t>(gj) * ldc];
+          *cp = (beta == 0.0) ? alpha * val : fma(alpha, val, beta * (*cp));
+          if (mirror) {
+            double* cq = &C[gj + static_cast<size_t>(gi) * ldc];
+            *cq = (beta == 0.0) ? alpha * val : fma(alpha, val, beta * (*cq));
+          }
+        }
       }
-    }
-  }
 }
 
 __global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const double* __restrict__ part,
@@ -209,6 +236,46 @@ __device__ double block_sum_1024(double x, double* red) {
 }
 
 // argmax with lowest index on ties
+// Rotation (cs, sn) that makes two columns with squared norms a, b and inner
+// product g orthogonal (the smaller-angle Jacobi rotation, Rutishauser's formulas):
+// zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+// cs = 1 / sqrt(1 + t^2), sn = cs t.  Reciprocals and reciprocal square roots come
+// from the hardware estimates refined by two Newton steps (a few ulp; a rotation only
+// needs cs^2 + sn^2 = 1 to rounding level, which it keeps since both come from t).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
+}
+__device__ __forceinline__ void jacobi_rotation(double a, double b, double g, double* cs, double* sn) {
+  double t;
+  if (fabs(g) < 1e-290) {  // reciprocal estimates are not valid near the subnormal range
+    const double zeta = (b - a) / (2.0 * g);
+    t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
+  } else {
+    const double zeta = (b - a) * rcp_nr(2.0 * g);
+    const double az = fabs(zeta);
+    if (az > 1e150) {
+      t = 0.5 / zeta;
+    } else {
+      const double q = fma(zeta, zeta, 1.0);
+      const double root = q * rsq_nr(q);
+      t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + root);
+    }
+  }
+  const double c = rsq_nr(fma(t, t, 1.0));
+  *cs = c;
+  *sn = c * t;
+}
+
 __device__ void block_argmax_1024(double v, int idx, double* redv, int* redi, double* outv, int* outi) {
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(v, o, 64);
@@ -242,6 +309,7 @@ __device__ void block_argmax_1024(double v, int idx, double* redv, int* redi, do
 }
 
 // Left-looking pivoted Cholesky (dynamic LDS: n doubles for the Schur diagonal).
+template <int LPJ>
 __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restrict__ G, int n, int ldg, int rmax,
                                                          double theta, double* __restrict__ L,
                                                          int32_t* __restrict__ piv, int32_t* __restrict__ d_r) {
@@ -259,6 +327,9 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
   int mi;
   block_argmax_1024(gmax, 0, redv, redi, &mv, &mi);
   const double thr = theta * mv;
+  // LPJ lanes share column j of the update; lane `sub` takes steps l = sub (mod LPJ)
+  constexpr int JPB = BT / LPJ;
+  const int sub = threadIdx.x % LPJ, jj = threadIdx.x / LPJ;
   int r = 0;
   for (int t = 0; t < rmax; ++t) {
     double v = -1.0;
@@ -275,21 +346,40 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
     if (threadIdx.x == 0) piv[t] = p;
     for (int l = threadIdx.x; l < t; l += BT) lp[l] = L[p + static_cast<size_t>(l) * n];
     __syncthreads();
-    const double inv = 1.0 / sqrt(pv);
-    for (int j = threadIdx.x; j < n; j += BT) {
-      double x;
-      if (j == p) {
-        x = sqrt(pv);
-        dg[j] = -1.0;
-      } else if (dg[j] < 0.0) {
-        x = 0.0;  // already a pivot: its Schur row is zero
-      } else {
-        double s = G[j + static_cast<size_t>(p) * ldg];
-        for (int l = 0; l < t; ++l) s = fma(-L[j + static_cast<size_t>(l) * n], lp[l], s);
-        x = s * inv;
-        dg[j] = dg[j] - x * x;
+    const double sq = sqrt(pv);
+    const double inv = 1.0 / sq;
+    for (int j0 = 0; j0 < n; j0 += JPB) {
+      const int j = j0 + jj;
+      const bool live = j < n && j != p && dg[min(j, n - 1)] >= 0.0;
+      // s = G[j, p] - sum_{l < t} L[j, l] L[p, l], four independent partial sums
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      if (live) {
+        const double* Lj = L + j;
+        int l = sub;
+        for (; l + 3 * LPJ < t; l += 4 * LPJ) {
+          s0 = fma(Lj[static_cast<size_t>(l) * n], lp[l], s0);
+          s1 = fma(Lj[static_cast<size_t>(l + LPJ) * n], lp[l + LPJ], s1);
+          s2 = fma(Lj[static_cast<size_t>(l + 2 * LPJ) * n], lp[l + 2 * LPJ], s2);
+          s3 = fma(Lj[static_cast<size_t>(l + 3 * LPJ) * n], lp[l + 3 * LPJ], s3);
+        }
+        for (; l < t; l += LPJ) s0 = fma(Lj[static_cast<size_t>(l) * n], lp[l], s0);
       }
-      L[j + static_cast<size_t>(t) * n] = x;
+      double acc = (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int o = LPJ / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPJ);
+      if (sub == 0 && j < n) {
+        double x;
+        if (j == p) {
+          x = sq;
+          dg[j] = -1.0;
+        } else if (!live) {
+          x = 0.0;  // already a pivot: its Schur row is zero
+        } else {
+          x = (G[j + static_cast<size_t>(p) * ldg] - acc) * inv;
+          dg[j] = dg[j] - x * x;
+        }
+        L[j + static_cast<size_t>(t) * n] = x;
+      }
     }
     __syncthreads();
     r = t + 1;
@@ -304,6 +394,68 @@ __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ 
   const int t = e % r, s = e / r;  // U[t, s] = L[piv[s], t] for t <= s
   U[t + static_cast<size_t>(s) * r] = (t <= s) ? L[piv[s] + static_cast<size_t>(t) * n] : 0.0;
 }
+
+// Cholesky of r <= R (R = 64 or 128) by one 1024-thread workgroup, upper factor.
+// The matrix sits row-major in LDS; thread (ty, c) owns column c of rows
+// ty, ty + G, ... (G = 1024 / R).  Step j subtracts a_ji a_jc / a_jj from every
+// (i, c) with j < i <= c, reading only row j: one barrier per step.  Row i is
+// scaled by 1 / sqrt(a_ii) when it is written out.
+template <int R>
+__global__ __launch_bounds__(1024) void k_cholesky_block(double* __restrict__ Ag, int r, int lda, double max_ratio,
+                                                         int32_t* __restrict__ ok) {
+  constexpr int GR = 1024 / R;
+  constexpr int RPT = R / GR;
+  __shared__ double A[R * R];
+  __shared__ int bad;
+  for (int e = threadIdx.x; e < r * r; e += 1024) {
+    const int i = e % r, c = e / r;
+    A[i * R + c] = Ag[i + static_cast<size_t>(c) * lda];
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int c = threadIdx.x % R, ty = threadIdx.x / R;
+  for (int j = 0; j < r; ++j) {
+    const double a = A[j * R + j];
+    if (!(a > 0.0)) {
+      if (threadIdx.x == 0) bad = 1;
+      break;
+    }
+    const double ia = 1.0 / a;
+    if (c > j && c < r) {
+      const double ajc = A[j * R + c] * ia;
+#pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int i = ty + u * GR;
+        if (i > j && i <= c) A[i * R + c] = fma(-A[j * R + i], ajc, A[i * R + c]);
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += 1024) {
+    const int i = e % r, cc = e / r;
+    double x = 0.0;
+    if (i == cc)
+      x = sqrt(A[i * R + i]);
+    else if (i < cc)
+      x = A[i * R + cc] / sqrt(A[i * R + i]);
+    Ag[i + static_cast<size_t>(cc) * lda] = bad ? 0.0 : x;
+  }
+  if (threadIdx.x == 0) {
+    int fail = bad;
+    if (!fail) {
+      double dmin = INFINITY, dmax = 0.0;
+      for (int i = 0; i < r; ++i) {
+        const double dd = sqrt(A[i * R + i]);
+        dmin = fmin(dmin, dd);
+        dmax = fmax(dmax, dd);
+      }
+      fail = dmax > max_ratio * dmin;
+    }
+    *ok = fail ? 0 : 1;
+  }
+}
+
 
 // Right-looking Cholesky, upper factor, in global memory, one workgroup.
 __global__ __launch_bounds__(BT) void k_cholesky_upper(double* __restrict__ A, int r, int lda, double max_ratio,
@@ -345,6 +497,83 @@ __global__ __launch_bounds__(BT) void k_cholesky_upper(double* __restrict__ A, i
     if (i > c) A[i + static_cast<size_t>(c) * lda] = 0.0;
   }
   if (threadIdx.x == 0) *ok = (bad || dmax > max_ratio * dmin) ? 0 : 1;
+}
+
+// Right triangular solve X = Y U^{-1} (U upper, r <= RM): one lane per row of Y,
+// one wave per workgroup (many workgroups for tall Y); U and the reciprocals of its
+// diagonal broadcast from LDS; forward substitution across the row with two
+// independent partial sums per entry.
+template <int RM>
+__global__ __launch_bounds__(64) void k_trsm_right_upper(const double* __restrict__ Y, int rows, int r, int ldy,
+                                                         const double* __restrict__ U, int ldu, double* __restrict__ X,
+                                                         int ldx, int32_t* __restrict__ ok) {
+  __shared__ double us[RM * RM];
+  __shared__ double dinv[RM];
+  for (int e = threadIdx.x; e < r * r; e += 64) us[e] = U[(e % r) + static_cast<size_t>(e / r) * ldu];
+  __syncthreads();
+  for (int j = threadIdx.x; j < r; j += 64) {
+    const double dd = us[j + j * r];
+    if (dd == 0.0 && blockIdx.x == 0) *ok = 0;
+    dinv[j] = (dd != 0.0) ? 1.0 / dd : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= rows) return;
+  double x[RM];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    if (j < r) {
+      double v0 = Y[i + static_cast<size_t>(j) * ldy], v1 = 0.0;
+      const double* uj = us + j * r;
+#pragma unroll
+      for (int l = 0; l + 1 < j; l += 2) {
+        v0 = fma(-x[l], uj[l], v0);
+        v1 = fma(-x[l + 1], uj[l + 1], v1);
+      }
+      if (j & 1) v0 = fma(-x[j - 1], uj[j - 1], v0);
+      x[j] = (v0 + v1) * dinv[j];
+      X[i + static_cast<size_t>(j) * ldx] = x[j];
+    }
+  }
+}
+
+// Inverse of an upper-triangular matrix staged in LDS (r <= 128): one thread per
+// column of the inverse, columns written back to global memory.
+__global__ __launch_bounds__(NT) void k_triu_inverse_lds(const double* __restrict__ U, int r, int ldu,
+                                                         double* __restrict__ X, int ldx, int32_t* __restrict__ ok) {
+  extern __shared__ double us[];
+  for (int e = threadIdx.x; e < r * r; e += NT) {
+    const int i = e % r, j = e / r;
+    us[e] = (i <= j) ? U[i + static_cast<size_t>(j) * ldu] : 0.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < r; j += NT) {
+    double* x = X + static_cast<size_t>(j) * ldx;
+    for (int i = j + 1; i < r; ++i) x[i] = 0.0;
+    const double ujj = us[j + j * r];
+    if (ujj == 0.0) {
+      *ok = 0;
+      continue;
+    }
+    double col[128];
+    col[j] = 1.0 / ujj;
+    bool bad = false;
+    for (int i = j - 1; i >= 0; --i) {
+      double sacc = 0.0;
+      for (int l = i + 1; l <= j; ++l) sacc = fma(us[i + l * r], col[l], sacc);
+      const double uii = us[i + i * r];
+      if (uii == 0.0) {
+        bad = true;
+        break;
+      }
+      col[i] = -sacc / uii;
+    }
+    if (bad) {
+      *ok = 0;
+      continue;
+    }
+    for (int i = 0; i <= j; ++i) x[i] = col[i];
+  }
 }
 
 // Inverse of an upper-triangular matrix: one thread per column of the inverse.
@@ -496,12 +725,13 @@ __global__ __launch_bounds__(NT) void k_flip_q(const double* __restrict__ A, int
   if (A[c + static_cast<size_t>(c) * lda] < 0.0) Q[i + static_cast<size_t>(c) * ldq] = -Q[i + static_cast<size_t>(c) * ldq];
 }
 
-// One-sided (Hestenes) Jacobi, one workgroup of 1024 threads = 64 groups of 16
+// One-sided (Hestenes) Jacobi, one workgroup of NTH threads = NTH/GW groups of GW
 // lanes, one column pair per group per step, circle-method pair ordering.
 // The matrix and V live in LDS when they fit (use_lds), else in global memory.
-__global__ __launch_bounds__(BT) void k_jacobi(double* __restrict__ Ag, int rows, int c, int lda,
-                                               double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
-                                               int use_lds) {
+template <int NTH, int GW>
+__global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int rows, int c, int lda,
+                                                double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
+                                                int use_lds) {
   extern __shared__ double sm[];
   __shared__ int rotated;
   double* A = Ag;
@@ -512,24 +742,27 @@ __global__ __launch_bounds__(BT) void k_jacobi(double* __restrict__ Ag, int rows
     V = sm + static_cast<size_t>(rows) * c;
     la = rows;
     lv = c;
-    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += BT) {
+    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
       const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
       A[i + static_cast<size_t>(j) * la] = Ag[i + static_cast<size_t>(j) * lda];
     }
   }
-  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += BT) {
+  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += NTH) {
     const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
     V[i + static_cast<size_t>(j) * lv] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
+  constexpr int NG = NTH / GW;
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
   const int N = c + (c & 1);  // players (a virtual empty column when c is odd)
-  const double tol = sqrt(static_cast<double>(rows)) * 2.220446049250313e-16;
+  // a column pair counts as orthogonal when |a_p . a_q| <= rows * eps * ||a_p|| ||a_q||,
+  // the rounding level of the computed dot product itself
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
   for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
-      for (int k = grp; k < N / 2; k += BT / 16) {
+      for (int k = grp; k < N / 2; k += NG) {
         int p, q;
         if (k == 0) {
           p = rd;
@@ -547,32 +780,30 @@ __global__ __launch_bounds__(BT) void k_jacobi(double* __restrict__ Ag, int rows
         double* ap = A + static_cast<size_t>(p) * la;
         double* aq = A + static_cast<size_t>(q) * la;
         double a = 0.0, b = 0.0, g = 0.0;
-        for (int i = gl; i < rows; i += 16) {
+        for (int i = gl; i < rows; i += GW) {
           const double x = ap[i], y = aq[i];
           a = fma(x, x, a);
           b = fma(y, y, b);
           g = fma(x, y, g);
         }
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          a += __shfl_xor(a, o, 16);
-          b += __shfl_xor(b, o, 16);
-          g += __shfl_xor(g, o, 16);
+        for (int o = GW / 2; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, GW);
+          b += __shfl_xor(b, o, GW);
+          g += __shfl_xor(g, o, GW);
         }
         if (a == 0.0 || b == 0.0) continue;
         if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
-        for (int i = gl; i < rows; i += 16) {
+        double cs, sn;
+        jacobi_rotation(a, b, g, &cs, &sn);
+        for (int i = gl; i < rows; i += GW) {
           const double x = ap[i], y = aq[i];
           ap[i] = cs * x - sn * y;
           aq[i] = sn * x + cs * y;
         }
         double* vp = V + static_cast<size_t>(p) * lv;
         double* vq = V + static_cast<size_t>(q) * lv;
-        for (int i = gl; i < c; i += 16) {
+        for (int i = gl; i < c; i += GW) {
           const double x = vp[i], y = vq[i];
           vp[i] = cs * x - sn * y;
           vq[i] = sn * x + cs * y;
@@ -585,23 +816,149 @@ __global__ __launch_bounds__(BT) void k_jacobi(double* __restrict__ Ag, int rows
     __syncthreads();
   }
   // column norms
-  for (int j = grp; j < c; j += BT / 16) {
+  for (int j = grp; j < c; j += NG) {
     const double* aj = A + static_cast<size_t>(j) * la;
-    double s = 0.0;
-    for (int i = gl; i < rows; i += 16) s = fma(aj[i], aj[i], s);
+    double sacc = 0.0;
+    for (int i = gl; i < rows; i += GW) sacc = fma(aj[i], aj[i], sacc);
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    if (gl == 0) sigma[j] = sqrt(s);
+    for (int o = GW / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, GW);
+    if (gl == 0) sigma[j] = sqrt(sacc);
   }
   if (use_lds) {
-    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += BT) {
+    __syncthreads();
+    for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
       const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
       Ag[i + static_cast<size_t>(j) * lda] = A[i + static_cast<size_t>(j) * la];
     }
-    for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += BT) {
+    for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += NTH) {
       const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
       Vg[i + static_cast<size_t>(j) * ldv] = V[i + static_cast<size_t>(j) * lv];
     }
+  }
+}
+
+// One-sided cyclic Jacobi (round-robin pair order) for c <= 64 columns of at most
+// GW * RPL rows, A and V staged in LDS.  32 groups of GW lanes, one column pair per
+// group per round; a lane holds its RPL entries of both columns in registers for the
+// round, so all loads of a round are in flight together.  Rotation rule and stopping
+// test as in k_jacobi.
+template <int GW, int RPL>
+__global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag, int rows, int c, int lda,
+                                                        double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+  constexpr int NTH = 32 * GW;
+  constexpr int VPL = (64 + GW - 1) / GW;
+  extern __shared__ double sm[];
+  __shared__ int rotated;
+  // odd leading dimensions: the lane groups of a wave work on different columns, and
+  // a column stride of an even number of doubles would put them on the same banks
+  const int la = rows | 1, lv = c | 1;
+  double* A = sm;                                // rows x c, leading dimension la
+  double* V = sm + static_cast<size_t>(la) * c;  // c x c, leading dimension lv
+  for (int e = threadIdx.x; e < rows * c; e += NTH) {
+    const int i = e % rows, j = e / rows;
+    A[i + j * la] = Ag[i + static_cast<size_t>(j) * lda];
+  }
+  for (int e = threadIdx.x; e < c * c; e += NTH) {
+    const int i = e % c, j = e / c;
+    V[i + j * lv] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const int N = c + (c & 1);  // players (a virtual empty column when c is odd)
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      int p = 0, q = c;
+      if (grp < N / 2) {
+        if (grp == 0) {
+          p = rd;
+          q = N - 1;
+        } else {
+          p = (rd + grp) % (N - 1);
+          q = (rd - grp + (N - 1)) % (N - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+      }
+      if (q < c) {  // uniform within the group
+        double* ap = A + static_cast<size_t>(p) * la;
+        double* aq = A + static_cast<size_t>(q) * la;
+        double x[RPL], y[RPL];
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int i = gl + u * GW;
+          x[u] = (i < rows) ? ap[i] : 0.0;
+          y[u] = (i < rows) ? aq[i] : 0.0;
+        }
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          a = fma(x[u], x[u], a);
+          b = fma(y[u], y[u], b);
+          g = fma(x[u], y[u], g);
+        }
+#pragma unroll
+        for (int o = GW / 2; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, GW);
+          b += __shfl_xor(b, o, GW);
+          g += __shfl_xor(g, o, GW);
+        }
+        if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          double cs, sn;
+          jacobi_rotation(a, b, g, &cs, &sn);
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const int i = gl + u * GW;
+            if (i < rows) {
+              ap[i] = cs * x[u] - sn * y[u];
+              aq[i] = sn * x[u] + cs * y[u];
+            }
+          }
+          double* vp = V + static_cast<size_t>(p) * lv;
+          double* vq = V + static_cast<size_t>(q) * lv;
+          double xv[VPL], yv[VPL];
+#pragma unroll
+          for (int u = 0; u < VPL; ++u) {
+            const int i = gl + u * GW;
+            xv[u] = (i < c) ? vp[i] : 0.0;
+            yv[u] = (i < c) ? vq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < VPL; ++u) {
+            const int i = gl + u * GW;
+            if (i < c) {
+              vp[i] = cs * xv[u] - sn * yv[u];
+              vq[i] = sn * xv[u] + cs * yv[u];
+            }
+          }
+          if (gl == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int j = grp; j < c; j += NTH / GW) {
+    const double* aj = A + static_cast<size_t>(j) * la;
+    double sacc = 0.0;
+    for (int i = gl; i < rows; i += GW) sacc = fma(aj[i], aj[i], sacc);
+#pragma unroll
+    for (int o = GW / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, GW);
+    if (gl == 0) sigma[j] = sqrt(sacc);
+  }
+  for (int e = threadIdx.x; e < rows * c; e += NTH) {
+    const int i = e % rows, j = e / rows;
+    Ag[i + static_cast<size_t>(j) * lda] = A[i + j * la];
+  }
+  for (int e = threadIdx.x; e < c * c; e += NTH) {
+    const int i = e % c, j = e / c;
+    Vg[i + static_cast<size_t>(j) * ldv] = V[i + j * lv];
   }
 }
 
@@ -648,7 +1005,7 @@ __global__ __launch_bounds__(NT) void k_bjacobi_round(double* __restrict__ Ag, i
   __syncthreads();
   const int grp = threadIdx.x >> 5, gl = threadIdx.x & 31;
   constexpr int NL = 2 * BJ_B;
-  const double tol = sqrt(static_cast<double>(rows)) * 2.220446049250313e-16;
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
   for (int inner = 0; inner < 4; ++inner) {
     if (threadIdx.x == 0) rot_sweep = 0;
     __syncthreads();
@@ -684,10 +1041,8 @@ __global__ __launch_bounds__(NT) void k_bjacobi_round(double* __restrict__ Ag, i
           g += __shfl_xor(g, o, 32);
         }
         if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
-          const double zeta = (b - a) / (2.0 * g);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
-          const double sn = cs * t;
+          double cs, sn;
+          jacobi_rotation(a, b, g, &cs, &sn);
           for (int i = gl; i < rows; i += 32) {
             const double x = ap[i], y = aq[i];
             ap[i] = cs * x - sn * y;
@@ -817,24 +1172,27 @@ __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int row
 void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
+  // C = A^T A: compute the upper tiles only
+  const bool sym = ta && !tb && A == B && lda == ldb && m == n;
   const int tm = (m + GT - 1) / GT, tn = (n + GT - 1) / GT;
-  const int tiles = tm * tn;
+  const int tiles = sym ? tm * (tm + 1) / 2 : tm * tn;
   int ns = 1;
-  if (tiles < 128 && k > 512) ns = std::min({(k + 255) / 256, std::max(1, 256 / tiles), 64});
+  if (tiles < 256 && k > 128) ns = std::min({(k + 127) / 128, std::max(1, 512 / tiles), 64});
   int kchunk = (k + ns - 1) / ns;
   kchunk = ((kchunk + GK - 1) / GK) * GK;
   if (kchunk == 0) kchunk = GK;
   ns = std::max(1, (k + kchunk - 1) / kchunk);
   KTimer kt("gemm", s, 8.0 * (static_cast<double>(m) * k + static_cast<double>(k) * n + static_cast<double>(m) * n),
             2.0 * static_cast<double>(m) * n * k);
+  const dim3 grid = sym ? dim3(tiles, 1, ns) : dim3(tm, tn, ns);
   if (ns == 1) {
-    k_gemm<<<dim3(tm, tn, 1), NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk > k ? kchunk : k,
-                                          nullptr);
+    k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk > k ? kchunk : k, nullptr,
+                               sym);
     TTS_LAUNCH_CHECK();
     return;
   }
   DBuf<double> part(al, static_cast<size_t>(ns) * m * n);
-  k_gemm<<<dim3(tm, tn, ns), NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part.get());
+  k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part.get(), sym);
   TTS_LAUNCH_CHECK();
   const size_t mn = static_cast<size_t>(m) * n;
   k_gemm_reduce<<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
@@ -885,7 +1243,16 @@ void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, d
                       hipStream_t s) {
   const size_t shm = sizeof(double) * (static_cast<size_t>(n) + rmax);
   if (shm > 150 * 1024) fail(TT_ERR_TOO_LARGE, "pivoted Cholesky: Gram matrix too large for one workgroup");
-  k_pivoted_cholesky<<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  if (n * 16 <= BT)
+    k_pivoted_cholesky<16><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  else if (n * 8 <= BT)
+    k_pivoted_cholesky<8><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  else if (n * 4 <= BT)
+    k_pivoted_cholesky<4><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  else if (n * 2 <= BT)
+    k_pivoted_cholesky<2><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  else
+    k_pivoted_cholesky<1><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
   TTS_LAUNCH_CHECK();
 }
 
@@ -895,13 +1262,47 @@ void pivot_factor(const double* L, int n, const int32_t* piv, int r, double* U, 
 }
 
 void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, hipStream_t s) {
+  if (r <= 64) {
+    k_cholesky_block<64><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  if (r <= 128) {
+    k_cholesky_block<128><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   k_cholesky_upper<<<1, BT, 0, s>>>(A, r, lda, max_ratio, d_ok);
   TTS_LAUNCH_CHECK();
 }
 
 void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t* d_ok, hipStream_t s) {
+  if (r <= 0) return;
+  if (r <= 128) {
+    k_triu_inverse_lds<<<1, NT, sizeof(double) * r * r, s>>>(U, r, ldu, Ui, ldi, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   k_triu_inverse<<<grid_for(r, NT), NT, 0, s>>>(U, r, ldu, Ui, ldi, d_ok);
   TTS_LAUNCH_CHECK();
+}
+
+void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
+                      int32_t* d_ok, hipStream_t s, Allocator* al) {
+  if (rows <= 0 || r <= 0) return;
+  if (r <= 32) {
+    k_trsm_right_upper<32><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  if (r <= 64) {
+    k_trsm_right_upper<64><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  DBuf<double> ui(al, static_cast<size_t>(r) * r);
+  triu_inverse(U, r, ldu, ui.get(), r, d_ok, s);
+  gemm(al, false, false, rows, r, r, 1.0, Y, ldy, ui.get(), r, 0.0, X, ldx, s);
 }
 
 void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde, const double* w, double* d_out,
@@ -945,9 +1346,20 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   KTimer kt("jacobi", s, 8.0 * 2.0 * (static_cast<double>(rows) * c + static_cast<double>(c) * c),
             // one sweep of rotations: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V)
             0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
+  const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
+  if (shm_odd <= 150 * 1024 && c <= 64 && rows <= 256) {
+    if (rows <= 64)
+      k_jacobi_reg<8, 8><<<1, 256, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+    else if (rows <= 128)
+      k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+    else
+      k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   if (shm <= 150 * 1024 || c <= 2 * BJ_B) {
     const int use_lds = shm <= 150 * 1024;
-    k_jacobi<<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds);
+    k_jacobi<BT, 16><<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds);
     TTS_LAUNCH_CHECK();
     return;
   }

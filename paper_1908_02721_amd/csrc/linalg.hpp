@@ -42,6 +42,11 @@ void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, 
 // Inverse of an upper-triangular r x r matrix (out-of-place).  *d_ok = 0 if singular.
 void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t* d_ok, hipStream_t s);
 
+// X = Y U^{-1} for an upper-triangular r x r U (rows x r, column-major).
+// *d_ok = 0 if U has a zero diagonal entry.
+void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
+                      int32_t* d_ok, hipStream_t s, Allocator* al);
+
 // out = sum_j w[j] * ||E[:, j]||^2  (deterministic), written to *d_out
 void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde, const double* w, double* d_out,
                     hipStream_t s);

@@ -58,19 +58,17 @@ void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
 // CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
 // Returns false when a Cholesky factor breaks down or is too ill-conditioned.
 bool cholqr2(Allocator* al, const double* G, int m, int c, double* Q, double* R, hipStream_t s) {
-  DBuf<double> g1(al, static_cast<size_t>(c) * c), u1i(al, static_cast<size_t>(c) * c),
-      q1(al, static_cast<size_t>(m) * c), g2(al, static_cast<size_t>(c) * c), u2i(al, static_cast<size_t>(c) * c);
+  DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
+      g2(al, static_cast<size_t>(c) * c);
   DBuf<int32_t> ok(al, 4);
   k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
   TTS_LAUNCH_CHECK();
   gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
   cholesky_upper(g1.get(), c, c, 1e7, ok.get() + 0, s);
-  triu_inverse(g1.get(), c, c, u1i.get(), c, ok.get() + 1, s);
-  gemm(al, false, false, m, c, c, 1.0, G, m, u1i.get(), c, 0.0, q1.get(), m, s);
+  trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok.get() + 1, s, al);
   gemm(al, true, false, c, c, m, 1.0, q1.get(), m, q1.get(), m, 0.0, g2.get(), c, s);
   cholesky_upper(g2.get(), c, c, 10.0, ok.get() + 2, s);
-  triu_inverse(g2.get(), c, c, u2i.get(), c, ok.get() + 3, s);
-  gemm(al, false, false, m, c, c, 1.0, q1.get(), m, u2i.get(), c, 0.0, Q, m, s);
+  trsm_right_upper(q1.get(), m, c, m, g2.get(), c, Q, m, ok.get() + 3, s, al);
   gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
   int32_t h[4];
   d2h(h, ok.get(), 4, s);
@@ -133,21 +131,18 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       d2h(&rsel, cnt.get(), 1, s);
       if (rsel > 0) {
         DBuf<double> Ys(A, static_cast<size_t>(rows) * rsel), U1(A, static_cast<size_t>(rsel) * rsel),
-            U1i(A, static_cast<size_t>(rsel) * rsel), Q1(A, static_cast<size_t>(rows) * rsel),
-            G2(A, static_cast<size_t>(rsel) * rsel), U2i(A, static_cast<size_t>(rsel) * rsel);
+            Q1(A, static_cast<size_t>(rows) * rsel), G2(A, static_cast<size_t>(rsel) * rsel);
         DBuf<int32_t> ok(A, 4);
         DBuf<double> e2(A, 1);
         k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
         TTS_LAUNCH_CHECK();
         gather_cols(X.get(), rows, rows, piv.get(), rsel, w[k].get(), Ys.get(), rows, s);
         pivot_factor(L.get(), cols, piv.get(), rsel, U1.get(), s);
-        triu_inverse(U1.get(), rsel, rsel, U1i.get(), rsel, ok.get() + 1, s);
-        gemm(A, false, false, rows, rsel, rsel, 1.0, Ys.get(), rows, U1i.get(), rsel, 0.0, Q1.get(), rows, s);
+        trsm_right_upper(Ys.get(), rows, rsel, rows, U1.get(), rsel, Q1.get(), rows, ok.get() + 1, s, A);
         gemm(A, true, false, rsel, rsel, rows, 1.0, Q1.get(), rows, Q1.get(), rows, 0.0, G2.get(), rsel, s);
         cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
-        triu_inverse(G2.get(), rsel, rsel, U2i.get(), rsel, ok.get() + 3, s);
         Q.reset(A, static_cast<size_t>(rows) * rsel);
-        gemm(A, false, false, rows, rsel, rsel, 1.0, Q1.get(), rows, U2i.get(), rsel, 0.0, Q.get(), rows, s);
+        trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
         Wn.reset(A, static_cast<size_t>(rsel) * cols);
         gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
         // residual of the basis, weighted by the right-part row norms
@@ -206,34 +201,41 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     const int rl = static_cast<int>(r[k - 1]), nk = n[k - 1], rr = static_cast<int>(r[k]);
     const int m = nk * rr;
     double* Gk = reinterpret_cast<double*>(cores[k - 1].get());  // column-major m x rl
-    DBuf<double> Qb, B;
-    int rowsB = m;
+    // G = Q R (m > rl) or G itself; one-sided Jacobi then runs on the transpose,
+    // Bt = R^T or G^T (rl x cB): Bt U_R = V_R Sigma, so the accumulated rotations
+    // are the left singular vectors of R (resp. G) and the rotated columns are
+    // V Sigma, both without a division by sigma.  (Jacobi on R^T rather than R
+    // also needs far fewer sweeps: the triangular factor acts as a preconditioner.)
+    DBuf<double> Qb, Bt;
     bool haveQ = false;
+    int cB = m;
+    Bt.reset(A, static_cast<size_t>(rl) * std::min(m, rl));
     if (m > rl) {
       Qb.reset(A, static_cast<size_t>(m) * rl);
-      B.reset(A, static_cast<size_t>(rl) * rl);
-      if (!cholqr2(A, Gk, m, rl, Qb.get(), B.get(), s)) {
+      DBuf<double> R(A, static_cast<size_t>(rl) * rl);
+      if (!cholqr2(A, Gk, m, rl, Qb.get(), R.get(), s)) {
         DBuf<double> Af(A, static_cast<size_t>(m) * rl), th(A, rl);
         copy_matrix(Gk, m, rl, m, Af.get(), m, s);
         householder_qr(Af.get(), m, rl, m, th.get(), s);
         householder_form_q(Af.get(), m, rl, m, th.get(), Qb.get(), m, s);
-        householder_extract_r(Af.get(), m, rl, m, B.get(), rl, Qb.get(), m, s);
+        householder_extract_r(Af.get(), m, rl, m, R.get(), rl, Qb.get(), m, s);
       }
-      rowsB = rl;
+      transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
+      cB = rl;
       haveQ = true;
     } else {
-      B.reset(A, static_cast<size_t>(m) * rl);
-      copy_matrix(Gk, m, rl, m, B.get(), m, s);
+      transpose(Gk, m, rl, m, Bt.get(), rl, s);
     }
-    DBuf<double> V(A, static_cast<size_t>(rl) * rl), sig(A, rl);
-    jacobi_svd(B.get(), rowsB, rl, rowsB, V.get(), rl, sig.get(), s);
-    std::vector<double> sh(rl);
-    d2h(sh.data(), sig.get(), rl, s);
-    std::vector<int32_t> perm(rl);
+    DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
+    jacobi_svd(Bt.get(), rl, cB, rl, V.get(), cB, sig.get(), s);
+    std::vector<double> sh(cB);
+    d2h(sh.data(), sig.get(), cB, s);
+    std::vector<int32_t> perm(cB);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return sh[x] > sh[y]; });
-    std::vector<double> ss(rl), tailsum(rl + 1, 0.0);
-    for (int j = 0; j < rl; ++j) ss[j] = sh[perm[j]];
+    // rl singular values in all (the rl - cB beyond the rank bound are zero)
+    std::vector<double> ss(rl, 0.0), tailsum(rl + 1, 0.0);
+    for (int j = 0; j < cB; ++j) ss[j] = sh[perm[j]];
     for (int j = rl - 1; j >= 0; --j) tailsum[j] = tailsum[j + 1] + ss[j] * ss[j];
     int rk;
     if (in.max_rank > 0) {
@@ -248,21 +250,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
           break;
         }
     }
+    rk = std::min(rk, cB);
     out.sigma[k - 2] = ss;
     out.tail[k - 2] = tailsum[rk];
-    std::vector<double> inv(rk), sc(rk);
-    for (int j = 0; j < rk; ++j) {
-      inv[j] = 1.0 / ss[j];
-      sc[j] = ss[j];
-    }
     DBuf<int32_t> dperm(A, rk);
-    DBuf<double> dinv(A, rk), dsc(A, rk);
     h2d(dperm.get(), perm.data(), rk, s);
-    h2d(dinv.get(), inv.data(), rk, s);
-    h2d(dsc.get(), sc.data(), rk, s);
-    DBuf<double> UR(A, static_cast<size_t>(rowsB) * rk), VS(A, static_cast<size_t>(rl) * rk);
-    permute_cols(B.get(), rowsB, rowsB, dperm.get(), dinv.get(), rk, UR.get(), rowsB, s);
-    permute_cols(V.get(), rl, rl, dperm.get(), dsc.get(), rk, VS.get(), rl, s);
+    DBuf<double> UR(A, static_cast<size_t>(cB) * rk), VS(A, static_cast<size_t>(rl) * rk);
+    permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
+    permute_cols(Bt.get(), rl, rl, dperm.get(), nullptr, rk, VS.get(), rl, s);
     DBuf<char> Unew(A, sizeof(double) * static_cast<size_t>(m) * rk);
     double* U = reinterpret_cast<double*>(Unew.get());
     if (haveQ)
