@@ -28,11 +28,12 @@ METRIC = "nonzeros decomposed/sec at fixed eps (FP64 vs mixed) + HBM/MFMA roofli
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0  # dense
 # Kernel family that dominates one step (per the rocprofv3 kernel-trace summaries
 # under profiles/), and what bounds it.
 DOMINANT = "eval_grad"
 FAMILY_BOUND = {
-    "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "gemm": "alu", "jacobi": "alu",
+    "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "gemm": "mfma", "gemm_lp": "mfma", "jacobi": "alu",
     "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm",
 }
 
@@ -50,13 +51,17 @@ def _parse():
     return p.parse_args()
 
 
-def cpu_baseline(idx, val, dims, eps, sample):
-    """The oracle (single-threaded FP64 C++), timed on this host on a bounded sample."""
+def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", max_rank=0):
+    """The oracle (single-threaded FP64 C++), timed on this host on a bounded sample.
+
+    Also returns ||B_gpu - B_oracle||_F / ||A||_F for the GPU result `gpu_cores`
+    (computed after the timing, with the oracle's stable TT-difference norm).
+    """
     import oracle
 
     oracle.build(force=False)
     t0 = time.perf_counter()
-    res = oracle.decompose(idx, val, dims, eps)
+    res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank)
     t_dec = time.perf_counter() - t0
     rng = np.random.Generator(np.random.PCG64(11))
     pick = rng.choice(len(val), min(sample, len(val)), replace=False)
@@ -66,14 +71,20 @@ def cpu_baseline(idx, val, dims, eps, sample):
     t_eval = time.perf_counter() - t0
     del y
     t_step = t_dec + t_eval * (len(val) / len(pick))
-    return {
+    base = {
         "value": len(val) / t_step,
         "unit": "nnz/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"full decomposition of the workload ({t_dec:.2f} s) + eval/backward on {len(pick)} of "
+        "sample": (f"full FP64 decomposition of the workload ({t_dec:.2f} s) + eval/backward on {len(pick)} of "
                    f"{len(val)} nonzeros ({t_eval:.2f} s, scaled linearly to all nonzeros)"),
     }
+    err = None
+    if gpu_cores is not None:
+        c64 = [np.ascontiguousarray(c, dtype=np.float64) for c in gpu_cores]
+        err = {"precision": precision, "rel_fro": oracle.tt_diff_norm(c64, res.cores) / res.norm,
+               "ranks_gpu": [int(c.shape[0]) for c in c64] + [1], "ranks_oracle": list(res.ranks)}
+    return base, err
 
 
 def main():
@@ -151,14 +162,21 @@ def main():
             peak, unit = HBM_PEAK_GBS, "GB/s"
         else:
             achieved = k_flops / (k_ms / 1000.0) / 1e12
-            fp32 = args.precision != "fp64" and args.roofline in ("eval_forward", "eval_up", "eval_grad")
-            peak, unit = (FP32_PEAK_TFLOPS if fp32 else FP64_PEAK_TFLOPS), "TFLOP/s"
+            unit = "TFLOP/s"
+            if args.roofline == "gemm_lp":
+                peak = BF16_PEAK_TFLOPS if args.precision == "bf16" else FP32_PEAK_TFLOPS
+            elif args.precision != "fp64" and args.roofline in ("eval_forward", "eval_up", "eval_grad"):
+                peak = FP32_PEAK_TFLOPS
+            else:
+                peak = FP64_PEAK_TFLOPS
         out["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                            "traffic": None, "kernel": args.roofline, "launches_per_step": k_n / args.steps,
                            "kernel_ms_per_step": k_ms / args.steps,
                            "algo_bytes_per_launch": k_bytes / k_n, "algo_flops_per_launch": k_flops / k_n}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample)
+        cores_host = [c.cpu().numpy() for c in tt.cores]
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample,
+                                                                   cores_host, args.precision)
     print(json.dumps(out), flush=True)
 
 

@@ -232,17 +232,24 @@ __global__ __launch_bounds__(NT) void k_zero(T* __restrict__ p, int64_t n) {
 
 tt_status check_args(int32_t d, const int64_t* dims, const int64_t* ranks, const void* const* cores, int32_t dtype,
                      int64_t m, const int32_t* idx, EvalDesc& ed) {
-  if (d < 1 || d > TT_MAX_D || !dims || !ranks || !cores || m < 0 || (m > 0 && !idx)) return TT_ERR_ARG;
-  if (dtype != TT_DTYPE_F64 && dtype != TT_DTYPE_F32) return TT_ERR_ARG;
-  if (ranks[0] != 1 || ranks[d] != 1) return TT_ERR_ARG;
+  auto bad = [](const char* why) {
+    set_last_error(why);
+    return TT_ERR_ARG;
+  };
+  if (d < 1 || d > TT_MAX_D) return bad("d must be in [1, TT_MAX_D]");
+  if (!dims || !ranks || !cores) return bad("dims, ranks and cores must not be NULL");
+  if (m < 0 || (m > 0 && !idx)) return bad("m must be >= 0 and idx non-NULL when m > 0");
+  if (dtype != TT_DTYPE_F64 && dtype != TT_DTYPE_F32) return bad("unknown dtype");
+  if (ranks[0] != 1 || ranks[d] != 1) return bad("ranks[0] and ranks[d] must be 1");
   ed = EvalDesc{};
   ed.d = d;
   for (int k = 0; k <= d; ++k) {
-    if (ranks[k] < 1 || ranks[k] > RMAX) return TT_ERR_ARG;
+    if (ranks[k] < 1 || ranks[k] > RMAX) return bad("every rank must be in [1, 256]");
     ed.r[k] = static_cast<int32_t>(ranks[k]);
   }
   for (int k = 0; k < d; ++k) {
-    if (dims[k] < 1 || dims[k] > INT32_MAX || !cores[k]) return TT_ERR_ARG;
+    if (dims[k] < 1 || dims[k] > INT32_MAX) return bad("every mode size must be in [1, 2^31 - 1]");
+    if (!cores[k]) return bad("a core pointer is NULL");
     ed.n[k] = static_cast<int32_t>(dims[k]);
     ed.core[k] = cores[k];
   }
@@ -990,7 +997,10 @@ extern "C" tt_status tt_eval_entries(int32_t d, const int64_t* dims, const int64
   EvalDesc ed;
   tt_status st = check_args(d, dims, ranks, cores, dtype, m, idx, ed);
   if (st != TT_OK) return st;
-  if (m > 0 && !y_out) return TT_ERR_ARG;
+  if (m > 0 && !y_out) {
+    set_last_error("y_out must not be NULL when m > 0");
+    return TT_ERR_ARG;
+  }
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dtype == TT_DTYPE_F64 ? eval_impl<double>(ed, m, idx, y_out, s) : eval_impl<float>(ed, m, idx, y_out, s);
@@ -1006,9 +1016,15 @@ extern "C" tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, co
   EvalDesc ed;
   tt_status st = check_args(d, dims, ranks, cores, dtype, m, idx, ed);
   if (st != TT_OK) return st;
-  if ((m > 0 && !grad_y) || !grad_cores) return TT_ERR_ARG;
+  if ((m > 0 && !grad_y) || !grad_cores) {
+    set_last_error("grad_y (when m > 0) and grad_cores must not be NULL");
+    return TT_ERR_ARG;
+  }
   for (int k = 0; k < d; ++k)
-    if (!grad_cores[k]) return TT_ERR_ARG;
+    if (!grad_cores[k]) {
+      set_last_error("a gradient core pointer is NULL");
+      return TT_ERR_ARG;
+    }
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
     return dtype == TT_DTYPE_F64

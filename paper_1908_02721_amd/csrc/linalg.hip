@@ -121,6 +121,132 @@ __global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k
       }
 }
 
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Reduced-precision variant of k_gemm for the mixed-precision modes: operands are
+// rounded to binary32 while staged in LDS (BF = 1: further to bfloat16, round to
+// nearest even, when packed into MFMA operands) and multiplied on the matrix cores
+// with binary32 accumulation -- v_mfma_f32_16x16x4_f32 (operands as in k_gemm) or
+// v_mfma_f32_16x16x32_bf16 (lane l holds A[l%16][8(l/16)..8(l/16)+7] and
+// B[8(l/16)..+7][l%16]); both accumulate row 4(l/16)+v, column l%16 in register v.
+// Storage stays binary64; split-K partials are summed in binary64.
+template <int BF>
+__global__ __launch_bounds__(NT) void k_gemm_lp(int ta, int tb, int m, int n, int k, double alpha,
+                                                const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                                int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
+                                                double* __restrict__ part, int sym) {
+  constexpr int LK = 32;
+  __shared__ float As[LK][GT + 1];
+  __shared__ float Bs[LK][GT + 1];
+  int bi = blockIdx.x, bj = blockIdx.y;
+  if (sym) {
+    int rem = blockIdx.x;
+    bj = 0;
+    while (rem > bj) {
+      rem -= bj + 1;
+      ++bj;
+    }
+    bi = rem;
+  }
+  const int m0 = bi * GT, n0 = bj * GT;
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(k, kb + kchunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  flt4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += LK) {
+    for (int e = threadIdx.x; e < GT * LK; e += NT) {
+      int i, kk;
+      if (!ta) {
+        i = e % GT;
+        kk = e / GT;
+      } else {
+        kk = e % LK;
+        i = e / LK;
+      }
+      const int gi = m0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < ke) v = ta ? A[gk + static_cast<size_t>(gi) * lda] : A[gi + static_cast<size_t>(gk) * lda];
+      As[kk][i] = static_cast<float>(v);
+    }
+    for (int e = threadIdx.x; e < GT * LK; e += NT) {
+      int j, kk;
+      if (!tb) {
+        kk = e % LK;
+        j = e / LK;
+      } else {
+        j = e % GT;
+        kk = e / GT;
+      }
+      const int gj = n0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < n && gk < ke) v = tb ? B[gj + static_cast<size_t>(gk) * ldb] : B[gk + static_cast<size_t>(gj) * ldb];
+      Bs[kk][j] = static_cast<float>(v);
+    }
+    __syncthreads();
+    if (BF) {
+      bf16x8 a0, a1, b0, b1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0[u] = static_cast<__bf16>(As[8 * lk + u][wm + li]);
+        a1[u] = static_cast<__bf16>(As[8 * lk + u][wm + 16 + li]);
+        b0[u] = static_cast<__bf16>(Bs[8 * lk + u][wn + li]);
+        b1[u] = static_cast<__bf16>(Bs[8 * lk + u][wn + 16 + li]);
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < LK; ks += 4) {
+        const float a0 = As[ks + lk][wm + li], a1 = As[ks + lk][wm + 16 + li];
+        const float b0 = Bs[ks + lk][wn + li], b1 = Bs[ks + lk][wn + 16 + li];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gi = m0 + wm + 16 * x + 4 * lk + v;
+        const int gj = n0 + wn + 16 * y + li;
+        if (gi >= m || gj >= n) continue;
+        const double val = static_cast<double>(acc[x][y][v]);
+        const bool mirror = sym && bi < bj;
+        if (part) {
+          double* pz = part + static_cast<size_t>(blockIdx.z) * m * n;
+          pz[gi + static_cast<size_t>(gj) * m] = val;
+          if (mirror) pz[gj + static_cast<size_t>(gi) * m] = val;
+        } else {
+          double* cp = &C[gi + static_cast<size_t>(gj) * ldc];
+          *cp = (beta == 0.0) ? alpha * val : fma(alpha, val, beta * (*cp));
+          if (mirror) {
+            double* cq = &C[gj + static_cast<size_t>(gi) * ldc];
+            *cq = (beta == 0.0) ? alpha * val : fma(alpha, val, beta * (*cq));
+          }
+        }
+      }
+}
+
+__global__ __launch_bounds__(NT) void k_to_f32(const double* __restrict__ x, size_t n, float* __restrict__ y) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e < n) y[e] = static_cast<float>(x[e]);
+}
+
 __global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const double* __restrict__ part,
                                                     double alpha, double beta, double* __restrict__ C, int ldc) {
   const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
@@ -1169,33 +1295,50 @@ __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int row
 
 }  // namespace
 
-void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
-          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
+void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
+               int lda, const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return;
   // C = A^T A: compute the upper tiles only
   const bool sym = ta && !tb && A == B && lda == ldb && m == n;
+  const int kstep = (prec == TT_FP64) ? GK : 32;
   const int tm = (m + GT - 1) / GT, tn = (n + GT - 1) / GT;
   const int tiles = sym ? tm * (tm + 1) / 2 : tm * tn;
   int ns = 1;
   if (tiles < 256 && k > 128) ns = std::min({(k + 127) / 128, std::max(1, 512 / tiles), 64});
   int kchunk = (k + ns - 1) / ns;
-  kchunk = ((kchunk + GK - 1) / GK) * GK;
-  if (kchunk == 0) kchunk = GK;
+  kchunk = ((kchunk + kstep - 1) / kstep) * kstep;
+  if (kchunk == 0) kchunk = kstep;
   ns = std::max(1, (k + kchunk - 1) / kchunk);
-  KTimer kt("gemm", s, 8.0 * (static_cast<double>(m) * k + static_cast<double>(k) * n + static_cast<double>(m) * n),
+  KTimer kt(prec == TT_FP64 ? "gemm" : "gemm_lp", s,
+            8.0 * (static_cast<double>(m) * k + static_cast<double>(k) * n + static_cast<double>(m) * n),
             2.0 * static_cast<double>(m) * n * k);
   const dim3 grid = sym ? dim3(tiles, 1, ns) : dim3(tm, tn, ns);
-  if (ns == 1) {
-    k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk > k ? kchunk : k, nullptr,
-                               sym);
-    TTS_LAUNCH_CHECK();
-    return;
-  }
-  DBuf<double> part(al, static_cast<size_t>(ns) * m * n);
-  k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part.get(), sym);
+  DBuf<double> part;
+  if (ns > 1) part.reset(al, static_cast<size_t>(ns) * m * n);
+  const int kc = (ns == 1) ? std::max(kchunk, k) : kchunk;
+  double* pp = (ns == 1) ? nullptr : part.get();
+  if (prec == TT_FP64)
+    k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
+  else if (prec == TT_FP32)
+    k_gemm_lp<0><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
+  else
+    k_gemm_lp<1><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
   TTS_LAUNCH_CHECK();
-  const size_t mn = static_cast<size_t>(m) * n;
-  k_gemm_reduce<<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+  if (ns > 1) {
+    const size_t mn = static_cast<size_t>(m) * n;
+    k_gemm_reduce<<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+    TTS_LAUNCH_CHECK();
+  }
+}
+
+void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+          const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s) {
+  gemm_prec(al, TT_FP64, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+void to_f32(const double* x, size_t n, float* y, hipStream_t s) {
+  if (n == 0) return;
+  k_to_f32<<<grid_for(n, NT), NT, 0, s>>>(x, n, y);
   TTS_LAUNCH_CHECK();
 }
 

@@ -10,6 +10,13 @@ namespace tts {
 // Split-K with a fixed-order reduction when the output is small (deterministic).
 void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
           const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
+// The same product with the operands rounded to the precision `prec` (tt_precision):
+// TT_FP64 as gemm; TT_FP32 binary32 operands, TT_BF16_FP32ACC bfloat16 operands, both
+// on the matrix cores with binary32 accumulation.  Storage stays binary64.
+void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
+               int lda, const double* B, int ldb, double beta, double* C, int ldc, hipStream_t s);
+// y = (float) x
+void to_f32(const double* x, size_t n, float* y, hipStream_t s);
 
 // X (rows = r * n_k, cols = ncols) = W x_1 N  with N in CSC (rows rho = g * n_k + i):
 // X[a * n_k + i, b] = sum_g W[a, g] * N[g * n_k + i, b];  W is r x rw (ld ldw).

@@ -78,7 +78,8 @@ bool cholqr2(Allocator* al, const double* G, int m, int c, double* Q, double* R,
 }  // namespace
 
 void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid) {
-  if (in.precision != TT_FP64) fail(TT_ERR_ARG, "mixed-precision rounding is not available in this build");
+  const int prec = in.precision;
+  if (prec != TT_FP64 && prec != TT_FP32 && prec != TT_BF16_FP32ACC) fail(TT_ERR_ARG, "unknown precision");
   const int d = in.d;
   std::vector<int> n(d), beta(d + 1);
   for (int k = 0; k < d; ++k) n[k] = static_cast<int>(in.dims[k]);
@@ -100,7 +101,12 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
                   w[k + 1].get(), w[k].get(), s);
   }
 
-  const double tau = std::min(1e-2 * in.delta, kTauRel * in.norm);
+  // Acceptance threshold of a deflated basis.  With reduced-precision contractions the
+  // carried factor W' = Q^T X is only accurate to the operands' unit roundoff u, so the
+  // threshold is raised to 64 u ||A||_F (the residual itself is always formed in FP64).
+  double tau = std::min(1e-2 * in.delta, kTauRel * in.norm);
+  if (prec == TT_FP32) tau = std::max(tau, 64.0 * 0x1p-24 * in.norm);
+  if (prec == TT_BF16_FP32ACC) tau = std::max(tau, 64.0 * 0x1p-8 * in.norm);
   std::vector<int64_t> r(d + 1, 1);
   std::vector<DBuf<char>> cores(d);
 
@@ -144,7 +150,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
         Q.reset(A, static_cast<size_t>(rows) * rsel);
         trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
         Wn.reset(A, static_cast<size_t>(rsel) * cols);
-        gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
+        gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
         // residual of the basis, weighted by the right-part row norms
         DBuf<double> E(A, static_cast<size_t>(rows) * cols);
         copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s);
@@ -186,7 +192,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     // last core: W (r_{d-1} x beta_{d-1}) times the exact last core (beta_{d-1} x n_d)
     const int nd = n[d - 1], bl = beta[d - 1];
     DBuf<double> C(A, static_cast<size_t>(rp) * nd);
-    gemm(A, false, true, rp, nd, bl, 1.0, W.get(), rp, in.last_core, nd, 0.0, C.get(), rp, s);
+    gemm_prec(A, prec, false, true, rp, nd, bl, 1.0, W.get(), rp, in.last_core, nd, 0.0, C.get(), rp, s);
     cores[d - 1].reset(A, sizeof(double) * static_cast<size_t>(rp) * nd);
     transpose(C.get(), rp, nd, rp, reinterpret_cast<double*>(cores[d - 1].get()), nd, s);
   }
@@ -261,14 +267,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     DBuf<char> Unew(A, sizeof(double) * static_cast<size_t>(m) * rk);
     double* U = reinterpret_cast<double*>(Unew.get());
     if (haveQ)
-      gemm(A, false, false, m, rk, rl, 1.0, Qb.get(), m, UR.get(), rl, 0.0, U, m, s);
+      gemm_prec(A, prec, false, false, m, rk, rl, 1.0, Qb.get(), m, UR.get(), rl, 0.0, U, m, s);
     else
       copy_matrix(UR.get(), m, rk, m, U, m, s);
     sign_fix(U, m, rk, m, VS.get(), rl, rl, s);
     // merge V*Sigma into core k-1: unfold_2(G_{k-1}) (rows2 x rl) * VS (rl x rk)
     const int rows2 = static_cast<int>(r[k - 2]) * n[k - 2];
     DBuf<char> Pnew(A, sizeof(double) * static_cast<size_t>(rows2) * rk);
-    gemm(A, true, false, rk, rows2, rl, 1.0, VS.get(), rl, reinterpret_cast<double*>(cores[k - 2].get()), rl, 0.0,
+    gemm_prec(A, prec, true, false, rk, rows2, rl, 1.0, VS.get(), rl, reinterpret_cast<double*>(cores[k - 2].get()), rl, 0.0,
          reinterpret_cast<double*>(Pnew.get()), rk, s);
     cores[k - 1] = std::move(Unew);
     cores[k - 2] = std::move(Pnew);
@@ -276,8 +282,18 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     TTS_HIP(hipStreamSynchronize(s));  // host vectors above are read by the copies
   }
   out.ranks = r;
-  out.cores = std::move(cores);
   out.dtype = TT_DTYPE_F64;
+  if (prec != TT_FP64) {
+    // mixed-precision results are handed out in binary32
+    for (int k = 0; k < d; ++k) {
+      const size_t ne = static_cast<size_t>(r[k]) * n[k] * r[k + 1];
+      DBuf<char> c32(A, sizeof(float) * ne);
+      to_f32(reinterpret_cast<const double*>(cores[k].get()), ne, reinterpret_cast<float*>(c32.get()), s);
+      cores[k] = std::move(c32);
+    }
+    out.dtype = TT_DTYPE_F32;
+  }
+  out.cores = std::move(cores);
 }
 
 }  // namespace tts

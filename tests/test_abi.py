@@ -85,3 +85,34 @@ def test_null_handles(lib):
     r = (ctypes.c_int64 * 4)()
     assert lib.tt_get_ranks(None, r) == 1
     assert lib.tt_get_core(None, 1, ctypes.byref(ctypes.c_void_p()), None) == 1
+
+
+def test_eval_host_argument_errors(lib):
+    """Argument errors of the evaluation calls are reported on the host, each with its own message."""
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    d = 2
+    cores = (ctypes.c_void_p * d)(fake, fake)
+    grads = (ctypes.c_void_p * d)(fake, fake)
+
+    def ev(dims, ranks, dtype=0, m=4, idx=fake, y=fake):
+        a = (ctypes.c_int64 * d)(*dims)
+        r = (ctypes.c_int64 * (d + 1))(*ranks)
+        return lib.tt_eval_entries(d, a, r, cores, dtype, m, idx, y, None)
+
+    def bw(dims, ranks, dtype=0, m=4):
+        a = (ctypes.c_int64 * d)(*dims)
+        r = (ctypes.c_int64 * (d + 1))(*ranks)
+        return lib.tt_eval_entries_backward(d, a, r, cores, dtype, m, fake, fake, grads, None)
+
+    cases = [
+        (lambda: ev([4, 4], [1, 300, 1]), "rank"),
+        (lambda: ev([4, 4], [2, 3, 1]), "ranks[0]"),
+        (lambda: ev([4, 0], [1, 3, 1]), "mode size"),
+        (lambda: ev([4, 4], [1, 3, 1], dtype=5), "dtype"),
+        (lambda: ev([4, 4], [1, 3, 1], m=-1), "m must"),
+        (lambda: ev([4, 4], [1, 3, 1], y=None), "y_out"),
+        (lambda: bw([4, 4], [1, 300, 1]), "rank"),
+    ]
+    for call, word in cases:
+        assert call() == 1
+        assert word in lib.tt_last_error().decode(), lib.tt_last_error()
