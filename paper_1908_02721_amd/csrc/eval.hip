@@ -146,73 +146,6 @@ __global__ __launch_bounds__(NT) void k_bucket_offsets(const uint64_t* __restric
   off[i] = lo;
 }
 
-// Partial gradient of core k for one (bucket i, chunk c, output tile) workgroup.
-// Output tile: rows a in [a0, a0+64), columns b in [b0, b0+64); thread owns a 4x4
-// register tile (rows ty + 16u, columns tx + 16v).
-template <typename T, int KC>
-__global__ __launch_bounds__(NT) void k_grad_partial(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
-                                                     const int64_t* __restrict__ off, const T* __restrict__ gy,
-                                                     const T* __restrict__ L, int64_t lsum, int64_t loff,
-                                                     const T* __restrict__ R, int64_t rsum, int64_t roff,
-                                                     int64_t chunk, T* __restrict__ part,
-                                                     const uint32_t* __restrict__ lidx) {
-  __shared__ T Ls[KC][65];
-  __shared__ T Rs[KC][65];
-  const int i = blockIdx.x;
-  const int c = blockIdx.y;
-  const int tA = (r0 + 63) / 64;
-  const int a0 = (blockIdx.z % tA) * 64, b0 = (blockIdx.z / tA) * 64;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t beg = off[i] + static_cast<int64_t>(c) * chunk;
-  const int64_t end = min(off[i + 1], beg + chunk);
-  T acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-  for (int64_t s0 = beg; s0 < end; s0 += KC) {
-    const int cnt = static_cast<int>(min(static_cast<int64_t>(KC), end - s0));
-    for (int e = threadIdx.x; e < KC * 64; e += NT) {
-      const int t = e / 64, j = e % 64;
-      T lv = T(0), rv = T(0);
-      if (t < cnt) {
-        const int64_t n = static_cast<int64_t>(perm[s0 + t]);
-        const int64_t nl = lidx ? static_cast<int64_t>(lidx[n]) : n;
-        const int a = a0 + j, b = b0 + j;
-        if (a < r0) lv = (loff < 0 ? T(1) : L[nl * lsum + loff + a]) * (gy ? gy[n] : T(1));
-        if (b < r1) rv = (roff < 0 ? T(1) : R[n * rsum + roff + b]);
-      }
-      Ls[t][j] = lv;
-      Rs[t][j] = rv;
-    }
-    __syncthreads();
-    for (int t = 0; t < cnt; ++t) {
-      T av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = Ls[t][ty + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Rs[t][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-  // partial of chunk c, laid out like the core: [a][i][b]
-  const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int a = a0 + ty + 16 * u;
-    if (a >= r0) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + tx + 16 * v;
-      if (b >= r1) continue;
-      part[static_cast<int64_t>(c) * csz + (static_cast<int64_t>(a) * nk + i) * r1 + b] = acc[u][v];
-    }
-  }
-}
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_grad_reduce(int64_t csz, int nchunk, const T* __restrict__ part,
@@ -403,22 +336,50 @@ __global__ __launch_bounds__(NT) void k_tri_fwd(int64_t P, const uint32_t* __res
   }
 }
 
+// Matrix-core tile step for the evaluation kernels: v_mfma_f64_16x16x4 (FP64) or
+// v_mfma_f32_16x16x4_f32 (FP32).  Operands: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register v of lane l holds row row(l, v), column l%16
+// (the two instructions order their accumulator rows differently).
+typedef double evd4 __attribute__((ext_vector_type(4)));
+typedef float evf4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef evd4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef evf4 acc_t;
+  static __device__ __forceinline__ acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
 // Bucketed row-times-slice product over the nodes of one trie depth grouped by their
 // last mode index: workgroup (i, chunk, tile) takes up to 64 nodes q whose index is
 // i, gathers their input rows src[parent(q)] (forward; src[q] when parent is null),
 // multiplies them by the r0 x r1 slice S_i (S_i[a][b] = G[i*sI + a*sK + b], staged
 // in LDS 32 rows at a time) and writes dst[q][b0:b0+64]: a small gather-GEMM-scatter
-// with a 4 nodes x 4 columns thread tile.  Forward: S_i = G[:, i, :].  Up pass:
-// S_i = G[:, i, :]^T, rows = the children's up vectors.
+// on the matrix cores, 4 waves each owning a 32 x 32 quarter of the tile as 2 x 2
+// MFMA blocks.  Forward: S_i = G[:, i, :].  Up pass: S_i = G[:, i, :]^T, rows = the
+// children's up vectors.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int64_t sK, int64_t sI,
-                                                       const uint64_t* __restrict__ perm,
-                                                       const int64_t* __restrict__ off,
-                                                       const uint32_t* __restrict__ parent,
-                                                       const T* __restrict__ Lprev, const T* __restrict__ G,
-                                                       T* __restrict__ Lcur) {
-  constexpr int NB = 64;  // nodes per workgroup
-  constexpr int AK = 32;  // slice rows staged per step
+__global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int64_t sK, int64_t sI,
+                                                            const uint64_t* __restrict__ perm,
+                                                            const int64_t* __restrict__ off,
+                                                            const uint32_t* __restrict__ parent,
+                                                            const T* __restrict__ Lprev, const T* __restrict__ G,
+                                                            T* __restrict__ Lcur) {
+  constexpr int NB = 64;
+  constexpr int AK = 32;
   __shared__ T Vs[AK][NB + 1];
   __shared__ T Ss[AK][64 + 1];
   __shared__ uint32_t qid[NB], pid[NB];
@@ -428,18 +389,20 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int64_t s
   if (beg >= end) return;
   const int cnt = static_cast<int>(end - beg);
   const int b0 = blockIdx.z * 64;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (threadIdx.x < NB) {
     const uint32_t q = (threadIdx.x < cnt) ? static_cast<uint32_t>(perm[beg + threadIdx.x]) : 0u;
     qid[threadIdx.x] = q;
     pid[threadIdx.x] = (threadIdx.x < cnt) ? (parent ? parent[q] : q) : 0u;
   }
   __syncthreads();
-  T acc[4][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::acc_t acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+    for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::zero();
   const T* Gi = G + static_cast<int64_t>(i) * sI;
   for (int a0 = 0; a0 < r0; a0 += AK) {
     for (int e = threadIdx.x; e < AK * NB; e += NT) {
@@ -451,32 +414,97 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket(int r0, int r1, int64_t s
       Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? Gi[(a0 + a) * sK + b0 + b] : T(0);
     }
     __syncthreads();
-    const int kk = min(AK, r0 - a0);
-    for (int a = 0; a < kk; ++a) {
-      T vv[4], sv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) vv[u] = Vs[a][ty + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sv[v] = Ss[a][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(vv[u], sv[v], acc[u][v]);
+    const int kk = ((min(AK, r0 - a0) + 3) / 4) * 4;
+    for (int k4 = 0; k4 < kk; k4 += 4) {
+      const T x0 = Vs[k4 + lk][wm + li], x1 = Vs[k4 + lk][wm + 16 + li];
+      const T y0 = Ss[k4 + lk][wn + li], y1 = Ss[k4 + lk][wn + 16 + li];
+      acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int nn = ty + 16 * u;
-    if (nn >= cnt) continue;
-    const int64_t q = qid[nn];
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int b = b0 + tx + 16 * v;
-      if (b < r1) Lcur[q * r1 + b] = acc[u][v];
-    }
-  }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int nn = wm + 16 * x + Mfma<T>::row(lane, v);
+        const int b = b0 + wn + 16 * y + li;
+        if (nn < cnt && b < r1) Lcur[static_cast<int64_t>(qid[nn]) * r1 + b] = acc[x][y][v];
+      }
 }
+
+// Partial gradient slice of one (bucket, chunk, tile): sum over the chunk's entries t
+// (all with mode index i) of Lrow_t[a] * Rrow_t[b] (Lrow scaled by grad_y when given),
+// a 64 x 64 tile of MFMA blocks contracting over the entries staged KC at a time;
+// written to part[chunk] laid out like the core, [a][i][b].
+template <typename T, int KC>
+__global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
+                                                          const int64_t* __restrict__ off, const T* __restrict__ gy,
+                                                          const T* __restrict__ L, int64_t lsum, int64_t loff,
+                                                          const T* __restrict__ R, int64_t rsum, int64_t roff,
+                                                          int64_t chunk, T* __restrict__ part,
+                                                          const uint32_t* __restrict__ lidx) {
+  __shared__ T Ls[KC][65];
+  __shared__ T Rs[KC][65];
+  const int i = blockIdx.x;
+  const int c = blockIdx.y;
+  const int tA = (r0 + 63) / 64;
+  const int a0 = (blockIdx.z % tA) * 64, b0 = (blockIdx.z / tA) * 64;
+  const int64_t beg = off[i] + static_cast<int64_t>(c) * chunk;
+  const int64_t end = min(off[i + 1], beg + chunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  typename Mfma<T>::acc_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::zero();
+  for (int64_t s0 = beg; s0 < end; s0 += KC) {
+    const int cnt = static_cast<int>(min(static_cast<int64_t>(KC), end - s0));
+    for (int e = threadIdx.x; e < KC * 64; e += NT) {
+      const int t = e / 64, j = e % 64;
+      T lv = T(0), rv = T(0);
+      if (t < cnt) {
+        const int64_t n = static_cast<int64_t>(perm[s0 + t]);
+        const int64_t nl = lidx ? static_cast<int64_t>(lidx[n]) : n;
+        const int a = a0 + j, b = b0 + j;
+        if (a < r0) lv = (loff < 0 ? T(1) : L[nl * lsum + loff + a]) * (gy ? gy[n] : T(1));
+        if (b < r1) rv = (roff < 0 ? T(1) : R[n * rsum + roff + b]);
+      }
+      Ls[t][j] = lv;
+      Rs[t][j] = rv;
+    }
+    __syncthreads();
+    const int kk = ((cnt + 3) / 4) * 4;
+    for (int k4 = 0; k4 < kk; k4 += 4) {
+      const T x0 = Ls[k4 + lk][wm + li], x1 = Ls[k4 + lk][wm + 16 + li];
+      const T y0 = Rs[k4 + lk][wn + li], y1 = Rs[k4 + lk][wn + 16 + li];
+      acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
+      acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
+      acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
+      acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + wm + 16 * x + Mfma<T>::row(lane, v);
+        const int b = b0 + wn + 16 * y + li;
+        if (a < r0 && b < r1)
+          part[static_cast<int64_t>(c) * csz + (static_cast<int64_t>(a) * nk + i) * r1 + b] = acc[x][y][v];
+      }
+}
+
 
 // Forward for narrow outputs (r1 < 16): one thread per (node, output column); the
 // node's parent vector is read from global memory, the slice column from LDS.
@@ -582,6 +610,34 @@ __global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __rest
   }
 }
 
+// Forward of a depth whose r1 is small, in trie order: one thread per (node, b),
+// L[q][b] = sum_a Lprev[parent(q)][a] G[a][coord(q)][b], the whole core staged in
+// LDS.  Siblings are adjacent in trie order, so their shared parent vector is read
+// once from memory and then from cache (bucket order would scatter them).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_fwd_trie(int64_t P, int r0, int r1, int nk,
+                                                     const uint32_t* __restrict__ parent,
+                                                     const uint32_t* __restrict__ coord, const T* __restrict__ Lprev,
+                                                     const T* __restrict__ G, T* __restrict__ Lcur) {
+  extern __shared__ unsigned char tri_smem[];
+  T* Gs = reinterpret_cast<T*>(tri_smem);
+  const int csz = r0 * nk * r1;
+  for (int e = threadIdx.x; e < csz; e += NT) Gs[e] = G[e];
+  __syncthreads();
+  const int64_t items = P * r1;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x; e < items;
+       e += static_cast<int64_t>(gridDim.x) * NT) {
+    const int64_t q = e / r1;
+    const int b = static_cast<int>(e - q * r1);
+    const T* v = Lprev + static_cast<int64_t>(parent[q]) * r0;
+    const T* g = Gs + static_cast<int64_t>(coord[q]) * r1 + b;
+    const int64_t ga = static_cast<int64_t>(nk) * r1;
+    T acc = T(0);
+    for (int a = 0; a < r0; ++a) acc = fma(v[a], g[a * ga], acc);
+    Lcur[e] = acc;
+  }
+}
+
 // Up vector of each parent as the fixed-order sum of its children's products:
 // U[q][a] = sum_{c in [cbeg[q], cbeg[q+1])} V[c][a].  One thread per (q, a).
 template <typename T>
@@ -647,6 +703,18 @@ struct Trie {
 };
 
 int lpe_for(const EvalDesc& ed) { return max_rank_of(ed) <= 32 ? 32 : 64; }
+
+// Chunking of the gradient buckets: chunks of the largest bucket, a multiple of kc
+// entries each, so that the whole launch has about 1024 workgroups (enough to fill
+// the chip) while every workgroup still reduces a long run of entries.
+void grad_chunks(int64_t maxb, int nk, int tiles, int kc, int64_t* chunk, int* nchunk) {
+  const int64_t want = std::max<int64_t>(1, (1024 + static_cast<int64_t>(nk) * tiles - 1) / (static_cast<int64_t>(nk) * tiles));
+  int64_t c = std::max<int64_t>(1, (maxb + want - 1) / want);
+  c = ((c + kc - 1) / kc) * kc;
+  *chunk = c;
+  *nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + c - 1) / c));
+  if (*nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
+}
 
 unsigned blocks_for(int64_t items, int lpe) {
   const int64_t per_block = (NT / 64) * (64 / lpe);
@@ -760,7 +828,7 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hip
 }
 
 // dst[q] = src[parent(q) or q] * S_{coord(q)} for every depth-t node q (see
-// k_tri_fwd_bucket); K x O slices with strides sK (rows) and sI (index).
+// k_tri_fwd_bucket_mfma); K x O slices with strides sK (rows) and sI (index).
 template <typename T>
 void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int64_t sI, const uint32_t* parent,
                     const T* src, const T* G, T* dst, hipStream_t s) {
@@ -774,7 +842,7 @@ void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int
     const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + 63) / 64);
     if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
     const int tiles = (O + 63) / 64;
-    k_tri_fwd_bucket<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
+    k_tri_fwd_bucket_mfma<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
         K, O, sK, sI, tr.bperm[t], tr.boff[t], parent, src, G, dst);
   }
   TTS_LAUNCH_CHECK();
@@ -796,8 +864,17 @@ void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std:
               static_cast<double>(P) * (r1 + 8) * sizeof(T) + static_cast<double>(tr.P[t - 1]) * r0 * sizeof(T) +
                   static_cast<double>(r0) * nk * r1 * sizeof(T),
               2.0 * static_cast<double>(P) * r0 * r1);
-    bucket_product<T>(tr, t, nk, r0, r1, static_cast<int64_t>(nk) * r1, r1, tr.parent[t], Lv[t - 1],
-                      static_cast<const T*>(ed.core[t - 1]), Lv[t], s);
+    const size_t core_bytes = sizeof(T) * static_cast<size_t>(r0) * nk * r1;
+    if (r1 < 16 && core_bytes <= 48 * 1024) {
+      const int64_t items = P * r1;
+      const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((items + NT - 1) / NT, 1024));
+      k_tri_fwd_trie<T><<<blocks, NT, core_bytes, s>>>(P, r0, r1, nk, tr.parent[t], tr.coord[t], Lv[t - 1],
+                                                       static_cast<const T*>(ed.core[t - 1]), Lv[t]);
+      TTS_LAUNCH_CHECK();
+    } else {
+      bucket_product<T>(tr, t, nk, r0, r1, static_cast<int64_t>(nk) * r1, r1, tr.parent[t], Lv[t - 1],
+                        static_cast<const T*>(ed.core[t - 1]), Lv[t], s);
+    }
   }
 }
 
@@ -833,7 +910,6 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
   }
   std::vector<T*> Lv;
   trie_forward<T>(ed, tr, mem, &al, Lv, s);
-  const int lpe = lpe_for(ed);
   // up vectors, bottom-up
   std::vector<T*> Uv(d + 1, nullptr);
   Uv[d] = mem.get<T>(tr.P[d]);
@@ -855,7 +931,7 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
               2.0 * static_cast<double>(Pc) * r0 * r1);
     if (r1 <= 4) {
       // short contraction: each parent walks its children directly
-      if (lpe == 32)
+      if (r0 <= 32)
         k_tri_up<T, 32><<<blocks_for(P, 32), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
       else
         k_tri_up<T, 64><<<blocks_for(P, 64), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);
@@ -876,22 +952,29 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     const int64_t Pc = tr.P[t + 1];
     const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
     const int64_t maxb = tr.bmax[t + 1];
-    const int64_t iters = std::max<int64_t>(1, (maxb + KC * 512 - 1) / (KC * 512));
-    const int64_t chunk = KC * iters;
-    const int nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + chunk - 1) / chunk));
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
+    const bool small = r0 * r1 <= NT && (r0 < 16 || r1 < 16);
+    int64_t chunk;
+    int nchunk;
+    if (small) {
+      // few lanes per output entry: many short chunks keep the loops short
+      chunk = KC * std::max<int64_t>(1, (maxb + KC * 512 - 1) / (KC * 512));
+      nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + chunk - 1) / chunk));
+    } else {
+      grad_chunks(maxb, nk, tiles, KC, &chunk, &nchunk);
+    }
     T* part = mem.get<T>(static_cast<size_t>(nchunk) * csz);
     {
       KTimer ktm("eval_grad", s,
                  static_cast<double>(Pc) * (r0 + r1 + 8) * sizeof(T) + static_cast<double>(nchunk) * csz * sizeof(T),
                  2.0 * static_cast<double>(Pc) * r0 * r1);
-      if (r0 * r1 <= NT && (r0 < 16 || r1 < 16))
+      if (small)
         k_grad_small<T><<<dim3(nk, nchunk), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], Lv[t],
                                                         t == 0 ? -1 : 0, Uv[t + 1], tr.parent[t + 1], chunk, part);
       else
-        k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1],
-                                                                     nullptr, Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1],
-                                                                     r1, 0, chunk, part, tr.parent[t + 1]);
+        k_grad_partial_mfma<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(
+            r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], nullptr, Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1], r1, 0, chunk,
+            part, tr.parent[t + 1]);
       TTS_LAUNCH_CHECK();
     }
     k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, static_cast<T*>(grads[t]));
@@ -969,16 +1052,15 @@ tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     TTS_HIP(hipStreamSynchronize(s));
     int64_t maxb = 0;
     for (int i = 0; i < nk; ++i) maxb = std::max(maxb, hoff[i + 1] - hoff[i]);
-    // chunks of the largest bucket: at most 512 per bucket, each a multiple of KC
-    const int64_t iters = std::max<int64_t>(1, (maxb + KC * 512 - 1) / (KC * 512));
-    const int64_t chunk = KC * iters;
-    const int nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + chunk - 1) / chunk));
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
+    int64_t chunk;
+    int nchunk;
+    grad_chunks(maxb, nk, tiles, KC, &chunk, &nchunk);
     T* part = mem.get<T>(static_cast<size_t>(nchunk) * csz);
     const int64_t lo = (k >= 1) ? ed.loff[k] : -1;              // l_k (k >= 1); l_0 = 1
     const int64_t ro = (k + 1 <= d - 1) ? ed.roff[k + 1] : -1;  // r_{k+1}; r_d = 1
-    k_grad_partial<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, perm, off, gy, L, ed.lsum, lo, R,
-                                                                 ed.rsum, ro, chunk, part, nullptr);
+    k_grad_partial_mfma<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, perm, off, gy, L, ed.lsum, lo, R,
+                                                                      ed.rsum, ro, chunk, part, nullptr);
     TTS_LAUNCH_CHECK();
     k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, gout);
     TTS_LAUNCH_CHECK();
