@@ -29,13 +29,17 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0  # dense
-# Kernel family that dominates one step (per the rocprofv3 kernel-trace summaries
-# under profiles/), and what bounds it.
-DOMINANT = "eval_grad"
+# Kernel families with live timers, and what bounds each.  The roofline object is
+# reported for the family that takes the most time per step (chosen live below).
 FAMILY_BOUND = {
-    "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "gemm": "mfma", "gemm_lp": "mfma", "jacobi": "alu",
+    "jacobi": "alu", "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "cholesky": "alu",
+    "trsm": "alu", "gemm": "mfma", "gemm_lp": "mfma",
     "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm",
 }
+# Per-launch HBM traffic of profiled kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes scaled by a plain copy of known size (profiles/traffic_*.txt).  A figure is
+# used only while the source file that holds the kernel is unchanged.
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def _parse():
@@ -47,7 +51,10 @@ def _parse():
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
-    p.add_argument("--roofline", default=DOMINANT, help="kernel family timed live for the roofline object")
+    p.add_argument("--roofline", default="auto",
+                   help="kernel family for the roofline object ('auto': the one with the most time per step)")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB five times (profiler calibration)")
     return p.parse_args()
 
 
@@ -87,8 +94,47 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
     return base, err
 
 
+def _traffic(family):
+    """(bytes per launch, source) from profiles/traffic_<family>.txt if still current, else None."""
+    import hashlib
+
+    path = os.path.join(PROFILES, f"traffic_{family}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    src = fields.get("source")
+    if not src or "traffic_bytes_per_launch" not in fields:
+        return None
+    with open(os.path.join(ROOT, src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
+            return None  # the kernel changed since the counters were taken
+    return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
+def calibrate_copy(mib):
+    import torch
+
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                      "copies": 5}), flush=True)
+
+
 def main():
     args = _parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is design-only.",
               file=sys.stderr)
@@ -117,7 +163,21 @@ def main():
     torch.cuda.synchronize()
     from paper_1908_02721_amd import _lib
 
-    _lib.kernel_timer_start(args.roofline)
+    family = args.roofline
+    if family == "auto":
+        # time every family over two steps and take the one with the most time
+        best = (-1.0, None)
+        for fam in FAMILY_BOUND:
+            _lib.kernel_timer_start(fam)
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            ms, n, _, _ = _lib.kernel_timer_read()
+            _lib.kernel_timer_start(None)
+            if n and ms > best[0]:
+                best = (ms, fam)
+        family = best[1]
+    _lib.kernel_timer_start(family)
     times = []
     dec_ms = []
     t_all0 = time.perf_counter()
@@ -155,7 +215,7 @@ def main():
         "step_ms_min": 1000.0 * min(times),
         "step_ms_median": 1000.0 * float(np.median(times)),
     }
-    bound = FAMILY_BOUND.get(args.roofline, "alu")
+    bound = FAMILY_BOUND.get(family, "alu")
     if k_n and k_ms > 0:
         if bound == "hbm":
             achieved = k_bytes / (k_ms / 1000.0) / 1e9
@@ -163,14 +223,16 @@ def main():
         else:
             achieved = k_flops / (k_ms / 1000.0) / 1e12
             unit = "TFLOP/s"
-            if args.roofline == "gemm_lp":
+            if family == "gemm_lp":
                 peak = BF16_PEAK_TFLOPS if args.precision == "bf16" else FP32_PEAK_TFLOPS
-            elif args.precision != "fp64" and args.roofline in ("eval_forward", "eval_up", "eval_grad"):
+            elif args.precision != "fp64" and family in ("eval_forward", "eval_up", "eval_grad"):
                 peak = FP32_PEAK_TFLOPS
             else:
                 peak = FP64_PEAK_TFLOPS
+        tr = _traffic(family) if args.precision == "fp64" else None
         out["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-                           "traffic": None, "kernel": args.roofline, "launches_per_step": k_n / args.steps,
+                           "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
+                           "kernel": family, "launches_per_step": k_n / args.steps,
                            "kernel_ms_per_step": k_ms / args.steps,
                            "algo_bytes_per_launch": k_bytes / k_n, "algo_flops_per_launch": k_flops / k_n}
     if not args.no_cpu_baseline:

@@ -189,8 +189,9 @@ const char* tt_last_error(void);
  * what the implementation happens to move) are accumulated.  tt_kernel_timer_read
  * waits for the recorded events and returns the totals; family NULL or "" stops
  * timing.  Families: "sort_scatter", "level_group", "level_canon",
- * "eval_forward", "eval_up", "eval_grad", "gemm", "jacobi".  Process-wide, not for
- * concurrent use from several threads.
+ * "eval_forward", "eval_up", "eval_grad", "gemm" (FP64), "gemm_lp" (FP32/BF16
+ * operands), "cholesky", "trsm", "jacobi" (algorithmic flops: one sweep).
+ * Process-wide, not for concurrent use from several threads.
  */
 tt_status tt_kernel_timer_start(const char* family);
 tt_status tt_kernel_timer_read(double* total_ms, int64_t* launches, double* algo_bytes, double* algo_flops);

@@ -705,10 +705,10 @@ struct Trie {
 int lpe_for(const EvalDesc& ed) { return max_rank_of(ed) <= 32 ? 32 : 64; }
 
 // Chunking of the gradient buckets: chunks of the largest bucket, a multiple of kc
-// entries each, so that the whole launch has about 1024 workgroups (enough to fill
+// entries each, so that the whole launch has about 2048 workgroups (enough to fill
 // the chip) while every workgroup still reduces a long run of entries.
 void grad_chunks(int64_t maxb, int nk, int tiles, int kc, int64_t* chunk, int* nchunk) {
-  const int64_t want = std::max<int64_t>(1, (1024 + static_cast<int64_t>(nk) * tiles - 1) / (static_cast<int64_t>(nk) * tiles));
+  const int64_t want = std::max<int64_t>(1, (2048 + static_cast<int64_t>(nk) * tiles - 1) / (static_cast<int64_t>(nk) * tiles));
   int64_t c = std::max<int64_t>(1, (maxb + want - 1) / want);
   c = ((c + kc - 1) / kc) * kc;
   *chunk = c;
@@ -946,7 +946,7 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     }
   }
   // gradients: core t pairs parents at depth t with children at depth t+1
-  constexpr int KC = sizeof(T) == 8 ? 64 : 128;
+  constexpr int KC = sizeof(T) == 8 ? 32 : 64;  // 33 KB of LDS: four workgroups per CU
   for (int t = 0; t < d; ++t) {
     const int nk = ed.n[t], r0 = ed.r[t], r1 = ed.r[t + 1];
     const int64_t Pc = tr.P[t + 1];
@@ -1029,7 +1029,7 @@ tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
   uint64_t* perm = mem.get<uint64_t>(std::max<int64_t>(m, 1));
   uint64_t* kt = mem.get<uint64_t>(std::max<int64_t>(m, 1));
   uint64_t* vt = mem.get<uint64_t>(std::max<int64_t>(m, 1));
-  constexpr int KC = sizeof(T) == 8 ? 64 : 128;
+  constexpr int KC = sizeof(T) == 8 ? 32 : 64;  // 33 KB of LDS: four workgroups per CU
   for (int k = 0; k < d; ++k) {
     const int nk = ed.n[k], r0 = ed.r[k], r1 = ed.r[k + 1];
     const int64_t csz = static_cast<int64_t>(r0) * nk * r1;

@@ -438,10 +438,12 @@ __device__ void block_argmax_1024(double v, int idx, double* redv, int* redi, do
 template <int LPJ>
 __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restrict__ G, int n, int ldg, int rmax,
                                                          double theta, double* __restrict__ L,
-                                                         int32_t* __restrict__ piv, int32_t* __restrict__ d_r) {
+                                                         int32_t* __restrict__ piv, int32_t* __restrict__ d_r,
+                                                         int tl) {
   extern __shared__ double sm[];
   double* dg = sm;               // n
   double* lp = sm + n;           // rmax (row p of L)
+  double* Lc = lp + rmax;        // the first tl columns of L, n x tl (LDS copy)
   __shared__ double redv[17];
   __shared__ int redi[17];
   double gmax = 0.0;
@@ -470,7 +472,7 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
     block_argmax_1024(v, idx, redv, redi, &pv, &p);
     if (!(pv > thr)) break;
     if (threadIdx.x == 0) piv[t] = p;
-    for (int l = threadIdx.x; l < t; l += BT) lp[l] = L[p + static_cast<size_t>(l) * n];
+    for (int l = threadIdx.x; l < t; l += BT) lp[l] = (l < tl) ? Lc[p + l * n] : L[p + static_cast<size_t>(l) * n];
     __syncthreads();
     const double sq = sqrt(pv);
     const double inv = 1.0 / sq;
@@ -480,8 +482,18 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
       // s = G[j, p] - sum_{l < t} L[j, l] L[p, l], four independent partial sums
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       if (live) {
-        const double* Lj = L + j;
+        // steps l < tl from the LDS copy, the rest from global memory
+        const int tlim = min(t, tl);
+        const double* Cj = Lc + j;
         int l = sub;
+        for (; l + 3 * LPJ < tlim; l += 4 * LPJ) {
+          s0 = fma(Cj[l * n], lp[l], s0);
+          s1 = fma(Cj[(l + LPJ) * n], lp[l + LPJ], s1);
+          s2 = fma(Cj[(l + 2 * LPJ) * n], lp[l + 2 * LPJ], s2);
+          s3 = fma(Cj[(l + 3 * LPJ) * n], lp[l + 3 * LPJ], s3);
+        }
+        for (; l < tlim; l += LPJ) s0 = fma(Cj[l * n], lp[l], s0);
+        const double* Lj = L + j;
         for (; l + 3 * LPJ < t; l += 4 * LPJ) {
           s0 = fma(Lj[static_cast<size_t>(l) * n], lp[l], s0);
           s1 = fma(Lj[static_cast<size_t>(l + LPJ) * n], lp[l + LPJ], s1);
@@ -505,6 +517,7 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
           dg[j] = dg[j] - x * x;
         }
         L[j + static_cast<size_t>(t) * n] = x;
+        if (t < tl) Lc[j + t * n] = x;
       }
     }
     __syncthreads();
@@ -521,19 +534,19 @@ __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ 
   U[t + static_cast<size_t>(s) * r] = (t <= s) ? L[piv[s] + static_cast<size_t>(t) * n] : 0.0;
 }
 
-// Cholesky of r <= R (R = 64 or 128) by one 1024-thread workgroup, upper factor.
+// Cholesky of r <= R (R = 64 or 128) by one NTH-thread workgroup, upper factor.
 // The matrix sits row-major in LDS; thread (ty, c) owns column c of rows
-// ty, ty + G, ... (G = 1024 / R).  Step j subtracts a_ji a_jc / a_jj from every
+// ty, ty + G, ... (G = NTH / R).  Step j subtracts a_ji a_jc / a_jj from every
 // (i, c) with j < i <= c, reading only row j: one barrier per step.  Row i is
 // scaled by 1 / sqrt(a_ii) when it is written out.
-template <int R>
-__global__ __launch_bounds__(1024) void k_cholesky_block(double* __restrict__ Ag, int r, int lda, double max_ratio,
-                                                         int32_t* __restrict__ ok) {
-  constexpr int GR = 1024 / R;
+template <int R, int NTH>
+__global__ __launch_bounds__(NTH) void k_cholesky_block(double* __restrict__ Ag, int r, int lda, double max_ratio,
+                                                        int32_t* __restrict__ ok) {
+  constexpr int GR = NTH / R;
   constexpr int RPT = R / GR;
   __shared__ double A[R * R];
   __shared__ int bad;
-  for (int e = threadIdx.x; e < r * r; e += 1024) {
+  for (int e = threadIdx.x; e < r * r; e += NTH) {
     const int i = e % r, c = e / r;
     A[i * R + c] = Ag[i + static_cast<size_t>(c) * lda];
   }
@@ -558,7 +571,7 @@ __global__ __launch_bounds__(1024) void k_cholesky_block(double* __restrict__ Ag
     __syncthreads();
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < r * r; e += 1024) {
+  for (int e = threadIdx.x; e < r * r; e += NTH) {
     const int i = e % r, cc = e / r;
     double x = 0.0;
     if (i == cc)
@@ -1088,6 +1101,120 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
   }
 }
 
+// Sum over the 8 lanes of an aligned lane group with DPP moves (no LDS round trip):
+// swap neighbours, swap pairs, then add the mirrored half of the 8 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double group8_sum(double x) {
+  x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_move<0x141>(x);  // row_half_mirror
+  return x;
+}
+
+// One-sided Jacobi for c <= 64 columns of at most 64 rows: k_jacobi_reg with
+// 8-lane groups, both A and V zero-padded to 64 rows in LDS so that every lane moves
+// its 8 entries of a column as four 16-byte LDS accesses with no bounds tests, and
+// the group's dot products reduced with DPP moves.
+__global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int rows, int c, int lda,
+                                                  double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+  constexpr int GW = 8, NTH = 256, LD = 64;
+  extern __shared__ double2 sm16[];  // 16-byte aligned: columns are read as double2
+  __shared__ int rotated;
+  double* A = reinterpret_cast<double*>(sm16);   // 64 x c (rows >= `rows` are zero)
+  double* V = A + static_cast<size_t>(LD) * c;   // 64 x c (rows >= c are zero)
+  for (int e = threadIdx.x; e < LD * c; e += NTH) {
+    const int i = e % LD, j = e / LD;
+    A[e] = (i < rows) ? Ag[i + static_cast<size_t>(j) * lda] : 0.0;
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const int N = c + (c & 1);
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      int p = 0, q = c;
+      if (grp < N / 2) {
+        if (grp == 0) {
+          p = rd;
+          q = N - 1;
+        } else {
+          p = (rd + grp) % (N - 1);
+          q = (rd - grp + (N - 1)) % (N - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+      }
+      if (q < c) {  // uniform within the group
+        double2* ap = reinterpret_cast<double2*>(A + static_cast<size_t>(p) * LD) + gl;
+        double2* aq = reinterpret_cast<double2*>(A + static_cast<size_t>(q) * LD) + gl;
+        double2 x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          x[u] = ap[8 * u];
+          y[u] = aq[8 * u];
+        }
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a = fma(x[u].x, x[u].x, fma(x[u].y, x[u].y, a));
+          b = fma(y[u].x, y[u].x, fma(y[u].y, y[u].y, b));
+          g = fma(x[u].x, y[u].x, fma(x[u].y, y[u].y, g));
+        }
+        a = group8_sum(a);
+        b = group8_sum(b);
+        g = group8_sum(g);
+        if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          double cs, sn;
+          jacobi_rotation(a, b, g, &cs, &sn);
+          double2* vp = reinterpret_cast<double2*>(V + static_cast<size_t>(p) * LD) + gl;
+          double2* vq = reinterpret_cast<double2*>(V + static_cast<size_t>(q) * LD) + gl;
+          double2 xv[4], yv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            xv[u] = vp[8 * u];
+            yv[u] = vq[8 * u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            ap[8 * u] = double2{cs * x[u].x - sn * y[u].x, cs * x[u].y - sn * y[u].y};
+            aq[8 * u] = double2{sn * x[u].x + cs * y[u].x, sn * x[u].y + cs * y[u].y};
+            vp[8 * u] = double2{cs * xv[u].x - sn * yv[u].x, cs * xv[u].y - sn * yv[u].y};
+            vq[8 * u] = double2{sn * xv[u].x + cs * yv[u].x, sn * xv[u].y + cs * yv[u].y};
+          }
+          if (gl == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int j = grp; j < c; j += NTH / GW) {
+    const double2* aj = reinterpret_cast<const double2*>(A + static_cast<size_t>(j) * LD) + gl;
+    double sacc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sacc = fma(aj[8 * u].x, aj[8 * u].x, fma(aj[8 * u].y, aj[8 * u].y, sacc));
+    sacc = group8_sum(sacc);
+    if (gl == 0) sigma[j] = sqrt(sacc);
+  }
+  for (int e = threadIdx.x; e < LD * c; e += NTH) {
+    const int i = e % LD, j = e / LD;
+    if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = A[e];
+    if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+  }
+}
+
 // Block-pair step of a one-sided block Jacobi sweep for wide matrices: workgroup w
 // takes the pair of column blocks given by the circle method for round `rd`,
 // stages both blocks of A (rows x 2b) and of V (c x 2b) in LDS, runs inner Jacobi
@@ -1384,18 +1511,22 @@ void gather_cols(const double* X, int rows, int ldx, const int32_t* piv, int r, 
 
 void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, double* L, int32_t* piv, int32_t* d_r,
                       hipStream_t s) {
-  const size_t shm = sizeof(double) * (static_cast<size_t>(n) + rmax);
-  if (shm > 150 * 1024) fail(TT_ERR_TOO_LARGE, "pivoted Cholesky: Gram matrix too large for one workgroup");
+  const size_t base = sizeof(double) * (static_cast<size_t>(n) + rmax);
+  const size_t cap = 150 * 1024;
+  if (base > cap) fail(TT_ERR_TOO_LARGE, "pivoted Cholesky: Gram matrix too large for one workgroup");
+  // as many leading columns of L as fit are kept in LDS
+  const int tl = static_cast<int>(std::min<size_t>(rmax, (cap - base) / (sizeof(double) * n)));
+  const size_t shm = base + sizeof(double) * static_cast<size_t>(n) * tl;
   if (n * 16 <= BT)
-    k_pivoted_cholesky<16><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+    k_pivoted_cholesky<16><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   else if (n * 8 <= BT)
-    k_pivoted_cholesky<8><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+    k_pivoted_cholesky<8><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   else if (n * 4 <= BT)
-    k_pivoted_cholesky<4><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+    k_pivoted_cholesky<4><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   else if (n * 2 <= BT)
-    k_pivoted_cholesky<2><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+    k_pivoted_cholesky<2><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   else
-    k_pivoted_cholesky<1><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+    k_pivoted_cholesky<1><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   TTS_LAUNCH_CHECK();
 }
 
@@ -1405,13 +1536,15 @@ void pivot_factor(const double* L, int n, const int32_t* piv, int r, double* U, 
 }
 
 void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, hipStream_t s) {
+  // r^3 / 3 multiply-adds; the matrix is read and written once
+  KTimer kt("cholesky", s, 16.0 * r * r, 2.0 * r * r * r / 3.0);
   if (r <= 64) {
-    k_cholesky_block<64><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    k_cholesky_block<64, 1024><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (r <= 128) {
-    k_cholesky_block<128><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    k_cholesky_block<128, 1024><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
@@ -1433,13 +1566,13 @@ void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t*
 void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
                       int32_t* d_ok, hipStream_t s, Allocator* al) {
   if (rows <= 0 || r <= 0) return;
-  if (r <= 32) {
-    k_trsm_right_upper<32><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
-    TTS_LAUNCH_CHECK();
-    return;
-  }
+  // rows * r^2 / 2 multiply-adds; Y read, X written, U read once
+  KTimer kt("trsm", s, 8.0 * (2.0 * rows * r + static_cast<double>(r) * r), static_cast<double>(rows) * r * r);
   if (r <= 64) {
-    k_trsm_right_upper<64><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
+    if (r <= 32)
+      k_trsm_right_upper<32><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
+    else
+      k_trsm_right_upper<64><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
@@ -1490,10 +1623,13 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
             // one sweep of rotations: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V)
             0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
+  if (c <= 64 && rows <= 64) {
+    k_jacobi64<<<1, 256, sizeof(double) * 128 * static_cast<size_t>(c), s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   if (shm_odd <= 150 * 1024 && c <= 64 && rows <= 256) {
-    if (rows <= 64)
-      k_jacobi_reg<8, 8><<<1, 256, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
-    else if (rows <= 128)
+    if (rows <= 128)
       k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
     else
       k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
