@@ -211,7 +211,10 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
   {
     DBuf<uint64_t> kt(al, nnz), vt(al, nnz);
     const int sort_bits = total_bits + (kept < nnz ? 1 : 0);
-    radix_sort_pairs(al, keys.get(), vals.get(), kt.get(), vt.get(), nnz, sort_bits, s);
+    if (radix_sort_pairs_pp(al, keys.get(), vals.get(), kt.get(), vt.get(), nnz, sort_bits, s)) {
+      keys.swap(kt);
+      vals.swap(vt);
+    }
   }
   TTS_HIP(hipEventRecord(ev.e[2], s));
 
@@ -251,7 +254,10 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
       if (rbits + cbits > 64) fail(TT_ERR_TOO_LARGE, "composite (column, row) key exceeds 64 bits");
       DBuf<uint64_t> ck(al, nE), cv(al, nE), ckt(al, nE), cvt(al, nE);
       launch_make_composite(flag.get(), pos.get(), erho.get(), nE, rbits, ck.get(), cv.get(), s);
-      radix_sort_pairs(al, ck.get(), cv.get(), ckt.get(), cvt.get(), nE, rbits + cbits, s);
+      if (radix_sort_pairs_pp(al, ck.get(), cv.get(), ckt.get(), cvt.get(), nE, rbits + cbits, s)) {
+        ck.swap(ckt);
+        cv.swap(cvt);
+      }
       DBuf<uint64_t> ek2(al, nE);
       DBuf<uint32_t> er2(al, nE);
       DBuf<double> ev2(al, nE);
@@ -305,7 +311,10 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, lkey.get(), lslot.get(), s);
     {
       DBuf<uint64_t> kt(al, beta), vt(al, beta);
-      radix_sort_pairs(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s);
+      if (radix_sort_pairs_pp(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s)) {
+        lkey.swap(kt);
+        lslot.swap(vt);
+      }
     }
     DBuf<uint32_t> slot_gid(al, tsize), nlen(al, beta), npos(al, beta);
     launch_group_ids(lslot.get(), beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);

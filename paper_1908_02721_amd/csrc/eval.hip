@@ -760,7 +760,10 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
   TTS_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
   TTS_HIP(hipStreamSynchronize(s));
   if (herr) return false;
-  radix_sort_pairs(al, key, val, kt, vt, static_cast<uint32_t>(m), total, s);
+  if (radix_sort_pairs_pp(al, key, val, kt, vt, static_cast<uint32_t>(m), total, s)) {
+    std::swap(key, kt);
+    std::swap(val, vt);
+  }
   tr.perm = val;
   uint32_t* flag = mem.get<uint32_t>(m);
   uint32_t* pos = mem.get<uint32_t>(m);
@@ -815,7 +818,11 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hip
     TTS_LAUNCH_CHECK();
     int bits = 0;
     while (bits < 31 && (static_cast<int64_t>(nk) - 1) >> bits) ++bits;
-    radix_sort_pairs(al, key, tr.bperm[t], kt, vt, static_cast<uint32_t>(P), bits, s);
+    if (radix_sort_pairs_pp(al, key, tr.bperm[t], kt, vt, static_cast<uint32_t>(P), bits, s)) {
+      std::swap(key, kt);
+      tr.bperm[t] = vt;                  // the sorted permutation stays with depth t
+      vt = mem.get<uint64_t>(pmax);      // fresh scratch for the next depth
+    }
     tr.boff[t] = mem.get<int64_t>(nk + 1);
     k_bucket_offsets<<<grid_for(nk + 1, NT), NT, 0, s>>>(key, P, nk, tr.boff[t]);
     TTS_LAUNCH_CHECK();
@@ -1043,7 +1050,10 @@ tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     TTS_LAUNCH_CHECK();
     int bits = 0;
     while (bits < 31 && (static_cast<int64_t>(nk) - 1) >> bits) ++bits;
-    radix_sort_pairs(&al, key, perm, kt, vt, static_cast<uint32_t>(m), bits, s);
+    if (radix_sort_pairs_pp(&al, key, perm, kt, vt, static_cast<uint32_t>(m), bits, s)) {
+      std::swap(key, kt);
+      std::swap(perm, vt);
+    }
     int64_t* off = mem.get<int64_t>(nk + 1);
     k_bucket_offsets<<<grid_for(nk + 1, NT), NT, 0, s>>>(key, m, nk, off);
     TTS_LAUNCH_CHECK();

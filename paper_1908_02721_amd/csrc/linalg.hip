@@ -1484,7 +1484,10 @@ void right_weights(Allocator* al, const int64_t* colptr, const int32_t* row, con
   TTS_LAUNCH_CHECK();
   int bits = 0;
   while (bits < 63 && (static_cast<uint64_t>(ngroups) * nk - 1) >> bits) ++bits;
-  radix_sort_pairs(al, key.get(), ent.get(), kt.get(), vt.get(), nnz, bits, s);
+  if (radix_sort_pairs_pp(al, key.get(), ent.get(), kt.get(), vt.get(), nnz, bits, s)) {
+    key.swap(kt);
+    ent.swap(vt);
+  }
   k_group_weights<<<grid_for(ngroups, NT), NT, 0, s>>>(key.get(), ent.get(), nnz, nk, ngroups, val, ecol.get(), wnext,
                                                        w);
   TTS_LAUNCH_CHECK();

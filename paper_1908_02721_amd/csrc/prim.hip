@@ -200,12 +200,43 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict
   }
 }
 
+// Exclusive scan of up to SMALL_SCAN elements in one launch: the input is staged in
+// LDS with coalesced loads, each of the 1024 threads scans a contiguous run, and the
+// runs are combined with a workgroup scan.
+constexpr uint32_t SMALL_SCAN = 16384;
+__global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                      uint32_t* __restrict__ d_total) {
+  __shared__ uint32_t buf[SMALL_SCAN];
+  __shared__ uint32_t lds[1024 / 64];
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) buf[i] = in[i];
+  __syncthreads();
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t b = min(n, threadIdx.x * per), e = min(n, b + per);
+  uint32_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += buf[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan_u32<1024>(sum, lds, &tot);
+  for (uint32_t i = b; i < e; ++i) {
+    const uint32_t v = buf[i];
+    buf[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) out[i] = buf[i];
+  if (threadIdx.x == 0 && d_total) *d_total = tot;
+}
+
 }  // namespace
 
 void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
                         hipStream_t s) {
   if (n == 0) {
     if (d_total) TTS_HIP(hipMemsetAsync(d_total, 0, sizeof(uint32_t), s));
+    return;
+  }
+  if (n <= SMALL_SCAN) {
+    k_scan_single<<<1, 1024, 0, s>>>(in, out, n, d_total);
+    TTS_LAUNCH_CHECK();
     return;
   }
   const uint32_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -218,9 +249,9 @@ void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32
   TTS_LAUNCH_CHECK();
 }
 
-void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
-                      uint32_t n, int nbits, hipStream_t s) {
-  if (n <= 1 || nbits <= 0) return;
+bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
+                         uint32_t n, int nbits, hipStream_t s) {
+  if (n <= 1 || nbits <= 0) return false;
   const uint32_t ntiles = (n + RS_TILE - 1) / RS_TILE;
   const int passes = (nbits + 7) / 8;
   DBuf<uint32_t> counts(al, static_cast<size_t>(256) * ntiles);
@@ -239,9 +270,14 @@ void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* k
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
-  if (ki != keys) {
-    TTS_HIP(hipMemcpyAsync(keys, ki, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-    TTS_HIP(hipMemcpyAsync(vals, vi, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  return ki != keys;
+}
+
+void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
+                      uint32_t n, int nbits, hipStream_t s) {
+  if (radix_sort_pairs_pp(al, keys, vals, ktmp, vtmp, n, nbits, s)) {
+    TTS_HIP(hipMemcpyAsync(keys, ktmp, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    TTS_HIP(hipMemcpyAsync(vals, vtmp, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
   }
 }
 

@@ -15,5 +15,9 @@ void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32
 // Keys with bits above nbits must be equal (or zero) for a full order.
 void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp,
                       uint64_t* vtmp, uint32_t n, int nbits, hipStream_t s);
+// The same sort without the final copy: returns true when the sorted pairs are in
+// (ktmp, vtmp) (an odd number of passes), false when they are in (keys, vals).
+bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp,
+                         uint64_t* vtmp, uint32_t n, int nbits, hipStream_t s);
 
 }  // namespace tts
