@@ -123,12 +123,16 @@ __global__ __launch_bounds__(NT) void k_bucket_keys(const int32_t* __restrict__ 
   val[n] = static_cast<uint64_t>(n);
 }
 
-__global__ __launch_bounds__(NT) void k_bucket_keys_u32(const uint32_t* __restrict__ coord, int64_t m,
+// Bucket keys of the depth-t trie nodes: key = mode index, value = node index in the
+// low 32 bits and its parent's index in the high 32 bits (so that consumers reach
+// the parent vector with one load fewer).
+__global__ __launch_bounds__(NT) void k_bucket_keys_u32(const uint32_t* __restrict__ coord,
+                                                        const uint32_t* __restrict__ parent, int64_t m,
                                                         uint64_t* __restrict__ key, uint64_t* __restrict__ val) {
   const int64_t n = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   if (n >= m) return;
   key[n] = static_cast<uint64_t>(coord[n]);
-  val[n] = static_cast<uint64_t>(n);
+  val[n] = (static_cast<uint64_t>(parent[n]) << 32) | static_cast<uint64_t>(n);
 }
 
 __global__ __launch_bounds__(NT) void k_bucket_offsets(const uint64_t* __restrict__ skey, int64_t m, int nk,
@@ -308,34 +312,6 @@ __global__ __launch_bounds__(NT) void k_tri_child_ranges(const uint32_t* __restr
   if (c == 0 || parent[c] != parent[c - 1]) cbeg[parent[c]] = static_cast<uint32_t>(c);
 }
 
-template <typename T, int LPE>
-__global__ __launch_bounds__(NT) void k_tri_fwd(int64_t P, const uint32_t* __restrict__ parent,
-                                                const uint32_t* __restrict__ coord, const T* __restrict__ Lprev,
-                                                int r0, int r1, const T* __restrict__ G, int nk,
-                                                T* __restrict__ Lcur) {
-  constexpr int EPW = 64 / LPE;
-  __shared__ T buf[NT / 64][EPW][RMAX];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int sub = lane / LPE, l = lane % LPE;
-  T* v = buf[wv][sub];
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * (NT / 64) * EPW;
-  const int64_t rs = static_cast<int64_t>(nk) * r1;
-  for (int64_t q = (static_cast<int64_t>(blockIdx.x) * (NT / 64) + wv) * EPW + sub; q < P + (EPW - 1); q += stride) {
-    const bool live = q < P;
-    const int64_t pq = live ? parent[q] : 0;
-    const int64_t i = live ? coord[q] : 0;
-    for (int a = l; a < r0; a += LPE) v[a] = live ? Lprev[pq * r0 + a] : T(0);
-    __builtin_amdgcn_wave_barrier();
-    const T* base = G + i * r1;
-    for (int j = l; j < r1; j += LPE) {
-      T acc = T(0);
-      for (int a = 0; a < r0; ++a) acc = fma(v[a], base[a * rs + j], acc);
-      if (live) Lcur[q * r1 + j] = acc;
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
 // Matrix-core tile step for the evaluation kernels: v_mfma_f64_16x16x4 (FP64) or
 // v_mfma_f32_16x16x4_f32 (FP32).  Operands: lane l holds A[l%16][l/16] and
 // B[l/16][l%16]; accumulator register v of lane l holds row row(l, v), column l%16
@@ -390,9 +366,10 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
   const int cnt = static_cast<int>(end - beg);
   const int b0 = blockIdx.z * 64;
   if (threadIdx.x < NB) {
-    const uint32_t q = (threadIdx.x < cnt) ? static_cast<uint32_t>(perm[beg + threadIdx.x]) : 0u;
+    const uint64_t pv = (threadIdx.x < cnt) ? perm[beg + threadIdx.x] : 0ull;
+    const uint32_t q = static_cast<uint32_t>(pv);
     qid[threadIdx.x] = q;
-    pid[threadIdx.x] = (threadIdx.x < cnt) ? (parent ? parent[q] : q) : 0u;
+    pid[threadIdx.x] = parent ? static_cast<uint32_t>(pv >> 32) : q;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -470,8 +447,9 @@ __global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk
       const int t = e / 64, j = e % 64;
       T lv = T(0), rv = T(0);
       if (t < cnt) {
-        const int64_t n = static_cast<int64_t>(perm[s0 + t]);
-        const int64_t nl = lidx ? static_cast<int64_t>(lidx[n]) : n;
+        const uint64_t pv = perm[s0 + t];
+        const int64_t n = static_cast<int64_t>(static_cast<uint32_t>(pv));
+        const int64_t nl = lidx ? static_cast<int64_t>(pv >> 32) : n;
         const int a = a0 + j, b = b0 + j;
         if (a < r0) lv = (loff < 0 ? T(1) : L[nl * lsum + loff + a]) * (gy ? gy[n] : T(1));
         if (b < r1) rv = (roff < 0 ? T(1) : R[n * rsum + roff + b]);
@@ -530,8 +508,9 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_narrow(int r0, int r1, int64_t s
   const int b = threadIdx.x % r1, nn = threadIdx.x / r1;
   if (nn >= per) return;
   for (int64_t t = beg + nn; t < end; t += per) {
-    const int64_t q = static_cast<int64_t>(perm[t]);
-    const T* v = Lprev + (parent ? static_cast<int64_t>(parent[q]) : q) * r0;
+    const uint64_t pv = perm[t];
+    const int64_t q = static_cast<int64_t>(static_cast<uint32_t>(pv));
+    const T* v = Lprev + (parent ? static_cast<int64_t>(pv >> 32) : q) * r0;
     T acc = T(0);
     for (int a = 0; a < r0; ++a) acc = fma(v[a], Ss[a * r1 + b], acc);
     Lcur[q * r1 + b] = acc;
@@ -559,8 +538,9 @@ __global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, int nk, const
   T acc = T(0);
   if (l < lanes) {
     for (int64_t t = beg + l; t < end; t += lanes) {
-      const int64_t n = static_cast<int64_t>(perm[t]);
-      const T lv = (loff < 0) ? T(1) : L[static_cast<int64_t>(lidx[n]) * r0 + a];
+      const uint64_t pv = perm[t];
+      const int64_t n = static_cast<int64_t>(static_cast<uint32_t>(pv));
+      const T lv = (loff < 0) ? T(1) : L[static_cast<int64_t>(pv >> 32) * r0 + a];
       acc = fma(lv, R[n * r1 + b], acc);
     }
   }
@@ -814,7 +794,7 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hip
     const int nk = ed.n[t - 1];
     const int64_t P = tr.P[t];
     tr.bperm[t] = mem.get<uint64_t>(P);
-    k_bucket_keys_u32<<<grid_for(P, NT), NT, 0, s>>>(tr.coord[t], P, key, tr.bperm[t]);
+    k_bucket_keys_u32<<<grid_for(P, NT), NT, 0, s>>>(tr.coord[t], tr.parent[t], P, key, tr.bperm[t]);
     TTS_LAUNCH_CHECK();
     int bits = 0;
     while (bits < 31 && (static_cast<int64_t>(nk) - 1) >> bits) ++bits;
