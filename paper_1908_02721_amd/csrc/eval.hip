@@ -156,9 +156,17 @@ __global__ __launch_bounds__(NT) void k_grad_reduce(int64_t csz, int nchunk, con
                                                     T* __restrict__ out) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
   if (e >= csz) return;
-  T s = T(0);
-  for (int c = 0; c < nchunk; ++c) s += part[static_cast<int64_t>(c) * csz + e];
-  out[e] = s;
+  // four interleaved partial sums (a fixed order) keep four loads in flight
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+  int c = 0;
+  for (; c + 3 < nchunk; c += 4) {
+    s0 += part[static_cast<int64_t>(c) * csz + e];
+    s1 += part[static_cast<int64_t>(c + 1) * csz + e];
+    s2 += part[static_cast<int64_t>(c + 2) * csz + e];
+    s3 += part[static_cast<int64_t>(c + 3) * csz + e];
+  }
+  for (; c < nchunk; ++c) s0 += part[static_cast<int64_t>(c) * csz + e];
+  out[e] = (s0 + s1) + (s2 + s3);
 }
 
 template <typename T>
@@ -380,25 +388,57 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::zero();
+  // 16 x 16 blocks that lie wholly outside the nodes or the columns are skipped
+  // (uniform per wave): skinny slices (r1 <= 32) and short last chunks
+  const bool act0 = wm < cnt, act1 = wm + 16 < cnt;
+  const bool actc0 = b0 + wn < r1, actc1 = b0 + wn + 16 < r1;
   const T* Gi = G + static_cast<int64_t>(i) * sI;
-  for (int a0 = 0; a0 < r0; a0 += AK) {
-    for (int e = threadIdx.x; e < AK * NB; e += NT) {
+  // staging: all loads of a K-stage in flight together (clamped addresses, masked
+  // afterwards); the next stage's loads are issued before this stage's MFMA
+  constexpr int PV = AK * NB / NT, PS = AK * 64 / NT;
+  T vv[PV], sv[PS];
+  auto load_stage = [&](int a0) {
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
       const int a = e % AK, nn = e / AK;
-      Vs[a][nn] = (nn < cnt && a0 + a < r0) ? Lprev[static_cast<int64_t>(pid[nn]) * r0 + a0 + a] : T(0);
+      const bool ok = nn < cnt && a0 + a < r0;
+      vv[u] = Lprev[ok ? static_cast<int64_t>(pid[nn]) * r0 + a0 + a : 0];
     }
-    for (int e = threadIdx.x; e < AK * 64; e += NT) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + u * NT;
       const int b = e % 64, a = e / 64;
-      Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? Gi[(a0 + a) * sK + b0 + b] : T(0);
+      const bool ok = a0 + a < r0 && b0 + b < r1;
+      sv[u] = Gi[ok ? (a0 + a) * sK + b0 + b : 0];
+    }
+  };
+  load_stage(0);
+  for (int a0 = 0; a0 < r0; a0 += AK) {
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
+      const int a = e % AK, nn = e / AK;
+      Vs[a][nn] = (nn < cnt && a0 + a < r0) ? vv[u] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + u * NT;
+      const int b = e % 64, a = e / 64;
+      Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? sv[u] : T(0);
     }
     __syncthreads();
+    if (a0 + AK < r0) load_stage(a0 + AK);
     const int kk = ((min(AK, r0 - a0) + 3) / 4) * 4;
-    for (int k4 = 0; k4 < kk; k4 += 4) {
-      const T x0 = Vs[k4 + lk][wm + li], x1 = Vs[k4 + lk][wm + 16 + li];
-      const T y0 = Ss[k4 + lk][wn + li], y1 = Ss[k4 + lk][wn + 16 + li];
-      acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
-      acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
-      acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
-      acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
+    if (act0 && actc0) {
+      for (int k4 = 0; k4 < kk; k4 += 4) {
+        const T x0 = Vs[k4 + lk][wm + li], x1 = Vs[k4 + lk][wm + 16 + li];
+        const T y0 = Ss[k4 + lk][wn + li], y1 = Ss[k4 + lk][wn + 16 + li];
+        acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
+        if (actc1) acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
+        if (act1) acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
+        if (act1 && actc1) acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
+      }
     }
     __syncthreads();
   }
@@ -436,36 +476,70 @@ __global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  // 16 x 16 blocks wholly outside r0 x r1 are skipped (uniform per wave)
+  const bool act0 = a0 + wm < r0, act1 = a0 + wm + 16 < r0;
+  const bool actc0 = b0 + wn < r1, actc1 = b0 + wn + 16 < r1;
   typename Mfma<T>::acc_t acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<T>::zero();
+  // staging: thread (tb, j) loads column j of entries tb, tb + 4, ...; all index loads
+  // of a stage are issued before its data loads (clamped addresses, masked
+  // afterwards, no branches between them), so a stage costs two memory round trips
+  // rather than two per entry
+  constexpr int PER = KC * 64 / NT;
+  const int j = threadIdx.x & 63, tb = threadIdx.x >> 6;
+  const int a = a0 + j, b = b0 + j;
   for (int64_t s0 = beg; s0 < end; s0 += KC) {
     const int cnt = static_cast<int>(min(static_cast<int64_t>(KC), end - s0));
-    for (int e = threadIdx.x; e < KC * 64; e += NT) {
-      const int t = e / 64, j = e % 64;
-      T lv = T(0), rv = T(0);
-      if (t < cnt) {
-        const uint64_t pv = perm[s0 + t];
-        const int64_t n = static_cast<int64_t>(static_cast<uint32_t>(pv));
-        const int64_t nl = lidx ? static_cast<int64_t>(pv >> 32) : n;
-        const int a = a0 + j, b = b0 + j;
-        if (a < r0) lv = (loff < 0 ? T(1) : L[nl * lsum + loff + a]) * (gy ? gy[n] : T(1));
-        if (b < r1) rv = (roff < 0 ? T(1) : R[n * rsum + roff + b]);
+    uint64_t pv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int t = tb + 4 * u;
+      pv[u] = (t < cnt) ? perm[s0 + t] : 0ull;
+    }
+    T lv[PER], rv[PER];
+    if (loff >= 0) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int64_t nl =
+            lidx ? static_cast<int64_t>(pv[u] >> 32) : static_cast<int64_t>(static_cast<uint32_t>(pv[u]));
+        lv[u] = L[(a < r0) ? nl * lsum + loff + a : 0];
       }
-      Ls[t][j] = lv;
-      Rs[t][j] = rv;
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) lv[u] = T(1);
+    }
+    if (roff >= 0) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        rv[u] = R[(b < r1) ? static_cast<int64_t>(static_cast<uint32_t>(pv[u])) * rsum + roff + b : 0];
+    } else {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) rv[u] = T(1);
+    }
+    if (gy) {
+#pragma unroll
+      for (int u = 0; u < PER; ++u) lv[u] *= gy[static_cast<uint32_t>(pv[u])];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const bool live = tb + 4 * u < cnt;
+      Ls[tb + 4 * u][j] = (live && a < r0) ? lv[u] : T(0);
+      Rs[tb + 4 * u][j] = (live && b < r1) ? rv[u] : T(0);
     }
     __syncthreads();
     const int kk = ((cnt + 3) / 4) * 4;
-    for (int k4 = 0; k4 < kk; k4 += 4) {
-      const T x0 = Ls[k4 + lk][wm + li], x1 = Ls[k4 + lk][wm + 16 + li];
-      const T y0 = Rs[k4 + lk][wn + li], y1 = Rs[k4 + lk][wn + 16 + li];
-      acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
-      acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
-      acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
-      acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
+    if (act0 && actc0) {
+      for (int k4 = 0; k4 < kk; k4 += 4) {
+        const T x0 = Ls[k4 + lk][wm + li], x1 = Ls[k4 + lk][wm + 16 + li];
+        const T y0 = Rs[k4 + lk][wn + li], y1 = Rs[k4 + lk][wn + 16 + li];
+        acc[0][0] = Mfma<T>::mma(x0, y0, acc[0][0]);
+        if (actc1) acc[0][1] = Mfma<T>::mma(x0, y1, acc[0][1]);
+        if (act1) acc[1][0] = Mfma<T>::mma(x1, y0, acc[1][0]);
+        if (act1 && actc1) acc[1][1] = Mfma<T>::mma(x1, y1, acc[1][1]);
+      }
     }
     __syncthreads();
   }
@@ -537,7 +611,22 @@ __global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, int nk, const
   const int64_t end = min(off[i + 1], beg + chunk);
   T acc = T(0);
   if (l < lanes) {
-    for (int64_t t = beg + l; t < end; t += lanes) {
+    // four entries per iteration so that their loads overlap
+    int64_t t = beg + l;
+    for (; t + 3 * lanes < end; t += 4 * lanes) {
+      uint64_t pv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pv[u] = perm[t + u * lanes];
+      T lv[4], rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        lv[u] = (loff < 0) ? T(1) : L[static_cast<int64_t>(pv[u] >> 32) * r0 + a];
+        rv[u] = R[static_cast<int64_t>(static_cast<uint32_t>(pv[u])) * r1 + b];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = fma(lv[u], rv[u], acc);
+    }
+    for (; t < end; t += lanes) {
       const uint64_t pv = perm[t];
       const int64_t n = static_cast<int64_t>(static_cast<uint32_t>(pv));
       const T lv = (loff < 0) ? T(1) : L[static_cast<int64_t>(pv >> 32) * r0 + a];
@@ -569,15 +658,30 @@ __global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __rest
     T acc[RMAX / LPE];
 #pragma unroll
     for (int s2 = 0; s2 < RMAX / LPE; ++s2) acc[s2] = T(0);
-    for (int64_t c = c0; c < c1; ++c) {
-      const T* u = Unext + c * r1;
-      const T* base = GT + static_cast<int64_t>(ccoord[c]) * r1 * r0;
+    // children four at a time: their indices and up vectors (r1 <= 4) are loaded
+    // together, then the slice entries; clamped addresses, masked contributions
+    for (int64_t c = c0; c < c1; c += 4) {
+      uint32_t co[4];
+      T uv[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t cc = (c + u < c1) ? c + u : c;
+        co[u] = ccoord[cc];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) uv[u][b] = (b < r1 && c + u < c1) ? Unext[cc * r1 + b] : T(0);
+      }
 #pragma unroll
       for (int s2 = 0; s2 < RMAX / LPE; ++s2) {
         const int a = l + s2 * LPE;
         if (a < r0) {
           T x = acc[s2];
-          for (int b = 0; b < r1; ++b) x = fma(base[b * r0 + a], u[b], x);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const T* base = GT + static_cast<int64_t>(co[u]) * r1 * r0 + a;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (b < r1) x = fma(base[b * r0], uv[u][b], x);
+          }
           acc[s2] = x;
         }
       }
@@ -613,6 +717,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_trie(int64_t P, int r0, int r1, 
     const T* g = Gs + static_cast<int64_t>(coord[q]) * r1 + b;
     const int64_t ga = static_cast<int64_t>(nk) * r1;
     T acc = T(0);
+#pragma unroll 8
     for (int a = 0; a < r0; ++a) acc = fma(v[a], g[a * ga], acc);
     Lcur[e] = acc;
   }
@@ -627,8 +732,17 @@ __global__ __launch_bounds__(NT) void k_tri_segsum(int64_t P, int r0, const uint
   if (e >= P * r0) return;
   const int64_t q = e / r0;
   const int a = static_cast<int>(e - q * r0);
+  const int64_t c0 = cbeg[q], c1 = cbeg[q + 1];
   T acc = T(0);
-  for (int64_t c = cbeg[q]; c < cbeg[q + 1]; ++c) acc += V[c * r0 + a];
+  int64_t c = c0;
+  for (; c + 3 < c1; c += 4) {  // four loads in flight, summed in child order
+    const T v0 = V[c * r0 + a], v1 = V[(c + 1) * r0 + a], v2 = V[(c + 2) * r0 + a], v3 = V[(c + 3) * r0 + a];
+    acc += v0;
+    acc += v1;
+    acc += v2;
+    acc += v3;
+  }
+  for (; c < c1; ++c) acc += V[c * r0 + a];
   U[e] = acc;
 }
 

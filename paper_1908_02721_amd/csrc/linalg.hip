@@ -252,8 +252,17 @@ __global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const 
   const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
   const size_t mn = static_cast<size_t>(m) * n;
   if (e >= mn) return;
-  double s = 0.0;
-  for (int z = 0; z < ns; ++z) s += part[static_cast<size_t>(z) * mn + e];
+  // four interleaved partial sums (a fixed order) keep four loads in flight
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int z = 0;
+  for (; z + 3 < ns; z += 4) {
+    s0 += part[static_cast<size_t>(z) * mn + e];
+    s1 += part[static_cast<size_t>(z + 1) * mn + e];
+    s2 += part[static_cast<size_t>(z + 2) * mn + e];
+    s3 += part[static_cast<size_t>(z + 3) * mn + e];
+  }
+  for (; z < ns; ++z) s0 += part[static_cast<size_t>(z) * mn + e];
+  const double s = (s0 + s1) + (s2 + s3);
   const int i = static_cast<int>(e % m), j = static_cast<int>(e / m);
   double* cp = &C[i + static_cast<size_t>(j) * ldc];
   *cp = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * (*cp));
