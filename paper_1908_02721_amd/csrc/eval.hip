@@ -846,14 +846,14 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
   uint64_t* val = mem.get<uint64_t>(m);
   uint64_t* kt = mem.get<uint64_t>(m);
   uint64_t* vt = mem.get<uint64_t>(m);
-  uint32_t* err = mem.get<uint32_t>(1);
-  TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
-  k_tri_keys<<<grid_for(m, NT), NT, 0, s>>>(idx, m, g, key, val, err);
+  // counts[0]: index error flag; counts[t]: nodes at depth t (read back once, at the end)
+  uint32_t* counts = mem.get<uint32_t>(d + 1);
+  TTS_HIP(hipMemsetAsync(counts, 0, sizeof(uint32_t) * (d + 1), s));
+  k_tri_keys<<<grid_for(m, NT), NT, 0, s>>>(idx, m, g, key, val, counts);
   TTS_LAUNCH_CHECK();
-  uint32_t herr = 0;
-  TTS_HIP(hipMemcpyAsync(&herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
-  if (herr) return false;
+  // The keys of out-of-range coordinates are garbage, but nothing below reads a core:
+  // the build only touches arrays of length m, and the error is checked before any
+  // use of the trie.
   if (radix_sort_pairs_pp(al, key, val, kt, vt, static_cast<uint32_t>(m), total, s)) {
     std::swap(key, kt);
     std::swap(val, vt);
@@ -863,25 +863,21 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
   uint32_t* pos = mem.get<uint32_t>(m);
   uint32_t* ida = mem.get<uint32_t>(m);
   uint32_t* idb = mem.get<uint32_t>(m);
-  uint32_t* cnt = mem.get<uint32_t>(1);
   tr.P.assign(d + 1, 1);
   tr.parent.assign(d + 1, nullptr);
   tr.coord.assign(d + 1, nullptr);
   uint32_t* prev = nullptr;
   for (int t = 1; t <= d; ++t) {
-    // prefix (i_0..i_{t-1}) = key >> off[t-1]; mode t-1's field sits at off[t-1]
+    // prefix (i_0..i_{t-1}) = key >> off[t-1]; mode t-1's field sits at off[t-1].
+    // Node arrays are sized by m (an upper bound), so no count is read back here.
     const int psh = static_cast<int>(g.off[t - 1]);
     k_tri_flags<<<grid_for(m, NT), NT, 0, s>>>(key, m, psh, flag);
     TTS_LAUNCH_CHECK();
-    exclusive_scan_u32(al, flag, pos, static_cast<uint32_t>(m), cnt, s);
-    uint32_t pt = 0;
-    TTS_HIP(hipMemcpyAsync(&pt, cnt, sizeof(pt), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
-    tr.P[t] = pt;
-    tr.parent[t] = mem.get<uint32_t>(pt);
-    tr.coord[t] = mem.get<uint32_t>(pt);
+    exclusive_scan_u32(al, flag, pos, static_cast<uint32_t>(m), counts + t, s);
+    tr.parent[t] = mem.get<uint32_t>(m);
+    tr.coord[t] = mem.get<uint32_t>(m);
     uint32_t* st = nullptr;
-    if (t == d) st = tr.start = mem.get<uint32_t>(pt);
+    if (t == d) st = tr.start = mem.get<uint32_t>(m);
     uint32_t* cur = (t & 1) ? ida : idb;
     const uint64_t cmask = g.bits[t - 1] >= 64 ? ~0ull : ((1ull << g.bits[t - 1]) - 1ull);
     k_tri_nodes<<<grid_for(m, NT), NT, 0, s>>>(key, flag, pos, m, prev, psh, cmask, cur, tr.parent[t], tr.coord[t],
@@ -889,6 +885,11 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
     TTS_LAUNCH_CHECK();
     prev = cur;
   }
+  std::vector<uint32_t> hc(d + 1);
+  TTS_HIP(hipMemcpyAsync(hc.data(), counts, sizeof(uint32_t) * (d + 1), hipMemcpyDeviceToHost, s));
+  TTS_HIP(hipStreamSynchronize(s));
+  if (hc[0]) return false;
+  for (int t = 1; t <= d; ++t) tr.P[t] = hc[t];
   tr.leaf = prev;
   return true;
 }

@@ -226,6 +226,46 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* in, uint32
   if (threadIdx.x == 0 && d_total) *d_total = tot;
 }
 
+// Stable sort of up to SMALL_SORT pairs by key bits [0, nbits) in one workgroup:
+// each element's output position is the number of elements with a smaller masked
+// key, or an equal one at a lower index.  A thread ranks its EPT elements in one
+// pass over the keys (staged in LDS, read as broadcasts).
+constexpr uint32_t SMALL_SORT = 2048;
+__global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* __restrict__ keys,
+                                                     const uint64_t* __restrict__ vals, uint32_t n, int nbits,
+                                                     uint64_t* __restrict__ kout, uint64_t* __restrict__ vout) {
+  constexpr int EPT = SMALL_SORT / 1024;
+  __shared__ uint64_t ks[SMALL_SORT];
+  const uint64_t mask = (nbits >= 64) ? ~0ull : ((1ull << nbits) - 1ull);
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) ks[i] = keys[i] & mask;
+  __syncthreads();
+  uint64_t km[EPT];
+  uint32_t rank[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t i = threadIdx.x + e * 1024;
+    km[e] = (i < n) ? ks[i] : ~0ull;
+    rank[e] = 0;
+  }
+#pragma unroll 8
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint64_t kj = ks[j];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t i = threadIdx.x + e * 1024;
+      rank[e] += (kj < km[e] || (kj == km[e] && j < i)) ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t i = threadIdx.x + e * 1024;
+    if (i < n) {
+      kout[rank[e]] = keys[i];
+      vout[rank[e]] = vals[i];
+    }
+  }
+}
+
 }  // namespace
 
 void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* d_total,
@@ -252,6 +292,12 @@ void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32
 bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
                          uint32_t n, int nbits, hipStream_t s) {
   if (n <= 1 || nbits <= 0) return false;
+  // one rank-sort launch costs about n / 60 us, a radix pass about 12 us at these sizes
+  if (n <= SMALL_SORT && n <= 700u * static_cast<uint32_t>((nbits + 7) / 8)) {
+    k_sort_small<<<1, 1024, 0, s>>>(keys, vals, n, nbits, ktmp, vtmp);
+    TTS_LAUNCH_CHECK();
+    return true;
+  }
   const uint32_t ntiles = (n + RS_TILE - 1) / RS_TILE;
   const int passes = (nbits + 7) / 8;
   DBuf<uint32_t> counts(al, static_cast<size_t>(256) * ntiles);

@@ -56,23 +56,34 @@ void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
 }
 
 // CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
-// Returns false when a Cholesky factor breaks down or is too ill-conditioned.
-bool cholqr2(Allocator* al, const double* G, int m, int c, double* Q, double* R, hipStream_t s) {
+// ok[0..3] (device) are set to 0 when a Cholesky factor breaks down or is too
+// ill-conditioned; nothing is read back here.
+void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s) {
   DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
       g2(al, static_cast<size_t>(c) * c);
-  DBuf<int32_t> ok(al, 4);
-  k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
+  k_set_i32<<<1, 64, 0, s>>>(ok, 4, 1);
   TTS_LAUNCH_CHECK();
   gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
-  cholesky_upper(g1.get(), c, c, 1e7, ok.get() + 0, s);
-  trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok.get() + 1, s, al);
+  cholesky_upper(g1.get(), c, c, 1e7, ok + 0, s);
+  trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok + 1, s, al);
   gemm(al, true, false, c, c, m, 1.0, q1.get(), m, q1.get(), m, 0.0, g2.get(), c, s);
-  cholesky_upper(g2.get(), c, c, 10.0, ok.get() + 2, s);
-  trsm_right_upper(q1.get(), m, c, m, g2.get(), c, Q, m, ok.get() + 3, s, al);
+  cholesky_upper(g2.get(), c, c, 10.0, ok + 2, s);
+  trsm_right_upper(q1.get(), m, c, m, g2.get(), c, Q, m, ok + 3, s, al);
   gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
-  int32_t h[4];
-  d2h(h, ok.get(), 4, s);
-  return h[0] && h[1] && h[2] && h[3];
+}
+
+// perm[rank(j)] = j for the stable non-ascending order of s[0..n): rank(j) = number of
+// i with s_i > s_j, or s_i == s_j and i < j.
+__global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv, int n, int32_t* __restrict__ perm) {
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double x = sv[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+      const double y = sv[i];
+      r += (y > x || (y == x && i < j)) ? 1 : 0;
+    }
+    perm[r] = j;
+  }
 }
 
 }  // namespace
@@ -212,30 +223,50 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     // are the left singular vectors of R (resp. G) and the rotated columns are
     // V Sigma, both without a division by sigma.  (Jacobi on R^T rather than R
     // also needs far fewer sweeps: the triangular factor acts as a preconditioner.)
+    // One read-back per bond: the singular values together with CholeskyQR2's
+    // success flags; on a breakdown the bond is redone with Householder QR.
     DBuf<double> Qb, Bt;
     bool haveQ = false;
     int cB = m;
     Bt.reset(A, static_cast<size_t>(rl) * std::min(m, rl));
     if (m > rl) {
+      cB = rl;
+      haveQ = true;
       Qb.reset(A, static_cast<size_t>(m) * rl);
+    }
+    DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
+    DBuf<int32_t> dperm(A, cB), okq(A, 4);
+    std::vector<double> sh(cB);
+    auto svd_of_bt = [&]() {
+      jacobi_svd(Bt.get(), rl, cB, rl, V.get(), cB, sig.get(), s);
+      k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
+      TTS_LAUNCH_CHECK();
+      TTS_HIP(hipMemcpyAsync(sh.data(), sig.get(), sizeof(double) * cB, hipMemcpyDeviceToHost, s));
+    };
+    if (haveQ) {
       DBuf<double> R(A, static_cast<size_t>(rl) * rl);
-      if (!cholqr2(A, Gk, m, rl, Qb.get(), R.get(), s)) {
+      cholqr2_async(A, Gk, m, rl, Qb.get(), R.get(), okq.get(), s);
+      transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
+      svd_of_bt();
+      int32_t okh[4];
+      TTS_HIP(hipMemcpyAsync(okh, okq.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
+      TTS_HIP(hipStreamSynchronize(s));
+      if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
         DBuf<double> Af(A, static_cast<size_t>(m) * rl), th(A, rl);
         copy_matrix(Gk, m, rl, m, Af.get(), m, s);
         householder_qr(Af.get(), m, rl, m, th.get(), s);
         householder_form_q(Af.get(), m, rl, m, th.get(), Qb.get(), m, s);
         householder_extract_r(Af.get(), m, rl, m, R.get(), rl, Qb.get(), m, s);
+        transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
+        svd_of_bt();
+        TTS_HIP(hipStreamSynchronize(s));
       }
-      transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
-      cB = rl;
-      haveQ = true;
     } else {
       transpose(Gk, m, rl, m, Bt.get(), rl, s);
+      svd_of_bt();
+      TTS_HIP(hipStreamSynchronize(s));
     }
-    DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
-    jacobi_svd(Bt.get(), rl, cB, rl, V.get(), cB, sig.get(), s);
-    std::vector<double> sh(cB);
-    d2h(sh.data(), sig.get(), cB, s);
+    // the same stable non-ascending order as k_rank_desc
     std::vector<int32_t> perm(cB);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return sh[x] > sh[y]; });
@@ -259,8 +290,6 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     rk = std::min(rk, cB);
     out.sigma[k - 2] = ss;
     out.tail[k - 2] = tailsum[rk];
-    DBuf<int32_t> dperm(A, rk);
-    h2d(dperm.get(), perm.data(), rk, s);
     DBuf<double> UR(A, static_cast<size_t>(cB) * rk), VS(A, static_cast<size_t>(rl) * rk);
     permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
     permute_cols(Bt.get(), rl, rl, dperm.get(), nullptr, rk, VS.get(), rl, s);
@@ -279,7 +308,6 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     cores[k - 1] = std::move(Unew);
     cores[k - 2] = std::move(Pnew);
     r[k - 1] = rk;
-    TTS_HIP(hipStreamSynchronize(s));  // host vectors above are read by the copies
   }
   out.ranks = r;
   out.dtype = TT_DTYPE_F64;
