@@ -36,6 +36,10 @@ FAMILY_BOUND = {
     "trsm": "alu", "gemm": "mfma", "gemm_lp": "mfma",
     "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm",
 }
+# Families whose every launch is one workgroup (one CU of 256): their roofline line
+# also states the fraction of one CU's share of the peak.
+SINGLE_WORKGROUP = {"jacobi", "cholesky"}
+NUM_CU = 256
 # Per-launch HBM traffic of profiled kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a plain copy of known size (profiles/traffic_*.txt).  A figure is
 # used only while the source file that holds the kernel is unchanged.
@@ -235,6 +239,9 @@ def main():
                            "kernel": family, "launches_per_step": k_n / args.steps,
                            "kernel_ms_per_step": k_ms / args.steps,
                            "algo_bytes_per_launch": k_bytes / k_n, "algo_flops_per_launch": k_flops / k_n}
+        if family in SINGLE_WORKGROUP:
+            out["roofline"]["single_workgroup"] = True
+            out["roofline"]["frac_of_one_cu"] = achieved / (peak / NUM_CU)
     if not args.no_cpu_baseline:
         cores_host = [c.cpu().numpy() for c in tt.cores]
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample,
