@@ -122,82 +122,119 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   std::vector<DBuf<char>> cores(d);
 
   // ---------------- left-to-right sweep ----------------
+  // A deflated basis is accepted on a residual test whose outcome is read back
+  // together with the next bond's pivot count (one read-back per bond).  Should the
+  // test fail, that bond is redone with an exact Householder QR and the bond after
+  // it is recomputed from the exact factor.
   DBuf<double> W(A, 1);
   k_set_f64<<<1, 1, 0, s>>>(W.get(), 1.0);
   TTS_LAUNCH_CHECK();
   int rp = 1;
-  for (int k = 1; k <= d - 1; ++k) {
+  // exact Householder QR of the bond-kb input Xb (rows x cols)
+  auto exact_bond = [&](int kb, const DBuf<double>& Xb, int rows, int cols) {
+    const int p = std::min(rows, cols);
+    DBuf<double> Af(A, static_cast<size_t>(rows) * cols), th(A, p), Q(A, static_cast<size_t>(rows) * p);
+    copy_matrix(Xb.get(), rows, cols, rows, Af.get(), rows, s);
+    householder_qr(Af.get(), rows, cols, rows, th.get(), s);
+    householder_form_q(Af.get(), rows, p, rows, th.get(), Q.get(), rows, s);
+    DBuf<double> Wn(A, static_cast<size_t>(p) * cols);
+    householder_extract_r(Af.get(), rows, cols, rows, Wn.get(), p, Q.get(), rows, s);
+    cores[kb - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * p);
+    transpose(Q.get(), rows, p, rows, reinterpret_cast<double*>(cores[kb - 1].get()), p, s);
+    W = std::move(Wn);
+    rp = p;
+    r[kb] = p;
+  };
+  struct Pending {
+    bool active = false;
+    int k = 0, rows = 0, cols = 0;
+    DBuf<double> X, e2;
+    DBuf<int32_t> ok;
+  } pend;
+  int32_t pok[4];
+  double pe2 = 0.0;
+  auto pending_accepted = [&]() { return pok[1] && pok[2] && pok[3] && pe2 <= tau * tau; };
+  int k = 1;
+  while (k <= d - 1) {
     const int nk = n[k - 1];
     const int rows = rp * nk, cols = beta[k];
     DBuf<double> X(A, static_cast<size_t>(rows) * cols);
     TTS_HIP(hipMemsetAsync(X.get(), 0, sizeof(double) * rows * cols, s));
     spmm_left(W.get(), rp, rp, in.n_colptr[k - 1], in.n_row[k - 1], in.n_val[k - 1], cols, nk, X.get(), rows, s);
-
-    DBuf<double> Q, Wn;
-    int rk = 0;
-    bool accepted = false;
+    const int rmax = std::min(rows, cols);
+    DBuf<double> L;
+    DBuf<int32_t> piv, cnt;
+    int32_t rsel = 0;
     if (tau > 0.0) {
       DBuf<double> Y(A, static_cast<size_t>(rows) * cols), G(A, static_cast<size_t>(cols) * cols);
       scale_cols_sqrt(X.get(), rows, cols, rows, w[k].get(), Y.get(), rows, s);
       gemm(A, true, false, cols, cols, rows, 1.0, Y.get(), rows, Y.get(), rows, 0.0, G.get(), cols, s);
-      const int rmax = std::min(rows, cols);
-      DBuf<double> L(A, static_cast<size_t>(cols) * rmax);
-      DBuf<int32_t> piv(A, rmax), cnt(A, 1);
+      L.reset(A, static_cast<size_t>(cols) * rmax);
+      piv.reset(A, rmax);
+      cnt.reset(A, 1);
       pivoted_cholesky(G.get(), cols, cols, rmax, kTheta, L.get(), piv.get(), cnt.get(), s);
-      int32_t rsel = 0;
-      d2h(&rsel, cnt.get(), 1, s);
-      if (rsel > 0) {
-        DBuf<double> Ys(A, static_cast<size_t>(rows) * rsel), U1(A, static_cast<size_t>(rsel) * rsel),
-            Q1(A, static_cast<size_t>(rows) * rsel), G2(A, static_cast<size_t>(rsel) * rsel);
-        DBuf<int32_t> ok(A, 4);
-        DBuf<double> e2(A, 1);
-        k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
-        TTS_LAUNCH_CHECK();
-        gather_cols(X.get(), rows, rows, piv.get(), rsel, w[k].get(), Ys.get(), rows, s);
-        pivot_factor(L.get(), cols, piv.get(), rsel, U1.get(), s);
-        trsm_right_upper(Ys.get(), rows, rsel, rows, U1.get(), rsel, Q1.get(), rows, ok.get() + 1, s, A);
-        gemm(A, true, false, rsel, rsel, rows, 1.0, Q1.get(), rows, Q1.get(), rows, 0.0, G2.get(), rsel, s);
-        cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
-        Q.reset(A, static_cast<size_t>(rows) * rsel);
-        trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
-        Wn.reset(A, static_cast<size_t>(rsel) * cols);
-        gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
-        // residual of the basis, weighted by the right-part row norms
-        DBuf<double> E(A, static_cast<size_t>(rows) * cols);
-        copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s);
-        gemm(A, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s);
-        weighted_sumsq(A, E.get(), rows, cols, rows, w[k].get(), e2.get(), s);
-        int32_t okh[4];
-        double e2h = 0.0;
-        TTS_HIP(hipMemcpyAsync(okh, ok.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
-        d2h(&e2h, e2.get(), 1, s);
-        // fixed-rank truncation keeps min(max_rank, #nonzero sigma): deflating below
-        // max_rank would drop numerically tiny but nonzero directions it keeps
-        const bool rank_ok = in.max_rank <= 0 || rsel >= in.max_rank;
-        if (okh[1] && okh[2] && okh[3] && e2h <= tau * tau && rank_ok) {
-          accepted = true;
-          rk = rsel;
-        }
+      TTS_HIP(hipMemcpyAsync(&rsel, cnt.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    if (pend.active) {
+      TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
+      TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (tau > 0.0 || pend.active) TTS_HIP(hipStreamSynchronize(s));
+    if (pend.active) {
+      pend.active = false;
+      if (!pending_accepted()) {
+        exact_bond(pend.k, pend.X, pend.rows, pend.cols);
+        k = pend.k + 1;  // this bond again, from the exact factor
+        continue;
       }
     }
-    if (!accepted) {
-      // exact Householder QR of X_k
-      const int p = std::min(rows, cols);
-      DBuf<double> Af(A, static_cast<size_t>(rows) * cols), th(A, p);
-      copy_matrix(X.get(), rows, cols, rows, Af.get(), rows, s);
-      householder_qr(Af.get(), rows, cols, rows, th.get(), s);
-      Q.reset(A, static_cast<size_t>(rows) * p);
-      householder_form_q(Af.get(), rows, p, rows, th.get(), Q.get(), rows, s);
-      Wn.reset(A, static_cast<size_t>(p) * cols);
-      householder_extract_r(Af.get(), rows, cols, rows, Wn.get(), p, Q.get(), rows, s);
-      rk = p;
+    // fixed-rank truncation keeps min(max_rank, #nonzero sigma): deflating below
+    // max_rank would drop numerically tiny but nonzero directions it keeps
+    const bool rank_ok = in.max_rank <= 0 || rsel >= in.max_rank;
+    if (tau > 0.0 && rsel > 0 && rank_ok) {
+      DBuf<double> Ys(A, static_cast<size_t>(rows) * rsel), U1(A, static_cast<size_t>(rsel) * rsel),
+          Q1(A, static_cast<size_t>(rows) * rsel), G2(A, static_cast<size_t>(rsel) * rsel),
+          Q(A, static_cast<size_t>(rows) * rsel), Wn(A, static_cast<size_t>(rsel) * cols);
+      DBuf<int32_t> ok(A, 4);
+      DBuf<double> e2(A, 1);
+      k_set_i32<<<1, 64, 0, s>>>(ok.get(), 4, 1);
+      TTS_LAUNCH_CHECK();
+      gather_cols(X.get(), rows, rows, piv.get(), rsel, w[k].get(), Ys.get(), rows, s);
+      pivot_factor(L.get(), cols, piv.get(), rsel, U1.get(), s);
+      trsm_right_upper(Ys.get(), rows, rsel, rows, U1.get(), rsel, Q1.get(), rows, ok.get() + 1, s, A);
+      gemm(A, true, false, rsel, rsel, rows, 1.0, Q1.get(), rows, Q1.get(), rows, 0.0, G2.get(), rsel, s);
+      cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
+      trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
+      gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
+      // residual of the basis, weighted by the right-part row norms
+      DBuf<double> E(A, static_cast<size_t>(rows) * cols);
+      copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s);
+      gemm(A, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s);
+      weighted_sumsq(A, E.get(), rows, cols, rows, w[k].get(), e2.get(), s);
+      // core k = Q reshaped to [r_{k-1}][n_k][r_k] (row-major) = Q^T column-major
+      cores[k - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * rsel);
+      transpose(Q.get(), rows, rsel, rows, reinterpret_cast<double*>(cores[k - 1].get()), rsel, s);
+      W = std::move(Wn);
+      rp = rsel;
+      r[k] = rsel;
+      pend.active = true;
+      pend.k = k;
+      pend.rows = rows;
+      pend.cols = cols;
+      pend.X = std::move(X);
+      pend.ok = std::move(ok);
+      pend.e2 = std::move(e2);
+    } else {
+      exact_bond(k, X, rows, cols);
     }
-    // core k = Q reshaped to [r_{k-1}][n_k][r_k] (row-major) = Q^T column-major
-    cores[k - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * rk);
-    transpose(Q.get(), rows, rk, rows, reinterpret_cast<double*>(cores[k - 1].get()), rk, s);
-    W = std::move(Wn);
-    rp = rk;
-    r[k] = rk;
+    ++k;
+  }
+  if (pend.active) {  // the last bond's test
+    TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipStreamSynchronize(s));
+    pend.active = false;
+    if (!pending_accepted()) exact_bond(pend.k, pend.X, pend.rows, pend.cols);
   }
   {
     // last core: W (r_{d-1} x beta_{d-1}) times the exact last core (beta_{d-1} x n_d)

@@ -74,6 +74,7 @@ CASES = [
     ("r5", 3, (4, 3, 5, 4, 3), 300, 0.3),
     ("r3", 5, (9, 8, 7), 150, 0.1),
     ("r4z", 6, (6, 5, 4, 6), 200, 0.0),
+    ("m2", 7, (30, 40), 300, 1e-3),  # d = 2: a sparse matrix, one bond
 ]
 
 
@@ -134,3 +135,25 @@ def test_determinism():
     assert a.ranks == b.ranks
     for x, y in zip(a.cores, b.cores):
         assert torch.equal(x, y)
+
+
+def test_deflation_rejected_and_redone(oracle_mod):
+    """A term at 2^-24 of the rest: pivoted Cholesky (threshold 1e-12 on squared
+    norms) drops its directions, the residual test (1e-13 ||A||) rejects the deflated
+    basis, and the bond is redone with an exact QR.  The result must still match the
+    oracle, and the QR ranks must show the exact bonds."""
+    idx1, val1, dims = synth.kronecker_sum(6, 10, 5, 3, seed=11)
+    idx2, val2, _ = synth.kronecker_sum(6, 10, 1, 3, seed=12)
+    keys = {}
+    for ix, v in zip(idx1, val1):
+        keys[tuple(ix)] = keys.get(tuple(ix), 0.0) + v
+    for ix, v in zip(idx2, val2 * 2.0 ** -24):
+        keys[tuple(ix)] = keys.get(tuple(ix), 0.0) + v
+    idx = np.array(list(keys.keys()), dtype=np.int32)
+    val = np.array(list(keys.values()), dtype=np.float64)
+    tt, res = check_round(oracle_mod, idx, val, dims, 1e-11, "kron + 2^-24 term")
+    print(f"[round parity] qr ranks gpu {tt.qr_ranks} oracle {res.qr_ranks}; final {tt.ranks}", flush=True)
+    assert tt.ranks == res.ranks
+    # every bond fell back to the exact QR: an accepted deflation would stop at the
+    # 5 dominant directions, the exact QR keeps all min(rows, cols)
+    assert tt.qr_ranks == res.qr_ranks
