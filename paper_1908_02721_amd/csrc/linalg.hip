@@ -54,36 +54,56 @@ __global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += GK) {
-    for (int e = threadIdx.x; e < GT * GK; e += NT) {
-      int i, kk;
-      if (!ta) {
-        i = e % GT;
-        kk = e / GT;
-      } else {
-        kk = e % GK;
-        i = e / GK;
-      }
-      const int gi = m0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < m && gk < ke) v = ta ? A[gk + static_cast<size_t>(gi) * lda] : A[gi + static_cast<size_t>(gk) * lda];
-      As[kk][i] = v;
+  // staging: all loads of a K-stage are issued together from clamped addresses and
+  // masked when written to LDS; the next stage's loads go out before this stage's
+  // MFMA.  Element e of a stage is A-tile entry (i, kk) and B-tile entry (kk, j),
+  // enumerated so that consecutive e are consecutive in memory.
+  constexpr int PL = GT * GK / NT;
+  auto a_pos = [&](int e, int* i, int* kk) {
+    if (!ta) {
+      *i = e % GT;
+      *kk = e / GT;
+    } else {
+      *kk = e % GK;
+      *i = e / GK;
     }
-    for (int e = threadIdx.x; e < GT * GK; e += NT) {
-      int j, kk;
-      if (!tb) {
-        kk = e % GK;
-        j = e / GK;
-      } else {
-        j = e % GT;
-        kk = e / GT;
-      }
-      const int gj = n0 + j, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < n && gk < ke) v = tb ? B[gj + static_cast<size_t>(gk) * ldb] : B[gk + static_cast<size_t>(gj) * ldb];
-      Bs[kk][j] = v;
+  };
+  auto b_pos = [&](int e, int* kk, int* j) {
+    if (!tb) {
+      *kk = e % GK;
+      *j = e / GK;
+    } else {
+      *j = e % GT;
+      *kk = e / GT;
+    }
+  };
+  double av[PL], bv[PL];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = threadIdx.x + u * NT;
+      int i, kk, j, kb2;
+      a_pos(e, &i, &kk);
+      b_pos(e, &kb2, &j);
+      const int gi = m0 + i, gka = k0 + kk, gj = n0 + j, gkb = k0 + kb2;
+      const bool oka = gi < m && gka < ke, okb = gj < n && gkb < ke;
+      av[u] = A[oka ? (ta ? gka + static_cast<size_t>(gi) * lda : gi + static_cast<size_t>(gka) * lda) : 0];
+      bv[u] = B[okb ? (tb ? gj + static_cast<size_t>(gkb) * ldb : gkb + static_cast<size_t>(gj) * ldb) : 0];
+    }
+  };
+  if (kb < ke) load_stage(kb);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = threadIdx.x + u * NT;
+      int i, kk, j, kb2;
+      a_pos(e, &i, &kk);
+      b_pos(e, &kb2, &j);
+      As[kk][i] = (m0 + i < m && k0 + kk < ke) ? (av[u]) : (0);
+      Bs[kb2][j] = (n0 + j < n && k0 + kb2 < ke) ? (bv[u]) : (0);
     }
     __syncthreads();
+    if (k0 + GK < ke) load_stage(k0 + GK);
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
       const double a0 = As[ks + lk][wm + li], a1 = As[ks + lk][wm + 16 + li];
@@ -160,36 +180,56 @@ __global__ __launch_bounds__(NT) void k_gemm_lp(int ta, int tb, int m, int n, in
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = flt4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += LK) {
-    for (int e = threadIdx.x; e < GT * LK; e += NT) {
-      int i, kk;
-      if (!ta) {
-        i = e % GT;
-        kk = e / GT;
-      } else {
-        kk = e % LK;
-        i = e / LK;
-      }
-      const int gi = m0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < m && gk < ke) v = ta ? A[gk + static_cast<size_t>(gi) * lda] : A[gi + static_cast<size_t>(gk) * lda];
-      As[kk][i] = static_cast<float>(v);
+  // staging: all loads of a K-stage are issued together from clamped addresses and
+  // masked when written to LDS; the next stage's loads go out before this stage's
+  // MFMA.  Element e of a stage is A-tile entry (i, kk) and B-tile entry (kk, j),
+  // enumerated so that consecutive e are consecutive in memory.
+  constexpr int PL = GT * LK / NT;
+  auto a_pos = [&](int e, int* i, int* kk) {
+    if (!ta) {
+      *i = e % GT;
+      *kk = e / GT;
+    } else {
+      *kk = e % LK;
+      *i = e / LK;
     }
-    for (int e = threadIdx.x; e < GT * LK; e += NT) {
-      int j, kk;
-      if (!tb) {
-        kk = e % LK;
-        j = e / LK;
-      } else {
-        j = e % GT;
-        kk = e / GT;
-      }
-      const int gj = n0 + j, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < n && gk < ke) v = tb ? B[gj + static_cast<size_t>(gk) * ldb] : B[gk + static_cast<size_t>(gj) * ldb];
-      Bs[kk][j] = static_cast<float>(v);
+  };
+  auto b_pos = [&](int e, int* kk, int* j) {
+    if (!tb) {
+      *kk = e % LK;
+      *j = e / LK;
+    } else {
+      *j = e % GT;
+      *kk = e / GT;
+    }
+  };
+  double av[PL], bv[PL];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = threadIdx.x + u * NT;
+      int i, kk, j, kb2;
+      a_pos(e, &i, &kk);
+      b_pos(e, &kb2, &j);
+      const int gi = m0 + i, gka = k0 + kk, gj = n0 + j, gkb = k0 + kb2;
+      const bool oka = gi < m && gka < ke, okb = gj < n && gkb < ke;
+      av[u] = A[oka ? (ta ? gka + static_cast<size_t>(gi) * lda : gi + static_cast<size_t>(gka) * lda) : 0];
+      bv[u] = B[okb ? (tb ? gj + static_cast<size_t>(gkb) * ldb : gkb + static_cast<size_t>(gj) * ldb) : 0];
+    }
+  };
+  if (kb < ke) load_stage(kb);
+  for (int k0 = kb; k0 < ke; k0 += LK) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = threadIdx.x + u * NT;
+      int i, kk, j, kb2;
+      a_pos(e, &i, &kk);
+      b_pos(e, &kb2, &j);
+      As[kk][i] = (m0 + i < m && k0 + kk < ke) ? static_cast<float>(av[u]) : static_cast<float>(0);
+      Bs[kb2][j] = (n0 + j < n && k0 + kb2 < ke) ? static_cast<float>(bv[u]) : static_cast<float>(0);
     }
     __syncthreads();
+    if (k0 + LK < ke) load_stage(k0 + LK);
     if (BF) {
       bf16x8 a0, a1, b0, b1;
 #pragma unroll
@@ -450,11 +490,12 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
                                                          int32_t* __restrict__ piv, int32_t* __restrict__ d_r,
                                                          int tl) {
   extern __shared__ double sm[];
-  double* dg = sm;               // n
-  double* lp = sm + n;           // rmax (row p of L)
-  double* Lc = lp + rmax;        // the first tl columns of L, n x tl (LDS copy)
+  double* dg = sm;      // n: diagonal of the current Schur complement (-1 once pivoted)
+  double* Lc = sm + n;  // the first tl columns of L, n x tl (LDS copy)
   __shared__ double redv[17];
   __shared__ int redi[17];
+  __shared__ double slotv[2][BT / 64];  // per-wave argmax candidates, double-buffered
+  __shared__ int sloti[2][BT / 64];
   double gmax = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
     dg[j] = G[j + static_cast<size_t>(j) * ldg];
@@ -467,8 +508,11 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
   // LPJ lanes share column j of the update; lane `sub` takes steps l = sub (mod LPJ)
   constexpr int JPB = BT / LPJ;
   const int sub = threadIdx.x % LPJ, jj = threadIdx.x / LPJ;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int r = 0;
   for (int t = 0; t < rmax; ++t) {
+    // argmax of the diagonal (largest value, lowest index on ties): wave reduction,
+    // one barrier, then every thread reduces the per-wave candidates itself
     double v = -1.0;
     int idx = n;
     for (int j = threadIdx.x; j < n; j += BT)
@@ -476,40 +520,62 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
         v = dg[j];
         idx = j;
       }
-    double pv;
-    int p;
-    block_argmax_1024(v, idx, redv, redi, &pv, &p);
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(idx, o, 64);
+      if (ov > v || (ov == v && oi < idx)) {
+        v = ov;
+        idx = oi;
+      }
+    }
+    if (lane == 0) {
+      slotv[t & 1][w] = v;
+      sloti[t & 1][w] = idx;
+    }
+    __syncthreads();
+    double pv = slotv[t & 1][0];
+    int p = sloti[t & 1][0];
+    for (int i = 1; i < BT / 64; ++i) {
+      const double cvv = slotv[t & 1][i];
+      const int cii = sloti[t & 1][i];
+      if (cvv > pv || (cvv == pv && cii < p)) {
+        pv = cvv;
+        p = cii;
+      }
+    }
     if (!(pv > thr)) break;
     if (threadIdx.x == 0) piv[t] = p;
-    for (int l = threadIdx.x; l < t; l += BT) lp[l] = (l < tl) ? Lc[p + l * n] : L[p + static_cast<size_t>(l) * n];
-    __syncthreads();
     const double sq = sqrt(pv);
     const double inv = 1.0 / sq;
     for (int j0 = 0; j0 < n; j0 += JPB) {
       const int j = j0 + jj;
       const bool live = j < n && j != p && dg[min(j, n - 1)] >= 0.0;
-      // s = G[j, p] - sum_{l < t} L[j, l] L[p, l], four independent partial sums
+      // the Gram entry is requested first so that its latency overlaps the dot product
+      const double gjp = (live && sub == 0) ? G[j + static_cast<size_t>(p) * ldg] : 0.0;
+      // s = G[j, p] - sum_{l < t} L[j, l] L[p, l], four independent partial sums;
+      // steps l < tl from the LDS copy (row p read as a broadcast), the rest from memory
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       if (live) {
-        // steps l < tl from the LDS copy, the rest from global memory
         const int tlim = min(t, tl);
         const double* Cj = Lc + j;
+        const double* Cp = Lc + p;
         int l = sub;
         for (; l + 3 * LPJ < tlim; l += 4 * LPJ) {
-          s0 = fma(Cj[l * n], lp[l], s0);
-          s1 = fma(Cj[(l + LPJ) * n], lp[l + LPJ], s1);
-          s2 = fma(Cj[(l + 2 * LPJ) * n], lp[l + 2 * LPJ], s2);
-          s3 = fma(Cj[(l + 3 * LPJ) * n], lp[l + 3 * LPJ], s3);
+          s0 = fma(Cj[l * n], Cp[l * n], s0);
+          s1 = fma(Cj[(l + LPJ) * n], Cp[(l + LPJ) * n], s1);
+          s2 = fma(Cj[(l + 2 * LPJ) * n], Cp[(l + 2 * LPJ) * n], s2);
+          s3 = fma(Cj[(l + 3 * LPJ) * n], Cp[(l + 3 * LPJ) * n], s3);
         }
-        for (; l < tlim; l += LPJ) s0 = fma(Cj[l * n], lp[l], s0);
+        for (; l < tlim; l += LPJ) s0 = fma(Cj[l * n], Cp[l * n], s0);
         const double* Lj = L + j;
+        const double* Lp = L + p;
         for (; l + 3 * LPJ < t; l += 4 * LPJ) {
-          s0 = fma(Lj[static_cast<size_t>(l) * n], lp[l], s0);
-          s1 = fma(Lj[static_cast<size_t>(l + LPJ) * n], lp[l + LPJ], s1);
-          s2 = fma(Lj[static_cast<size_t>(l + 2 * LPJ) * n], lp[l + 2 * LPJ], s2);
-          s3 = fma(Lj[static_cast<size_t>(l + 3 * LPJ) * n], lp[l + 3 * LPJ], s3);
+          s0 = fma(Lj[static_cast<size_t>(l) * n], Lp[static_cast<size_t>(l) * n], s0);
+          s1 = fma(Lj[static_cast<size_t>(l + LPJ) * n], Lp[static_cast<size_t>(l + LPJ) * n], s1);
+          s2 = fma(Lj[static_cast<size_t>(l + 2 * LPJ) * n], Lp[static_cast<size_t>(l + 2 * LPJ) * n], s2);
+          s3 = fma(Lj[static_cast<size_t>(l + 3 * LPJ) * n], Lp[static_cast<size_t>(l + 3 * LPJ) * n], s3);
         }
-        for (; l < t; l += LPJ) s0 = fma(Lj[static_cast<size_t>(l) * n], lp[l], s0);
+        for (; l < t; l += LPJ) s0 = fma(Lj[static_cast<size_t>(l) * n], Lp[static_cast<size_t>(l) * n], s0);
       }
       double acc = (s0 + s1) + (s2 + s3);
 #pragma unroll
@@ -522,7 +588,7 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
         } else if (!live) {
           x = 0.0;  // already a pivot: its Schur row is zero
         } else {
-          x = (G[j + static_cast<size_t>(p) * ldg] - acc) * inv;
+          x = (gjp - acc) * inv;
           dg[j] = dg[j] - x * x;
         }
         L[j + static_cast<size_t>(t) * n] = x;
@@ -1523,7 +1589,7 @@ void gather_cols(const double* X, int rows, int ldx, const int32_t* piv, int r, 
 
 void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, double* L, int32_t* piv, int32_t* d_r,
                       hipStream_t s) {
-  const size_t base = sizeof(double) * (static_cast<size_t>(n) + rmax);
+  const size_t base = sizeof(double) * static_cast<size_t>(n);
   const size_t cap = 150 * 1024;
   if (base > cap) fail(TT_ERR_TOO_LARGE, "pivoted Cholesky: Gram matrix too large for one workgroup");
   // as many leading columns of L as fit are kept in LDS
