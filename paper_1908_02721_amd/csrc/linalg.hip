@@ -713,6 +713,65 @@ __global__ __launch_bounds__(BT) void k_cholesky_upper(double* __restrict__ A, i
   if (threadIdx.x == 0) *ok = (bad || dmax > max_ratio * dmin) ? 0 : 1;
 }
 
+// Right triangular solve X = Y U^{-1} (U upper, r <= 64), blocked, 64 rows of Y per
+// workgroup.  U is padded to 64 x 64 with a unit diagonal.  Wave w solves rows
+// 16w..16w+15 block column by block column (16 columns each): the update
+// T = Y_J - sum_{I<J} X_I U_IJ runs on the matrix cores (v_mfma_f64_16x16x4), then
+// X_J solves X_J U_JJ = T by substitution, one lane per row -- the standard blocked
+// algorithm, backward stable like plain substitution.  The tile stays in LDS and each
+// wave touches only its own rows, so the block loop needs no barrier.  *ok = 0 if U
+// has a zero diagonal entry.
+__global__ __launch_bounds__(256) void k_trsm_mfma(const double* __restrict__ Y, int rows, int r, int ldy,
+                                                   const double* __restrict__ U, int ldu, double* __restrict__ X,
+                                                   int ldx, int32_t* __restrict__ ok) {
+  __shared__ double us[64][65];
+  __shared__ double xs[64][65];
+  const int row0 = blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e % 64, l = e / 64;
+    us[i][l] = (i < r && l < r) ? U[i + static_cast<size_t>(l) * ldu] : (i == l ? 1.0 : 0.0);
+    xs[i][l] = (row0 + i < rows && l < r) ? Y[row0 + i + static_cast<size_t>(l) * ldy] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64 && us[tid][tid] == 0.0) *ok = 0;
+  const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int rw = 16 * w;
+  for (int J = 0; J < 4; ++J) {
+    if (J > 0) {
+      dbl4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = xs[rw + 4 * v + lk][16 * J + li];
+      for (int I = 0; I < J; ++I)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-xs[rw + li][16 * I + kk + lk],
+                                                     us[16 * I + kk + lk][16 * J + li], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xs[rw + 4 * v + lk][16 * J + li] = acc[v];
+    }
+    if (lk == 0) {
+      const int bj = 16 * J;
+      double x[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        double v = xs[rw + li][bj + jj];
+#pragma unroll
+        for (int l = 0; l < jj; ++l) v = fma(-x[l], us[bj + l][bj + jj], v);
+        const double dd = us[bj + jj][bj + jj];
+        x[jj] = (dd != 0.0) ? v / dd : 0.0;
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) xs[rw + li][bj + jj] = x[jj];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e % 64, l = e / 64;
+    if (row0 + i < rows && l < r) X[row0 + i + static_cast<size_t>(l) * ldx] = xs[i][l];
+  }
+}
+
 // Right triangular solve X = Y U^{-1} (U upper, r <= RM): one lane per row of Y,
 // one wave per workgroup (many workgroups for tall Y); U and the reciprocals of its
 // diagonal broadcast from LDS; forward substitution across the row with two
@@ -1646,6 +1705,11 @@ void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U
   if (rows <= 0 || r <= 0) return;
   // rows * r^2 / 2 multiply-adds; Y read, X written, U read once
   KTimer kt("trsm", s, 8.0 * (2.0 * rows * r + static_cast<double>(r) * r), static_cast<double>(rows) * r * r);
+  if (r <= 64 && rows >= 256) {
+    k_trsm_mfma<<<grid_for(rows, 64), 256, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   if (r <= 64) {
     if (r <= 32)
       k_trsm_right_upper<32><<<grid_for(rows, 64), 64, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
