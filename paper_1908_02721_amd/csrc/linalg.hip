@@ -609,6 +609,105 @@ __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ 
   U[t + static_cast<size_t>(s) * r] = (t <= s) ? L[piv[s] + static_cast<size_t>(t) * n] : 0.0;
 }
 
+// Blocked Cholesky of r <= 64 (upper factor) by one 256-thread workgroup; the matrix
+// is padded to 64 x 64 with a unit diagonal and kept row-major in LDS.  For each of the
+// four 16-wide block columns J: wave 0 factors the diagonal block (right-looking,
+// wave-local synchronisation only), one lane per column solves the block row to its
+// right (U_JJ^T X = A_JK), and the trailing upper blocks are updated on the matrix
+// cores (A_KL -= U_JK^T U_JL, v_mfma_f64_16x16x4).  Failure rules as in
+// k_cholesky_block: a non-positive pivot, or max/min of the diagonal above max_ratio.
+__global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, int r, int lda, double max_ratio,
+                                                       int32_t* __restrict__ ok) {
+  __shared__ double a[64][65];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  {  // staging: the 16 loads of each thread are issued together (clamped addresses)
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+      v[u] = Ag[(i < r && j < r) ? i + static_cast<size_t>(j) * lda : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+      a[i][j] = (i < r && j < r) ? v[u] : (i == j ? 1.0 : 0.0);
+    }
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  for (int J = 0; J < 4; ++J) {
+    const int b = 16 * J;
+    if (w == 0) {
+      for (int jj = 0; jj < 16; ++jj) {
+        const double d = a[b + jj][b + jj];
+        const bool pos = d > 0.0;
+        if (!pos && lane == 0) bad = 1;
+        const double piv = sqrt(pos ? d : 1.0);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == jj) a[b + jj][b + jj] = piv;
+        if (lane > jj && lane < 16) a[b + jj][b + lane] /= piv;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u, i = e >> 4, c = e & 15;
+          if (i > jj && c >= i) a[b + i][b + c] = fma(-a[b + jj][b + i], a[b + jj][b + c], a[b + i][b + c]);
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    const int rest = 64 - b - 16;
+    if (rest > 0 && tid < rest) {
+      const int c = b + 16 + tid;
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double v = a[b + i][c];
+#pragma unroll
+        for (int l = 0; l < i; ++l) v = fma(-a[b + l][b + i], x[l], v);
+        x[i] = v / a[b + i][b + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[b + i][c] = x[i];
+    }
+    __syncthreads();
+    // trailing upper blocks (K, L), J < K <= L, round-robin over the waves
+    int t = 0;
+    for (int K = J + 1; K < 4; ++K)
+      for (int L = K; L < 4; ++L, ++t) {
+        if (t % 4 != w) continue;
+        dbl4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = a[16 * K + 4 * v + lk][16 * L + li];
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[b + kk + lk][16 * K + li], a[b + kk + lk][16 * L + li], acc, 0,
+                                                     0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[16 * K + 4 * v + lk][16 * L + li] = acc[v];
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, j = e / r;
+    Ag[i + static_cast<size_t>(j) * lda] = (bad || i > j) ? 0.0 : a[i][j];
+  }
+  if (tid == 0) {
+    int fail = bad;
+    if (!fail) {
+      double dmin = INFINITY, dmax = 0.0;
+      for (int i = 0; i < r; ++i) {
+        dmin = fmin(dmin, a[i][i]);
+        dmax = fmax(dmax, a[i][i]);
+      }
+      fail = dmax > max_ratio * dmin;
+    }
+    *ok = fail ? 0 : 1;
+  }
+}
+
 // Cholesky of r <= R (R = 64 or 128) by one NTH-thread workgroup, upper factor.
 // The matrix sits row-major in LDS; thread (ty, c) owns column c of rows
 // ty, ty + G, ... (G = NTH / R).  Step j subtracts a_ji a_jc / a_jj from every
@@ -728,10 +827,20 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(const double* __restrict__ Y,
   __shared__ double xs[64][65];
   const int row0 = blockIdx.x * 64;
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int i = e % 64, l = e / 64;
-    us[i][l] = (i < r && l < r) ? U[i + static_cast<size_t>(l) * ldu] : (i == l ? 1.0 : 0.0);
-    xs[i][l] = (row0 + i < rows && l < r) ? Y[row0 + i + static_cast<size_t>(l) * ldy] : 0.0;
+  {  // staging: the 32 loads of each thread are issued together (clamped addresses)
+    double uv[16], yv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e % 64, l = e / 64;
+      uv[u] = U[(i < r && l < r) ? i + static_cast<size_t>(l) * ldu : 0];
+      yv[u] = Y[(row0 + i < rows && l < r) ? row0 + i + static_cast<size_t>(l) * ldy : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e % 64, l = e / 64;
+      us[i][l] = (i < r && l < r) ? uv[u] : (i == l ? 1.0 : 0.0);
+      xs[i][l] = (row0 + i < rows && l < r) ? yv[u] : 0.0;
+    }
   }
   __syncthreads();
   if (tid < 64 && us[tid][tid] == 0.0) *ok = 0;
@@ -1261,10 +1370,21 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
   __shared__ int rotated;
   double* A = reinterpret_cast<double*>(sm16);   // 64 x c (rows >= `rows` are zero)
   double* V = A + static_cast<size_t>(LD) * c;   // 64 x c (rows >= c are zero)
-  for (int e = threadIdx.x; e < LD * c; e += NTH) {
-    const int i = e % LD, j = e / LD;
-    A[e] = (i < rows) ? Ag[i + static_cast<size_t>(j) * lda] : 0.0;
-    V[e] = (i == j) ? 1.0 : 0.0;
+  {  // staging: each thread's loads are issued together (clamped addresses)
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
+      v[u] = Ag[(i < rows && j < c) ? i + static_cast<size_t>(j) * lda : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
+      if (j < c) {
+        A[e] = (i < rows) ? v[u] : 0.0;
+        V[e] = (i == j) ? 1.0 : 0.0;
+      }
+    }
   }
   __syncthreads();
   const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
@@ -1273,22 +1393,19 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
   for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
+    // round-robin positions of this group's pair, advanced by one (mod N - 1) per
+    // round instead of recomputed with divisions: group 0 pairs rd with N - 1, group
+    // k pairs rd + k with rd - k
+    int pp = (grp == 0) ? 0 : grp % (N - 1);
+    int qq = (grp == 0) ? N - 1 : (N - 1 - grp % (N - 1)) % (N - 1);
     for (int rd = 0; rd < N - 1; ++rd) {
       int p = 0, q = c;
       if (grp < N / 2) {
-        if (grp == 0) {
-          p = rd;
-          q = N - 1;
-        } else {
-          p = (rd + grp) % (N - 1);
-          q = (rd - grp + (N - 1)) % (N - 1);
-        }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
+        p = min(pp, qq);
+        q = max(pp, qq);
       }
+      pp = (pp + 1 == N - 1) ? 0 : pp + 1;
+      if (grp != 0) qq = (qq + 1 == N - 1) ? 0 : qq + 1;
       if (q < c) {  // uniform within the group
         double2* ap = reinterpret_cast<double2*>(A + static_cast<size_t>(p) * LD) + gl;
         double2* aq = reinterpret_cast<double2*>(A + static_cast<size_t>(q) * LD) + gl;
@@ -1308,7 +1425,10 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
         a = group8_sum(a);
         b = group8_sum(b);
         g = group8_sum(g);
-        if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+        // |g| > tol sqrt(a b), as g^2 > tol^2 a b while a b is a normal number
+        const double ab = a * b;
+        const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
+        if (a != 0.0 && b != 0.0 && rot) {
           double cs, sn;
           jacobi_rotation(a, b, g, &cs, &sn);
           double2* vp = reinterpret_cast<double2*>(V + static_cast<size_t>(p) * LD) + gl;
@@ -1676,7 +1796,7 @@ void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, 
   // r^3 / 3 multiply-adds; the matrix is read and written once
   KTimer kt("cholesky", s, 16.0 * r * r, 2.0 * r * r * r / 3.0);
   if (r <= 64) {
-    k_cholesky_block<64, 1024><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    k_cholesky_mfma<<<1, 256, 0, s>>>(A, r, lda, max_ratio, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
