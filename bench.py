@@ -6,8 +6,9 @@ One step is one pass of the whole hot path over the workload's nonzeros, all in
 libttsparse kernels:
   tt_sparse_decompose   ingest, sort, parallel-vector rounding of every level,
                         left-to-right QR sweep, right-to-left truncated-SVD sweep
-  tt_eval_entries       the TT at every nonzero coordinate
-  tt_eval_entries_backward  gradient of sum_n val[n] * TT(i_n) w.r.t. every core
+  tt_eval_plan_create   sort of the nonzero coordinates and their prefix trie
+  tt_eval_plan_forward  the TT at every nonzero coordinate (left products kept)
+  tt_eval_plan_backward gradient of sum_n val[n] * TT(i_n) w.r.t. every core
 Inputs are resident in HBM before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -158,8 +159,11 @@ def main():
         tt = tts.decompose(gi, gv, dims, eps, precision=args.precision)
         cores = tt.cores
         gy = gv if cores[0].dtype == torch.float64 else gv.float()
-        y = tts.eval_entries(cores, gi)
-        grads = tts.eval_entries_backward(cores, gi, gy)
+        # one plan per step: the sort and trie of the coordinates serve the forward and
+        # the backward, and the backward reuses the forward's left products
+        plan = tts.EvalPlan(gi, dims)
+        y = plan.forward(cores, save=True)
+        grads = plan.backward(cores, gy, use_saved=True)
         return tt, y, grads
 
     for _ in range(args.warmup):

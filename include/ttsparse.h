@@ -178,6 +178,40 @@ tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, const int64_t
                                    const int32_t* idx, const void* grad_y, void* const* grad_cores,
                                    void* stream);
 
+/*
+ * Evaluation plan: the same two operations as tt_eval_entries and
+ * tt_eval_entries_backward (entry formula of Sec. 2.3 and its derivative), split
+ * so that work which depends only on the coordinates is done once.
+ *
+ * tt_eval_plan_create sorts the m coordinates idx (device int32[m][d]) and builds
+ * the prefix tree of the distinct coordinate prefixes and its index buckets.  The
+ * plan owns copies of everything it needs: idx may be freed once the call returns.
+ * Coordinates out of range -> TT_ERR_INDEX, and *plan is left NULL.
+ *
+ * tt_eval_plan_forward writes y_out (device [m], caller-owned) for the TT given by
+ * ranks (host int64[d+1]), cores and dtype, as tt_eval_entries does.  With
+ * save != 0 the plan keeps the left partial products of this call (device memory
+ * owned by the plan, replacing any kept earlier) for a later backward.
+ *
+ * tt_eval_plan_backward writes the gradients, as tt_eval_entries_backward does.
+ * With use_saved != 0 it reuses the left partial products of the last forward
+ * called with save != 0 instead of recomputing them: the ranks and dtype must
+ * match that call's (TT_ERR_ARG otherwise), and the caller guarantees that the
+ * core values have not changed since.  The kept products stay for further calls.
+ *
+ * Every call returns once its work on the stream has finished.  A plan may be used
+ * from one thread at a time; tt_eval_plan_free releases it (NULL is ignored).
+ */
+typedef struct tt_eval_plan_s* tt_eval_plan;
+tt_status tt_eval_plan_create(int32_t d, const int64_t* dims, int64_t m, const int32_t* idx,
+                              void* stream, tt_eval_plan* plan);
+tt_status tt_eval_plan_forward(tt_eval_plan plan, const int64_t* ranks, const void* const* cores,
+                               int32_t dtype, void* y_out, int32_t save, void* stream);
+tt_status tt_eval_plan_backward(tt_eval_plan plan, const int64_t* ranks, const void* const* cores,
+                                int32_t dtype, const void* grad_y, void* const* grad_cores,
+                                int32_t use_saved, void* stream);
+void tt_eval_plan_free(tt_eval_plan plan);
+
 const char* tt_status_string(tt_status s);
 const char* tt_last_error(void);
 

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import STAGES, TTError
 
-__all__ = ["decompose", "TT", "eval_entries", "eval_entries_backward", "EvalEntries", "TTError", "library_path"]
+__all__ = ["decompose", "TT", "eval_entries", "eval_entries_backward", "EvalPlan", "EvalEntries", "TTError", "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -211,16 +211,87 @@ def eval_entries_backward(cores, idx: torch.Tensor, grad_y: torch.Tensor, stream
     return grads
 
 
+class EvalPlan:
+    """Sorted coordinates and their prefix trie, built once for idx int32 [m, d] (cuda).
+
+    forward(cores, save=False) -> y; backward(cores, grad_y, use_saved=False) -> grads.
+    With save, the forward keeps its left partial products; a backward with
+    use_saved reuses them (same ranks and dtype, unchanged core values).
+    """
+
+    def __init__(self, idx: torch.Tensor, dims, stream=None):
+        L = _lib.load()
+        idx = idx.contiguous()
+        if idx.dtype != torch.int32 or idx.dim() != 2:
+            raise TypeError("idx must be an int32 [m, d] tensor")
+        self.dims = [int(n) for n in dims]
+        self.m = int(idx.shape[0])
+        self.device = idx.device
+        d = len(self.dims)
+        a = (ctypes.c_int64 * d)(*self.dims)
+        h = ctypes.c_void_p()
+        _lib.check(L.tt_eval_plan_create(d, a, self.m, ctypes.c_void_p(idx.data_ptr()), _stream_handle(stream),
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().tt_eval_plan_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _cores(self, cores):
+        cores = [c.contiguous() for c in cores]
+        if [int(c.shape[1]) for c in cores] != self.dims:
+            raise ValueError("core mode sizes differ from the plan's dims")
+        if any(c.dtype != cores[0].dtype for c in cores):
+            raise TypeError("all cores must share one dtype")
+        return cores
+
+    def forward(self, cores, save: bool = False, stream=None) -> torch.Tensor:
+        L = _lib.load()
+        cores = self._cores(cores)
+        dt = _dtype_code(cores[0])
+        y = torch.empty(self.m, dtype=cores[0].dtype, device=cores[0].device)
+        _, _, ranks, ptrs = _core_args(cores)
+        _lib.check(L.tt_eval_plan_forward(self._h, ranks, ptrs, dt, ctypes.c_void_p(y.data_ptr()), int(bool(save)),
+                                          _stream_handle(stream)))
+        return y
+
+    def backward(self, cores, grad_y: torch.Tensor, use_saved: bool = False, stream=None):
+        L = _lib.load()
+        cores = self._cores(cores)
+        dt = _dtype_code(cores[0])
+        grad_y = grad_y.contiguous().to(cores[0].dtype)
+        grads = [torch.empty_like(c) for c in cores]
+        d, _, ranks, ptrs = _core_args(cores)
+        gptrs = (ctypes.c_void_p * d)(*[g.data_ptr() for g in grads])
+        _lib.check(L.tt_eval_plan_backward(self._h, ranks, ptrs, dt, ctypes.c_void_p(grad_y.data_ptr()), gptrs,
+                                           int(bool(use_saved)), _stream_handle(stream)))
+        return grads
+
+
 class EvalEntries(torch.autograd.Function):
-    """Differentiable sampled-entry evaluation: EvalEntries.apply(idx, *cores) -> y."""
+    """Differentiable sampled-entry evaluation: EvalEntries.apply(idx, *cores) -> y.
+
+    The forward builds an EvalPlan and keeps its left partial products; the backward
+    reuses both.  The cores are saved for backward, so autograd rejects an in-place
+    change of them in between.
+    """
 
     @staticmethod
     def forward(ctx, idx, *cores):
-        ctx.save_for_backward(idx, *cores)
-        return eval_entries(cores, idx)
+        plan = EvalPlan(idx, [int(c.shape[1]) for c in cores])
+        y = plan.forward(cores, save=True)
+        ctx.plan = plan
+        ctx.save_for_backward(*cores)
+        return y
 
     @staticmethod
     def backward(ctx, grad_y):
-        idx, *cores = ctx.saved_tensors
-        grads = eval_entries_backward(cores, idx, grad_y)
+        cores = ctx.saved_tensors
+        grads = ctx.plan.backward(cores, grad_y, use_saved=True)
         return (None, *grads)

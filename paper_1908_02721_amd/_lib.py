@@ -52,7 +52,8 @@ class tt_options(ctypes.Structure):
 EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
     "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_times", "tt_get_level", "tt_free",
-    "tt_eval_entries", "tt_eval_entries_backward", "tt_status_string", "tt_last_error",
+    "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_plan_create", "tt_eval_plan_forward",
+    "tt_eval_plan_backward", "tt_eval_plan_free", "tt_status_string", "tt_last_error",
     "tt_kernel_timer_start", "tt_kernel_timer_read",
 )
 
@@ -92,6 +93,14 @@ def load():
         L.tt_eval_entries.restype = ctypes.c_int
         L.tt_eval_entries_backward.argtypes = [i32, P(i64), P(i64), P(vp), i32, i64, vp, vp, P(vp), vp]
         L.tt_eval_entries_backward.restype = ctypes.c_int
+        L.tt_eval_plan_create.argtypes = [i32, P(i64), i64, vp, vp, P(vp)]
+        L.tt_eval_plan_create.restype = ctypes.c_int
+        L.tt_eval_plan_forward.argtypes = [vp, P(i64), P(vp), i32, vp, i32, vp]
+        L.tt_eval_plan_forward.restype = ctypes.c_int
+        L.tt_eval_plan_backward.argtypes = [vp, P(i64), P(vp), i32, vp, P(vp), i32, vp]
+        L.tt_eval_plan_backward.restype = ctypes.c_int
+        L.tt_eval_plan_free.argtypes = [vp]
+        L.tt_eval_plan_free.restype = None
         L.tt_status_string.argtypes = [ctypes.c_int]
         L.tt_status_string.restype = ctypes.c_char_p
         L.tt_last_error.argtypes = []

@@ -13,6 +13,7 @@
 // registers from LDS-staged rows.  Chunk partials are summed in a fixed order, so
 // the gradient is bitwise reproducible.
 #include <algorithm>
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -175,15 +176,14 @@ __global__ __launch_bounds__(NT) void k_zero(T* __restrict__ p, int64_t n) {
   if (e < n) p[e] = T(0);
 }
 
-tt_status check_args(int32_t d, const int64_t* dims, const int64_t* ranks, const void* const* cores, int32_t dtype,
-                     int64_t m, const int32_t* idx, EvalDesc& ed) {
+tt_status check_core_args(int32_t d, const int64_t* dims, const int64_t* ranks, const void* const* cores,
+                          int32_t dtype, EvalDesc& ed) {
   auto bad = [](const char* why) {
     set_last_error(why);
     return TT_ERR_ARG;
   };
   if (d < 1 || d > TT_MAX_D) return bad("d must be in [1, TT_MAX_D]");
   if (!dims || !ranks || !cores) return bad("dims, ranks and cores must not be NULL");
-  if (m < 0 || (m > 0 && !idx)) return bad("m must be >= 0 and idx non-NULL when m > 0");
   if (dtype != TT_DTYPE_F64 && dtype != TT_DTYPE_F32) return bad("unknown dtype");
   if (ranks[0] != 1 || ranks[d] != 1) return bad("ranks[0] and ranks[d] must be 1");
   ed = EvalDesc{};
@@ -206,6 +206,15 @@ tt_status check_args(int32_t d, const int64_t* dims, const int64_t* ranks, const
   }
   ed.lsum = ed.rsum = lo;
   return TT_OK;
+}
+
+tt_status check_args(int32_t d, const int64_t* dims, const int64_t* ranks, const void* const* cores, int32_t dtype,
+                     int64_t m, const int32_t* idx, EvalDesc& ed) {
+  if (m < 0 || (m > 0 && !idx)) {
+    set_last_error("m must be >= 0 and idx non-NULL when m > 0");
+    return TT_ERR_ARG;
+  }
+  return check_core_args(d, dims, ranks, cores, dtype, ed);
 }
 
 int max_rank_of(const EvalDesc& ed) {
@@ -827,8 +836,10 @@ bool trie_possible(const EvalDesc& ed) {
 
 // Sorts the entries and builds the node arrays of every depth.  Returns false on a
 // coordinate out of range.
-bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, Allocator* al, Trie& tr,
-                hipStream_t s) {
+// The arrays the trie keeps come from `mem`, temporaries from `scratch` (which may
+// be the same object).
+bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, DevMem& scratch, Allocator* al,
+                Trie& tr, hipStream_t s) {
   const int d = ed.d;
   TrieGeom g{};
   g.d = d;
@@ -842,12 +853,12 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
     total += b;
   }
   tr.m = m;
-  uint64_t* key = mem.get<uint64_t>(m);
+  uint64_t* key = scratch.get<uint64_t>(m);
   uint64_t* val = mem.get<uint64_t>(m);
-  uint64_t* kt = mem.get<uint64_t>(m);
+  uint64_t* kt = scratch.get<uint64_t>(m);
   uint64_t* vt = mem.get<uint64_t>(m);
   // counts[0]: index error flag; counts[t]: nodes at depth t (read back once, at the end)
-  uint32_t* counts = mem.get<uint32_t>(d + 1);
+  uint32_t* counts = scratch.get<uint32_t>(d + 1);
   TTS_HIP(hipMemsetAsync(counts, 0, sizeof(uint32_t) * (d + 1), s));
   k_tri_keys<<<grid_for(m, NT), NT, 0, s>>>(idx, m, g, key, val, counts);
   TTS_LAUNCH_CHECK();
@@ -859,8 +870,8 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
     std::swap(val, vt);
   }
   tr.perm = val;
-  uint32_t* flag = mem.get<uint32_t>(m);
-  uint32_t* pos = mem.get<uint32_t>(m);
+  uint32_t* flag = scratch.get<uint32_t>(m);
+  uint32_t* pos = scratch.get<uint32_t>(m);
   uint32_t* ida = mem.get<uint32_t>(m);
   uint32_t* idb = mem.get<uint32_t>(m);
   tr.P.assign(d + 1, 1);
@@ -895,14 +906,14 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
 }
 
 // Buckets of the depth-t nodes by their last index (stable radix sort).
-void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, hipStream_t s) {
+void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, DevMem& scratch, Allocator* al, hipStream_t s) {
   const int d = ed.d;
   tr.bperm.assign(d + 1, nullptr);
   tr.boff.assign(d + 1, nullptr);
   tr.bmax.assign(d + 1, 0);
   const int64_t pmax = *std::max_element(tr.P.begin(), tr.P.end());
-  uint64_t* key = mem.get<uint64_t>(pmax);
-  uint64_t* kt = mem.get<uint64_t>(pmax);
+  uint64_t* key = scratch.get<uint64_t>(pmax);
+  uint64_t* kt = scratch.get<uint64_t>(pmax);
   uint64_t* vt = mem.get<uint64_t>(pmax);
   std::vector<std::vector<int64_t>> hoff(d + 1);
   for (int t = 1; t <= d; ++t) {
@@ -953,7 +964,7 @@ void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int
 template <typename T>
 void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std::vector<T*>& Lv, hipStream_t s) {
   const int d = ed.d;
-  if (tr.bperm.empty()) build_buckets(ed, tr, mem, al, s);
+  if (tr.bperm.empty()) build_buckets(ed, tr, mem, mem, al, s);
   Lv.assign(d + 1, nullptr);
   Lv[0] = mem.get<T>(1);
   k_one<T><<<1, 1, 0, s>>>(Lv[0]);
@@ -986,7 +997,7 @@ tt_status trie_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, T* y, hip
   Allocator al;
   al.stream = s;
   Trie tr;
-  if (!build_trie(ed, m, idx, mem, &al, tr, s)) {
+  if (!build_trie(ed, m, idx, mem, mem, &al, tr, s)) {
     set_last_error("a coordinate is outside its mode range");
     return TT_ERR_INDEX;
   }
@@ -998,20 +1009,13 @@ tt_status trie_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, T* y, hip
   return TT_OK;
 }
 
+// Up vectors (bottom-up) and the gradient of every core, from the left products of
+// trie_forward.
 template <typename T>
-tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
-                    hipStream_t s) {
-  DevMem mem(s);
-  Allocator al;
-  al.stream = s;
+void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv, const T* gy, void* const* grads,
+                   DevMem& mem, hipStream_t s) {
   const int d = ed.d;
-  Trie tr;
-  if (!build_trie(ed, m, idx, mem, &al, tr, s)) {
-    set_last_error("a coordinate is outside its mode range");
-    return TT_ERR_INDEX;
-  }
-  std::vector<T*> Lv;
-  trie_forward<T>(ed, tr, mem, &al, Lv, s);
+  const int64_t m = tr.m;
   // up vectors, bottom-up
   std::vector<T*> Uv(d + 1, nullptr);
   Uv[d] = mem.get<T>(tr.P[d]);
@@ -1082,13 +1086,31 @@ tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
     k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, static_cast<T*>(grads[t]));
     TTS_LAUNCH_CHECK();
   }
+}
+
+template <typename T>
+tt_status trie_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
+                    hipStream_t s) {
+  DevMem mem(s);
+  Allocator al;
+  al.stream = s;
+  Trie tr;
+  if (!build_trie(ed, m, idx, mem, mem, &al, tr, s)) {
+    set_last_error("a coordinate is outside its mode range");
+    return TT_ERR_INDEX;
+  }
+  std::vector<T*> Lv;
+  trie_forward<T>(ed, tr, mem, &al, Lv, s);
+  trie_backward<T>(ed, tr, Lv, gy, grads, mem, s);
   TTS_HIP(hipStreamSynchronize(s));
   return TT_OK;
 }
 
+bool trie_usable(const EvalDesc& ed, int64_t m) { return m > 0 && m < (int64_t(1) << 31) && trie_possible(ed); }
+
+// Entry-by-entry evaluation (no trie): the fallback for coordinates too wide to pack.
 template <typename T>
-tt_status eval_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_out, hipStream_t s) {
-  if (m > 0 && m < (int64_t(1) << 31) && trie_possible(ed)) return trie_eval<T>(ed, m, idx, static_cast<T*>(y_out), s);
+tt_status direct_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_out, hipStream_t s) {
   DevMem mem(s);
   uint32_t* err = mem.get<uint32_t>(1);
   TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
@@ -1104,9 +1126,8 @@ tt_status eval_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_o
 }
 
 template <typename T>
-tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
-                    hipStream_t s) {
-  if (m > 0 && m < (int64_t(1) << 31) && trie_possible(ed)) return trie_grad<T>(ed, m, idx, gy, grads, s);
+tt_status direct_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
+                      hipStream_t s) {
   DevMem mem(s);
   Allocator al;
   al.stream = s;
@@ -1174,6 +1195,28 @@ tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* 
   return TT_OK;
 }
 
+template <typename T>
+tt_status eval_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y_out, hipStream_t s) {
+  if (trie_usable(ed, m)) return trie_eval<T>(ed, m, idx, static_cast<T*>(y_out), s);
+  return direct_eval<T>(ed, m, idx, y_out, s);
+}
+
+template <typename T>
+tt_status grad_impl(const EvalDesc& ed, int64_t m, const int32_t* idx, const T* gy, void* const* grads,
+                    hipStream_t s) {
+  if (trie_usable(ed, m)) return trie_grad<T>(ed, m, idx, gy, grads, s);
+  return direct_grad<T>(ed, m, idx, gy, grads, s);
+}
+
+__global__ __launch_bounds__(NT) void k_check_coords(const int32_t* __restrict__ idx, int64_t m, EvalDesc ed,
+                                                     uint32_t* __restrict__ err) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= m * ed.d) return;
+  const int k = static_cast<int>(e % ed.d);
+  const int32_t c = idx[e];
+  if (c < 0 || c >= ed.n[k]) *err = 1u;
+}
+
 }  // namespace
 }  // namespace tts
 
@@ -1222,3 +1265,197 @@ extern "C" tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, co
     return e.code;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Evaluation plans: the trie (or, for coordinates too wide to pack, a copy of the
+// coordinates) is built once and serves any number of forward and backward calls;
+// a forward may keep its left products for the backward that follows.
+// ---------------------------------------------------------------------------
+struct tt_eval_plan_s {
+  int32_t d = 0;
+  int64_t dims[TT_MAX_D] = {};
+  int64_t m = 0;
+  bool trie = false;
+  tts::DevMem mem;                 // trie arrays, or the copy of the coordinates
+  tts::Trie tr;
+  const int32_t* idx = nullptr;    // direct path: the plan's copy of the coordinates
+  std::unique_ptr<tts::DevMem> saved;  // left products of the last saving forward
+  std::vector<void*> Lv;
+  int32_t saved_dtype = -1;
+  int64_t saved_ranks[TT_MAX_D + 1] = {};
+  explicit tt_eval_plan_s(hipStream_t s) : mem(s) {}
+};
+
+namespace tts {
+namespace {
+
+template <typename T>
+tt_status plan_forward(tt_eval_plan_s& p, const EvalDesc& ed, T* y, bool save, hipStream_t s) {
+  if (!p.trie) return direct_eval<T>(ed, p.m, p.idx, y, s);
+  auto mem = std::make_unique<DevMem>(s);
+  Allocator al;
+  al.stream = s;
+  std::vector<T*> Lv;
+  trie_forward<T>(ed, p.tr, *mem, &al, Lv, s);
+  k_tri_out<T><<<grid_for(p.m, NT), NT, 0, s>>>(p.m, p.tr.leaf, p.tr.perm, Lv[ed.d], y);
+  TTS_LAUNCH_CHECK();
+  TTS_HIP(hipStreamSynchronize(s));
+  if (save) {
+    p.saved = std::move(mem);
+    p.Lv.assign(Lv.begin(), Lv.end());
+  }
+  return TT_OK;
+}
+
+template <typename T>
+tt_status plan_backward(tt_eval_plan_s& p, const EvalDesc& ed, const T* gy, void* const* grads, bool use_saved,
+                        hipStream_t s) {
+  if (!p.trie) return direct_grad<T>(ed, p.m, p.idx, gy, grads, s);
+  DevMem mem(s);
+  std::vector<T*> Lv;
+  if (use_saved) {
+    for (void* v : p.Lv) Lv.push_back(static_cast<T*>(v));
+  } else {
+    Allocator al;
+    al.stream = s;
+    trie_forward<T>(ed, p.tr, mem, &al, Lv, s);
+  }
+  trie_backward<T>(ed, p.tr, Lv, gy, grads, mem, s);
+  TTS_HIP(hipStreamSynchronize(s));
+  return TT_OK;
+}
+
+}  // namespace
+}  // namespace tts
+
+extern "C" tt_status tt_eval_plan_create(int32_t d, const int64_t* dims, int64_t m, const int32_t* idx, void* stream,
+                                         tt_eval_plan* plan) {
+  auto bad = [](const char* why) {
+    set_last_error(why);
+    return TT_ERR_ARG;
+  };
+  if (!plan) return bad("plan must not be NULL");
+  *plan = nullptr;
+  if (d < 1 || d > TT_MAX_D) return bad("d must be in [1, TT_MAX_D]");
+  if (!dims) return bad("dims must not be NULL");
+  if (m < 0 || (m > 0 && !idx)) return bad("m must be >= 0 and idx non-NULL when m > 0");
+  EvalDesc ed{};
+  ed.d = d;
+  for (int k = 0; k < d; ++k) {
+    if (dims[k] < 1 || dims[k] > INT32_MAX) return bad("every mode size must be in [1, 2^31 - 1]");
+    ed.n[k] = static_cast<int32_t>(dims[k]);
+  }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto p = std::make_unique<tt_eval_plan_s>(s);
+    p->d = d;
+    for (int k = 0; k < d; ++k) p->dims[k] = dims[k];
+    p->m = m;
+    p->trie = trie_usable(ed, m);
+    if (p->trie) {
+      DevMem scratch(s);
+      Allocator al;
+      al.stream = s;
+      if (!build_trie(ed, m, idx, p->mem, scratch, &al, p->tr, s)) {
+        set_last_error("a coordinate is outside its mode range");
+        return TT_ERR_INDEX;
+      }
+      build_buckets(ed, p->tr, p->mem, scratch, &al, s);
+    } else if (m > 0) {
+      int32_t* c = p->mem.get<int32_t>(static_cast<size_t>(m) * d);
+      TTS_HIP(hipMemcpyAsync(c, idx, sizeof(int32_t) * static_cast<size_t>(m) * d, hipMemcpyDeviceToDevice, s));
+      DevMem scratch(s);
+      uint32_t* err = scratch.get<uint32_t>(1);
+      TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
+      k_check_coords<<<grid_for(m * d, NT), NT, 0, s>>>(c, m, ed, err);
+      TTS_LAUNCH_CHECK();
+      uint32_t h = 0;
+      TTS_HIP(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
+      TTS_HIP(hipStreamSynchronize(s));
+      if (h) {
+        set_last_error("a coordinate is outside its mode range");
+        return TT_ERR_INDEX;
+      }
+      p->idx = c;
+    }
+    TTS_HIP(hipStreamSynchronize(s));
+    *plan = p.release();
+    return TT_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+extern "C" tt_status tt_eval_plan_forward(tt_eval_plan plan, const int64_t* ranks, const void* const* cores,
+                                          int32_t dtype, void* y_out, int32_t save, void* stream) {
+  if (!plan) {
+    set_last_error("plan must not be NULL");
+    return TT_ERR_ARG;
+  }
+  EvalDesc ed;
+  tt_status st = check_core_args(plan->d, plan->dims, ranks, cores, dtype, ed);
+  if (st != TT_OK) return st;
+  if (plan->m > 0 && !y_out) {
+    set_last_error("y_out must not be NULL when m > 0");
+    return TT_ERR_ARG;
+  }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (save) {
+      plan->saved.reset();
+      plan->Lv.clear();
+      plan->saved_dtype = -1;
+    }
+    st = dtype == TT_DTYPE_F64 ? plan_forward<double>(*plan, ed, static_cast<double*>(y_out), save != 0, s)
+                               : plan_forward<float>(*plan, ed, static_cast<float*>(y_out), save != 0, s);
+    if (st == TT_OK && save) {
+      plan->saved_dtype = dtype;
+      for (int k = 0; k <= plan->d; ++k) plan->saved_ranks[k] = ranks[k];
+    }
+    return st;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+extern "C" tt_status tt_eval_plan_backward(tt_eval_plan plan, const int64_t* ranks, const void* const* cores,
+                                           int32_t dtype, const void* grad_y, void* const* grad_cores,
+                                           int32_t use_saved, void* stream) {
+  if (!plan) {
+    set_last_error("plan must not be NULL");
+    return TT_ERR_ARG;
+  }
+  EvalDesc ed;
+  tt_status st = check_core_args(plan->d, plan->dims, ranks, cores, dtype, ed);
+  if (st != TT_OK) return st;
+  if ((plan->m > 0 && !grad_y) || !grad_cores) {
+    set_last_error("grad_y (when m > 0) and grad_cores must not be NULL");
+    return TT_ERR_ARG;
+  }
+  for (int k = 0; k < plan->d; ++k)
+    if (!grad_cores[k]) {
+      set_last_error("a gradient core pointer is NULL");
+      return TT_ERR_ARG;
+    }
+  if (use_saved) {
+    bool same = plan->saved_dtype == dtype;
+    for (int k = 0; same && k <= plan->d; ++k) same = plan->saved_ranks[k] == ranks[k];
+    if (!same) {
+      set_last_error("use_saved needs a saving forward with the same ranks and dtype");
+      return TT_ERR_ARG;
+    }
+  }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dtype == TT_DTYPE_F64
+               ? plan_backward<double>(*plan, ed, static_cast<const double*>(grad_y), grad_cores, use_saved != 0, s)
+               : plan_backward<float>(*plan, ed, static_cast<const float*>(grad_y), grad_cores, use_saved != 0, s);
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
+
+extern "C" void tt_eval_plan_free(tt_eval_plan plan) { delete plan; }

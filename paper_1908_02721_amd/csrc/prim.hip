@@ -1,12 +1,13 @@
 // Device-wide exclusive scan and stable LSD radix sort, hand-written for gfx950.
 //
 // Radix sort: 8-bit digits, one pass per digit, three kernels per pass:
-//   k_rs_hist    -- per-tile digit histogram (wave-aggregated with a ballot match,
-//                   one LDS histogram per wave), written digit-major.
-//   scan         -- exclusive scan of the digit-major counts = global offsets.
-//   k_rs_scatter -- stable per-tile ranking (ballot match inside each wave, wave
-//                   prefix over the tile), staging through LDS so that the global
-//                   writes of one digit run are contiguous.
+//   k_rs_hist      -- per-tile digit histogram (LDS atomics), written digit-major.
+//   k_rs_scan_rows -- exclusive scan of each digit's row of tile counts, plus the
+//                     digit totals.
+//   k_rs_scatter   -- stable per-tile ranking (ballot match inside each wave, wave
+//                     prefix over the tile), staging through LDS so that the global
+//                     writes of one digit run are contiguous.
+// A single tile needs only the scatter: its own offsets are the global ones.
 // No inter-block waiting anywhere: every kernel only reads what earlier launches
 // wrote.
 #include "prim.hpp"
@@ -19,16 +20,42 @@ constexpr int SCAN_NT = 256;
 constexpr int SCAN_IPT = 8;
 constexpr int SCAN_TILE = SCAN_NT * SCAN_IPT;
 
+// A thread's SCAN_IPT = 8 consecutive words: two 16-byte loads when the buffer is
+// 16-byte aligned and the run is whole, guarded word loads otherwise.
+__device__ __forceinline__ void load_run8(const uint32_t* in, size_t j, uint32_t n, bool vec, uint32_t v[8]) {
+  if (vec && j + 8 <= n) {
+    const uint4 a = *reinterpret_cast<const uint4*>(in + j);
+    const uint4 b = *reinterpret_cast<const uint4*>(in + j + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (j + i < n) ? in[j + i] : 0u;
+  }
+}
+
+__device__ __forceinline__ void store_run8(uint32_t* out, size_t j, uint32_t n, bool vec, const uint32_t v[8]) {
+  if (vec && j + 8 <= n) {
+    *reinterpret_cast<uint4*>(out + j) = make_uint4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<uint4*>(out + j + 4) = make_uint4(v[4], v[5], v[6], v[7]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (j + i < n) out[j + i] = v[i];
+  }
+}
+
+static_assert(SCAN_IPT == 8, "the run loads assume eight words per thread");
+
 __global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n,
-                                                         uint32_t* __restrict__ part) {
+                                                         uint32_t* __restrict__ part, int vec) {
   __shared__ uint32_t lds[SCAN_NT / 64];
   const size_t base = static_cast<size_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_IPT;
+  uint32_t v[SCAN_IPT];
+  load_run8(in, base, n, vec != 0, v);
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) {
-    const size_t j = base + i;
-    if (j < n) s += in[j];
-  }
+  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
   uint32_t tot;
   block_excl_scan_u32<SCAN_NT>(s, lds, &tot);
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
@@ -49,26 +76,47 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t* __restrict__ p
   if (threadIdx.x == 0 && d_total) *d_total = carry;
 }
 
+// Second pass.  With `fused`, part[] holds the raw tile sums (at most FUSED_TILES of
+// them) and each tile adds up the sums before it itself; the last tile writes the
+// total.  Otherwise part[] already holds the exclusive prefixes.
+constexpr uint32_t FUSED_TILES = 4096;
 __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* in, uint32_t* out, uint32_t n,
-                                                        const uint32_t* __restrict__ part) {
+                                                        const uint32_t* __restrict__ part, int fused,
+                                                        uint32_t* __restrict__ d_total, int vin, int vout) {
   __shared__ uint32_t lds[SCAN_NT / 64];
   const size_t base = static_cast<size_t>(blockIdx.x) * SCAN_TILE + threadIdx.x * SCAN_IPT;
   uint32_t v[SCAN_IPT];
+  load_run8(in, base, n, vin != 0, v);
+  uint32_t prefix;
+  if (fused) {
+    constexpr int R = FUSED_TILES / SCAN_NT;
+    uint32_t q[R];
+    const uint32_t b = blockIdx.x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t j = threadIdx.x + r * SCAN_NT;
+      q[r] = part[j < b ? j : 0u];
+    }
+    uint32_t p = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) p += (threadIdx.x + r * SCAN_NT < b) ? q[r] : 0u;
+    block_excl_scan_u32<SCAN_NT>(p, lds, &prefix);
+  } else {
+    prefix = part[blockIdx.x];
+  }
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) {
-    const size_t j = base + i;
-    v[i] = (j < n) ? in[j] : 0u;
-    s += v[i];
-  }
+  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
   uint32_t tot;
-  uint32_t run = block_excl_scan_u32<SCAN_NT>(s, lds, &tot) + part[blockIdx.x];
+  uint32_t run = block_excl_scan_u32<SCAN_NT>(s, lds, &tot) + prefix;
 #pragma unroll
   for (int i = 0; i < SCAN_IPT; ++i) {
-    const size_t j = base + i;
-    if (j < n) out[j] = run;
-    run += v[i];
+    const uint32_t x = v[i];
+    v[i] = run;
+    run += x;
   }
+  store_run8(out, base, n, vout != 0, v);
+  if (fused && d_total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *d_total = prefix + tot;
 }
 
 // ----------------------------------------------------------------------------
@@ -90,34 +138,62 @@ __device__ __forceinline__ uint64_t match_digit(unsigned dig) {
   return m;
 }
 
+// Per-tile digit histogram: LDS atomic adds (integer counts, so the order of the adds
+// does not matter), all of a thread's keys loaded before any add.  Written digit-major.
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
                                                    uint32_t* __restrict__ counts, uint32_t ntiles) {
-  __shared__ uint32_t h[RS_NW][256];
-  for (int i = threadIdx.x; i < RS_NW * 256; i += RS_NT) (&h[0][0])[i] = 0;
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
   __syncthreads();
-  const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const size_t base = static_cast<size_t>(blockIdx.x) * RS_TILE + static_cast<size_t>(w) * 64 * RS_IPT;
-  for (int r = 0; r < RS_IPT; ++r) {
-    const size_t i = base + static_cast<size_t>(r) * 64 + lane;
-    const bool valid = i < n;
-    const unsigned dig = valid ? static_cast<unsigned>((keys[i] >> shift) & 255u) : 0u;
-    const uint64_t peers = match_digit(dig) & __ballot(valid);
-    if (valid && (peers & lanemask_lt()) == 0) h[w][dig] += static_cast<uint32_t>(__popcll(peers));
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  const unsigned t = threadIdx.x;
-  uint32_t c = 0;
+  const size_t base = static_cast<size_t>(blockIdx.x) * RS_TILE;
+  unsigned dig[RS_IPT];
 #pragma unroll
-  for (int ww = 0; ww < RS_NW; ++ww) c += h[ww][t];
-  counts[static_cast<size_t>(t) * ntiles + blockIdx.x] = c;
+  for (int r = 0; r < RS_IPT; ++r) {
+    const size_t i = base + static_cast<size_t>(r) * RS_NT + threadIdx.x;
+    dig[r] = (i < n) ? static_cast<unsigned>((keys[i] >> shift) & 255u) : 256u;
+  }
+#pragma unroll
+  for (int r = 0; r < RS_IPT; ++r)
+    if (dig[r] < 256u) atomicAdd(&h[dig[r]], 1u);
+  __syncthreads();
+  counts[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of one digit's row of per-tile counts (one workgroup per digit),
+// in place; the row total goes to dtot[digit].  The scatter adds the exclusive scan
+// of the 256 digit totals itself.
+__global__ __launch_bounds__(RS_NT) void k_rs_scan_rows(uint32_t* __restrict__ counts, uint32_t ntiles,
+                                                        uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t lds[RS_NW];
+  constexpr int IPT = 4;
+  uint32_t* row = counts + static_cast<size_t>(blockIdx.x) * ntiles;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < ntiles; base += RS_NT * IPT) {
+    const uint32_t j0 = base + threadIdx.x * IPT;
+    uint32_t v[IPT], s = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      v[i] = (j0 + i < ntiles) ? row[j0 + i] : 0u;
+      s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_excl_scan_u32<RS_NT>(s, lds, &tot);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      if (j0 + i < ntiles) row[j0 + i] = run;
+      run += v[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                       const uint64_t* __restrict__ vin,
                                                       uint64_t* __restrict__ kout,
                                                       uint64_t* __restrict__ vout, uint32_t n, int shift,
-                                                      const uint32_t* __restrict__ offs, uint32_t ntiles) {
+                                                      const uint32_t* __restrict__ offs,
+                                                      const uint32_t* __restrict__ dtot, uint32_t ntiles) {
   __shared__ uint32_t wcnt[RS_NW][256];
   __shared__ uint32_t toff[256];
   __shared__ uint32_t goff[256];
@@ -126,7 +202,14 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict
   __shared__ uint8_t sdig[RS_TILE];
 
   for (int i = threadIdx.x; i < RS_NW * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
-  goff[threadIdx.x] = offs[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x];
+  // global offset of this tile's run of each digit; a single tile (offs == nullptr)
+  // takes its own tile offsets, set below
+  uint32_t gbase = 0;
+  if (offs) {
+    uint32_t all;
+    gbase = block_excl_scan_u32<RS_NT>(dtot[threadIdx.x], scan_lds, &all) +
+            offs[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x];
+  }
   __syncthreads();
 
   const unsigned w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -165,7 +248,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict
       s += c;
     }
     uint32_t tot;
-    toff[t] = block_excl_scan_u32<RS_NT>(s, scan_lds, &tot);
+    const uint32_t to = block_excl_scan_u32<RS_NT>(s, scan_lds, &tot);
+    toff[t] = to;
+    goff[t] = offs ? gbase : to;
   }
   __syncthreads();
 #pragma unroll
@@ -281,11 +366,16 @@ void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32
   }
   const uint32_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   DBuf<uint32_t> part(al, nb);
-  k_scan_reduce<<<nb, SCAN_NT, 0, s>>>(in, n, part.get());
+  const int vin = (reinterpret_cast<uintptr_t>(in) & 15u) == 0;
+  const int vout = (reinterpret_cast<uintptr_t>(out) & 15u) == 0;
+  k_scan_reduce<<<nb, SCAN_NT, 0, s>>>(in, n, part.get(), vin);
   TTS_LAUNCH_CHECK();
-  k_scan_partials<<<1, 1024, 0, s>>>(part.get(), nb, d_total);
-  TTS_LAUNCH_CHECK();
-  k_scan_apply<<<nb, SCAN_NT, 0, s>>>(in, out, n, part.get());
+  const int fused = nb <= FUSED_TILES;
+  if (!fused) {
+    k_scan_partials<<<1, 1024, 0, s>>>(part.get(), nb, d_total);
+    TTS_LAUNCH_CHECK();
+  }
+  k_scan_apply<<<nb, SCAN_NT, 0, s>>>(in, out, n, part.get(), fused, d_total, vin, vout);
   TTS_LAUNCH_CHECK();
 }
 
@@ -300,17 +390,22 @@ bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t
   }
   const uint32_t ntiles = (n + RS_TILE - 1) / RS_TILE;
   const int passes = (nbits + 7) / 8;
-  DBuf<uint32_t> counts(al, static_cast<size_t>(256) * ntiles);
+  DBuf<uint32_t> counts(al, ntiles > 1 ? static_cast<size_t>(256) * ntiles + 256 : 1);
+  uint32_t* dtot = counts.get() + static_cast<size_t>(256) * ntiles;
   uint64_t *ki = keys, *vi = vals, *ko = ktmp, *vo = vtmp;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, counts.get(), ntiles);
-    TTS_LAUNCH_CHECK();
-    exclusive_scan_u32(al, counts.get(), counts.get(), 256u * ntiles, nullptr, s);
+    if (ntiles > 1) {
+      k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ki, n, shift, counts.get(), ntiles);
+      TTS_LAUNCH_CHECK();
+      k_rs_scan_rows<<<256, RS_NT, 0, s>>>(counts.get(), ntiles, dtot);
+      TTS_LAUNCH_CHECK();
+    }
     {
       // algorithmic bytes of one pass: read and write every (key, value) pair once
       KTimer kt("sort_scatter", s, 32.0 * n, 0.0);
-      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, counts.get(), ntiles);
+      k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ki, vi, ko, vo, n, shift, ntiles > 1 ? counts.get() : nullptr,
+                                            ntiles > 1 ? dtot : nullptr, ntiles);
       TTS_LAUNCH_CHECK();
     }
     std::swap(ki, ko);

@@ -116,3 +116,27 @@ def test_eval_host_argument_errors(lib):
     for call, word in cases:
         assert call() == 1
         assert word in lib.tt_last_error().decode(), lib.tt_last_error()
+
+
+def test_eval_plan_host_argument_errors(lib):
+    """The plan calls check their arguments on the host before any device work."""
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    d = 2
+    dims = (ctypes.c_int64 * d)(4, 4)
+    plan = ctypes.c_void_p()
+    assert lib.tt_eval_plan_create(d, dims, 4, fake, None, None) == 1
+    assert "plan" in lib.tt_last_error().decode()
+    assert lib.tt_eval_plan_create(0, dims, 4, fake, None, ctypes.byref(plan)) == 1
+    assert "d must" in lib.tt_last_error().decode()
+    assert plan.value is None
+    assert lib.tt_eval_plan_create(d, dims, -1, fake, None, ctypes.byref(plan)) == 1
+    assert "m must" in lib.tt_last_error().decode()
+    assert lib.tt_eval_plan_create(d, dims, 4, None, None, ctypes.byref(plan)) == 1
+    bad = (ctypes.c_int64 * d)(4, 0)
+    assert lib.tt_eval_plan_create(d, bad, 4, fake, None, ctypes.byref(plan)) == 1
+    assert "mode size" in lib.tt_last_error().decode()
+    ranks = (ctypes.c_int64 * (d + 1))(1, 3, 1)
+    cores = (ctypes.c_void_p * d)(fake, fake)
+    assert lib.tt_eval_plan_forward(None, ranks, cores, 0, fake, 1, None) == 1
+    assert lib.tt_eval_plan_backward(None, ranks, cores, 0, fake, cores, 1, None) == 1
+    lib.tt_eval_plan_free(None)

@@ -162,3 +162,88 @@ def test_repeated_and_shared_prefix_coordinates(oracle_mod):
     g = tts.eval_entries_backward(_cuda(cores, torch.float64), gi, torch.from_numpy(gy).cuda())
     for a, b in zip(g, oracle_mod.eval_grad(cores, idx, gy)):
         assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-11 * max(1.0, np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name,dims,ranks,m", CFGS)
+def test_plan_matches_one_shot_calls(oracle_mod, name, dims, ranks, m):
+    """An EvalPlan gives bit-for-bit the results of the one-shot calls (same kernels,
+    same order), whether the backward reuses the kept left products or recomputes
+    them, over repeated calls and in both precisions."""
+    tts = _tts()
+    print(f"[eval plan] {name}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(100 + len(name)))
+    cores = _rand_tt(rng, dims, ranks)
+    idx = _idx(rng, dims, m)
+    gy = rng.standard_normal(m)
+    gi = torch.from_numpy(idx).cuda()
+    plan = tts.EvalPlan(gi, dims)
+    for dtype in (torch.float64, torch.float32):
+        cs = _cuda(cores, dtype)
+        g = torch.from_numpy(gy).to(dtype).cuda()
+        y1 = tts.eval_entries(cs, gi)
+        gr1 = tts.eval_entries_backward(cs, gi, g)
+        for _ in range(2):
+            y = plan.forward(cs, save=True)
+            assert torch.equal(y, y1)
+            for use_saved in (True, False, True):
+                gr = plan.backward(cs, g, use_saved=use_saved)
+                for a, b in zip(gr, gr1):
+                    assert torch.equal(a, b)
+        if dtype == torch.float64:
+            ref = oracle_mod.eval_entries(cores, idx)
+            assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+            for a, b in zip(gr, oracle_mod.eval_grad(cores, idx, gy)):
+                assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-11 * max(1.0, np.max(np.abs(b)))
+
+
+def test_plan_wide_coordinates_and_errors(oracle_mod):
+    """Coordinates too wide to pack into one 64-bit key (8 modes of 300) take the
+    entry-by-entry path inside the plan; errors of the plan calls."""
+    tts = _tts()
+    rng = np.random.Generator(np.random.PCG64(11))
+    dims, ranks = (300,) * 8, (4, 6, 5, 7, 3, 5, 4)
+    cores = _rand_tt(rng, dims, ranks)
+    idx = _idx(rng, dims, 3000)
+    gy = rng.standard_normal(3000)
+    gi = torch.from_numpy(idx).cuda()
+    plan = tts.EvalPlan(gi, dims)
+    del gi  # the plan keeps its own copy
+    cs = _cuda(cores, torch.float64)
+    y = plan.forward(cs, save=True).cpu().numpy()
+    assert np.max(np.abs(y - oracle_mod.eval_entries(cores, idx))) <= 1e-12 * max(1.0, np.max(np.abs(y)))
+    g = plan.backward(cs, torch.from_numpy(gy).cuda(), use_saved=True)
+    for a, b in zip(g, oracle_mod.eval_grad(cores, idx, gy)):
+        assert np.max(np.abs(a.cpu().numpy() - b)) <= 1e-11 * max(1.0, np.max(np.abs(b)))
+    # use_saved after a saving forward of another dtype is refused
+    plan.forward(_cuda(cores, torch.float32), save=True)
+    with pytest.raises(tts.TTError) as e:
+        plan.backward(cs, torch.from_numpy(gy).cuda(), use_saved=True)
+    assert e.value.status == "TT_ERR_ARG"
+
+    # packed-key path: errors
+    dims2, ranks2 = (9, 8, 7), (3, 4)
+    cores2 = _cuda(_rand_tt(rng, dims2, ranks2), torch.float64)
+    idx2 = torch.from_numpy(_idx(rng, dims2, 500)).cuda()
+    p2 = tts.EvalPlan(idx2, dims2)
+    gy2 = torch.randn(500, dtype=torch.float64, device="cuda")
+    with pytest.raises(tts.TTError) as e:
+        p2.backward(cores2, gy2, use_saved=True)  # nothing kept yet
+    assert e.value.status == "TT_ERR_ARG"
+    p2.forward(cores2, save=False)
+    with pytest.raises(tts.TTError):
+        p2.backward(cores2, gy2, use_saved=True)  # that forward kept nothing
+    p2.forward(cores2, save=True)
+    other = _cuda(_rand_tt(rng, dims2, (2, 4)), torch.float64)
+    with pytest.raises(tts.TTError):
+        p2.backward(other, gy2, use_saved=True)  # other ranks
+    with pytest.raises(ValueError):
+        p2.forward(_cuda(_rand_tt(rng, (9, 8, 6), ranks2), torch.float64))
+    bad = idx2.clone()
+    bad[3, 2] = 7
+    with pytest.raises(tts.TTError) as e:
+        tts.EvalPlan(bad, dims2)
+    assert e.value.status == "TT_ERR_INDEX"
+    empty = tts.EvalPlan(idx2[:0], dims2)
+    assert empty.forward(cores2, save=True).numel() == 0
+    gz = empty.backward(cores2, gy2[:0], use_saved=True)
+    assert all(float(g.abs().max()) == 0.0 for g in gz)
