@@ -410,7 +410,66 @@ __device__ double block_sum_1024(double x, double* red) {
   return s;
 }
 
-// argmax with lowest index on ties
+// Lane moves within rows of 16 lanes (DPP, no LDS round trip).  quad_perm [1,0,3,2]
+// and [2,3,0,1] swap neighbours and pairs, row_half_mirror reverses each 8 lanes,
+// row_mirror each 16: applied in that order, each one combines aligned groups of
+// 2, 4, 8 and 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// Sum over an aligned group of G lanes (G = 1, 2, 4, 8 or 16); every lane gets it.
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
+  if (G >= 2) x += dpp_move<0xB1>(x);
+  if (G >= 4) x += dpp_move<0x4E>(x);
+  if (G >= 8) x += dpp_move<0x141>(x);
+  if (G >= 16) x += dpp_move<0x140>(x);
+  return x;
+}
+__device__ __forceinline__ double group8_sum(double x) { return group_sum<8>(x); }
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                          __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+// Largest v over the wave (NaN counts as -inf), and the lowest lane holding it.
+// Every lane of the wave must be active.
+__device__ __forceinline__ void wave_argmax_lane(double v, double* vmax, int* lane) {
+  v = (v == v) ? v : -HUGE_VAL;
+  double m = v;
+  m = fmax(m, dpp_move<0xB1>(m));
+  m = fmax(m, dpp_move<0x4E>(m));
+  m = fmax(m, dpp_move<0x141>(m));
+  m = fmax(m, dpp_move<0x140>(m));
+  m = fmax(fmax(readlane_f64(m, 0), readlane_f64(m, 16)), fmax(readlane_f64(m, 32), readlane_f64(m, 48)));
+  const uint64_t hit = __ballot(v == m);
+  *vmax = m;
+  *lane = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+}
+
+// Argmax over per-wave candidates (value, index) kept in LDS: lane i of the calling
+// wave reads candidate i; the largest value wins, the lowest index among equal
+// values.  Every lane of the wave gets the winner.
+template <int NW>
+__device__ __forceinline__ void slot_argmax(const double* sv, const int* si, double* pv, int* p) {
+  const int lane = threadIdx.x & 63;
+  const double v = (lane < NW) ? sv[lane] : -HUGE_VAL;
+  const int ix = (lane < NW) ? si[lane] : 0;
+  int wl;
+  wave_argmax_lane(v, pv, &wl);
+  const uint64_t hit = __ballot(v == *pv);
+  if (__popcll(hit) > 1) {
+    int c = (v == *pv) ? ix : INT_MAX;
+    for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o, 64));
+    *p = c;
+  } else {
+    *p = __builtin_amdgcn_readlane(ix, wl);
+  }
+}
+
 // Rotation (cs, sn) that makes two columns with squared norms a, b and inner
 // product g orthogonal (the smaller-angle Jacobi rotation, Rutishauser's formulas):
 // zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
@@ -496,6 +555,8 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
   __shared__ int redi[17];
   __shared__ double slotv[2][BT / 64];  // per-wave argmax candidates, double-buffered
   __shared__ int sloti[2][BT / 64];
+  constexpr int PIVS = 1024;             // pivots kept in LDS until the end
+  __shared__ int pivs[PIVS];
   double gmax = 0.0;
   for (int j = threadIdx.x; j < n; j += BT) {
     dg[j] = G[j + static_cast<size_t>(j) * ldg];
@@ -511,8 +572,9 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int r = 0;
   for (int t = 0; t < rmax; ++t) {
-    // argmax of the diagonal (largest value, lowest index on ties): wave reduction,
-    // one barrier, then every thread reduces the per-wave candidates itself
+    // argmax of the diagonal (largest value, lowest index on ties): each thread's own
+    // candidate, a DPP wave reduction, one barrier, then every thread reduces the
+    // per-wave candidates (in index order, so a tie keeps the lower index)
     double v = -1.0;
     int idx = n;
     for (int j = threadIdx.x; j < n; j += BT)
@@ -520,31 +582,35 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
         v = dg[j];
         idx = j;
       }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(v, o, 64);
-      const int oi = __shfl_xor(idx, o, 64);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
+    double wv;
+    int wl;
+    wave_argmax_lane(v, &wv, &wl);
+    const int widx = __builtin_amdgcn_readlane(idx, wl);
+    if (n > BT) {
+      // a lane may hold a later index than another lane with the same value
+      const uint64_t hit = __ballot(v == wv);
+      if (__popcll(hit) > 1) {
+        int c = (v == wv) ? idx : n;
+        for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o, 64));
+        if (lane == 0) sloti[t & 1][w] = c;
+      } else if (lane == 0) {
+        sloti[t & 1][w] = widx;
       }
+    } else if (lane == 0) {
+      sloti[t & 1][w] = widx;
     }
-    if (lane == 0) {
-      slotv[t & 1][w] = v;
-      sloti[t & 1][w] = idx;
-    }
+    if (lane == 0) slotv[t & 1][w] = wv;
     __syncthreads();
-    double pv = slotv[t & 1][0];
-    int p = sloti[t & 1][0];
-    for (int i = 1; i < BT / 64; ++i) {
-      const double cvv = slotv[t & 1][i];
-      const int cii = sloti[t & 1][i];
-      if (cvv > pv || (cvv == pv && cii < p)) {
-        pv = cvv;
-        p = cii;
-      }
-    }
+    double pv;
+    int p;
+    slot_argmax<BT / 64>(slotv[t & 1], sloti[t & 1], &pv, &p);
     if (!(pv > thr)) break;
-    if (threadIdx.x == 0) piv[t] = p;
+    if (threadIdx.x == 0) {
+      if (t < PIVS)
+        pivs[t] = p;
+      else
+        piv[t] = p;
+    }
     const double sq = sqrt(pv);
     const double inv = 1.0 / sq;
     for (int j0 = 0; j0 < n; j0 += JPB) {
@@ -577,9 +643,7 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
         }
         for (; l < t; l += LPJ) s0 = fma(Lj[static_cast<size_t>(l) * n], Lp[static_cast<size_t>(l) * n], s0);
       }
-      double acc = (s0 + s1) + (s2 + s3);
-#pragma unroll
-      for (int o = LPJ / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPJ);
+      const double acc = group_sum<LPJ>((s0 + s1) + (s2 + s3));
       if (sub == 0 && j < n) {
         double x;
         if (j == p) {
@@ -591,13 +655,133 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
           x = (gjp - acc) * inv;
           dg[j] = dg[j] - x * x;
         }
-        L[j + static_cast<size_t>(t) * n] = x;
-        if (t < tl) Lc[j + t * n] = x;
+        // columns kept in LDS go to memory after the loop, so that the barrier
+        // does not wait for their stores
+        if (t < tl)
+          Lc[j + t * n] = x;
+        else
+          L[j + static_cast<size_t>(t) * n] = x;
       }
     }
     __syncthreads();
     r = t + 1;
   }
+  for (int e = threadIdx.x; e < n * min(r, tl); e += BT) L[e] = Lc[e];
+  for (int e = threadIdx.x; e < min(r, PIVS); e += BT) piv[e] = pivs[e];
+  if (threadIdx.x == 0) *d_r = r;
+}
+
+// Left-looking pivoted Cholesky for n <= NREG * LPJ (at most 128) by NTH = n_max * LPJ
+// threads: the whole Gram matrix is staged in LDS once, and the LPJ lanes of column j
+// keep row j of L in registers (lane `sub` holds L[j, l] for l = sub (mod LPJ)).  A
+// step costs a DPP argmax, a barrier, the pivot's row of L published to LDS, a second
+// barrier, and a dot product over the t columns so far.  Same pivot rule, threshold
+// and output as k_pivoted_cholesky.
+template <int LPJ, int NREG, int NTH>
+__global__ __launch_bounds__(NTH) void k_pivchol_lds(const double* __restrict__ G, int n, int ldg, int rmax,
+                                                     double theta, double* __restrict__ L,
+                                                     int32_t* __restrict__ piv, int32_t* __restrict__ d_r) {
+  constexpr int NMAX = NREG * LPJ, NW = NTH / 64;
+  static_assert(NMAX * LPJ == NTH, "one lane group per column");
+  extern __shared__ double gs[];  // n x n, column-major
+  __shared__ double prow[NMAX];
+  __shared__ double slotv[2][NW];
+  __shared__ int sloti[2][NW];
+  __shared__ int pivs[NMAX];
+  {  // staging: a thread's loads are issued together (clamped addresses)
+    constexpr int PER = NMAX * NMAX / NTH;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + NTH * u, i = e % n, j = e / n;
+      v[u] = G[(j < n) ? i + static_cast<size_t>(j) * ldg : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + NTH * u;
+      if (e < n * n) gs[e] = v[u];
+    }
+  }
+  for (int e = threadIdx.x; e < NMAX; e += NTH) prow[e] = 0.0;
+  __syncthreads();
+  const int sub = threadIdx.x % LPJ, j = threadIdx.x / LPJ;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double dj = (j < n) ? gs[j + j * n] : -1.0;  // Schur diagonal of column j (-1 once pivoted)
+  double thr;
+  {  // threshold: theta times the largest diagonal entry of G
+    double wv;
+    int wl;
+    wave_argmax_lane(j < n ? dj : 0.0, &wv, &wl);
+    if (lane == 0) slotv[1][w] = wv;
+    __syncthreads();
+    double mv;
+    int unused;
+    slot_argmax<NW>(slotv[1], sloti[1], &mv, &unused);
+    thr = theta * mv;
+    __syncthreads();
+  }
+  double lr[NREG];
+#pragma unroll
+  for (int u = 0; u < NREG; ++u) lr[u] = 0.0;
+  int r = 0;
+  for (int t = 0; t < rmax; ++t) {
+    double wv;
+    int wl;
+    wave_argmax_lane(dj, &wv, &wl);
+    if (lane == 0) {
+      slotv[t & 1][w] = wv;
+      sloti[t & 1][w] = (w * 64 + wl) / LPJ;
+    }
+    __syncthreads();
+    double pv;
+    int p;
+    slot_argmax<NW>(slotv[t & 1], sloti[t & 1], &pv, &p);
+    if (!(pv > thr)) break;
+    if (threadIdx.x == 0) pivs[t] = p;
+    if (j == p) {
+#pragma unroll
+      for (int u = 0; u < NREG; ++u) prow[sub + u * LPJ] = lr[u];
+    }
+    __syncthreads();
+    const double sq = sqrt(pv);
+    const double inv = 1.0 / sq;
+    const double gjp = gs[min(j, n - 1) + p * n];
+    // sum over l < t of L[j, l] L[p, l]: this lane's terms l = sub + u LPJ, u < ul
+    const int ul = (t + LPJ - 1) / LPJ;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < NREG; u += 2) {
+      if (u < ul) s0 = fma(lr[u], prow[sub + u * LPJ], s0);
+      if (u + 1 < ul) s1 = fma(lr[u + 1], prow[sub + (u + 1) * LPJ], s1);
+    }
+    const double s = group_sum<LPJ>(s0 + s1);
+    double x = 0.0;
+    if (j == p) {
+      x = sq;
+      dj = -1.0;
+    } else if (j < n && dj >= 0.0) {
+      x = (gjp - s) * inv;
+      dj = dj - x * x;
+    }
+    // columns already pivoted (dj = -1), or whose Schur diagonal has gone negative by
+    // rounding, keep dj and get a zero entry
+    const int ut = t / LPJ, st = t % LPJ;
+#pragma unroll
+    for (int u = 0; u < NREG; ++u)
+      if (u == ut && sub == st) lr[u] = x;
+    r = t + 1;
+  }
+  // the loop touches no global memory, so its barriers never wait for stores: L and
+  // the pivots are written once, here
+  __syncthreads();
+  if (j < n) {
+#pragma unroll
+    for (int u = 0; u < NREG; ++u) {
+      const int l = sub + u * LPJ;
+      if (l < r) L[j + static_cast<size_t>(l) * n] = lr[u];
+    }
+  }
+  for (int t = threadIdx.x; t < r; t += NTH) piv[t] = pivs[t];
   if (threadIdx.x == 0) *d_r = r;
 }
 
@@ -1344,21 +1528,6 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
   }
 }
 
-// Sum over the 8 lanes of an aligned lane group with DPP moves (no LDS round trip):
-// swap neighbours, swap pairs, then add the mirrored half of the 8 lanes.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double group8_sum(double x) {
-  x += dpp_move<0xB1>(x);   // quad_perm [1,0,3,2]
-  x += dpp_move<0x4E>(x);   // quad_perm [2,3,0,1]
-  x += dpp_move<0x141>(x);  // row_half_mirror
-  return x;
-}
-
 // One-sided Jacobi for c <= 64 columns of at most 64 rows: k_jacobi_reg with
 // 8-lane groups, both A and V zero-padded to 64 rows in LDS so that every lane moves
 // its 8 entries of a column as four 16-byte LDS accesses with no bounds tests, and
@@ -1774,7 +1943,11 @@ void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, d
   // as many leading columns of L as fit are kept in LDS
   const int tl = static_cast<int>(std::min<size_t>(rmax, (cap - base) / (sizeof(double) * n)));
   const size_t shm = base + sizeof(double) * static_cast<size_t>(n) * tl;
-  if (n * 16 <= BT)
+  if (n <= 64) {
+    k_pivchol_lds<8, 8, 512><<<1, 512, sizeof(double) * n * n, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  } else if (n <= 128) {
+    k_pivchol_lds<4, 32, 512><<<1, 512, sizeof(double) * n * n, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  } else if (n * 16 <= BT)
     k_pivoted_cholesky<16><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
   else if (n * 8 <= BT)
     k_pivoted_cholesky<8><<<1, BT, shm, s>>>(G, n, ldg, rmax, theta, L, piv, d_r, tl);
