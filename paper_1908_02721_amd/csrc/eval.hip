@@ -13,7 +13,9 @@
 // registers from LDS-staged rows.  Chunk partials are summed in a fixed order, so
 // the gradient is bitwise reproducible.
 #include <algorithm>
+#include <map>
 #include <memory>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -152,21 +154,29 @@ __global__ __launch_bounds__(NT) void k_bucket_offsets(const uint64_t* __restric
 }
 
 
+// out[a][i][b] = sum over the chunks c of bucket i of part[c][a][b], in chunk order
+// (four interleaved partial sums keep four loads in flight; the order is fixed).
 template <typename T>
-__global__ __launch_bounds__(NT) void k_grad_reduce(int64_t csz, int nchunk, const T* __restrict__ part,
-                                                    T* __restrict__ out) {
+__global__ __launch_bounds__(NT) void k_grad_reduce(int r0, int nk, int r1, const int64_t* __restrict__ cstart,
+                                                    const T* __restrict__ part, T* __restrict__ out) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * NT + threadIdx.x;
+  const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
   if (e >= csz) return;
-  // four interleaved partial sums (a fixed order) keep four loads in flight
+  const int b = static_cast<int>(e % r1);
+  const int i = static_cast<int>((e / r1) % nk);
+  const int a = static_cast<int>(e / (static_cast<int64_t>(r1) * nk));
+  const int64_t O = static_cast<int64_t>(r0) * r1;
+  const T* p = part + a * r1 + b;
+  const int64_t c1 = cstart[i + 1];
   T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-  int c = 0;
-  for (; c + 3 < nchunk; c += 4) {
-    s0 += part[static_cast<int64_t>(c) * csz + e];
-    s1 += part[static_cast<int64_t>(c + 1) * csz + e];
-    s2 += part[static_cast<int64_t>(c + 2) * csz + e];
-    s3 += part[static_cast<int64_t>(c + 3) * csz + e];
+  int64_t c = cstart[i];
+  for (; c + 3 < c1; c += 4) {
+    s0 += p[c * O];
+    s1 += p[(c + 1) * O];
+    s2 += p[(c + 2) * O];
+    s3 += p[(c + 3) * O];
   }
-  for (; c < nchunk; ++c) s0 += part[static_cast<int64_t>(c) * csz + e];
+  for (; c < c1; ++c) s0 += p[c * O];
   out[e] = (s0 + s1) + (s2 + s3);
 }
 
@@ -356,41 +366,54 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// One chunk of a bucket: nodes [beg, beg + cnt) of the bucket order, all with last
+// mode index i.
+struct ChunkDesc {
+  int64_t beg;
+  uint32_t i, cnt;
+};
+struct ChunkList {
+  const ChunkDesc* d = nullptr;
+  int64_t n = 0;
+  const int64_t* cstart = nullptr;
+};
+
 // Bucketed row-times-slice product over the nodes of one trie depth grouped by their
-// last mode index: workgroup (i, chunk, tile) takes up to 64 nodes q whose index is
-// i, gathers their input rows src[parent(q)] (forward; src[q] when parent is null),
+// last mode index: workgroup (chunk, tile) takes the chunk's NB nodes q (index i),
+// gathers their input rows src[parent(q)] (forward; src[q] when parent is null),
 // multiplies them by the r0 x r1 slice S_i (S_i[a][b] = G[i*sI + a*sK + b], staged
-// in LDS 32 rows at a time) and writes dst[q][b0:b0+64]: a small gather-GEMM-scatter
-// on the matrix cores, 4 waves each owning a 32 x 32 quarter of the tile as 2 x 2
-// MFMA blocks.  Forward: S_i = G[:, i, :].  Up pass: S_i = G[:, i, :]^T, rows = the
-// children's up vectors.
-template <typename T>
+// in LDS 32 rows at a time) and writes dst[q][b0:b0+TW]: a small gather-GEMM-scatter
+// on the matrix cores, each of the 4 waves owning a 32 x 32 block of the NB x TW tile
+// as 2 x 2 MFMA blocks (NB = 64: TW = 64; NB = 128 for slices at most 32 wide:
+// TW = 32).  Only non-empty chunks are launched.  Forward: S_i = G[:, i, :].  Up
+// pass: S_i = G[:, i, :]^T, rows = the children's up vectors.
+template <typename T, int NB>
 __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int64_t sK, int64_t sI,
+                                                            const ChunkDesc* __restrict__ chunks,
                                                             const uint64_t* __restrict__ perm,
-                                                            const int64_t* __restrict__ off,
                                                             const uint32_t* __restrict__ parent,
                                                             const T* __restrict__ Lprev, const T* __restrict__ G,
                                                             T* __restrict__ Lcur) {
-  constexpr int NB = 64;
+  static_assert(NB == 64 || NB == 128, "64- or 128-node chunks");
+  constexpr int TW = NB == 64 ? 64 : 32;
   constexpr int AK = 32;
   __shared__ T Vs[AK][NB + 1];
-  __shared__ T Ss[AK][64 + 1];
+  __shared__ T Ss[AK][TW + 1];
   __shared__ uint32_t qid[NB], pid[NB];
-  const int i = blockIdx.x;
-  const int64_t beg = off[i] + static_cast<int64_t>(blockIdx.y) * NB;
-  const int64_t end = min(off[i + 1], beg + NB);
-  if (beg >= end) return;
-  const int cnt = static_cast<int>(end - beg);
-  const int b0 = blockIdx.z * 64;
-  if (threadIdx.x < NB) {
-    const uint64_t pv = (threadIdx.x < cnt) ? perm[beg + threadIdx.x] : 0ull;
+  const ChunkDesc cd = chunks[blockIdx.x];
+  const int i = static_cast<int>(cd.i);
+  const int64_t beg = cd.beg;
+  const int cnt = static_cast<int>(cd.cnt);
+  const int b0 = blockIdx.y * TW;
+  for (int e = threadIdx.x; e < NB; e += NT) {
+    const uint64_t pv = (e < cnt) ? perm[beg + e] : 0ull;
     const uint32_t q = static_cast<uint32_t>(pv);
-    qid[threadIdx.x] = q;
-    pid[threadIdx.x] = parent ? static_cast<uint32_t>(pv >> 32) : q;
+    qid[e] = q;
+    pid[e] = parent ? static_cast<uint32_t>(pv >> 32) : q;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  const int wm = NB == 64 ? (w & 1) * 32 : w * 32, wn = NB == 64 ? (w >> 1) * 32 : 0;
   const int li = lane & 15, lk = lane >> 4;
   typename Mfma<T>::acc_t acc[2][2];
 #pragma unroll
@@ -404,7 +427,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
   const T* Gi = G + static_cast<int64_t>(i) * sI;
   // staging: all loads of a K-stage in flight together (clamped addresses, masked
   // afterwards); the next stage's loads are issued before this stage's MFMA
-  constexpr int PV = AK * NB / NT, PS = AK * 64 / NT;
+  constexpr int PV = AK * NB / NT, PS = AK * TW / NT;
   T vv[PV], sv[PS];
   auto load_stage = [&](int a0) {
 #pragma unroll
@@ -417,7 +440,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
 #pragma unroll
     for (int u = 0; u < PS; ++u) {
       const int e = threadIdx.x + u * NT;
-      const int b = e % 64, a = e / 64;
+      const int b = e % TW, a = e / TW;
       const bool ok = a0 + a < r0 && b0 + b < r1;
       sv[u] = Gi[ok ? (a0 + a) * sK + b0 + b : 0];
     }
@@ -433,7 +456,7 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
 #pragma unroll
     for (int u = 0; u < PS; ++u) {
       const int e = threadIdx.x + u * NT;
-      const int b = e % 64, a = e / 64;
+      const int b = e % TW, a = e / TW;
       Ss[a][b] = (a0 + a < r0 && b0 + b < r1) ? sv[u] : T(0);
     }
     __syncthreads();
@@ -468,20 +491,18 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_bucket_mfma(int r0, int r1, int6
 // a 64 x 64 tile of MFMA blocks contracting over the entries staged KC at a time;
 // written to part[chunk] laid out like the core, [a][i][b].
 template <typename T, int KC>
-__global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
-                                                          const int64_t* __restrict__ off, const T* __restrict__ gy,
+__global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, const ChunkDesc* __restrict__ chunks,
+                                                          const uint64_t* __restrict__ perm, const T* __restrict__ gy,
                                                           const T* __restrict__ L, int64_t lsum, int64_t loff,
                                                           const T* __restrict__ R, int64_t rsum, int64_t roff,
-                                                          int64_t chunk, T* __restrict__ part,
-                                                          const uint32_t* __restrict__ lidx) {
+                                                          T* __restrict__ part, const uint32_t* __restrict__ lidx) {
   __shared__ T Ls[KC][65];
   __shared__ T Rs[KC][65];
-  const int i = blockIdx.x;
-  const int c = blockIdx.y;
+  const ChunkDesc cd = chunks[blockIdx.x];
   const int tA = (r0 + 63) / 64;
-  const int a0 = (blockIdx.z % tA) * 64, b0 = (blockIdx.z / tA) * 64;
-  const int64_t beg = off[i] + static_cast<int64_t>(c) * chunk;
-  const int64_t end = min(off[i + 1], beg + chunk);
+  const int a0 = (blockIdx.y % tA) * 64, b0 = (blockIdx.y / tA) * 64;
+  const int64_t beg = cd.beg;
+  const int64_t end = beg + cd.cnt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -552,7 +573,7 @@ __global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk
     }
     __syncthreads();
   }
-  const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
+  T* pc = part + static_cast<int64_t>(blockIdx.x) * r0 * r1;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -561,8 +582,7 @@ __global__ __launch_bounds__(NT) void k_grad_partial_mfma(int r0, int r1, int nk
       for (int v = 0; v < 4; ++v) {
         const int a = a0 + wm + 16 * x + Mfma<T>::row(lane, v);
         const int b = b0 + wn + 16 * y + li;
-        if (a < r0 && b < r1)
-          part[static_cast<int64_t>(c) * csz + (static_cast<int64_t>(a) * nk + i) * r1 + b] = acc[x][y][v];
+        if (a < r0 && b < r1) pc[a * r1 + b] = acc[x][y][v];
       }
 }
 
@@ -604,20 +624,18 @@ __global__ __launch_bounds__(NT) void k_tri_fwd_narrow(int r0, int r1, int64_t s
 // o = t % O for the entries t / O, t / O + NT / O, ... of its chunk; the per-thread
 // sums are then added in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, int nk, const uint64_t* __restrict__ perm,
-                                                   const int64_t* __restrict__ off, const T* __restrict__ L,
+__global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, const ChunkDesc* __restrict__ chunks,
+                                                   const uint64_t* __restrict__ perm, const T* __restrict__ L,
                                                    int64_t loff, const T* __restrict__ R,
-                                                   const uint32_t* __restrict__ lidx, int64_t chunk,
-                                                   T* __restrict__ part) {
+                                                   const uint32_t* __restrict__ lidx, T* __restrict__ part) {
   __shared__ T red[NT];
-  const int i = blockIdx.x;
-  const int c = blockIdx.y;
+  const ChunkDesc cd = chunks[blockIdx.x];
   const int O = r0 * r1;
   const int lanes = NT / O;
   const int o = threadIdx.x % O, l = threadIdx.x / O;
   const int a = o / r1, b = o % r1;
-  const int64_t beg = off[i] + static_cast<int64_t>(c) * chunk;
-  const int64_t end = min(off[i + 1], beg + chunk);
+  const int64_t beg = cd.beg;
+  const int64_t end = beg + cd.cnt;
   T acc = T(0);
   if (l < lanes) {
     // four entries per iteration so that their loads overlap
@@ -647,8 +665,7 @@ __global__ __launch_bounds__(NT) void k_grad_small(int r0, int r1, int nk, const
   if (threadIdx.x < O) {
     T s2 = T(0);
     for (int ll = 0; ll < lanes; ++ll) s2 += red[ll * O + threadIdx.x];
-    const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
-    part[static_cast<int64_t>(c) * csz + (static_cast<int64_t>(a) * nk + i) * r1 + b] = s2;
+    part[static_cast<int64_t>(blockIdx.x) * O + a * r1 + b] = s2;
   }
 }
 
@@ -803,20 +820,55 @@ struct Trie {
   uint32_t* leaf = nullptr;               // per sorted entry: depth-d node
   uint32_t* start = nullptr;              // per depth-d node: first sorted entry
   uint64_t* perm = nullptr;               // sorted position -> entry
+  std::vector<std::vector<int64_t>> hoff; // host copy of boff
+  DevMem* owner = nullptr;                // memory of the chunk lists, built on first use
+  mutable std::map<std::pair<int, int64_t>, ChunkList> chunks;
 };
+
+// Non-empty chunks of at most `cl` entries of every bucket (bucket by bucket), built
+// on the host from the bucket offsets and uploaded: d[c] for c < n, and the chunks
+// of bucket i are [cstart[i], cstart[i + 1]).
+ChunkList make_chunk_list(const std::vector<int64_t>& off, int64_t cl, DevMem& mem, hipStream_t s) {
+  std::vector<ChunkDesc> h;
+  std::vector<int64_t> cs(off.size(), 0);
+  for (size_t i = 0; i + 1 < off.size(); ++i) {
+    cs[i] = static_cast<int64_t>(h.size());
+    for (int64_t b = off[i]; b < off[i + 1]; b += cl)
+      h.push_back(ChunkDesc{b, static_cast<uint32_t>(i), static_cast<uint32_t>(std::min<int64_t>(cl, off[i + 1] - b))});
+  }
+  cs.back() = static_cast<int64_t>(h.size());
+  ChunkDesc* dptr = mem.get<ChunkDesc>(std::max<size_t>(h.size(), 1));
+  int64_t* cptr = mem.get<int64_t>(cs.size());
+  // pageable-memory copies have consumed their sources when the calls return
+  if (!h.empty()) TTS_HIP(hipMemcpyAsync(dptr, h.data(), sizeof(ChunkDesc) * h.size(), hipMemcpyHostToDevice, s));
+  TTS_HIP(hipMemcpyAsync(cptr, cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice, s));
+  return ChunkList{dptr, static_cast<int64_t>(h.size()), cptr};
+}
+
+// The chunk list of depth t for chunk length cl, built on first use and kept with the
+// trie.
+ChunkList chunk_list(const Trie& tr, int t, int64_t cl, hipStream_t s) {
+  const auto key = std::make_pair(t, cl);
+  auto it = tr.chunks.find(key);
+  if (it != tr.chunks.end()) return it->second;
+  const ChunkList c = make_chunk_list(tr.hoff[t], cl, *tr.owner, s);
+  tr.chunks.emplace(key, c);
+  return c;
+}
 
 int lpe_for(const EvalDesc& ed) { return max_rank_of(ed) <= 32 ? 32 : 64; }
 
-// Chunking of the gradient buckets: chunks of the largest bucket, a multiple of kc
-// entries each, so that the whole launch has about 2048 workgroups (enough to fill
-// the chip) while every workgroup still reduces a long run of entries.
-void grad_chunks(int64_t maxb, int nk, int tiles, int kc, int64_t* chunk, int* nchunk) {
-  const int64_t want = std::max<int64_t>(1, (2048 + static_cast<int64_t>(nk) * tiles - 1) / (static_cast<int64_t>(nk) * tiles));
-  int64_t c = std::max<int64_t>(1, (maxb + want - 1) / want);
-  c = ((c + kc - 1) / kc) * kc;
-  *chunk = c;
-  *nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + c - 1) / c));
-  if (*nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
+// Chunk length of the gradient kernels over P entries: a multiple of kc near
+// P * tiles / 2048, so that the launch has about 2048 workgroups of equal work (plus
+// at most one short chunk per bucket).
+int64_t grad_chunk_len(int64_t P, int tiles, int kc) {
+  const int64_t c = std::max<int64_t>(kc, (P * tiles + 2047) / 2048);
+  return ((c + kc - 1) / kc) * kc;
+}
+// k_grad_small (few lanes per output entry): about 4096 chunks, at least 256 entries
+int64_t grad_chunk_small(int64_t P) {
+  const int64_t c = std::max<int64_t>(256, (P + 4095) / 4096);
+  return ((c + 63) / 64) * 64;
 }
 
 unsigned blocks_for(int64_t items, int lpe) {
@@ -841,6 +893,7 @@ bool trie_possible(const EvalDesc& ed) {
 bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, DevMem& scratch, Allocator* al,
                 Trie& tr, hipStream_t s) {
   const int d = ed.d;
+  tr.owner = &mem;
   TrieGeom g{};
   g.d = d;
   int total = 0;
@@ -915,7 +968,8 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, DevMem& scratch, A
   uint64_t* key = scratch.get<uint64_t>(pmax);
   uint64_t* kt = scratch.get<uint64_t>(pmax);
   uint64_t* vt = mem.get<uint64_t>(pmax);
-  std::vector<std::vector<int64_t>> hoff(d + 1);
+  std::vector<std::vector<int64_t>>& hoff = tr.hoff;
+  hoff.assign(d + 1, {});
   for (int t = 1; t <= d; ++t) {
     const int nk = ed.n[t - 1];
     const int64_t P = tr.P[t];
@@ -951,12 +1005,16 @@ void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int
     if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
     k_tri_fwd_narrow<T><<<dim3(nk, static_cast<unsigned>(nchunk)), NT, 0, s>>>(K, O, sK, sI, tr.bperm[t], tr.boff[t],
                                                                                 parent, src, G, dst);
+  } else if (O <= 32) {
+    const ChunkList cl = chunk_list(tr, t, 128, s);
+    if (cl.n > 0)
+      k_tri_fwd_bucket_mfma<T, 128><<<dim3(static_cast<unsigned>(cl.n), (O + 31) / 32), NT, 0, s>>>(
+          K, O, sK, sI, cl.d, tr.bperm[t], parent, src, G, dst);
   } else {
-    const int64_t nchunk = std::max<int64_t>(1, (tr.bmax[t] + 63) / 64);
-    if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
-    const int tiles = (O + 63) / 64;
-    k_tri_fwd_bucket_mfma<T><<<dim3(nk, static_cast<unsigned>(nchunk), tiles), NT, 0, s>>>(
-        K, O, sK, sI, tr.bperm[t], tr.boff[t], parent, src, G, dst);
+    const ChunkList cl = chunk_list(tr, t, 64, s);
+    if (cl.n > 0)
+      k_tri_fwd_bucket_mfma<T, 64><<<dim3(static_cast<unsigned>(cl.n), (O + 63) / 64), NT, 0, s>>>(
+          K, O, sK, sI, cl.d, tr.bperm[t], parent, src, G, dst);
   }
   TTS_LAUNCH_CHECK();
 }
@@ -1057,33 +1115,27 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
     const int nk = ed.n[t], r0 = ed.r[t], r1 = ed.r[t + 1];
     const int64_t Pc = tr.P[t + 1];
     const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
-    const int64_t maxb = tr.bmax[t + 1];
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
     const bool small = r0 * r1 <= NT && (r0 < 16 || r1 < 16);
-    int64_t chunk;
-    int nchunk;
-    if (small) {
-      // few lanes per output entry: many short chunks keep the loops short
-      chunk = KC * std::max<int64_t>(1, (maxb + KC * 512 - 1) / (KC * 512));
-      nchunk = static_cast<int>(std::max<int64_t>(1, (maxb + chunk - 1) / chunk));
-    } else {
-      grad_chunks(maxb, nk, tiles, KC, &chunk, &nchunk);
-    }
-    T* part = mem.get<T>(static_cast<size_t>(nchunk) * csz);
+    const int64_t cl = small ? grad_chunk_small(Pc) : grad_chunk_len(Pc, tiles, KC);
+    const ChunkList ch = chunk_list(tr, t + 1, cl, s);
+    T* part = mem.get<T>(static_cast<size_t>(std::max<int64_t>(ch.n, 1)) * r0 * r1);
     {
       KTimer ktm("eval_grad", s,
-                 static_cast<double>(Pc) * (r0 + r1 + 8) * sizeof(T) + static_cast<double>(nchunk) * csz * sizeof(T),
+                 static_cast<double>(Pc) * (r0 + r1 + 8) * sizeof(T) + static_cast<double>(ch.n) * r0 * r1 * sizeof(T),
                  2.0 * static_cast<double>(Pc) * r0 * r1);
-      if (small)
-        k_grad_small<T><<<dim3(nk, nchunk), NT, 0, s>>>(r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], Lv[t],
-                                                        t == 0 ? -1 : 0, Uv[t + 1], tr.parent[t + 1], chunk, part);
-      else
-        k_grad_partial_mfma<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(
-            r0, r1, nk, tr.bperm[t + 1], tr.boff[t + 1], nullptr, Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1], r1, 0, chunk,
-            part, tr.parent[t + 1]);
-      TTS_LAUNCH_CHECK();
+      if (ch.n > 0) {
+        if (small)
+          k_grad_small<T><<<static_cast<unsigned>(ch.n), NT, 0, s>>>(r0, r1, ch.d, tr.bperm[t + 1], Lv[t],
+                                                                     t == 0 ? -1 : 0, Uv[t + 1], tr.parent[t + 1], part);
+        else
+          k_grad_partial_mfma<T, KC><<<dim3(static_cast<unsigned>(ch.n), tiles), NT, 0, s>>>(
+              r0, r1, ch.d, tr.bperm[t + 1], nullptr, Lv[t], r0, t == 0 ? -1 : 0, Uv[t + 1], r1, 0, part,
+              tr.parent[t + 1]);
+        TTS_LAUNCH_CHECK();
+      }
     }
-    k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, static_cast<T*>(grads[t]));
+    k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(r0, nk, r1, ch.cstart, part, static_cast<T*>(grads[t]));
     TTS_LAUNCH_CHECK();
   }
 }
@@ -1176,19 +1228,17 @@ tt_status direct_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T
     std::vector<int64_t> hoff(nk + 1);
     TTS_HIP(hipMemcpyAsync(hoff.data(), off, sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
-    int64_t maxb = 0;
-    for (int i = 0; i < nk; ++i) maxb = std::max(maxb, hoff[i + 1] - hoff[i]);
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
-    int64_t chunk;
-    int nchunk;
-    grad_chunks(maxb, nk, tiles, KC, &chunk, &nchunk);
-    T* part = mem.get<T>(static_cast<size_t>(nchunk) * csz);
+    const ChunkList ch = make_chunk_list(hoff, grad_chunk_len(m, tiles, KC), mem, s);
+    T* part = mem.get<T>(static_cast<size_t>(std::max<int64_t>(ch.n, 1)) * r0 * r1);
     const int64_t lo = (k >= 1) ? ed.loff[k] : -1;              // l_k (k >= 1); l_0 = 1
     const int64_t ro = (k + 1 <= d - 1) ? ed.roff[k + 1] : -1;  // r_{k+1}; r_d = 1
-    k_grad_partial_mfma<T, KC><<<dim3(nk, nchunk, tiles), NT, 0, s>>>(r0, r1, nk, perm, off, gy, L, ed.lsum, lo, R,
-                                                                      ed.rsum, ro, chunk, part, nullptr);
-    TTS_LAUNCH_CHECK();
-    k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(csz, nchunk, part, gout);
+    if (ch.n > 0) {
+      k_grad_partial_mfma<T, KC><<<dim3(static_cast<unsigned>(ch.n), tiles), NT, 0, s>>>(
+          r0, r1, ch.d, perm, gy, L, ed.lsum, lo, R, ed.rsum, ro, part, nullptr);
+      TTS_LAUNCH_CHECK();
+    }
+    k_grad_reduce<T><<<grid_for(csz, NT), NT, 0, s>>>(r0, nk, r1, ch.cstart, part, gout);
     TTS_LAUNCH_CHECK();
   }
   TTS_HIP(hipStreamSynchronize(s));
