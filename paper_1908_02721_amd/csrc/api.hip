@@ -197,13 +197,13 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
   DBuf<uint64_t> keys(al, nnz), vals(al, nnz);
   launch_ingest(idx, val, nnz, mi, keys.get(), vals.get(), st.get(), s);
   sync_status(st.get(), s);
+  const uint32_t kept = nnz - host_status()->dropped;
   {
     const DevStatus* h = host_status();
     if (h->err & kErrIndex) fail(TT_ERR_INDEX, "a coordinate is outside its mode range");
     if (h->err & kErrNonfinite) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");
-    if (h->kept == 0) fail(TT_ERR_EMPTY, "no nonzero left after dropping explicit zeros");
+    if (kept == 0) fail(TT_ERR_EMPTY, "no nonzero left after dropping explicit zeros");
   }
-  const uint32_t kept = host_status()->kept;
   R->nnz = kept;
   TTS_HIP(hipEventRecord(ev.e[1], s));
 

@@ -720,6 +720,62 @@ __global__ __launch_bounds__(NT) void k_tri_up(int64_t P, const uint32_t* __rest
   }
 }
 
+// Up vectors as k_tri_up, for a core that fits in LDS: workgroup per QB consecutive
+// parents, whose children are consecutive too (trie order).  The transposed core, the
+// parents' child ranges and the children's indices and up vectors (r1 <= 4) are
+// staged in LDS with coalesced loads (the children in pieces of UP_CH), then thread
+// (q, a) sums over the children of q from LDS and the rows are stored coalesced.
+constexpr int UP_CH = 512;
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tri_up_seg(int64_t P, int QB, const uint32_t* __restrict__ cbeg,
+                                                   const uint32_t* __restrict__ ccoord, const T* __restrict__ Unext,
+                                                   int r0, int r1, int nk, const T* __restrict__ GT,
+                                                   T* __restrict__ Ucur) {
+  extern __shared__ unsigned char up_sm[];
+  T* gs = reinterpret_cast<T*>(up_sm);                       // r0 * nk * r1
+  const int csz = r0 * nk * r1;
+  T* su = gs + csz;                                          // UP_CH * 4
+  uint32_t* sco = reinterpret_cast<uint32_t*>(su + UP_CH * 4);  // UP_CH
+  uint32_t* scb = sco + UP_CH;                               // QB + 1
+  const int64_t q0 = static_cast<int64_t>(blockIdx.x) * QB;
+  const int nq = static_cast<int>(min(static_cast<int64_t>(QB), P - q0));
+  for (int e = threadIdx.x; e <= nq; e += NT) scb[e] = cbeg[q0 + e];
+  for (int e = threadIdx.x; e < csz; e += NT) gs[e] = GT[e];
+  __syncthreads();
+  const uint32_t clo = scb[0], chi = scb[nq];
+  constexpr int PT = 8;  // (parent, row) pairs per thread: QB * r0 <= PT * NT
+  T acc[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) acc[j] = T(0);
+  for (uint32_t p0 = clo; p0 < chi; p0 += UP_CH) {
+    const int pc = static_cast<int>(min(static_cast<uint32_t>(UP_CH), chi - p0));
+    if (p0 != clo) __syncthreads();  // the previous piece is no longer read
+    for (int e = threadIdx.x; e < pc; e += NT) sco[e] = ccoord[p0 + e];
+    for (int e = threadIdx.x; e < pc * r1; e += NT) su[e] = Unext[static_cast<int64_t>(p0) * r1 + e];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int e = threadIdx.x + j * NT;
+      const int qq = e / r0, a = e % r0;
+      if (qq < nq) {
+        const uint32_t c0 = max(scb[qq], p0), c1 = min(scb[qq + 1], p0 + static_cast<uint32_t>(pc));
+        T x = acc[j];
+        for (uint32_t c = c0; c < c1; ++c) {
+          const int cl = static_cast<int>(c - p0);
+          const T* g = gs + static_cast<int64_t>(sco[cl]) * r1 * r0 + a;
+          for (int b = 0; b < r1; ++b) x = fma(g[b * r0], su[cl * r1 + b], x);
+        }
+        acc[j] = x;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int e = threadIdx.x + j * NT;
+    if (e / r0 < nq) Ucur[q0 * r0 + e] = acc[j];
+  }
+}
+
 // Forward of a depth whose r1 is small, in trie order: one thread per (node, b),
 // L[q][b] = sum_a Lprev[parent(q)][a] G[a][coord(q)][b], the whole core staged in
 // LDS.  Siblings are adjacent in trie order, so their shared parent vector is read
@@ -871,9 +927,11 @@ int64_t grad_chunk_small(int64_t P) {
   return ((c + 63) / 64) * 64;
 }
 
+// One pass over the items (no grid-stride repetition): every item's dependent loads
+// are in flight at once rather than one after another within a workgroup.
 unsigned blocks_for(int64_t items, int lpe) {
   const int64_t per_block = (NT / 64) * (64 / lpe);
-  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, 256 * 64)));
+  return static_cast<unsigned>(std::max<int64_t>(1, std::min<int64_t>((items + per_block - 1) / per_block, 1 << 30)));
 }
 
 bool trie_possible(const EvalDesc& ed) {
@@ -1038,7 +1096,7 @@ void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std:
     const size_t core_bytes = sizeof(T) * static_cast<size_t>(r0) * nk * r1;
     if (r1 < 16 && core_bytes <= 48 * 1024) {
       const int64_t items = P * r1;
-      const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((items + NT - 1) / NT, 1024));
+      const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((items + NT - 1) / NT, 4096));
       k_tri_fwd_trie<T><<<blocks, NT, core_bytes, s>>>(P, r0, r1, nk, tr.parent[t], tr.coord[t], Lv[t - 1],
                                                        static_cast<const T*>(ed.core[t - 1]), Lv[t]);
       TTS_LAUNCH_CHECK();
@@ -1093,7 +1151,14 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
     Uv[t] = mem.get<T>(static_cast<size_t>(P) * r0);
     KTimer kt("eval_up", s, static_cast<double>(Pc) * (r1 + 8) * sizeof(T) + static_cast<double>(P) * r0 * sizeof(T),
               2.0 * static_cast<double>(Pc) * r0 * r1);
-    if (r1 <= 4) {
+    const size_t up_lds = sizeof(T) * (static_cast<size_t>(r0) * nk * r1 + UP_CH * 4) + sizeof(uint32_t) * UP_CH;
+    if (r1 <= 4 && r0 <= 256 && up_lds + sizeof(uint32_t) * (8 * NT / r0 + 1) <= 40 * 1024) {
+      // short contraction, core in LDS: segments of consecutive parents
+      const int QB = 8 * NT / r0;
+      k_tri_up_seg<T><<<static_cast<unsigned>((P + QB - 1) / QB), NT, up_lds + sizeof(uint32_t) * (QB + 1), s>>>(
+          P, QB, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, nk, GT, Uv[t]);
+      TTS_LAUNCH_CHECK();
+    } else if (r1 <= 4) {
       // short contraction: each parent walks its children directly
       if (r0 <= 32)
         k_tri_up<T, 32><<<blocks_for(P, 32), NT, 0, s>>>(P, cbeg[t], tr.coord[t + 1], Uv[t + 1], r0, r1, GT, Uv[t]);

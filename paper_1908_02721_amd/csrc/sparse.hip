@@ -31,29 +31,37 @@ __device__ __forceinline__ uint64_t fmask(uint32_t b) { return (b >= 64) ? ~0ull
 __global__ __launch_bounds__(NT) void k_ingest(const int32_t* __restrict__ idx, const double* __restrict__ val,
                                                uint32_t nnz, ModeInfo mi, uint64_t* __restrict__ keys,
                                                uint64_t* __restrict__ vbits, DevStatus* st) {
-  __shared__ uint32_t lds[NT / 64];
   const uint32_t e = blockIdx.x * NT + threadIdx.x;
-  uint32_t keep = 0;
+  bool zero = false;
   if (e < nnz) {
     const int32_t* c = idx + static_cast<size_t>(e) * mi.d;
+    const double v = val[e];
     uint64_t key = 0;
     bool bad = false;
-    for (int j = 0; j < mi.d; ++j) {
-      const int32_t x = c[j];
-      bad |= (x < 0) || (static_cast<uint32_t>(x) >= mi.n[j]);
-      key |= static_cast<uint64_t>(static_cast<uint32_t>(x)) << mi.off[j];
+    // the coordinates eight at a time, each group's loads issued together
+    for (int j0 = 0; j0 < mi.d; j0 += 8) {
+      int32_t x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = c[(j0 + u < mi.d) ? j0 + u : 0];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = j0 + u;
+        if (j < mi.d) {
+          bad |= (x[u] < 0) || (static_cast<uint32_t>(x[u]) >= mi.n[j]);
+          key |= static_cast<uint64_t>(static_cast<uint32_t>(x[u])) << mi.off[j];
+        }
+      }
     }
-    const double v = val[e];
     if (bad) atomicOr(&st->err, kErrIndex);
     if (!isfinite(v)) atomicOr(&st->err, kErrNonfinite);
-    const bool zero = (v == 0.0);
+    zero = (v == 0.0);
     keys[e] = zero ? ~0ull : key;
     vbits[e] = __double_as_longlong(v);
-    keep = zero ? 0u : 1u;
   }
-  uint32_t tot;
-  block_excl_scan_u32<NT>(keep, lds, &tot);
-  if (threadIdx.x == 0 && tot) atomicAdd(&st->kept, tot);
+  // explicit zeros are rare: one atomic per wave that has any (a count of kept
+  // entries would need one per workgroup, all on one address)
+  const uint64_t zm = __ballot(zero);
+  if (zm && (threadIdx.x & 63) == 0) atomicAdd(&st->dropped, static_cast<uint32_t>(__popcll(zm)));
 }
 
 __global__ __launch_bounds__(NT) void k_col_flags(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,

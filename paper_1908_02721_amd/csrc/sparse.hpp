@@ -19,10 +19,10 @@ struct ModeInfo {
 struct DevStatus {
   uint32_t err;       // bit 0: index out of range, bit 1: non-finite, bit 2: duplicate
   uint32_t longcol;   // a level >= 2 column has more than kMaxLocal entries
-  uint32_t kept;      // nonzeros kept after dropping explicit zeros
   uint32_t ncols;     // columns of the current level
   uint32_t beta;      // groups of the current level
   uint32_t nnz_n;     // entries of N_k
+  uint32_t dropped;   // explicit zeros among the input entries
   uint32_t pad0, pad1;
   double norm2;       // ||A||_F^2
 };
