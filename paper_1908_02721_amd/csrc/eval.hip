@@ -881,35 +881,80 @@ struct Trie {
   mutable std::map<std::pair<int, int64_t>, ChunkList> chunks;
 };
 
-// Non-empty chunks of at most `cl` entries of every bucket (bucket by bucket), built
-// on the host from the bucket offsets and uploaded: d[c] for c < n, and the chunks
-// of bucket i are [cstart[i], cstart[i + 1]).
-ChunkList make_chunk_list(const std::vector<int64_t>& off, int64_t cl, DevMem& mem, hipStream_t s) {
-  std::vector<ChunkDesc> h;
-  std::vector<int64_t> cs(off.size(), 0);
+// Non-empty chunks of at most `cl` entries of every bucket (bucket by bucket): the
+// host vectors of make_chunk_host, uploaded as d[c] for c < n, with the chunks of
+// bucket i at [cstart[i], cstart[i + 1]).
+void make_chunk_host(const std::vector<int64_t>& off, int64_t cl, std::vector<ChunkDesc>& h,
+                     std::vector<int64_t>& cs) {
+  h.clear();
+  cs.assign(off.size(), 0);
   for (size_t i = 0; i + 1 < off.size(); ++i) {
     cs[i] = static_cast<int64_t>(h.size());
     for (int64_t b = off[i]; b < off[i + 1]; b += cl)
       h.push_back(ChunkDesc{b, static_cast<uint32_t>(i), static_cast<uint32_t>(std::min<int64_t>(cl, off[i + 1] - b))});
   }
   cs.back() = static_cast<int64_t>(h.size());
+}
+
+// Builds the missing chunk lists among `keys` (depth, chunk length) and uploads them
+// together: one device block and one host-to-device copy for all of them.  The lists
+// are kept with the trie.
+void ensure_chunk_lists(const Trie& tr, const std::vector<std::pair<int, int64_t>>& keys, hipStream_t s) {
+  std::vector<std::pair<int, int64_t>> todo;
+  for (const auto& k : keys)
+    if (tr.chunks.find(k) == tr.chunks.end() && std::find(todo.begin(), todo.end(), k) == todo.end())
+      todo.push_back(k);
+  if (todo.empty()) return;
+  std::vector<std::vector<ChunkDesc>> hd(todo.size());
+  std::vector<std::vector<int64_t>> hc(todo.size());
+  std::vector<size_t> at(todo.size());
+  size_t bytes = 0;
+  for (size_t j = 0; j < todo.size(); ++j) {
+    make_chunk_host(tr.hoff[todo[j].first], todo[j].second, hd[j], hc[j]);
+    at[j] = bytes;
+    bytes += sizeof(ChunkDesc) * hd[j].size();
+    bytes += (sizeof(int64_t) * hc[j].size() + 15) / 16 * 16;  // keeps every list 16-byte aligned
+  }
+  std::vector<unsigned char> host(bytes);
+  for (size_t j = 0; j < todo.size(); ++j) {
+    std::copy(reinterpret_cast<const unsigned char*>(hd[j].data()),
+              reinterpret_cast<const unsigned char*>(hd[j].data() + hd[j].size()), host.begin() + at[j]);
+    std::copy(reinterpret_cast<const unsigned char*>(hc[j].data()),
+              reinterpret_cast<const unsigned char*>(hc[j].data() + hc[j].size()),
+              host.begin() + at[j] + sizeof(ChunkDesc) * hd[j].size());
+  }
+  unsigned char* dev = tr.owner->get<unsigned char>(bytes);
+  // a pageable-memory copy has consumed its source when the call returns
+  TTS_HIP(hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s));
+  for (size_t j = 0; j < todo.size(); ++j) {
+    ChunkList c;
+    c.d = reinterpret_cast<const ChunkDesc*>(dev + at[j]);
+    c.n = static_cast<int64_t>(hd[j].size());
+    c.cstart = reinterpret_cast<const int64_t*>(dev + at[j] + sizeof(ChunkDesc) * hd[j].size());
+    tr.chunks.emplace(todo[j], c);
+  }
+}
+
+// One chunk list, uploaded into `mem` (entry-by-entry path, no trie).
+ChunkList make_chunk_list(const std::vector<int64_t>& off, int64_t cl, DevMem& mem, hipStream_t s) {
+  std::vector<ChunkDesc> h;
+  std::vector<int64_t> cs;
+  make_chunk_host(off, cl, h, cs);
   ChunkDesc* dptr = mem.get<ChunkDesc>(std::max<size_t>(h.size(), 1));
   int64_t* cptr = mem.get<int64_t>(cs.size());
-  // pageable-memory copies have consumed their sources when the calls return
   if (!h.empty()) TTS_HIP(hipMemcpyAsync(dptr, h.data(), sizeof(ChunkDesc) * h.size(), hipMemcpyHostToDevice, s));
   TTS_HIP(hipMemcpyAsync(cptr, cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice, s));
   return ChunkList{dptr, static_cast<int64_t>(h.size()), cptr};
 }
 
-// The chunk list of depth t for chunk length cl, built on first use and kept with the
-// trie.
+// Chunk length of a bucket product with O output columns (0: the narrow kernel,
+// which takes no chunk list).
+int64_t bucket_chunk(int O) { return O < 16 ? 0 : (O <= 32 ? 128 : 64); }
+
+// The chunk list of depth t for chunk length cl (built and uploaded on first use).
 ChunkList chunk_list(const Trie& tr, int t, int64_t cl, hipStream_t s) {
-  const auto key = std::make_pair(t, cl);
-  auto it = tr.chunks.find(key);
-  if (it != tr.chunks.end()) return it->second;
-  const ChunkList c = make_chunk_list(tr.hoff[t], cl, *tr.owner, s);
-  tr.chunks.emplace(key, c);
-  return c;
+  ensure_chunk_lists(tr, {std::make_pair(t, cl)}, s);
+  return tr.chunks.find(std::make_pair(t, cl))->second;
 }
 
 int lpe_for(const EvalDesc& ed) { return max_rank_of(ed) <= 32 ? 32 : 64; }
@@ -925,6 +970,13 @@ int64_t grad_chunk_len(int64_t P, int tiles, int kc) {
 int64_t grad_chunk_small(int64_t P) {
   const int64_t c = std::max<int64_t>(256, (P + 4095) / 4096);
   return ((c + 63) / 64) * 64;
+}
+// The gradient of an r0 x r1 core slice takes k_grad_small when an output entry has
+// few lanes of work, the matrix-core kernel otherwise.
+bool grad_is_small(int r0, int r1) { return r0 * r1 <= NT && (r0 < 16 || r1 < 16); }
+int64_t grad_chunk(int r0, int r1, int64_t P, int kc) {
+  const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
+  return grad_is_small(r0, r1) ? grad_chunk_small(P) : grad_chunk_len(P, tiles, kc);
 }
 
 // One pass over the items (no grid-stride repetition): every item's dependent loads
@@ -1063,7 +1115,7 @@ void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int
     if (nchunk > 65535) fail(TT_ERR_TOO_LARGE, "evaluation bucket too large");
     k_tri_fwd_narrow<T><<<dim3(nk, static_cast<unsigned>(nchunk)), NT, 0, s>>>(K, O, sK, sI, tr.bperm[t], tr.boff[t],
                                                                                 parent, src, G, dst);
-  } else if (O <= 32) {
+  } else if (bucket_chunk(O) == 128) {
     const ChunkList cl = chunk_list(tr, t, 128, s);
     if (cl.n > 0)
       k_tri_fwd_bucket_mfma<T, 128><<<dim3(static_cast<unsigned>(cl.n), (O + 31) / 32), NT, 0, s>>>(
@@ -1081,6 +1133,15 @@ template <typename T>
 void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std::vector<T*>& Lv, hipStream_t s) {
   const int d = ed.d;
   if (tr.bperm.empty()) build_buckets(ed, tr, mem, mem, al, s);
+  {  // the chunk lists of this pass, uploaded together
+    std::vector<std::pair<int, int64_t>> keys;
+    for (int t = 1; t <= d; ++t) {
+      const int r0 = ed.r[t - 1], r1 = ed.r[t];
+      const size_t core_bytes = sizeof(T) * static_cast<size_t>(r0) * ed.n[t - 1] * r1;
+      if (!(r1 < 16 && core_bytes <= 48 * 1024) && bucket_chunk(r1) > 0) keys.emplace_back(t, bucket_chunk(r1));
+    }
+    ensure_chunk_lists(tr, keys, s);
+  }
   Lv.assign(d + 1, nullptr);
   Lv[0] = mem.get<T>(1);
   k_one<T><<<1, 1, 0, s>>>(Lv[0]);
@@ -1132,6 +1193,14 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
                    DevMem& mem, hipStream_t s) {
   const int d = ed.d;
   const int64_t m = tr.m;
+  constexpr int KC = sizeof(T) == 8 ? 32 : 64;  // 33 KB of LDS: four workgroups per CU
+  {  // the chunk lists of the up pass and the gradients, uploaded together
+    std::vector<std::pair<int, int64_t>> keys;
+    for (int t = d - 1; t >= 1; --t)
+      if (ed.r[t + 1] > 4 && bucket_chunk(ed.r[t]) > 0) keys.emplace_back(t + 1, bucket_chunk(ed.r[t]));
+    for (int t = 0; t < d; ++t) keys.emplace_back(t + 1, grad_chunk(ed.r[t], ed.r[t + 1], tr.P[t + 1], KC));
+    ensure_chunk_lists(tr, keys, s);
+  }
   // up vectors, bottom-up
   std::vector<T*> Uv(d + 1, nullptr);
   Uv[d] = mem.get<T>(tr.P[d]);
@@ -1175,15 +1244,13 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
     }
   }
   // gradients: core t pairs parents at depth t with children at depth t+1
-  constexpr int KC = sizeof(T) == 8 ? 32 : 64;  // 33 KB of LDS: four workgroups per CU
   for (int t = 0; t < d; ++t) {
     const int nk = ed.n[t], r0 = ed.r[t], r1 = ed.r[t + 1];
     const int64_t Pc = tr.P[t + 1];
     const int64_t csz = static_cast<int64_t>(r0) * nk * r1;
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
-    const bool small = r0 * r1 <= NT && (r0 < 16 || r1 < 16);
-    const int64_t cl = small ? grad_chunk_small(Pc) : grad_chunk_len(Pc, tiles, KC);
-    const ChunkList ch = chunk_list(tr, t + 1, cl, s);
+    const bool small = grad_is_small(r0, r1);
+    const ChunkList ch = chunk_list(tr, t + 1, grad_chunk(r0, r1, Pc, KC), s);
     T* part = mem.get<T>(static_cast<size_t>(std::max<int64_t>(ch.n, 1)) * r0 * r1);
     {
       KTimer ktm("eval_grad", s,

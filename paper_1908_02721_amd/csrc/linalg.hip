@@ -1638,6 +1638,137 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
   }
 }
 
+// One-sided Jacobi for NC/2 < c <= NC columns (NC = 32 or 64) of at most 64 rows,
+// padded to 64 x NC, with a hierarchical parallel ordering that keeps one column of
+// each pair in registers.  A sweep has log2(NC) phases: in phase h the NC columns form
+// 2^h blocks of S = NC >> h; in each block the first S/2 columns stay with their
+// groups ("kept") while the last S/2 circulate: in round s of the phase, group i of a
+// block pairs its kept column i with circulating column S/2 + (i + s) mod S/2.  The
+// phases pair every two columns exactly once in NC - 1 rounds, and per round a group
+// reads and writes only the circulating column (of A and of V) through LDS: half the
+// LDS traffic of an ordering in which both columns move.  Groups are
+// GW = 512 / NC lanes; a lane holds 64 / GW rows of a column as double2 pairs.
+// Padded columns are zero and never rotate.  Same rotation, stopping test and output
+// as k_jacobi64.
+template <int NC>
+__global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
+                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+  constexpr int NTH = 256, LD = 64, GW = 512 / NC, UP = 32 / GW;
+  static_assert(NC == 32 || NC == 64, "32 or 64 columns");
+  __shared__ double2 sA[NC * LD / 2];  // 64 x NC, column-major (rows >= `rows` zero)
+  __shared__ double2 sV[NC * LD / 2];  // 64 x NC (identity outside the leading c x c block)
+  __shared__ int rotated;
+  double* A = reinterpret_cast<double*>(sA);
+  double* V = reinterpret_cast<double*>(sV);
+  {  // staging: each thread's loads are issued together (clamped addresses)
+    constexpr int PER = NC * LD / NTH;
+    double v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
+      v[u] = Ag[(i < rows && j < c) ? i + static_cast<size_t>(j) * lda : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
+      A[e] = (i < rows && j < c) ? v[u] : 0.0;
+      V[e] = (i == j) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    bool any = false;
+    for (int half = NC / 2; half >= 1; half >>= 1) {
+      const int blk = grp / half, i = grp % half;
+      const int kc = blk * 2 * half + i;  // kept column
+      double2 ka[UP], kv[UP];
+      {
+        const double2* ap = sA + kc * (LD / 2) + gl;
+        const double2* vp = sV + kc * (LD / 2) + gl;
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          ka[u] = ap[GW * u];
+          kv[u] = vp[GW * u];
+        }
+      }
+      for (int st = 0; st < half; ++st) {
+        const int qc = blk * 2 * half + half + (i + st) % half;  // circulating column
+        double2* aq = sA + qc * (LD / 2) + gl;
+        double2* vq = sV + qc * (LD / 2) + gl;
+        // with 64 columns the LDS traffic decides: V is read only for a rotation;
+        // with 32, the latency does, and V is read together with A
+        constexpr bool PRE_V = NC == 32;
+        double2 y[UP], yv[UP];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          y[u] = aq[GW * u];
+          if (PRE_V) yv[u] = vq[GW * u];
+        }
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          a = fma(ka[u].x, ka[u].x, fma(ka[u].y, ka[u].y, a));
+          b = fma(y[u].x, y[u].x, fma(y[u].y, y[u].y, b));
+          g = fma(ka[u].x, y[u].x, fma(ka[u].y, y[u].y, g));
+        }
+        a = group_sum<GW>(a);
+        b = group_sum<GW>(b);
+        g = group_sum<GW>(g);
+        const double ab = a * b;
+        const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
+        if (a != 0.0 && b != 0.0 && rot) {  // uniform within the group
+          double cs, sn;
+          jacobi_rotation(a, b, g, &cs, &sn);
+          if (!PRE_V) {
+#pragma unroll
+            for (int u = 0; u < UP; ++u) yv[u] = vq[GW * u];
+          }
+#pragma unroll
+          for (int u = 0; u < UP; ++u) {
+            const double2 x = ka[u], xv = kv[u];
+            ka[u] = double2{cs * x.x - sn * y[u].x, cs * x.y - sn * y[u].y};
+            aq[GW * u] = double2{sn * x.x + cs * y[u].x, sn * x.y + cs * y[u].y};
+            kv[u] = double2{cs * xv.x - sn * yv[u].x, cs * xv.y - sn * yv[u].y};
+            vq[GW * u] = double2{sn * xv.x + cs * yv[u].x, sn * xv.y + cs * yv[u].y};
+          }
+          any = true;
+        }
+        __syncthreads();
+      }
+      {  // the kept column goes back before the next phase regroups the columns
+        double2* ap = sA + kc * (LD / 2) + gl;
+        double2* vp = sV + kc * (LD / 2) + gl;
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          ap[GW * u] = ka[u];
+          vp[GW * u] = kv[u];
+        }
+      }
+      __syncthreads();
+    }
+    if (any && gl == 0) rotated = 1;
+    __syncthreads();
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int j = grp; j < c; j += NTH / GW) {
+    const double2* aj = sA + j * (LD / 2) + gl;
+    double sacc = 0.0;
+#pragma unroll
+    for (int u = 0; u < UP; ++u) sacc = fma(aj[GW * u].x, aj[GW * u].x, fma(aj[GW * u].y, aj[GW * u].y, sacc));
+    sacc = group_sum<GW>(sacc);
+    if (gl == 0) sigma[j] = sqrt(sacc);
+  }
+  for (int e = threadIdx.x; e < LD * c; e += NTH) {
+    const int i = e % LD, j = e / LD;
+    if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = A[e];
+    if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+  }
+}
+
 // Block-pair step of a one-sided block Jacobi sweep for wide matrices: workgroup w
 // takes the pair of column blocks given by the circle method for round `rd`,
 // stages both blocks of A (rows x 2b) and of V (c x 2b) in LDS, runs inner Jacobi
@@ -2058,6 +2189,16 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
             // one sweep of rotations: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V)
             0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
+  if (c > 32 && c <= 64 && rows <= 64) {
+    k_jacobi64h<64><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  if (c > 16 && c <= 32 && rows <= 64) {
+    k_jacobi64h<32><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
   if (c <= 64 && rows <= 64) {
     k_jacobi64<<<1, 256, sizeof(double) * 128 * static_cast<size_t>(c), s>>>(A, rows, c, lda, V, ldv, sigma);
     TTS_LAUNCH_CHECK();
