@@ -431,6 +431,35 @@ __device__ __forceinline__ double group_sum(double x) {
   return x;
 }
 __device__ __forceinline__ double group8_sum(double x) { return group_sum<8>(x); }
+// Three group sums at once, their moves interleaved so that they overlap.
+template <int G>
+__device__ __forceinline__ void group_sum3(double& a, double& b, double& c) {
+  static_assert(G == 8 || G == 16, "group of 8 or 16 lanes");
+  {
+    const double x = dpp_move<0xB1>(a), y = dpp_move<0xB1>(b), z = dpp_move<0xB1>(c);
+    a += x;
+    b += y;
+    c += z;
+  }
+  {
+    const double x = dpp_move<0x4E>(a), y = dpp_move<0x4E>(b), z = dpp_move<0x4E>(c);
+    a += x;
+    b += y;
+    c += z;
+  }
+  {
+    const double x = dpp_move<0x141>(a), y = dpp_move<0x141>(b), z = dpp_move<0x141>(c);
+    a += x;
+    b += y;
+    c += z;
+  }
+  if (G == 16) {
+    const double x = dpp_move<0x140>(a), y = dpp_move<0x140>(b), z = dpp_move<0x140>(c);
+    a += x;
+    b += y;
+    c += z;
+  }
+}
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
                           __builtin_amdgcn_readlane(__double2loint(x), lane));
@@ -471,11 +500,17 @@ __device__ __forceinline__ void slot_argmax(const double* sv, const int* si, dou
 }
 
 // Rotation (cs, sn) that makes two columns with squared norms a, b and inner
-// product g orthogonal (the smaller-angle Jacobi rotation, Rutishauser's formulas):
-// zeta = (b - a) / 2g, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-// cs = 1 / sqrt(1 + t^2), sn = cs t.  Reciprocals and reciprocal square roots come
-// from the hardware estimates refined by two Newton steps (a few ulp; a rotation only
-// needs cs^2 + sn^2 = 1 to rounding level, which it keeps since both come from t).
+// product g orthogonal: the smaller-angle Jacobi rotation, tan(2 theta) = 2g / (b - a)
+// with |theta| <= pi/4.  With d = b - a, e = 2g and h = sqrt(d^2 + e^2), the half-angle
+// formulas give cs^2 = (h + |d|) / 2h and sn = sign(d) e / (2h cs), so
+// cs = w rsqrt(w) and sn = sign(d) e (1/2h) rsqrt(w) for w = (h + |d|) / 2h: two
+// reciprocal square roots and no cancellation (h + |d| adds positive numbers).
+// Outside [1e-140, 1e140] for |d| and |e|, where d^2 + e^2 could overflow or lose
+// its low part, Rutishauser's formulas are used instead: zeta = (b - a) / 2g,
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1 / sqrt(1 + t^2), sn = cs t.
+// Both give tan(theta) = sign(d) e / (|d| + h).  Reciprocals and reciprocal square
+// roots come from the hardware estimates refined by two Newton steps (a few ulp; a
+// rotation only needs cs^2 + sn^2 = 1 to rounding level, which both forms keep).
 __device__ __forceinline__ double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
   double e = fma(-x, y, 1.0);
@@ -489,7 +524,30 @@ __device__ __forceinline__ double rsq_nr(double x) {
   y = y * fma(-h * y, y, 1.5);
   return y * fma(-h * y, y, 1.5);
 }
+// sqrt(x) and 1 / sqrt(x) from one refined reciprocal square root (a few ulp) for x
+// in the normal range, IEEE sqrt and division outside it.
+__device__ __forceinline__ void sqrt_and_rsqrt(double x, double* sq, double* inv) {
+  if (x > 1e-280 && x < 1e280) {
+    const double r = rsq_nr(x);
+    *inv = r;
+    *sq = x * r;
+  } else {
+    *sq = sqrt(x);
+    *inv = 1.0 / *sq;
+  }
+}
 __device__ __forceinline__ void jacobi_rotation(double a, double b, double g, double* cs, double* sn) {
+  const double d = b - a, e = 2.0 * g;
+  const double m = fmax(fabs(d), fabs(e));
+  if (m > 1e-140 && m < 1e140) {
+    const double s2 = fma(d, d, e * e);
+    const double r = rsq_nr(s2);                       // 1 / h
+    const double w = (fma(s2, r, fabs(d))) * (0.5 * r);  // (h + |d|) / 2h
+    const double y = rsq_nr(w);
+    *cs = w * y;
+    *sn = (d >= 0.0 ? 0.5 : -0.5) * e * r * y;
+    return;
+  }
   double t;
   if (fabs(g) < 1e-290) {  // reciprocal estimates are not valid near the subnormal range
     const double zeta = (b - a) / (2.0 * g);
@@ -611,8 +669,8 @@ __global__ __launch_bounds__(BT) void k_pivoted_cholesky(const double* __restric
       else
         piv[t] = p;
     }
-    const double sq = sqrt(pv);
-    const double inv = 1.0 / sq;
+    double sq, inv;
+    sqrt_and_rsqrt(pv, &sq, &inv);
     for (int j0 = 0; j0 < n; j0 += JPB) {
       const int j = j0 + jj;
       const bool live = j < n && j != p && dg[min(j, n - 1)] >= 0.0;
@@ -743,16 +801,24 @@ __global__ __launch_bounds__(NTH) void k_pivchol_lds(const double* __restrict__ 
       for (int u = 0; u < NREG; ++u) prow[sub + u * LPJ] = lr[u];
     }
     __syncthreads();
-    const double sq = sqrt(pv);
-    const double inv = 1.0 / sq;
+    double sq, inv;
+    sqrt_and_rsqrt(pv, &sq, &inv);
     const double gjp = gs[min(j, n - 1) + p * n];
     // sum over l < t of L[j, l] L[p, l]: this lane's terms l = sub + u LPJ, u < ul
     const int ul = (t + LPJ - 1) / LPJ;
+    // in groups of four terms (entries past t are zero on both sides), each group's
+    // loads issued together
     double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int u = 0; u < NREG; u += 2) {
-      if (u < ul) s0 = fma(lr[u], prow[sub + u * LPJ], s0);
-      if (u + 1 < ul) s1 = fma(lr[u + 1], prow[sub + (u + 1) * LPJ], s1);
+    for (int u = 0; u < NREG; u += 4) {
+      if (u < ul) {
+        const double p0 = prow[sub + u * LPJ], p1 = prow[sub + (u + 1) * LPJ];
+        const double p2 = prow[sub + (u + 2) * LPJ], p3 = prow[sub + (u + 3) * LPJ];
+        s0 = fma(lr[u], p0, s0);
+        s1 = fma(lr[u + 1], p1, s1);
+        s0 = fma(lr[u + 2], p2, s0);
+        s1 = fma(lr[u + 3], p3, s1);
+      }
     }
     const double s = group_sum<LPJ>(s0 + s1);
     double x = 0.0;
@@ -1681,8 +1747,9 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
   for (int sweep = 0; sweep < 80; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     bool any = false;
-    for (int half = NC / 2; half >= 1; half >>= 1) {
-      const int blk = grp / half, i = grp % half;
+    for (int lh = (NC == 64 ? 5 : 4); lh >= 0; --lh) {
+      const int half = 1 << lh;
+      const int blk = grp >> lh, i = grp & (half - 1);
       const int kc = blk * 2 * half + i;  // kept column
       double2 ka[UP], kv[UP];
       {
@@ -1694,8 +1761,10 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
           kv[u] = vp[GW * u];
         }
       }
+      int qi = i;  // (i + st) mod half, stepped without a division
       for (int st = 0; st < half; ++st) {
-        const int qc = blk * 2 * half + half + (i + st) % half;  // circulating column
+        const int qc = blk * 2 * half + half + qi;  // circulating column
+        qi = (qi + 1 == half) ? 0 : qi + 1;
         double2* aq = sA + qc * (LD / 2) + gl;
         double2* vq = sV + qc * (LD / 2) + gl;
         // with 64 columns the LDS traffic decides: V is read only for a rotation;
@@ -1714,9 +1783,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
           b = fma(y[u].x, y[u].x, fma(y[u].y, y[u].y, b));
           g = fma(ka[u].x, y[u].x, fma(ka[u].y, y[u].y, g));
         }
-        a = group_sum<GW>(a);
-        b = group_sum<GW>(b);
-        g = group_sum<GW>(g);
+        group_sum3<GW>(a, b, g);
         const double ab = a * b;
         const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
         if (a != 0.0 && b != 0.0 && rot) {  // uniform within the group
