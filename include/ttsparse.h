@@ -98,8 +98,8 @@ void tt_options_default(tt_options* opt);
  *   opt   : NULL for the defaults
  *   out   : receives the result handle; release it with tt_free
  * All work is enqueued on `stream`; the call waits for its own small device-to-
- * host counts (one or two per level and per bond) and returns when the result
- * is complete.
+ * host counts (two per level, three for a level of more than 2048 groups, and one
+ * per bond) and returns when the result is complete.
  */
 tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                               const double* val, double eps, const tt_options* opt, void* stream,
@@ -199,8 +199,13 @@ tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, const int64_t
  * match that call's (TT_ERR_ARG otherwise), and the caller guarantees that the
  * core values have not changed since.  The kept products stay for further calls.
  *
- * Every call returns once its work on the stream has finished.  A plan may be used
- * from one thread at a time; tt_eval_plan_free releases it (NULL is ignored).
+ * tt_eval_plan_create returns once its work has finished.  tt_eval_plan_forward and
+ * tt_eval_plan_backward called on the creation stream return once their work is
+ * enqueued: outputs are ready in stream order, and the input buffers must stay
+ * valid until the stream reaches them.  Called on another stream, they wait for the
+ * creation stream first and return once their work has finished.  A plan may be used
+ * from one thread at a time; tt_eval_plan_free releases it (NULL is ignored), and
+ * work on the creation stream that uses it must have been enqueued before.
  */
 typedef struct tt_eval_plan_s* tt_eval_plan;
 tt_status tt_eval_plan_create(int32_t d, const int64_t* dims, int64_t m, const int32_t* idx,

@@ -301,25 +301,41 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
                  slotmin.get(), tsize - 1, slot.get(), isrep.get(), s);
     DBuf<uint32_t> reppos(al, ncols);
     exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, &st.get()->beta, s);
+    int rm_bits = 0;
+    for (int j = kidx; j < d; ++j) rm_bits += static_cast<int>(mi.bits[j]);
+    // Up to kSmallSortMax groups (the common case) the leaders are ordered without
+    // knowing beta on the host: the group count is read by the kernels from the
+    // device, and beta and nnz(N_k) come back in one read-back.  Beyond that the
+    // leaders are sorted again with the device-wide radix sort.
+    const uint32_t cap = std::min<uint32_t>(ncols, kSmallSortMax);
+    DBuf<uint64_t> lkey(al, cap), lslot(al, cap), lks(al, cap), lss(al, cap);
+    DBuf<uint32_t> slot_gid(al, tsize), nlen(al, cap), npos(al, cap);
+    launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, cap, lkey.get(), lslot.get(), s);
+    sort_small_device_count(lkey.get(), lslot.get(), &st.get()->beta, cap, rm_bits, lks.get(), lss.get(), s);
+    launch_group_ids(lss.get(), 0, &st.get()->beta, cap, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
+    exclusive_scan_u32(al, nlen.get(), npos.get(), cap, &st.get()->nnz_n, s);
     sync_status(st.get(), s);
     const uint32_t beta = host_status()->beta;
     if (static_cast<uint64_t>(beta) * (k < d ? mi.n[k] : 1) > static_cast<uint64_t>(INT32_MAX))
       fail(TT_ERR_TOO_LARGE, "rank times mode size exceeds 2^31");
-    int rm_bits = 0;
-    for (int j = kidx; j < d; ++j) rm_bits += static_cast<int>(mi.bits[j]);
-    DBuf<uint64_t> lkey(al, beta), lslot(al, beta);
-    launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, lkey.get(), lslot.get(), s);
-    {
-      DBuf<uint64_t> kt(al, beta), vt(al, beta);
-      if (radix_sort_pairs_pp(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s)) {
-        lkey.swap(kt);
-        lslot.swap(vt);
+    if (beta > cap) {
+      lkey.reset(al, beta);
+      lslot.reset(al, beta);
+      launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, beta, lkey.get(), lslot.get(), s);
+      {
+        DBuf<uint64_t> kt(al, beta), vt(al, beta);
+        if (radix_sort_pairs_pp(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s)) {
+          lkey.swap(kt);
+          lslot.swap(vt);
+        }
       }
+      lss = std::move(lslot);
+      nlen.reset(al, beta);
+      npos.reset(al, beta);
+      launch_group_ids(lss.get(), beta, nullptr, beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
+      exclusive_scan_u32(al, nlen.get(), npos.get(), beta, &st.get()->nnz_n, s);
+      sync_status(st.get(), s);
     }
-    DBuf<uint32_t> slot_gid(al, tsize), nlen(al, beta), npos(al, beta);
-    launch_group_ids(lslot.get(), beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
-    exclusive_scan_u32(al, nlen.get(), npos.get(), beta, &st.get()->nnz_n, s);
-    sync_status(st.get(), s);
     const uint32_t nnz_n = host_status()->nnz_n;
     LevelData& L = R->lev[k - 1];
     L.ncols = ncols;
@@ -330,7 +346,7 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     L.colptr.reset(al, static_cast<size_t>(beta) + 1);
     L.row.reset(al, nnz_n);
     L.val.reset(al, nnz_n);
-    launch_emit_n(lslot.get(), beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
+    launch_emit_n(lss.get(), beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
                   L.colptr.get(), L.row.get(), L.val.get(), st.get(), s);
     // a7: next level (or the last core)
     EmitArgs ea{};

@@ -1458,6 +1458,7 @@ struct tt_eval_plan_s {
   int64_t dims[TT_MAX_D] = {};
   int64_t m = 0;
   bool trie = false;
+  hipStream_t stream = nullptr;    // the creation stream: calls on it are stream-ordered
   tts::DevMem mem;                 // trie arrays, or the copy of the coordinates
   tts::Trie tr;
   const int32_t* idx = nullptr;    // direct path: the plan's copy of the coordinates
@@ -1481,7 +1482,6 @@ tt_status plan_forward(tt_eval_plan_s& p, const EvalDesc& ed, T* y, bool save, h
   trie_forward<T>(ed, p.tr, *mem, &al, Lv, s);
   k_tri_out<T><<<grid_for(p.m, NT), NT, 0, s>>>(p.m, p.tr.leaf, p.tr.perm, Lv[ed.d], y);
   TTS_LAUNCH_CHECK();
-  TTS_HIP(hipStreamSynchronize(s));
   if (save) {
     p.saved = std::move(mem);
     p.Lv.assign(Lv.begin(), Lv.end());
@@ -1503,9 +1503,21 @@ tt_status plan_backward(tt_eval_plan_s& p, const EvalDesc& ed, const T* gy, void
     trie_forward<T>(ed, p.tr, mem, &al, Lv, s);
   }
   trie_backward<T>(ed, p.tr, Lv, gy, grads, mem, s);
-  TTS_HIP(hipStreamSynchronize(s));
   return TT_OK;
 }
+
+// A call on another stream than the plan's waits for the plan's stream first and for
+// its own work at the end, so that memory freed to either stream's cache is idle.
+struct StreamGuard {
+  hipStream_t s;
+  bool other;
+  StreamGuard(const tt_eval_plan_s& p, hipStream_t call) : s(call), other(call != p.stream) {
+    if (other) TTS_HIP(hipStreamSynchronize(p.stream));
+  }
+  void finish() {
+    if (other) TTS_HIP(hipStreamSynchronize(s));
+  }
+};
 
 }  // namespace
 }  // namespace tts
@@ -1530,6 +1542,7 @@ extern "C" tt_status tt_eval_plan_create(int32_t d, const int64_t* dims, int64_t
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto p = std::make_unique<tt_eval_plan_s>(s);
+    p->stream = s;
     p->d = d;
     for (int k = 0; k < d; ++k) p->dims[k] = dims[k];
     p->m = m;
@@ -1584,6 +1597,7 @@ extern "C" tt_status tt_eval_plan_forward(tt_eval_plan plan, const int64_t* rank
   }
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StreamGuard guard(*plan, s);
     if (save) {
       plan->saved.reset();
       plan->Lv.clear();
@@ -1591,6 +1605,7 @@ extern "C" tt_status tt_eval_plan_forward(tt_eval_plan plan, const int64_t* rank
     }
     st = dtype == TT_DTYPE_F64 ? plan_forward<double>(*plan, ed, static_cast<double*>(y_out), save != 0, s)
                                : plan_forward<float>(*plan, ed, static_cast<float*>(y_out), save != 0, s);
+    guard.finish();
     if (st == TT_OK && save) {
       plan->saved_dtype = dtype;
       for (int k = 0; k <= plan->d; ++k) plan->saved_ranks[k] = ranks[k];
@@ -1631,9 +1646,12 @@ extern "C" tt_status tt_eval_plan_backward(tt_eval_plan plan, const int64_t* ran
   }
   try {
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return dtype == TT_DTYPE_F64
-               ? plan_backward<double>(*plan, ed, static_cast<const double*>(grad_y), grad_cores, use_saved != 0, s)
-               : plan_backward<float>(*plan, ed, static_cast<const float*>(grad_y), grad_cores, use_saved != 0, s);
+    StreamGuard guard(*plan, s);
+    st = dtype == TT_DTYPE_F64
+             ? plan_backward<double>(*plan, ed, static_cast<const double*>(grad_y), grad_cores, use_saved != 0, s)
+             : plan_backward<float>(*plan, ed, static_cast<const float*>(grad_y), grad_cores, use_saved != 0, s);
+    guard.finish();
+    return st;
   } catch (const Error& e) {
     set_last_error(e.msg);
     return e.code;

@@ -869,6 +869,7 @@ __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ 
 __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, int r, int lda, double max_ratio,
                                                        int32_t* __restrict__ ok) {
   __shared__ double a[64][65];
+  __shared__ double rdiag[64];  // reciprocals of the diagonal of the factor
   __shared__ int bad;
   const int tid = threadIdx.x;
   {  // staging: the 16 loads of each thread are issued together (clamped addresses)
@@ -894,10 +895,14 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
         const double d = a[b + jj][b + jj];
         const bool pos = d > 0.0;
         if (!pos && lane == 0) bad = 1;
-        const double piv = sqrt(pos ? d : 1.0);
+        double piv, ip;
+        sqrt_and_rsqrt(pos ? d : 1.0, &piv, &ip);
         __builtin_amdgcn_wave_barrier();
-        if (lane == jj) a[b + jj][b + jj] = piv;
-        if (lane > jj && lane < 16) a[b + jj][b + lane] /= piv;
+        if (lane == jj) {
+          a[b + jj][b + jj] = piv;
+          rdiag[b + jj] = ip;
+        }
+        if (lane > jj && lane < 16) a[b + jj][b + lane] *= ip;
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -917,7 +922,7 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
         double v = a[b + i][c];
 #pragma unroll
         for (int l = 0; l < i; ++l) v = fma(-a[b + l][b + i], x[l], v);
-        x[i] = v / a[b + i][b + i];
+        x[i] = v * rdiag[b + i];
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[b + i][c] = x[i];
@@ -1075,6 +1080,7 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(const double* __restrict__ Y,
                                                    int ldx, int32_t* __restrict__ ok) {
   __shared__ double us[64][65];
   __shared__ double xs[64][65];
+  __shared__ double dinv[64];  // reciprocals of U's diagonal (0 for a zero pivot)
   const int row0 = blockIdx.x * 64;
   const int tid = threadIdx.x;
   {  // staging: the 32 loads of each thread are issued together (clamped addresses)
@@ -1093,7 +1099,12 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(const double* __restrict__ Y,
     }
   }
   __syncthreads();
-  if (tid < 64 && us[tid][tid] == 0.0) *ok = 0;
+  if (tid < 64) {
+    const double dd = us[tid][tid];
+    if (dd == 0.0) *ok = 0;
+    dinv[tid] = (dd != 0.0) ? 1.0 / dd : 0.0;
+  }
+  __syncthreads();
   const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const int rw = 16 * w;
   for (int J = 0; J < 4; ++J) {
@@ -1117,8 +1128,7 @@ __global__ __launch_bounds__(256) void k_trsm_mfma(const double* __restrict__ Y,
         double v = xs[rw + li][bj + jj];
 #pragma unroll
         for (int l = 0; l < jj; ++l) v = fma(-x[l], us[bj + l][bj + jj], v);
-        const double dd = us[bj + jj][bj + jj];
-        x[jj] = (dd != 0.0) ? v / dd : 0.0;
+        x[jj] = v * dinv[bj + jj];
       }
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) xs[rw + li][bj + jj] = x[jj];

@@ -313,41 +313,81 @@ __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* in, uint32
 
 // Stable sort of up to SMALL_SORT pairs by key bits [0, nbits) in one workgroup:
 // each element's output position is the number of elements with a smaller masked
-// key, or an equal one at a lower index.  A thread ranks its EPT elements in one
-// pass over the keys (staged in LDS, read as broadcasts).
-constexpr uint32_t SMALL_SORT = 2048;
+// key, or an equal one at a lower index.  With nbits <= 53 the key and the index are
+// packed into one word (key << 11 | index), so that one comparison decides.  Up to
+// 1024 elements, P = 2^k threads share an element (n P <= 1024), each counting over
+// a contiguous part of the keys (staged in LDS, read as broadcasts), and the parts
+// are added with LDS atomics (integers: the order does not matter).
+constexpr uint32_t SMALL_SORT = kSmallSortMax;
 __global__ __launch_bounds__(1024) void k_sort_small(const uint64_t* __restrict__ keys,
-                                                     const uint64_t* __restrict__ vals, uint32_t n, int nbits,
-                                                     uint64_t* __restrict__ kout, uint64_t* __restrict__ vout) {
-  constexpr int EPT = SMALL_SORT / 1024;
+                                                     const uint64_t* __restrict__ vals, uint32_t n_arg, int nbits,
+                                                     uint64_t* __restrict__ kout, uint64_t* __restrict__ vout,
+                                                     const uint32_t* __restrict__ d_n, uint32_t cap) {
   __shared__ uint64_t ks[SMALL_SORT];
+  __shared__ uint32_t rk[SMALL_SORT];
+  const uint32_t n = d_n ? *d_n : n_arg;  // the count from the device when given
+  if (n == 0 || n > cap) return;
   const uint64_t mask = (nbits >= 64) ? ~0ull : ((1ull << nbits) - 1ull);
-  for (uint32_t i = threadIdx.x; i < n; i += 1024) ks[i] = keys[i] & mask;
-  __syncthreads();
-  uint64_t km[EPT];
-  uint32_t rank[EPT];
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const uint32_t i = threadIdx.x + e * 1024;
-    km[e] = (i < n) ? ks[i] : ~0ull;
-    rank[e] = 0;
+  const bool packed = nbits <= 53;
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) {
+    const uint64_t k = keys[i] & mask;
+    ks[i] = packed ? ((k << 11) | i) : k;
+    rk[i] = 0;
   }
+  __syncthreads();
+  if (n <= 1024) {
+    uint32_t P = 1;
+    while (P < 1024 && n * P * 2 <= 1024) P *= 2;
+    const uint32_t i = threadIdx.x / P, part = threadIdx.x % P;
+    if (i < n) {
+      const uint32_t len = (n + P - 1) / P, j0 = part * len, j1 = min(n, j0 + len);
+      const uint64_t ki = ks[i];
+      uint32_t r = 0;
+      if (packed) {
 #pragma unroll 8
-  for (uint32_t j = 0; j < n; ++j) {
-    const uint64_t kj = ks[j];
+        for (uint32_t j = j0; j < j1; ++j) r += (ks[j] < ki) ? 1u : 0u;
+      } else {
+#pragma unroll 8
+        for (uint32_t j = j0; j < j1; ++j) {
+          const uint64_t kj = ks[j];
+          r += (kj < ki || (kj == ki && j < i)) ? 1u : 0u;
+        }
+      }
+      if (P == 1)
+        rk[i] = r;
+      else
+        atomicAdd(&rk[i], r);
+    }
+  } else {
+    constexpr int EPT = SMALL_SORT / 1024;
+    uint64_t km[EPT];
+    uint32_t rank[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const uint32_t i = threadIdx.x + e * 1024;
-      rank[e] += (kj < km[e] || (kj == km[e] && j < i)) ? 1u : 0u;
+      km[e] = (i < n) ? ks[i] : ~0ull;
+      rank[e] = 0;
+    }
+#pragma unroll 8
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint64_t kj = ks[j];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const uint32_t i = threadIdx.x + e * 1024;
+        rank[e] += (packed ? (kj < km[e]) : (kj < km[e] || (kj == km[e] && j < i))) ? 1u : 0u;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t i = threadIdx.x + e * 1024;
+      if (i < n) rk[i] = rank[e];
     }
   }
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const uint32_t i = threadIdx.x + e * 1024;
-    if (i < n) {
-      kout[rank[e]] = keys[i];
-      vout[rank[e]] = vals[i];
-    }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) {
+    const uint32_t r = rk[i];
+    kout[r] = keys[i];
+    vout[r] = vals[i];
   }
 }
 
@@ -382,9 +422,11 @@ void exclusive_scan_u32(Allocator* al, const uint32_t* in, uint32_t* out, uint32
 bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
                          uint32_t n, int nbits, hipStream_t s) {
   if (n <= 1 || nbits <= 0) return false;
-  // one rank-sort launch costs about n / 60 us, a radix pass about 12 us at these sizes
-  if (n <= SMALL_SORT && n <= 700u * static_cast<uint32_t>((nbits + 7) / 8)) {
-    k_sort_small<<<1, 1024, 0, s>>>(keys, vals, n, nbits, ktmp, vtmp);
+  // the rank sort costs about 3 + n^2 / 50000 us, a radix pass over one tile about
+  // 10 us (more tiles: a few us more per tile)
+  const uint64_t passes_n = static_cast<uint64_t>((nbits + 7) / 8);
+  if (n <= SMALL_SORT && static_cast<uint64_t>(n) * n <= 40000ull * (10 * passes_n - 3)) {
+    k_sort_small<<<1, 1024, 0, s>>>(keys, vals, n, nbits, ktmp, vtmp, nullptr, SMALL_SORT);
     TTS_LAUNCH_CHECK();
     return true;
   }
@@ -412,6 +454,14 @@ bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t
     std::swap(vi, vo);
   }
   return ki != keys;
+}
+
+void sort_small_device_count(const uint64_t* keys, const uint64_t* vals, const uint32_t* d_n, uint32_t cap,
+                             int nbits, uint64_t* kout, uint64_t* vout, hipStream_t s) {
+  if (cap == 0) return;
+  if (cap > SMALL_SORT) fail(TT_ERR_TOO_LARGE, "device-count small sort beyond its capacity");
+  k_sort_small<<<1, 1024, 0, s>>>(keys, vals, 0, nbits, kout, vout, d_n, cap);
+  TTS_LAUNCH_CHECK();
 }
 
 void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,

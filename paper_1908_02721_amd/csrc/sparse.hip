@@ -250,22 +250,32 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
 
 __global__ __launch_bounds__(NT) void k_rep_list(const uint32_t* __restrict__ isrep, const uint32_t* __restrict__ reppos,
                                                  const uint32_t* __restrict__ slot, const uint64_t* __restrict__ slotmin,
-                                                 uint32_t ncols, uint64_t* __restrict__ lkey,
+                                                 uint32_t ncols, uint32_t cap, uint64_t* __restrict__ lkey,
                                                  uint64_t* __restrict__ lslot) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
   if (c >= ncols || !isrep[c]) return;
   const uint32_t j = reppos[c];
+  if (j >= cap) return;
   const uint32_t p = slot[c];
   lkey[j] = slotmin[p];
   lslot[j] = p;
 }
 
-__global__ __launch_bounds__(NT) void k_group_ids(const uint64_t* __restrict__ lslot, uint32_t beta,
+__global__ __launch_bounds__(NT) void k_group_ids(const uint64_t* __restrict__ lslot, uint32_t beta_arg,
+                                                  const uint32_t* __restrict__ d_beta, uint32_t n,
                                                   const uint64_t* __restrict__ table,
                                                   const uint32_t* __restrict__ col_start, uint32_t* __restrict__ slot_gid,
                                                   uint32_t* __restrict__ nlen) {
   const uint32_t j = blockIdx.x * NT + threadIdx.x;
-  if (j >= beta) return;
+  if (j >= n) return;
+  const uint32_t beta = d_beta ? *d_beta : beta_arg;
+  // more groups than the device-count path holds: its leader list was not sorted, so
+  // nothing is written (the host redoes this step with the full count)
+  if (beta > n) return;
+  if (j >= beta) {
+    nlen[j] = 0;
+    return;
+  }
   const uint32_t p = static_cast<uint32_t>(lslot[j]);
   slot_gid[p] = j;
   const uint32_t r = static_cast<uint32_t>(table[p] - 1);
@@ -381,16 +391,17 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
 }
 
 void launch_rep_list(const uint32_t* isrep, const uint32_t* reppos, const uint32_t* slot, const uint64_t* slotmin,
-                     uint32_t ncols, uint64_t* lkey, uint64_t* lslot, hipStream_t s) {
-  if (!ncols) return;
-  k_rep_list<<<grid_for(ncols, NT), NT, 0, s>>>(isrep, reppos, slot, slotmin, ncols, lkey, lslot);
+                     uint32_t ncols, uint32_t cap, uint64_t* lkey, uint64_t* lslot, hipStream_t s) {
+  if (!ncols || !cap) return;
+  k_rep_list<<<grid_for(ncols, NT), NT, 0, s>>>(isrep, reppos, slot, slotmin, ncols, cap, lkey, lslot);
   TTS_LAUNCH_CHECK();
 }
 
-void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
-                      uint32_t* slot_gid, uint32_t* nlen, hipStream_t s) {
-  if (!beta) return;
-  k_group_ids<<<grid_for(beta, NT), NT, 0, s>>>(lslot_sorted, beta, table, col_start, slot_gid, nlen);
+void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_t* d_beta, uint32_t n,
+                      const uint64_t* table, const uint32_t* col_start, uint32_t* slot_gid, uint32_t* nlen,
+                      hipStream_t s) {
+  if (!n) return;
+  k_group_ids<<<grid_for(n, NT), NT, 0, s>>>(lslot_sorted, beta, d_beta, n, table, col_start, slot_gid, nlen);
   TTS_LAUNCH_CHECK();
 }
 

@@ -75,11 +75,15 @@ void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus* st, hipStre
 void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* cval, const uint32_t* col_start,
                   const uint64_t* rmkey, uint32_t ncols, uint64_t* table, uint64_t* slotmin, uint32_t tmask,
                   uint32_t* slot, uint32_t* isrep, hipStream_t s);
+// the leaders' (row-major key, slot) pairs at their group positions below cap
 void launch_rep_list(const uint32_t* isrep, const uint32_t* reppos, const uint32_t* slot, const uint64_t* slotmin,
-                     uint32_t ncols, uint64_t* lkey, uint64_t* lslot, hipStream_t s);
-// group id of each slot (= rank of its leader) and the length of each group's column
-void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
-                      uint32_t* slot_gid, uint32_t* nlen, hipStream_t s);
+                     uint32_t ncols, uint32_t cap, uint64_t* lkey, uint64_t* lslot, hipStream_t s);
+// group id of each slot (= rank of its leader) and the length of each group's column,
+// for entries j < n of nlen, n = *d_beta when given (then zero for beta <= j < n),
+// else beta
+void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_t* d_beta, uint32_t n,
+                      const uint64_t* table, const uint32_t* col_start, uint32_t* slot_gid, uint32_t* nlen,
+                      hipStream_t s);
 
 // a6: N_k in CSC (one canonical column per group, in group order).
 void launch_emit_n(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
