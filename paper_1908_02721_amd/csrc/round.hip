@@ -26,6 +26,8 @@
 // singular vector positive and merges V*Sigma into the left neighbour.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -86,6 +88,34 @@ __global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv
   }
 }
 
+// A library-owned stream per device (default priority) for work off the critical
+// path; ordered against the caller's stream with events only.
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  TTS_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  TTS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  streams.emplace(dev, st);
+  return st;
+}
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    TTS_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    TTS_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 }  // namespace
 
 void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid) {
@@ -145,10 +175,22 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     rp = p;
     r[kb] = p;
   };
+  // The deflation residual of a bond is only read together with the next bond's
+  // pivot count, so it runs on a side stream next to the next bond's work (the
+  // single-workgroup pivoted Cholesky leaves the chip nearly idle).  Its inputs stay
+  // alive in `pend` until that read, which waits for it.  With caller allocator hooks
+  // (not stream-ordered) everything stays on the caller's stream.
+  const bool side = !A->hook_alloc;
+  const hipStream_t s2 = side ? side_stream() : s;
+  Allocator al2;
+  al2.stream = s2;
+  al2.budget = A->budget;
+  Allocator* A2 = side ? &al2 : A;
+  EventPair ev;  // a: the basis and W' are ready; b: the residual is done
   struct Pending {
     bool active = false;
     int k = 0, rows = 0, cols = 0;
-    DBuf<double> X, e2;
+    DBuf<double> X, Q, e2;
     DBuf<int32_t> ok;
   } pend;
   int32_t pok[4];
@@ -176,6 +218,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       TTS_HIP(hipMemcpyAsync(&rsel, cnt.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
     if (pend.active) {
+      if (side) TTS_HIP(hipStreamWaitEvent(s, ev.b, 0));
       TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
       TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
     }
@@ -206,11 +249,18 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
       trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
       gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
-      // residual of the basis, weighted by the right-part row norms
-      DBuf<double> E(A, static_cast<size_t>(rows) * cols);
-      copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s);
-      gemm(A, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s);
-      weighted_sumsq(A, E.get(), rows, cols, rows, w[k].get(), e2.get(), s);
+      // residual of the basis, weighted by the right-part row norms (side stream)
+      if (side) {
+        TTS_HIP(hipEventRecord(ev.a, s));
+        TTS_HIP(hipStreamWaitEvent(s2, ev.a, 0));
+      }
+      {
+        DBuf<double> E(A2, static_cast<size_t>(rows) * cols);
+        copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s2);
+        gemm(A2, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s2);
+        weighted_sumsq(A2, E.get(), rows, cols, rows, w[k].get(), e2.get(), s2);
+      }
+      if (side) TTS_HIP(hipEventRecord(ev.b, s2));
       // core k = Q reshaped to [r_{k-1}][n_k][r_k] (row-major) = Q^T column-major
       cores[k - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * rsel);
       transpose(Q.get(), rows, rsel, rows, reinterpret_cast<double*>(cores[k - 1].get()), rsel, s);
@@ -222,6 +272,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       pend.rows = rows;
       pend.cols = cols;
       pend.X = std::move(X);
+      pend.Q = std::move(Q);
       pend.ok = std::move(ok);
       pend.e2 = std::move(e2);
     } else {
@@ -230,6 +281,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     ++k;
   }
   if (pend.active) {  // the last bond's test
+    if (side) TTS_HIP(hipStreamWaitEvent(s, ev.b, 0));
     TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
