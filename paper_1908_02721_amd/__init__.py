@@ -134,10 +134,19 @@ class TT:
         }
 
 
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision: str = "fp64",
               max_rank: int = 0, keep_intermediates: bool = False, sparse_only: bool = False,
-              device_mem_budget: int = 0, stream=None) -> TT:
-    """Sparse TT decomposition of the COO tensor (idx int32 [nnz, d], val float64 [nnz], on cuda)."""
+              device_mem_budget: int = 0, stream=None, allocator=None) -> TT:
+    """Sparse TT decomposition of the COO tensor (idx int32 [nnz, d], val float64 [nnz], on cuda).
+
+    allocator: optional (alloc(nbytes) -> device pointer int, free(pointer int)) used for
+    every device allocation of the call and of the result (the tt_options hooks); it
+    must be ordered on `stream`, as torch's caching allocator is on the current stream.
+    """
     L = _lib.load()
     if not (idx.is_cuda and val.is_cuda):
         raise ValueError("idx and val must be cuda tensors")
@@ -156,12 +165,21 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     opt.keep_intermediates = int(bool(keep_intermediates))
     opt.sparse_only = int(bool(sparse_only))
     opt.device_mem_budget = int(device_mem_budget)
+    hooks = None
+    if allocator is not None:
+        a_fn, f_fn = allocator
+        hooks = (_ALLOC_T(lambda nbytes, ctx: int(a_fn(int(nbytes)) or 0)),
+                 _FREE_T(lambda ptr, ctx: f_fn(int(ptr))))
+        opt.alloc = ctypes.cast(hooks[0], ctypes.c_void_p)
+        opt.free = ctypes.cast(hooks[1], ctypes.c_void_p)
     dims_a = (ctypes.c_int64 * d)(*[int(x) for x in dims])
     h = ctypes.c_void_p()
     st = L.tt_sparse_decompose(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
                                float(eps), ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h))
     _lib.check(st)
-    return TT(h, dims)
+    tt = TT(h, dims)
+    tt._hooks = hooks  # the result frees through them in tt_free
+    return tt
 
 
 def _core_args(cores):
