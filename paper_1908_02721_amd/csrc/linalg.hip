@@ -1722,26 +1722,22 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
 // block pairs its kept column i with circulating column S/2 + (i + s) mod S/2.  The
 // phases pair every two columns exactly once in NC - 1 rounds, and per round a group
 // reads and writes only the circulating column (of A and of V) through LDS: half the
-// LDS traffic of an ordering in which both columns move.  Groups are GW lanes (8
-// for 64 columns, 16 for 32: NC / 2 groups, 256 threads; 16-lane groups over 512
-// threads measured slower for 64); a lane holds 64 / GW rows of a column as double2
-// pairs.
+// LDS traffic of an ordering in which both columns move.  Groups are
+// GW = 512 / NC lanes; a lane holds 64 / GW rows of a column as double2 pairs.
 // Padded columns are zero and never rotate.  Same rotation, stopping test and output
 // as k_jacobi64.
-template <int NC, int GW>
-__global__ __launch_bounds__(NC / 2 * GW) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
-                                                           double* __restrict__ Vg, int ldv,
-                                                           double* __restrict__ sigma) {
-  constexpr int NTH = NC / 2 * GW, LD = 64, UP = 32 / GW;
+template <int NC>
+__global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
+                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+  constexpr int NTH = 256, LD = 64, GW = 512 / NC, UP = 32 / GW;
   static_assert(NC == 32 || NC == 64, "32 or 64 columns");
-  static_assert(GW == 8 || GW == 16, "8 or 16 lanes per group");
   __shared__ double2 sA[NC * LD / 2];  // 64 x NC, column-major (rows >= `rows` zero)
   __shared__ double2 sV[NC * LD / 2];  // 64 x NC (identity outside the leading c x c block)
   __shared__ int rotated;
   double* A = reinterpret_cast<double*>(sA);
   double* V = reinterpret_cast<double*>(sV);
   {  // staging: each thread's loads are issued together (clamped addresses)
-    constexpr int PER = (NC * LD + NTH - 1) / NTH;
+    constexpr int PER = NC * LD / NTH;
     double v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -1751,10 +1747,8 @@ __global__ __launch_bounds__(NC / 2 * GW) void k_jacobi64h(double* __restrict__ 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
-      if (j < NC) {
-        A[e] = (i < rows && j < c) ? v[u] : 0.0;
-        V[e] = (i == j) ? 1.0 : 0.0;
-      }
+      A[e] = (i < rows && j < c) ? v[u] : 0.0;
+      V[e] = (i == j) ? 1.0 : 0.0;
     }
   }
   __syncthreads();
@@ -2273,12 +2267,12 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
             0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
   if (c > 32 && c <= 64 && rows <= 64) {
-    k_jacobi64h<64, 8><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    k_jacobi64h<64><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (c > 16 && c <= 32 && rows <= 64) {
-    k_jacobi64h<32, 16><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    k_jacobi64h<32><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
     TTS_LAUNCH_CHECK();
     return;
   }
