@@ -289,7 +289,8 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     ca.cols = cols.get();
     ca.colsuf = colsuf.get();
     ca.rmkey = rmkey.get();
-    launch_canon(ca, mi, st.get(), s);
+    // levels with long columns and few columns: a workgroup per column
+    launch_canon(ca, mi, st.get(), !level1 && hs.longcol && ncols <= 16384, s);
     // a5: group
     uint32_t tsize = 1;
     while (tsize < 2u * ncols + 2u) tsize <<= 1;

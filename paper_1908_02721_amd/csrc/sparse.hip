@@ -146,50 +146,20 @@ __global__ __launch_bounds__(NT) void k_permute(const uint64_t* __restrict__ per
   ev_out[e] = ev_in[src];
 }
 
-__global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
-  const uint32_t c = blockIdx.x * NT + threadIdx.x;
-  if (c >= a.ncols) return;
-  const uint32_t st = a.col_start[c], en = a.col_start[c + 1];
-  const uint32_t m = en - st;
-  uint64_t h = mix64(static_cast<uint64_t>(m) * 0x9e3779b97f4a7c15ull);
-  double s;
-  if (!a.sort_rows) {
-    s = a.ev[st];
-    for (uint32_t j = 0; j < m; ++j) {
-      const uint32_t rho = a.erho ? a.erho[st + j] : static_cast<uint32_t>(a.ekey[st + j] & a.rho_mask);
-      const double cv = a.ev[st + j] / s;
-      a.crho[st + j] = rho;
-      a.cval[st + j] = cv;
-      h = mix64(h ^ rho);
-      h = mix64(h ^ static_cast<uint64_t>(__double_as_longlong(cv)));
-    }
-  } else {
-    // at most kMaxLocal entries (checked by the host): insertion sort by rho
-    uint32_t rr[kMaxLocal];
-    double vv[kMaxLocal];
-    for (uint32_t j = 0; j < m; ++j) {
-      const uint32_t r = a.erho[st + j];
-      const double v = a.ev[st + j];
-      uint32_t t = j;
-      while (t > 0 && rr[t - 1] > r) {
-        rr[t] = rr[t - 1];
-        vv[t] = vv[t - 1];
-        --t;
-      }
-      rr[t] = r;
-      vv[t] = v;
-    }
-    s = vv[0];
-    for (uint32_t j = 0; j < m; ++j) {
-      const double cv = vv[j] / s;
-      a.crho[st + j] = rr[j];
-      a.cval[st + j] = cv;
-      h = mix64(h ^ rr[j]);
-      h = mix64(h ^ static_cast<uint64_t>(__double_as_longlong(cv)));
-    }
-  }
-  a.colhash[c] = h;
-  a.cols[c] = s;
+// Hash of a canonical column: a function of its length and of every (position,
+// row, canonical value), summed over the entries (mod 2^64) so that it can be formed
+// in any order, also in parallel.  Only a filter: equal hashes are verified entry by
+// entry before two columns are grouped.
+__device__ __forceinline__ uint64_t col_hash_term(uint32_t j, uint32_t rho, double cv) {
+  return mix64(mix64((static_cast<uint64_t>(j) << 32 | rho) ^ 0x9e3779b97f4a7c15ull) ^
+               static_cast<uint64_t>(__double_as_longlong(cv)));
+}
+__device__ __forceinline__ uint64_t col_hash_final(uint32_t m, uint64_t sum) {
+  return mix64(sum ^ mix64(static_cast<uint64_t>(m) * 0x9e3779b97f4a7c15ull));
+}
+
+// Suffix fields of column c: its packed suffix and its row-major key.
+__device__ __forceinline__ void col_keys(const CanonArgs& a, const ModeInfo& mi, uint32_t c, uint32_t st) {
   const uint64_t suf = a.ekey[st] >> a.sh;
   a.colsuf[c] = suf;
   uint64_t rm = 0;
@@ -201,11 +171,136 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   a.rmkey[c] = rm;
 }
 
+__global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
+  const uint32_t c = blockIdx.x * NT + threadIdx.x;
+  const bool active = c < a.ncols;
+  const uint32_t st = active ? a.col_start[c] : 0;
+  const uint32_t m = active ? a.col_start[c + 1] - st : 0;
+  uint64_t hs = 0;
+  double s = 0.0;
+  if (!a.sort_rows) {
+    // rows already ascending: eight entries at a time, each group's loads issued
+    // together (clamped addresses)
+    if (active) {
+      s = a.ev[st];
+      for (uint32_t j0 = 0; j0 < m; j0 += 8) {
+        uint32_t rr[8];
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t e = st + min(j0 + u, m - 1);
+          rr[u] = a.erho ? a.erho[e] : static_cast<uint32_t>(a.ekey[e] & a.rho_mask);
+          vv[u] = a.ev[e];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const uint32_t j = j0 + u;
+          if (j < m) {
+            const double cv = vv[u] / s;
+            a.crho[st + j] = rr[u];
+            a.cval[st + j] = cv;
+            hs += col_hash_term(j, rr[u], cv);
+          }
+        }
+      }
+    }
+  } else {
+    // at most kMaxLocal entries (checked by the host), all loaded at once; the rows
+    // of a column are distinct, so an entry's place in row order is the number of
+    // smaller rows.  Loops run to the wave's longest column, with fixed register
+    // indices throughout.
+    uint32_t mw = m;
+    for (int o = 32; o > 0; o >>= 1) mw = max(mw, static_cast<uint32_t>(__shfl_xor(mw, o, 64)));
+    uint32_t rr[kMaxLocal];
+    double vv[kMaxLocal];
+#pragma unroll
+    for (int j = 0; j < kMaxLocal; ++j) {
+      if (static_cast<uint32_t>(j) < mw) {
+        const uint32_t e = st + min(static_cast<uint32_t>(j), m > 0 ? m - 1 : 0u);
+        rr[j] = active ? a.erho[e] : 0u;
+        vv[j] = active ? a.ev[e] : 0.0;
+      } else {
+        rr[j] = 0u;
+        vv[j] = 0.0;
+      }
+    }
+    // value at the smallest row
+    uint32_t rmin = 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < kMaxLocal; ++j)
+      if (static_cast<uint32_t>(j) < m && rr[j] < rmin) {
+        rmin = rr[j];
+        s = vv[j];
+      }
+#pragma unroll
+    for (int j = 0; j < kMaxLocal; ++j) {
+      if (static_cast<uint32_t>(j) < mw) {
+        uint32_t rank = 0;
+#pragma unroll
+        for (int l = 0; l < kMaxLocal; ++l)
+          if (static_cast<uint32_t>(l) < mw) rank += (static_cast<uint32_t>(l) < m && rr[l] < rr[j]) ? 1u : 0u;
+        if (static_cast<uint32_t>(j) < m) {
+          const double cv = vv[j] / s;
+          a.crho[st + rank] = rr[j];
+          a.cval[st + rank] = cv;
+          hs += col_hash_term(rank, rr[j], cv);
+        }
+      }
+    }
+  }
+  if (!active) return;
+  a.colhash[c] = col_hash_final(m, hs);
+  a.cols[c] = s;
+  col_keys(a, mi, c, st);
+}
+
+// The same for levels whose columns are already in row order and include long ones:
+// one workgroup per column, its entries spread over the threads.
+__global__ __launch_bounds__(NT) void k_canon_wide(CanonArgs a, ModeInfo mi) {
+  __shared__ uint64_t red[NT / 64];
+  const uint32_t c = blockIdx.x;
+  const uint32_t st = a.col_start[c], en = a.col_start[c + 1];
+  const uint32_t m = en - st;
+  const double s = a.ev[st];
+  uint64_t hs = 0;
+  for (uint32_t j = threadIdx.x; j < m; j += NT) {
+    const uint32_t rho = a.erho ? a.erho[st + j] : static_cast<uint32_t>(a.ekey[st + j] & a.rho_mask);
+    const double cv = a.ev[st + j] / s;
+    a.crho[st + j] = rho;
+    a.cval[st + j] = cv;
+    hs += col_hash_term(j, rho, cv);
+  }
+  for (int o = 32; o > 0; o >>= 1) hs += __shfl_xor(hs, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = hs;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    a.colhash[c] = col_hash_final(m, t);
+    a.cols[c] = s;
+    col_keys(a, mi, c, st);
+  }
+}
+
+// Entry-by-entry equality of two canonical columns of m entries, eight entries at a
+// time with each group's loads issued together (clamped addresses).
 __device__ __forceinline__ bool same_column(const uint32_t* __restrict__ crho, const double* __restrict__ cval,
                                             uint32_t sa, uint32_t sb, uint32_t m) {
-  for (uint32_t j = 0; j < m; ++j) {
-    if (crho[sa + j] != crho[sb + j]) return false;
-    if (__double_as_longlong(cval[sa + j]) != __double_as_longlong(cval[sb + j])) return false;
+  for (uint32_t j0 = 0; j0 < m; j0 += 8) {
+    uint32_t ra[8], rb[8];
+    uint64_t va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t j = min(j0 + u, m - 1);
+      ra[u] = crho[sa + j];
+      rb[u] = crho[sb + j];
+      va[u] = static_cast<uint64_t>(__double_as_longlong(cval[sa + j]));
+      vb[u] = static_cast<uint64_t>(__double_as_longlong(cval[sb + j]));
+    }
+    bool eq = true;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) eq = eq && ra[u] == rb[u] && va[u] == vb[u];
+    if (!eq) return false;
   }
   return true;
 }
@@ -214,16 +309,16 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
                                               const double* __restrict__ cval, const uint32_t* __restrict__ col_start,
                                               const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
                                               uint64_t* slotmin, uint32_t tmask, uint32_t* __restrict__ slot,
-                                              uint32_t* __restrict__ isrep) {
+                                              uint32_t* __restrict__ isrep, int aggregate) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
-  if (c >= ncols) return;
-  const uint64_t h = colhash[c];
-  const uint32_t st = col_start[c];
-  const uint32_t m = col_start[c + 1] - st;
+  const bool active = c < ncols;
+  const uint64_t h = active ? colhash[c] : 0;
+  const uint32_t st = active ? col_start[c] : 0;
+  const uint32_t m = active ? col_start[c + 1] - st : 0;
   uint32_t p = static_cast<uint32_t>(h) & tmask;
   uint32_t rep = 0;
   // The table has more slots than columns, so an empty slot is always reached.
-  for (uint32_t probe = 0; probe <= tmask; ++probe) {
+  for (uint32_t probe = 0; active && probe <= tmask; ++probe) {
     uint64_t cur = __hip_atomic_load(&table[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cur == 0) {
       const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&table[p]), 0ull,
@@ -241,11 +336,36 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
     }
     p = (p + 1) & tmask;
   }
-  slot[c] = p;
-  isrep[c] = rep;
-  const uint64_t rk = rmkey[c];
-  if (rk < __hip_atomic_load(&slotmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p]), static_cast<unsigned long long>(rk));
+  if (active) {
+    slot[c] = p;
+    isrep[c] = rep;
+  }
+  // Group leader = smallest row-major key.  On large levels parallel columns share a
+  // few slots (a level can put 10^4 columns into one group), so the lanes of a wave
+  // first take the minimum per slot among themselves and one lane per slot updates
+  // memory; on small levels every lane updates its own slot.
+  const uint64_t rk = active ? rmkey[c] : ~0ull;
+  if (!aggregate) {
+    if (active && rk < __hip_atomic_load(&slotmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p]), static_cast<unsigned long long>(rk));
+    return;
+  }
+  const unsigned lane = threadIdx.x & 63;
+  uint64_t todo = __ballot(active);
+  while (todo) {
+    const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+    const uint32_t p0 = __shfl(p, lead, 64);
+    const bool mine = active && p == p0;
+    todo &= ~__ballot(mine);
+    uint64_t v = mine ? rk : ~0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint64_t w = __shfl_xor(v, o, 64);
+      v = w < v ? w : v;
+    }
+    if (static_cast<int>(lane) == lead &&
+        v < __hip_atomic_load(&slotmin[p0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p0]), static_cast<unsigned long long>(v));
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_rep_list(const uint32_t* __restrict__ isrep, const uint32_t* __restrict__ reppos,
@@ -369,13 +489,16 @@ void launch_permute_entries(const uint64_t* perm, uint32_t nE, const uint64_t* e
   TTS_LAUNCH_CHECK();
 }
 
-void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, hipStream_t s) {
+void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, bool wide, hipStream_t s) {
   if (!a.ncols) return;
   // per column: read its entries' (key, rho, value) once, write (rho, c) and the
   // column record (hash, s, suffix, row-major key) once -- the caller passes the
   // entry count through the column starts; bytes are estimated from ncols here
   KTimer kt("level_canon", s, 56.0 * a.ncols, 0.0);
-  k_canon<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
+  if (wide && !a.sort_rows)
+    k_canon_wide<<<a.ncols, NT, 0, s>>>(a, mi);
+  else
+    k_canon<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
   TTS_LAUNCH_CHECK();
 }
 
@@ -385,8 +508,9 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
   if (!ncols) return;
   // per column: read hash, start and row-major key, write slot and flag
   KTimer kt("level_group", s, 32.0 * ncols, 0.0);
+  // large levels: per-wave minima before the atomics (see k_group)
   k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
-                                             slot, isrep);
+                                             slot, isrep, ncols >= 65536 ? 1 : 0);
   TTS_LAUNCH_CHECK();
 }
 

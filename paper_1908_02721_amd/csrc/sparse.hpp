@@ -68,7 +68,9 @@ struct CanonArgs {
   uint64_t* rmkey;      // row-major-ordered suffix key (numbering order)
 };
 // a4: canonicalise every column by its entry of smallest row, key and hash it.
-void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus* st, hipStream_t s);
+// wide: one workgroup per column (for levels of few, long columns already in row
+// order); otherwise one lane per column.
+void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus* st, bool wide, hipStream_t s);
 
 // a5: group identical canonical columns (open-addressing table with full-key
 // verification), leader = smallest row-major suffix key of each group.
