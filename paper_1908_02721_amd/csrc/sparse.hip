@@ -368,6 +368,110 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
   }
 }
 
+// Probe of the global table for column c (hash h, m entries from st): returns the
+// slot of its group and whether c became the group's representative.
+__device__ __forceinline__ uint32_t global_probe(const uint64_t* __restrict__ colhash, const uint32_t* __restrict__ crho,
+                                                 const double* __restrict__ cval,
+                                                 const uint32_t* __restrict__ col_start, uint64_t* table, uint32_t tmask,
+                                                 uint32_t c, uint64_t h, uint32_t st, uint32_t m, uint32_t* rep) {
+  uint32_t p = static_cast<uint32_t>(h) & tmask;
+  *rep = 0;
+  for (uint32_t probe = 0; probe <= tmask; ++probe) {
+    uint64_t cur = __hip_atomic_load(&table[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == 0) {
+      const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&table[p]), 0ull,
+                                     static_cast<unsigned long long>(c) + 1ull);
+      if (old == 0) {
+        *rep = 1;
+        return p;
+      }
+      cur = old;
+    }
+    const uint32_t r = static_cast<uint32_t>(cur - 1);
+    if (colhash[r] == h) {
+      const uint32_t sr = col_start[r];
+      if (col_start[r + 1] - sr == m && same_column(crho, cval, sr, st, m)) return p;
+    }
+    p = (p + 1) & tmask;
+  }
+  return p;
+}
+
+// k_group for large levels, where parallel columns put many columns into few groups:
+// a workgroup first groups its GL_CH columns in an LDS table (full-key verification
+// against the chunk-local representative, minimum row-major key by LDS atomics),
+// then only one column per chunk-local group probes the global table, and the
+// group's minimum goes to memory once per chunk.  Same slots, representatives and
+// minima as k_group.
+constexpr int GL_CH = 2048, GL_TL = 4096, GL_PT = GL_CH / NT;
+__global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__ colhash,
+                                                    const uint32_t* __restrict__ crho, const double* __restrict__ cval,
+                                                    const uint32_t* __restrict__ col_start,
+                                                    const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
+                                                    uint64_t* slotmin, uint32_t tmask, uint32_t* __restrict__ slot,
+                                                    uint32_t* __restrict__ isrep) {
+  __shared__ uint32_t ltab[GL_TL];   // chunk-local representative + 1, 0 = empty
+  __shared__ uint32_t lglob[GL_TL];  // global slot of the local group
+  __shared__ uint32_t lrep[GL_TL];   // its representative is the global one
+  __shared__ unsigned long long lmin[GL_TL];
+  for (int e = threadIdx.x; e < GL_TL; e += NT) {
+    ltab[e] = 0u;
+    lmin[e] = ~0ull;
+  }
+  __syncthreads();
+  const uint32_t c0 = blockIdx.x * GL_CH;
+  uint32_t ls[GL_PT];
+  // local grouping
+  for (int u = 0; u < GL_PT; ++u) {
+    const uint32_t c = c0 + threadIdx.x + u * NT;
+    ls[u] = 0xffffffffu;
+    if (c >= ncols) continue;
+    const uint64_t h = colhash[c];
+    const uint32_t st = col_start[c];
+    const uint32_t m = col_start[c + 1] - st;
+    uint32_t q = static_cast<uint32_t>(h >> 32) & (GL_TL - 1);
+    for (int probe = 0; probe < GL_TL; ++probe) {  // at most GL_CH of GL_TL slots are used
+      uint32_t cur = ltab[q];
+      if (cur == 0u) {
+        const uint32_t old = atomicCAS(&ltab[q], 0u, c + 1u);
+        if (old == 0u) break;
+        cur = old;
+      }
+      const uint32_t r = cur - 1u;
+      if (colhash[r] == h) {
+        const uint32_t sr = col_start[r];
+        if (col_start[r + 1] - sr == m && same_column(crho, cval, sr, st, m)) break;
+      }
+      q = (q + 1u) & (GL_TL - 1);
+    }
+    ls[u] = q;
+    atomicMin(&lmin[q], static_cast<unsigned long long>(rmkey[c]));
+  }
+  __syncthreads();
+  // one global probe per chunk-local group (by its local representative)
+  for (int u = 0; u < GL_PT; ++u) {
+    const uint32_t c = c0 + threadIdx.x + u * NT;
+    if (ls[u] == 0xffffffffu || ltab[ls[u]] != c + 1u) continue;
+    const uint64_t h = colhash[c];
+    const uint32_t st = col_start[c];
+    const uint32_t m = col_start[c + 1] - st;
+    uint32_t rep;
+    const uint32_t p = global_probe(colhash, crho, cval, col_start, table, tmask, c, h, st, m, &rep);
+    lglob[ls[u]] = p;
+    lrep[ls[u]] = rep;
+    const unsigned long long v = lmin[ls[u]];
+    if (v < __hip_atomic_load(&slotmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p]), v);
+  }
+  __syncthreads();
+  for (int u = 0; u < GL_PT; ++u) {
+    const uint32_t c = c0 + threadIdx.x + u * NT;
+    if (ls[u] == 0xffffffffu) continue;
+    slot[c] = lglob[ls[u]];
+    isrep[c] = (ltab[ls[u]] == c + 1u) ? lrep[ls[u]] : 0u;
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_rep_list(const uint32_t* __restrict__ isrep, const uint32_t* __restrict__ reppos,
                                                  const uint32_t* __restrict__ slot, const uint64_t* __restrict__ slotmin,
                                                  uint32_t ncols, uint32_t cap, uint64_t* __restrict__ lkey,
@@ -508,9 +612,14 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
   if (!ncols) return;
   // per column: read hash, start and row-major key, write slot and flag
   KTimer kt("level_group", s, 32.0 * ncols, 0.0);
-  // large levels: per-wave minima before the atomics (see k_group)
-  k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
-                                             slot, isrep, ncols >= 65536 ? 1 : 0);
+  if (ncols >= 16384) {
+    // large levels: chunk-local grouping first (see k_group_local)
+    k_group_local<<<(ncols + GL_CH - 1) / GL_CH, NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table,
+                                                             slotmin, tmask, slot, isrep);
+  } else {
+    k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
+                                               slot, isrep, 0);
+  }
   TTS_LAUNCH_CHECK();
 }
 
