@@ -870,7 +870,7 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
                                                        int32_t* __restrict__ ok) {
   __shared__ double a[64][65];
   __shared__ double rdiag[64];  // reciprocals of the diagonal of the factor
-  __shared__ int bad;
+  __shared__ int bad, near_id;
   const int tid = threadIdx.x;
   {  // staging: the 16 loads of each thread are issued together (clamped addresses)
     double v[16];
@@ -885,8 +885,33 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
       a[i][j] = (i < r && j < r) ? v[u] : (i == j ? 1.0 : 0.0);
     }
   }
-  if (tid == 0) bad = 0;
+  if (tid == 0) {
+    bad = 0;
+    near_id = 1;
+  }
   __syncthreads();
+  // A = I + E with max |E_ij| <= 2^-34 (the second Gram of CholeskyQR2): its factor is
+  // I + triu(E, 1) + diag(E) / 2 up to terms below n max|E|^2 <= 2^-62, under the
+  // rounding of the entries, and needs no sequential steps
+  {
+    bool far = false;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+      if (i <= j && j < r) far = far || !(fabs(a[i][j] - (i == j ? 1.0 : 0.0)) <= 0x1p-34);
+    }
+    if (far) near_id = 0;
+  }
+  __syncthreads();
+  if (near_id) {
+    for (int e = tid; e < r * r; e += 256) {
+      const int i = e % r, j = e / r;
+      const double v = a[i][j];
+      Ag[i + static_cast<size_t>(j) * lda] = (i > j) ? 0.0 : (i == j ? 1.0 + 0.5 * (v - 1.0) : v);
+    }
+    if (tid == 0) *ok = 1;
+    return;
+  }
   const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   for (int J = 0; J < 4; ++J) {
     const int b = 16 * J;
