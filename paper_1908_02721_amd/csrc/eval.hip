@@ -881,70 +881,78 @@ struct Trie {
   mutable std::map<std::pair<int, int64_t>, ChunkList> chunks;
 };
 
-// Non-empty chunks of at most `cl` entries of every bucket (bucket by bucket): the
-// host vectors of make_chunk_host, uploaded as d[c] for c < n, with the chunks of
-// bucket i at [cstart[i], cstart[i + 1]).
-void make_chunk_host(const std::vector<int64_t>& off, int64_t cl, std::vector<ChunkDesc>& h,
-                     std::vector<int64_t>& cs) {
-  h.clear();
+// Non-empty chunks of at most `cl` entries of every bucket, bucket by bucket: d[c]
+// for c < n, the chunks of bucket i at [cstart[i], cstart[i + 1]).  The host counts
+// the chunks of each bucket from the bucket offsets (one value per bucket); the
+// descriptors themselves are written on the device.
+void chunk_starts_host(const std::vector<int64_t>& off, int64_t cl, std::vector<int64_t>& cs) {
   cs.assign(off.size(), 0);
+  int64_t n = 0;
   for (size_t i = 0; i + 1 < off.size(); ++i) {
-    cs[i] = static_cast<int64_t>(h.size());
-    for (int64_t b = off[i]; b < off[i + 1]; b += cl)
-      h.push_back(ChunkDesc{b, static_cast<uint32_t>(i), static_cast<uint32_t>(std::min<int64_t>(cl, off[i + 1] - b))});
+    cs[i] = n;
+    n += (off[i + 1] - off[i] + cl - 1) / cl;
   }
-  cs.back() = static_cast<int64_t>(h.size());
+  cs.back() = n;
 }
 
-// Builds the missing chunk lists among `keys` (depth, chunk length) and uploads them
-// together: one device block and one host-to-device copy for all of them.  The lists
-// are kept with the trie.
+__global__ __launch_bounds__(NT) void k_fill_chunks(const int64_t* __restrict__ off,
+                                                    const int64_t* __restrict__ cstart, int64_t cl,
+                                                    ChunkDesc* __restrict__ d) {
+  const int i = blockIdx.x;
+  const int64_t c0 = cstart[i], c1 = cstart[i + 1], o0 = off[i], o1 = off[i + 1];
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += NT) {
+    const int64_t b = o0 + (c - c0) * cl;
+    d[c] = ChunkDesc{b, static_cast<uint32_t>(i), static_cast<uint32_t>(min(cl, o1 - b))};
+  }
+}
+
+// Builds the missing chunk lists among `keys` (depth, chunk length): their chunk
+// starts go up in one small host-to-device copy, the descriptors are filled on the
+// device.  The lists are kept with the trie.
 void ensure_chunk_lists(const Trie& tr, const std::vector<std::pair<int, int64_t>>& keys, hipStream_t s) {
   std::vector<std::pair<int, int64_t>> todo;
   for (const auto& k : keys)
     if (tr.chunks.find(k) == tr.chunks.end() && std::find(todo.begin(), todo.end(), k) == todo.end())
       todo.push_back(k);
   if (todo.empty()) return;
-  std::vector<std::vector<ChunkDesc>> hd(todo.size());
-  std::vector<std::vector<int64_t>> hc(todo.size());
+  std::vector<int64_t> host, cs;
   std::vector<size_t> at(todo.size());
-  size_t bytes = 0;
+  std::vector<int64_t> nch(todo.size());
   for (size_t j = 0; j < todo.size(); ++j) {
-    make_chunk_host(tr.hoff[todo[j].first], todo[j].second, hd[j], hc[j]);
-    at[j] = bytes;
-    bytes += sizeof(ChunkDesc) * hd[j].size();
-    bytes += (sizeof(int64_t) * hc[j].size() + 15) / 16 * 16;  // keeps every list 16-byte aligned
+    chunk_starts_host(tr.hoff[todo[j].first], todo[j].second, cs);
+    at[j] = host.size();
+    nch[j] = cs.back();
+    host.insert(host.end(), cs.begin(), cs.end());
   }
-  std::vector<unsigned char> host(bytes);
-  for (size_t j = 0; j < todo.size(); ++j) {
-    std::copy(reinterpret_cast<const unsigned char*>(hd[j].data()),
-              reinterpret_cast<const unsigned char*>(hd[j].data() + hd[j].size()), host.begin() + at[j]);
-    std::copy(reinterpret_cast<const unsigned char*>(hc[j].data()),
-              reinterpret_cast<const unsigned char*>(hc[j].data() + hc[j].size()),
-              host.begin() + at[j] + sizeof(ChunkDesc) * hd[j].size());
-  }
-  unsigned char* dev = tr.owner->get<unsigned char>(bytes);
+  int64_t* dev = tr.owner->get<int64_t>(host.size());
   // a pageable-memory copy has consumed its source when the call returns
-  TTS_HIP(hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s));
+  TTS_HIP(hipMemcpyAsync(dev, host.data(), sizeof(int64_t) * host.size(), hipMemcpyHostToDevice, s));
   for (size_t j = 0; j < todo.size(); ++j) {
-    ChunkList c;
-    c.d = reinterpret_cast<const ChunkDesc*>(dev + at[j]);
-    c.n = static_cast<int64_t>(hd[j].size());
-    c.cstart = reinterpret_cast<const int64_t*>(dev + at[j] + sizeof(ChunkDesc) * hd[j].size());
-    tr.chunks.emplace(todo[j], c);
+    const int t = todo[j].first;
+    const int nk = static_cast<int>(tr.hoff[t].size()) - 1;
+    ChunkDesc* d = tr.owner->get<ChunkDesc>(std::max<int64_t>(nch[j], 1));
+    if (nch[j] > 0) {
+      k_fill_chunks<<<nk, NT, 0, s>>>(tr.boff[t], dev + at[j], todo[j].second, d);
+      TTS_LAUNCH_CHECK();
+    }
+    tr.chunks.emplace(todo[j], ChunkList{d, nch[j], dev + at[j]});
   }
 }
 
-// One chunk list, uploaded into `mem` (entry-by-entry path, no trie).
-ChunkList make_chunk_list(const std::vector<int64_t>& off, int64_t cl, DevMem& mem, hipStream_t s) {
-  std::vector<ChunkDesc> h;
+// One chunk list for the bucket offsets `off` (device) and `hoff` (host), in `mem`
+// (entry-by-entry path, no trie).
+ChunkList make_chunk_list(const int64_t* off, const std::vector<int64_t>& hoff, int64_t cl, DevMem& mem,
+                          hipStream_t s) {
   std::vector<int64_t> cs;
-  make_chunk_host(off, cl, h, cs);
-  ChunkDesc* dptr = mem.get<ChunkDesc>(std::max<size_t>(h.size(), 1));
+  chunk_starts_host(hoff, cl, cs);
   int64_t* cptr = mem.get<int64_t>(cs.size());
-  if (!h.empty()) TTS_HIP(hipMemcpyAsync(dptr, h.data(), sizeof(ChunkDesc) * h.size(), hipMemcpyHostToDevice, s));
   TTS_HIP(hipMemcpyAsync(cptr, cs.data(), sizeof(int64_t) * cs.size(), hipMemcpyHostToDevice, s));
-  return ChunkList{dptr, static_cast<int64_t>(h.size()), cptr};
+  ChunkDesc* d = mem.get<ChunkDesc>(std::max<int64_t>(cs.back(), 1));
+  if (cs.back() > 0) {
+    k_fill_chunks<<<static_cast<unsigned>(hoff.size() - 1), NT, 0, s>>>(off, cptr, cl, d);
+    TTS_LAUNCH_CHECK();
+  }
+  return ChunkList{d, cs.back(), cptr};
 }
 
 // Chunk length of a bucket product with O output columns (0: the narrow kernel,
@@ -1129,17 +1137,28 @@ void bucket_product(const Trie& tr, int t, int nk, int K, int O, int64_t sK, int
   TTS_LAUNCH_CHECK();
 }
 
+// The chunk lists a backward uses: the up pass's bucket products and the gradients.
+template <typename T>
+void backward_chunk_keys(const EvalDesc& ed, const Trie& tr, std::vector<std::pair<int, int64_t>>& keys) {
+  constexpr int KC = sizeof(T) == 8 ? 32 : 64;
+  const int d = ed.d;
+  for (int t = d - 1; t >= 1; --t)
+    if (ed.r[t + 1] > 4 && bucket_chunk(ed.r[t]) > 0) keys.emplace_back(t + 1, bucket_chunk(ed.r[t]));
+  for (int t = 0; t < d; ++t) keys.emplace_back(t + 1, grad_chunk(ed.r[t], ed.r[t + 1], tr.P[t + 1], KC));
+}
+
 template <typename T>
 void trie_forward(const EvalDesc& ed, Trie& tr, DevMem& mem, Allocator* al, std::vector<T*>& Lv, hipStream_t s) {
   const int d = ed.d;
   if (tr.bperm.empty()) build_buckets(ed, tr, mem, mem, al, s);
-  {  // the chunk lists of this pass, uploaded together
+  {  // the chunk lists of this pass and of a backward, uploaded together
     std::vector<std::pair<int, int64_t>> keys;
     for (int t = 1; t <= d; ++t) {
       const int r0 = ed.r[t - 1], r1 = ed.r[t];
       const size_t core_bytes = sizeof(T) * static_cast<size_t>(r0) * ed.n[t - 1] * r1;
       if (!(r1 < 16 && core_bytes <= 48 * 1024) && bucket_chunk(r1) > 0) keys.emplace_back(t, bucket_chunk(r1));
     }
+    backward_chunk_keys<T>(ed, tr, keys);
     ensure_chunk_lists(tr, keys, s);
   }
   Lv.assign(d + 1, nullptr);
@@ -1194,11 +1213,9 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
   const int d = ed.d;
   const int64_t m = tr.m;
   constexpr int KC = sizeof(T) == 8 ? 32 : 64;  // 33 KB of LDS: four workgroups per CU
-  {  // the chunk lists of the up pass and the gradients, uploaded together
+  {  // the chunk lists of the up pass and the gradients (normally uploaded by the forward)
     std::vector<std::pair<int, int64_t>> keys;
-    for (int t = d - 1; t >= 1; --t)
-      if (ed.r[t + 1] > 4 && bucket_chunk(ed.r[t]) > 0) keys.emplace_back(t + 1, bucket_chunk(ed.r[t]));
-    for (int t = 0; t < d; ++t) keys.emplace_back(t + 1, grad_chunk(ed.r[t], ed.r[t + 1], tr.P[t + 1], KC));
+    backward_chunk_keys<T>(ed, tr, keys);
     ensure_chunk_lists(tr, keys, s);
   }
   // up vectors, bottom-up
@@ -1361,7 +1378,7 @@ tt_status direct_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T
     TTS_HIP(hipMemcpyAsync(hoff.data(), off, sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
-    const ChunkList ch = make_chunk_list(hoff, grad_chunk_len(m, tiles, KC), mem, s);
+    const ChunkList ch = make_chunk_list(off, hoff, grad_chunk_len(m, tiles, KC), mem, s);
     T* part = mem.get<T>(static_cast<size_t>(std::max<int64_t>(ch.n, 1)) * r0 * r1);
     const int64_t lo = (k >= 1) ? ed.loff[k] : -1;              // l_k (k >= 1); l_0 = 1
     const int64_t ro = (k + 1 <= d - 1) ? ed.roff[k + 1] : -1;  // r_{k+1}; r_d = 1
