@@ -54,6 +54,8 @@ def _parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="kron8d_n32_t64")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    p.add_argument("--dynamic-delta", action="store_true",
+                   help="per-bond truncation thresholds from the remaining error budget (Algorithm 8)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
     p.add_argument("--roofline", default="auto",
@@ -63,7 +65,7 @@ def _parse():
     return p.parse_args()
 
 
-def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", max_rank=0):
+def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", max_rank=0, dynamic=False):
     """The oracle (single-threaded FP64 C++), timed on this host on a bounded sample.
 
     Also returns ||B_gpu - B_oracle||_F / ||A||_F for the GPU result `gpu_cores`
@@ -73,7 +75,7 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
 
     oracle.build(force=False)
     t0 = time.perf_counter()
-    res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank)
+    res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic)
     t_dec = time.perf_counter() - t0
     rng = np.random.Generator(np.random.PCG64(11))
     pick = rng.choice(len(val), min(sample, len(val)), replace=False)
@@ -156,7 +158,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        tt = tts.decompose(gi, gv, dims, eps, precision=args.precision)
+        tt = tts.decompose(gi, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta)
         cores = tt.cores
         gy = gv if cores[0].dtype == torch.float64 else gv.float()
         # one plan per step: the sort and trie of the coordinates serve the forward and
@@ -216,7 +218,7 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else args.precision,
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "nnz": nnz, "eps": eps,
-                   "precision": args.precision, "ranks": tt.ranks},
+                   "precision": args.precision, "dynamic_delta": bool(args.dynamic_delta), "ranks": tt.ranks},
         "decompose_ms_median": float(np.median(dec_ms)),
         "decompose_nnz_per_s": nnz / (float(np.median(dec_ms)) / 1000.0),
         "stage_ms": tt.times_ms,
@@ -249,7 +251,8 @@ def main():
     if not args.no_cpu_baseline:
         cores_host = [c.cpu().numpy() for c in tt.cores]
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample,
-                                                                   cores_host, args.precision)
+                                                                   cores_host, args.precision,
+                                                                   dynamic=args.dynamic_delta)
     print(json.dumps(out), flush=True)
 
 

@@ -73,6 +73,14 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
   void* alloc_ctx;
+  int32_t dynamic_delta;      /* 0: the same threshold eps*||A||_F/sqrt(d-1) at every
+                                 bond (Algorithm 2); 1: thresholds from the budget
+                                 left by the bonds already truncated (Algorithm 8,
+                                 Sec. 3.5): with j bonds to go, rem/sqrt(j), then
+                                 rem^2 -= the bond's discarded sum of sigma^2, from
+                                 rem = eps*||A||_F.  Same eps guarantee (the
+                                 correctness theorem of Algorithm 8), usually lower
+                                 ranks.  Ignored with max_rank > 0. */
 } tt_options;
 
 typedef struct tt_result_s* tt_result; /* opaque, owned by the library */
@@ -125,6 +133,11 @@ tt_status tt_get_sparse_ranks(tt_result r, int64_t* betas, int64_t* qr_ranks);
    sum of squares.  Not available with sparse_only. */
 tt_status tt_get_sigma(tt_result r, int32_t b, int64_t* count, const double** host_sigma,
                        double* tail);
+
+/* Truncation threshold used at bond b (1..d-1): eps*||A||_F/sqrt(d-1), or with
+   dynamic_delta the one Algorithm 8 gave that bond (unused with max_rank > 0).
+   TT_ERR_ARG for a sparse_only result or b out of range. */
+tt_status tt_get_bond_delta(tt_result r, int32_t b, double* delta);
 
 /* Stage times in milliseconds (host_ms[TT_NUM_STAGES]), measured with HIP events
    on the call's stream: ingest, sort, sparse levels, QR sweep, SVD sweep, total. */

@@ -61,7 +61,7 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             P = ctypes.POINTER
             i32, i64, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
-            lib.orc_decompose.argtypes = [i32, P(i64), i64, P(ctypes.c_int32), P(f64), f64, i32, i32, P(vp)]
+            lib.orc_decompose.argtypes = [i32, P(i64), i64, P(ctypes.c_int32), P(f64), f64, i32, i32, i32, P(vp)]
             lib.orc_decompose.restype = ctypes.c_int
             lib.orc_free.argtypes = [vp]
             lib.orc_summary.argtypes = [vp, P(i64), P(f64), P(f64)]
@@ -75,6 +75,8 @@ def _load():
             lib.orc_sigma_count.argtypes = [vp, i32]
             lib.orc_sigma_count.restype = i64
             lib.orc_sigma.argtypes = [vp, i32, P(f64), P(f64)]
+            lib.orc_bond_delta.argtypes = [vp, i32]
+            lib.orc_bond_delta.restype = f64
             lib.orc_eval.argtypes = [i32, P(i64), P(i64), P(P(f64)), i64, P(i32), P(f64)]
             lib.orc_eval.restype = ctypes.c_int
             lib.orc_eval_grad.argtypes = [i32, P(i64), P(i64), P(P(f64)), i64, P(i32), P(f64), P(P(f64))]
@@ -113,6 +115,7 @@ class OracleResult:
     cores: list = None                                # dense [r_{k-1}, n_k, r_k]
     sigma: list = None                                # sigma[b-1]
     tail: list = None
+    bond_delta: list = None                           # threshold used at bond b-1
     times: tuple = None
 
     @property
@@ -135,7 +138,8 @@ class OracleResult:
         return cores
 
 
-def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True) -> OracleResult:
+def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True,
+              dynamic_delta: bool = False) -> OracleResult:
     lib = _load()
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -146,7 +150,7 @@ def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True) -> 
         raise ValueError("idx must be [nnz, d]")
     h = ctypes.c_void_p()
     st = lib.orc_decompose(d, _p(dims_a, ctypes.c_int64), nnz, _p(idx, ctypes.c_int32), _p(val, ctypes.c_double),
-                           float(eps), int(max_rank), int(bool(do_round)), ctypes.byref(h))
+                           float(eps), int(max_rank), int(bool(do_round)), int(bool(dynamic_delta)), ctypes.byref(h))
     if st != 0:
         raise OracleError(st)
     try:
@@ -185,6 +189,7 @@ def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True) -> 
                 lib.orc_core(h, k, _p(c, ctypes.c_double))
                 res.cores.append(c.reshape(res.ranks[k - 1], dims[k - 1], res.ranks[k]))
             res.sigma, res.tail = [], []
+            res.bond_delta = [lib.orc_bond_delta(h, b) for b in range(1, d)]
             for b in range(1, d):
                 cnt = lib.orc_sigma_count(h, b)
                 sg = np.zeros(cnt)

@@ -36,6 +36,11 @@
 //     (Sec. 3.4) keeps min(max_rank, #nonzero sigma) instead.  In each kept left
 //     singular vector the entry of largest magnitude (lowest index on ties) is made
 //     positive.
+//     Dynamic truncation (Algorithm 8, Sec. 3.5), read for this sweep direction:
+//     the whole budget eps*||A||_F is spent by the one SVD sweep (Algorithm 8 with
+//     p = d has an empty first loop, so delta_left = eps*||A||_F).  With j bonds
+//     still to truncate, the bond's threshold is rem/sqrt(j); after the bond, rem^2
+//     loses the discarded sum of sigma^2.
 //  5. Entry evaluation a_i = G1[i1] G2[i2] ... Gd[id] (Sec. 2.3) and its gradient by
 //     the product rule, with explicit left and right partial products.
 
@@ -230,13 +235,14 @@ struct orc_result_s {
   std::vector<std::vector<double>> cores;
   std::vector<std::vector<double>> sigma;  // sigma[b-1], bond b = 1..d-1
   std::vector<double> tail;
+  std::vector<double> bond_delta;          // threshold used at bond b = 1..d-1
 };
 
 extern "C" {
 
 int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                   const double* val, double eps, int32_t max_rank, int32_t do_round,
-                  orc_result** out) {
+                  int32_t dynamic_delta, orc_result** out) {
   if (!out) return ORC_ERR_ARG;
   *out = nullptr;
   if (d < 2 || !dims || nnz < 0 || (nnz > 0 && (!idx || !val))) return ORC_ERR_ARG;
@@ -424,10 +430,16 @@ int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* id
   t0 = Clock::now();
   res->sigma.assign(d - 1, {});
   res->tail.assign(d - 1, 0.0);
-  const double delta2 = res->delta * res->delta;
+  const double delta_static2 = res->delta * res->delta;
+  // remaining budget of Algorithm 8 (squared): eps^2 ||A||_F^2 before the first bond
+  double rem2 = (eps * res->norm) * (eps * res->norm);
+  res->bond_delta.assign(d - 1, 0.0);
   for (int32_t k = d; k >= 2; --k) {
     const int64_t rl = r[k - 1], nk = n[k - 1], rr = r[k];
     const int64_t m = nk * rr;  // rows of unfold_1^T
+    // bonds k-1, k-2, ..., 1 are still to be truncated: k-1 of them
+    const double delta2 = dynamic_delta ? rem2 / static_cast<double>(k - 1) : delta_static2;
+    res->bond_delta[k - 2] = std::sqrt(delta2);
     // gmat: column-major m x rl, column alpha = row alpha of unfold_1.
     std::vector<double> gmat(G[k - 1]);
     std::vector<double> V;
@@ -458,6 +470,7 @@ int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* id
     }
     res->sigma[k - 2] = ss_sorted;
     res->tail[k - 2] = tailsum[rk];
+    rem2 = std::max(0.0, rem2 - tailsum[rk]);
     // U (m x rk) and V*Sigma (rl x rk) with the sign rule.
     std::vector<double> U(static_cast<size_t>(m * rk)), VS(static_cast<size_t>(rl * rk));
     for (int64_t j = 0; j < rk; ++j) {
@@ -540,6 +553,8 @@ void orc_sigma(const orc_result* r, int32_t b, double* sig, double* tail) {
   std::copy(r->sigma[b - 1].begin(), r->sigma[b - 1].end(), sig);
   *tail = r->tail[b - 1];
 }
+
+double orc_bond_delta(const orc_result* r, int32_t b) { return r->bond_delta[b - 1]; }
 
 int orc_eval(int32_t d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
              int64_t m, const int32_t* idx, double* y) {

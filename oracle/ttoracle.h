@@ -39,10 +39,12 @@ typedef struct orc_result_s orc_result;
  *   max_rank : 0 = truncate by eps; > 0 = fixed-rank truncation (eps ignored)
  *   do_round : 0 = stop after the exact sparse TT (parallel-vector rounding);
  *              1 = also run the QR and truncated-SVD sweeps.
+ *   dynamic_delta : 0 = the same threshold eps*||A||_F/sqrt(d-1) at every bond;
+ *              1 = thresholds from the remaining budget (Algorithm 8).
  * On success *out owns every result; release with orc_free. */
 int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                   const double* val, double eps, int32_t max_rank, int32_t do_round,
-                  orc_result** out);
+                  int32_t dynamic_delta, orc_result** out);
 void orc_free(orc_result* r);
 
 /* Summary.  info[0] = nnz kept, info[1] = rounded (0/1).
@@ -70,6 +72,8 @@ void orc_qr_ranks(const orc_result* r, int64_t* ranks);
  * non-ascending; count via orc_sigma_count.  tail = discarded sum of sigma^2. */
 int64_t orc_sigma_count(const orc_result* r, int32_t b);
 void orc_sigma(const orc_result* r, int32_t b, double* sig, double* tail);
+/* Truncation threshold used at bond b (1..d-1) (unused in fixed-rank mode). */
+double orc_bond_delta(const orc_result* r, int32_t b);
 
 /* Entries y[m] of a TT at coordinates idx [m][d] (FP64). */
 int orc_eval(int32_t d, const int64_t* dims, const int64_t* ranks, const double* const* cores,

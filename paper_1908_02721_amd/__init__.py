@@ -112,6 +112,13 @@ class TT:
         sig = np.ctypeslib.as_array(ptr, shape=(cnt.value,)).copy() if cnt.value else np.zeros(0)
         return sig, tail.value
 
+    def bond_delta(self, b: int) -> float:
+        """Truncation threshold used at bond b (1..d-1)."""
+        L = _lib.load()
+        x = ctypes.c_double()
+        _lib.check(L.tt_get_bond_delta(self._h, b, ctypes.byref(x)))
+        return x.value
+
     def level(self, k: int):
         """Level k (1..d-1) of the sparse stage (needs keep_intermediates=True)."""
         L = _lib.load()
@@ -140,12 +147,14 @@ _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision: str = "fp64",
               max_rank: int = 0, keep_intermediates: bool = False, sparse_only: bool = False,
-              device_mem_budget: int = 0, stream=None, allocator=None) -> TT:
+              device_mem_budget: int = 0, stream=None, allocator=None, dynamic_delta: bool = False) -> TT:
     """Sparse TT decomposition of the COO tensor (idx int32 [nnz, d], val float64 [nnz], on cuda).
 
     allocator: optional (alloc(nbytes) -> device pointer int, free(pointer int)) used for
     every device allocation of the call and of the result (the tt_options hooks); it
     must be ordered on `stream`, as torch's caching allocator is on the current stream.
+    dynamic_delta: per-bond truncation thresholds from the remaining error budget
+    (Algorithm 8) instead of eps ||A|| / sqrt(d-1) at every bond.
     """
     L = _lib.load()
     if not (idx.is_cuda and val.is_cuda):
@@ -165,6 +174,7 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     opt.keep_intermediates = int(bool(keep_intermediates))
     opt.sparse_only = int(bool(sparse_only))
     opt.device_mem_budget = int(device_mem_budget)
+    opt.dynamic_delta = int(bool(dynamic_delta))
     hooks = None
     if allocator is not None:
         a_fn, f_fn = allocator

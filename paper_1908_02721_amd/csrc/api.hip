@@ -162,6 +162,7 @@ struct tt_result_s {
   int32_t dtype = TT_DTYPE_F64;
   std::vector<std::vector<double>> sigma;
   std::vector<double> tail;
+  std::vector<double> bond_delta;
   double ms[TT_NUM_STAGES] = {};
 };
 
@@ -496,6 +497,7 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     in.delta = R->delta;
     in.norm = R->norm;
     in.max_rank = o.max_rank;
+    in.dynamic_delta = o.dynamic_delta != 0;
     in.precision = o.precision;
     for (int k = 1; k <= d - 1; ++k) {
       const LevelData& L = R->lev[k - 1];
@@ -520,6 +522,7 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
       R->dtype = ro.dtype;
       R->sigma = std::move(ro.sigma);
       R->tail = std::move(ro.tail);
+      R->bond_delta = std::move(ro.bond_delta);
       R->rounded = 1;
       TTS_HIP(hipEventRecord(ev.e[5], s));
     }
@@ -616,6 +619,16 @@ tt_status tt_get_sigma(tt_result r, int32_t b, int64_t* count, const double** ho
   if (count) *count = static_cast<int64_t>(r->sigma[b - 1].size());
   if (host_sigma) *host_sigma = r->sigma[b - 1].data();
   if (tail) *tail = r->tail[b - 1];
+  return TT_OK;
+}
+
+tt_status tt_get_bond_delta(tt_result r, int32_t b, double* delta) {
+  if (!r || b < 1 || b >= r->d || !delta) return TT_ERR_ARG;
+  if (!r->rounded) {
+    set_error("no truncation thresholds: sparse_only result");
+    return TT_ERR_ARG;
+  }
+  *delta = r->bond_delta[b - 1];
   return TT_OK;
 }
 

@@ -13,6 +13,7 @@ struct RoundInput {
   std::vector<int64_t> betas;              // ranks of the exact sparse TT, d+1
   double eps = 0.0, delta = 0.0, norm = 0.0;
   int max_rank = 0;
+  bool dynamic_delta = false;  // per-bond thresholds from the remaining budget (Alg 8)
   int precision = TT_FP64;
   // N_k (k = 1..d-1), CSC, rows rho = g_{k-1} * n_k + i_k
   std::vector<const int64_t*> n_colptr;
@@ -28,6 +29,7 @@ struct RoundOutput {
   int32_t dtype = TT_DTYPE_F64;
   std::vector<std::vector<double>> sigma;  // sigma[b-1]
   std::vector<double> tail;                // discarded sum of sigma^2 per bond
+  std::vector<double> bond_delta;          // truncation threshold used per bond
 };
 
 // Rounds the exact TT.  Records `mid` on the stream between the QR sweep and the

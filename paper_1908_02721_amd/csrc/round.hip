@@ -302,10 +302,18 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   // ---------------- right-to-left truncated SVD sweep ----------------
   out.sigma.assign(d - 1, {});
   out.tail.assign(d - 1, 0.0);
-  const double delta2 = in.delta * in.delta;
+  out.bond_delta.assign(d - 1, 0.0);
+  // Truncation thresholds.  Fixed: delta = eps ||A||_F / sqrt(d-1) at every bond.
+  // Dynamic (Algorithm 8, Sec. 3.5; with this sweep order its first loop is empty,
+  // so the whole budget eps ||A||_F goes to this one sweep): with j bonds still to
+  // truncate the threshold is rem / sqrt(j), and rem^2 then loses what the bond
+  // discarded.  The discarded sums of all bonds stay within eps^2 ||A||_F^2.
+  double rem2 = (in.eps * in.norm) * (in.eps * in.norm);
   for (int k = d; k >= 2; --k) {
     const int rl = static_cast<int>(r[k - 1]), nk = n[k - 1], rr = static_cast<int>(r[k]);
     const int m = nk * rr;
+    const double delta2 = in.dynamic_delta ? rem2 / static_cast<double>(k - 1) : in.delta * in.delta;
+    out.bond_delta[k - 2] = std::sqrt(delta2);
     double* Gk = reinterpret_cast<double*>(cores[k - 1].get());  // column-major m x rl
     // G = Q R (m > rl) or G itself; one-sided Jacobi then runs on the transpose,
     // Bt = R^T or G^T (rl x cB): Bt U_R = V_R Sigma, so the accumulated rotations
@@ -379,6 +387,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     rk = std::min(rk, cB);
     out.sigma[k - 2] = ss;
     out.tail[k - 2] = tailsum[rk];
+    rem2 = std::max(0.0, rem2 - tailsum[rk]);
     DBuf<double> UR(A, static_cast<size_t>(cB) * rk), VS(A, static_cast<size_t>(rl) * rk);
     permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
     permute_cols(Bt.get(), rl, rl, dperm.get(), nullptr, rk, VS.get(), rl, s);

@@ -118,15 +118,19 @@ def tt_full(cores):
     return X.reshape(X.shape[:-1] if X.shape[-1] == 1 else X.shape)
 
 
-def tt_svd_right_to_left(A, eps=None, ranks_fixed=None):
+def tt_svd_right_to_left(A, eps=None, ranks_fixed=None, dynamic=False):
     """Dense TT-SVD (Algorithm 1) run from the last mode to the first, LAPACK SVDs.
 
+    dynamic: thresholds of Algorithm 8 (Sec. 3.5) instead of one fixed threshold:
+    the budget (eps ||A||)^2, less what earlier bonds discarded, shared evenly by
+    the bonds still to come.
     Returns (ranks [1, r_1, ..., r_{d-1}, 1], sigma per bond b = 1..d-1).
     """
     d = A.ndim
     n = A.shape
     nrm = np.linalg.norm(A.reshape(-1))
     delta = 0.0 if eps is None else eps * nrm / np.sqrt(d - 1)
+    budget = 0.0 if eps is None else (eps * nrm) ** 2
     ranks = [1] * (d + 1)
     sig = [None] * (d - 1)
     C = A.reshape(-1)
@@ -138,7 +142,9 @@ def tt_svd_right_to_left(A, eps=None, ranks_fixed=None):
             r = max(1, min(int(ranks_fixed), int(np.sum(S > 0))))
         else:
             tail = np.concatenate([np.cumsum((S * S)[::-1])[::-1], [0.0]])
-            r = next(rr for rr in range(1, S.size + 1) if tail[rr] <= delta * delta)
+            thr2 = budget / (k - 1) if dynamic else delta * delta
+            r = next(rr for rr in range(1, S.size + 1) if tail[rr] <= thr2)
+            budget = max(0.0, budget - tail[r])
         sig[k - 2] = S
         ranks[k - 1] = r
         C = U[:, :r] * S[:r]

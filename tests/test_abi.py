@@ -85,6 +85,29 @@ def test_null_handles(lib):
     r = (ctypes.c_int64 * 4)()
     assert lib.tt_get_ranks(None, r) == 1
     assert lib.tt_get_core(None, 1, ctypes.byref(ctypes.c_void_p()), None) == 1
+    assert lib.tt_get_bond_delta(None, 1, ctypes.byref(ctypes.c_double())) == 1
+
+
+def test_options_layout_matches_header(tmp_path):
+    """The ctypes mirror of tt_options has the C struct's size and field offsets."""
+    import shutil
+    import subprocess
+
+    from paper_1908_02721_amd import _lib
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in _lib.tt_options._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"ttsparse.h\"\nint main(void) {\n"
+                   + "".join(f'  printf("%zu\\n", offsetof(tt_options, {f}));\n' for f in fields)
+                   + '  printf("%zu\\n", sizeof(tt_options));\n  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = [getattr(_lib.tt_options, f).offset for f in fields] + [ctypes.sizeof(_lib.tt_options)]
+    assert got == want
 
 
 def test_eval_host_argument_errors(lib):

@@ -30,14 +30,19 @@ def _gpu(idx, val):
         torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).cuda()
 
 
-def check_round(oracle_mod, idx, val, dims, eps, label, max_rank=0, samples=4096, dense=None):
+def check_round(oracle_mod, idx, val, dims, eps, label, max_rank=0, samples=4096, dense=None, dynamic=False):
     tts = _tt()
-    print(f"[round parity] {label} dims={tuple(dims)} nnz={len(val)} eps={eps} max_rank={max_rank}", flush=True)
-    res = oracle_mod.decompose(idx, val, dims, eps, max_rank=max_rank)
+    print(f"[round parity] {label} dims={tuple(dims)} nnz={len(val)} eps={eps} max_rank={max_rank} "
+          f"dynamic={dynamic}", flush=True)
+    res = oracle_mod.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic)
     gi, gv = _gpu(idx, val)
-    tt = tts.decompose(gi, gv, dims, eps, max_rank=max_rank)
+    tt = tts.decompose(gi, gv, dims, eps, max_rank=max_rank, dynamic_delta=dynamic)
     nrm = res.norm
     assert tt.ranks == res.ranks, (tt.ranks, res.ranks)
+    if max_rank == 0:
+        for b in range(1, len(dims)):
+            # thresholds follow from the discarded sums, which agree to round-off
+            assert abs(tt.bond_delta(b) ** 2 - res.bond_delta[b - 1] ** 2) <= TOL * nrm * nrm, f"bond {b} delta"
     for b in range(1, len(dims)):
         sg, tail = tt.sigma(b)
         so = res.sigma[b - 1]
@@ -157,3 +162,48 @@ def test_deflation_rejected_and_redone(oracle_mod):
     # every bond fell back to the exact QR: an accepted deflation would stop at the
     # 5 dominant directions, the exact QR keeps all min(rows, cols)
     assert tt.qr_ranks == res.qr_ranks
+
+
+# ---- dynamic truncation thresholds (Algorithm 8) ----
+
+@pytest.mark.parametrize("name,seed,dims,nnz,eps", CASES)
+def test_dynamic_delta_small_random(oracle_mod, name, seed, dims, nnz, eps):
+    idx, val, dims = synth.random_sparse(dims, nnz, seed)
+    tt, res = check_round(oracle_mod, idx, val, dims, eps, name, dense=True, dynamic=True)
+    # the budget is never overdrawn
+    tails = [tt.sigma(b)[1] for b in range(1, len(dims))]
+    assert sum(tails) <= (eps * res.norm) ** 2 * (1 + 1e-12) + 1e-24 * res.norm ** 2
+
+
+def test_dynamic_delta_superdiagonal():
+    """Singular values (1, 0.5, 0.1) at both bonds, eps^2 = 0.012: the fixed threshold
+    keeps all three everywhere, the dynamic one drops 0.1 at bond 1 (budget argument
+    of Algorithm 8, worked out in the oracle's pin)."""
+    tts = _tt()
+    idx = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], dtype=np.int32)
+    val = np.array([1.0, 0.5, 0.1])
+    gi, gv = _gpu(idx, val)
+    eps = float(np.sqrt(0.012))
+    print("[round parity] superdiagonal 3x3x3 dynamic", flush=True)
+    assert tts.decompose(gi, gv, (3, 3, 3), eps).ranks == [1, 3, 3, 1]
+    tt = tts.decompose(gi, gv, (3, 3, 3), eps, dynamic_delta=True)
+    assert tt.ranks == [1, 2, 3, 1]
+    assert abs(tt.bond_delta(2) ** 2 - 0.00756) <= 1e-15 and abs(tt.bond_delta(1) ** 2 - 0.01512) <= 1e-15
+    B = _brute.tt_full([c.cpu().numpy() for c in tt.cores])
+    A = _brute.dense_tensor(idx, val, (3, 3, 3))
+    assert abs(np.linalg.norm(A - B) - 0.1) <= 1e-14
+
+
+def test_dynamic_delta_random4d_truncating(oracle_mod):
+    idx, val, dims, _ = synth.workload("random4d_n20_nnz1k")
+    tt, res = check_round(oracle_mod, idx, val, dims, 0.3, "random4d_n20_nnz1k eps=0.3", dense=True, dynamic=True)
+    st = oracle_mod.decompose(idx, val, dims, 0.3)
+    print(f"[round parity] ranks fixed {st.ranks} dynamic {tt.ranks}", flush=True)
+    assert tt.ranks[len(dims) - 1] == st.ranks[len(dims) - 1]
+
+
+def test_dynamic_delta_kron_truncating(oracle_mod):
+    idx, val, dims = synth.kronecker_sum(6, 10, 6, 3, seed=4)
+    # at eps = 0.4 the fixed thresholds give ranks [1, 5, 6, 6, 6, 5, 1], the dynamic ones lower
+    tt, _ = check_round(oracle_mod, idx, val, dims, 0.4, "kron d6 t6 eps=0.4", dense=True, dynamic=True)
+    assert tt.ranks == [1, 3, 5, 6, 6, 5, 1]

@@ -137,3 +137,61 @@ def test_fdm_mpo_ranks_table2(oracle_mod, case):
     assert len(val) == case["nnz"]
     res = oracle_mod.decompose(idx, val, dims, 1e-14)
     assert res.ranks == [1] + case["final_ranks"] + [1]
+
+
+# ---- dynamic truncation thresholds (Algorithm 8, Theorem 10) ----
+
+def test_dynamic_delta_superdiagonal_closed_form(oracle_mod):
+    # A = e0 x e0 x e0 + 0.5 e1 x e1 x e1 + 0.1 e2 x e2 x e2: both unfoldings have
+    # singular values (1, 0.5, 0.1), ||A||^2 = 1.26.  With eps^2 = 0.012 the fixed
+    # threshold delta^2 = eps^2 ||A||^2 / 2 = 0.00756 keeps 0.1 (0.01 > 0.00756) at
+    # both bonds.  The dynamic one keeps it at bond 2 as well (same threshold first),
+    # discards nothing there, and so offers the whole budget eps^2 ||A||^2 = 0.01512
+    # to bond 1, which then drops 0.1 (0.01 <= 0.01512) but not 0.5.
+    idx = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], dtype=np.int32)
+    val = np.array([1.0, 0.5, 0.1])
+    eps = np.sqrt(0.012)
+    st = oracle_mod.decompose(idx, val, (3, 3, 3), eps)
+    dy = oracle_mod.decompose(idx, val, (3, 3, 3), eps, dynamic_delta=True)
+    assert st.ranks == [1, 3, 3, 1]
+    assert dy.ranks == [1, 2, 3, 1]
+    assert dy.tail[1] == 0.0 and abs(dy.tail[0] - 0.01) <= 1e-15
+    assert abs(dy.bond_delta[1] ** 2 - 0.00756) <= 1e-15
+    assert abs(dy.bond_delta[0] ** 2 - 0.01512) <= 1e-15
+    B = _brute.tt_full(dy.cores)
+    A = _brute.dense_tensor(idx, val, (3, 3, 3))
+    assert abs(np.linalg.norm(A - B) - 0.1) <= 1e-14
+
+
+@pytest.mark.parametrize("name,seed,dims,nnz,kind,eps", CASES)
+def test_dynamic_delta_matches_dense_and_theorem10(oracle_mod, name, seed, dims, nnz, kind, eps):
+    idx, val, dims = _sparse(seed, dims, nnz, kind)
+    st = oracle_mod.decompose(idx, val, dims, eps)
+    dy = oracle_mod.decompose(idx, val, dims, eps, dynamic_delta=True)
+    A = _brute.dense_tensor(idx, val, dims)
+    nrm = np.linalg.norm(A)
+    ranks, _ = _brute.tt_svd_right_to_left(A, eps, dynamic=True)
+    assert dy.ranks == ranks
+    d = len(dims)
+    # the first bond truncated (bond d-1) sees the same threshold in both modes
+    assert dy.ranks[d - 1] == st.ranks[d - 1]
+    assert abs(dy.bond_delta[d - 2] - st.delta) <= 1e-15 * nrm
+    # every later threshold is at least the fixed one (loop invariant of Theorem 10)
+    assert all(x >= st.delta * (1 - 1e-14) for x in dy.bond_delta)
+    # Theorem 10: ||A - B|| <= eps ||A||; the discarded sums stay within the budget
+    B = _brute.tt_full(dy.cores)
+    err = np.linalg.norm(A - B)
+    assert err <= eps * nrm + 1e-13 * nrm
+    assert sum(dy.tail) <= (eps * nrm) ** 2 * (1 + 1e-12) + 1e-26
+    assert abs(err ** 2 - sum(dy.tail)) <= 1e-13 * nrm ** 2
+
+
+def test_dynamic_delta_two_modes_is_static(oracle_mod):
+    # d = 2: one bond, whose threshold is eps ||A|| in both modes
+    idx, val, dims = _sparse(12, (9, 11), 60)
+    for eps in (1e-12, 0.2, 0.5):
+        st = oracle_mod.decompose(idx, val, dims, eps)
+        dy = oracle_mod.decompose(idx, val, dims, eps, dynamic_delta=True)
+        assert st.ranks == dy.ranks
+        for a, b in zip(st.cores, dy.cores):
+            assert np.array_equal(a, b)
