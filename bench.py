@@ -1,6 +1,7 @@
 """Benchmark of the sparse TT decomposition hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
+                    [--dynamic-delta] [--matrix-input] [--roofline FAMILY]
 
 One step is one pass of the whole hot path over the workload's nonzeros, all in
 libttsparse kernels:
@@ -9,6 +10,9 @@ libttsparse kernels:
   tt_eval_plan_create   sort of the nonzero coordinates and their prefix trie
   tt_eval_plan_forward  the TT at every nonzero coordinate (left products kept)
   tt_eval_plan_backward gradient of sum_n val[n] * TT(i_n) w.r.t. every core
+With --matrix-input (the Laplacian workload) the step starts from the sparse matrix
+and first runs tt_matrix_to_tensor, the front-end of the MPO form.  With
+--dynamic-delta the truncation thresholds follow Algorithm 8.
 Inputs are resident in HBM before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -35,7 +39,7 @@ BF16_PEAK_TFLOPS = 2500.0  # dense
 FAMILY_BOUND = {
     "jacobi": "alu", "eval_forward": "alu", "eval_up": "alu", "eval_grad": "alu", "cholesky": "alu",
     "trsm": "alu", "gemm": "mfma", "gemm_lp": "mfma",
-    "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm",
+    "sort_scatter": "hbm", "level_group": "hbm", "level_canon": "hbm", "mpo_coords": "hbm",
 }
 # Families whose every launch is one workgroup (one CU of 256): their roofline line
 # also states the fraction of one CU's share of the peak.
@@ -54,6 +58,9 @@ def _parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="kron8d_n32_t64")
     p.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    p.add_argument("--matrix-input", action="store_true",
+                   help="start from the workload's sparse matrix (laplace2d_qtt_L10): the step then also runs the "
+                        "matrix -> tensor front-end of the MPO form")
     p.add_argument("--dynamic-delta", action="store_true",
                    help="per-bond truncation thresholds from the remaining error budget (Algorithm 8)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -155,15 +162,22 @@ def main():
     nnz = len(val)
     gi = torch.from_numpy(np.ascontiguousarray(idx)).cuda()
     gv = torch.from_numpy(np.ascontiguousarray(val)).cuda()
-    stream = torch.cuda.current_stream()
+    matrix = None
+    if args.matrix_input:
+        if synth.WORKLOADS[args.workload]["kind"] != "laplace":
+            sys.exit("--matrix-input needs a workload with a matrix form (laplace2d_qtt_L10)")
+        r, c, v, m_dims, n_dims = synth.laplacian_matrix(synth.WORKLOADS[args.workload]["L"])
+        matrix = (torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), m_dims, n_dims)
+        gv = torch.from_numpy(np.ascontiguousarray(v)).cuda()
 
     def step():
-        tt = tts.decompose(gi, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta)
+        ci = tts.matrix_to_tensor(*matrix) if matrix is not None else gi
+        tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta)
         cores = tt.cores
         gy = gv if cores[0].dtype == torch.float64 else gv.float()
         # one plan per step: the sort and trie of the coordinates serve the forward and
         # the backward, and the backward reuses the forward's left products
-        plan = tts.EvalPlan(gi, dims)
+        plan = tts.EvalPlan(ci, dims)
         y = plan.forward(cores, save=True)
         grads = plan.backward(cores, gy, use_saved=True)
         return tt, y, grads
@@ -218,7 +232,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else args.precision,
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "nnz": nnz, "eps": eps,
-                   "precision": args.precision, "dynamic_delta": bool(args.dynamic_delta), "ranks": tt.ranks},
+                   "precision": args.precision, "dynamic_delta": bool(args.dynamic_delta),
+                   "matrix_input": bool(args.matrix_input), "ranks": tt.ranks},
         "decompose_ms_median": float(np.median(dec_ms)),
         "decompose_nnz_per_s": nnz / (float(np.median(dec_ms)) / 1000.0),
         "stage_ms": tt.times_ms,

@@ -113,6 +113,28 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
                               const double* val, double eps, const tt_options* opt, void* stream,
                               tt_result* out);
 
+/*
+ * Matrix -> tensor coordinates for the matrix-in-TT-format (MPO) front-end
+ * (Sec. 3.4, matrices in TT-format).  An M x N matrix, M = m_1...m_d,
+ * N = n_1...n_d, is the d-way tensor with modes of size m_k n_k: the row index
+ * has digits (i_1..i_d) in the mixed radix (m_1..m_d), the column index digits
+ * (j_1..j_d) in (n_1..n_d), first digit most significant, and mode k holds
+ * i_k n_k + j_k.  Decomposing that tensor (tt_sparse_decompose with dims
+ * m_k n_k) gives the MPO; core k reshaped to [r_{k-1}][m_k][n_k][r_k] is the
+ * MPO core.
+ *   d        : 1 <= d <= TT_MAX_D
+ *   row_dims : host int64[d] (m_k), col_dims : host int64[d] (n_k); each >= 1 with
+ *              m_k n_k <= 2^31-1 (else TT_ERR_ARG); M, N <= 2^63 (else TT_ERR_TOO_LARGE)
+ *   rows, cols : device int64[nnz] (borrowed); nnz in [0, 2^31)
+ *   idx      : device int32[nnz][d], caller-owned, row-major, overwritten; entry e
+ *              of the output belongs to entry e of the input (values need no copy)
+ * A row outside [0, M) or a column outside [0, N) gives TT_ERR_INDEX (the
+ * contents of idx are then unspecified).  Enqueued on `stream`; the call waits
+ * for its one 4-byte read-back of that check.
+ */
+tt_status tt_matrix_to_tensor(int32_t d, const int64_t* row_dims, const int64_t* col_dims, int64_t nnz,
+                              const int64_t* rows, const int64_t* cols, int32_t* idx, void* stream);
+
 /* Final TT-ranks, host int64[d+1] (r_0 = r_d = 1). */
 tt_status tt_get_ranks(tt_result r, int64_t* ranks);
 

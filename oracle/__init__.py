@@ -13,6 +13,12 @@ Parity status per function (see the pins in ``tests/test_oracle_*.py``):
                                LAPACK on tiny tensors, error bound, Pythagorean
                                error identity, orthonormality, known QTT ranks of
                                the 2D Laplacian, FDM matrix ranks printed in the paper.
+  decompose (dynamic delta) -- pinned: a worked case with closed-form singular
+                               values, dense TT-SVD with the same thresholds, the
+                               bound of Algorithm 8's correctness theorem.
+  matrix_coords (MPO)       -- pinned: dense reshape/transpose of tiny matrices,
+                               the quantized Laplacian and FDM layouts built from
+                               grid coordinates, MPO matrix-vector products.
   eval / eval_grad          -- pinned: dense reconstruction, rank-1 closed form,
                                central finite differences.
   tt_diff_norm              -- pinned: dense subtraction on tiny tensors.
@@ -256,3 +262,32 @@ def tt_diff_norm(cores_a, cores_b) -> float:
     ab, pb = _core_ptrs(cores_b)
     return float(lib.orc_tt_diff_norm(d, _p(dims, ctypes.c_int64), _p(ra, ctypes.c_int64), pa,
                                       _p(rb, ctypes.c_int64), pb))
+
+
+def matrix_coords(rows, cols, row_dims, col_dims) -> np.ndarray:
+    """Tensor coordinates of matrix entries (matrix in TT format, Sec. 3.4).
+
+    The M x N matrix, M = m_1...m_d, N = n_1...n_d, is the tensor of order 2d with
+    indices (i_1, j_1, ..., i_d, j_d): (i_k) are the digits of the row index in the
+    radix (m_1..m_d), (j_k) those of the column index in (n_1..n_d), first digit most
+    significant.  Mode k of the d-way tensor merges (i_k, j_k) into i_k n_k + j_k.
+    Returns int32 [nnz, d]; raises IndexError for an index outside the matrix.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    m = [int(x) for x in row_dims]
+    n = [int(x) for x in col_dims]
+    M = int(np.prod(np.array(m, dtype=object)))
+    N = int(np.prod(np.array(n, dtype=object)))
+    if rows.size and (rows.min() < 0 or int(rows.max()) >= M or cols.min() < 0 or int(cols.max()) >= N):
+        raise IndexError("row or column index outside the matrix")
+    d = len(m)
+    out = np.empty((rows.size, d), dtype=np.int64)
+    # digits from the least significant (mode d) to the most significant (mode 1)
+    I = rows.astype(object) if M >= 2 ** 62 else rows.copy()
+    J = cols.astype(object) if N >= 2 ** 62 else cols.copy()
+    for k in range(d - 1, -1, -1):
+        ik, I = I % m[k], I // m[k]
+        jk, J = J % n[k], J // n[k]
+        out[:, k] = np.asarray(ik, dtype=np.int64) * n[k] + np.asarray(jk, dtype=np.int64)
+    return out.astype(np.int32)

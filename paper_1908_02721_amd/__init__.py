@@ -7,6 +7,8 @@ arguments (PyTorch provides device memory and streams).
     tt = decompose(idx, val, dims, eps)          # idx int32 [nnz, d], val float64 [nnz] on cuda
     tt.ranks, tt.cores                            # cores [r_{k-1}, n_k, r_k]
     y = EvalEntries.apply(idx, *cores)            # TT entries at idx, differentiable
+    mpo = decompose_matrix(rows, cols, val, row_dims, col_dims, eps)   # sparse matrix -> MPO
+    mpo.mpo_cores()                               # [r_{k-1}, m_k, n_k, r_k]
 """
 from __future__ import annotations
 
@@ -17,7 +19,8 @@ import torch
 from . import _lib
 from ._lib import STAGES, TTError
 
-__all__ = ["decompose", "TT", "eval_entries", "eval_entries_backward", "EvalPlan", "EvalEntries", "TTError", "library_path"]
+__all__ = ["decompose", "decompose_matrix", "matrix_to_tensor", "TT", "eval_entries", "eval_entries_backward",
+           "EvalPlan", "EvalEntries", "TTError", "library_path"]
 
 library_path = _lib.LIB_PATH
 
@@ -74,6 +77,7 @@ class TT:
         _lib.check(L.tt_get_times(self._h, t))
         self.times_ms = dict(zip(STAGES, (float(x) for x in t)))
         self._cores = None
+        self.row_dims = self.col_dims = None  # set for a matrix decomposed as an MPO
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -111,6 +115,12 @@ class TT:
 
         sig = np.ctypeslib.as_array(ptr, shape=(cnt.value,)).copy() if cnt.value else np.zeros(0)
         return sig, tail.value
+
+    def mpo_cores(self):
+        """Cores of a matrix decomposed by decompose_matrix, viewed as [r_{k-1}, m_k, n_k, r_k]."""
+        if self.row_dims is None:
+            raise ValueError("not a matrix decomposition (use decompose_matrix)")
+        return [c.view(c.shape[0], m, n, c.shape[2]) for c, m, n in zip(self.cores, self.row_dims, self.col_dims)]
 
     def bond_delta(self, b: int) -> float:
         """Truncation threshold used at bond b (1..d-1)."""
@@ -189,6 +199,50 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     _lib.check(st)
     tt = TT(h, dims)
     tt._hooks = hooks  # the result frees through them in tt_free
+    return tt
+
+
+def matrix_to_tensor(rows: torch.Tensor, cols: torch.Tensor, row_dims, col_dims, stream=None) -> torch.Tensor:
+    """Tensor coordinates of matrix entries for the MPO front-end (tt_matrix_to_tensor).
+
+    rows, cols: int64 [nnz] on cuda.  Returns int32 [nnz, d] with mode k index
+    i_k * n_k + j_k, where (i_k) and (j_k) are the mixed-radix digits of the row
+    and column index in (m_1..m_d) and (n_1..n_d), first digit most significant.
+    """
+    L = _lib.load()
+    if not (rows.is_cuda and cols.is_cuda):
+        raise ValueError("rows and cols must be cuda tensors")
+    if rows.dtype != torch.int64 or cols.dtype != torch.int64:
+        raise TypeError("rows and cols must be int64")
+    rows = rows.contiguous()
+    cols = cols.contiguous()
+    d = len(row_dims)
+    if len(col_dims) != d:
+        raise ValueError("row_dims and col_dims must have the same length")
+    nnz = int(rows.numel())
+    if int(cols.numel()) != nnz:
+        raise ValueError("rows and cols must have the same length")
+    idx = torch.empty((nnz, d), dtype=torch.int32, device=rows.device)
+    ra = (ctypes.c_int64 * d)(*[int(x) for x in row_dims])
+    ca = (ctypes.c_int64 * d)(*[int(x) for x in col_dims])
+    _lib.check(L.tt_matrix_to_tensor(d, ra, ca, nnz, ctypes.c_void_p(rows.data_ptr()), ctypes.c_void_p(cols.data_ptr()),
+                                     ctypes.c_void_p(idx.data_ptr()), _stream_handle(stream)))
+    return idx
+
+
+def decompose_matrix(rows: torch.Tensor, cols: torch.Tensor, val: torch.Tensor, row_dims, col_dims, eps: float,
+                     stream=None, **kw) -> TT:
+    """Matrix in TT format (MPO) of a sparse M x N matrix, M = prod(row_dims), N = prod(col_dims).
+
+    The matrix becomes the tensor with modes m_k * n_k (matrix_to_tensor), which is
+    decomposed with the same options as ``decompose``; ``TT.mpo_cores()`` gives the
+    cores as [r_{k-1}, m_k, n_k, r_k].
+    """
+    idx = matrix_to_tensor(rows, cols, row_dims, col_dims, stream=stream)
+    dims = [int(m) * int(n) for m, n in zip(row_dims, col_dims)]
+    tt = decompose(idx, val, dims, eps, stream=stream, **kw)
+    tt.row_dims = tuple(int(x) for x in row_dims)
+    tt.col_dims = tuple(int(x) for x in col_dims)
     return tt
 
 

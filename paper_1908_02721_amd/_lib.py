@@ -52,7 +52,7 @@ class tt_options(ctypes.Structure):
 
 EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
-    "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_bond_delta", "tt_get_times", "tt_get_level", "tt_free",
+    "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_bond_delta", "tt_get_times", "tt_matrix_to_tensor", "tt_get_level", "tt_free",
     "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_plan_create", "tt_eval_plan_forward",
     "tt_eval_plan_backward", "tt_eval_plan_free", "tt_status_string", "tt_last_error",
     "tt_kernel_timer_start", "tt_kernel_timer_read",
@@ -86,6 +86,8 @@ def load():
         L.tt_get_sigma.restype = ctypes.c_int
         L.tt_get_bond_delta.argtypes = [vp, i32, P(f64)]
         L.tt_get_bond_delta.restype = ctypes.c_int
+        L.tt_matrix_to_tensor.argtypes = [i32, P(i64), P(i64), i64, vp, vp, vp, vp]
+        L.tt_matrix_to_tensor.restype = ctypes.c_int
         L.tt_get_times.argtypes = [vp, P(f64)]
         L.tt_get_times.restype = ctypes.c_int
         L.tt_get_level.argtypes = [vp, i32, P(i64), P(i64), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp)]

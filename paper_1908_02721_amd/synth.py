@@ -31,7 +31,9 @@ import numpy as np
 __all__ = [
     "random_sparse",
     "kronecker_sum",
+    "laplacian_matrix",
     "laplacian_qtt",
+    "fdm3d_matrix",
     "fdm3d_mpo",
     "unravel",
     "checksum",
@@ -102,13 +104,13 @@ def kronecker_sum(d: int, n: int, terms: int, q: int, seed: int, continuous: boo
     return unravel(uniq, dims), acc, dims
 
 
-def laplacian_qtt(L: int):
-    """2D Dirichlet 5-point Laplacian on a 2^L x 2^L grid in quantized-TT layout.
+def laplacian_matrix(L: int):
+    """2D Dirichlet 5-point Laplacian on a 2^L x 2^L grid as a sparse matrix.
 
     Matrix index I = x * 2^L + y.  Entries: 4 on the diagonal, -1 between grid
-    neighbours.  The tensor has 2L modes of size 4; mode k (1-based) holds
-    2 * bit_{2L-k}(I) + bit_{2L-k}(J), i.e. x bits first, most significant first.
-    nnz = 5 * 4^L - 4 * 2^L.
+    neighbours.  Returns (rows int64, cols int64, vals, row_dims, col_dims) with
+    row_dims = col_dims = (2,) * 2L (the binary digits of the index, the quantized
+    layout).  nnz = 5 * 4^L - 4 * 2^L.
     """
     side = 1 << L
     x, y = np.meshgrid(np.arange(side, dtype=np.int64), np.arange(side, dtype=np.int64), indexing="ij")
@@ -124,7 +126,17 @@ def laplacian_qtt(L: int):
         vals.append(np.full(int(ok.sum()), -1.0))
     r = np.concatenate(rows)
     c = np.concatenate(cols)
-    v = np.concatenate(vals)
+    v = np.concatenate(vals).astype(np.float64)
+    return r, c, v, (2,) * (2 * L), (2,) * (2 * L)
+
+
+def laplacian_qtt(L: int):
+    """The matrix of ``laplacian_matrix(L)`` in quantized-TT layout.
+
+    The tensor has 2L modes of size 4; mode k (1-based) holds
+    2 * bit_{2L-k}(I) + bit_{2L-k}(J), i.e. x bits first, most significant first.
+    """
+    r, c, v, _, _ = laplacian_matrix(L)
     d = 2 * L
     idx = np.empty((r.size, d), dtype=np.int32)
     for k in range(1, d + 1):
@@ -133,14 +145,8 @@ def laplacian_qtt(L: int):
     return idx, v.astype(np.float64), (4,) * d
 
 
-def fdm3d_mpo(n: int, coeff: str = "pattern", seed: int = 0):
-    """3D 7-point finite-difference matrix on an n x n x n grid, as a 3-way tensor.
-
-    Grid point p = (x, y, z), matrix index I = (x * n + y) * n + z.  ``pattern``:
-    6 on the diagonal and -1 for each neighbour; ``random``: every stored entry
-    N(0,1).  The tensor modes are (x, x'), (y, y'), (z, z'), each of size n^2 with
-    index a * n + a'.  nnz = n^3 + 6 n^2 (n - 1).
-    """
+def _fdm3d_stencil(n: int, coeff: str, seed: int):
+    """Grid coordinates of both ends of every stored entry, and its value."""
     rng = np.random.Generator(np.random.PCG64(seed))
     g = np.arange(n, dtype=np.int64)
     x, y, z = np.meshgrid(g, g, g, indexing="ij")
@@ -156,8 +162,30 @@ def fdm3d_mpo(n: int, coeff: str = "pattern", seed: int = 0):
         v = rng.standard_normal(v.size)
     elif coeff != "pattern":
         raise ValueError("coeff must be 'pattern' or 'random'")
+    return xa, ya, za, xb, yb, zb, v.astype(np.float64)
+
+
+def fdm3d_matrix(n: int, coeff: str = "pattern", seed: int = 0):
+    """3D 7-point finite-difference matrix on an n x n x n grid as a sparse matrix.
+
+    Grid point p = (x, y, z), matrix index I = (x * n + y) * n + z.  ``pattern``:
+    6 on the diagonal and -1 for each neighbour; ``random``: every stored entry
+    N(0,1).  Returns (rows int64, cols int64, vals, row_dims, col_dims) with
+    row_dims = col_dims = (n, n, n).  nnz = n^3 + 6 n^2 (n - 1).
+    """
+    xa, ya, za, xb, yb, zb, v = _fdm3d_stencil(n, coeff, seed)
+    return (xa * n + ya) * n + za, (xb * n + yb) * n + zb, v, (n,) * 3, (n,) * 3
+
+
+def fdm3d_mpo(n: int, coeff: str = "pattern", seed: int = 0):
+    """The matrix of ``fdm3d_matrix`` as a 3-way tensor.
+
+    The tensor modes are (x, x'), (y, y'), (z, z'), each of size n^2 with index
+    a * n + a'.
+    """
+    xa, ya, za, xb, yb, zb, v = _fdm3d_stencil(n, coeff, seed)
     idx = np.stack([xa * n + xb, ya * n + yb, za * n + zb], axis=1).astype(np.int32)
-    return idx, v.astype(np.float64), (n * n,) * 3
+    return idx, v, (n * n,) * 3
 
 
 def checksum(idx: np.ndarray, val: np.ndarray, dims) -> str:

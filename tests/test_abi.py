@@ -88,6 +88,28 @@ def test_null_handles(lib):
     assert lib.tt_get_bond_delta(None, 1, ctypes.byref(ctypes.c_double())) == 1
 
 
+def test_matrix_to_tensor_host_argument_errors(lib):
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+
+    def call(d, m, n, nnz=4, rows=fake, cols=fake, idx=fake):
+        ma = (ctypes.c_int64 * max(1, len(m)))(*m)
+        na = (ctypes.c_int64 * max(1, len(n)))(*n)
+        return lib.tt_matrix_to_tensor(d, ma, na, nnz, rows, cols, idx, None)
+
+    assert call(0, [2], [2]) == 1                      # d < 1
+    assert call(65, [2] * 65, [2] * 65) == 1           # d > 64
+    assert call(2, [2, 0], [2, 2]) == 1                # m_k < 1
+    assert call(2, [2, 2], [2, -1]) == 1               # n_k < 1
+    assert call(2, [1 << 16, 2], [1 << 15, 2]) == 1    # m_k n_k > 2^31 - 1
+    assert call(2, [2, 2], [2, 2], nnz=-1) == 1
+    assert call(2, [2, 2], [2, 2], rows=None) == 1
+    assert call(2, [2, 2], [2, 2], idx=None) == 1
+    assert call(2, [1 << 31, 2], [1, 1]) == 1          # m_k above 2^31 - 1
+    assert call(3, [1 << 30, 1 << 30, 1 << 30], [1, 1, 1]) == 6  # M above 2^63
+    assert len(lib.tt_last_error()) > 0
+    assert call(2, [2, 2], [2, 2], nnz=0, rows=None, cols=None, idx=None) == 0  # nothing to do
+
+
 def test_options_layout_matches_header(tmp_path):
     """The ctypes mirror of tt_options has the C struct's size and field offsets."""
     import shutil

@@ -1,0 +1,135 @@
+"""GPU parity of the matrix -> tensor front-end (matrix in TT format, Sec. 3.4).
+
+Coordinates are integer work: bit-exact against the oracle's mapping.  The MPO
+decomposition then runs the unchanged decomposition path and is held to the same
+bar as every other decomposition (tests/test_gpu_round.py).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_02721_amd import synth
+from tests import _brute
+from tests.test_gpu_round import check_round
+
+pytestmark = pytest.mark.gpu
+
+
+def _tts():
+    import paper_1908_02721_amd as tts
+
+    return tts
+
+
+def _coords_gpu(rows, cols, m, n):
+    tts = _tts()
+    r = torch.from_numpy(np.ascontiguousarray(rows, dtype=np.int64)).cuda()
+    c = torch.from_numpy(np.ascontiguousarray(cols, dtype=np.int64)).cuda()
+    return tts.matrix_to_tensor(r, c, m, n).cpu().numpy()
+
+
+def _random_entries(m, n, nnz, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M, N = int(np.prod(np.array(m, dtype=object))), int(np.prod(np.array(n, dtype=object)))
+    rows = rng.integers(0, M, nnz, dtype=np.int64, endpoint=False) if M < 2 ** 63 else \
+        rng.integers(0, 2 ** 63 - 1, nnz, dtype=np.int64)
+    cols = rng.integers(0, N, nnz, dtype=np.int64)
+    return rows, cols
+
+
+CASES = [
+    ("2x2 modes, ragged tail", (3, 4), (5, 2), 256 * 7 + 13, 1),
+    ("d=3 mixed radix", (2, 3, 2), (3, 1, 4), 1000, 2),
+    ("d=1", (7,), (5,), 300, 3),
+    ("rows above 2^32", (70000, 70000), (3, 5), 4096 + 5, 4),
+    ("d=64, M = 2^63", (2,) * 63 + (1,), (1,) * 63 + (3,), 2 * 256 + 1, 5),
+    ("one entry", (4, 4), (4, 4), 1, 6),
+]
+
+
+@pytest.mark.parametrize("label,m,n,nnz,seed", CASES)
+def test_coords_bit_exact(oracle_mod, label, m, n, nnz, seed):
+    print(f"[mpo coords] {label} m={m[:4]}.. n={n[:4]}.. nnz={nnz}", flush=True)
+    rows, cols = _random_entries(m, n, nnz, seed)
+    got = _coords_gpu(rows, cols, m, n)
+    want = oracle_mod.matrix_coords(rows, cols, m, n)
+    assert got.dtype == np.int32 and got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_unaligned_output(oracle_mod):
+    """An output buffer at a 4-byte but not 16-byte aligned address (the scalar store path)."""
+    import ctypes
+
+    from paper_1908_02721_amd import _lib
+
+    m, n, nnz = (3, 4, 5), (2, 7, 3), 256 * 3 + 7
+    rows, cols = _random_entries(m, n, nnz, 8)
+    r = torch.from_numpy(rows).cuda()
+    c = torch.from_numpy(cols).cuda()
+    buf = torch.full((nnz * 3 + 8,), -7, dtype=torch.int32, device="cuda")
+    sub = buf[1:1 + nnz * 3]
+    assert sub.data_ptr() % 16 != 0
+    L = _lib.load()
+    ra = (ctypes.c_int64 * 3)(*m)
+    ca = (ctypes.c_int64 * 3)(*n)
+    print("[mpo coords] unaligned output", flush=True)
+    _lib.check(L.tt_matrix_to_tensor(3, ra, ca, nnz, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                     ctypes.c_void_p(sub.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy()
+    assert h[0] == -7 and np.all(h[1 + nnz * 3:] == -7)
+    assert np.array_equal(h[1:1 + nnz * 3].reshape(nnz, 3), oracle_mod.matrix_coords(rows, cols, m, n))
+
+
+def test_empty_and_index_errors():
+    tts = _tts()
+    e = torch.zeros(0, dtype=torch.int64, device="cuda")
+    assert tts.matrix_to_tensor(e, e, (2, 3), (4, 5)).shape == (0, 2)
+    print("[mpo coords] out-of-range rows and columns", flush=True)
+    for r, c in (([0, 6], [0, 1]), ([0, 1], [20, 1]), ([-1, 0], [0, 0]), ([0, 0], [0, -5])):
+        rr = torch.tensor(r, dtype=torch.int64, device="cuda")
+        cc = torch.tensor(c, dtype=torch.int64, device="cuda")
+        with pytest.raises(tts.TTError) as ei:
+            tts.matrix_to_tensor(rr, cc, (2, 3), (4, 5))
+        assert ei.value.status == "TT_ERR_INDEX"
+
+
+def test_laplacian_full_size_layout(oracle_mod):
+    r, c, v, m, n = synth.laplacian_matrix(10)
+    print(f"[mpo coords] laplacian 1024^2 grid, nnz={len(v)}", flush=True)
+    got = _coords_gpu(r, c, m, n)
+    ref, _, _ = synth.laplacian_qtt(10)
+    assert np.array_equal(got, ref)
+
+
+def test_fdm_mpo_decomposition_table2(oracle_mod):
+    """FDM n = 10, random coefficients: front-end on the GPU, then the decomposition
+    against the oracle; final ranks 28, 28 at eps = 1e-14."""
+    r, c, v, m, n = synth.fdm3d_matrix(10, "random", seed=1)
+    idx = _coords_gpu(r, c, m, n)
+    assert np.array_equal(idx, oracle_mod.matrix_coords(r, c, m, n))
+    tt, _ = check_round(oracle_mod, idx, v, [a * b for a, b in zip(m, n)], 1e-14, "fdm n=10 random via front-end")
+    assert tt.ranks == [1, 28, 28, 1]
+
+
+def test_decompose_matrix_matvec():
+    """decompose_matrix end to end: the MPO applied to a vector equals the sparse product."""
+    tts = _tts()
+    r, c, v, m, n = synth.fdm3d_matrix(6, "random", seed=2)
+    gr = torch.from_numpy(r).cuda()
+    gc = torch.from_numpy(c).cuda()
+    gv = torch.from_numpy(v).cuda()
+    mpo = tts.decompose_matrix(gr, gc, gv, m, n, 1e-14)
+    cores = [G.cpu().numpy() for G in mpo.mpo_cores()]
+    assert [G.shape[1:3] for G in cores] == [(6, 6)] * 3
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.standard_normal(int(np.prod(n)))
+    y_ref = np.zeros(int(np.prod(m)))
+    np.add.at(y_ref, r, v * x[c])
+    T = np.tensordot(cores[0][0], x.reshape(n), axes=([1], [0]))
+    U = np.einsum("irjk,rpjs->ipsk", T, cores[1])
+    V = np.einsum("ipsk,sqkt->ipqt", U, cores[2])[..., 0]
+    assert np.max(np.abs(V.reshape(-1) - y_ref)) <= 1e-12 * np.abs(v).sum()
+    dense = _brute.dense_tensor(_coords_gpu(r, c, m, n), v, [a * b for a, b in zip(m, n)])
+    assert np.linalg.norm(_brute.tt_full([G.cpu().numpy() for G in mpo.cores]) - dense) <= 1e-12 * np.linalg.norm(v)
