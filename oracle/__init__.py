@@ -16,6 +16,11 @@ Parity status per function (see the pins in ``tests/test_oracle_*.py``):
   decompose (dynamic delta) -- pinned: a worked case with closed-form singular
                                values, dense TT-SVD with the same thresholds, the
                                bound of Algorithm 8's correctness theorem.
+  decompose (key_bits)      -- pinned: the rounding equals NumPy's binary32 and
+                               binary16 conversions at 23 and 10 bits; snapped
+                               grouping of noisy parallel columns equals the exact
+                               grouping of the noise-free tensor; per-entry error
+                               bound of the reconstruction.
   matrix_coords (MPO)       -- pinned: dense reshape/transpose of tiny matrices,
                                the quantized Laplacian and FDM layouts built from
                                grid coordinates, MPO matrix-vector products.
@@ -67,7 +72,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             P = ctypes.POINTER
             i32, i64, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
-            lib.orc_decompose.argtypes = [i32, P(i64), i64, P(ctypes.c_int32), P(f64), f64, i32, i32, i32, P(vp)]
+            lib.orc_decompose.argtypes = [i32, P(i64), i64, P(ctypes.c_int32), P(f64), f64, i32, i32, i32, i32, P(vp)]
+            lib.orc_snap.argtypes = [P(f64), i64, i32, P(f64)]
             lib.orc_decompose.restype = ctypes.c_int
             lib.orc_free.argtypes = [vp]
             lib.orc_summary.argtypes = [vp, P(i64), P(f64), P(f64)]
@@ -145,7 +151,7 @@ class OracleResult:
 
 
 def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True,
-              dynamic_delta: bool = False) -> OracleResult:
+              dynamic_delta: bool = False, key_bits: int = 0) -> OracleResult:
     lib = _load()
     idx = np.ascontiguousarray(idx, dtype=np.int32)
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -156,7 +162,8 @@ def decompose(idx, val, dims, eps, max_rank: int = 0, do_round: bool = True,
         raise ValueError("idx must be [nnz, d]")
     h = ctypes.c_void_p()
     st = lib.orc_decompose(d, _p(dims_a, ctypes.c_int64), nnz, _p(idx, ctypes.c_int32), _p(val, ctypes.c_double),
-                           float(eps), int(max_rank), int(bool(do_round)), int(bool(dynamic_delta)), ctypes.byref(h))
+                           float(eps), int(max_rank), int(bool(do_round)), int(bool(dynamic_delta)), int(key_bits),
+                           ctypes.byref(h))
     if st != 0:
         raise OracleError(st)
     try:
@@ -291,3 +298,12 @@ def matrix_coords(rows, cols, row_dims, col_dims) -> np.ndarray:
         jk, J = J % n[k], J // n[k]
         out[:, k] = np.asarray(ik, dtype=np.int64) * n[k] + np.asarray(jk, dtype=np.int64)
     return out.astype(np.int32)
+
+
+def snap(x, key_bits: int) -> np.ndarray:
+    """The oracle's rounding of canonical values to key_bits fraction bits."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.empty_like(x)
+    lib.orc_snap(_p(x, ctypes.c_double), x.size, int(key_bits), _p(out, ctypes.c_double))
+    return out

@@ -27,6 +27,12 @@
 //     reshape(N_k, [beta_{k-1}, n_k, beta_k]) (Algorithm 1, core step); the
 //     transfer matrix becomes the next level (C := T in place of C := Sigma V^T).
 //     At the last level the transfer matrix is the last core.
+//     Tolerant parallel test (optional, key_bits = b in 1..52): every canonical
+//     value is rounded to b fraction bits before it is keyed and stored, by
+//     round-half-to-even on the magnitude's bit pattern (a carry may move into the
+//     exponent; a rounding that would reach the infinity/NaN exponent truncates
+//     instead).  Columns parallel up to a relative perturbation well below 2^-b
+//     then share one key; each stored entry moves by at most 2^-(b+1) relative.
 //  4. TT-rounding (Algorithm 2, run mirrored): a left-to-right Householder QR sweep
 //     (all-zero rows are left out of each QR, m = min(non-zero rows, columns),
 //     diag(R) >= 0) followed by a right-to-left sweep of delta-truncated SVDs of
@@ -62,6 +68,27 @@ using Clock = std::chrono::steady_clock;
 
 double seconds_since(Clock::time_point t0) {
   return std::chrono::duration<double>(Clock::now() - t0).count();
+}
+
+// Canonical value rounded to b fraction bits (b = 0: unchanged).
+double snap_value(double x, int32_t b) {
+  if (b <= 0 || b >= 52) return x;
+  uint64_t u;
+  std::memcpy(&u, &x, sizeof(u));
+  const uint64_t sign = u & (uint64_t(1) << 63);
+  const uint64_t mag = u & ~sign;
+  const int drop = 52 - b;
+  const uint64_t kept = mag >> drop;            // bits that stay, as an integer
+  const uint64_t rest = mag & ((uint64_t(1) << drop) - 1);
+  const uint64_t half = uint64_t(1) << (drop - 1);
+  uint64_t up = kept;
+  if (rest > half || (rest == half && (kept & 1))) up = kept + 1;
+  uint64_t r = up << drop;
+  if ((r >> 52) >= 0x7FF) r = kept << drop;     // would reach inf/NaN: truncate
+  r |= sign;
+  double y;
+  std::memcpy(&y, &r, sizeof(y));
+  return y;
 }
 
 struct LevelOut {
@@ -242,11 +269,11 @@ extern "C" {
 
 int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                   const double* val, double eps, int32_t max_rank, int32_t do_round,
-                  int32_t dynamic_delta, orc_result** out) {
+                  int32_t dynamic_delta, int32_t key_bits, orc_result** out) {
   if (!out) return ORC_ERR_ARG;
   *out = nullptr;
   if (d < 2 || !dims || nnz < 0 || (nnz > 0 && (!idx || !val))) return ORC_ERR_ARG;
-  if (!(eps >= 0.0 && eps < 1.0) || max_rank < 0) return ORC_ERR_ARG;
+  if (!(eps >= 0.0 && eps < 1.0) || max_rank < 0 || key_bits < 0 || key_bits > 52) return ORC_ERR_ARG;
   for (int32_t k = 0; k < d; ++k)
     if (dims[k] <= 0 || dims[k] > std::numeric_limits<int32_t>::max()) return ORC_ERR_ARG;
 
@@ -331,7 +358,7 @@ int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* id
         key.push_back(static_cast<uint64_t>(E[a + j].rho));
       }
       for (int64_t j = 0; j < m; ++j) {
-        c[j] = E[a + j].v / s;
+        c[j] = snap_value(E[a + j].v / s, key_bits);
         key.push_back(bits_of(c[j]));
       }
       auto it = groups.find(key);
@@ -555,6 +582,10 @@ void orc_sigma(const orc_result* r, int32_t b, double* sig, double* tail) {
 }
 
 double orc_bond_delta(const orc_result* r, int32_t b) { return r->bond_delta[b - 1]; }
+
+void orc_snap(const double* x, int64_t n, int32_t key_bits, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = snap_value(x[i], key_bits);
+}
 
 int orc_eval(int32_t d, const int64_t* dims, const int64_t* ranks, const double* const* cores,
              int64_t m, const int32_t* idx, double* y) {

@@ -41,10 +41,14 @@ typedef struct orc_result_s orc_result;
  *              1 = also run the QR and truncated-SVD sweeps.
  *   dynamic_delta : 0 = the same threshold eps*||A||_F/sqrt(d-1) at every bond;
  *              1 = thresholds from the remaining budget (Algorithm 8).
+ *   key_bits : 0 = exact parallel test; 1..52 = canonical values rounded to that
+ *              many fraction bits (round half to even) before keying and storing.
  * On success *out owns every result; release with orc_free. */
 int orc_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                   const double* val, double eps, int32_t max_rank, int32_t do_round,
-                  int32_t dynamic_delta, orc_result** out);
+                  int32_t dynamic_delta, int32_t key_bits, orc_result** out);
+/* The rounding of canonical values used with key_bits, applied to x[0..n). */
+void orc_snap(const double* x, int64_t n, int32_t key_bits, double* out);
 void orc_free(orc_result* r);
 
 /* Summary.  info[0] = nnz kept, info[1] = rounded (0/1).
