@@ -81,6 +81,15 @@ typedef struct {
                                  rem = eps*||A||_F.  Same eps guarantee (the
                                  correctness theorem of Algorithm 8), usually lower
                                  ranks.  Ignored with max_rank > 0. */
+  int32_t key_bits;           /* 0: exact parallel test (Algorithm 3; bitwise equal
+                                 canonical columns).  1..52: tolerant test: every
+                                 canonical value v/s is rounded to key_bits fraction
+                                 bits (round half to even on its bit pattern) before
+                                 it is keyed and stored in N_k, so columns parallel
+                                 up to a relative perturbation well below 2^-key_bits
+                                 group together.  Each N_k entry then moves by at most
+                                 2^-(key_bits+1) relative; 52 is the exact test.
+                                 Outside [0, 52]: TT_ERR_ARG. */
 } tt_options;
 
 typedef struct tt_result_s* tt_result; /* opaque, owned by the library */

@@ -157,7 +157,8 @@ _FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision: str = "fp64",
               max_rank: int = 0, keep_intermediates: bool = False, sparse_only: bool = False,
-              device_mem_budget: int = 0, stream=None, allocator=None, dynamic_delta: bool = False) -> TT:
+              device_mem_budget: int = 0, stream=None, allocator=None, dynamic_delta: bool = False,
+              key_bits: int = 0) -> TT:
     """Sparse TT decomposition of the COO tensor (idx int32 [nnz, d], val float64 [nnz], on cuda).
 
     allocator: optional (alloc(nbytes) -> device pointer int, free(pointer int)) used for
@@ -165,6 +166,8 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     must be ordered on `stream`, as torch's caching allocator is on the current stream.
     dynamic_delta: per-bond truncation thresholds from the remaining error budget
     (Algorithm 8) instead of eps ||A|| / sqrt(d-1) at every bond.
+    key_bits: 0 for the exact parallel test; 1..52 rounds every canonical value to
+    that many fraction bits before grouping (tolerant test for noisy parallel columns).
     """
     L = _lib.load()
     if not (idx.is_cuda and val.is_cuda):
@@ -185,6 +188,7 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     opt.sparse_only = int(bool(sparse_only))
     opt.device_mem_budget = int(device_mem_budget)
     opt.dynamic_delta = int(bool(dynamic_delta))
+    opt.key_bits = int(key_bits)
     hooks = None
     if allocator is not None:
         a_fn, f_fn = allocator

@@ -47,6 +47,7 @@ class tt_options(ctypes.Structure):
         ("free", ctypes.c_void_p),
         ("alloc_ctx", ctypes.c_void_p),
         ("dynamic_delta", ctypes.c_int32),
+        ("key_bits", ctypes.c_int32),
     ]
 
 

@@ -188,7 +188,7 @@ void sync_status(DevStatus* d_st, hipStream_t s) {
 
 // Exact sparse TT: ingest, sort, and parallel-vector rounding level by level.
 void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
-                  int total_bits, bool keep, hipStream_t s, Events& ev) {
+                  int total_bits, bool keep, int key_bits, hipStream_t s, Events& ev) {
   Allocator* al = &R->al;
   const int d = mi.d;
   DBuf<DevStatus> st(al, 1);
@@ -284,6 +284,7 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     ca.rho_mask = (mi.bits[0] >= 64) ? ~0ull : ((1ull << mi.bits[0]) - 1ull);
     ca.kidx = kidx;
     ca.sort_rows = sort_rows;
+    ca.snap = (key_bits >= 1 && key_bits <= 51) ? 52 - key_bits : 0;
     ca.crho = crho.get();
     ca.cval = cval.get();
     ca.colhash = colhash.get();
@@ -448,6 +449,7 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
   else if (!(eps >= 0.0 && eps < 1.0)) why = "eps must satisfy 0 <= eps < 1";
   else if (o.precision < TT_FP64 || o.precision > TT_BF16_FP32ACC) why = "unknown precision";
   else if (o.max_rank < 0) why = "max_rank must be >= 0";
+  else if (o.key_bits < 0 || o.key_bits > 52) why = "key_bits must be in [0, 52]";
   else if ((o.alloc == nullptr) != (o.free == nullptr)) why = "alloc and free hooks must be given together";
   if (why.empty())
     for (int k = 0; k < d; ++k)
@@ -487,7 +489,8 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     R->dims.assign(dims, dims + d);
     Events ev;
     TTS_HIP(hipEventRecord(ev.e[0], s));
-    sparse_stage(R, idx, val, static_cast<uint32_t>(nnz), mi, total_bits, o.keep_intermediates != 0, s, ev);
+    sparse_stage(R, idx, val, static_cast<uint32_t>(nnz), mi, total_bits, o.keep_intermediates != 0, o.key_bits, s,
+                 ev);
     R->delta = eps * R->norm / std::sqrt(static_cast<double>(d - 1));
     RoundInput in{};
     in.d = d;
@@ -498,6 +501,7 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     in.norm = R->norm;
     in.max_rank = o.max_rank;
     in.dynamic_delta = o.dynamic_delta != 0;
+    if (o.key_bits >= 1 && o.key_bits <= 51) in.snap_rel = (d - 1) * std::ldexp(1.0, -(o.key_bits + 1));
     in.precision = o.precision;
     for (int k = 1; k <= d - 1; ++k) {
       const LevelData& L = R->lev[k - 1];

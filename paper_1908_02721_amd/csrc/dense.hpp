@@ -14,6 +14,7 @@ struct RoundInput {
   double eps = 0.0, delta = 0.0, norm = 0.0;
   int max_rank = 0;
   bool dynamic_delta = false;  // per-bond thresholds from the remaining budget (Alg 8)
+  double snap_rel = 0.0;       // (d-1) 2^-(key_bits+1) with the tolerant parallel test, else 0
   int precision = TT_FP64;
   // N_k (k = 1..d-1), CSC, rows rho = g_{k-1} * n_k + i_k
   std::vector<const int64_t*> n_colptr;

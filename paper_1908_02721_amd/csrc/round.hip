@@ -142,10 +142,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
                   w[k + 1].get(), w[k].get(), s);
   }
 
-  // Acceptance threshold of a deflated basis.  With reduced-precision contractions the
-  // carried factor W' = Q^T X is only accurate to the operands' unit roundoff u, so the
-  // threshold is raised to 64 u ||A||_F (the residual itself is always formed in FP64).
-  double tau = std::min(1e-2 * in.delta, kTauRel * in.norm);
+  // Acceptance threshold of a deflated basis.  With the tolerant parallel test the
+  // exact sparse TT itself carries up to snap_rel ||A||_F of rounding (its canonical
+  // values are rounded to key_bits fraction bits), so directions at that level are
+  // dropped too, still within 1% of the bond's truncation threshold.  With
+  // reduced-precision contractions the carried factor W' = Q^T X is only accurate to
+  // the operands' unit roundoff u, so the threshold is raised to 64 u ||A||_F (the
+  // residual itself is always formed in FP64).
+  double tau = std::min(1e-2 * in.delta, std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
   if (prec == TT_FP32) tau = std::max(tau, 64.0 * 0x1p-24 * in.norm);
   if (prec == TT_BF16_FP32ACC) tau = std::max(tau, 64.0 * 0x1p-8 * in.norm);
   std::vector<int64_t> r(d + 1, 1);

@@ -7,7 +7,8 @@
 //   col_flags/col_starts : segment boundaries -> column start offsets
 //   canon                : one thread per column: order its entries by row rho,
 //                          s = value at the smallest row, c_j = v_j / s (IEEE
-//                          binary64 division), 64-bit hash of (m, rho_j, bits(c_j))
+//                          binary64 division, optionally rounded to fewer fraction
+//                          bits: the tolerant test), 64-bit hash of (m, rho_j, bits(c_j))
 //   group                : open-addressing table keyed by the hash; a column that
 //                          finds an occupied slot compares its full canonical key
 //                          with the slot's representative column; the smallest
@@ -154,6 +155,21 @@ __device__ __forceinline__ uint64_t col_hash_term(uint32_t j, uint32_t rho, doub
   return mix64(mix64((static_cast<uint64_t>(j) << 32 | rho) ^ 0x9e3779b97f4a7c15ull) ^
                static_cast<uint64_t>(__double_as_longlong(cv)));
 }
+// Canonical value v / s, rounded to 52 - drop fraction bits when drop > 0 (round half
+// to even on the magnitude's bit pattern; a carry may move into the exponent, and a
+// rounding that would reach the infinity/NaN exponent truncates instead).  Columns
+// parallel up to a perturbation well below that precision then share one key.
+__device__ __forceinline__ double canon_value(double v, double s, int drop) {
+  const double x = v / s;
+  if (drop == 0) return x;
+  const uint64_t u = static_cast<uint64_t>(__double_as_longlong(x));
+  const uint64_t sign = u & (1ull << 63), mag = u ^ sign;
+  const uint64_t kept = mag >> drop, rest = mag & ((1ull << drop) - 1ull), half = 1ull << (drop - 1);
+  const uint64_t up = kept + ((rest > half || (rest == half && (kept & 1ull))) ? 1ull : 0ull);
+  uint64_t r = up << drop;
+  if ((r >> 52) >= 0x7FFull) r = kept << drop;
+  return __longlong_as_double(static_cast<long long>(r | sign));
+}
 __device__ __forceinline__ uint64_t col_hash_final(uint32_t m, uint64_t sum) {
   return mix64(sum ^ mix64(static_cast<uint64_t>(m) * 0x9e3779b97f4a7c15ull));
 }
@@ -196,7 +212,7 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
         for (int u = 0; u < 8; ++u) {
           const uint32_t j = j0 + u;
           if (j < m) {
-            const double cv = vv[u] / s;
+            const double cv = canon_value(vv[u], s, a.snap);
             a.crho[st + j] = rr[u];
             a.cval[st + j] = cv;
             hs += col_hash_term(j, rr[u], cv);
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
         for (int l = 0; l < kMaxLocal; ++l)
           if (static_cast<uint32_t>(l) < mw) rank += (static_cast<uint32_t>(l) < m && rr[l] < rr[j]) ? 1u : 0u;
         if (static_cast<uint32_t>(j) < m) {
-          const double cv = vv[j] / s;
+          const double cv = canon_value(vv[j], s, a.snap);
           a.crho[st + rank] = rr[j];
           a.cval[st + rank] = cv;
           hs += col_hash_term(rank, rr[j], cv);
@@ -265,7 +281,7 @@ __global__ __launch_bounds__(NT) void k_canon_wide(CanonArgs a, ModeInfo mi) {
   uint64_t hs = 0;
   for (uint32_t j = threadIdx.x; j < m; j += NT) {
     const uint32_t rho = a.erho ? a.erho[st + j] : static_cast<uint32_t>(a.ekey[st + j] & a.rho_mask);
-    const double cv = a.ev[st + j] / s;
+    const double cv = canon_value(a.ev[st + j], s, a.snap);
     a.crho[st + j] = rho;
     a.cval[st + j] = cv;
     hs += col_hash_term(j, rho, cv);

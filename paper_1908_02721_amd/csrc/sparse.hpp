@@ -60,6 +60,7 @@ struct CanonArgs {
   uint64_t rho_mask;    // level 1: mask of the mode-0 field
   int kidx;             // first suffix mode (0-based) = k
   bool sort_rows;       // entries of a column still need ordering by rho
+  int snap;             // fraction bits dropped from every canonical value (0: exact test)
   uint32_t* crho;       // out, per entry: rho in ascending order
   double* cval;         // out, per entry: canonical value v / s
   uint64_t* colhash;

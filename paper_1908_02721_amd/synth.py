@@ -31,6 +31,7 @@ import numpy as np
 __all__ = [
     "random_sparse",
     "kronecker_sum",
+    "noisy_kronecker",
     "laplacian_matrix",
     "laplacian_qtt",
     "fdm3d_matrix",
@@ -102,6 +103,27 @@ def kronecker_sum(d: int, n: int, terms: int, q: int, seed: int, continuous: boo
     acc = np.zeros(uniq.size, dtype=np.float64)
     np.add.at(acc, inv, v)
     return unravel(uniq, dims), acc, dims
+
+
+def noisy_kronecker(seed: int, noise: float, d: int = 4, n: int = 6, terms: int = 5, q: int = 3):
+    """Sum of rank-1 terms with factor values in {1, 2, 3}, and a noisy copy.
+
+    Returns (idx, clean, noisy, dims): ``noisy`` is every entry times (1 + eta),
+    eta ~ U(-noise, noise), so parallel columns of ``clean`` stay parallel in
+    ``noisy`` only up to that perturbation.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    acc = {}
+    for _ in range(terms):
+        pos = [rng.choice(n, q, replace=False) for _ in range(d)]
+        vals = [rng.integers(1, 4, q).astype(np.float64) for _ in range(d)]
+        for a in np.ndindex(*(q,) * d):
+            key = tuple(int(pos[k][a[k]]) for k in range(d))
+            acc[key] = acc.get(key, 0.0) + float(np.prod([vals[k][a[k]] for k in range(d)]))
+    idx = np.array(list(acc.keys()), dtype=np.int32)
+    clean = np.array(list(acc.values()))
+    noisy = clean * (1 + rng.uniform(-noise, noise, clean.size))
+    return idx, clean, noisy, (n,) * d
 
 
 def laplacian_matrix(L: int):
@@ -205,6 +227,9 @@ WORKLOADS = {
     "random4d_n20_nnz1k": dict(kind="random", dims=(20,) * 4, nnz=1000, seed=1, eps=1e-12),
     # 8-way 32^8, 64 Kronecker terms with 4 nonzeros per mode factor (~4.19M nnz), eps 1e-8.
     "kron8d_n32_t64": dict(kind="kron", d=8, n=32, terms=64, q=4, seed=2, eps=1e-8),
+    # The same with continuous U[0.5, 1.5) factor values: parallel columns only up to
+    # rounding, so it needs the tolerant parallel test (key_bits).
+    "kron8d_n32_t64_cont": dict(kind="kron", d=8, n=32, terms=64, q=4, seed=2, eps=1e-8, continuous=True),
     # 2D 5-point Laplacian, 1024 x 1024 grid, as a 20-way QTT tensor (5,238,784 nnz), eps 1e-10.
     "laplace2d_qtt_L10": dict(kind="laplace", L=10, eps=1e-10),
     # 5-way 200^5 with 10M random nonzeros, N(0,1), eps 1e-2.
@@ -218,7 +243,7 @@ def workload(name: str):
     if w["kind"] == "random":
         idx, val, dims = random_sparse(w["dims"], w["nnz"], w["seed"])
     elif w["kind"] == "kron":
-        idx, val, dims = kronecker_sum(w["d"], w["n"], w["terms"], w["q"], w["seed"])
+        idx, val, dims = kronecker_sum(w["d"], w["n"], w["terms"], w["q"], w["seed"], w.get("continuous", False))
     elif w["kind"] == "laplace":
         idx, val, dims = laplacian_qtt(w["L"])
     else:  # pragma: no cover

@@ -71,6 +71,9 @@ def test_host_argument_errors(lib):
     assert st == 1
     st, _ = _call(lib, 2, [4, 4], 1, fake, fake, 0.1, {"max_rank": -2})
     assert st == 1
+    for kb in (-1, 53):
+        st, _ = _call(lib, 2, [4, 4], 1, fake, fake, 0.1, {"key_bits": kb})
+        assert st == 1
 
 
 def test_status_strings(lib):

@@ -30,42 +30,48 @@ def _gpu(idx, val):
         torch.from_numpy(np.ascontiguousarray(val, dtype=np.float64)).cuda()
 
 
-def check_round(oracle_mod, idx, val, dims, eps, label, max_rank=0, samples=4096, dense=None, dynamic=False):
+def check_round(oracle_mod, idx, val, dims, eps, label, max_rank=0, samples=4096, dense=None, dynamic=False,
+                key_bits=0):
     tts = _tt()
     print(f"[round parity] {label} dims={tuple(dims)} nnz={len(val)} eps={eps} max_rank={max_rank} "
-          f"dynamic={dynamic}", flush=True)
-    res = oracle_mod.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic)
+          f"dynamic={dynamic} key_bits={key_bits}", flush=True)
+    res = oracle_mod.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic, key_bits=key_bits)
     gi, gv = _gpu(idx, val)
-    tt = tts.decompose(gi, gv, dims, eps, max_rank=max_rank, dynamic_delta=dynamic)
+    tt = tts.decompose(gi, gv, dims, eps, max_rank=max_rank, dynamic_delta=dynamic, key_bits=key_bits)
     nrm = res.norm
+    d = len(dims)
+    # With the tolerant parallel test the sparse TT carries up to (d-1) 2^-(b+1) ||A||
+    # of rounding, and the GPU's deflation may drop up to 4 times that per bond, where
+    # the oracle keeps everything: the bar widens by sqrt(d-1) bonds of that.
+    tol = TOL if not (1 <= key_bits <= 51) else TOL + 4.0 * (d - 1) ** 1.5 * 2.0 ** -(key_bits + 1)
     assert tt.ranks == res.ranks, (tt.ranks, res.ranks)
     if max_rank == 0:
         for b in range(1, len(dims)):
             # thresholds follow from the discarded sums, which agree to round-off
-            assert abs(tt.bond_delta(b) ** 2 - res.bond_delta[b - 1] ** 2) <= TOL * nrm * nrm, f"bond {b} delta"
+            assert abs(tt.bond_delta(b) ** 2 - res.bond_delta[b - 1] ** 2) <= tol * nrm * nrm, f"bond {b} delta"
     for b in range(1, len(dims)):
         sg, tail = tt.sigma(b)
         so = res.sigma[b - 1]
         m = min(len(sg), len(so))
-        assert np.max(np.abs(sg[:m] - so[:m])) <= TOL * nrm, f"bond {b} sigma"
-        assert np.all(sg[m:] <= TOL * nrm) and np.all(so[m:] <= TOL * nrm), f"bond {b} sigma tail"
+        assert np.max(np.abs(sg[:m] - so[:m])) <= tol * nrm, f"bond {b} sigma"
+        assert np.all(sg[m:] <= tol * nrm) and np.all(so[m:] <= tol * nrm), f"bond {b} sigma tail"
     cores = [c.cpu().numpy() for c in tt.cores]
     for k, (cg, co) in enumerate(zip(cores, res.cores)):
         assert cg.shape == co.shape, (k, cg.shape, co.shape)
     diff = oracle_mod.tt_diff_norm(cores, res.cores)
-    assert diff <= TOL * nrm, f"||B_gpu - B_oracle|| = {diff / nrm:.3e} ||A||"
+    assert diff <= tol * nrm, f"||B_gpu - B_oracle|| = {diff / nrm:.3e} ||A||"
     rng = np.random.Generator(np.random.PCG64(7))
     pick = rng.choice(len(val), min(samples, len(val)), replace=False)
     rnd = np.stack([rng.integers(0, n, samples) for n in dims], 1).astype(np.int32)
     pts = np.concatenate([idx[pick], rnd])
     yg = oracle_mod.eval_entries(cores, pts)
     yo = oracle_mod.eval_entries(res.cores, pts)
-    assert np.max(np.abs(yg - yo)) <= TOL * nrm
+    assert np.max(np.abs(yg - yo)) <= tol * nrm
     if dense is not None and max_rank == 0:
         A = _brute.dense_tensor(idx, val, dims)
         B = _brute.tt_full(cores)
         err = np.linalg.norm(A - B)
-        assert err <= eps * nrm + 1e-12 * nrm, "error bound"
+        assert err <= eps * nrm + tol * nrm, "error bound"
     # cores 2..d are right-orthonormal
     for G in cores[1:]:
         M = G.reshape(G.shape[0], -1)
@@ -207,3 +213,27 @@ def test_dynamic_delta_kron_truncating(oracle_mod):
     # at eps = 0.4 the fixed thresholds give ranks [1, 5, 6, 6, 6, 5, 1], the dynamic ones lower
     tt, _ = check_round(oracle_mod, idx, val, dims, 0.4, "kron d6 t6 eps=0.4", dense=True, dynamic=True)
     assert tt.ranks == [1, 3, 5, 6, 6, 5, 1]
+
+
+def test_tolerant_continuous_kron_rounded(oracle_mod):
+    """Continuous-valued Kronecker sum (parallel columns only up to rounding): with the
+    tolerant test (key_bits = 40) the decomposition still matches the oracle."""
+    idx, val, dims = synth.kronecker_sum(6, 10, 6, 3, seed=4, continuous=True)
+    tt, res = check_round(oracle_mod, idx, val, dims, 1e-10, "continuous kron d6", dense=True, key_bits=40)
+    ex = oracle_mod.decompose(idx, val, dims, 1e-10)
+    print(f"[round parity] betas exact {ex.betas} tolerant {tt.betas}; ranks {tt.ranks}", flush=True)
+    assert tt.ranks == ex.ranks
+
+
+@pytest.mark.timeout(400)
+def test_tolerant_continuous_kron8d_full_size(oracle_mod):
+    """The 8-way Kronecker workload with continuous factor values at key_bits = 40:
+    the exact test would leave 261,836 groups at level 2; the tolerant one groups
+    the columns that are parallel up to rounding."""
+    idx, val, dims, eps = synth.workload("kron8d_n32_t64_cont")
+    tt, _ = check_round(oracle_mod, idx, val, dims, eps, "kron8d_n32_t64_cont key_bits=40", key_bits=40)
+    print(f"[round parity] betas {tt.betas} qr ranks {tt.qr_ranks} ranks {tt.ranks}", flush=True)
+    assert tt.betas == [1, 78, 98, 138, 180, 289, 338, 32, 1]
+    # the deflation accepts bases at the snapping level: no bond falls back to the
+    # exact QR, which would carry all beta_k columns into the SVD sweep
+    assert max(tt.qr_ranks) <= 64

@@ -27,12 +27,12 @@ def _bits(a):
     return np.ascontiguousarray(a, dtype=np.float64).view(np.int64)
 
 
-def check_sparse_parity(oracle_mod, idx, val, dims, label="", dense_cores=True):
+def check_sparse_parity(oracle_mod, idx, val, dims, label="", dense_cores=True, key_bits=0):
     tts = _tt()
-    print(f"[sparse parity] {label} dims={tuple(dims)} nnz={len(val)}", flush=True)
-    res = oracle_mod.decompose(idx, val, dims, 0.0, do_round=False)
+    print(f"[sparse parity] {label} dims={tuple(dims)} nnz={len(val)} key_bits={key_bits}", flush=True)
+    res = oracle_mod.decompose(idx, val, dims, 0.0, do_round=False, key_bits=key_bits)
     gi, gv = _to_gpu(idx, val)
-    tt = tts.decompose(gi, gv, dims, 0.0, sparse_only=True, keep_intermediates=True)
+    tt = tts.decompose(gi, gv, dims, 0.0, sparse_only=True, keep_intermediates=True, key_bits=key_bits)
     assert tt.nnz == res.nnz
     assert tt.betas == res.betas, (tt.betas, res.betas)
     assert abs(tt.norm - res.norm) <= 1e-13 * res.norm
@@ -172,3 +172,42 @@ def test_full_size_sparse_stage_random5d(oracle_mod):
     idx, val, dims, _ = synth.workload("random5d_n200_nnz10m")
     tt, res = check_sparse_parity(oracle_mod, idx, val, dims, "random5d_n200_nnz10m", dense_cores=False)
     assert tt.betas[2] > 10**6
+
+
+# ---- tolerant parallel test (canonical values rounded to key_bits fraction bits) ----
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_tolerant_noisy_kronecker(oracle_mod, seed):
+    """Noisy parallel columns: bit-identical to the oracle with key_bits = 20, and the
+    grouping is the exact grouping of the noise-free tensor (the oracle's pin)."""
+    idx, clean, noisy, dims = synth.noisy_kronecker(seed, 1e-14)
+    tt, _ = check_sparse_parity(oracle_mod, idx, noisy, dims, f"noisy kron {seed}", key_bits=20)
+    ex = oracle_mod.decompose(idx, clean, dims, 0.0, do_round=False)
+    assert tt.betas == ex.betas
+
+
+@pytest.mark.parametrize("key_bits", [1, 23, 40, 51, 52])
+def test_tolerant_continuous_kronecker(oracle_mod, key_bits):
+    idx, val, dims = synth.kronecker_sum(5, 12, 10, 3, seed=9, continuous=True)
+    check_sparse_parity(oracle_mod, idx, val, dims, "continuous kron d5", key_bits=key_bits)
+
+
+def test_tolerant_long_columns_and_wide_canon(oracle_mod):
+    # long level-2 columns (composite sort) and few long sorted columns (one
+    # workgroup per column) with rounded canonical values
+    rng = np.random.Generator(np.random.PCG64(17))
+    dims = (3, 48, 4)
+    total = int(np.prod(dims))
+    lin = rng.choice(total, total // 2, replace=False)
+    val = rng.uniform(0.5, 1.5, lin.size)
+    check_sparse_parity(oracle_mod, synth.unravel(lin, dims), val, dims, "long columns", key_bits=8)
+    idx, val, dims = synth.random_sparse((40, 60, 2), 3000, 21)
+    check_sparse_parity(oracle_mod, idx, np.round(val, 1) + 0.05, dims, "wide canon", key_bits=6)
+
+
+def test_key_bits_argument_errors():
+    tts = _tt()
+    gi, gv = _to_gpu(np.zeros((1, 2), dtype=np.int32), np.ones(1))
+    for kb in (-1, 53):
+        with pytest.raises(tts.TTError):
+            tts.decompose(gi, gv, (2, 2), 0.1, key_bits=kb)

@@ -40,29 +40,11 @@ def test_snap_carry_and_limits(oracle_mod):
     assert np.array_equal(oracle_mod.snap(x, 52), x) and np.array_equal(oracle_mod.snap(x, 0), x)
 
 
-def _small_kron(seed, noise):
-    """Sum of rank-1 terms with factor values in {1, 2, 3}; entries then multiplied by
-    (1 + eta), |eta| <= noise, so parallel columns stay parallel only up to noise."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    d, n, terms, q = 4, 6, 5, 3
-    acc = {}
-    for _ in range(terms):
-        pos = [rng.choice(n, q, replace=False) for _ in range(d)]
-        vals = [rng.integers(1, 4, q).astype(np.float64) for _ in range(d)]
-        for a in np.ndindex(*(q,) * d):
-            key = tuple(int(pos[k][a[k]]) for k in range(d))
-            acc[key] = acc.get(key, 0.0) + float(np.prod([vals[k][a[k]] for k in range(d)]))
-    idx = np.array(list(acc.keys()), dtype=np.int32)
-    clean = np.array(list(acc.values()))
-    noisy = clean * (1 + rng.uniform(-noise, noise, clean.size))
-    return idx, clean, noisy, (n,) * d
-
-
 @pytest.mark.parametrize("seed", [3, 4, 5])
 def test_snapped_grouping_of_noisy_columns_is_exact_grouping(oracle_mod, seed):
     # small-integer data: every canonical value is a ratio of integers below 2^10, so
     # its distance to a rounding boundary at 20 bits is far above the 1e-14 noise
-    idx, clean, noisy, dims = _small_kron(seed, 1e-14)
+    idx, clean, noisy, dims = synth.noisy_kronecker(seed, 1e-14)
     ex = oracle_mod.decompose(idx, clean, dims, 0.0, do_round=False)
     raw = oracle_mod.decompose(idx, noisy, dims, 0.0, do_round=False)
     sn = oracle_mod.decompose(idx, noisy, dims, 0.0, do_round=False, key_bits=20)
