@@ -123,6 +123,36 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
                               tt_result* out);
 
 /*
+ * The paper's fiber-trie FastTT (Algorithm 7): the exact TT of the nonzero p-fibers
+ * reduced by Deparallelisation of quasi-permutation matrices (Algorithm 4 with
+ * Algorithm 5; the Theorem on the rank-R TT), then rounded from core p outwards
+ * (Algorithm 6: truncated-SVD sweep to the right, QR sweep back, truncated-SVD sweep
+ * to the left, delta = eps ||A||_F / (sqrt(p-1) + sqrt(d-p))).  The result satisfies
+ * ||A - B||_F <= eps ||A||_F (Algorithm 6's correctness theorem), up to round-off.
+ *   p   : 1..d, or 0 to choose it by Algorithm 9 (least estimated SVD cost, the
+ *         rank bounds of Algorithm 4, f_SVD(m, n) = m n min(m, n); lowest p on ties)
+ *   other arguments, inputs, errors and the result handle as tt_sparse_decompose.
+ *   The exact ranks r~ of Algorithm 4 are the result's sparse ranks
+ *   (tt_get_sparse_ranks: betas), the ranks after the QR sweep its qr_ranks.
+ *   Options: FP64 only; max_rank, sparse_only (exact cores), device_mem_budget and
+ *   the allocator hooks apply; dynamic_delta, key_bits and keep_intermediates give
+ *   TT_ERR_ARG.  Every exact rank r~_k must be <= 16384 and every exact core at most
+ *   4e9 entries (else TT_ERR_TOO_LARGE): the variant suits tensors with few, dense
+ *   fibers.  tt_get_level is not available.
+ */
+tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                              double eps, int32_t p, const tt_options* opt, void* stream, tt_result* out);
+
+/* For a tt_fasttt_decompose result: the p used and R, its number of nonzero
+   p-fibers.  TT_ERR_ARG for other results. */
+tt_status tt_get_fasttt_info(tt_result r, int32_t* p, int64_t* fibers);
+
+/* Algorithm 9 alone: the chosen p and, in costs (host double[d], may be NULL), the
+   estimated cost of every p = 1..d.  Inputs as tt_sparse_decompose (nnz >= 1). */
+tt_status tt_fasttt_select_p(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                             double* costs, int32_t* p, void* stream);
+
+/*
  * Matrix -> tensor coordinates for the matrix-in-TT-format (MPO) front-end
  * (Sec. 3.4, matrices in TT-format).  An M x N matrix, M = m_1...m_d,
  * N = n_1...n_d, is the d-way tensor with modes of size m_k n_k: the row index

@@ -9,6 +9,7 @@ arguments (PyTorch provides device memory and streams).
     y = EvalEntries.apply(idx, *cores)            # TT entries at idx, differentiable
     mpo = decompose_matrix(rows, cols, val, row_dims, col_dims, eps)   # sparse matrix -> MPO
     mpo.mpo_cores()                               # [r_{k-1}, m_k, n_k, r_k]
+    ftt = fasttt_decompose(idx, val, dims, eps, p=0)   # the paper's fiber-trie variant
 """
 from __future__ import annotations
 
@@ -19,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import STAGES, TTError
 
-__all__ = ["decompose", "decompose_matrix", "matrix_to_tensor", "TT", "eval_entries", "eval_entries_backward",
+__all__ = ["decompose", "decompose_matrix", "matrix_to_tensor", "fasttt_decompose", "fasttt_select_p", "TT", "eval_entries", "eval_entries_backward",
            "EvalPlan", "EvalEntries", "TTError", "library_path"]
 
 library_path = _lib.LIB_PATH
@@ -204,6 +205,57 @@ def decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, precision:
     tt = TT(h, dims)
     tt._hooks = hooks  # the result frees through them in tt_free
     return tt
+
+
+def _coo_args(idx, val, dims):
+    if not (idx.is_cuda and val.is_cuda):
+        raise ValueError("idx and val must be cuda tensors")
+    if idx.dtype != torch.int32 or val.dtype != torch.float64:
+        raise TypeError("idx must be int32 and val float64")
+    idx = idx.contiguous()
+    val = val.contiguous()
+    d = len(dims)
+    nnz = int(val.numel())
+    if idx.numel() != nnz * d:
+        raise ValueError("idx must have shape [nnz, d]")
+    return idx, val, d, nnz, (ctypes.c_int64 * d)(*[int(x) for x in dims])
+
+
+def fasttt_decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, p: int = 0, max_rank: int = 0,
+                     sparse_only: bool = False, device_mem_budget: int = 0, stream=None) -> TT:
+    """The paper's fiber-trie FastTT (Algorithm 7): exact TT of the nonzero p-fibers
+    reduced by Algorithm 4, rounded from core p outwards (Algorithm 6).
+
+    p = 0 chooses p by Algorithm 9.  The returned TT also has ``ftt_p`` (the p used)
+    and ``fibers`` (R, the number of nonzero p-fibers); ``betas`` holds the exact
+    ranks r~ of Algorithm 4.
+    """
+    L = _lib.load()
+    idx, val, d, nnz, dims_a = _coo_args(idx, val, dims)
+    opt = _lib.tt_options()
+    L.tt_options_default(ctypes.byref(opt))
+    opt.max_rank = int(max_rank)
+    opt.sparse_only = int(bool(sparse_only))
+    opt.device_mem_budget = int(device_mem_budget)
+    h = ctypes.c_void_p()
+    _lib.check(L.tt_fasttt_decompose(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                     float(eps), int(p), ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h)))
+    tt = TT(h, dims)
+    pp, R = ctypes.c_int32(), ctypes.c_int64()
+    _lib.check(L.tt_get_fasttt_info(h, ctypes.byref(pp), ctypes.byref(R)))
+    tt.ftt_p, tt.fibers = int(pp.value), int(R.value)
+    return tt
+
+
+def fasttt_select_p(idx: torch.Tensor, val: torch.Tensor, dims, stream=None):
+    """Algorithm 9: (p, estimated cost of every p = 1..d)."""
+    L = _lib.load()
+    idx, val, d, nnz, dims_a = _coo_args(idx, val, dims)
+    costs = (ctypes.c_double * d)()
+    pp = ctypes.c_int32()
+    _lib.check(L.tt_fasttt_select_p(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                    costs, ctypes.byref(pp), _stream_handle(stream)))
+    return int(pp.value), [float(x) for x in costs]
 
 
 def matrix_to_tensor(rows: torch.Tensor, cols: torch.Tensor, row_dims, col_dims, stream=None) -> torch.Tensor:

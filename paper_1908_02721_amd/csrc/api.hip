@@ -13,6 +13,7 @@
 
 #include "common.hpp"
 #include "dense.hpp"
+#include "ftt.hpp"
 #include "prim.hpp"
 #include "sparse.hpp"
 
@@ -164,6 +165,8 @@ struct tt_result_s {
   std::vector<double> tail;
   std::vector<double> bond_delta;
   double ms[TT_NUM_STAGES] = {};
+  int32_t ftt_p = 0;        // fiber-trie FastTT result: the p used (0 otherwise)
+  int64_t ftt_fibers = 0;   // and its number of nonzero p-fibers
 };
 
 namespace tts {
@@ -566,6 +569,153 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
   }
 }
 
+tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                              double eps, int32_t p, const tt_options* opt, void* stream, tt_result* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return TT_ERR_ARG;
+  }
+  *out = nullptr;
+  tt_options o;
+  tt_options_default(&o);
+  if (opt) o = *opt;
+  std::string why;
+  if (d < 2 || d > TT_MAX_D) why = "d must be in [2, 64]";
+  else if (!dims) why = "dims is NULL";
+  else if (nnz < 0 || nnz >= (int64_t(1) << 31)) why = "nnz must be in [0, 2^31)";
+  else if (nnz > 0 && (!idx || !val)) why = "idx/val is NULL";
+  else if (!(eps >= 0.0 && eps < 1.0)) why = "eps must satisfy 0 <= eps < 1";
+  else if (p < 0 || p > d) why = "p must be in [0, d] (0: chosen by Algorithm 9)";
+  else if (o.precision != TT_FP64) why = "the fiber-trie variant computes in FP64 only";
+  else if (o.max_rank < 0) why = "max_rank must be >= 0";
+  else if (o.dynamic_delta || o.key_bits || o.keep_intermediates)
+    why = "dynamic_delta, key_bits and keep_intermediates apply to tt_sparse_decompose only";
+  else if ((o.alloc == nullptr) != (o.free == nullptr)) why = "alloc and free hooks must be given together";
+  if (why.empty())
+    for (int k = 0; k < d; ++k)
+      if (dims[k] < 1 || dims[k] > INT32_MAX) why = "every n_k must be in [1, 2^31-1]";
+  if (!why.empty()) {
+    set_error(why);
+    return TT_ERR_ARG;
+  }
+  if (nnz == 0) {
+    set_error("no nonzero given");
+    return TT_ERR_EMPTY;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tt_result_s* R = nullptr;
+  try {
+    configure_pool_once();
+    R = new tt_result_s();
+    R->al.stream = s;
+    R->al.hook_alloc = o.alloc;
+    R->al.hook_free = o.free;
+    R->al.ctx = o.alloc_ctx;
+    R->al.budget = o.device_mem_budget;
+    R->d = d;
+    R->dims.assign(dims, dims + d);
+    Events ev;
+    TTS_HIP(hipEventRecord(ev.e[0], s));
+    if (p == 0) p = ftt_select_p(&R->al, idx, val, static_cast<uint32_t>(nnz), R->dims, nullptr, s);
+    TTS_HIP(hipEventRecord(ev.e[1], s));
+    TTS_HIP(hipEventRecord(ev.e[2], s));
+    FttExact ex;
+    ftt_exact(&R->al, idx, val, static_cast<uint32_t>(nnz), R->dims, p, ex, s);
+    TTS_HIP(hipEventRecord(ev.e[3], s));
+    R->nnz = ex.nnz;
+    R->norm = ex.norm;
+    R->betas = ex.ranks;
+    R->ftt_p = p;
+    R->ftt_fibers = ex.fibers;
+    R->delta = eps * ex.norm / (std::sqrt(static_cast<double>(p - 1)) + std::sqrt(static_cast<double>(d - p)));
+    if (o.sparse_only) {
+      R->cores = std::move(ex.cores);
+      R->ranks = R->betas;
+      TTS_HIP(hipEventRecord(ev.e[4], s));
+      TTS_HIP(hipEventRecord(ev.e[5], s));
+    } else {
+      RoundOutput ro;
+      std::vector<int64_t> r = ex.ranks;
+      ftt_round(&R->al, R->dims, p, eps, ex.norm, o.max_rank, ex.cores, r, ro, ev.e[4], s);
+      R->qr_ranks = ro.qr_ranks;
+      R->ranks = ro.ranks;
+      R->cores = std::move(ex.cores);
+      R->sigma = std::move(ro.sigma);
+      R->tail = std::move(ro.tail);
+      R->bond_delta = std::move(ro.bond_delta);
+      R->rounded = 1;
+      TTS_HIP(hipEventRecord(ev.e[5], s));
+    }
+    R->dtype = TT_DTYPE_F64;
+    TTS_HIP(hipEventRecord(ev.e[6], s));
+    TTS_HIP(hipEventSynchronize(ev.e[6]));
+    for (int i = 0; i < TT_NUM_STAGES - 1; ++i) {
+      float ms = 0.f;
+      TTS_HIP(hipEventElapsedTime(&ms, ev.e[i], ev.e[i + 1]));
+      R->ms[i] = ms;
+    }
+    float tot = 0.f;
+    TTS_HIP(hipEventElapsedTime(&tot, ev.e[0], ev.e[6]));
+    R->ms[TT_NUM_STAGES - 1] = tot;
+    *out = R;
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return TT_ERR_NOMEM;
+  }
+}
+
+tt_status tt_get_fasttt_info(tt_result r, int32_t* p, int64_t* fibers) {
+  if (!r) return TT_ERR_ARG;
+  if (r->ftt_p == 0) {
+    set_error("not a fiber-trie FastTT result");
+    return TT_ERR_ARG;
+  }
+  if (p) *p = r->ftt_p;
+  if (fibers) *fibers = r->ftt_fibers;
+  return TT_OK;
+}
+
+tt_status tt_fasttt_select_p(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                             double* costs, int32_t* p, void* stream) {
+  std::string why;
+  if (d < 2 || d > TT_MAX_D) why = "d must be in [2, 64]";
+  else if (!dims || !p) why = "dims/p is NULL";
+  else if (nnz <= 0 || nnz >= (int64_t(1) << 31)) why = "nnz must be in [1, 2^31)";
+  else if (!idx || !val) why = "idx/val is NULL";
+  if (why.empty())
+    for (int k = 0; k < d; ++k)
+      if (dims[k] < 1 || dims[k] > INT32_MAX) why = "every n_k must be in [1, 2^31-1]";
+  if (!why.empty()) {
+    set_error(why);
+    return TT_ERR_ARG;
+  }
+  try {
+    configure_pool_once();
+    Allocator al;
+    al.stream = static_cast<hipStream_t>(stream);
+    std::vector<int64_t> dv(dims, dims + d);
+    std::vector<double> c;
+    *p = ftt_select_p(&al, idx, val, static_cast<uint32_t>(nnz), dv, &c, al.stream);
+    if (costs) std::copy(c.begin(), c.end(), costs);
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
+}
+
 void tt_free(tt_result r) {
   if (!r) return;
   // The cores may still be read by the caller's work on any stream: wait for the
@@ -645,6 +795,10 @@ tt_status tt_get_times(tt_result r, double* host_ms) {
 tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, const int64_t** col, const int32_t** g,
                        const double** s, const int64_t** n_colptr, const int32_t** n_row, const double** n_val) {
   if (!r || k < 1 || k >= r->d) return TT_ERR_ARG;
+  if (r->lev.size() < static_cast<size_t>(k)) {
+    set_error("no sparse-stage levels in this result (fiber-trie FastTT)");
+    return TT_ERR_ARG;
+  }
   const LevelData& L = r->lev[k - 1];
   if (ncols) *ncols = L.ncols;
   if (beta) *beta = L.beta;

@@ -33,6 +33,18 @@ struct RoundOutput {
   std::vector<double> bond_delta;          // truncation threshold used per bond
 };
 
+// Truncated SVD of a column-major m x c matrix (left singular vectors U, m x rank,
+// and V Sigma, c x rank, with the sign rule applied to both).
+struct SvdPart {
+  DBuf<char> U;                // m x rank, column-major (double)
+  DBuf<double> VS;             // c x rank, column-major
+  std::vector<double> sigma;   // c singular values, non-ascending
+  double tail = 0.0;           // discarded sum of sigma^2
+  int rank = 0;
+};
+void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,
+                   hipStream_t s);
+
 // Rounds the exact TT.  Records `mid` on the stream between the QR sweep and the
 // truncated-SVD sweep.
 void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid);

@@ -118,6 +118,97 @@ struct EventPair {
 
 }  // namespace
 
+// Truncated SVD of the column-major m x c matrix G (read only): G = Q R (m > c) or G
+// itself; one-sided Jacobi then runs on the transpose, Bt = R^T or G^T (c x cB):
+// Bt U_R = V_R Sigma, so the accumulated rotations are the left singular vectors of
+// R (resp. G) and the rotated columns are V Sigma, both without a division by sigma.
+// (Jacobi on R^T rather than R also needs far fewer sweeps: the triangular factor
+// acts as a preconditioner.)  One read-back: the singular values together with
+// CholeskyQR2's success flags; on a breakdown the QR is redone with Householder.
+// Rank: the smallest r >= 1 with discarded sum of sigma^2 <= delta2, or with
+// max_rank > 0 min(max_rank, #nonzero sigma).  U (m x rank) and VS (c x rank) follow
+// the sign rule (largest-magnitude entry of each column of U positive).
+void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,
+                   hipStream_t s) {
+  DBuf<double> Qb, Bt;
+  bool haveQ = false;
+  int cB = m;
+  Bt.reset(A, static_cast<size_t>(c) * std::min(m, c));
+  if (m > c) {
+    cB = c;
+    haveQ = true;
+    Qb.reset(A, static_cast<size_t>(m) * c);
+  }
+  DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
+  DBuf<int32_t> dperm(A, cB), okq(A, 4);
+  std::vector<double> sh(cB);
+  auto svd_of_bt = [&]() {
+    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), s);
+    k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
+    TTS_LAUNCH_CHECK();
+    TTS_HIP(hipMemcpyAsync(sh.data(), sig.get(), sizeof(double) * cB, hipMemcpyDeviceToHost, s));
+  };
+  if (haveQ) {
+    DBuf<double> R(A, static_cast<size_t>(c) * c);
+    cholqr2_async(A, G, m, c, Qb.get(), R.get(), okq.get(), s);
+    transpose(R.get(), c, c, c, Bt.get(), c, s);
+    svd_of_bt();
+    int32_t okh[4];
+    TTS_HIP(hipMemcpyAsync(okh, okq.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipStreamSynchronize(s));
+    if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
+      DBuf<double> Af(A, static_cast<size_t>(m) * c), th(A, c);
+      copy_matrix(G, m, c, m, Af.get(), m, s);
+      householder_qr(Af.get(), m, c, m, th.get(), s);
+      householder_form_q(Af.get(), m, c, m, th.get(), Qb.get(), m, s);
+      householder_extract_r(Af.get(), m, c, m, R.get(), c, Qb.get(), m, s);
+      transpose(R.get(), c, c, c, Bt.get(), c, s);
+      svd_of_bt();
+      TTS_HIP(hipStreamSynchronize(s));
+    }
+  } else {
+    transpose(G, m, c, m, Bt.get(), c, s);
+    svd_of_bt();
+    TTS_HIP(hipStreamSynchronize(s));
+  }
+  // the same stable non-ascending order as k_rank_desc
+  std::vector<int32_t> perm(cB);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return sh[x] > sh[y]; });
+  // c singular values in all (the c - cB beyond the rank bound are zero)
+  std::vector<double> ss(c, 0.0), tailsum(c + 1, 0.0);
+  for (int j = 0; j < cB; ++j) ss[j] = sh[perm[j]];
+  for (int j = c - 1; j >= 0; --j) tailsum[j] = tailsum[j + 1] + ss[j] * ss[j];
+  int rk;
+  if (max_rank > 0) {
+    int nz = 0;
+    for (double x : ss) nz += (x > 0.0);
+    rk = std::max(1, std::min(max_rank, nz));
+  } else {
+    rk = c;
+    for (int t = 1; t <= c; ++t)
+      if (tailsum[t] <= delta2) {
+        rk = t;
+        break;
+      }
+  }
+  rk = std::min(rk, cB);
+  o.sigma = ss;
+  o.tail = tailsum[rk];
+  o.rank = rk;
+  DBuf<double> UR(A, static_cast<size_t>(cB) * rk);
+  o.VS.reset(A, static_cast<size_t>(c) * rk);
+  permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
+  permute_cols(Bt.get(), c, c, dperm.get(), nullptr, rk, o.VS.get(), c, s);
+  o.U.reset(A, sizeof(double) * static_cast<size_t>(m) * rk);
+  double* U = reinterpret_cast<double*>(o.U.get());
+  if (haveQ)
+    gemm_prec(A, prec, false, false, m, rk, c, 1.0, Qb.get(), m, UR.get(), c, 0.0, U, m, s);
+  else
+    copy_matrix(UR.get(), m, rk, m, U, m, s);
+  sign_fix(U, m, rk, m, o.VS.get(), c, c, s);
+}
+
 void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t s, hipEvent_t mid) {
   const int prec = in.precision;
   if (prec != TT_FP64 && prec != TT_FP32 && prec != TT_BF16_FP32ACC) fail(TT_ERR_ARG, "unknown precision");
@@ -318,96 +409,19 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     const int m = nk * rr;
     const double delta2 = in.dynamic_delta ? rem2 / static_cast<double>(k - 1) : in.delta * in.delta;
     out.bond_delta[k - 2] = std::sqrt(delta2);
-    double* Gk = reinterpret_cast<double*>(cores[k - 1].get());  // column-major m x rl
-    // G = Q R (m > rl) or G itself; one-sided Jacobi then runs on the transpose,
-    // Bt = R^T or G^T (rl x cB): Bt U_R = V_R Sigma, so the accumulated rotations
-    // are the left singular vectors of R (resp. G) and the rotated columns are
-    // V Sigma, both without a division by sigma.  (Jacobi on R^T rather than R
-    // also needs far fewer sweeps: the triangular factor acts as a preconditioner.)
-    // One read-back per bond: the singular values together with CholeskyQR2's
-    // success flags; on a breakdown the bond is redone with Householder QR.
-    DBuf<double> Qb, Bt;
-    bool haveQ = false;
-    int cB = m;
-    Bt.reset(A, static_cast<size_t>(rl) * std::min(m, rl));
-    if (m > rl) {
-      cB = rl;
-      haveQ = true;
-      Qb.reset(A, static_cast<size_t>(m) * rl);
-    }
-    DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
-    DBuf<int32_t> dperm(A, cB), okq(A, 4);
-    std::vector<double> sh(cB);
-    auto svd_of_bt = [&]() {
-      jacobi_svd(Bt.get(), rl, cB, rl, V.get(), cB, sig.get(), s);
-      k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
-      TTS_LAUNCH_CHECK();
-      TTS_HIP(hipMemcpyAsync(sh.data(), sig.get(), sizeof(double) * cB, hipMemcpyDeviceToHost, s));
-    };
-    if (haveQ) {
-      DBuf<double> R(A, static_cast<size_t>(rl) * rl);
-      cholqr2_async(A, Gk, m, rl, Qb.get(), R.get(), okq.get(), s);
-      transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
-      svd_of_bt();
-      int32_t okh[4];
-      TTS_HIP(hipMemcpyAsync(okh, okq.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
-      TTS_HIP(hipStreamSynchronize(s));
-      if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
-        DBuf<double> Af(A, static_cast<size_t>(m) * rl), th(A, rl);
-        copy_matrix(Gk, m, rl, m, Af.get(), m, s);
-        householder_qr(Af.get(), m, rl, m, th.get(), s);
-        householder_form_q(Af.get(), m, rl, m, th.get(), Qb.get(), m, s);
-        householder_extract_r(Af.get(), m, rl, m, R.get(), rl, Qb.get(), m, s);
-        transpose(R.get(), rl, rl, rl, Bt.get(), rl, s);
-        svd_of_bt();
-        TTS_HIP(hipStreamSynchronize(s));
-      }
-    } else {
-      transpose(Gk, m, rl, m, Bt.get(), rl, s);
-      svd_of_bt();
-      TTS_HIP(hipStreamSynchronize(s));
-    }
-    // the same stable non-ascending order as k_rank_desc
-    std::vector<int32_t> perm(cB);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return sh[x] > sh[y]; });
-    // rl singular values in all (the rl - cB beyond the rank bound are zero)
-    std::vector<double> ss(rl, 0.0), tailsum(rl + 1, 0.0);
-    for (int j = 0; j < cB; ++j) ss[j] = sh[perm[j]];
-    for (int j = rl - 1; j >= 0; --j) tailsum[j] = tailsum[j + 1] + ss[j] * ss[j];
-    int rk;
-    if (in.max_rank > 0) {
-      int nz = 0;
-      for (double x : ss) nz += (x > 0.0);
-      rk = std::max(1, std::min(in.max_rank, nz));
-    } else {
-      rk = rl;
-      for (int c = 1; c <= rl; ++c)
-        if (tailsum[c] <= delta2) {
-          rk = c;
-          break;
-        }
-    }
-    rk = std::min(rk, cB);
-    out.sigma[k - 2] = ss;
-    out.tail[k - 2] = tailsum[rk];
-    rem2 = std::max(0.0, rem2 - tailsum[rk]);
-    DBuf<double> UR(A, static_cast<size_t>(cB) * rk), VS(A, static_cast<size_t>(rl) * rk);
-    permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
-    permute_cols(Bt.get(), rl, rl, dperm.get(), nullptr, rk, VS.get(), rl, s);
-    DBuf<char> Unew(A, sizeof(double) * static_cast<size_t>(m) * rk);
-    double* U = reinterpret_cast<double*>(Unew.get());
-    if (haveQ)
-      gemm_prec(A, prec, false, false, m, rk, rl, 1.0, Qb.get(), m, UR.get(), rl, 0.0, U, m, s);
-    else
-      copy_matrix(UR.get(), m, rk, m, U, m, s);
-    sign_fix(U, m, rk, m, VS.get(), rl, rl, s);
-    // merge V*Sigma into core k-1: unfold_2(G_{k-1}) (rows2 x rl) * VS (rl x rk)
+    SvdPart sv;
+    truncated_svd(A, prec, reinterpret_cast<const double*>(cores[k - 1].get()), m, rl, delta2, in.max_rank, sv, s);
+    out.sigma[k - 2] = std::move(sv.sigma);
+    out.tail[k - 2] = sv.tail;
+    rem2 = std::max(0.0, rem2 - sv.tail);
+    const int rk = sv.rank;
+    // core k = U (m x rk column-major = [rk][n_k][r_k] row-major); merge V*Sigma into
+    // core k-1: unfold_2(G_{k-1}) (rows2 x rl) * VS (rl x rk)
     const int rows2 = static_cast<int>(r[k - 2]) * n[k - 2];
     DBuf<char> Pnew(A, sizeof(double) * static_cast<size_t>(rows2) * rk);
-    gemm_prec(A, prec, true, false, rk, rows2, rl, 1.0, VS.get(), rl, reinterpret_cast<double*>(cores[k - 2].get()), rl, 0.0,
-         reinterpret_cast<double*>(Pnew.get()), rk, s);
-    cores[k - 1] = std::move(Unew);
+    gemm_prec(A, prec, true, false, rk, rows2, rl, 1.0, sv.VS.get(), rl, reinterpret_cast<double*>(cores[k - 2].get()),
+              rl, 0.0, reinterpret_cast<double*>(Pnew.get()), rk, s);
+    cores[k - 1] = std::move(sv.U);
     cores[k - 2] = std::move(Pnew);
     r[k - 1] = rk;
   }

@@ -113,6 +113,37 @@ def test_matrix_to_tensor_host_argument_errors(lib):
     assert call(2, [2, 2], [2, 2], nnz=0, rows=None, cols=None, idx=None) == 0  # nothing to do
 
 
+def test_fasttt_host_argument_errors(lib):
+    from paper_1908_02721_amd import _lib
+
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+
+    def call(d, dims, nnz, p, opt=None, eps=0.1):
+        o = _lib.tt_options()
+        lib.tt_options_default(ctypes.byref(o))
+        for k, v in (opt or {}).items():
+            setattr(o, k, v)
+        a = (ctypes.c_int64 * len(dims))(*dims)
+        h = ctypes.c_void_p(123)
+        st = lib.tt_fasttt_decompose(d, a, nnz, fake, fake, eps, p, ctypes.byref(o), None, ctypes.byref(h))
+        assert h.value is None
+        return st
+
+    assert call(3, [4, 4, 4], 5, -1) == 1
+    assert call(3, [4, 4, 4], 5, 4) == 1
+    assert call(3, [4, 4, 4], 5, 2, {"precision": 1}) == 1
+    assert call(3, [4, 4, 4], 5, 2, {"dynamic_delta": 1}) == 1
+    assert call(3, [4, 4, 4], 5, 2, {"key_bits": 30}) == 1
+    assert call(3, [4, 4, 4], 5, 2, {"keep_intermediates": 1}) == 1
+    assert call(3, [4, 4, 4], 5, 2, eps=1.0) == 1
+    assert call(1, [4], 5, 1) == 1
+    assert call(3, [4, 4, 4], 0, 2) == 5
+    assert lib.tt_get_fasttt_info(None, None, None) == 1
+    pp = ctypes.c_int32()
+    a = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert lib.tt_fasttt_select_p(3, a, 0, fake, fake, None, ctypes.byref(pp), None) == 1
+
+
 def test_options_layout_matches_header(tmp_path):
     """The ctypes mirror of tt_options has the C struct's size and field offsets."""
     import shutil
