@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp64|fp32|bf16]
                     [--dynamic-delta] [--key-bits B] [--matrix-input] [--roofline FAMILY]
+                    [--method cps|fasttt] [--p P]
 
 One step is one pass of the whole hot path over the workload's nonzeros, all in
 libttsparse kernels:
@@ -13,7 +14,9 @@ libttsparse kernels:
 With --matrix-input (the Laplacian workload) the step starts from the sparse matrix
 and first runs tt_matrix_to_tensor, the front-end of the MPO form.  With
 --dynamic-delta the truncation thresholds follow Algorithm 8; with --key-bits B the
-parallel test groups canonical values rounded to B fraction bits.
+parallel test groups canonical values rounded to B fraction bits.  With --method
+fasttt the decomposition is the paper's fiber-trie variant (tt_fasttt_decompose,
+p from --p or Algorithm 9).
 Inputs are resident in HBM before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -62,6 +65,9 @@ def _parse():
     p.add_argument("--matrix-input", action="store_true",
                    help="start from the workload's sparse matrix (laplace2d_qtt_L10): the step then also runs the "
                         "matrix -> tensor front-end of the MPO form")
+    p.add_argument("--method", default="cps", choices=["cps", "fasttt"],
+                   help="cps: column-parallel sweep (tt_sparse_decompose); fasttt: the fiber-trie variant")
+    p.add_argument("--p", type=int, default=0, help="fasttt: the middle core p (0: Algorithm 9)")
     p.add_argument("--key-bits", type=int, default=0,
                    help="tolerant parallel test: canonical values rounded to this many fraction bits (0: exact)")
     p.add_argument("--dynamic-delta", action="store_true",
@@ -76,7 +82,7 @@ def _parse():
 
 
 def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", max_rank=0, dynamic=False,
-                 key_bits=0):
+                 key_bits=0, method="cps", p=0):
     """The oracle (single-threaded FP64 C++), timed on this host on a bounded sample.
 
     Also returns ||B_gpu - B_oracle||_F / ||A||_F for the GPU result `gpu_cores`
@@ -86,7 +92,13 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
 
     oracle.build(force=False)
     t0 = time.perf_counter()
-    res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic, key_bits=key_bits)
+    if method == "fasttt":
+        from oracle import ftt
+
+        res = ftt.decompose(idx, val, dims, eps, p=p, max_rank=max_rank)
+        res.cores = [np.ascontiguousarray(c) for c in res.cores]
+    else:
+        res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic, key_bits=key_bits)
     t_dec = time.perf_counter() - t0
     rng = np.random.Generator(np.random.PCG64(11))
     pick = rng.choice(len(val), min(sample, len(val)), replace=False)
@@ -176,8 +188,11 @@ def main():
 
     def step():
         ci = tts.matrix_to_tensor(*matrix) if matrix is not None else gi
-        tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
-                           key_bits=args.key_bits)
+        if args.method == "fasttt":
+            tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p)
+        else:
+            tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
+                               key_bits=args.key_bits)
         cores = tt.cores
         gy = gv if cores[0].dtype == torch.float64 else gv.float()
         # one plan per step: the sort and trie of the coordinates serve the forward and
@@ -238,7 +253,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "nnz": nnz, "eps": eps,
                    "precision": args.precision, "dynamic_delta": bool(args.dynamic_delta),
-                   "matrix_input": bool(args.matrix_input), "key_bits": args.key_bits, "ranks": tt.ranks},
+                   "matrix_input": bool(args.matrix_input), "key_bits": args.key_bits, "method": args.method,
+                   "ranks": tt.ranks},
         "decompose_ms_median": float(np.median(dec_ms)),
         "decompose_nnz_per_s": nnz / (float(np.median(dec_ms)) / 1000.0),
         "stage_ms": tt.times_ms,
@@ -272,7 +288,8 @@ def main():
         cores_host = [c.cpu().numpy() for c in tt.cores]
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample,
                                                                    cores_host, args.precision,
-                                                                   dynamic=args.dynamic_delta, key_bits=args.key_bits)
+                                                                   dynamic=args.dynamic_delta, key_bits=args.key_bits,
+                                                                   method=args.method, p=args.p)
     print(json.dumps(out), flush=True)
 
 

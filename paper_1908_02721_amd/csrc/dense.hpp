@@ -33,6 +33,11 @@ struct RoundOutput {
   std::vector<double> bond_delta;          // truncation threshold used per bond
 };
 
+// CholeskyQR2 of the column-major m x c matrix G (m >= c): Q (m x c), R (c x c upper,
+// positive diagonal).  ok[0..3] (device) are set to 0 when a Cholesky factor breaks
+// down or is too ill-conditioned; nothing is read back.
+void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s);
+
 // Truncated SVD of a column-major m x c matrix (left singular vectors U, m x rank,
 // and V Sigma, c x rank, with the sign rule applied to both).
 struct SvdPart {

@@ -404,12 +404,24 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
   for (int k = d; k >= p + 1; --k) {
     const int r0 = static_cast<int>(r[k - 1]), n = static_cast<int>(dims[k - 1]), r1 = static_cast<int>(r[k]);
     const int m = n * r1, q = std::min(m, r0);
-    DBuf<double> Af(al, static_cast<size_t>(m) * r0), th(al, q), Rm(al, static_cast<size_t>(q) * r0);
-    copy_matrix(core(k), m, r0, m, Af.get(), m, s);
-    householder_qr(Af.get(), m, r0, m, th.get(), s);
+    DBuf<double> Rm(al, static_cast<size_t>(q) * r0);
     DBuf<char> Q(al, sizeof(double) * static_cast<size_t>(m) * q);
-    householder_form_q(Af.get(), m, q, m, th.get(), reinterpret_cast<double*>(Q.get()), m, s);
-    householder_extract_r(Af.get(), m, r0, m, Rm.get(), q, reinterpret_cast<double*>(Q.get()), m, s);
+    bool done = false;
+    if (m >= r0) {  // CholeskyQR2, checked; Householder when a factor breaks down
+      DBuf<int32_t> ok(al, 4);
+      cholqr2_async(al, core(k), m, r0, reinterpret_cast<double*>(Q.get()), Rm.get(), ok.get(), s);
+      int32_t h[4];
+      TTS_HIP(hipMemcpyAsync(h, ok.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+      TTS_HIP(hipStreamSynchronize(s));
+      done = h[0] && h[1] && h[2] && h[3];
+    }
+    if (!done) {
+      DBuf<double> Af(al, static_cast<size_t>(m) * r0), th(al, q);
+      copy_matrix(core(k), m, r0, m, Af.get(), m, s);
+      householder_qr(Af.get(), m, r0, m, th.get(), s);
+      householder_form_q(Af.get(), m, q, m, th.get(), reinterpret_cast<double*>(Q.get()), m, s);
+      householder_extract_r(Af.get(), m, r0, m, Rm.get(), q, reinterpret_cast<double*>(Q.get()), m, s);
+    }
     // core k-1 stored as column-major r0 x (r0' n') = spl_2^T; new = R (q x r0) times it
     const int cols = static_cast<int>(r[k - 2]) * static_cast<int>(dims[k - 2]);
     DBuf<char> Cp(al, sizeof(double) * static_cast<size_t>(q) * cols);

@@ -2076,6 +2076,79 @@ __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int row
   for (int i = lane; i < vrows; i += 64) v[i] = -v[i];
 }
 
+// Tall columns: each workgroup finds the entry of largest magnitude (lowest index on
+// ties) of one slice of rows of one column; slices are combined in order by
+// k_sign_decide, and k_apply_sign flips the columns whose entry is negative.
+constexpr int kSignRows = 4096;  // longer columns take the sliced path
+__global__ __launch_bounds__(NT) void k_colmax_slices(const double* __restrict__ U, int rows, int ldu, int slice,
+                                                      double* __restrict__ pabs, int* __restrict__ pidx,
+                                                      double* __restrict__ pval) {
+  __shared__ double sb[NT];
+  __shared__ int si[NT];
+  const int j = blockIdx.y, sl = blockIdx.x;
+  const int i0 = sl * slice, i1 = min(rows, i0 + slice);
+  const double* u = U + static_cast<size_t>(j) * ldu;
+  double best = -1.0;
+  int bi = rows;
+  for (int i = i0 + threadIdx.x; i < i1; i += 4 * NT) {
+    double a[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = (i + t * NT < i1) ? fabs(u[i + t * NT]) : -1.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (a[t] > best) {  // increasing index within a thread: a tie keeps the earlier one
+        best = a[t];
+        bi = i + t * NT;
+      }
+  }
+  sb[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double ob = sb[threadIdx.x + o];
+      const int oi = si[threadIdx.x + o];
+      if (ob > sb[threadIdx.x] || (ob == sb[threadIdx.x] && oi < si[threadIdx.x])) {
+        sb[threadIdx.x] = ob;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int q = j * gridDim.x + sl;
+    pabs[q] = sb[0];
+    pidx[q] = si[0];
+    pval[q] = si[0] < rows ? u[si[0]] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_sign_decide(const double* __restrict__ pabs, const int* __restrict__ pidx,
+                                                    const double* __restrict__ pval, int nslices, int r,
+                                                    double* __restrict__ sgn) {
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j >= r) return;
+  double best = -1.0, v = 0.0;
+  int bi = 0x7fffffff;
+  for (int sl = 0; sl < nslices; ++sl) {  // slices in row order: a tie keeps the earlier one
+    const int q = j * nslices + sl;
+    if (pabs[q] > best || (pabs[q] == best && pidx[q] < bi)) {
+      best = pabs[q];
+      bi = pidx[q];
+      v = pval[q];
+    }
+  }
+  sgn[j] = (v < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(NT) void k_apply_sign(double* __restrict__ X, int rows, int cols, int ld,
+                                                   const double* __restrict__ sgn) {
+  const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
+  if (e >= static_cast<size_t>(rows) * cols) return;
+  const int j = static_cast<int>(e / rows), i = static_cast<int>(e - static_cast<size_t>(j) * rows);
+  if (sgn[j] < 0.0) X[i + static_cast<size_t>(j) * ld] = -X[i + static_cast<size_t>(j) * ld];
+}
+
 }  // namespace
 
 void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
@@ -2365,8 +2438,32 @@ void permute_cols(const double* A, int rows, int lda, const int32_t* perm, const
 
 void sign_fix(double* U, int rows, int r, int ldu, double* VS, int vrows, int ldv, hipStream_t s) {
   if (r <= 0) return;
-  k_sign_fix<<<(r + 3) / 4, NT, 0, s>>>(U, rows, r, ldu, VS, vrows, ldv);
+  if (rows <= kSignRows) {
+    k_sign_fix<<<(r + 3) / 4, NT, 0, s>>>(U, rows, r, ldu, VS, vrows, ldv);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  // about 2048 workgroups over r columns, slices of at least 4 NT rows
+  int ns = std::max(1, std::min((rows + 4 * NT - 1) / (4 * NT), 2048 / std::max(1, r)));
+  const int slice = (rows + ns - 1) / ns;
+  ns = (rows + slice - 1) / slice;
+  const size_t np = static_cast<size_t>(ns) * r;
+  const size_t bytes = np * (2 * sizeof(double) + sizeof(int)) + sizeof(double) * r;
+  char* buf = static_cast<char*>(cached_alloc(bytes, s));
+  if (!buf) fail(TT_ERR_NOMEM, "device allocation failed");
+  double* pabs = reinterpret_cast<double*>(buf);
+  double* pval = pabs + np;
+  double* sgn = pval + np;
+  int* pidx = reinterpret_cast<int*>(sgn + r);
+  k_colmax_slices<<<dim3(ns, r), NT, 0, s>>>(U, rows, ldu, slice, pabs, pidx, pval);
   TTS_LAUNCH_CHECK();
+  k_sign_decide<<<(r + NT - 1) / NT, NT, 0, s>>>(pabs, pidx, pval, ns, r, sgn);
+  TTS_LAUNCH_CHECK();
+  k_apply_sign<<<grid_for(static_cast<size_t>(rows) * r, NT), NT, 0, s>>>(U, rows, r, ldu, sgn);
+  TTS_LAUNCH_CHECK();
+  k_apply_sign<<<grid_for(static_cast<size_t>(vrows) * r, NT), NT, 0, s>>>(VS, vrows, r, ldv, sgn);
+  TTS_LAUNCH_CHECK();
+  cached_free(buf, bytes, s);
 }
 
 }  // namespace tts

@@ -57,23 +57,6 @@ void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
   TTS_HIP(hipMemcpyAsync(dev, host, sizeof(T) * n, hipMemcpyHostToDevice, s));
 }
 
-// CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
-// ok[0..3] (device) are set to 0 when a Cholesky factor breaks down or is too
-// ill-conditioned; nothing is read back here.
-void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s) {
-  DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
-      g2(al, static_cast<size_t>(c) * c);
-  k_set_i32<<<1, 64, 0, s>>>(ok, 4, 1);
-  TTS_LAUNCH_CHECK();
-  gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
-  cholesky_upper(g1.get(), c, c, 1e7, ok + 0, s);
-  trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok + 1, s, al);
-  gemm(al, true, false, c, c, m, 1.0, q1.get(), m, q1.get(), m, 0.0, g2.get(), c, s);
-  cholesky_upper(g2.get(), c, c, 10.0, ok + 2, s);
-  trsm_right_upper(q1.get(), m, c, m, g2.get(), c, Q, m, ok + 3, s, al);
-  gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
-}
-
 // perm[rank(j)] = j for the stable non-ascending order of s[0..n): rank(j) = number of
 // i with s_i > s_j, or s_i == s_j and i < j.
 __global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv, int n, int32_t* __restrict__ perm) {
@@ -117,6 +100,23 @@ struct EventPair {
 };
 
 }  // namespace
+
+// CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
+// ok[0..3] (device) are set to 0 when a Cholesky factor breaks down or is too
+// ill-conditioned; nothing is read back here.
+void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s) {
+  DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
+      g2(al, static_cast<size_t>(c) * c);
+  k_set_i32<<<1, 64, 0, s>>>(ok, 4, 1);
+  TTS_LAUNCH_CHECK();
+  gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
+  cholesky_upper(g1.get(), c, c, 1e7, ok + 0, s);
+  trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok + 1, s, al);
+  gemm(al, true, false, c, c, m, 1.0, q1.get(), m, q1.get(), m, 0.0, g2.get(), c, s);
+  cholesky_upper(g2.get(), c, c, 10.0, ok + 2, s);
+  trsm_right_upper(q1.get(), m, c, m, g2.get(), c, Q, m, ok + 3, s, al);
+  gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
+}
 
 // Truncated SVD of the column-major m x c matrix G (read only): G = Q R (m > c) or G
 // itself; one-sided Jacobi then runs on the transpose, Bt = R^T or G^T (c x cB):

@@ -232,6 +232,10 @@ WORKLOADS = {
     "kron8d_n32_t64_cont": dict(kind="kron", d=8, n=32, terms=64, q=4, seed=2, eps=1e-8, continuous=True),
     # 2D 5-point Laplacian, 1024 x 1024 grid, as a 20-way QTT tensor (5,238,784 nnz), eps 1e-10.
     "laplace2d_qtt_L10": dict(kind="laplace", L=10, eps=1e-10),
+    # 3D 7-point FDM matrix on a 40^3 grid, random coefficients, as a 3-way tensor
+    # with modes of size 1600 (438,400 nnz), eps 1e-14: the largest case of the FDM
+    # table, for the fiber-trie variant.
+    "fdm3d_n40_random": dict(kind="fdm", n=40, coeff="random", seed=1, eps=1e-14),
     # 5-way 200^5 with 10M random nonzeros, N(0,1), eps 1e-2.
     "random5d_n200_nnz10m": dict(kind="random", dims=(200,) * 5, nnz=10_000_000, seed=4, eps=1e-2),
 }
@@ -246,6 +250,8 @@ def workload(name: str):
         idx, val, dims = kronecker_sum(w["d"], w["n"], w["terms"], w["q"], w["seed"], w.get("continuous", False))
     elif w["kind"] == "laplace":
         idx, val, dims = laplacian_qtt(w["L"])
+    elif w["kind"] == "fdm":
+        idx, val, dims = fdm3d_mpo(w["n"], w["coeff"], w["seed"])
     else:  # pragma: no cover
         raise KeyError(name)
     return idx, val, dims, w["eps"]
