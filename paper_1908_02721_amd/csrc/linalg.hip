@@ -1204,70 +1204,6 @@ __global__ __launch_bounds__(64) void k_trsm_right_upper(const double* __restric
   }
 }
 
-// Inverse of an upper-triangular matrix staged in LDS (r <= 128): one thread per
-// column of the inverse, columns written back to global memory.
-__global__ __launch_bounds__(NT) void k_triu_inverse_lds(const double* __restrict__ U, int r, int ldu,
-                                                         double* __restrict__ X, int ldx, int32_t* __restrict__ ok) {
-  extern __shared__ double us[];
-  for (int e = threadIdx.x; e < r * r; e += NT) {
-    const int i = e % r, j = e / r;
-    us[e] = (i <= j) ? U[i + static_cast<size_t>(j) * ldu] : 0.0;
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < r; j += NT) {
-    double* x = X + static_cast<size_t>(j) * ldx;
-    for (int i = j + 1; i < r; ++i) x[i] = 0.0;
-    const double ujj = us[j + j * r];
-    if (ujj == 0.0) {
-      *ok = 0;
-      continue;
-    }
-    double col[128];
-    col[j] = 1.0 / ujj;
-    bool bad = false;
-    for (int i = j - 1; i >= 0; --i) {
-      double sacc = 0.0;
-      for (int l = i + 1; l <= j; ++l) sacc = fma(us[i + l * r], col[l], sacc);
-      const double uii = us[i + i * r];
-      if (uii == 0.0) {
-        bad = true;
-        break;
-      }
-      col[i] = -sacc / uii;
-    }
-    if (bad) {
-      *ok = 0;
-      continue;
-    }
-    for (int i = 0; i <= j; ++i) x[i] = col[i];
-  }
-}
-
-// Inverse of an upper-triangular matrix: one thread per column of the inverse.
-__global__ __launch_bounds__(NT) void k_triu_inverse(const double* __restrict__ U, int r, int ldu,
-                                                     double* __restrict__ X, int ldx, int32_t* __restrict__ ok) {
-  const int j = blockIdx.x * NT + threadIdx.x;
-  if (j >= r) return;
-  double* x = X + static_cast<size_t>(j) * ldx;
-  for (int i = j + 1; i < r; ++i) x[i] = 0.0;
-  const double ujj = U[j + static_cast<size_t>(j) * ldu];
-  if (ujj == 0.0) {
-    *ok = 0;
-    return;
-  }
-  x[j] = 1.0 / ujj;
-  for (int i = j - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int l = i + 1; l <= j; ++l) s = fma(U[i + static_cast<size_t>(l) * ldu], x[l], s);
-    const double uii = U[i + static_cast<size_t>(i) * ldu];
-    if (uii == 0.0) {
-      *ok = 0;
-      return;
-    }
-    x[i] = -s / uii;
-  }
-}
-
 __global__ __launch_bounds__(NT) void k_col_sumsq(const double* __restrict__ E, int rows, int lde,
                                                   double* __restrict__ out) {
   __shared__ double red[NT / 64];
@@ -1501,6 +1437,110 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
       const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
       Vg[i + static_cast<size_t>(j) * ldv] = V[i + static_cast<size_t>(j) * lv];
     }
+  }
+}
+
+// One-sided Jacobi for matrices whose A fits in LDS but A and V together do not
+// (c up to VT * GW columns): A in LDS, V in global memory (it stays in L2).  The
+// pair order, threshold and rotation are those of k_jacobi; each lane updates its
+// VT entries of both V columns with all loads issued before the stores.
+template <int NTH, int GW, int VT>
+__global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int rows, int c, int lda,
+                                                   double* __restrict__ V, int ldv, double* __restrict__ sigma) {
+  extern __shared__ double A[];  // rows x c, column-major, leading dimension rows
+  __shared__ int rotated;
+  for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
+    const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+    A[e] = Ag[i + static_cast<size_t>(j) * lda];
+  }
+  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += NTH) {
+    const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+    V[i + static_cast<size_t>(j) * ldv] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  constexpr int NG = NTH / GW;
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const int N = c + (c & 1);
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      for (int k = grp; k < N / 2; k += NG) {
+        int p, q;
+        if (k == 0) {
+          p = rd;
+          q = N - 1;
+        } else {
+          p = (rd + k) % (N - 1);
+          q = (rd - k + (N - 1)) % (N - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q >= c) continue;  // pair with the virtual column (uniform within the group)
+        double* ap = A + static_cast<size_t>(p) * rows;
+        double* aq = A + static_cast<size_t>(q) * rows;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = gl; i < rows; i += GW) {
+          const double x = ap[i], y = aq[i];
+          a = fma(x, x, a);
+          b = fma(y, y, b);
+          g = fma(x, y, g);
+        }
+#pragma unroll
+        for (int o = GW / 2; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, GW);
+          b += __shfl_xor(b, o, GW);
+          g += __shfl_xor(g, o, GW);
+        }
+        if (a == 0.0 || b == 0.0) continue;
+        if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
+        double cs, sn;
+        jacobi_rotation(a, b, g, &cs, &sn);
+        for (int i = gl; i < rows; i += GW) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = cs * x - sn * y;
+          aq[i] = sn * x + cs * y;
+        }
+        double* vp = V + static_cast<size_t>(p) * ldv;
+        double* vq = V + static_cast<size_t>(q) * ldv;
+        double xv[VT], yv[VT];
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {
+          const int i = min(gl + t * GW, c - 1);
+          xv[t] = vp[i];
+          yv[t] = vq[i];
+        }
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {
+          const int i = gl + t * GW;
+          if (i < c) {
+            vp[i] = cs * xv[t] - sn * yv[t];
+            vq[i] = sn * xv[t] + cs * yv[t];
+          }
+        }
+        if (gl == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int j = grp; j < c; j += NG) {
+    const double* aj = A + static_cast<size_t>(j) * rows;
+    double sacc = 0.0;
+    for (int i = gl; i < rows; i += GW) sacc = fma(aj[i], aj[i], sacc);
+#pragma unroll
+    for (int o = GW / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, GW);
+    if (gl == 0) sigma[j] = sqrt(sacc);
+  }
+  __syncthreads();
+  for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
+    const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+    Ag[i + static_cast<size_t>(j) * lda] = A[e];
   }
 }
 
@@ -2288,22 +2328,12 @@ void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, 
   TTS_LAUNCH_CHECK();
 }
 
-void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t* d_ok, hipStream_t s) {
-  if (r <= 0) return;
-  if (r <= 128) {
-    k_triu_inverse_lds<<<1, NT, sizeof(double) * r * r, s>>>(U, r, ldu, Ui, ldi, d_ok);
-    TTS_LAUNCH_CHECK();
-    return;
-  }
-  k_triu_inverse<<<grid_for(r, NT), NT, 0, s>>>(U, r, ldu, Ui, ldi, d_ok);
-  TTS_LAUNCH_CHECK();
-}
+namespace {
 
-void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
-                      int32_t* d_ok, hipStream_t s, Allocator* al) {
-  if (rows <= 0 || r <= 0) return;
-  // rows * r^2 / 2 multiply-adds; Y read, X written, U read once
-  KTimer kt("trsm", s, 8.0 * (2.0 * rows * r + static_cast<double>(r) * r), static_cast<double>(rows) * r * r);
+// X = Y U^{-1}.  Up to 64 columns by substitution kernels; wider U in blocks of 64
+// columns: X1 = Y1 U11^{-1}, then X2 = (Y2 - X1 U12) U22^{-1} (GEMM update).
+void trsm_blocks(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
+                 int32_t* d_ok, hipStream_t s, Allocator* al) {
   if (r <= 64 && rows >= 256) {
     k_trsm_mfma<<<grid_for(rows, 64), 256, 0, s>>>(Y, rows, r, ldy, U, ldu, X, ldx, d_ok);
     TTS_LAUNCH_CHECK();
@@ -2317,9 +2347,24 @@ void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U
     TTS_LAUNCH_CHECK();
     return;
   }
-  DBuf<double> ui(al, static_cast<size_t>(r) * r);
-  triu_inverse(U, r, ldu, ui.get(), r, d_ok, s);
-  gemm(al, false, false, rows, r, r, 1.0, Y, ldy, ui.get(), r, 0.0, X, ldx, s);
+  constexpr int B = 64;
+  const int r2 = r - B;
+  DBuf<double> Y2(al, static_cast<size_t>(rows) * r2);
+  copy_matrix(Y + static_cast<size_t>(B) * ldy, rows, r2, ldy, Y2.get(), rows, s);
+  trsm_blocks(Y, rows, B, ldy, U, ldu, X, ldx, d_ok, s, al);
+  gemm(al, false, false, rows, r2, B, -1.0, X, ldx, U + static_cast<size_t>(B) * ldu, ldu, 1.0, Y2.get(), rows, s);
+  trsm_blocks(Y2.get(), rows, r2, rows, U + B + static_cast<size_t>(B) * ldu, ldu, X + static_cast<size_t>(B) * ldx,
+              ldx, d_ok, s, al);
+}
+
+}  // namespace
+
+void trsm_right_upper(const double* Y, int rows, int r, int ldy, const double* U, int ldu, double* X, int ldx,
+                      int32_t* d_ok, hipStream_t s, Allocator* al) {
+  if (rows <= 0 || r <= 0) return;
+  // rows * r^2 / 2 multiply-adds; Y read, X written, U read once
+  KTimer kt("trsm", s, 8.0 * (2.0 * rows * r + static_cast<double>(r) * r), static_cast<double>(rows) * r * r);
+  trsm_blocks(Y, rows, r, ldy, U, ldu, X, ldx, d_ok, s, al);
 }
 
 void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde, const double* w, double* d_out,
@@ -2384,6 +2429,13 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
       k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
     else
       k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  // A in LDS, V in global memory: up to 160 columns
+  if (shm > 150 * 1024 && c <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
+    k_jacobi_lv<1024, 16, 10><<<1, 1024, sizeof(double) * static_cast<size_t>(rows) * c, s>>>(A, rows, c, lda, V,
+                                                                                             ldv, sigma);
     TTS_LAUNCH_CHECK();
     return;
   }

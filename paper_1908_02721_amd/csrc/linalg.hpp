@@ -46,8 +46,6 @@ void pivot_factor(const double* L, int n, const int32_t* piv, int r, double* U, 
 // In-place Cholesky A = U^T U of an r x r SPD matrix (upper factor, lower part zeroed);
 // *d_ok = 0 on breakdown or when max_j U_jj / min_j U_jj > max_ratio.
 void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, hipStream_t s);
-// Inverse of an upper-triangular r x r matrix (out-of-place).  *d_ok = 0 if singular.
-void triu_inverse(const double* U, int r, int ldu, double* Ui, int ldi, int32_t* d_ok, hipStream_t s);
 
 // X = Y U^{-1} for an upper-triangular r x r U (rows x r, column-major).
 // *d_ok = 0 if U has a zero diagonal entry.
