@@ -134,9 +134,13 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
  *   other arguments, inputs, errors and the result handle as tt_sparse_decompose.
  *   The exact ranks r~ of Algorithm 4 are the result's sparse ranks
  *   (tt_get_sparse_ranks: betas), the ranks after the QR sweep its qr_ranks.
- *   Options: FP64 only; max_rank, sparse_only (exact cores), device_mem_budget and
- *   the allocator hooks apply; dynamic_delta, key_bits and keep_intermediates give
- *   TT_ERR_ARG.  Every exact rank r~_k must be <= 16384 and every exact core at most
+ *   Options: FP64 only; max_rank, sparse_only (exact cores), device_mem_budget,
+ *   the allocator hooks and dynamic_delta apply (Algorithm 8 as stated: budgets
+ *   sqrt(d-p)/(sqrt(d-p)+sqrt(p-1)) eps ||A||_F right of p and
+ *   sqrt(p-1)/(...) eps ||A||_F left of p, bond k of the right sweep gets
+ *   delta_right/sqrt(d-k), bond k-1 of the left sweep delta_left/sqrt(k-1), each
+ *   budget then less the bond's discarded sum of sigma^2); key_bits and
+ *   keep_intermediates give TT_ERR_ARG.  Every exact rank r~_k must be <= 16384 and every exact core at most
  *   4e9 entries (else TT_ERR_TOO_LARGE): the variant suits tensors with few, dense
  *   fibers.  tt_get_level is not available.
  */

@@ -19,11 +19,16 @@ What it computes (0-based modes; p is 1-based as in the paper):
         spl_1^T(G^(k)) is i_k * r_k + (suffix id of i_{k+1}..i_d));
         G^(k)[a, i, b] = 1 when suffix a is i followed by suffix b;
       - the middle core holds the values: G^(p)[prefix id, i_p, suffix id] = a_i.
-  * round_tt(cores, p, eps, norm, max_rank) -- Algorithm 6: a delta-truncated SVD
-    sweep from core p to the right, a QR sweep back to core p, and a delta-truncated
-    SVD sweep from core p to the left, delta = eps ||A||_F / (sqrt(p-1) + sqrt(d-p))
-    (the static thresholds).  rank_delta = the smallest r >= 1 whose discarded sum of
-    sigma^2 is <= delta^2; fixed-rank truncation keeps min(max_rank, #nonzero sigma).
+  * round_tt(cores, p, eps, norm, max_rank, dynamic) -- Algorithm 6: a delta-truncated
+    SVD sweep from core p to the right, a QR sweep back to core p, and a
+    delta-truncated SVD sweep from core p to the left, delta = eps ||A||_F /
+    (sqrt(p-1) + sqrt(d-p)) (the static thresholds).  With dynamic, Algorithm 8: the
+    budgets delta_right = sqrt(d-p)/(sqrt(d-p)+sqrt(p-1)) eps ||A||_F and delta_left
+    = sqrt(p-1)/(...) eps ||A||_F; bond k of the first sweep gets
+    delta_right/sqrt(d-k), bond k-1 of the second delta_left/sqrt(k-1), and each
+    budget then loses the bond's discarded sum of sigma^2.  rank_delta = the smallest
+    r >= 1 whose discarded sum of sigma^2 is <= delta^2; fixed-rank truncation keeps
+    min(max_rank, #nonzero sigma).
   * flop_estimate / select_p -- the cost model of the complexity analysis (Sec. 3.6)
     with f_SVD(m, n) = m n min(m, n) and the rank bounds of Algorithm 4 (the upper
     bounds r_bar), and Algorithm 9: the p of least estimated cost (lowest p on ties).
@@ -32,7 +37,8 @@ Parity status: pinned (tests/test_oracle_ftt.py) by exact reconstruction of dens
 tiny tensors, the rank bounds, orthonormality of the indicator cores (corollary on
 left/right orthonormality), the paper's FDM numbers R and r~ (Table 2), dense
 TT-SVD ranks at eps -> 0, the error bound of Algorithm 6's correctness theorem,
-and the paper's worked FLOP examples.
+the paper's worked FLOP examples, and for Algorithm 8 its correctness theorem, the
+per-sweep budget invariants and dense TT-SVD ranks with the same thresholds at p = d.
 """
 from __future__ import annotations
 
@@ -60,6 +66,7 @@ class FttResult:
     delta: float
     sigma: list          # sigma[b-1] at bond b, sorted non-ascending
     tail: list           # discarded sum of sigma^2 at bond b
+    bond_delta: list = None  # threshold used at bond b
 
 
 def _validate(idx, val, dims):
@@ -140,21 +147,29 @@ def _sign_fix(U, VS):
     return U, VS
 
 
-def round_tt(cores, p: int, eps: float, norm: float, max_rank: int = 0):
-    """Algorithm 6 on dense cores; returns (cores, ranks, sigma, tail, delta)."""
+def round_tt(cores, p: int, eps: float, norm: float, max_rank: int = 0, dynamic: bool = False):
+    """Algorithm 6 (Algorithm 8 with dynamic) on dense cores;
+    returns (cores, ranks, sigma, tail, delta, bond_delta)."""
     G = [c.copy() for c in cores]
     d = len(G)
-    delta = eps * norm / (np.sqrt(p - 1) + np.sqrt(d - p)) if d > 1 else 0.0
+    den = np.sqrt(p - 1) + np.sqrt(d - p)
+    delta = eps * norm / den if d > 1 else 0.0
+    right2 = (np.sqrt(d - p) / den * eps * norm) ** 2   # delta_right^2
+    left2 = (np.sqrt(p - 1) / den * eps * norm) ** 2    # delta_left^2
     sigma = [None] * (d - 1)
     tail = [0.0] * (d - 1)
+    bond_delta = [delta] * (d - 1)
     # first SVD sweep: k = p..d-1, G = spl_2(G^(k)) = U S V^T, core k := U, G^(k+1) := (S V^T) G^(k+1)
     for k in range(p, d):
         r0, n, r1 = G[k - 1].shape
         M = G[k - 1].reshape(r0 * n, r1)
         U, s, Vt = np.linalg.svd(M, full_matrices=False)
-        r = _rank_rule(s, delta, max_rank)
+        dk = np.sqrt(right2 / (d - k)) if dynamic else delta
+        bond_delta[k - 1] = dk
+        r = _rank_rule(s, dk, max_rank)
         sigma[k - 1] = s
         tail[k - 1] = float(np.sum(s[r:] ** 2))
+        right2 = max(0.0, right2 - tail[k - 1])
         Uk = U[:, :r].copy()
         VS = (Vt[:r].T * s[:r]).copy()
         Uk, VS = _sign_fix(Uk, VS)
@@ -172,16 +187,19 @@ def round_tt(cores, p: int, eps: float, norm: float, max_rank: int = 0):
         r0, n, r1 = G[k - 1].shape
         M = G[k - 1].reshape(r0, n * r1).T
         U, s, Vt = np.linalg.svd(M, full_matrices=False)
-        r = _rank_rule(s, delta, max_rank)
+        dk = np.sqrt(left2 / (k - 1)) if dynamic else delta
+        bond_delta[k - 2] = dk
+        r = _rank_rule(s, dk, max_rank)
         sigma[k - 2] = s
         tail[k - 2] = float(np.sum(s[r:] ** 2))
+        left2 = max(0.0, left2 - tail[k - 2])
         Uk = U[:, :r].copy()
         VS = (Vt[:r].T * s[:r]).copy()
         Uk, VS = _sign_fix(Uk, VS)
         G[k - 1] = Uk.T.reshape(r, n, r1)
         G[k - 2] = np.tensordot(G[k - 2], VS, axes=([2], [0]))
     ranks = [1] + [int(g.shape[2]) for g in G]
-    return G, ranks, sigma, tail, delta
+    return G, ranks, sigma, tail, delta, bond_delta
 
 
 def fiber_count(idx, dims, p: int) -> int:
@@ -229,12 +247,13 @@ def select_p(idx, dims):
     return int(np.argmin(costs)) + 1, costs
 
 
-def decompose(idx, val, dims, eps: float, p: int = 0, max_rank: int = 0) -> FttResult:
-    """Algorithm 7 (FastTT): exact rank-reduced TT, then Algorithm 6.  p = 0: Algorithm 9."""
+def decompose(idx, val, dims, eps: float, p: int = 0, max_rank: int = 0, dynamic_delta: bool = False) -> FttResult:
+    """Algorithm 7 (FastTT): exact rank-reduced TT, then Algorithm 6 (Algorithm 8 with
+    dynamic_delta).  p = 0: Algorithm 9."""
     if p == 0:
         idx_v, _ = _validate(idx, val, dims)
         p, _ = select_p(idx_v, dims)
     ex = exact_tt(idx, val, dims, p)
-    cores, ranks, sigma, tail, delta = round_tt(ex.cores, p, eps, ex.norm, max_rank)
+    cores, ranks, sigma, tail, delta, bd = round_tt(ex.cores, p, eps, ex.norm, max_rank, dynamic_delta)
     return FttResult(cores=cores, ranks=ranks, exact_ranks=ex.ranks, R=ex.R, p=p, norm=ex.norm, delta=delta,
-                     sigma=sigma, tail=tail)
+                     sigma=sigma, tail=tail, bond_delta=bd)

@@ -588,8 +588,8 @@ tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
   else if (p < 0 || p > d) why = "p must be in [0, d] (0: chosen by Algorithm 9)";
   else if (o.precision != TT_FP64) why = "the fiber-trie variant computes in FP64 only";
   else if (o.max_rank < 0) why = "max_rank must be >= 0";
-  else if (o.dynamic_delta || o.key_bits || o.keep_intermediates)
-    why = "dynamic_delta, key_bits and keep_intermediates apply to tt_sparse_decompose only";
+  else if (o.key_bits || o.keep_intermediates)
+    why = "key_bits and keep_intermediates apply to tt_sparse_decompose only";
   else if ((o.alloc == nullptr) != (o.free == nullptr)) why = "alloc and free hooks must be given together";
   if (why.empty())
     for (int k = 0; k < d; ++k)
@@ -636,7 +636,7 @@ tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     } else {
       RoundOutput ro;
       std::vector<int64_t> r = ex.ranks;
-      ftt_round(&R->al, R->dims, p, eps, ex.norm, o.max_rank, ex.cores, r, ro, ev.e[4], s);
+      ftt_round(&R->al, R->dims, p, eps, ex.norm, o.max_rank, o.dynamic_delta != 0, ex.cores, r, ro, ev.e[4], s);
       R->qr_ranks = ro.qr_ranks;
       R->ranks = ro.ranks;
       R->cores = std::move(ex.cores);

@@ -367,11 +367,17 @@ int ftt_select_p(Allocator* al, const int32_t* idx, const double* val, uint32_t 
 }
 
 void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double eps, double norm, int max_rank,
-               std::vector<DBuf<char>>& cores, std::vector<int64_t>& r, RoundOutput& out, hipEvent_t mid,
+               bool dynamic, std::vector<DBuf<char>>& cores, std::vector<int64_t>& r, RoundOutput& out, hipEvent_t mid,
                hipStream_t s) {
   const int d = static_cast<int>(dims.size());
-  const double delta = eps * norm / (std::sqrt(static_cast<double>(p - 1)) + std::sqrt(static_cast<double>(d - p)));
-  const double delta2 = delta * delta;
+  const double den = std::sqrt(static_cast<double>(p - 1)) + std::sqrt(static_cast<double>(d - p));
+  const double delta = eps * norm / den;
+  // Algorithm 8: budgets of the sweep right of p and of the sweep left of p; a bond
+  // gets the remaining budget shared by the bonds still to come in its sweep, and the
+  // budget then loses what the bond discarded
+  const double right = std::sqrt(static_cast<double>(d - p)) / den * eps * norm;
+  const double left = std::sqrt(static_cast<double>(p - 1)) / den * eps * norm;
+  double right2 = right * right, left2 = left * left;
   out.sigma.assign(d - 1, {});
   out.tail.assign(d - 1, 0.0);
   out.bond_delta.assign(d - 1, delta);
@@ -383,11 +389,14 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
     const int m = r0 * n;
     DBuf<double> G(al, static_cast<size_t>(m) * r1);
     transpose(core(k), r1, m, r1, G.get(), m, s);  // stored [r0][n][r1] = column-major r1 x m
+    const double dk = dynamic ? std::sqrt(right2 / static_cast<double>(d - k)) : delta;
+    out.bond_delta[k - 1] = dk;
     SvdPart sv;
-    truncated_svd(al, TT_FP64, G.get(), m, r1, delta2, max_rank, sv, s);
+    truncated_svd(al, TT_FP64, G.get(), m, r1, dk * dk, max_rank, sv, s);
     const int rk = sv.rank;
     out.sigma[k - 1] = std::move(sv.sigma);
     out.tail[k - 1] = sv.tail;
+    right2 = std::max(0.0, right2 - sv.tail);
     DBuf<char> Ck(al, sizeof(double) * static_cast<size_t>(m) * rk);
     transpose(reinterpret_cast<const double*>(sv.U.get()), m, rk, m, reinterpret_cast<double*>(Ck.get()), rk, s);
     // core k+1 stored as column-major (n' r1') x r1 = spl_1^T; times VS (r1 x rk)
@@ -438,11 +447,14 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
   for (int k = p; k >= 2; --k) {
     const int r0 = static_cast<int>(r[k - 1]), n = static_cast<int>(dims[k - 1]), r1 = static_cast<int>(r[k]);
     const int m = n * r1;
+    const double dk = dynamic ? std::sqrt(left2 / static_cast<double>(k - 1)) : delta;
+    out.bond_delta[k - 2] = dk;
     SvdPart sv;
-    truncated_svd(al, TT_FP64, core(k), m, r0, delta2, max_rank, sv, s);
+    truncated_svd(al, TT_FP64, core(k), m, r0, dk * dk, max_rank, sv, s);
     const int rk = sv.rank;
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;
+    left2 = std::max(0.0, left2 - sv.tail);
     const int rows2 = static_cast<int>(r[k - 2]) * static_cast<int>(dims[k - 2]);
     DBuf<char> Pn(al, sizeof(double) * static_cast<size_t>(rows2) * rk);
     gemm(al, true, false, rk, rows2, r0, 1.0, sv.VS.get(), r0, core(k - 1), r0, 0.0,

@@ -31,9 +31,10 @@ int ftt_select_p(Allocator* al, const int32_t* idx, const double* val, uint32_t 
                  std::vector<double>* costs, hipStream_t s);
 
 // Algorithm 6 on the exact cores: SVD sweep from core p to the right, QR sweep back,
-// SVD sweep from core p to the left, delta = eps ||A|| / (sqrt(p-1) + sqrt(d-p)).
+// SVD sweep from core p to the left, delta = eps ||A|| / (sqrt(p-1) + sqrt(d-p));
+// with dynamic, the thresholds of Algorithm 8.
 void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double eps, double norm, int max_rank,
-               std::vector<DBuf<char>>& cores, std::vector<int64_t>& ranks, RoundOutput& out, hipEvent_t mid,
-               hipStream_t s);
+               bool dynamic, std::vector<DBuf<char>>& cores, std::vector<int64_t>& ranks, RoundOutput& out,
+               hipEvent_t mid, hipStream_t s);
 
 }  // namespace tts

@@ -52,12 +52,13 @@ def check_exact(idx, val, dims, p, label):
     return tt
 
 
-def check_round(oracle_mod, idx, val, dims, eps, p, label, max_rank=0, dense=False):
+def check_round(oracle_mod, idx, val, dims, eps, p, label, max_rank=0, dense=False, dynamic=False):
     tts = _tts()
-    print(f"[ftt round] {label} dims={tuple(dims)} nnz={len(val)} eps={eps} p={p} max_rank={max_rank}", flush=True)
-    res = oftt.decompose(idx, val, dims, eps, p=p, max_rank=max_rank)
+    print(f"[ftt round] {label} dims={tuple(dims)} nnz={len(val)} eps={eps} p={p} max_rank={max_rank} "
+          f"dynamic={dynamic}", flush=True)
+    res = oftt.decompose(idx, val, dims, eps, p=p, max_rank=max_rank, dynamic_delta=dynamic)
     gi, gv = _gpu(idx, val)
-    tt = tts.fasttt_decompose(gi, gv, dims, eps, p=p, max_rank=max_rank)
+    tt = tts.fasttt_decompose(gi, gv, dims, eps, p=p, max_rank=max_rank, dynamic_delta=dynamic)
     nrm = res.norm
     assert tt.ftt_p == res.p
     assert tt.betas == res.exact_ranks
@@ -68,7 +69,7 @@ def check_round(oracle_mod, idx, val, dims, eps, p, label, max_rank=0, dense=Fal
         mm = min(len(sg), len(so))
         assert np.max(np.abs(sg[:mm] - so[:mm])) <= TOL * nrm, f"bond {b} sigma"
         assert np.all(sg[mm:] <= TOL * nrm) and np.all(so[mm:] <= TOL * nrm)
-        assert abs(tt.bond_delta(b) - res.delta) <= 1e-15 * nrm
+        assert abs(tt.bond_delta(b) ** 2 - res.bond_delta[b - 1] ** 2) <= TOL * nrm * nrm
     cores = [c.cpu().numpy() for c in tt.cores]
     diff = oracle_mod.tt_diff_norm(cores, [np.ascontiguousarray(c) for c in res.cores])
     assert diff <= TOL * nrm, f"||B_gpu - B_oracle|| = {diff / nrm:.3e} ||A||"
@@ -184,3 +185,12 @@ def test_device_detected_errors():
     with pytest.raises(tts.TTError) as ei:
         tts.fasttt_decompose(gi, gv, dims, 0.1, p=1, sparse_only=True)
     assert ei.value.status == "TT_ERR_TOO_LARGE"
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.3, 0.6])
+@pytest.mark.parametrize("dims,nnz,seed", TINY[:4])
+def test_round_dynamic_thresholds(oracle_mod, dims, nnz, seed, eps):
+    """Algorithm 8 in the fiber-trie rounding, every p, against the oracle."""
+    idx, val, dims = synth.random_sparse(dims, nnz, seed)
+    for p in range(1, len(dims) + 1):
+        check_round(oracle_mod, idx, val, dims, eps, p, f"tiny {seed}", dense=True, dynamic=True)

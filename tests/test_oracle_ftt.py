@@ -123,3 +123,41 @@ def test_flop_examples_of_the_complexity_analysis():
     f = ftt.flop_estimate(dims, 7, rb, r)
     assert abs(f - 5.7e9) <= 0.02 * 5.7e9
     assert ftt.f_svd(3, 12000) == 1.08e5 and ftt.f_svd(12000, 3) == 1.08e5
+
+
+# ---- Algorithm 8 in the fiber-trie rounding ----
+
+@pytest.mark.parametrize("eps", [0.1, 0.3, 0.6])
+@pytest.mark.parametrize("dims,nnz,seed", TINY[:4])
+def test_dynamic_thresholds_theorem10(dims, nnz, seed, eps):
+    idx, val, dims = synth.random_sparse(dims, nnz, seed)
+    A = _brute.dense_tensor(idx, val, dims)
+    nrm = np.linalg.norm(A)
+    d = len(dims)
+    for p in range(1, d + 1):
+        st = ftt.decompose(idx, val, dims, eps, p=p)
+        dy = ftt.decompose(idx, val, dims, eps, p=p, dynamic_delta=True)
+        den = np.sqrt(p - 1) + np.sqrt(d - p)
+        right, left = np.sqrt(d - p) / den * eps * nrm, np.sqrt(p - 1) / den * eps * nrm
+        # loop invariants: each sweep's discarded sums stay within its budget
+        assert sum(dy.tail[k - 1] for k in range(p, d)) <= right ** 2 * (1 + 1e-12) + 1e-28
+        assert sum(dy.tail[k - 2] for k in range(2, p + 1)) <= left ** 2 * (1 + 1e-12) + 1e-28
+        # the correctness theorem of Algorithm 8
+        assert np.linalg.norm(_brute.tt_full(dy.cores) - A) <= eps * nrm + 1e-13 * nrm
+        # the first bond of each sweep sees the static threshold
+        if p < d:
+            assert abs(dy.bond_delta[p - 1] - st.delta) <= 1e-14 * nrm
+        if p > 1:
+            assert abs(dy.bond_delta[p - 2] - st.delta) <= 1e-14 * nrm
+
+
+@pytest.mark.parametrize("dims,nnz,seed", TINY[:4])
+def test_dynamic_thresholds_at_p_d_match_dense_ttsvd(dims, nnz, seed):
+    # at p = d the first sweep and the QR sweep are empty, and the second sweep is the
+    # right-to-left TT-SVD of the whole tensor with Algorithm 8's thresholds
+    idx, val, dims = synth.random_sparse(dims, nnz, seed)
+    A = _brute.dense_tensor(idx, val, dims)
+    for eps in (0.2, 0.5):
+        dy = ftt.decompose(idx, val, dims, eps, p=len(dims), dynamic_delta=True)
+        ranks, _ = _brute.tt_svd_right_to_left(A, eps, dynamic=True)
+        assert dy.ranks == ranks
