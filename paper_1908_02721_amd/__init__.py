@@ -289,16 +289,22 @@ def matrix_to_tensor(rows: torch.Tensor, cols: torch.Tensor, row_dims, col_dims,
 
 
 def decompose_matrix(rows: torch.Tensor, cols: torch.Tensor, val: torch.Tensor, row_dims, col_dims, eps: float,
-                     stream=None, **kw) -> TT:
+                     stream=None, method: str = "cps", **kw) -> TT:
     """Matrix in TT format (MPO) of a sparse M x N matrix, M = prod(row_dims), N = prod(col_dims).
 
     The matrix becomes the tensor with modes m_k * n_k (matrix_to_tensor), which is
-    decomposed with the same options as ``decompose``; ``TT.mpo_cores()`` gives the
+    decomposed by ``decompose`` (method "cps") or by the fiber-trie ``fasttt_decompose``
+    (method "fasttt"), with that function's options; ``TT.mpo_cores()`` gives the
     cores as [r_{k-1}, m_k, n_k, r_k].
     """
     idx = matrix_to_tensor(rows, cols, row_dims, col_dims, stream=stream)
     dims = [int(m) * int(n) for m, n in zip(row_dims, col_dims)]
-    tt = decompose(idx, val, dims, eps, stream=stream, **kw)
+    if method == "fasttt":
+        tt = fasttt_decompose(idx, val, dims, eps, stream=stream, **kw)
+    elif method == "cps":
+        tt = decompose(idx, val, dims, eps, stream=stream, **kw)
+    else:
+        raise ValueError("method must be 'cps' or 'fasttt'")
     tt.row_dims = tuple(int(x) for x in row_dims)
     tt.col_dims = tuple(int(x) for x in col_dims)
     return tt

@@ -133,3 +133,26 @@ def test_decompose_matrix_matvec():
     assert np.max(np.abs(V.reshape(-1) - y_ref)) <= 1e-12 * np.abs(v).sum()
     dense = _brute.dense_tensor(_coords_gpu(r, c, m, n), v, [a * b for a, b in zip(m, n)])
     assert np.linalg.norm(_brute.tt_full([G.cpu().numpy() for G in mpo.cores]) - dense) <= 1e-12 * np.linalg.norm(v)
+
+
+def test_fasttt_mpo_table2(oracle_mod):
+    """The FDM experiment of Table 2 end to end: matrix -> MPO by the front-end and the
+    fiber-trie FastTT (p by Algorithm 9), n = 20 with random coefficients: R = 1920,
+    r~ = 58, 58, final ranks 58, 58 at eps = 1e-14, and the MPO applied to a vector
+    equals the sparse product."""
+    tts = _tts()
+    r, c, v, m, n = synth.fdm3d_matrix(20, "random", seed=1)
+    print("[mpo fasttt] fdm n=20 random", flush=True)
+    mpo = tts.decompose_matrix(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda(),
+                               m, n, 1e-14, method="fasttt")
+    assert mpo.ftt_p == 2 and mpo.fibers == 1920
+    assert mpo.betas == [1, 58, 58, 1] and mpo.ranks == [1, 58, 58, 1]
+    cores = [G.cpu().numpy() for G in mpo.mpo_cores()]
+    rng = np.random.Generator(np.random.PCG64(5))
+    x = rng.standard_normal(int(np.prod(n)))
+    y_ref = np.zeros(int(np.prod(m)))
+    np.add.at(y_ref, r, v * x[c])
+    T = np.tensordot(cores[0][0], x.reshape(n), axes=([1], [0]))
+    U = np.einsum("irjk,rpjs->ipsk", T, cores[1])
+    V = np.einsum("ipsk,sqkt->ipqt", U, cores[2])[..., 0]
+    assert np.max(np.abs(V.reshape(-1) - y_ref)) <= 1e-12 * np.abs(v).sum()
