@@ -1441,9 +1441,10 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
 }
 
 // One-sided Jacobi for matrices whose A fits in LDS but A and V together do not
-// (c up to VT * GW columns): A in LDS, V in global memory (it stays in L2).  The
-// pair order, threshold and rotation are those of k_jacobi; each lane updates its
-// VT entries of both V columns with all loads issued before the stores.
+// (c and rows up to VT * GW): A in LDS, V in global memory (it stays in L2).  The
+// pair order, threshold and rotation are those of k_jacobi.  Each lane holds its VT
+// entries of both columns of A (and then of V) in registers, all loads issued before
+// the arithmetic; the group sums are DPP row reductions.
 template <int NTH, int GW, int VT>
 __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int rows, int c, int lda,
                                                    double* __restrict__ V, int ldv, double* __restrict__ sigma) {
@@ -1483,27 +1484,35 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
         if (q >= c) continue;  // pair with the virtual column (uniform within the group)
         double* ap = A + static_cast<size_t>(p) * rows;
         double* aq = A + static_cast<size_t>(q) * rows;
-        double a = 0.0, b = 0.0, g = 0.0;
-        for (int i = gl; i < rows; i += GW) {
-          const double x = ap[i], y = aq[i];
-          a = fma(x, x, a);
-          b = fma(y, y, b);
-          g = fma(x, y, g);
-        }
+        double xa[VT], ya[VT];
 #pragma unroll
-        for (int o = GW / 2; o > 0; o >>= 1) {
-          a += __shfl_xor(a, o, GW);
-          b += __shfl_xor(b, o, GW);
-          g += __shfl_xor(g, o, GW);
+        for (int t = 0; t < VT; ++t) {
+          const int i = min(gl + t * GW, rows - 1);
+          xa[t] = ap[i];
+          ya[t] = aq[i];
         }
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int t = 0; t < VT; ++t)
+          if (gl + t * GW < rows) {
+            a = fma(xa[t], xa[t], a);
+            b = fma(ya[t], ya[t], b);
+            g = fma(xa[t], ya[t], g);
+          }
+        a = group_sum<GW>(a);
+        b = group_sum<GW>(b);
+        g = group_sum<GW>(g);
         if (a == 0.0 || b == 0.0) continue;
         if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
         double cs, sn;
         jacobi_rotation(a, b, g, &cs, &sn);
-        for (int i = gl; i < rows; i += GW) {
-          const double x = ap[i], y = aq[i];
-          ap[i] = cs * x - sn * y;
-          aq[i] = sn * x + cs * y;
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {
+          const int i = gl + t * GW;
+          if (i < rows) {
+            ap[i] = cs * xa[t] - sn * ya[t];
+            aq[i] = sn * xa[t] + cs * ya[t];
+          }
         }
         double* vp = V + static_cast<size_t>(p) * ldv;
         double* vq = V + static_cast<size_t>(q) * ldv;
@@ -2433,7 +2442,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     return;
   }
   // A in LDS, V in global memory: up to 160 columns
-  if (shm > 150 * 1024 && c <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
+  if (shm > 150 * 1024 && c <= 160 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
     k_jacobi_lv<1024, 16, 10><<<1, 1024, sizeof(double) * static_cast<size_t>(rows) * c, s>>>(A, rows, c, lda, V,
                                                                                              ldv, sigma);
     TTS_LAUNCH_CHECK();
