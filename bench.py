@@ -5,7 +5,8 @@
                     [--method cps|fasttt] [--p P]
 
 One step is one pass of the whole hot path over the workload's nonzeros, all in
-libttsparse kernels:
+libttsparse kernels (the plan is built on a second stream beside the decomposition,
+as it needs only the coordinates; --no-overlap builds it afterwards):
   tt_sparse_decompose   ingest, sort, parallel-vector rounding of every level,
                         left-to-right QR sweep, right-to-left truncated-SVD sweep
   tt_eval_plan_create   sort of the nonzero coordinates and their prefix trie
@@ -25,6 +26,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -73,6 +75,8 @@ def _parse():
     p.add_argument("--dynamic-delta", action="store_true",
                    help="per-bond truncation thresholds from the remaining error budget (Algorithm 8)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-overlap", action="store_true",
+                   help="build the evaluation plan after the decomposition instead of beside it")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
     p.add_argument("--roofline", default="auto",
                    help="kernel family for the roofline object ('auto': the one with the most time per step)")
@@ -186,20 +190,45 @@ def main():
         matrix = (torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), m_dims, n_dims)
         gv = torch.from_numpy(np.ascontiguousarray(v)).cuda()
 
+    # The evaluation plan depends only on the coordinates: it is built on a second
+    # stream by a worker thread while the decomposition runs (the library calls
+    # release the GIL), and its kernels fill the decomposition's read-back gaps.
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+
     def step():
         ci = tts.matrix_to_tensor(*matrix) if matrix is not None else gi
-        if args.method == "fasttt":
-            tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p)
+        box = {}
+
+        def build_plan():
+            side.wait_stream(main)  # the coordinates are ready
+            box["plan"] = tts.EvalPlan(ci, dims, stream=side)
+
+        th = None
+        if args.no_overlap:
+            build_plan()
         else:
-            tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
-                               key_bits=args.key_bits)
+            th = threading.Thread(target=build_plan)
+            th.start()
+        try:
+            if args.method == "fasttt":
+                tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p)
+            else:
+                tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
+                                   key_bits=args.key_bits)
+        finally:
+            if th is not None:
+                th.join()
         cores = tt.cores
         gy = gv if cores[0].dtype == torch.float64 else gv.float()
         # one plan per step: the sort and trie of the coordinates serve the forward and
         # the backward, and the backward reuses the forward's left products
-        plan = tts.EvalPlan(ci, dims)
-        y = plan.forward(cores, save=True)
-        grads = plan.backward(cores, gy, use_saved=True)
+        plan = box["plan"]
+        side.wait_stream(main)  # the cores are ready
+        with torch.cuda.stream(side):
+            y = plan.forward(cores, save=True, stream=side)
+            grads = plan.backward(cores, gy, use_saved=True, stream=side)
+        main.wait_stream(side)
         return tt, y, grads
 
     for _ in range(args.warmup):

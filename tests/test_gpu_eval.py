@@ -247,3 +247,49 @@ def test_plan_wide_coordinates_and_errors(oracle_mod):
     assert empty.forward(cores2, save=True).numel() == 0
     gz = empty.backward(cores2, gy2[:0], use_saved=True)
     assert all(float(g.abs().max()) == 0.0 for g in gz)
+
+
+def test_plan_built_beside_a_decomposition():
+    """A plan built on a second stream by a worker thread while a decomposition runs
+    (both library calls release the GIL) gives bit-identical results to the same
+    calls made one after the other."""
+    import threading
+
+    import paper_1908_02721_amd as tts
+    from paper_1908_02721_amd import synth
+
+    idx, val, dims = synth.kronecker_sum(6, 12, 8, 3, seed=21)
+    gi = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda()
+    gv = torch.from_numpy(np.ascontiguousarray(val)).cuda()
+    print(f"[plan concurrency] kron d6 nnz={len(val)}", flush=True)
+    ref_tt = tts.decompose(gi, gv, dims, 1e-10)
+    ref_plan = tts.EvalPlan(gi, dims)
+    ref_y = ref_plan.forward(ref_tt.cores, save=True)
+    ref_g = ref_plan.backward(ref_tt.cores, gv, use_saved=True)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    for _ in range(3):
+        box = {}
+
+        def build():
+            side.wait_stream(main)
+            box["plan"] = tts.EvalPlan(gi, dims, stream=side)
+
+        th = threading.Thread(target=build)
+        th.start()
+        tt = tts.decompose(gi, gv, dims, 1e-10)
+        th.join()
+        cores = tt.cores
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            y = box["plan"].forward(cores, save=True, stream=side)
+            g = box["plan"].backward(cores, gv, use_saved=True, stream=side)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        assert tt.ranks == ref_tt.ranks
+        for a, b in zip(cores, ref_tt.cores):
+            assert torch.equal(a, b)
+        assert torch.equal(y, ref_y)
+        for a, b in zip(g, ref_g):
+            assert torch.equal(a, b)
