@@ -1553,6 +1553,158 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
   }
 }
 
+// The same Jacobi in two phases for c <= 138 (when V alone fits in LDS): the sweeps
+// run on A in LDS and log every slot's rotation (cos, sin) -- (1, 0) for a pair left
+// alone -- to `rot` in global memory; A goes back to memory, and V is then built in
+// LDS by replaying the log round by round (each group loads its next rotation one
+// round ahead).  No V traffic crosses L2 inside the sweeps.
+template <int NTH, int GW, int VT>
+__global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int rows, int c, int lda,
+                                                    double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
+                                                    double2* __restrict__ rot, int max_sweeps) {
+  extern __shared__ double sm[];  // A (rows x c), later V (c x c)
+  __shared__ int rotated, nsw;
+  double* A = sm;
+  for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
+    const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+    A[e] = Ag[i + static_cast<size_t>(j) * lda];
+  }
+  if (threadIdx.x == 0) nsw = 0;
+  __syncthreads();
+  constexpr int NG = NTH / GW;
+  const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const int N = c + (c & 1), H = N / 2;
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  auto pair_of = [&](int rd, int k, int* pp, int* qq) {
+    int p, q;
+    if (k == 0) {
+      p = rd;
+      q = N - 1;
+    } else {
+      p = (rd + k) % (N - 1);
+      q = (rd - k + (N - 1)) % (N - 1);
+    }
+    *pp = min(p, q);
+    *qq = max(p, q);
+  };
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int rd = 0; rd < N - 1; ++rd) {
+      double2* lr = rot + (static_cast<size_t>(sweep) * (N - 1) + rd) * H;
+      for (int k = grp; k < H; k += NG) {
+        int p, q;
+        pair_of(rd, k, &p, &q);
+        double cs = 1.0, sn = 0.0;
+        if (q < c) {  // uniform within the group
+          double* ap = A + static_cast<size_t>(p) * rows;
+          double* aq = A + static_cast<size_t>(q) * rows;
+          double xa[VT], ya[VT];
+#pragma unroll
+          for (int t = 0; t < VT; ++t) {
+            const int i = min(gl + t * GW, rows - 1);
+            xa[t] = ap[i];
+            ya[t] = aq[i];
+          }
+          double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+          for (int t = 0; t < VT; ++t)
+            if (gl + t * GW < rows) {
+              a = fma(xa[t], xa[t], a);
+              b = fma(ya[t], ya[t], b);
+              g = fma(xa[t], ya[t], g);
+            }
+          a = group_sum<GW>(a);
+          b = group_sum<GW>(b);
+          g = group_sum<GW>(g);
+          if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+            jacobi_rotation(a, b, g, &cs, &sn);
+#pragma unroll
+            for (int t = 0; t < VT; ++t) {
+              const int i = gl + t * GW;
+              if (i < rows) {
+                ap[i] = cs * xa[t] - sn * ya[t];
+                aq[i] = sn * xa[t] + cs * ya[t];
+              }
+            }
+            if (gl == 0) rotated = 1;
+          }
+        }
+        if (gl == 0) lr[k] = make_double2(cs, sn);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) nsw = sweep + 1;
+    if (!rotated) break;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int j = grp; j < c; j += NG) {
+    const double* aj = A + static_cast<size_t>(j) * rows;
+    double sacc = 0.0;
+    for (int i = gl; i < rows; i += GW) sacc = fma(aj[i], aj[i], sacc);
+    sacc = group_sum<GW>(sacc);
+    if (gl == 0) sigma[j] = sqrt(sacc);
+  }
+  for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
+    const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
+    Ag[i + static_cast<size_t>(j) * lda] = A[e];
+  }
+  __syncthreads();
+  // replay: V = product of the logged rotations, in LDS (c x c)
+  double* V = sm;
+  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += NTH) {
+    const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int total = nsw * (N - 1);  // rounds to replay
+  if (N > 1) {
+    // each group's slots: k = grp, grp + NG, ... (at most two for c <= 138 and NG = 64)
+    double2 nxt0 = (total > 0 && grp < H) ? rot[grp] : make_double2(1.0, 0.0);
+    double2 nxt1 = (total > 0 && grp + NG < H) ? rot[grp + NG] : make_double2(1.0, 0.0);
+    for (int t = 0; t < total; ++t) {
+      const int rd = t % (N - 1);
+      const double2 cur0 = nxt0, cur1 = nxt1;
+      if (t + 1 < total) {
+        const double2* nr = rot + static_cast<size_t>(t + 1) * H;
+        if (grp < H) nxt0 = nr[grp];
+        if (grp + NG < H) nxt1 = nr[grp + NG];
+      }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int k = grp + s2 * NG;
+        const double2 cr = s2 == 0 ? cur0 : cur1;
+        if (k >= H || cr.y == 0.0) continue;
+        int p, q;
+        pair_of(rd, k, &p, &q);
+        double* vp = V + static_cast<size_t>(p) * c;
+        double* vq = V + static_cast<size_t>(q) * c;
+        double xv[VT], yv[VT];
+#pragma unroll
+        for (int u = 0; u < VT; ++u) {
+          const int i = min(gl + u * GW, c - 1);
+          xv[u] = vp[i];
+          yv[u] = vq[i];
+        }
+#pragma unroll
+        for (int u = 0; u < VT; ++u) {
+          const int i = gl + u * GW;
+          if (i < c) {
+            vp[i] = cr.x * xv[u] - cr.y * yv[u];
+            vq[i] = cr.y * xv[u] + cr.x * yv[u];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (long long e = threadIdx.x; e < static_cast<long long>(c) * c; e += NTH) {
+    const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
+    Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+  }
+}
+
 // One-sided cyclic Jacobi (round-robin pair order) for c <= 64 columns of at most
 // GW * RPL rows, A and V staged in LDS.  32 groups of GW lanes, one column pair per
 // group per round; a lane holds its RPL entries of both columns in registers for the
@@ -2439,6 +2591,20 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     else
       k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
     TTS_LAUNCH_CHECK();
+    return;
+  }
+  // A in LDS with the rotations logged, then V in LDS: up to 138 columns
+  if (shm > 150 * 1024 && c <= 138 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
+    constexpr int kMaxSweeps = 80;
+    const int N = c + (c & 1);
+    const size_t lbytes = sizeof(double2) * static_cast<size_t>(kMaxSweeps) * (N - 1) * (N / 2);
+    void* lg = cached_alloc(lbytes, s);
+    if (!lg) fail(TT_ERR_NOMEM, "device allocation failed");
+    const size_t lshm = sizeof(double) * std::max(static_cast<size_t>(rows) * c, static_cast<size_t>(c) * c);
+    k_jacobi_log<1024, 16, 10><<<1, 1024, lshm, s>>>(A, rows, c, lda, V, ldv, sigma, static_cast<double2*>(lg),
+                                                      kMaxSweeps);
+    TTS_LAUNCH_CHECK();
+    cached_free(lg, lbytes, s);
     return;
   }
   // A in LDS, V in global memory: up to 160 columns
