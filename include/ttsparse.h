@@ -102,7 +102,9 @@ void tt_options_default(tt_options* opt);
  * Decompose the sparse tensor given in COO form.
  *   d     : order, 2 <= d <= TT_MAX_D
  *   dims  : host int64[d], 1 <= n_k <= 2^31-1; the packed coordinate
- *           sum_k ceil(log2 n_k) must not exceed 63 bits (else TT_ERR_TOO_LARGE)
+ *           sum_k ceil(log2 n_k) must not exceed 63 bits, and every level's rows
+ *           g_{k-1} n_k + i_k must stay below 2^31 (beta_{k-1} n_k <= 2^31; both
+ *           else TT_ERR_TOO_LARGE)
  *   nnz   : number of stored entries, 0 <= nnz < 2^31
  *   idx   : device int32[nnz][d], row-major, 0-based (borrowed, not modified)
  *   val   : device double[nnz] (borrowed, not modified).  Explicit zeros (+-0) are

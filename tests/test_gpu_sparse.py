@@ -211,3 +211,55 @@ def test_key_bits_argument_errors():
     for kb in (-1, 53):
         with pytest.raises(tts.TTError):
             tts.decompose(gi, gv, (2, 2), 0.1, key_bits=kb)
+
+
+# ---- size limits ----
+
+def _rand_coords(dims, nnz, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = np.stack([rng.integers(0, n, nnz) for n in dims], 1).astype(np.int32)
+    idx = np.unique(idx, axis=0)
+    return idx, rng.standard_normal(len(idx))
+
+
+def test_packed_key_of_63_bits(oracle_mod):
+    """A mode of 2^31 - 1 and 32 modes of 2: the packed coordinate uses all 63 bits."""
+    dims = ((1 << 31) - 1,) + (2,) * 32
+    idx, val = _rand_coords(dims, 3000, 5)
+    check_sparse_parity(oracle_mod, idx, val, dims, "63-bit keys", dense_cores=False)
+
+
+def test_row_range_limit_is_refused():
+    """Rows of a level are g_{k-1} n_k + i_k in 32 bits: with n_2 = 2^31 - 1 and 5000
+    groups at level 1 the range is exceeded, and the call says so."""
+    tts = _tt()
+    dims = ((1 << 31) - 1, (1 << 31) - 1, 2)
+    idx, val = _rand_coords(dims, 5000, 5)
+    gi, gv = _to_gpu(idx, val)
+    with pytest.raises(tts.TTError) as ei:
+        tts.decompose(gi, gv, dims, 0.0, sparse_only=True)
+    assert ei.value.status == "TT_ERR_TOO_LARGE"
+
+
+def test_largest_mode_size(oracle_mod):
+    tts = _tt()
+    dims = ((1 << 31) - 1, 3)
+    idx, val = _rand_coords(dims, 3000, 6)
+    check_sparse_parity(oracle_mod, idx, val, dims, "mode of 2^31-1", dense_cores=False)
+    gi, gv = _to_gpu(idx, val)
+    # the first bond's dense unfolding would have 2^31 - 1 rows: refused, not attempted
+    with pytest.raises(tts.TTError) as ei:
+        tts.decompose(gi, gv, dims, 1e-8)
+    assert ei.value.status == "TT_ERR_TOO_LARGE"
+
+
+def test_63_binary_modes(oracle_mod):
+    """d = 63 modes of size 2 (63 key bits): the sparse stage bit for bit, and the
+    full decomposition against the oracle."""
+    from tests.test_gpu_round import check_round
+
+    dims = (2,) * 63
+    idx, val = _rand_coords(dims, 200, 7)
+    check_sparse_parity(oracle_mod, idx, val, dims, "d=63")
+    tt, _ = check_round(oracle_mod, idx, val, dims, 1e-10, "d=63")
+    assert max(tt.ranks) <= len(val)
