@@ -57,7 +57,8 @@ NUM_CU = 256
 PUBLISHED = {("fdm3d_n40_random", "fasttt"): (438400 / 57.5, "Table 2, FastTT, FDM n=40 random, 57.5 s, 32-core CPU")}
 # Per-launch HBM traffic of profiled kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a plain copy of known size (profiles/traffic_*.txt).  A figure is
-# used only while the source file that holds the kernel is unchanged.
+# used only for the workload it was taken on, and only while the source file that
+# holds the kernel is unchanged.
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -132,8 +133,9 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
     return base, err
 
 
-def _traffic(family):
-    """(bytes per launch, source) from profiles/traffic_<family>.txt if still current, else None."""
+def _traffic(family, workload, method):
+    """(bytes per launch, source) from profiles/traffic_<family>.txt if it was taken on this
+    workload and method and its kernel source is unchanged since, else None."""
     import hashlib
 
     path = os.path.join(PROFILES, f"traffic_{family}.txt")
@@ -148,6 +150,8 @@ def _traffic(family):
     src = fields.get("source")
     if not src or "traffic_bytes_per_launch" not in fields:
         return None
+    if fields.get("workload") != workload or fields.get("method", "cps") != method:
+        return None  # measured on another workload: other launch shapes
     with open(os.path.join(ROOT, src), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
             return None  # the kernel changed since the counters were taken
@@ -312,7 +316,7 @@ def main():
                 peak = FP32_PEAK_TFLOPS
             else:
                 peak = FP64_PEAK_TFLOPS
-        tr = _traffic(family) if args.precision == "fp64" else None
+        tr = _traffic(family, args.workload, args.method) if args.precision == "fp64" else None
         out["roofline"] = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
                            "traffic": tr[0] if tr else None, "traffic_source": tr[1] if tr else None,
                            "kernel": family, "launches_per_step": k_n / args.steps,
