@@ -51,10 +51,14 @@ FAMILY_BOUND = {
 # also states the fraction of one CU's share of the peak.
 SINGLE_WORKGROUP = {"jacobi", "cholesky"}
 NUM_CU = 256
-# The paper's own end-to-end FastTT rate for a workload run here, derived as nonzeros
-# / reported time (Table 2: FDM n = 40, random coefficients, eps = 1e-14, 438,400
-# nonzeros in 57.5 s on a 32-core x86 server).  Another machine's number: context.
-PUBLISHED = {("fdm3d_n40_random", "fasttt"): (438400 / 57.5, "Table 2, FastTT, FDM n=40 random, 57.5 s, 32-core CPU")}
+# The paper's own end-to-end FastTT rates for workloads run here, derived as nonzeros
+# / reported time (Table 2: FDM matrices, eps = 1e-14, on a 32-core x86 server).
+# Another machine's numbers: context.
+PUBLISHED = {
+    (f"fdm3d_n{n}_{c}", "fasttt"): (nnz / t, f"Table 2, FastTT, FDM n={n} {c}, {t} s, 32-core CPU")
+    for n, c, nnz, t in ((20, "pattern", 53600, 0.788), (30, "pattern", 183600, 2.88), (20, "random", 53600, 1.67),
+                         (30, "random", 183600, 12.4), (40, "random", 438400, 57.5))
+}
 # Per-launch HBM traffic of profiled kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes scaled by a plain copy of known size (profiles/traffic_*.txt).  A figure is
 # used only for the workload it was taken on, and only while the source file that

@@ -236,6 +236,11 @@ WORKLOADS = {
     # with modes of size 1600 (438,400 nnz), eps 1e-14: the largest case of the FDM
     # table, for the fiber-trie variant.
     "fdm3d_n40_random": dict(kind="fdm", n=40, coeff="random", seed=1, eps=1e-14),
+    # the other FDM cases of the same table
+    "fdm3d_n20_pattern": dict(kind="fdm", n=20, coeff="pattern", seed=1, eps=1e-14),
+    "fdm3d_n30_pattern": dict(kind="fdm", n=30, coeff="pattern", seed=1, eps=1e-14),
+    "fdm3d_n20_random": dict(kind="fdm", n=20, coeff="random", seed=1, eps=1e-14),
+    "fdm3d_n30_random": dict(kind="fdm", n=30, coeff="random", seed=1, eps=1e-14),
     # 5-way 200^5 with 10M random nonzeros, N(0,1), eps 1e-2.
     "random5d_n200_nnz10m": dict(kind="random", dims=(200,) * 5, nnz=10_000_000, seed=4, eps=1e-2),
 }
