@@ -424,13 +424,7 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
       TTS_HIP(hipStreamSynchronize(s));
       done = h[0] && h[1] && h[2] && h[3];
     }
-    if (!done) {
-      DBuf<double> Af(al, static_cast<size_t>(m) * r0), th(al, q);
-      copy_matrix(core(k), m, r0, m, Af.get(), m, s);
-      householder_qr(Af.get(), m, r0, m, th.get(), s);
-      householder_form_q(Af.get(), m, q, m, th.get(), reinterpret_cast<double*>(Q.get()), m, s);
-      householder_extract_r(Af.get(), m, r0, m, Rm.get(), q, reinterpret_cast<double*>(Q.get()), m, s);
-    }
+    if (!done) qr_explicit(al, core(k), m, r0, m, reinterpret_cast<double*>(Q.get()), m, Rm.get(), q, s);
     // core k-1 stored as column-major r0 x (r0' n') = spl_2^T; new = R (q x r0) times it
     const int cols = static_cast<int>(r[k - 2]) * static_cast<int>(dims[k - 2]);
     DBuf<char> Cp(al, sizeof(double) * static_cast<size_t>(q) * cols);

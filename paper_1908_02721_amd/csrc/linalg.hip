@@ -1239,8 +1239,7 @@ __global__ __launch_bounds__(NT) void k_weighted_total(const double* __restrict_
 }
 
 // Householder QR, one workgroup, LAPACK geqr2/larfg conventions.
-__global__ __launch_bounds__(BT) void k_householder_qr(double* __restrict__ A, int m, int n, int lda,
-                                                       double* __restrict__ tau) {
+__device__ void householder_qr_body(double* __restrict__ A, int m, int n, int lda, double* __restrict__ tau) {
   __shared__ double red[17];
   __shared__ double sh_tau, sh_beta, sh_scale;
   const int p = min(m, n);
@@ -1284,9 +1283,24 @@ __global__ __launch_bounds__(BT) void k_householder_qr(double* __restrict__ A, i
   }
 }
 
-__global__ __launch_bounds__(BT) void k_householder_form_q(const double* __restrict__ A, int m, int p, int lda,
-                                                           const double* __restrict__ tau, double* __restrict__ Q,
-                                                           int ldq) {
+__global__ __launch_bounds__(BT) void k_householder_qr(double* __restrict__ A, int m, int n, int lda,
+                                                       double* __restrict__ tau) {
+  householder_qr_body(A, m, n, lda, tau);
+}
+
+// Row block i of a tall m x n matrix: rows [i b, i b + m_i), m_i = b except the last
+// block, which takes the remainder (b <= m_i < 2b).
+__device__ __forceinline__ int tsqr_rows(int m, int b, int nblk, int i) { return i + 1 < nblk ? b : m - i * b; }
+
+// Householder QR of every row block, one workgroup per block; tau of block i at tau + i n.
+__global__ __launch_bounds__(BT) void k_householder_qr_blocks(double* __restrict__ A, int m, int n, int lda, int b,
+                                                              int nblk, double* __restrict__ tau) {
+  const int i = blockIdx.x;
+  householder_qr_body(A + static_cast<size_t>(i) * b, tsqr_rows(m, b, nblk, i), n, lda, tau + static_cast<size_t>(i) * n);
+}
+
+__device__ void householder_form_q_body(const double* __restrict__ A, int m, int p, int lda,
+                                        const double* __restrict__ tau, double* __restrict__ Q, int ldq) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (long long e = threadIdx.x; e < static_cast<long long>(m) * p; e += BT) {
     const int i = static_cast<int>(e % m), c = static_cast<int>(e / m);
@@ -1308,6 +1322,58 @@ __global__ __launch_bounds__(BT) void k_householder_form_q(const double* __restr
       }
     }
     __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(BT) void k_householder_form_q(const double* __restrict__ A, int m, int p, int lda,
+                                                           const double* __restrict__ tau, double* __restrict__ Q,
+                                                           int ldq) {
+  householder_form_q_body(A, m, p, lda, tau, Q, ldq);
+}
+
+// Explicit Q (m_i x n) of every row block, one workgroup per block.
+__global__ __launch_bounds__(BT) void k_householder_form_q_blocks(const double* __restrict__ A, int m, int n, int lda,
+                                                                  int b, int nblk, const double* __restrict__ tau,
+                                                                  double* __restrict__ Q, int ldq) {
+  const int i = blockIdx.x;
+  householder_form_q_body(A + static_cast<size_t>(i) * b, tsqr_rows(m, b, nblk, i), n, lda,
+                          tau + static_cast<size_t>(i) * n, Q + static_cast<size_t>(i) * b, ldq);
+}
+
+// S = the blocks' R factors stacked: rows [i n, (i+1) n) of S (ld = nblk n) hold the
+// upper triangle of block i's factored rows.
+__global__ __launch_bounds__(NT) void k_stack_r(const double* __restrict__ A, int n, int lda, int b, int nblk,
+                                                double* __restrict__ S) {
+  const long long e = static_cast<long long>(blockIdx.x) * NT + threadIdx.x;
+  const long long ls = static_cast<long long>(nblk) * n;
+  if (e >= ls * n) return;
+  const int row = static_cast<int>(e % ls), c = static_cast<int>(e / ls);
+  const int i = row / n, r = row - i * n;
+  S[e] = (c >= r) ? A[static_cast<size_t>(i) * b + r + static_cast<size_t>(c) * lda] : 0.0;
+}
+
+// Q = diag(Q_i) Q_S: rows of block i are Q_i (m_i x n, in Qb) times rows [i n, (i+1) n)
+// of Q_S (ld = nblk n).  One thread per output row, 16 output columns per pass.
+__global__ __launch_bounds__(NT) void k_tsqr_combine(const double* __restrict__ Qb, int m, int n, int b, int nblk,
+                                                     const double* __restrict__ QS, double* __restrict__ Q, int ldq) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= m) return;
+  const int i = min(r / b, nblk - 1);
+  const size_t ls = static_cast<size_t>(nblk) * n;
+  const double* qs = QS + static_cast<size_t>(i) * n;
+  for (int c0 = 0; c0 < n; c0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+    for (int t = 0; t < n; ++t) {
+      const double a = Qb[r + static_cast<size_t>(t) * m];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (c0 + u < n) acc[u] = fma(a, qs[t + static_cast<size_t>(c0 + u) * ls], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (c0 + u < n) Q[r + static_cast<size_t>(c0 + u) * ldq] = acc[u];
   }
 }
 
@@ -2548,6 +2614,40 @@ void householder_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s
 void householder_form_q(const double* A, int m, int p, int lda, const double* tau, double* Q, int ldq, hipStream_t s) {
   if (m <= 0 || p <= 0) return;
   k_householder_form_q<<<1, BT, 0, s>>>(A, m, p, lda, tau, Q, ldq);
+  TTS_LAUNCH_CHECK();
+}
+
+void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* Q, int ldq, double* R, int ldr,
+                 hipStream_t s) {
+  const int p = std::min(m, n);
+  if (p <= 0) return;
+  constexpr int kTallRows = 4096;
+  if (m < kTallRows || m < 8 * n) {
+    DBuf<double> Af(al, static_cast<size_t>(m) * n), th(al, p);
+    copy_matrix(G, m, n, ldg, Af.get(), m, s);
+    householder_qr(Af.get(), m, n, m, th.get(), s);
+    householder_form_q(Af.get(), m, p, m, th.get(), Q, ldq, s);
+    householder_extract_r(Af.get(), m, n, m, R, ldr, Q, ldq, s);
+    return;
+  }
+  // tall: blocks of b >= 2n rows (at least 1024), factored in parallel
+  const int b = std::max(1024, 2 * n);
+  const int nblk = m / b;  // the last block takes the remainder
+  const int ls = nblk * n;
+  DBuf<double> Af(al, static_cast<size_t>(m) * n), tb(al, static_cast<size_t>(nblk) * n),
+      Qb(al, static_cast<size_t>(m) * n), S(al, static_cast<size_t>(ls) * n), ts(al, n),
+      QS(al, static_cast<size_t>(ls) * n);
+  copy_matrix(G, m, n, ldg, Af.get(), m, s);
+  k_householder_qr_blocks<<<nblk, BT, 0, s>>>(Af.get(), m, n, m, b, nblk, tb.get());
+  TTS_LAUNCH_CHECK();
+  k_stack_r<<<grid_for(static_cast<size_t>(ls) * n, NT), NT, 0, s>>>(Af.get(), n, m, b, nblk, S.get());
+  TTS_LAUNCH_CHECK();
+  k_householder_form_q_blocks<<<nblk, BT, 0, s>>>(Af.get(), m, n, m, b, nblk, tb.get(), Qb.get(), m);
+  TTS_LAUNCH_CHECK();
+  householder_qr(S.get(), ls, n, ls, ts.get(), s);
+  householder_form_q(S.get(), ls, n, ls, ts.get(), QS.get(), ls, s);
+  householder_extract_r(S.get(), ls, n, ls, R, ldr, QS.get(), ls, s);  // R with diag >= 0, Q_S columns matched
+  k_tsqr_combine<<<grid_for(static_cast<size_t>(m), NT), NT, 0, s>>>(Qb.get(), m, n, b, nblk, QS.get(), Q, ldq);
   TTS_LAUNCH_CHECK();
 }
 

@@ -59,6 +59,12 @@ void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde,
 // Householder QR (LAPACK geqr2 conventions) in one workgroup, in place:
 // R on and above the diagonal, reflectors below, tau[min(m,n)].
 void householder_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s);
+// Economic QR of the column-major m x n matrix G (read only), Householder-based:
+// Q (m x min(m, n)), R (min(m, n) x n) upper with a nonnegative diagonal.  Tall
+// matrices (m >= 4096 and m >= 8 n) are factored by row blocks in parallel and the
+// blocks' R factors once more (tall-skinny QR); others in one workgroup.
+void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* Q, int ldq, double* R, int ldr,
+                 hipStream_t s);
 // Explicit Q (m x p) of the first p reflectors.
 void householder_form_q(const double* A, int m, int p, int lda, const double* tau, double* Q, int ldq, hipStream_t s);
 // R (p x n) from a factored A: upper part, diag made >= 0 (row signs flipped), and the

@@ -157,11 +157,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     TTS_HIP(hipMemcpyAsync(okh, okq.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
     if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
-      DBuf<double> Af(A, static_cast<size_t>(m) * c), th(A, c);
-      copy_matrix(G, m, c, m, Af.get(), m, s);
-      householder_qr(Af.get(), m, c, m, th.get(), s);
-      householder_form_q(Af.get(), m, c, m, th.get(), Qb.get(), m, s);
-      householder_extract_r(Af.get(), m, c, m, R.get(), c, Qb.get(), m, s);
+      qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
       transpose(R.get(), c, c, c, Bt.get(), c, s);
       svd_of_bt();
       TTS_HIP(hipStreamSynchronize(s));
@@ -258,12 +254,8 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   // exact Householder QR of the bond-kb input Xb (rows x cols)
   auto exact_bond = [&](int kb, const DBuf<double>& Xb, int rows, int cols) {
     const int p = std::min(rows, cols);
-    DBuf<double> Af(A, static_cast<size_t>(rows) * cols), th(A, p), Q(A, static_cast<size_t>(rows) * p);
-    copy_matrix(Xb.get(), rows, cols, rows, Af.get(), rows, s);
-    householder_qr(Af.get(), rows, cols, rows, th.get(), s);
-    householder_form_q(Af.get(), rows, p, rows, th.get(), Q.get(), rows, s);
-    DBuf<double> Wn(A, static_cast<size_t>(p) * cols);
-    householder_extract_r(Af.get(), rows, cols, rows, Wn.get(), p, Q.get(), rows, s);
+    DBuf<double> Q(A, static_cast<size_t>(rows) * p), Wn(A, static_cast<size_t>(p) * cols);
+    qr_explicit(A, Xb.get(), rows, cols, rows, Q.get(), rows, Wn.get(), p, s);
     cores[kb - 1].reset(A, sizeof(double) * static_cast<size_t>(rows) * p);
     transpose(Q.get(), rows, p, rows, reinterpret_cast<double*>(cores[kb - 1].get()), p, s);
     W = std::move(Wn);
