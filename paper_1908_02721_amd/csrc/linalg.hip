@@ -2621,8 +2621,9 @@ void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* 
                  hipStream_t s) {
   const int p = std::min(m, n);
   if (p <= 0) return;
-  constexpr int kTallRows = 4096;
-  if (m < kTallRows || m < 8 * n) {
+  // tall: row blocks of b >= 2n rows (at least 256), factored in parallel
+  const int b = std::max(256, 2 * n);
+  if (m < 4 * b) {
     DBuf<double> Af(al, static_cast<size_t>(m) * n), th(al, p);
     copy_matrix(G, m, n, ldg, Af.get(), m, s);
     householder_qr(Af.get(), m, n, m, th.get(), s);
@@ -2630,13 +2631,10 @@ void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* 
     householder_extract_r(Af.get(), m, n, m, R, ldr, Q, ldq, s);
     return;
   }
-  // tall: blocks of b >= 2n rows (at least 1024), factored in parallel
-  const int b = std::max(1024, 2 * n);
   const int nblk = m / b;  // the last block takes the remainder
   const int ls = nblk * n;
   DBuf<double> Af(al, static_cast<size_t>(m) * n), tb(al, static_cast<size_t>(nblk) * n),
-      Qb(al, static_cast<size_t>(m) * n), S(al, static_cast<size_t>(ls) * n), ts(al, n),
-      QS(al, static_cast<size_t>(ls) * n);
+      Qb(al, static_cast<size_t>(m) * n), S(al, static_cast<size_t>(ls) * n), QS(al, static_cast<size_t>(ls) * n);
   copy_matrix(G, m, n, ldg, Af.get(), m, s);
   k_householder_qr_blocks<<<nblk, BT, 0, s>>>(Af.get(), m, n, m, b, nblk, tb.get());
   TTS_LAUNCH_CHECK();
@@ -2644,9 +2642,8 @@ void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* 
   TTS_LAUNCH_CHECK();
   k_householder_form_q_blocks<<<nblk, BT, 0, s>>>(Af.get(), m, n, m, b, nblk, tb.get(), Qb.get(), m);
   TTS_LAUNCH_CHECK();
-  householder_qr(S.get(), ls, n, ls, ts.get(), s);
-  householder_form_q(S.get(), ls, n, ls, ts.get(), QS.get(), ls, s);
-  householder_extract_r(S.get(), ls, n, ls, R, ldr, QS.get(), ls, s);  // R with diag >= 0, Q_S columns matched
+  // the stack (nblk n rows) the same way: blocks again while it is tall, R with diag >= 0
+  qr_explicit(al, S.get(), ls, n, ls, QS.get(), ls, R, ldr, s);
   k_tsqr_combine<<<grid_for(static_cast<size_t>(m), NT), NT, 0, s>>>(Qb.get(), m, n, b, nblk, QS.get(), Q, ldq);
   TTS_LAUNCH_CHECK();
 }

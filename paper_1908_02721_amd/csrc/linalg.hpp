@@ -61,8 +61,9 @@ void weighted_sumsq(Allocator* al, const double* E, int rows, int cols, int lde,
 void householder_qr(double* A, int m, int n, int lda, double* tau, hipStream_t s);
 // Economic QR of the column-major m x n matrix G (read only), Householder-based:
 // Q (m x min(m, n)), R (min(m, n) x n) upper with a nonnegative diagonal.  Tall
-// matrices (m >= 4096 and m >= 8 n) are factored by row blocks in parallel and the
-// blocks' R factors once more (tall-skinny QR); others in one workgroup.
+// matrices (m >= 4 b, b = max(256, 2 n)) are factored by row blocks of b rows in
+// parallel and the blocks' stacked R factors the same way (tall-skinny QR); others
+// in one workgroup.
 void qr_explicit(Allocator* al, const double* G, int m, int n, int ldg, double* Q, int ldq, double* R, int ldr,
                  hipStream_t s);
 // Explicit Q (m x p) of the first p reflectors.
