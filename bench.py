@@ -224,7 +224,7 @@ def main():
             th.start()
         try:
             if args.method == "fasttt":
-                tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p)
+                tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p, precision=args.precision)
             else:
                 tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
                                    key_bits=args.key_bits)

@@ -136,8 +136,10 @@ tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
  *   other arguments, inputs, errors and the result handle as tt_sparse_decompose.
  *   The exact ranks r~ of Algorithm 4 are the result's sparse ranks
  *   (tt_get_sparse_ranks: betas), the ranks after the QR sweep its qr_ranks.
- *   Options: FP64 only; max_rank, sparse_only (exact cores), device_mem_budget,
- *   the allocator hooks and dynamic_delta apply (Algorithm 8 as stated: budgets
+ *   Options: precision (as tt_sparse_decompose: the contractions with the cores
+ *   in FP32 or BF16 on the matrix cores, Grams, R factors and the SVD in FP64,
+ *   cores handed out in binary32), max_rank, sparse_only (exact cores, FP64),
+ *   device_mem_budget, the allocator hooks and dynamic_delta apply (Algorithm 8 as stated: budgets
  *   sqrt(d-p)/(sqrt(d-p)+sqrt(p-1)) eps ||A||_F right of p and
  *   sqrt(p-1)/(...) eps ||A||_F left of p, bond k of the right sweep gets
  *   delta_right/sqrt(d-k), bond k-1 of the left sweep delta_left/sqrt(k-1), each

@@ -223,7 +223,7 @@ def _coo_args(idx, val, dims):
 
 def fasttt_decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, p: int = 0, max_rank: int = 0,
                      sparse_only: bool = False, device_mem_budget: int = 0, stream=None,
-                     dynamic_delta: bool = False) -> TT:
+                     dynamic_delta: bool = False, precision: str = "fp64") -> TT:
     """The paper's fiber-trie FastTT (Algorithm 7): exact TT of the nonzero p-fibers
     reduced by Algorithm 4, rounded from core p outwards (Algorithm 6).
 
@@ -239,6 +239,7 @@ def fasttt_decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, p: 
     opt.sparse_only = int(bool(sparse_only))
     opt.device_mem_budget = int(device_mem_budget)
     opt.dynamic_delta = int(bool(dynamic_delta))
+    opt.precision = _lib.PRECISION[precision]
     h = ctypes.c_void_p()
     _lib.check(L.tt_fasttt_decompose(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
                                      float(eps), int(p), ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h)))

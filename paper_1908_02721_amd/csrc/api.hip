@@ -586,7 +586,7 @@ tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
   else if (nnz > 0 && (!idx || !val)) why = "idx/val is NULL";
   else if (!(eps >= 0.0 && eps < 1.0)) why = "eps must satisfy 0 <= eps < 1";
   else if (p < 0 || p > d) why = "p must be in [0, d] (0: chosen by Algorithm 9)";
-  else if (o.precision != TT_FP64) why = "the fiber-trie variant computes in FP64 only";
+  else if (o.precision < TT_FP64 || o.precision > TT_BF16_FP32ACC) why = "unknown precision";
   else if (o.max_rank < 0) why = "max_rank must be >= 0";
   else if (o.key_bits || o.keep_intermediates)
     why = "key_bits and keep_intermediates apply to tt_sparse_decompose only";
@@ -631,22 +631,24 @@ tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     if (o.sparse_only) {
       R->cores = std::move(ex.cores);
       R->ranks = R->betas;
+      R->dtype = TT_DTYPE_F64;
       TTS_HIP(hipEventRecord(ev.e[4], s));
       TTS_HIP(hipEventRecord(ev.e[5], s));
     } else {
       RoundOutput ro;
       std::vector<int64_t> r = ex.ranks;
-      ftt_round(&R->al, R->dims, p, eps, ex.norm, o.max_rank, o.dynamic_delta != 0, ex.cores, r, ro, ev.e[4], s);
+      ftt_round(&R->al, R->dims, p, eps, ex.norm, o.max_rank, o.dynamic_delta != 0, o.precision, ex.cores, r, ro,
+                ev.e[4], s);
       R->qr_ranks = ro.qr_ranks;
       R->ranks = ro.ranks;
       R->cores = std::move(ex.cores);
       R->sigma = std::move(ro.sigma);
       R->tail = std::move(ro.tail);
       R->bond_delta = std::move(ro.bond_delta);
+      R->dtype = ro.dtype;
       R->rounded = 1;
       TTS_HIP(hipEventRecord(ev.e[5], s));
     }
-    R->dtype = TT_DTYPE_F64;
     TTS_HIP(hipEventRecord(ev.e[6], s));
     TTS_HIP(hipEventSynchronize(ev.e[6]));
     for (int i = 0; i < TT_NUM_STAGES - 1; ++i) {

@@ -367,8 +367,8 @@ int ftt_select_p(Allocator* al, const int32_t* idx, const double* val, uint32_t 
 }
 
 void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double eps, double norm, int max_rank,
-               bool dynamic, std::vector<DBuf<char>>& cores, std::vector<int64_t>& r, RoundOutput& out, hipEvent_t mid,
-               hipStream_t s) {
+               bool dynamic, int prec, std::vector<DBuf<char>>& cores, std::vector<int64_t>& r, RoundOutput& out,
+               hipEvent_t mid, hipStream_t s) {
   const int d = static_cast<int>(dims.size());
   const double den = std::sqrt(static_cast<double>(p - 1)) + std::sqrt(static_cast<double>(d - p));
   const double delta = eps * norm / den;
@@ -392,7 +392,7 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
     const double dk = dynamic ? std::sqrt(right2 / static_cast<double>(d - k)) : delta;
     out.bond_delta[k - 1] = dk;
     SvdPart sv;
-    truncated_svd(al, TT_FP64, G.get(), m, r1, dk * dk, max_rank, sv, s);
+    truncated_svd(al, prec, G.get(), m, r1, dk * dk, max_rank, sv, s);
     const int rk = sv.rank;
     out.sigma[k - 1] = std::move(sv.sigma);
     out.tail[k - 1] = sv.tail;
@@ -402,7 +402,7 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
     // core k+1 stored as column-major (n' r1') x r1 = spl_1^T; times VS (r1 x rk)
     const int m2 = static_cast<int>(dims[k]) * static_cast<int>(r[k + 1]);
     DBuf<char> Cn(al, sizeof(double) * static_cast<size_t>(m2) * rk);
-    gemm(al, false, false, m2, rk, r1, 1.0, core(k + 1), m2, sv.VS.get(), r1, 0.0,
+    gemm_prec(al, prec, false, false, m2, rk, r1, 1.0, core(k + 1), m2, sv.VS.get(), r1, 0.0,
          reinterpret_cast<double*>(Cn.get()), m2, s);
     cores[k - 1] = std::move(Ck);
     cores[k] = std::move(Cn);
@@ -428,7 +428,7 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
     // core k-1 stored as column-major r0 x (r0' n') = spl_2^T; new = R (q x r0) times it
     const int cols = static_cast<int>(r[k - 2]) * static_cast<int>(dims[k - 2]);
     DBuf<char> Cp(al, sizeof(double) * static_cast<size_t>(q) * cols);
-    gemm(al, false, false, q, cols, r0, 1.0, Rm.get(), q, core(k - 1), r0, 0.0, reinterpret_cast<double*>(Cp.get()),
+    gemm_prec(al, prec, false, false, q, cols, r0, 1.0, Rm.get(), q, core(k - 1), r0, 0.0, reinterpret_cast<double*>(Cp.get()),
          q, s);
     cores[k - 1] = std::move(Q);  // column-major m x q = [q][n][r1]
     cores[k - 2] = std::move(Cp);
@@ -444,14 +444,14 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
     const double dk = dynamic ? std::sqrt(left2 / static_cast<double>(k - 1)) : delta;
     out.bond_delta[k - 2] = dk;
     SvdPart sv;
-    truncated_svd(al, TT_FP64, core(k), m, r0, dk * dk, max_rank, sv, s);
+    truncated_svd(al, prec, core(k), m, r0, dk * dk, max_rank, sv, s);
     const int rk = sv.rank;
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;
     left2 = std::max(0.0, left2 - sv.tail);
     const int rows2 = static_cast<int>(r[k - 2]) * static_cast<int>(dims[k - 2]);
     DBuf<char> Pn(al, sizeof(double) * static_cast<size_t>(rows2) * rk);
-    gemm(al, true, false, rk, rows2, r0, 1.0, sv.VS.get(), r0, core(k - 1), r0, 0.0,
+    gemm_prec(al, prec, true, false, rk, rows2, r0, 1.0, sv.VS.get(), r0, core(k - 1), r0, 0.0,
          reinterpret_cast<double*>(Pn.get()), rk, s);
     cores[k - 1] = std::move(sv.U);
     cores[k - 2] = std::move(Pn);
@@ -459,6 +459,15 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
   }
   out.ranks = r;
   out.dtype = TT_DTYPE_F64;
+  if (prec != TT_FP64) {  // reduced-precision results are handed out in binary32
+    for (int k = 0; k < d; ++k) {
+      const size_t ne = static_cast<size_t>(r[k]) * dims[k] * r[k + 1];
+      DBuf<char> c32(al, sizeof(float) * ne);
+      to_f32(reinterpret_cast<const double*>(cores[k].get()), ne, reinterpret_cast<float*>(c32.get()), s);
+      cores[k] = std::move(c32);
+    }
+    out.dtype = TT_DTYPE_F32;
+  }
 }
 
 }  // namespace tts

@@ -32,9 +32,12 @@ int ftt_select_p(Allocator* al, const int32_t* idx, const double* val, uint32_t 
 
 // Algorithm 6 on the exact cores: SVD sweep from core p to the right, QR sweep back,
 // SVD sweep from core p to the left, delta = eps ||A|| / (sqrt(p-1) + sqrt(d-p));
-// with dynamic, the thresholds of Algorithm 8.
+// with dynamic, the thresholds of Algorithm 8.  prec (tt_precision): the contractions
+// with the cores (merges, U = Q U_R) in that precision on the matrix cores; Grams,
+// R factors, triangular solves and the SVD stay in FP64; reduced-precision results
+// are handed out in binary32.
 void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double eps, double norm, int max_rank,
-               bool dynamic, std::vector<DBuf<char>>& cores, std::vector<int64_t>& ranks, RoundOutput& out,
+               bool dynamic, int prec, std::vector<DBuf<char>>& cores, std::vector<int64_t>& ranks, RoundOutput& out,
                hipEvent_t mid, hipStream_t s);
 
 }  // namespace tts

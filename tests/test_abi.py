@@ -131,7 +131,7 @@ def test_fasttt_host_argument_errors(lib):
 
     assert call(3, [4, 4, 4], 5, -1) == 1
     assert call(3, [4, 4, 4], 5, 4) == 1
-    assert call(3, [4, 4, 4], 5, 2, {"precision": 1}) == 1
+    assert call(3, [4, 4, 4], 5, 2, {"precision": 7}) == 1
     assert call(3, [4, 4, 4], 5, 2, {"key_bits": 30}) == 1
     assert call(3, [4, 4, 4], 5, 2, {"keep_intermediates": 1}) == 1
     assert call(3, [4, 4, 4], 5, 2, eps=1.0) == 1

@@ -95,3 +95,25 @@ def test_fp64_unchanged_by_mode_switches(oracle_mod):
     assert tt.cores[0].dtype == torch.float64
     diff = oracle_mod.tt_diff_norm([c.cpu().numpy() for c in tt.cores], res.cores)
     assert diff <= 1e-12 * res.norm
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fasttt_mixed_precision(oracle_mod, precision):
+    """The fiber-trie variant's rounding in the precision form: FDM n = 20 with random
+    coefficients (p = 2) and a tiny random tensor at every p, against the FP64 oracle."""
+    import paper_1908_02721_amd as tts
+    from oracle import ftt as oftt
+
+    cases = [(synth.fdm3d_mpo(20, "random", seed=1), 1e-14, [2])]
+    cases.append((synth.random_sparse((4, 3, 5, 2), 40, 1), 0.1, [1, 2, 3, 4]))
+    for (idx, val, dims), eps, ps in cases:
+        gi, gv = _gpu(idx, val)
+        for p in ps:
+            res = oftt.decompose(idx, val, dims, eps, p=p)
+            tt = tts.fasttt_decompose(gi, gv, dims, eps, p=p, precision=precision)
+            assert all(c.dtype == torch.float32 for c in tt.cores)
+            c64 = [np.ascontiguousarray(c.double().cpu().numpy()) for c in tt.cores]
+            err = oracle_mod.tt_diff_norm(c64, [np.ascontiguousarray(c) for c in res.cores]) / res.norm
+            print(f"[mixed] fasttt {tuple(dims)} p={p} {precision}: ranks {tt.ranks} (fp64 oracle {res.ranks}); "
+                  f"||B - B_oracle|| / ||A|| = {err:.3e}", flush=True)
+            assert np.isfinite(err) and err <= GATE[precision] + eps
