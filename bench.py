@@ -169,11 +169,16 @@ def calibrate_copy(mib):
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
+    b.copy_(a)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(5):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
     print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
-                      "copies": 5}), flush=True)
+                      "copies": 6, "ms_per_copy": ms, "copy_GBps": 2 * n * 8 / (ms / 1000.0) / 1e9}), flush=True)
 
 
 def main():
