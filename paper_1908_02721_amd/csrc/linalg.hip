@@ -1771,6 +1771,144 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
   }
 }
 
+// One-sided Jacobi with A and V held in registers, for c <= 16 VT columns of at most
+// 16 VT rows.  Group k of 16 lanes holds two columns of A with the matching columns of
+// V (lane l: entries l, l + 16, ...) and rotates them as one pair per step.  The pairs
+// follow the odd-even ordering of positions 0..N-1, N = c + (c & 1): even steps pair
+// (2k, 2k+1), odd steps (2k+1, 2k+2) with positions N-1 and 0 left alone, and the two
+// columns of a pair trade positions, so that N steps meet every pair of columns once.
+// Group k holds positions (2k, 2k+1) before an even step and (2k+1, 2k+2 mod N)
+// before an odd one; between steps each group hands one column (A, V and its index)
+// to a neighbour through LDS, half the LDS traffic of a round that loads and stores
+// both columns, and V needs no second pass.  Rotation rule and stopping test as in
+// k_jacobi; column j of A and V goes back to column j.
+template <int VT>
+__global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int rows, int c, int lda,
+                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
+                                                   int max_sweeps) {
+  constexpr int GW = 16;
+  constexpr int SL = 2 * VT * GW;   // doubles per slot: an A column, then its V column
+  extern __shared__ double slot[];  // [H][SL]
+  __shared__ int sid[64];
+  __shared__ int rotated;
+  const int N = c + (c & 1), H = N / 2;
+  const int k = threadIdx.x / GW, gl = threadIdx.x % GW;
+  const bool act = k < H;  // uniform within a group
+  const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
+  double x[VT], y[VT], vx[VT], vy[VT];
+  int ix = 2 * k, iy = 2 * k + 1;  // column held at the first and second position
+#pragma unroll
+  for (int t = 0; t < VT; ++t) {
+    const int i = gl + t * GW;
+    x[t] = (act && i < rows && ix < c) ? Ag[i + static_cast<size_t>(ix) * lda] : 0.0;
+    y[t] = (act && i < rows && iy < c) ? Ag[i + static_cast<size_t>(iy) * lda] : 0.0;
+    vx[t] = (ix < c && i == ix) ? 1.0 : 0.0;  // the padding column (index c) stays zero
+    vy[t] = (iy < c && i == iy) ? 1.0 : 0.0;
+  }
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int st = 0; st < N; ++st) {
+      const bool odd = st & 1;
+      const bool idle = odd && k == H - 1;
+      if (act && !idle) {
+        double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {  // entries past rows are zero
+          a = fma(x[t], x[t], a);
+          b = fma(y[t], y[t], b);
+          g = fma(x[t], y[t], g);
+        }
+        group_sum3<GW>(a, b, g);
+        if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+          double cs, sn;
+          jacobi_rotation(a, b, g, &cs, &sn);
+#pragma unroll
+          for (int t = 0; t < VT; ++t) {
+            const double xa = x[t], ya = y[t], xv = vx[t], yv = vy[t];
+            x[t] = cs * xa - sn * ya;
+            y[t] = sn * xa + cs * ya;
+            vx[t] = cs * xv - sn * yv;
+            vy[t] = sn * xv + cs * yv;
+          }
+          if (gl == 0) rotated = 1;
+        }
+      }
+      // after an even step position 2k holds y and 2k+1 holds x: y goes to group k-1,
+      // the column at 2k+2 comes from group k+1.  After an odd step position 2k+2
+      // holds x (y for the idle pair, which did not trade): it goes to group k+1, the
+      // column at 2k comes from group k-1.
+      if (idle) {
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {
+          const double ta = x[t], tv = vx[t];
+          x[t] = y[t];
+          vx[t] = vy[t];
+          y[t] = ta;
+          vy[t] = tv;
+        }
+        const int ti = ix;
+        ix = iy;
+        iy = ti;
+      }
+      if (act) {
+        double* my = slot + static_cast<size_t>(k) * SL;
+#pragma unroll
+        for (int t = 0; t < VT; ++t) {
+          my[t * GW + gl] = odd ? x[t] : y[t];
+          my[(VT + t) * GW + gl] = odd ? vx[t] : vy[t];
+        }
+        if (gl == 0) sid[k] = odd ? ix : iy;
+      }
+      __syncthreads();
+      if (act) {
+        const int nb = odd ? (k == 0 ? H - 1 : k - 1) : (k == H - 1 ? 0 : k + 1);
+        const double* in = slot + static_cast<size_t>(nb) * SL;
+        if (odd) {
+#pragma unroll
+          for (int t = 0; t < VT; ++t) {
+            x[t] = in[t * GW + gl];
+            vx[t] = in[(VT + t) * GW + gl];
+          }
+          ix = sid[nb];
+        } else {
+#pragma unroll
+          for (int t = 0; t < VT; ++t) {
+            y[t] = in[t * GW + gl];
+            vy[t] = in[(VT + t) * GW + gl];
+          }
+          iy = sid[nb];
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  if (act) {
+    double sa = 0.0, sb = 0.0, dummy = 0.0;
+#pragma unroll
+    for (int t = 0; t < VT; ++t) {
+      sa = fma(x[t], x[t], sa);
+      sb = fma(y[t], y[t], sb);
+    }
+    group_sum3<GW>(sa, sb, dummy);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = h == 0 ? ix : iy;
+      if (j >= c) continue;  // the padding column
+      if (gl == 0) sigma[j] = sqrt(h == 0 ? sa : sb);
+#pragma unroll
+      for (int t = 0; t < VT; ++t) {
+        const int i = gl + t * GW;
+        if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = h == 0 ? x[t] : y[t];
+        if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = h == 0 ? vx[t] : vy[t];
+      }
+    }
+  }
+}
+
 // One-sided cyclic Jacobi (round-robin pair order) for c <= 64 columns of at most
 // GW * RPL rows, A and V staged in LDS.  32 groups of GW lanes, one column pair per
 // group per round; a lane holds its RPL entries of both columns in registers for the
@@ -2687,6 +2825,14 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
       k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
     else
       k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+    TTS_LAUNCH_CHECK();
+    return;
+  }
+  // A and V in registers: 64 < c <= 128 columns of at most 128 rows
+  if (c > 64 && c <= 128 && rows <= 128) {
+    const int H = (c + 1) / 2;
+    k_jacobi_oe<8><<<1, 1024, sizeof(double) * 2 * 8 * 16 * static_cast<size_t>(H), s>>>(A, rows, c, lda, V, ldv,
+                                                                                         sigma, 80);
     TTS_LAUNCH_CHECK();
     return;
   }

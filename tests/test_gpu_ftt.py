@@ -130,6 +130,18 @@ def test_round_fdm_table2_final_ranks(oracle_mod):
         assert tt.ranks[1:3] == c["final_ranks"]
 
 
+@pytest.mark.parametrize("c", [65, 66, 97, 117, 127, 128])
+@pytest.mark.parametrize("eps", [1e-14, 0.3])
+def test_round_bond_widths_65_to_128(oracle_mod, c, eps):
+    """Bonds of 65..128 columns (odd and even): the SVD of every bond is the
+    register-resident Jacobi of that width, with and without truncation."""
+    idx, val, dims = synth.random_sparse((c, 3, c), int(1.5 * c * c), 40 + c)
+    tt, res = check_round(oracle_mod, idx, val, dims, eps, 2, f"bond width {c}")
+    assert tt.betas == [1, c, c, 1]
+    if eps < 1e-10:
+        assert tt.ranks == [1, c, c, 1]
+
+
 @pytest.mark.timeout(400)
 def test_round_fdm_n40_random(oracle_mod):
     idx, val, dims = synth.fdm3d_mpo(40, "random", seed=1)
