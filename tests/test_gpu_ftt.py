@@ -142,6 +142,16 @@ def test_round_bond_widths_65_to_128(oracle_mod, c, eps):
         assert tt.ranks == [1, c, c, 1]
 
 
+@pytest.mark.parametrize("dims,eps", [((120, 2, 40), 0.2), ((124, 2, 60), 0.4)])
+def test_round_left_svd_wide_transpose(oracle_mod, dims, eps):
+    """After the right sweep truncates bond 2, the left SVD's matrix has fewer rows
+    (n_2 r_2 = 78, 106) than columns (120, 124): the Jacobi runs on its transpose,
+    with more rows than columns, in the register-resident kernel."""
+    idx, val, dims = synth.random_sparse(dims, int(0.6 * dims[0] * dims[1] * dims[2]), 7)
+    tt, res = check_round(oracle_mod, idx, val, dims, eps, 2, "left SVD on a wide matrix")
+    assert 64 < 2 * tt.ranks[2] < dims[0]
+
+
 @pytest.mark.timeout(400)
 def test_round_fdm_n40_random(oracle_mod):
     idx, val, dims = synth.fdm3d_mpo(40, "random", seed=1)
