@@ -30,10 +30,14 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k, double alpha,
                                              const double* __restrict__ A, int lda, const double* __restrict__ B,
                                              int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
-                                             double* __restrict__ part, int sym) {
+                                             double* __restrict__ part, int sym, int lin_tn) {
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
   int bi = blockIdx.x, bj = blockIdx.y;
+  if (lin_tn > 0) {  // blockIdx.x = bi * lin_tn + bj: a row block's column tiles run together
+    bi = blockIdx.x / lin_tn;
+    bj = blockIdx.x - bi * lin_tn;
+  }
   if (sym) {  // blockIdx.x enumerates the tiles bi <= bj
     int rem = blockIdx.x;
     bj = 0;
@@ -155,11 +159,15 @@ template <int BF>
 __global__ __launch_bounds__(NT) void k_gemm_lp(int ta, int tb, int m, int n, int k, double alpha,
                                                 const double* __restrict__ A, int lda, const double* __restrict__ B,
                                                 int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
-                                                double* __restrict__ part, int sym) {
+                                                double* __restrict__ part, int sym, int lin_tn) {
   constexpr int LK = 32;
   __shared__ float As[LK][GT + 1];
   __shared__ float Bs[LK][GT + 1];
   int bi = blockIdx.x, bj = blockIdx.y;
+  if (lin_tn > 0) {
+    bi = blockIdx.x / lin_tn;
+    bj = blockIdx.x - bi * lin_tn;
+  }
   if (sym) {
     int rem = blockIdx.x;
     bj = 0;
@@ -2565,7 +2573,9 @@ void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, d
   const int tm = (m + GT - 1) / GT, tn = (n + GT - 1) / GT;
   const int tiles = sym ? tm * (tm + 1) / 2 : tm * tn;
   int ns = 1;
-  if (tiles < 256 && k > 128) ns = std::min({(k + 127) / 128, std::max(1, 512 / tiles), 64});
+  // split K until about 1024 workgroups (a few per CU, so that the k-stage latency
+  // of one overlaps another's) with at least 128 rows of K each
+  if (tiles < 256 && k > 128) ns = std::min({(k + 127) / 128, std::max(1, 1024 / tiles), 256});
   int kchunk = (k + ns - 1) / ns;
   kchunk = ((kchunk + kstep - 1) / kstep) * kstep;
   if (kchunk == 0) kchunk = kstep;
@@ -2573,17 +2583,20 @@ void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, d
   KTimer kt(prec == TT_FP64 ? "gemm" : "gemm_lp", s,
             8.0 * (static_cast<double>(m) * k + static_cast<double>(k) * n + static_cast<double>(m) * n),
             2.0 * static_cast<double>(m) * n * k);
-  const dim3 grid = sym ? dim3(tiles, 1, ns) : dim3(tm, tn, ns);
+  // a few column tiles: linear tile order with the column index fastest, so that the
+  // tiles sharing a block of rows of op(A) run together and it is read from HBM once
+  const int lin_tn = (!sym && tn > 1 && tn <= 8 && static_cast<int64_t>(tm) * tn < (int64_t(1) << 31)) ? tn : 0;
+  const dim3 grid = sym ? dim3(tiles, 1, ns) : lin_tn ? dim3(tm * tn, 1, ns) : dim3(tm, tn, ns);
   DBuf<double> part;
   if (ns > 1) part.reset(al, static_cast<size_t>(ns) * m * n);
   const int kc = (ns == 1) ? std::max(kchunk, k) : kchunk;
   double* pp = (ns == 1) ? nullptr : part.get();
   if (prec == TT_FP64)
-    k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
+    k_gemm<<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym, lin_tn);
   else if (prec == TT_FP32)
-    k_gemm_lp<0><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
+    k_gemm_lp<0><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym, lin_tn);
   else
-    k_gemm_lp<1><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym);
+    k_gemm_lp<1><<<grid, NT, 0, s>>>(ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, kc, pp, sym, lin_tn);
   TTS_LAUNCH_CHECK();
   if (ns > 1) {
     const size_t mn = static_cast<size_t>(m) * n;
