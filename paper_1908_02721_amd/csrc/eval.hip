@@ -861,6 +861,33 @@ __global__ __launch_bounds__(NT) void k_slice_transpose(const T* __restrict__ G,
   GT[(static_cast<int64_t>(i) * r1 + b) * r0 + a] = G[e];
 }
 
+// The same transpose through 32 x 32 LDS tiles of one slice i: the tile of G[a][i][b]
+// is read along b and written along a, so both sides are coalesced.  blockIdx.x =
+// (i * ta + ta_index) * tb + tb_index with ta = ceil(r0 / 32), tb = ceil(r1 / 32).
+template <typename T>
+__global__ __launch_bounds__(256) void k_slice_transpose_tiled(const T* __restrict__ G, int r0, int nk, int r1,
+                                                               int ta, int tb, T* __restrict__ GT) {
+  __shared__ T tile[32][33];
+  const int64_t blk = blockIdx.x;
+  const int jb = static_cast<int>(blk % tb);
+  const int64_t q = blk / tb;
+  const int ja = static_cast<int>(q % ta);
+  const int i = static_cast<int>(q / ta);
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8 threads
+  const int a0 = ja * 32, b0 = jb * 32;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int a = a0 + ty + 8 * u, b = b0 + tx;
+    if (a < r0 && b < r1) tile[ty + 8 * u][tx] = G[(static_cast<int64_t>(a) * nk + i) * r1 + b];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int b = b0 + ty + 8 * u, a = a0 + tx;
+    if (a < r0 && b < r1) GT[(static_cast<int64_t>(i) * r1 + b) * r0 + a] = tile[tx][ty + 8 * u];
+  }
+}
+
 template <typename T>
 __global__ void k_one(T* p) {
   *p = T(1);
@@ -1231,9 +1258,16 @@ void trie_backward(const EvalDesc& ed, const Trie& tr, const std::vector<T*>& Lv
     k_tri_child_ranges<<<grid_for(Pc, NT), NT, 0, s>>>(tr.parent[t + 1], Pc, P, cbeg[t]);
     TTS_LAUNCH_CHECK();
     T* GT = mem.get<T>(static_cast<size_t>(r0) * nk * r1);
-    k_slice_transpose<T><<<grid_for(static_cast<size_t>(r0) * nk * r1, NT), NT, 0, s>>>(
-        static_cast<const T*>(ed.core[t]), r0, nk, r1, GT);
-    TTS_LAUNCH_CHECK();
+    {
+      const int ta = (r0 + 31) / 32, tb = (r1 + 31) / 32;
+      if (r0 >= 16 && static_cast<int64_t>(nk) * ta * tb < (int64_t(1) << 31))
+        k_slice_transpose_tiled<T><<<static_cast<unsigned>(static_cast<int64_t>(nk) * ta * tb), 256, 0, s>>>(
+            static_cast<const T*>(ed.core[t]), r0, nk, r1, ta, tb, GT);
+      else
+        k_slice_transpose<T><<<grid_for(static_cast<size_t>(r0) * nk * r1, NT), NT, 0, s>>>(
+            static_cast<const T*>(ed.core[t]), r0, nk, r1, GT);
+      TTS_LAUNCH_CHECK();
+    }
     Uv[t] = mem.get<T>(static_cast<size_t>(P) * r0);
     KTimer kt("eval_up", s, static_cast<double>(Pc) * (r1 + 8) * sizeof(T) + static_cast<double>(P) * r0 * sizeof(T),
               2.0 * static_cast<double>(Pc) * r0 * r1);
