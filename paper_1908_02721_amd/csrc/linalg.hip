@@ -27,7 +27,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // Operand tiles go through LDS 16 k-steps at a time.  sym (C = A^T A): only tiles on
 // or above the diagonal are computed, each written to both halves.  With `part` set,
 // raw tile sums go to part[z] for a fixed-order split-K reduction.
-__global__ __launch_bounds__(NT) void k_gemm(int ta, int tb, int m, int n, int k, double alpha,
+__global__ __launch_bounds__(NT, 4) void k_gemm(int ta, int tb, int m, int n, int k, double alpha,
                                              const double* __restrict__ A, int lda, const double* __restrict__ B,
                                              int ldb, double beta, double* __restrict__ C, int ldc, int kchunk,
                                              double* __restrict__ part, int sym, int lin_tn) {
