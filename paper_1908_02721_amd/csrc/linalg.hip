@@ -867,29 +867,32 @@ __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ 
   U[t + static_cast<size_t>(s) * r] = (t <= s) ? L[piv[s] + static_cast<size_t>(t) * n] : 0.0;
 }
 
-// Blocked Cholesky of r <= 64 (upper factor) by one 256-thread workgroup; the matrix
-// is padded to 64 x 64 with a unit diagonal and kept row-major in LDS.  For each of the
-// four 16-wide block columns J: wave 0 factors the diagonal block (right-looking,
+// Blocked Cholesky of r <= R (R = 64 or 128, upper factor) by one 256-thread
+// workgroup; the matrix is padded to R x R with a unit diagonal and kept row-major in
+// LDS.  For each of the R / 16 block columns J: wave 0 factors the diagonal block (right-looking,
 // wave-local synchronisation only), one lane per column solves the block row to its
 // right (U_JJ^T X = A_JK), and the trailing upper blocks are updated on the matrix
 // cores (A_KL -= U_JK^T U_JL, v_mfma_f64_16x16x4).  Failure rules as in
-// k_cholesky_block: a non-positive pivot, or max/min of the diagonal above max_ratio.
+// k_cholesky_upper: a non-positive pivot, or max/min of the diagonal above max_ratio.
+template <int R>
 __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, int r, int lda, double max_ratio,
                                                        int32_t* __restrict__ ok) {
-  __shared__ double a[64][65];
-  __shared__ double rdiag[64];  // reciprocals of the diagonal of the factor
+  constexpr int NB = R / 16;        // block columns
+  constexpr int PT = R * R / 256;   // entries per thread
+  __shared__ double a[R][R + 1];
+  __shared__ double rdiag[R];  // reciprocals of the diagonal of the factor
   __shared__ int bad, near_id;
   const int tid = threadIdx.x;
-  {  // staging: the 16 loads of each thread are issued together (clamped addresses)
+  for (int u0 = 0; u0 < PT; u0 += 16) {  // staging: 16 loads of each thread at a time (clamped addresses)
     double v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+      const int e = tid + 256 * (u0 + u), i = e % R, j = e / R;
       v[u] = Ag[(i < r && j < r) ? i + static_cast<size_t>(j) * lda : 0];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+      const int e = tid + 256 * (u0 + u), i = e % R, j = e / R;
       a[i][j] = (i < r && j < r) ? v[u] : (i == j ? 1.0 : 0.0);
     }
   }
@@ -903,9 +906,9 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
   // rounding of the entries, and needs no sequential steps
   {
     bool far = false;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = tid + 256 * u, i = e % 64, j = e / 64;
+#pragma unroll 16
+    for (int u = 0; u < PT; ++u) {
+      const int e = tid + 256 * u, i = e % R, j = e / R;
       if (i <= j && j < r) far = far || !(fabs(a[i][j] - (i == j ? 1.0 : 0.0)) <= 0x1p-34);
     }
     if (far) near_id = 0;
@@ -921,7 +924,7 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
     return;
   }
   const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  for (int J = 0; J < 4; ++J) {
+  for (int J = 0; J < NB; ++J) {
     const int b = 16 * J;
     if (w == 0) {
       for (int jj = 0; jj < 16; ++jj) {
@@ -946,7 +949,7 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
       }
     }
     __syncthreads();
-    const int rest = 64 - b - 16;
+    const int rest = R - b - 16;
     if (rest > 0 && tid < rest) {
       const int c = b + 16 + tid;
       double x[16];
@@ -963,8 +966,8 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
     __syncthreads();
     // trailing upper blocks (K, L), J < K <= L, round-robin over the waves
     int t = 0;
-    for (int K = J + 1; K < 4; ++K)
-      for (int L = K; L < 4; ++L, ++t) {
+    for (int K = J + 1; K < NB; ++K)
+      for (int L = K; L < NB; ++L, ++t) {
         if (t % 4 != w) continue;
         dbl4 acc;
 #pragma unroll
@@ -995,68 +998,6 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
     *ok = fail ? 0 : 1;
   }
 }
-
-// Cholesky of r <= R (R = 64 or 128) by one NTH-thread workgroup, upper factor.
-// The matrix sits row-major in LDS; thread (ty, c) owns column c of rows
-// ty, ty + G, ... (G = NTH / R).  Step j subtracts a_ji a_jc / a_jj from every
-// (i, c) with j < i <= c, reading only row j: one barrier per step.  Row i is
-// scaled by 1 / sqrt(a_ii) when it is written out.
-template <int R, int NTH>
-__global__ __launch_bounds__(NTH) void k_cholesky_block(double* __restrict__ Ag, int r, int lda, double max_ratio,
-                                                        int32_t* __restrict__ ok) {
-  constexpr int GR = NTH / R;
-  constexpr int RPT = R / GR;
-  __shared__ double A[R * R];
-  __shared__ int bad;
-  for (int e = threadIdx.x; e < r * r; e += NTH) {
-    const int i = e % r, c = e / r;
-    A[i * R + c] = Ag[i + static_cast<size_t>(c) * lda];
-  }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  const int c = threadIdx.x % R, ty = threadIdx.x / R;
-  for (int j = 0; j < r; ++j) {
-    const double a = A[j * R + j];
-    if (!(a > 0.0)) {
-      if (threadIdx.x == 0) bad = 1;
-      break;
-    }
-    const double ia = 1.0 / a;
-    if (c > j && c < r) {
-      const double ajc = A[j * R + c] * ia;
-#pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int i = ty + u * GR;
-        if (i > j && i <= c) A[i * R + c] = fma(-A[j * R + i], ajc, A[i * R + c]);
-      }
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * r; e += NTH) {
-    const int i = e % r, cc = e / r;
-    double x = 0.0;
-    if (i == cc)
-      x = sqrt(A[i * R + i]);
-    else if (i < cc)
-      x = A[i * R + cc] / sqrt(A[i * R + i]);
-    Ag[i + static_cast<size_t>(cc) * lda] = bad ? 0.0 : x;
-  }
-  if (threadIdx.x == 0) {
-    int fail = bad;
-    if (!fail) {
-      double dmin = INFINITY, dmax = 0.0;
-      for (int i = 0; i < r; ++i) {
-        const double dd = sqrt(A[i * R + i]);
-        dmin = fmin(dmin, dd);
-        dmax = fmax(dmax, dd);
-      }
-      fail = dmax > max_ratio * dmin;
-    }
-    *ok = fail ? 0 : 1;
-  }
-}
-
 
 // Right-looking Cholesky, upper factor, in global memory, one workgroup.
 __global__ __launch_bounds__(BT) void k_cholesky_upper(double* __restrict__ A, int r, int lda, double max_ratio,
@@ -2693,12 +2634,12 @@ void cholesky_upper(double* A, int r, int lda, double max_ratio, int32_t* d_ok, 
   // r^3 / 3 multiply-adds; the matrix is read and written once
   KTimer kt("cholesky", s, 16.0 * r * r, 2.0 * r * r * r / 3.0);
   if (r <= 64) {
-    k_cholesky_mfma<<<1, 256, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    k_cholesky_mfma<64><<<1, 256, 0, s>>>(A, r, lda, max_ratio, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (r <= 128) {
-    k_cholesky_block<128, 1024><<<1, 1024, 0, s>>>(A, r, lda, max_ratio, d_ok);
+    k_cholesky_mfma<128><<<1, 256, 0, s>>>(A, r, lda, max_ratio, d_ok);
     TTS_LAUNCH_CHECK();
     return;
   }
