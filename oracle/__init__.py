@@ -307,3 +307,37 @@ def snap(x, key_bits: int) -> np.ndarray:
     out = np.empty_like(x)
     lib.orc_snap(_p(x, ctypes.c_double), x.size, int(key_bits), _p(out, ctypes.c_double))
     return out
+
+
+@dataclass
+class KnifeEdge:
+    """How far each bond's rank decision sits from flipping (rank rule of Alg 2, Sec. 2.4).
+
+    margin_rel[b]: min over r of |tail_r - delta^2| / ||A||_F^2, tail_r the sum of the
+                   squared singular values beyond r; a rank decision that rounding could
+                   flip has this near the unit roundoff.
+    kept_over_delta[b]: the smallest kept singular value over delta (inf for rank 0).
+    dropped_over_delta[b]: the largest discarded singular value over delta (0 if none).
+    """
+    margin_rel: list
+    kept_over_delta: list
+    dropped_over_delta: list
+
+
+def knife_edge(res: OracleResult) -> KnifeEdge:
+    """Distances of the oracle's rank decisions from the truncation threshold.
+
+    Uses only the singular values each bond met and the threshold it used, so the
+    same report can be made for any result carrying those (the GPU path's too).
+    """
+    margins, kept, dropped = [], [], []
+    norm2 = res.norm * res.norm
+    for b, sig in enumerate(res.sigma):
+        delta = res.bond_delta[b]
+        s = np.asarray(sig, dtype=np.float64)
+        tails = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])  # tails[r] = sum_{i>=r} s_i^2
+        margins.append(float(np.min(np.abs(tails[1:] - delta * delta))) / norm2)
+        r = res.ranks[b + 1]
+        kept.append(float(s[r - 1] / delta) if r >= 1 and delta > 0 else float("inf"))
+        dropped.append(float(s[r] / delta) if r < len(s) and delta > 0 else 0.0)
+    return KnifeEdge(margins, kept, dropped)

@@ -44,6 +44,13 @@ def check_round(oracle_mod, idx, val, dims, eps, label, max_rank=0, samples=4096
     # of rounding, and the GPU's deflation may drop up to 4 times that per bond, where
     # the oracle keeps everything: the bar widens by sqrt(d-1) bonds of that.
     tol = TOL if not (1 <= key_bits <= 51) else TOL + 4.0 * (d - 1) ** 1.5 * 2.0 ** -(key_bits + 1)
+    if max_rank == 0:
+        # a rank match on a knife edge (a tail sum within round-off of delta^2) is
+        # reported, not hidden
+        ke = oracle_mod.knife_edge(res)
+        print(f"  knife edge: min |tail - delta^2| = {min(ke.margin_rel):.2e} ||A||^2, smallest kept sigma "
+              f"{min(ke.kept_over_delta):.3g} delta, largest dropped {max(ke.dropped_over_delta):.3g} delta",
+              flush=True)
     assert tt.ranks == res.ranks, (tt.ranks, res.ranks)
     if max_rank == 0:
         for b in range(1, len(dims)):
