@@ -261,6 +261,23 @@ tt_status tt_eval_entries_backward(int32_t d, const int64_t* dims, const int64_t
                                    void* stream);
 
 /*
+ * tt_eval_entries without any device allocation, for callers that cannot allocate
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, result (y_out) and errors as tt_eval_entries; the entries
+ * are computed entry by entry (left-to-right chain per coordinate), so they agree
+ * with tt_eval_entries to round-off of a different summation order.  The call's
+ * only scratch, a 4-byte coordinate-check flag, lives in a static 256-byte device
+ * array of the library (one per device, held until the process ends); its size does
+ * not depend on m or the ranks, so no input is too large for it.  The flag is
+ * cleared by a kernel at the start of every call.  Calls that overlap on one device
+ * (other streams, other threads) share that array and race: serialise them.
+ * Returns after its one 4-byte read-back of the flag.
+ */
+tt_status tt_eval_entries_noalloc(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                  const void* const* cores, int32_t dtype, int64_t m, const int32_t* idx,
+                                  void* y_out, void* stream);
+
+/*
  * Evaluation plan: the same two operations as tt_eval_entries and
  * tt_eval_entries_backward (entry formula of Sec. 2.3 and its derivative), split
  * so that work which depends only on the coordinates is done once.

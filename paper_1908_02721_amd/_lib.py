@@ -55,7 +55,7 @@ EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
     "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_bond_delta", "tt_get_times", "tt_matrix_to_tensor",
     "tt_fasttt_decompose", "tt_get_fasttt_info", "tt_fasttt_select_p", "tt_get_level", "tt_free",
-    "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_plan_create", "tt_eval_plan_forward",
+    "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_entries_noalloc", "tt_eval_plan_create", "tt_eval_plan_forward",
     "tt_eval_plan_backward", "tt_eval_plan_free", "tt_status_string", "tt_last_error",
     "tt_kernel_timer_start", "tt_kernel_timer_read",
 )
@@ -104,6 +104,8 @@ def load():
         L.tt_free.restype = None
         L.tt_eval_entries.argtypes = [i32, P(i64), P(i64), P(vp), i32, i64, vp, vp, vp]
         L.tt_eval_entries.restype = ctypes.c_int
+        L.tt_eval_entries_noalloc.argtypes = [i32, P(i64), P(i64), P(vp), i32, i64, vp, vp, vp]
+        L.tt_eval_entries_noalloc.restype = ctypes.c_int
         L.tt_eval_entries_backward.argtypes = [i32, P(i64), P(i64), P(vp), i32, i64, vp, vp, P(vp), vp]
         L.tt_eval_entries_backward.restype = ctypes.c_int
         L.tt_eval_plan_create.argtypes = [i32, P(i64), i64, vp, vp, P(vp)]

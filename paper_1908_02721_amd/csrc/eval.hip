@@ -18,8 +18,16 @@
 #include <utility>
 #include <vector>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "prim.hpp"
+
+// Scratch of the allocation-free evaluation (tt_eval_entries_noalloc): word 0 is the
+// coordinate-check flag of the per-entry kernel.  One copy per device, held until
+// the process ends.  Host code never passes this name to a kernel or a copy: it
+// takes the device address from hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) uint32_t scratch[64];
 
 namespace tts {
 namespace {
@@ -1710,3 +1718,74 @@ extern "C" tt_status tt_eval_plan_backward(tt_eval_plan plan, const int64_t* ran
 }
 
 extern "C" void tt_eval_plan_free(tt_eval_plan plan) { delete plan; }
+
+// ---------------------------------------------------------------------------
+// Allocation-free evaluation: the per-entry chain kernel (as tt_eval_entries uses
+// for coordinates it cannot pack), with its one word of scratch taken from the
+// static `scratch` array instead of an allocation.
+// ---------------------------------------------------------------------------
+namespace tts {
+namespace {
+
+// The call needs one 4-byte word (the flag) whatever m and the ranks, so no input
+// size can exceed the array.
+static_assert(sizeof(uint32_t) <= sizeof(::scratch), "scratch too small");
+
+__global__ void k_clear_flag(uint32_t* __restrict__ f) { *f = 0u; }
+
+// Device address of `scratch` on the current device, looked up once per device with
+// that device current.
+uint32_t* noalloc_scratch() {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  TTS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(TT_ERR_DEVICE, "device ordinal outside [0, 64)");
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    TTS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch)));
+    if (!p) fail(TT_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    ptr[dev] = p;
+  }
+  return static_cast<uint32_t*>(ptr[dev]);
+}
+
+template <typename T>
+tt_status noalloc_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, T* y, hipStream_t s) {
+  uint32_t* flag = noalloc_scratch();
+  k_clear_flag<<<1, 1, 0, s>>>(flag);  // the array keeps the last call's contents
+  TTS_LAUNCH_CHECK();
+  if (m > 0) launch_left<T>(ed, m, idx, y, nullptr, flag, s);
+  uint32_t h = 0;
+  TTS_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+  TTS_HIP(hipStreamSynchronize(s));
+  if (h) {
+    set_last_error("a coordinate is outside its mode range");
+    return TT_ERR_INDEX;
+  }
+  return TT_OK;
+}
+
+}  // namespace
+}  // namespace tts
+
+extern "C" tt_status tt_eval_entries_noalloc(int32_t d, const int64_t* dims, const int64_t* ranks,
+                                             const void* const* cores, int32_t dtype, int64_t m, const int32_t* idx,
+                                             void* y_out, void* stream) {
+  EvalDesc ed;
+  tt_status st = check_args(d, dims, ranks, cores, dtype, m, idx, ed);
+  if (st != TT_OK) return st;
+  if (m > 0 && !y_out) {
+    set_last_error("y_out must not be NULL when m > 0");
+    return TT_ERR_ARG;
+  }
+  try {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return dtype == TT_DTYPE_F64 ? noalloc_eval<double>(ed, m, idx, static_cast<double*>(y_out), s)
+                                 : noalloc_eval<float>(ed, m, idx, static_cast<float*>(y_out), s);
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+}
