@@ -161,6 +161,66 @@ tt_status tt_fasttt_select_p(int32_t d, const int64_t* dims, int64_t nnz, const 
                              double* costs, int32_t* p, void* stream);
 
 /*
+ * Bond-2 Gram slice of the orthogonalisation sweep, for tensors whose second bond
+ * is too wide to factor on one device (the left-to-right QR sweep of TT-rounding,
+ * Algorithm 2 in Sec. 2.4, stopped at the Gram matrix of bond 2).  After the exact
+ * sparse TT (as tt_sparse_decompose):
+ *   bond 1: X_1 = unfold_2(G^(1)) (n_1 x beta_1) = Q_1 R_1, an economic QR with
+ *     m = min(#nonzero rows of X_1, beta_1).  The bond-1 unfolding must be wide
+ *     (beta_1 >= n_1, else TT_ERR_ARG) and then leaves Q_1 free up to an orthogonal
+ *     factor; the call fixes it by the SVD: Q_1 = left singular vectors, singular
+ *     values non-ascending, the entry of largest magnitude of each column positive
+ *     (lowest index on ties); R_1 = Q_1^T X_1.  FP64 in every precision.
+ *   X_2 = unfold_2(R_1 x_1 G^(2)) ((m n_2) x beta_2), block-sparse: block (j, i)
+ *     (column j, slot i = i_2) is the m-vector sum over the entries
+ *     (rho = g n_2 + i, column j, value c) of N_2 of c R_1[:, g].  In TT_FP64 it is
+ *     computed and stored in binary64; in TT_FP32 / TT_BF16_FP32ACC its operands are
+ *     rounded to binary32 / bfloat16 (via binary32), products accumulated and
+ *     stored in binary32.
+ *   the weighted Gram Gamma = X_2 diag(w_2) X_2^T in FP64, w_2[j] the squared norm
+ *     of row j of the right part of bond 2 (the product of the exact cores 3..d,
+ *     whose rows are mutually orthogonal).  Up to the orthogonal factor Q_1 (x) I,
+ *     Gamma is the Gram matrix of the bond-2 unfolding of A: its eigenvalues are
+ *     that unfolding's squared singular values and its trace is ||A||_F^2.
+ * Arguments, inputs, errors and the handle as tt_sparse_decompose (d >= 3,
+ * n_1 <= 208); options: precision, keep_intermediates (tt_get_level), key_bits,
+ * device_mem_budget and the allocator hooks apply; max_rank, dynamic_delta and
+ * sparse_only give TT_ERR_ARG.  The handle answers tt_get_info, tt_get_sparse_ranks,
+ * tt_get_level, tt_get_times (stage 4 = the whole slice) and the tt_get_slice_*
+ * calls below; it holds no cores.  Device memory: X_2 (nblocks m values) and the
+ * packed Gram (n_2 (n_2 + 1) / 2 m^2 doubles) stay allocated until tt_free.
+ */
+tt_status tt_sparse_gram_slice(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                               const tt_options* opt, void* stream, tt_result* out);
+
+/* Bond 1 of a Gram slice: *m; Q_1 (device, n_1 x m column-major), R_1 (device,
+   m x beta_1 column-major), singular values of X_1 (host, m, non-ascending); all
+   borrowed until tt_free.  Any pointer may be NULL.  TT_ERR_ARG for other results. */
+tt_status tt_get_slice_bond1(tt_result r, int64_t* m, const double** q1, const double** r1, const double** sigma);
+
+/* X_2 of a Gram slice, blocks stored slot-major: the blocks of slot i are
+   [slot_ptr[i], slot_ptr[i+1]) (device int64[n_2 + 1]), ordered by column;
+   blk_col (device int32[nblocks]) is each block's column j; vals (device,
+   [nblocks][m], binary64 when *dtype is TT_DTYPE_F64, else binary32) the block
+   vectors.  Borrowed until tt_free; any pointer may be NULL. */
+tt_status tt_get_slice_x2(tt_result r, int64_t* nblocks, const int64_t** slot_ptr, const int32_t** blk_col,
+                          const void** vals, int32_t* dtype);
+
+/* The weighted Gram of a Gram slice, packed by blocks: rows and columns are
+   q = i m + a (slot i = i_2, a = the bond-1 index); only the blocks (i, i2) with
+   i <= i2 are stored, block (i, i2) at element offset
+   (i n_2 - i (i - 1) / 2 + (i2 - i)) m^2, as an m x m row-major matrix
+   (Gamma[(i, a), (i2, a2)] at a m + a2); Gamma is symmetric.  Also: wnorm2 =
+   sum over the blocks of w_2[j] ||block||^2 (= trace Gamma, in FP64), npairs = the
+   number of (slot, slot) pairs of the columns of N_2 (i < i2), flops = the
+   algorithmic FP64 flops of the Gram (symmetric part: m (m + 1) per diagonal-block
+   term, 2 m^2 per off-diagonal pair), host_ms[5] = the slice's stage times
+   (bond-1 QR, X_2, pair lists, Gram, whole slice) from HIP events.  Any pointer
+   may be NULL. */
+tt_status tt_get_slice_gram(tt_result r, const double** gram, double* wnorm2, int64_t* npairs, double* flops,
+                            double* host_ms);
+
+/*
  * Matrix -> tensor coordinates for the matrix-in-TT-format (MPO) front-end
  * (Sec. 3.4, matrices in TT-format).  An M x N matrix, M = m_1...m_d,
  * N = n_1...n_d, is the d-way tensor with modes of size m_k n_k: the row index

@@ -149,6 +149,23 @@ class Slice:
         common, p1, p2 = np.intersect1d(c1, c2, assume_unique=True, return_indices=True)
         return float(np.sum(self.w2[common] * v1[p1] * v2[p2]))
 
+    def dense_x2(self):
+        """X_2 as a dense (n_2 m) x beta_2 array with slot-major rows q = i m + a (small sizes only)."""
+        X = np.zeros((self.n2 * self.m, self.beta2))
+        for i in range(self.n2):
+            lo, hi = self.slot_start[i], self.slot_start[i + 1]
+            if hi == lo:
+                continue
+            cols, starts = self._slot_cols(i)
+            V = self.e_c[lo:hi, None] * self.b1.R1[:, self.e_g[lo:hi]].T
+            X[i * self.m:(i + 1) * self.m, cols] = np.add.reduceat(V, starts, axis=0).T
+        return X
+
+    def dense_gram(self):
+        """Gamma = X_2 diag(w_2) X_2^T, dense, slot-major (small sizes only)."""
+        X = self.dense_x2()
+        return (X * self.w2[None, :]) @ X.T
+
     def block_trace(self, i):
         """trace of the diagonal block (i, i) of Gamma: sum_a Gamma[(i, a), (i, a)]."""
         return float(sum(self.gram(i * self.m + a, i * self.m + a) for a in range(self.m)))

@@ -250,6 +250,105 @@ def fasttt_decompose(idx: torch.Tensor, val: torch.Tensor, dims, eps: float, p: 
     return tt
 
 
+class GramSlice(TT):
+    """Result of ``gram_slice``: the bond-2 Gram slice of the QR sweep (tt_sparse_gram_slice).
+
+    Attributes: m (bond-1 rank), sigma1 (singular values of X_1, numpy), nblocks,
+    npairs, wnorm2 (= trace of the Gram), gram_flops (algorithmic FP64 flops of the
+    Gram), slice_ms (stage times).  q1() and r1() return owning copies; x2_view()
+    and gram_view() return views of library memory, valid while this object lives.
+    """
+
+    def __init__(self, handle: ctypes.c_void_p, dims):
+        super().__init__(handle, dims)
+        import numpy as np
+
+        L = _lib.load()
+        m = ctypes.c_int64()
+        q1, r1 = ctypes.c_void_p(), ctypes.c_void_p()
+        sg = ctypes.POINTER(ctypes.c_double)()
+        _lib.check(L.tt_get_slice_bond1(self._h, ctypes.byref(m), ctypes.byref(q1), ctypes.byref(r1), ctypes.byref(sg)))
+        self.m = int(m.value)
+        self._q1, self._r1 = q1.value, r1.value
+        self.sigma1 = np.ctypeslib.as_array(sg, shape=(self.m,)).copy()
+        nb = ctypes.c_int64()
+        sp, bc, xv = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        dt = ctypes.c_int32()
+        _lib.check(L.tt_get_slice_x2(self._h, ctypes.byref(nb), ctypes.byref(sp), ctypes.byref(bc), ctypes.byref(xv),
+                                     ctypes.byref(dt)))
+        self.nblocks = int(nb.value)
+        self._slot_ptr, self._blk_col, self._x2 = sp.value, bc.value, xv.value
+        self.x2_dtype = torch.float64 if dt.value == _lib.DTYPE_F64 else torch.float32
+        g = ctypes.c_void_p()
+        wn, fl = ctypes.c_double(), ctypes.c_double()
+        npairs = ctypes.c_int64()
+        ms = (ctypes.c_double * 5)()
+        _lib.check(L.tt_get_slice_gram(self._h, ctypes.byref(g), ctypes.byref(wn), ctypes.byref(npairs),
+                                       ctypes.byref(fl), ms))
+        self._gram = g.value
+        self.wnorm2, self.gram_flops, self.npairs = wn.value, fl.value, int(npairs.value)
+        self.slice_ms = dict(zip(("bond1_qr", "x2", "pairs", "gram", "slice"), (float(x) for x in ms)))
+        self.n2 = self.dims[1]
+
+    def q1(self) -> torch.Tensor:
+        """Q_1 as an owning [n_1, m] tensor."""
+        return _copy_from_device(self._q1, (self.m, self.dims[0]), torch.float64).T
+
+    def r1(self) -> torch.Tensor:
+        """R_1 as an owning [m, beta_1] tensor."""
+        return _copy_from_device(self._r1, (self.betas[1], self.m), torch.float64).T
+
+    def slot_ptr(self) -> torch.Tensor:
+        return _copy_from_device(self._slot_ptr, (self.n2 + 1,), torch.int64)
+
+    def blk_col(self) -> torch.Tensor:
+        return _copy_from_device(self._blk_col, (self.nblocks,), torch.int32)
+
+    def x2_view(self) -> torch.Tensor:
+        """The X_2 blocks [nblocks, m] (slot-major), a view of library memory."""
+        return torch.as_tensor(_CAI(self._x2, (self.nblocks, self.m), _TYPESTR[self.x2_dtype]), device="cuda")
+
+    def gram_view(self) -> torch.Tensor:
+        """The packed upper blocks of the Gram (1-D), a view of library memory."""
+        n = self.n2 * (self.n2 + 1) // 2 * self.m * self.m
+        return torch.as_tensor(_CAI(self._gram, (n,), "<f8"), device="cuda")
+
+    def gram_offset(self, q, q2):
+        """Element offsets in gram_view() of Gamma[q, q2] (q = i m + a; arrays or ints, i <= i2 after swap)."""
+        import numpy as np
+
+        q = np.asarray(q, dtype=np.int64)
+        q2 = np.asarray(q2, dtype=np.int64)
+        lo, hi = np.minimum(q, q2), np.maximum(q, q2)
+        swap = (q // self.m) > (q2 // self.m)
+        a_row = np.where(swap, q2, q)
+        a_col = np.where(swap, q, q2)
+        i, a = a_row // self.m, a_row % self.m
+        i2, a2 = a_col // self.m, a_col % self.m
+        blk = i * self.n2 - i * (i - 1) // 2 + (i2 - i)
+        del lo, hi
+        return blk * self.m * self.m + a * self.m + a2
+
+
+def gram_slice(idx: torch.Tensor, val: torch.Tensor, dims, precision: str = "fp64", keep_intermediates: bool = False,
+               key_bits: int = 0, device_mem_budget: int = 0, stream=None) -> GramSlice:
+    """Bond-2 Gram slice of the QR sweep (tt_sparse_gram_slice): bond-1 QR in the SVD
+    gauge, X_2 = R_1 x_1 G^(2) (block-sparse, in the precision's operands) and the
+    weighted FP64 Gram of bond 2."""
+    L = _lib.load()
+    idx, val, d, nnz, dims_a = _coo_args(idx, val, dims)
+    opt = _lib.tt_options()
+    L.tt_options_default(ctypes.byref(opt))
+    opt.precision = _lib.PRECISION[precision]
+    opt.keep_intermediates = int(bool(keep_intermediates))
+    opt.key_bits = int(key_bits)
+    opt.device_mem_budget = int(device_mem_budget)
+    h = ctypes.c_void_p()
+    _lib.check(L.tt_sparse_gram_slice(d, dims_a, nnz, ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                                      ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h)))
+    return GramSlice(h, dims)
+
+
 def fasttt_select_p(idx: torch.Tensor, val: torch.Tensor, dims, stream=None):
     """Algorithm 9: (p, estimated cost of every p = 1..d)."""
     L = _lib.load()

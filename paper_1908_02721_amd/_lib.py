@@ -54,7 +54,8 @@ class tt_options(ctypes.Structure):
 EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
     "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_bond_delta", "tt_get_times", "tt_matrix_to_tensor",
-    "tt_fasttt_decompose", "tt_get_fasttt_info", "tt_fasttt_select_p", "tt_get_level", "tt_free",
+    "tt_fasttt_decompose", "tt_get_fasttt_info", "tt_sparse_gram_slice", "tt_get_slice_bond1", "tt_get_slice_x2",
+    "tt_get_slice_gram", "tt_fasttt_select_p", "tt_get_level", "tt_free",
     "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_entries_noalloc", "tt_eval_plan_create", "tt_eval_plan_forward",
     "tt_eval_plan_backward", "tt_eval_plan_free", "tt_status_string", "tt_last_error",
     "tt_kernel_timer_start", "tt_kernel_timer_read",
@@ -92,6 +93,14 @@ def load():
         L.tt_matrix_to_tensor.restype = ctypes.c_int
         L.tt_fasttt_decompose.argtypes = [i32, P(i64), i64, vp, vp, f64, i32, P(tt_options), vp, P(vp)]
         L.tt_fasttt_decompose.restype = ctypes.c_int
+        L.tt_sparse_gram_slice.argtypes = [i32, P(i64), i64, vp, vp, P(tt_options), vp, P(vp)]
+        L.tt_sparse_gram_slice.restype = ctypes.c_int
+        L.tt_get_slice_bond1.argtypes = [vp, P(i64), P(vp), P(vp), P(P(f64))]
+        L.tt_get_slice_bond1.restype = ctypes.c_int
+        L.tt_get_slice_x2.argtypes = [vp, P(i64), P(vp), P(vp), P(vp), P(i32)]
+        L.tt_get_slice_x2.restype = ctypes.c_int
+        L.tt_get_slice_gram.argtypes = [vp, P(vp), P(f64), P(i64), P(f64), P(f64)]
+        L.tt_get_slice_gram.restype = ctypes.c_int
         L.tt_get_fasttt_info.argtypes = [vp, P(i32), P(i64)]
         L.tt_get_fasttt_info.restype = ctypes.c_int
         L.tt_fasttt_select_p.argtypes = [i32, P(i64), i64, vp, vp, P(f64), P(i32), vp]

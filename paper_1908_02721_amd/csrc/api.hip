@@ -6,6 +6,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -15,6 +16,7 @@
 #include "dense.hpp"
 #include "ftt.hpp"
 #include "prim.hpp"
+#include "slice.hpp"
 #include "sparse.hpp"
 
 namespace tts {
@@ -167,6 +169,7 @@ struct tt_result_s {
   double ms[TT_NUM_STAGES] = {};
   int32_t ftt_p = 0;        // fiber-trie FastTT result: the p used (0 otherwise)
   int64_t ftt_fibers = 0;   // and its number of nonzero p-fibers
+  std::unique_ptr<tts::SliceOut> slice;  // bond-2 Gram slice result (tt_sparse_gram_slice)
 };
 
 namespace tts {
@@ -676,6 +679,166 @@ tt_status tt_fasttt_decompose(int32_t d, const int64_t* dims, int64_t nnz, const
     }
     return TT_ERR_NOMEM;
   }
+}
+
+tt_status tt_sparse_gram_slice(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx, const double* val,
+                               const tt_options* opt, void* stream, tt_result* out) {
+  if (!out) {
+    set_error("out is NULL");
+    return TT_ERR_ARG;
+  }
+  *out = nullptr;
+  tt_options o;
+  tt_options_default(&o);
+  if (opt) o = *opt;
+  std::string why;
+  if (d < 3 || d > TT_MAX_D) why = "d must be in [3, 64]";
+  else if (!dims) why = "dims is NULL";
+  else if (nnz < 0 || nnz >= (int64_t(1) << 31)) why = "nnz must be in [0, 2^31)";
+  else if (nnz > 0 && (!idx || !val)) why = "idx/val is NULL";
+  else if (o.precision < TT_FP64 || o.precision > TT_BF16_FP32ACC) why = "unknown precision";
+  else if (o.max_rank || o.dynamic_delta || o.sparse_only)
+    why = "max_rank, dynamic_delta and sparse_only do not apply to the Gram slice";
+  else if (o.key_bits < 0 || o.key_bits > 52) why = "key_bits must be in [0, 52]";
+  else if ((o.alloc == nullptr) != (o.free == nullptr)) why = "alloc and free hooks must be given together";
+  if (why.empty())
+    for (int k = 0; k < d; ++k)
+      if (dims[k] < 1 || dims[k] > INT32_MAX) why = "every n_k must be in [1, 2^31-1]";
+  if (why.empty() && dims[0] > 208) why = "the Gram slice supports n_1 <= 208";
+  if (!why.empty()) {
+    set_error(why);
+    return TT_ERR_ARG;
+  }
+  ModeInfo mi{};
+  mi.d = d;
+  int total_bits = 0;
+  for (int k = 0; k < d; ++k) {
+    mi.n[k] = static_cast<uint32_t>(dims[k]);
+    mi.bits[k] = bits_for(static_cast<uint64_t>(dims[k]));
+    mi.off[k] = static_cast<uint32_t>(total_bits);
+    total_bits += static_cast<int>(mi.bits[k]);
+  }
+  if (total_bits > 63) {
+    set_error("packed coordinate needs more than 63 bits");
+    return TT_ERR_TOO_LARGE;
+  }
+  if (nnz == 0) {
+    set_error("no nonzero given");
+    return TT_ERR_EMPTY;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  tt_result_s* R = nullptr;
+  try {
+    configure_pool_once();
+    R = new tt_result_s();
+    R->al.stream = s;
+    R->al.hook_alloc = o.alloc;
+    R->al.hook_free = o.free;
+    R->al.ctx = o.alloc_ctx;
+    R->al.budget = o.device_mem_budget;
+    R->d = d;
+    R->dims.assign(dims, dims + d);
+    Events ev;
+    TTS_HIP(hipEventRecord(ev.e[0], s));
+    sparse_stage(R, idx, val, static_cast<uint32_t>(nnz), mi, total_bits, o.keep_intermediates != 0, o.key_bits, s,
+                 ev);
+    SliceInput in{};
+    in.d = d;
+    in.dims = R->dims;
+    in.betas = R->betas;
+    in.precision = o.precision;
+    for (int k = 1; k <= d - 1; ++k) {
+      const LevelData& L = R->lev[k - 1];
+      in.n_colptr.push_back(L.colptr.get());
+      in.n_row.push_back(L.row.get());
+      in.n_val.push_back(L.val.get());
+      in.n_nnz.push_back(L.nnz_n);
+    }
+    in.last_core = R->last_exact.get();
+    R->slice = std::make_unique<SliceOut>();
+    gram_slice(R->al, in, *R->slice, s);
+    TTS_HIP(hipEventRecord(ev.e[4], s));
+    TTS_HIP(hipEventRecord(ev.e[5], s));
+    TTS_HIP(hipEventRecord(ev.e[6], s));
+    TTS_HIP(hipEventSynchronize(ev.e[6]));
+    for (int i = 0; i < TT_NUM_STAGES - 1; ++i) {
+      float ms = 0.f;
+      TTS_HIP(hipEventElapsedTime(&ms, ev.e[i], ev.e[i + 1]));
+      R->ms[i] = ms;
+    }
+    float tot = 0.f;
+    TTS_HIP(hipEventElapsedTime(&tot, ev.e[0], ev.e[6]));
+    R->ms[TT_NUM_STAGES - 1] = tot;
+    R->ranks = R->betas;
+    if (!o.keep_intermediates) {
+      for (auto& L : R->lev) {
+        L.colptr.release();
+        L.row.release();
+        L.val.release();
+      }
+      R->last_exact.release();
+    }
+    *out = R;
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    if (R) {
+      (void)hipStreamSynchronize(s);
+      delete R;
+    }
+    return TT_ERR_NOMEM;
+  }
+}
+
+tt_status tt_get_slice_bond1(tt_result r, int64_t* m, const double** q1, const double** r1, const double** sigma) {
+  if (!r || !r->slice) {
+    set_error("not a Gram slice result");
+    return TT_ERR_ARG;
+  }
+  const SliceOut& o = *r->slice;
+  if (m) *m = o.m;
+  if (q1) *q1 = o.q1.get();
+  if (r1) *r1 = o.r1.get();
+  if (sigma) *sigma = o.sigma1.data();
+  return TT_OK;
+}
+
+tt_status tt_get_slice_x2(tt_result r, int64_t* nblocks, const int64_t** slot_ptr, const int32_t** blk_col,
+                          const void** vals, int32_t* dtype) {
+  if (!r || !r->slice) {
+    set_error("not a Gram slice result");
+    return TT_ERR_ARG;
+  }
+  const SliceOut& o = *r->slice;
+  if (nblocks) *nblocks = o.nblocks;
+  if (slot_ptr) *slot_ptr = o.slot_ptr.get();
+  if (blk_col) *blk_col = o.blk_col.get();
+  if (vals) *vals = o.x2.get();
+  if (dtype) *dtype = o.x2_dtype;
+  return TT_OK;
+}
+
+tt_status tt_get_slice_gram(tt_result r, const double** gram, double* wnorm2, int64_t* npairs, double* flops,
+                            double* host_ms) {
+  if (!r || !r->slice) {
+    set_error("not a Gram slice result");
+    return TT_ERR_ARG;
+  }
+  const SliceOut& o = *r->slice;
+  if (gram) *gram = o.gram.get();
+  if (wnorm2) *wnorm2 = o.wnorm2;
+  if (npairs) *npairs = o.npairs;
+  if (flops) *flops = o.gram_flops;
+  if (host_ms)
+    for (int i = 0; i < 5; ++i) host_ms[i] = o.ms[i];
+  return TT_OK;
 }
 
 tt_status tt_get_fasttt_info(tt_result r, int32_t* p, int64_t* fibers) {

@@ -13,7 +13,7 @@ def _declared():
     with open(os.path.join(ROOT, "include", "ttsparse.h")) as f:
         txt = f.read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(tt_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(tt_[a-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")

@@ -71,6 +71,8 @@ def test_x2_weights_and_gram_against_dense(oracle_mod, name, dims, nnz, seed):
     N = n2 * m
     gg = np.array([[sl.gram(q, q2) for q2 in range(N)] for q in range(N)])
     assert np.max(np.abs(gg - Gam)) <= 1e-12 * np.max(np.abs(Gam))
+    assert np.max(np.abs(sl.dense_x2() - X2p)) <= 1e-13 * max(1.0, np.max(np.abs(X2p)))
+    assert np.max(np.abs(sl.dense_gram() - Gam)) <= 1e-12 * np.max(np.abs(Gam))
     # its eigenvalues are the squared singular values of the dense bond-2 unfolding of A
     s = np.linalg.svd(A.reshape(dims[0] * dims[1], -1), compute_uv=False)
     ev = np.sort(np.linalg.eigvalsh(Gam))[::-1]
