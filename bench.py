@@ -12,6 +12,10 @@ as it needs only the coordinates; --no-overlap builds it afterwards):
   tt_eval_plan_create   sort of the nonzero coordinates and their prefix trie
   tt_eval_plan_forward  the TT at every nonzero coordinate (left products kept)
   tt_eval_plan_backward gradient of sum_n val[n] * TT(i_n) w.r.t. every core
+The FP64 run also times the FP32 form of the same step ("mixed"), the sparse stage
+against HBM ("roofline.sparse_hbm") and the bond-2 Gram slice on the 5-way 200^5
+tensor with 10^7 nonzeros in FP64/FP32/BF16 ("c4_slice": its Gram kernel against the
+FP64 matrix-core peak, errors against oracle values stored in tests/golden).
 With --matrix-input (the Laplacian workload) the step starts from the sparse matrix
 and first runs tt_matrix_to_tensor, the front-end of the MPO form.  With
 --dynamic-delta the truncation thresholds follow Algorithm 8; with --key-bits B the
@@ -84,6 +88,9 @@ def _parse():
     p.add_argument("--dynamic-delta", action="store_true",
                    help="per-bond truncation thresholds from the remaining error budget (Algorithm 8)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-mixed", action="store_true", help="skip the FP32 leg of the FP64 run")
+    p.add_argument("--no-slice", action="store_true",
+                   help="skip the bond-2 Gram slice leg (5-way 200^5 tensor, 10^7 nonzeros)")
     p.add_argument("--no-overlap", action="store_true",
                    help="build the evaluation plan after the decomposition instead of beside it")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
@@ -104,15 +111,19 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
     import oracle
 
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    if method == "fasttt":
-        from oracle import ftt
+    t_runs = []
+    for _ in range(3):  # median of three runs of the whole decomposition
+        t0 = time.perf_counter()
+        if method == "fasttt":
+            from oracle import ftt
 
-        res = ftt.decompose(idx, val, dims, eps, p=p, max_rank=max_rank)
-        res.cores = [np.ascontiguousarray(c) for c in res.cores]
-    else:
-        res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic, key_bits=key_bits)
-    t_dec = time.perf_counter() - t0
+            res = ftt.decompose(idx, val, dims, eps, p=p, max_rank=max_rank)
+            res.cores = [np.ascontiguousarray(c) for c in res.cores]
+        else:
+            res = oracle.decompose(idx, val, dims, eps, max_rank=max_rank, dynamic_delta=dynamic,
+                                   key_bits=key_bits)
+        t_runs.append(time.perf_counter() - t0)
+    t_dec = float(np.median(t_runs))
     rng = np.random.Generator(np.random.PCG64(11))
     pick = rng.choice(len(val), min(sample, len(val)), replace=False)
     t0 = time.perf_counter()
@@ -126,15 +137,76 @@ def cpu_baseline(idx, val, dims, eps, sample, gpu_cores=None, precision="fp64", 
         "unit": "nnz/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"full FP64 decomposition of the workload ({t_dec:.2f} s) + eval/backward on {len(pick)} of "
+        "sample": (f"full FP64 decomposition of the workload (median of 3: {t_dec:.2f} s; runs "
+                   f"{', '.join(f'{t:.2f}' for t in t_runs)} s) + eval/backward on {len(pick)} of "
                    f"{len(val)} nonzeros ({t_eval:.2f} s, scaled linearly to all nonzeros)"),
+        "host": host_info(),
     }
     err = None
     if gpu_cores is not None:
-        c64 = [np.ascontiguousarray(c, dtype=np.float64) for c in gpu_cores]
-        err = {"precision": precision, "rel_fro": oracle.tt_diff_norm(c64, res.cores) / res.norm,
-               "ranks_gpu": [int(c.shape[0]) for c in c64] + [1], "ranks_oracle": list(res.ranks)}
-    return base, err
+        err = error_vs_oracle(res, gpu_cores, precision)
+    return base, err, res
+
+
+def error_vs_oracle(res, gpu_cores, precision):
+    import oracle
+
+    c64 = [np.ascontiguousarray(c, dtype=np.float64) for c in gpu_cores]
+    return {"precision": precision, "rel_fro": oracle.tt_diff_norm(c64, res.cores) / res.norm,
+            "ranks_gpu": [int(c.shape[0]) for c in c64] + [1], "ranks_oracle": list(res.ranks)}
+
+
+def host_info():
+    """CPU model and core counts of this host (the oracle uses one core)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable, "oracle_threads": 1}
+
+
+def sparse_alg_bytes(nnz, d, level_sizes):
+    """Algorithmic bytes of the sparse stage (ingest, sort, every level): read the COO
+    once, each level once, write each next level and each N_k once:
+    nnz (4d + 8) + 16 nnz + sum_{k>=2} 20 nnz_k + sum_k (20 nnz_{k+1} + 12 nnz(N_k)),
+    nnz_k the entries of level k (nnz_{k+1} = the columns of level k)."""
+    b = nnz * (4 * d + 8) + 16 * nnz
+    prev = None
+    for ncols, _beta, nnz_n in level_sizes:
+        if prev is not None:
+            b += 20 * prev
+        b += 20 * ncols + 12 * nnz_n
+        prev = ncols
+    return float(b)
+
+
+def copy_gbps(mib=1024, reps=5):
+    """Bytes moved per second by a plain device-to-device copy (read + write)."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 8 / (ms / 1000.0) / 1e9
 
 
 def _traffic(family, workload, method):
@@ -181,6 +253,69 @@ def calibrate_copy(mib):
                       "copies": 6, "ms_per_copy": ms, "copy_GBps": 2 * n * 8 / (ms / 1000.0) / 1e9}), flush=True)
 
 
+def c4_slice_leg(reps=3):
+    """The bond-2 Gram slice (tt_sparse_gram_slice) on the 5-way 200^5 tensor with 10^7
+    N(0,1) nonzeros, in the three precisions: whole-call nonzeros/s, stage times, the
+    Gram kernel's FP64 MFMA rate from the live timer, and the error against the
+    oracle's values stored at seeded positions (tests/golden)."""
+    import torch
+
+    import paper_1908_02721_amd as tts
+    from paper_1908_02721_amd import _lib, synth
+
+    golden = os.path.join(ROOT, "tests", "golden", "slice_random5d_n200_nnz10m.json")
+    with open(golden) as f:
+        gold = json.load(f)
+    idx, val, dims, _ = synth.workload(gold["workload"])
+    gi = torch.from_numpy(idx).cuda()
+    gv = torch.from_numpy(val).cuda()
+    out = {"workload": gold["workload"], "dims": list(dims), "nnz": len(val), "reps": reps}
+    for prec in ("fp64", "fp32", "bf16"):
+        gs = tts.gram_slice(gi, gv, dims, precision=prec)  # warm-up
+        del gs
+        torch.cuda.synchronize()
+        _lib.kernel_timer_start("slice_gram")
+        tot, stages = [], []
+        for r in range(reps):
+            gs = tts.gram_slice(gi, gv, dims, precision=prec)
+            tot.append(gs.times_ms["total"])
+            stages.append(gs.slice_ms)
+            if r < reps - 1:
+                del gs
+        k_ms, k_n, k_bytes, k_flops = _lib.kernel_timer_read()
+        _lib.kernel_timer_start(None)
+        tf = k_flops / (k_ms / 1000.0) / 1e12
+        m, n2 = gold["m"], dims[1]
+        # error against the oracle's samples (the same scales as tests/test_gpu_slice.py)
+        x = gold["x2"]
+        sp = gs.slot_ptr().cpu().numpy()
+        bc = gs.blk_col().cpu().numpy()
+        b = np.array([sp[i] + np.searchsorted(bc[sp[i]:sp[i + 1]], j) for i, j in zip(x["i"], x["j"])])
+        xv = gs.x2_view()[torch.from_numpy(b).cuda(), torch.from_numpy(np.asarray(x["a"])).cuda()]
+        ex = np.abs(xv.double().cpu().numpy() - np.asarray(x["v"])) / np.asarray(x["scale"])
+        g = gold["gram"]
+        off = gs.gram_offset(np.asarray(g["q"]), np.asarray(g["q2"]))
+        gvv = gs.gram_view()[torch.from_numpy(off).cuda()].cpu().numpy()
+        eg = np.abs(gvv - np.asarray(g["v"])) / np.asarray(g["scale"])
+        med = {k: float(np.median([st[k] for st in stages])) for k in stages[0]}
+        out[prec] = {
+            "ms_median": float(np.median(tot)),
+            "nnz_per_s": len(val) / (float(np.median(tot)) / 1000.0),
+            "slice_ms": med,
+            "gram_kernel": {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": tf / FP64_PEAK_TFLOPS, "launches": k_n, "kernel_ms": k_ms / k_n,
+                            "algo_flops_per_launch": k_flops / k_n, "algo_bytes_per_launch": k_bytes / k_n},
+            "x2_dtype": "f64" if gs.x2_dtype == torch.float64 else "f32",
+            "error_vs_oracle": {"x2_max": float(np.max(ex)), "x2_median": float(np.median(ex)),
+                                "gram_max": float(np.max(eg)), "gram_median": float(np.median(eg)),
+                                "wnorm2_rel": abs(gs.wnorm2 - gold["norm2"]) / gold["norm2"],
+                                "samples": len(ex), "scales": "x2: sum |c R_1[a, g]|; gram: sqrt(G_qq G_q2q2)"},
+        }
+        del gs
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     args = _parse()
     if args.calibrate_copy:
@@ -213,7 +348,7 @@ def main():
     side = torch.cuda.Stream()
     main = torch.cuda.current_stream()
 
-    def step():
+    def step(precision):
         ci = tts.matrix_to_tensor(*matrix) if matrix is not None else gi
         box = {}
 
@@ -229,9 +364,9 @@ def main():
             th.start()
         try:
             if args.method == "fasttt":
-                tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p, precision=args.precision)
+                tt = tts.fasttt_decompose(ci, gv, dims, eps, p=args.p, precision=precision)
             else:
-                tt = tts.decompose(ci, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
+                tt = tts.decompose(ci, gv, dims, eps, precision=precision, dynamic_delta=args.dynamic_delta,
                                    key_bits=args.key_bits)
         finally:
             if th is not None:
@@ -248,8 +383,22 @@ def main():
         main.wait_stream(side)
         return tt, y, grads
 
+    def timed(precision, steps):
+        times, dec_ms, stage = [], [], []
+        t_all0 = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            tt, y, grads = step(precision)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            dec_ms.append(tt.times_ms["total"])
+            stage.append(tt.times_ms)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t_all0
+        return tt, t_all, times, dec_ms, stage
+
     for _ in range(args.warmup):
-        step()
+        step(args.precision)
     torch.cuda.synchronize()
     from paper_1908_02721_amd import _lib
 
@@ -260,7 +409,7 @@ def main():
         for fam in FAMILY_BOUND:
             _lib.kernel_timer_start(fam)
             for _ in range(2):
-                step()
+                step(args.precision)
             torch.cuda.synchronize()
             ms, n, _, _ = _lib.kernel_timer_read()
             _lib.kernel_timer_start(None)
@@ -268,21 +417,12 @@ def main():
                 best = (ms, fam)
         family = best[1]
     _lib.kernel_timer_start(family)
-    times = []
-    dec_ms = []
-    t_all0 = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        tt, y, grads = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        dec_ms.append(tt.times_ms["total"])
-    torch.cuda.synchronize()
-    t_all = time.perf_counter() - t_all0
+    tt, t_all, times, dec_ms, stage = timed(args.precision, args.steps)
     k_ms, k_n, k_bytes, k_flops = _lib.kernel_timer_read()
     _lib.kernel_timer_start(None)
     ms_per_step = 1000.0 * t_all / args.steps
     value = nnz / (t_all / args.steps)
+    stage_med = {k: float(np.median([st[k] for st in stage])) for k in stage[0]}
 
     out = {
         "metric": METRIC,
@@ -304,7 +444,7 @@ def main():
                    "ranks": tt.ranks},
         "decompose_ms_median": float(np.median(dec_ms)),
         "decompose_nnz_per_s": nnz / (float(np.median(dec_ms)) / 1000.0),
-        "stage_ms": tt.times_ms,
+        "stage_ms": stage_med,
         "step_ms_min": 1000.0 * min(times),
         "step_ms_median": 1000.0 * float(np.median(times)),
     }
@@ -331,15 +471,44 @@ def main():
                            "kernel": family, "launches_per_step": k_n / args.steps,
                            "kernel_ms_per_step": k_ms / args.steps,
                            "algo_bytes_per_launch": k_bytes / k_n, "algo_flops_per_launch": k_flops / k_n}
+        if family == "jacobi":
+            out["roofline"]["flops_note"] = "per launch: one sweep's flops times the sweeps the launch reported"
         if family in SINGLE_WORKGROUP:
             out["roofline"]["single_workgroup"] = True
             out["roofline"]["frac_of_one_cu"] = achieved / (peak / NUM_CU)
+    if args.method == "cps":
+        # the sparse stage (ingest, sort, every level) against HBM: algorithmic bytes over
+        # its time, against the spec and against a device copy measured here
+        b_alg = sparse_alg_bytes(nnz, len(dims), tt.level_sizes())
+        t_sparse = stage_med["ingest"] + stage_med["sort"] + stage_med["sparse_levels"]
+        gbps = b_alg / (t_sparse / 1000.0) / 1e9
+        cp = copy_gbps()
+        out.setdefault("roofline", {})["sparse_hbm"] = {
+            "bound": "hbm", "algo_bytes": b_alg, "t_ms": t_sparse, "achieved": gbps, "unit": "GB/s",
+            "peak": HBM_PEAK_GBS, "frac": gbps / HBM_PEAK_GBS, "copy_GBps": cp, "frac_of_copy": gbps / cp,
+            "level_sizes": tt.level_sizes()}
+    mixed_tt = None
+    if args.precision == "fp64" and not args.no_mixed:
+        # the precision form on the same workload: FP32 contractions, FP64 Grams/R/SVD
+        step("fp32")
+        torch.cuda.synchronize()
+        mixed_tt, m_all, m_times, m_dec, m_stage = timed("fp32", args.steps)
+        out["mixed"] = {"precision": "fp32", "value": nnz / (m_all / args.steps), "unit": "nnz/s",
+                        "ms_per_step": 1000.0 * m_all / args.steps,
+                        "decompose_ms_median": float(np.median(m_dec)),
+                        "decompose_nnz_per_s": nnz / (float(np.median(m_dec)) / 1000.0),
+                        "stage_ms": {k: float(np.median([st[k] for st in m_stage])) for k in m_stage[0]},
+                        "ranks": mixed_tt.ranks,
+                        "bf16": "not run: this workload's eps is below bfloat16's resolution (see c4_slice)"}
+    if not args.no_slice and args.method == "cps":
+        out["c4_slice"] = c4_slice_leg()
     if not args.no_cpu_baseline:
         cores_host = [c.cpu().numpy() for c in tt.cores]
-        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(idx, val, dims, eps, args.cpu_sample,
-                                                                   cores_host, args.precision,
-                                                                   dynamic=args.dynamic_delta, key_bits=args.key_bits,
-                                                                   method=args.method, p=args.p)
+        out["cpu_baseline"], out["error_vs_oracle"], res = cpu_baseline(
+            idx, val, dims, eps, args.cpu_sample, cores_host, args.precision, dynamic=args.dynamic_delta,
+            key_bits=args.key_bits, method=args.method, p=args.p)
+        if mixed_tt is not None:
+            out["mixed"]["error_vs_oracle"] = error_vs_oracle(res, [c.cpu().numpy() for c in mixed_tt.cores], "fp32")
     print(json.dumps(out), flush=True)
 
 

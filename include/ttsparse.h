@@ -291,6 +291,11 @@ tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, co
                        const int32_t** g, const double** s, const int64_t** n_colptr,
                        const int32_t** n_row, const double** n_val);
 
+/* Sizes of level k (1..d-1) of the sparse stage, kept without keep_intermediates:
+   sizes[0] = number of unfolding columns (nnz_{k+1}, the entries of level k+1),
+   sizes[1] = beta_k, sizes[2] = nnz(N_k).  TT_ERR_ARG for a fiber-trie result. */
+tt_status tt_get_level_sizes(tt_result r, int32_t k, int64_t* sizes);
+
 /* Release a result (NULL is ignored). */
 void tt_free(tt_result r);
 

@@ -130,6 +130,16 @@ class TT:
         _lib.check(L.tt_get_bond_delta(self._h, b, ctypes.byref(x)))
         return x.value
 
+    def level_sizes(self):
+        """Per level k = 1..d-1: (columns = nnz_{k+1}, beta_k, nnz(N_k))."""
+        L = _lib.load()
+        out = []
+        for k in range(1, self.d):
+            sz = (ctypes.c_int64 * 3)()
+            _lib.check(L.tt_get_level_sizes(self._h, k, sz))
+            out.append(tuple(int(x) for x in sz))
+        return out
+
     def level(self, k: int):
         """Level k (1..d-1) of the sparse stage (needs keep_intermediates=True)."""
         L = _lib.load()

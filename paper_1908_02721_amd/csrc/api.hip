@@ -981,6 +981,22 @@ tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, co
   return TT_OK;
 }
 
+tt_status tt_get_level_sizes(tt_result r, int32_t k, int64_t* sizes) {
+  if (!r || !sizes || k < 1 || k >= r->d) {
+    set_error("result, sizes or k invalid");
+    return TT_ERR_ARG;
+  }
+  if (r->lev.size() < static_cast<size_t>(k)) {
+    set_error("no sparse-stage levels in this result (fiber-trie FastTT)");
+    return TT_ERR_ARG;
+  }
+  const LevelData& L = r->lev[k - 1];
+  sizes[0] = L.ncols;
+  sizes[1] = L.beta;
+  sizes[2] = L.nnz_n;
+  return TT_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
@@ -997,6 +1013,10 @@ struct TimerState {
   std::vector<hipEvent_t> pool;
   double bytes = 0.0, flops = 0.0;
   int64_t launches = 0;
+  // launches whose flops scale with a device count: (flops per unit, slot in dcount)
+  std::vector<std::pair<double, int>> per_count;
+  int32_t* dcount = nullptr;  // device copies of the counts (timer-owned)
+  int dcount_cap = 0;
 };
 TimerState& timer_state() {
   static TimerState* t = new TimerState();
@@ -1026,6 +1046,12 @@ KTimer::KTimer(const char* family, hipStream_t s, double bytes, double flops) {
   t.bytes += bytes;
   t.flops += flops;
   t.launches += 1;
+  flops_ = flops;
+}
+
+void KTimer::flops_per_count(const int32_t* dev_count) {
+  if (slot_ < 0 || !dev_count) return;
+  count_ = dev_count;
 }
 
 KTimer::~KTimer() {
@@ -1033,6 +1059,22 @@ KTimer::~KTimer() {
   TimerState& t = timer_state();
   std::lock_guard<std::mutex> g(t.mu);
   if (slot_ < static_cast<int>(t.ev.size())) (void)hipEventRecord(t.ev[slot_].second, s_);
+  if (count_) {
+    // keep a copy of the count, stream-ordered after the launch, for the read
+    if (!t.dcount) {
+      void* p = nullptr;
+      if (hipMalloc(&p, sizeof(int32_t) * 65536) == hipSuccess) {
+        t.dcount = static_cast<int32_t*>(p);
+        t.dcount_cap = 65536;
+      }
+    }
+    const int k = static_cast<int>(t.per_count.size());
+    if (t.dcount && k < t.dcount_cap &&
+        hipMemcpyAsync(t.dcount + k, count_, sizeof(int32_t), hipMemcpyDeviceToDevice, s_) == hipSuccess) {
+      t.flops -= flops_;
+      t.per_count.emplace_back(flops_, k);
+    }
+  }
 }
 
 }  // namespace tts
@@ -1047,6 +1089,7 @@ extern "C" tt_status tt_kernel_timer_start(const char* family) {
   t.ev.clear();
   t.bytes = t.flops = 0.0;
   t.launches = 0;
+  t.per_count.clear();
   t.family = family ? family : "";
   return TT_OK;
 }
@@ -1062,9 +1105,17 @@ extern "C" tt_status tt_kernel_timer_read(double* total_ms, int64_t* launches, d
     if (hipEventElapsedTime(&x, p.first, p.second) != hipSuccess) return TT_ERR_DEVICE;
     ms += x;
   }
+  double flops = t.flops;
+  if (!t.per_count.empty()) {
+    std::vector<int32_t> cnt(t.per_count.size());
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(cnt.data(), t.dcount, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return TT_ERR_DEVICE;
+    for (size_t i = 0; i < cnt.size(); ++i) flops += t.per_count[i].first * cnt[t.per_count[i].second];
+  }
   if (total_ms) *total_ms = ms;
   if (launches) *launches = t.launches;
   if (algo_bytes) *algo_bytes = t.bytes;
-  if (algo_flops) *algo_flops = t.flops;
+  if (algo_flops) *algo_flops = flops;
   return TT_OK;
 }

@@ -104,10 +104,15 @@ class KTimer {
   ~KTimer();
   KTimer(const KTimer&) = delete;
   KTimer& operator=(const KTimer&) = delete;
+  // The launch's flops are `flops` times the int32 the launch leaves at dev_count
+  // (e.g. the sweeps an iteration ran), read when the timer is read.  Null: fixed.
+  void flops_per_count(const int32_t* dev_count);
 
  private:
   int slot_ = -1;
   hipStream_t s_ = nullptr;
+  double flops_ = 0.0;
+  const int32_t* count_ = nullptr;
 };
 
 inline unsigned grid_for(size_t n, unsigned block) {

@@ -49,6 +49,11 @@ struct SvdPart {
 };
 void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,
                    hipStream_t s);
+// Host check after a Jacobi SVD's read-back (info = the int32[4] of jacobi_svd, sigma
+// its n singular values, rows the matrix's rows): TT_ERR_NONFINITE for a non-finite
+// singular value; TT_ERR_DEVICE when the sweep cap stopped the iteration while a
+// rotated product was still above round-off, rows u ||A||_F^2.
+void svd_check(const int32_t info[4], const double* sigma, int n, int rows);
 
 // Rounds the exact TT.  Records `mid` on the stream between the QR sweep and the
 // truncated-SVD sweep.

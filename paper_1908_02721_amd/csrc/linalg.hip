@@ -2,6 +2,7 @@
 #include "linalg.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "prim.hpp"
 
@@ -1349,7 +1350,9 @@ __global__ __launch_bounds__(NT) void k_flip_q(const double* __restrict__ A, int
 template <int NTH, int GW>
 __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int rows, int c, int lda,
                                                 double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
-                                                int use_lds) {
+                                                int use_lds, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   extern __shared__ double sm[];
   __shared__ int rotated;
   double* A = Ag;
@@ -1376,7 +1379,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
   // a column pair counts as orthogonal when |a_p . a_q| <= rows * eps * ||a_p|| ||a_q||,
   // the rounding level of the computed dot product itself
   const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+  int nsw_ = 0, conv_ = 0;
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
@@ -1413,6 +1418,7 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
         if (a == 0.0 || b == 0.0) continue;
         if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
         double cs, sn;
+        if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
         jacobi_rotation(a, b, g, &cs, &sn);
         for (int i = gl; i < rows; i += GW) {
           const double x = ap[i], y = aq[i];
@@ -1430,7 +1436,10 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   // column norms
@@ -1453,6 +1462,13 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
       Vg[i + static_cast<size_t>(j) * ldv] = V[i + static_cast<size_t>(j) * lv];
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
+  }
 }
 
 // One-sided Jacobi for matrices whose A fits in LDS but A and V together do not
@@ -1462,7 +1478,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi(double* __restrict__ Ag, int row
 // the arithmetic; the group sums are DPP row reductions.
 template <int NTH, int GW, int VT>
 __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int rows, int c, int lda,
-                                                   double* __restrict__ V, int ldv, double* __restrict__ sigma) {
+                                                   double* __restrict__ V, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   extern __shared__ double A[];  // rows x c, column-major, leading dimension rows
   __shared__ int rotated;
   for (long long e = threadIdx.x; e < static_cast<long long>(rows) * c; e += NTH) {
@@ -1478,7 +1496,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
   const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
   const int N = c + (c & 1);
   const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+  int nsw_ = 0, conv_ = 0;
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
@@ -1520,6 +1540,7 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
         if (a == 0.0 || b == 0.0) continue;
         if (!(fabs(g) > tol * sqrt(a) * sqrt(b))) continue;
         double cs, sn;
+        if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
         jacobi_rotation(a, b, g, &cs, &sn);
 #pragma unroll
         for (int t = 0; t < VT; ++t) {
@@ -1550,7 +1571,10 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   for (int j = grp; j < c; j += NG) {
@@ -1566,6 +1590,13 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
     const int i = static_cast<int>(e % rows), j = static_cast<int>(e / rows);
     Ag[i + static_cast<size_t>(j) * lda] = A[e];
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
+  }
 }
 
 // The same Jacobi in two phases for c <= 138 (when V alone fits in LDS): the sweeps
@@ -1576,7 +1607,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi_lv(double* __restrict__ Ag, int 
 template <int NTH, int GW, int VT>
 __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int rows, int c, int lda,
                                                     double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
-                                                    double2* __restrict__ rot, int max_sweeps) {
+                                                    double2* __restrict__ rot, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   extern __shared__ double sm[];  // A (rows x c), later V (c x c)
   __shared__ int rotated, nsw;
   double* A = sm;
@@ -1602,7 +1635,9 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
     *pp = min(p, q);
     *qq = max(p, q);
   };
+  int nsw_ = 0, conv_ = 0;
   for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
@@ -1633,6 +1668,7 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
           b = group_sum<GW>(b);
           g = group_sum<GW>(g);
           if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
+            if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
             jacobi_rotation(a, b, g, &cs, &sn);
 #pragma unroll
             for (int t = 0; t < VT; ++t) {
@@ -1650,7 +1686,10 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
       __syncthreads();
     }
     if (threadIdx.x == 0) nsw = sweep + 1;
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   __syncthreads();
@@ -1718,6 +1757,13 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
     const int i = static_cast<int>(e % c), j = static_cast<int>(e / c);
     Vg[i + static_cast<size_t>(j) * ldv] = V[e];
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
+  }
 }
 
 // One-sided Jacobi with A and V held in registers, for c <= 16 VT columns of at most
@@ -1734,7 +1780,10 @@ __global__ __launch_bounds__(NTH) void k_jacobi_log(double* __restrict__ Ag, int
 template <int VT>
 __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int rows, int c, int lda,
                                                    double* __restrict__ Vg, int ldv, double* __restrict__ sigma,
-                                                   int max_sweeps) {
+                                                   int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
+  __syncthreads();
   constexpr int GW = 16;
   constexpr int SL = 2 * VT * GW;   // doubles per slot: an A column, then its V column
   extern __shared__ double slot[];  // [H][SL]
@@ -1754,7 +1803,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int
     vx[t] = (ix < c && i == ix) ? 1.0 : 0.0;  // the padding column (index c) stays zero
     vy[t] = (iy < c && i == iy) ? 1.0 : 0.0;
   }
+  int nsw_ = 0, conv_ = 0;
   for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int st = 0; st < N; ++st) {
@@ -1771,6 +1822,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int
         group_sum3<GW>(a, b, g);
         if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           double cs, sn;
+          if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
           jacobi_rotation(a, b, g, &cs, &sn);
 #pragma unroll
           for (int t = 0; t < VT; ++t) {
@@ -1833,7 +1885,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int
     }
     const int any = rotated;
     __syncthreads();
-    if (!any) break;
+    if (!any) {
+      conv_ = 1;
+      break;
+    }
   }
   if (act) {
     double sa = 0.0, sb = 0.0, dummy = 0.0;
@@ -1856,6 +1911,13 @@ __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int
       }
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
+  }
 }
 
 // One-sided cyclic Jacobi (round-robin pair order) for c <= 64 columns of at most
@@ -1865,7 +1927,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_oe(double* __restrict__ Ag, int
 // test as in k_jacobi.
 template <int GW, int RPL>
 __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag, int rows, int c, int lda,
-                                                        double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+                                                        double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   constexpr int NTH = 32 * GW;
   constexpr int VPL = (64 + GW - 1) / GW;
   extern __shared__ double sm[];
@@ -1887,7 +1951,9 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
   const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
   const int N = c + (c & 1);  // players (a virtual empty column when c is odd)
   const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+  int nsw_ = 0, conv_ = 0;
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int rd = 0; rd < N - 1; ++rd) {
@@ -1931,6 +1997,7 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
         }
         if (a != 0.0 && b != 0.0 && fabs(g) > tol * sqrt(a) * sqrt(b)) {
           double cs, sn;
+          if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
           jacobi_rotation(a, b, g, &cs, &sn);
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
@@ -1962,7 +2029,10 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   for (int j = grp; j < c; j += NTH / GW) {
@@ -1981,6 +2051,13 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
     const int i = e % c, j = e / c;
     Vg[i + static_cast<size_t>(j) * ldv] = V[i + j * lv];
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
+  }
 }
 
 // One-sided Jacobi for c <= 64 columns of at most 64 rows: k_jacobi_reg with
@@ -1988,7 +2065,9 @@ __global__ __launch_bounds__(32 * GW) void k_jacobi_reg(double* __restrict__ Ag,
 // its 8 entries of a column as four 16-byte LDS accesses with no bounds tests, and
 // the group's dot products reduced with DPP moves.
 __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int rows, int c, int lda,
-                                                  double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+                                                  double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   constexpr int GW = 8, NTH = 256, LD = 64;
   extern __shared__ double2 sm16[];  // 16-byte aligned: columns are read as double2
   __shared__ int rotated;
@@ -2014,7 +2093,9 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
   const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
   const int N = c + (c & 1);
   const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80 && N > 1; ++sweep) {
+  int nsw_ = 0, conv_ = 0;
+  for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     // round-robin positions of this group's pair, advanced by one (mod N - 1) per
@@ -2054,6 +2135,7 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
         const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
         if (a != 0.0 && b != 0.0 && rot) {
           double cs, sn;
+          if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
           jacobi_rotation(a, b, g, &cs, &sn);
           double2* vp = reinterpret_cast<double2*>(V + static_cast<size_t>(p) * LD) + gl;
           double2* vq = reinterpret_cast<double2*>(V + static_cast<size_t>(q) * LD) + gl;
@@ -2075,7 +2157,10 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   for (int j = grp; j < c; j += NTH / GW) {
@@ -2090,6 +2175,13 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
     const int i = e % LD, j = e / LD;
     if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = A[e];
     if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
   }
 }
 
@@ -2107,7 +2199,9 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
 // as k_jacobi64.
 template <int NC>
 __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
-                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma) {
+                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
+  __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
+  if (threadIdx.x == 0) gmax_ = 0ull;
   constexpr int NTH = 256, LD = 64, GW = 512 / NC, UP = 32 / GW;
   static_assert(NC == 32 || NC == 64, "32 or 64 columns");
   __shared__ double2 sA[NC * LD / 2];  // 64 x NC, column-major (rows >= `rows` zero)
@@ -2133,7 +2227,9 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
   __syncthreads();
   const int grp = threadIdx.x / GW, gl = threadIdx.x % GW;
   const double tol = static_cast<double>(max(rows, 16)) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 80; ++sweep) {
+  int nsw_ = 0, conv_ = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    nsw_ = sweep + 1;
     if (threadIdx.x == 0) rotated = 0;
     bool any = false;
     for (int lh = (NC == 64 ? 5 : 4); lh >= 0; --lh) {
@@ -2177,6 +2273,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
         const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
         if (a != 0.0 && b != 0.0 && rot) {  // uniform within the group
           double cs, sn;
+          if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
           jacobi_rotation(a, b, g, &cs, &sn);
           if (!PRE_V) {
 #pragma unroll
@@ -2207,7 +2304,10 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
     }
     if (any && gl == 0) rotated = 1;
     __syncthreads();
-    if (!rotated) break;
+    if (!rotated) {
+      conv_ = 1;
+      break;
+    }
     __syncthreads();
   }
   for (int j = grp; j < c; j += NTH / GW) {
@@ -2222,6 +2322,13 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
     const int i = e % LD, j = e / LD;
     if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = A[e];
     if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
+    info[0] = nsw_;
+    info[1] = (nsw_ == 0 || conv_) ? 1 : 0;
+    const double gm = (nsw_ == 0 || conv_) ? 0.0 : __longlong_as_double(static_cast<long long>(gmax_));
+    *reinterpret_cast<double*>(info + 2) = gm;
   }
 }
 
@@ -2752,33 +2859,57 @@ void householder_extract_r(const double* A, int m, int n, int lda, double* R, in
   }
 }
 
-void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, hipStream_t s) {
+namespace {
+__global__ void k_set_info(int32_t* info, int32_t sweeps, int32_t converged) {
+  info[0] = sweeps;
+  info[1] = converged;
+  // the block kernel keeps no largest rotated product: unknown unless converged
+  *reinterpret_cast<double*>(info + 2) = converged ? 0.0 : __builtin_inf();
+}
+
+// Sweep cap of the Jacobi kernels: 80, or TTSPARSE_JACOBI_MAX_SWEEPS (1..80), which
+// exists to exercise the non-convergence path from the host.
+int jacobi_sweep_cap() {
+  static const int cap = [] {
+    const char* e = std::getenv("TTSPARSE_JACOBI_MAX_SWEEPS");
+    const int v = e ? std::atoi(e) : 0;
+    return (v >= 1 && v <= 80) ? v : 80;
+  }();
+  return cap;
+}
+}  // namespace
+
+void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s) {
   if (c <= 0) return;
+  const int ms = jacobi_sweep_cap();
   const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
   KTimer kt("jacobi", s, 8.0 * 2.0 * (static_cast<double>(rows) * c + static_cast<double>(c) * c),
-            // one sweep of rotations: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V)
+            // per sweep: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V); the
+            // timer multiplies it by the sweeps the launch reports in info[0]
             0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
+  kt.flops_per_count(info);
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
   if (c > 32 && c <= 64 && rows <= 64) {
-    k_jacobi64h<64><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    k_jacobi64h<64><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (c > 16 && c <= 32 && rows <= 64) {
-    k_jacobi64h<32><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma);
+    k_jacobi64h<32><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (c <= 64 && rows <= 64) {
-    k_jacobi64<<<1, 256, sizeof(double) * 128 * static_cast<size_t>(c), s>>>(A, rows, c, lda, V, ldv, sigma);
+    k_jacobi64<<<1, 256, sizeof(double) * 128 * static_cast<size_t>(c), s>>>(A, rows, c, lda, V, ldv, sigma, ms,
+                                                                               info);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (shm_odd <= 150 * 1024 && c <= 64 && rows <= 256) {
     if (rows <= 128)
-      k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+      k_jacobi_reg<16, 8><<<1, 512, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     else
-      k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma);
+      k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
@@ -2786,20 +2917,20 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   if (c > 64 && c <= 128 && rows <= 128) {
     const int H = (c + 1) / 2;
     k_jacobi_oe<8><<<1, 1024, sizeof(double) * 2 * 8 * 16 * static_cast<size_t>(H), s>>>(A, rows, c, lda, V, ldv,
-                                                                                         sigma, 80);
+                                                                                         sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
   // A in LDS with the rotations logged, then V in LDS: up to 138 columns
   if (shm > 150 * 1024 && c <= 138 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
-    constexpr int kMaxSweeps = 80;
+    constexpr int kMaxSweeps = 80;  // the rotation log holds this many sweeps
     const int N = c + (c & 1);
     const size_t lbytes = sizeof(double2) * static_cast<size_t>(kMaxSweeps) * (N - 1) * (N / 2);
     void* lg = cached_alloc(lbytes, s);
     if (!lg) fail(TT_ERR_NOMEM, "device allocation failed");
     const size_t lshm = sizeof(double) * std::max(static_cast<size_t>(rows) * c, static_cast<size_t>(c) * c);
     k_jacobi_log<1024, 16, 10><<<1, 1024, lshm, s>>>(A, rows, c, lda, V, ldv, sigma, static_cast<double2*>(lg),
-                                                      kMaxSweeps);
+                                                      std::min(ms, kMaxSweeps), info);
     TTS_LAUNCH_CHECK();
     cached_free(lg, lbytes, s);
     return;
@@ -2807,13 +2938,13 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   // A in LDS, V in global memory: up to 160 columns
   if (shm > 150 * 1024 && c <= 160 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
     k_jacobi_lv<1024, 16, 10><<<1, 1024, sizeof(double) * static_cast<size_t>(rows) * c, s>>>(A, rows, c, lda, V,
-                                                                                             ldv, sigma);
+                                                                                             ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (shm <= 150 * 1024 || c <= 2 * BJ_B) {
     const int use_lds = shm <= 150 * 1024;
-    k_jacobi<BT, 16><<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds);
+    k_jacobi<BT, 16><<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
@@ -2827,7 +2958,9 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   int32_t* flag = static_cast<int32_t*>(cached_alloc(sizeof(int32_t), s));
   if (!flag) fail(TT_ERR_NOMEM, "device allocation failed");
   int32_t hflag = 1;
-  for (int sweep = 0; sweep < 60 && hflag; ++sweep) {
+  int sweeps = 0;
+  const int bcap = std::min(ms, 60);
+  for (int sweep = 0; sweep < bcap && hflag; ++sweep) {
     TTS_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     for (int rd = 0; rd < nb - 1; ++rd) {
       k_bjacobi_round<<<nb / 2, NT, bshm, s>>>(A, rows, c, lda, V, ldv, nb, rd, flag);
@@ -2835,10 +2968,15 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     }
     TTS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     TTS_HIP(hipStreamSynchronize(s));
+    sweeps = sweep + 1;
   }
   cached_free(flag, sizeof(int32_t), s);
   k_col_norms<<<c, NT, 0, s>>>(A, rows, c, lda, sigma);
   TTS_LAUNCH_CHECK();
+  if (info) {
+    k_set_info<<<1, 1, 0, s>>>(info, sweeps, hflag ? 0 : 1);
+    TTS_LAUNCH_CHECK();
+  }
 }
 
 void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s) {

@@ -73,9 +73,13 @@ void householder_form_q(const double* A, int m, int p, int lda, const double* ta
 void householder_extract_r(const double* A, int m, int n, int lda, double* R, int ldr, double* Q, int ldq,
                            hipStream_t s);
 
-// One-sided Jacobi SVD of the c x c matrix A (in place: columns become u_j sigma_j),
-// V (c x c) accumulates the rotations.  sigma[j] = ||A[:, j]||.
-void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, hipStream_t s);
+// One-sided Jacobi SVD of the rows x c matrix A (in place: columns become u_j sigma_j),
+// V (c x c) accumulates the rotations.  sigma[j] = ||A[:, j]||.  info (device int32[4],
+// 8-byte aligned, may be null) receives the sweeps run, 1 if the last sweep rotated
+// nothing (converged) or 0 if the sweep cap stopped it, and in info[2..3] the largest
+// |a_p^T a_q| rotated in the last sweep (a double; 0 when converged).
+void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info,
+                hipStream_t s);
 
 // Copy / transpose helpers.
 void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s);

@@ -26,6 +26,7 @@
 // singular vector positive and merges V*Sigma into the left neighbour.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -101,6 +102,25 @@ struct EventPair {
 
 }  // namespace
 
+void svd_check(const int32_t info[4], const double* sigma, int n, int rows) {
+  double f2 = 0.0;
+  for (int j = 0; j < n; ++j) {
+    if (!std::isfinite(sigma[j])) fail(TT_ERR_NONFINITE, "a singular value of a bond factor is not finite");
+    f2 += sigma[j] * sigma[j];
+  }
+  if (info[1]) return;
+  // Stopped by the sweep cap.  Columns at the round-off floor can keep meeting the
+  // relative test |a^T b| > tol ||a|| ||b||; the factors are still accurate when
+  // every product rotated in the last sweep is at round-off relative to ||A||_F^2.
+  double gmax;
+  std::memcpy(&gmax, info + 2, sizeof(double));
+  const double floor2 = static_cast<double>(std::max(rows, 16)) * 0x1p-52 * f2;
+  if (gmax <= floor2) return;
+  fail(TT_ERR_DEVICE, "one-sided Jacobi SVD did not converge within " + std::to_string(info[0]) +
+                          " sweeps (largest rotated |a^T b| " + std::to_string(gmax / std::max(f2, 1e-300)) +
+                          " of ||A||_F^2)");
+}
+
 // CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
 // ok[0..3] (device) are set to 0 when a Cholesky factor breaks down or is too
 // ill-conditioned; nothing is read back here.
@@ -140,13 +160,15 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     Qb.reset(A, static_cast<size_t>(m) * c);
   }
   DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
-  DBuf<int32_t> dperm(A, cB), okq(A, 4);
+  DBuf<int32_t> dperm(A, cB), okq(A, 4), jinfo(A, 4);
   std::vector<double> sh(cB);
+  alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
   auto svd_of_bt = [&]() {
-    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), s);
+    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s);
     k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
     TTS_LAUNCH_CHECK();
     TTS_HIP(hipMemcpyAsync(sh.data(), sig.get(), sizeof(double) * cB, hipMemcpyDeviceToHost, s));
+    TTS_HIP(hipMemcpyAsync(hinfo, jinfo.get(), sizeof(hinfo), hipMemcpyDeviceToHost, s));
   };
   if (haveQ) {
     DBuf<double> R(A, static_cast<size_t>(c) * c);
@@ -167,6 +189,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     svd_of_bt();
     TTS_HIP(hipStreamSynchronize(s));
   }
+  svd_check(hinfo, sh.data(), cB, c);
   // the same stable non-ascending order as k_rank_desc
   std::vector<int32_t> perm(cB);
   std::iota(perm.begin(), perm.end(), 0);

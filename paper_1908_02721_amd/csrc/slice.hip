@@ -69,8 +69,6 @@ __host__ __device__ constexpr int tiles_per_item(int mt, int kind) {
   return (tiles_of(mt, kind) + gram_split(mt, kind) - 1) / gram_split(mt, kind);
 }
 
-__global__ void k_one(double* p) { *p = 1.0; }
-
 // X_1 (n_1 x beta_1, column-major): column b of N_1 (rows rho = i_1 since r_0 = 1)
 __global__ __launch_bounds__(NT) void k_slice_x1(const int64_t* __restrict__ colptr, int ncols,
                                                  const int32_t* __restrict__ row, const double* __restrict__ val,
@@ -297,23 +295,52 @@ __global__ __launch_bounds__(NT) void k_pair_emit(const int64_t* __restrict__ cp
   }
 }
 
+// One k-step of NTPW accumulator tiles, starting at tile (tr, tc) of a wave's run:
+// the fragments are read first, then the MFMA chain runs.  Tiles past the wave's nt
+// live ones repeat its last live tile (valid addresses; never written back).
+template <int MT, int NTPW>
+__device__ __forceinline__ void gram_kstep(const double* __restrict__ Ak, const double* __restrict__ Bk, dbl4* acc,
+                                           int tr, int tc, int nt, bool diag) {
+  // software pipeline of depth one: the next tile's fragments are read before this
+  // tile's MFMA is issued
+  double a0 = Ak[tr * 16], b0 = Bk[tc * 16];
+#pragma unroll
+  for (int u = 0; u < NTPW; ++u) {
+    double a1 = a0, b1 = b0;
+    if (u + 1 < NTPW) {
+      if (u + 1 < nt && ++tc == MT) {
+        ++tr;
+        tc = diag ? tr : 0;
+      }
+      a1 = Ak[tr * 16];
+      b1 = Bk[tc * 16];
+    }
+    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[u], 0, 0, 0);
+    a0 = a1;
+    b0 = b1;
+  }
+}
+
 // One work item of the Gram per workgroup: the m x m block (padded to W = 16 MT)
 // sum_k A_k B_k^T with A_k = w x_{b_k} and B_k = x_{b'_k} over the item's pairs, on
 // v_mfma_f64_16x16x4 (operand lanes: A[i][k] in lane i + 16k, B[k][j] in lane
-// j + 16k; accumulator register v of lane l holds row 4v + l/16, column l%16).  The
-// MT x MT output tiles are split into contiguous runs of TPW tiles over the 8
-// waves.  Pairs go through LDS 16 at a time (double-buffered), converted to FP64
-// (and A scaled by w) as they are staged; the next stage's loads are in flight
-// during this stage's MFMA.
-template <typename T, int MT>
+// j + 16k; accumulator register v of lane l holds row 4v + l/16, column l%16).
+// KIND 1 (off-diagonal blocks) takes all MT x MT tiles, KIND 0 (diagonal blocks) the
+// tiles on or above the diagonal, mirrored when written; an item's tiles are split
+// into contiguous runs of TPW over the 8 waves, each run a compile-time count so
+// that a k-step reads all its fragments ahead of an unbranched MFMA chain.  Pairs go
+// through LDS 16 at a time (double-buffered), converted to FP64 (and A scaled by w)
+// as they are staged by coalesced per-wave loads; the next stage's loads are in
+// flight during this stage's MFMA.
+template <typename T, int MT, int KIND>
 __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __restrict__ items,
                                                              const T* __restrict__ x2, int m,
                                                              const double* __restrict__ wblk,
                                                              const uint64_t* __restrict__ pairs,
                                                              double* __restrict__ gram, double* __restrict__ part) {
-  constexpr int W = 16 * MT, NU = (W + 63) / 64;
-  constexpr int TPI = tiles_per_item(MT, 1) > tiles_per_item(MT, 0) ? tiles_per_item(MT, 1) : tiles_per_item(MT, 0);
-  constexpr int TPW = (TPI + kGramWaves - 1) / kGramWaves;
+  constexpr int W = 16 * MT;
+  // accumulator tiles per wave; every item of a launch is of kind KIND
+  constexpr int TPW = (tiles_per_item(MT, KIND) + kGramWaves - 1) / kGramWaves;
   static_assert(TPW <= kTilesPerWave, "accumulator tiles per wave");
   extern __shared__ double lds[];
   double* SA = lds;                 // [2][kKC][W]
@@ -322,8 +349,11 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  // staging role: wave wv stages pairs wv + kGramWaves * h of each stage
+  // staging: wave wv stages pairs wv + kGramWaves h of each stage, lane a of each
+  // vector (coalesced); side A is stored scaled by the pair's weight, side B as is
+  // (a diagonal item pairs a block with itself)
   constexpr int PPW = kKC / kGramWaves;
+  constexpr int NU = (W + 63) / 64;
   static_assert(PPW * kGramWaves == kKC, "whole pairs per wave");
   T xa[PPW][NU], xb[PPW][NU];
   double wa[PPW];
@@ -334,7 +364,7 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
       const bool live = p < it.nk;
       int64_t ba = 0, bb = 0;
       if (live) {
-        if (it.kind == 0) {
+        if (KIND == 0) {
           ba = bb = it.start + p;
         } else {
           const uint64_t pr = pairs[it.start + p];
@@ -348,7 +378,7 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
         const int a = lane + 64 * u;
         const bool ok = live && a < m;
         xa[h][u] = ok ? x2[static_cast<size_t>(ba) * m + a] : T(0);
-        xb[h][u] = (ok && it.kind != 0) ? x2[static_cast<size_t>(bb) * m + a] : T(0);
+        if (KIND != 0) xb[h][u] = ok ? x2[static_cast<size_t>(bb) * m + a] : T(0);
       }
     }
   };
@@ -363,7 +393,7 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
         if (a < W) {
           const double x = static_cast<double>(xa[h][u]);
           A[a] = wa[h] * x;
-          B[a] = it.kind == 0 ? x : static_cast<double>(xb[h][u]);  // a diagonal block pairs a block with itself
+          B[a] = KIND == 0 ? x : static_cast<double>(xb[h][u]);
         }
       }
     }
@@ -373,28 +403,23 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
   for (int u = 0; u < TPW; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
   // this wave's tiles: positions tile0 + wv TPW + u of the item's tile order (row-major
   // over all tiles, or over the upper tiles of a diagonal block)
-  const int ntiles = tiles_of(MT, it.kind);
-  const int t1 = min(ntiles, it.tile0 + tiles_per_item(MT, it.kind));
-  int toff_a[TPW], toff_b[TPW];
-  bool tlive[TPW];
-#pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    const int t = it.tile0 + wv * TPW + u;
-    tlive[u] = t < t1;
-    int tr = 0, tc = 0;
-    if (it.kind == 0) {
-      int rem = tlive[u] ? t : 0;
-      while (rem >= MT - tr) {
-        rem -= MT - tr;
-        ++tr;
-      }
-      tc = tr + rem;
-    } else {
-      tr = t / MT;
-      tc = t - tr * MT;
+  // this wave's tiles: positions tile0 + wv TPW + u of the item's tile order (row-major
+  // over all tiles, or over the upper tiles of a diagonal block): its first tile
+  // (tr0, tc0) and count nt; later tiles step along the row, then to the next row
+  const int ntiles = tiles_of(MT, KIND);
+  const int tfirst = it.tile0 + wv * TPW;
+  const int nt = max(0, min(TPW, min(ntiles, it.tile0 + tiles_per_item(MT, KIND)) - tfirst));
+  int tr0 = 0, tc0 = 0;
+  if (KIND == 0) {
+    int rem = nt > 0 ? tfirst : 0;
+    while (rem >= MT - tr0) {
+      rem -= MT - tr0;
+      ++tr0;
     }
-    toff_a[u] = tr * 16;
-    toff_b[u] = tc * 16;
+    tc0 = tr0 + rem;
+  } else if (nt > 0) {
+    tr0 = tfirst / MT;
+    tc0 = tfirst - tr0 * MT;
   }
   const int nst = (it.nk + kKC - 1) / kKC;
   load(0);
@@ -410,25 +435,28 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
     for (int ks = 0; ks < kKC; ks += 4) {
       const double* Ak = A + (ks + lk) * W + li;
       const double* Bk = B + (ks + lk) * W + li;
-#pragma unroll
-      for (int u = 0; u < TPW; ++u)
-        if (tlive[u]) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ak[toff_a[u]], Bk[toff_b[u]], acc[u], 0, 0, 0);
+      if (nt > 0) gram_kstep<MT, TPW>(Ak, Bk, acc, tr0, tc0, nt, KIND == 0);
     }
     if (st + 1 < nst) store(buf ^ 1);
     __syncthreads();
   }
   double* dst = (it.to_part ? part : gram) + it.dst;
+  int tr = tr0, tc = tc0;
 #pragma unroll
   for (int u = 0; u < TPW; ++u) {
-    if (!tlive[u]) continue;
-    const bool mirror = it.kind == 0 && toff_a[u] != toff_b[u];
+    if (u >= nt) continue;
+    const bool mirror = KIND == 0 && tr != tc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int r = toff_a[u] + 4 * v + lk, c = toff_b[u] + li;
+      const int r = tr * 16 + 4 * v + lk, c = tc * 16 + li;
       if (r < m && c < m) {
         dst[static_cast<size_t>(r) * m + c] = acc[u][v];
         if (mirror) dst[static_cast<size_t>(c) * m + r] = acc[u][v];
       }
+    }
+    if (++tc == MT) {
+      ++tr;
+      tc = KIND == 0 ? tr : 0;
     }
   }
 }
@@ -560,44 +588,57 @@ void run_gram(Allocator* A, const SliceInput& in, SliceOut& o, const double* wbl
   DBuf<ReduceItem> dreds(A, std::max<size_t>(reds.size(), 1));
   DBuf<int64_t> dzeros(A, std::max<size_t>(zeros.size(), 1));
   DBuf<double> part(A, std::max<int64_t>(nparts, 1) * mm);
-  if (!items.empty())
-    TTS_HIP(hipMemcpyAsync(ditems.get(), items.data(), sizeof(GramItem) * items.size(), hipMemcpyHostToDevice, s));
   if (!reds.empty())
     TTS_HIP(hipMemcpyAsync(dreds.get(), reds.data(), sizeof(ReduceItem) * reds.size(), hipMemcpyHostToDevice, s));
   if (!zeros.empty())
     TTS_HIP(hipMemcpyAsync(dzeros.get(), zeros.data(), sizeof(int64_t) * zeros.size(), hipMemcpyHostToDevice, s));
   const T* x2 = reinterpret_cast<const T*>(o.x2.get());
+  // diagonal items first (they are the largest), then the off-diagonal ones; one
+  // launch per kind so that each has its own accumulator count per wave
+  const size_t ndiag = static_cast<size_t>(
+      std::stable_partition(items.begin(), items.end(), [](const GramItem& x) { return x.kind == 0; }) -
+      items.begin());
+  if (!items.empty())
+    TTS_HIP(hipMemcpyAsync(ditems.get(), items.data(), sizeof(GramItem) * items.size(), hipMemcpyHostToDevice, s));
   if (!items.empty()) {
     KTimer kt("slice_gram", s,
               static_cast<double>(sizeof(T)) * o.nblocks * m + 8.0 * static_cast<double>(n2) * (n2 + 1) / 2 * mm,
               flops);
-    const unsigned g = static_cast<unsigned>(items.size());
-#define TTS_GRAM_CASE(MTV)                                                                                    \
-  case MTV:                                                                                                   \
-    k_slice_gram<T, MTV><<<g, kGramThreads, sizeof(double) * 4 * kKC * 16 * MTV, s>>>(ditems.get(), x2,       \
-                                                                                     static_cast<int>(m), wblk, \
-                                                                                     pairs, o.gram.get(),      \
-                                                                                     part.get());              \
+    const size_t shm = sizeof(double) * 4 * kKC * 16 * static_cast<size_t>(MT);
+    for (int kind = 0; kind < 2; ++kind) {
+      const size_t first = kind == 0 ? 0 : ndiag, cnt = kind == 0 ? ndiag : items.size() - ndiag;
+      if (cnt == 0) continue;
+      const unsigned g = static_cast<unsigned>(cnt);
+      const GramItem* di = ditems.get() + first;
+#define TTS_GRAM_CASE(MTV)                                                                                      \
+  case MTV:                                                                                                     \
+    if (kind == 0)                                                                                              \
+      k_slice_gram<T, MTV, 0><<<g, kGramThreads, shm, s>>>(di, x2, static_cast<int>(m), wblk, pairs, o.gram.get(), \
+                                                           part.get());                                         \
+    else                                                                                                        \
+      k_slice_gram<T, MTV, 1><<<g, kGramThreads, shm, s>>>(di, x2, static_cast<int>(m), wblk, pairs, o.gram.get(), \
+                                                           part.get());                                         \
     break;
-    switch (MT) {
-      TTS_GRAM_CASE(1)
-      TTS_GRAM_CASE(2)
-      TTS_GRAM_CASE(3)
-      TTS_GRAM_CASE(4)
-      TTS_GRAM_CASE(5)
-      TTS_GRAM_CASE(6)
-      TTS_GRAM_CASE(7)
-      TTS_GRAM_CASE(8)
-      TTS_GRAM_CASE(9)
-      TTS_GRAM_CASE(10)
-      TTS_GRAM_CASE(11)
-      TTS_GRAM_CASE(12)
-      TTS_GRAM_CASE(13)
-      default:
-        fail(TT_ERR_TOO_LARGE, "bond-1 rank above 208");
-    }
+      switch (MT) {
+        TTS_GRAM_CASE(1)
+        TTS_GRAM_CASE(2)
+        TTS_GRAM_CASE(3)
+        TTS_GRAM_CASE(4)
+        TTS_GRAM_CASE(5)
+        TTS_GRAM_CASE(6)
+        TTS_GRAM_CASE(7)
+        TTS_GRAM_CASE(8)
+        TTS_GRAM_CASE(9)
+        TTS_GRAM_CASE(10)
+        TTS_GRAM_CASE(11)
+        TTS_GRAM_CASE(12)
+        TTS_GRAM_CASE(13)
+        default:
+          fail(TT_ERR_TOO_LARGE, "bond-1 rank above 208");
+      }
 #undef TTS_GRAM_CASE
-    TTS_LAUNCH_CHECK();
+      TTS_LAUNCH_CHECK();
+    }
   }
   if (!reds.empty()) {
     const unsigned gx = static_cast<unsigned>(std::min<int64_t>((mm + NT - 1) / NT, 64));
@@ -656,9 +697,13 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   if (m < 1) fail(TT_ERR_EMPTY, "bond-1 unfolding is zero");
   o.m = m;
   DBuf<double> V(A, static_cast<size_t>(n1) * n1), sig(A, n1);
-  jacobi_svd(Rg.get(), n1, n1, n1, V.get(), n1, sig.get(), s);
+  DBuf<int32_t> jinfo(A, 4);
+  jacobi_svd(Rg.get(), n1, n1, n1, V.get(), n1, sig.get(), jinfo.get(), s);
+  alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
+  TTS_HIP(hipMemcpyAsync(hinfo, jinfo.get(), sizeof(hinfo), hipMemcpyDeviceToHost, s));
   std::vector<double> hs;
   to_host(hs, sig.get(), n1, s);
+  svd_check(hinfo, hs.data(), n1, n1);
   std::vector<int32_t> perm(n1);
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) { return hs[x] > hs[y]; });

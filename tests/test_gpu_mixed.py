@@ -69,6 +69,15 @@ def test_mixed_laplacian(oracle_mod, precision):
     check_mixed(oracle_mod, idx, val, dims, 1e-10, "laplace L=5", precision)
 
 
+def test_mixed_laplacian_full_size_fp32(oracle_mod):
+    # the 1024 x 1024 grid (20 modes of size 4, 5,238,784 nonzeros): FP32 GPU against
+    # the FP64 oracle at eps = 1e-10; the gate is FP32's error plus eps
+    idx, val, dims, eps = synth.workload("laplace2d_qtt_L10")
+    tt, res, err = check_mixed(oracle_mod, idx, val, dims, eps, "laplace2d_qtt_L10", "fp32")
+    print(f"[mixed] laplace2d_qtt_L10 fp32 ranks {tt.ranks}, oracle {res.ranks}, error {err:.3e}", flush=True)
+    assert res.ranks == [1] + [3] * 9 + [2] + [4] * 8 + [3] + [1]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_mixed_random4d(oracle_mod, precision):
     idx, val, dims, eps = synth.workload("random4d_n20_nnz1k")

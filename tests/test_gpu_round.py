@@ -244,3 +244,31 @@ def test_tolerant_continuous_kron8d_full_size(oracle_mod):
     # the deflation accepts bases at the snapping level: no bond falls back to the
     # exact QR, which would carry all beta_k columns into the SVD sweep
     assert max(tt.qr_ranks) <= 64
+
+
+def test_jacobi_sweep_cap_reports_non_convergence():
+    # With the sweep cap forced to 1 from the host (TTSPARSE_JACOBI_MAX_SWEEPS, read
+    # once per process, hence a child process), a bond whose SVD needs more sweeps
+    # must fail with TT_ERR_DEVICE instead of returning unconverged factors.
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch, numpy as np\n"
+        "import paper_1908_02721_amd as tts\n"
+        "from paper_1908_02721_amd import synth\n"
+        "from paper_1908_02721_amd._lib import TTError\n"
+        "idx, val, dims = synth.random_sparse((6, 5, 4, 6), 200, 1)\n"
+        "gi = torch.from_numpy(idx).cuda(); gv = torch.from_numpy(val).cuda()\n"
+        "try:\n"
+        "    tts.decompose(gi, gv, dims, 1e-12)\n"
+        "    print('NO ERROR')\n"
+        "except TTError as e:\n"
+        "    print('ERROR', e.status, e)\n" % root)
+    env = dict(os.environ, TTSPARSE_JACOBI_MAX_SWEEPS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
+    assert "ERROR TT_ERR_DEVICE" in r.stdout and "did not converge" in r.stdout
