@@ -40,7 +40,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ttoracle.cpp")
-_LIB = os.path.join(_HERE, "libttoracle.so")
+# TTORACLE_LIB names another build of the same source (the sanitizer test loads an
+# ASan/UBSan build this way); the default is the in-tree library built by build().
+_LIB = os.environ.get("TTORACLE_LIB") or os.path.join(_HERE, "libttoracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -56,6 +58,8 @@ class OracleError(RuntimeError):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (-O2, single-threaded, strict IEEE)."""
+    if os.environ.get("TTORACLE_LIB"):
+        return _LIB  # a prebuilt variant (see above): never rebuilt here
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         cmd = ["g++", "-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
                "-Wall", "-Wextra", "-o", _LIB, _SRC]

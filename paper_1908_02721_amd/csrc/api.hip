@@ -2,7 +2,11 @@
 // result ownership.  Every step of the decomposition runs in the library's HIP
 // kernels; the host only sequences launches and reads back small counts.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -62,6 +66,28 @@ uint32_t bits_for(uint64_t n) {  // bits to hold values 0..n-1
 }  // namespace
 
 void fail(tt_status s, const std::string& msg) { throw Error{s, msg}; }
+
+bool log_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("TTSPARSE_LOG");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+void logf(const char* fmt, ...) {
+  if (!log_on()) return;
+  std::va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[ttsparse] ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  va_end(ap);
+}
+
+double host_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 // ---------------------------------------------------------------------------
 // Device block cache.  Blocks are kept per stream in size classes (four classes per
@@ -233,7 +259,9 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
   uint32_t nE = kept;
   R->lev.resize(d - 1);
   R->betas.assign(d + 1, 1);
+  logf("sparse stage: %u nonzeros kept of %u, %d modes", kept, nnz, d);
   for (int k = 1; k <= d - 1; ++k) {
+    const double t_level = host_ms();
     const int kidx = k;           // first suffix mode, 0-based
     const int sh = static_cast<int>(mi.bits[k - 1]);
     const bool level1 = (k == 1);
@@ -391,6 +419,8 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
       ea.last_core = R->last_exact.get();
     }
     launch_emit_next(ea, mi, s);
+    logf("level %d: %u entries, %u columns, beta %u, nnz(N_k) %u, %.3f ms (host)", k, nE, ncols, beta, nnz_n,
+         host_ms() - t_level);
     if (!ea.last) {
       ekey = std::move(nk);
       erho = std::move(nr);

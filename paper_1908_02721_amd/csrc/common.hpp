@@ -115,6 +115,13 @@ class KTimer {
   const int32_t* count_ = nullptr;
 };
 
+// Progress log on stderr, on when the environment has TTSPARSE_LOG=1 (read once):
+// per level of the sparse stage and per bond of the sweeps, sizes, ranks and host
+// milliseconds (each line is written after the step's own read-back).
+bool log_on();
+void logf(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+double host_ms();  // monotonic host clock in milliseconds
+
 inline unsigned grid_for(size_t n, unsigned block) {
   size_t g = (n + block - 1) / block;
   return static_cast<unsigned>(g == 0 ? 1 : g);

@@ -255,13 +255,11 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   // Acceptance threshold of a deflated basis.  With the tolerant parallel test the
   // exact sparse TT itself carries up to snap_rel ||A||_F of rounding (its canonical
   // values are rounded to key_bits fraction bits), so directions at that level are
-  // dropped too, still within 1% of the bond's truncation threshold.  With
-  // reduced-precision contractions the carried factor W' = Q^T X is only accurate to
-  // the operands' unit roundoff u, so the threshold is raised to 64 u ||A||_F (the
-  // residual itself is always formed in FP64).
-  double tau = std::min(1e-2 * in.delta, std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
-  if (prec == TT_FP32) tau = std::max(tau, 64.0 * 0x1p-24 * in.norm);
-  if (prec == TT_BF16_FP32ACC) tau = std::max(tau, 64.0 * 0x1p-8 * in.norm);
+  // dropped too, still within 1% of the bond's truncation threshold.  The residual
+  // measures what the basis leaves out, X - Q Q^T X, with Q^T X formed in FP64 in
+  // every precision, so the same threshold certifies the deflation in the reduced
+  // modes; their FP32/BF16 contraction of the carried factor adds its own rounding.
+  const double tau = std::min(1e-2 * in.delta, std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
   std::vector<int64_t> r(d + 1, 1);
   std::vector<DBuf<char>> cores(d);
 
@@ -300,13 +298,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   struct Pending {
     bool active = false;
     int k = 0, rows = 0, cols = 0;
-    DBuf<double> X, Q, e2;
+    DBuf<double> X, Q, e2, W64;
     DBuf<int32_t> ok;
   } pend;
   int32_t pok[4];
   double pe2 = 0.0;
   auto pending_accepted = [&]() { return pok[1] && pok[2] && pok[3] && pe2 <= tau * tau; };
   int k = 1;
+  double t_bond = host_ms();
   while (k <= d - 1) {
     const int nk = n[k - 1];
     const int rows = rp * nk, cols = beta[k];
@@ -335,12 +334,17 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     if (tau > 0.0 || pend.active) TTS_HIP(hipStreamSynchronize(s));
     if (pend.active) {
       pend.active = false;
+      logf("QR bond %d: deflation to rank %lld %s (residual %.3e ||A||, threshold %.3e ||A||)", pend.k,
+           static_cast<long long>(r[pend.k]), pending_accepted() ? "accepted" : "rejected, exact QR",
+           std::sqrt(pe2) / in.norm, tau / in.norm);
       if (!pending_accepted()) {
         exact_bond(pend.k, pend.X, pend.rows, pend.cols);
         k = pend.k + 1;  // this bond again, from the exact factor
         continue;
       }
     }
+    logf("QR bond %d: %d x %d, %.3f ms (host)", k, rows, cols, host_ms() - t_bond);
+    t_bond = host_ms();
     // fixed-rank truncation keeps min(max_rank, #nonzero sigma): deflating below
     // max_rank would drop numerically tiny but nonzero directions it keeps
     const bool rank_ok = in.max_rank <= 0 || rsel >= in.max_rank;
@@ -359,6 +363,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
       trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
       gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
+      // the certifying residual uses Q^T X in FP64 whatever the contraction precision
+      DBuf<double> W64;
+      const double* Wres = Wn.get();
+      if (prec != TT_FP64) {
+        W64.reset(A, static_cast<size_t>(rsel) * cols);
+        gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, W64.get(), rsel, s);
+        Wres = W64.get();
+      }
       // residual of the basis, weighted by the right-part row norms (side stream)
       if (side) {
         TTS_HIP(hipEventRecord(ev.a, s));
@@ -367,7 +379,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       {
         DBuf<double> E(A2, static_cast<size_t>(rows) * cols);
         copy_matrix(X.get(), rows, cols, rows, E.get(), rows, s2);
-        gemm(A2, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wn.get(), rsel, 1.0, E.get(), rows, s2);
+        gemm(A2, false, false, rows, cols, rsel, -1.0, Q.get(), rows, Wres, rsel, 1.0, E.get(), rows, s2);
         weighted_sumsq(A2, E.get(), rows, cols, rows, w[k].get(), e2.get(), s2);
       }
       if (side) TTS_HIP(hipEventRecord(ev.b, s2));
@@ -385,6 +397,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       pend.Q = std::move(Q);
       pend.ok = std::move(ok);
       pend.e2 = std::move(e2);
+      pend.W64 = std::move(W64);  // read by the side-stream residual
     } else {
       exact_bond(k, X, rows, cols);
     }
@@ -426,6 +439,9 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     out.bond_delta[k - 2] = std::sqrt(delta2);
     SvdPart sv;
     truncated_svd(A, prec, reinterpret_cast<const double*>(cores[k - 1].get()), m, rl, delta2, in.max_rank, sv, s);
+    logf("SVD bond %d: %d x %d, rank %d, discarded sum of sigma^2 %.3e ||A||^2 (threshold^2 %.3e), %.3f ms (host)",
+         k - 1, m, rl, sv.rank, sv.tail / (in.norm * in.norm), delta2 / (in.norm * in.norm), host_ms() - t_bond);
+    t_bond = host_ms();
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;
     rem2 = std::max(0.0, rem2 - sv.tail);

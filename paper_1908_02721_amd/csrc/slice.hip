@@ -852,6 +852,8 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   float tot = 0.f;
   TTS_HIP(hipEventElapsedTime(&tot, ev.e[0], ev.e[4]));
   o.ms[4] = tot;
+  logf("Gram slice: m %d, %lld blocks, %lld pairs; bond-1 QR %.3f ms, X_2 %.3f ms, pairs %.3f ms, Gram %.3f ms", m,
+       static_cast<long long>(o.nblocks), static_cast<long long>(o.npairs), o.ms[0], o.ms[1], o.ms[2], o.ms[3]);
 }
 
 }  // namespace tts

@@ -126,3 +126,27 @@ def test_fasttt_mixed_precision(oracle_mod, precision):
             print(f"[mixed] fasttt {tuple(dims)} p={p} {precision}: ranks {tt.ranks} (fp64 oracle {res.ranks}); "
                   f"||B - B_oracle|| / ||A|| = {err:.3e}", flush=True)
             assert np.isfinite(err) and err <= GATE[precision] + eps
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_reduced_precision_deflation_is_certified(oracle_mod, precision):
+    """A term at 2^-24 of the rest: the pivoted Cholesky drops its directions, and the
+    residual test, with Q^T X formed in FP64 whatever the contraction precision, must
+    reject every such deflation (threshold min(1e-2 delta, 1e-13 ||A||) in every mode),
+    so each bond is redone with an exact QR: the QR ranks are the oracle's."""
+    import paper_1908_02721_amd as tts
+
+    idx1, val1, dims = synth.kronecker_sum(6, 10, 5, 3, seed=11)
+    idx2, val2, _ = synth.kronecker_sum(6, 10, 1, 3, seed=12)
+    keys = {}
+    for ix, v in zip(idx1, val1):
+        keys[tuple(ix)] = keys.get(tuple(ix), 0.0) + v
+    for ix, v in zip(idx2, val2 * 2.0 ** -24):
+        keys[tuple(ix)] = keys.get(tuple(ix), 0.0) + v
+    idx = np.array(list(keys.keys()), dtype=np.int32)
+    val = np.array(list(keys.values()), dtype=np.float64)
+    res = oracle_mod.decompose(idx, val, dims, 1e-11)
+    gi, gv = _gpu(idx, val)
+    tt = tts.decompose(gi, gv, dims, 1e-11, precision=precision)
+    print(f"[mixed] deflation certificate {precision}: qr ranks {tt.qr_ranks}, oracle {res.qr_ranks}", flush=True)
+    assert tt.qr_ranks == res.qr_ranks

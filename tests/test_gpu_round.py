@@ -272,3 +272,29 @@ def test_jacobi_sweep_cap_reports_non_convergence():
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
     print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
     assert "ERROR TT_ERR_DEVICE" in r.stdout and "did not converge" in r.stdout
+
+
+def test_progress_log():
+    # TTSPARSE_LOG=1 (read once per process, hence a child process) prints one line per
+    # level of the sparse stage and per bond of both sweeps
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "import paper_1908_02721_amd as tts\n"
+        "from paper_1908_02721_amd import synth\n"
+        "idx, val, dims = synth.random_sparse((6, 5, 4, 6), 200, 1)\n"
+        "tt = tts.decompose(torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda(), dims, 1e-3)\n"
+        "print('ranks', tt.ranks)\n" % root)
+    env = dict(os.environ, TTSPARSE_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    print(r.stderr[-3000:], flush=True)
+    assert r.returncode == 0
+    for k in (1, 2, 3):
+        assert f"[ttsparse] level {k}:" in r.stderr
+        assert f"[ttsparse] SVD bond {k}:" in r.stderr
+        assert f"[ttsparse] QR bond {k}:" in r.stderr
