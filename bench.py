@@ -91,11 +91,18 @@ def _parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the FP32 leg of the FP64 run")
     p.add_argument("--no-slice", action="store_true",
                    help="skip the bond-2 Gram slice leg (5-way 200^5 tensor, 10^7 nonzeros)")
+    p.add_argument("--slice-only", type=int, default=0, metavar="REPS",
+                   help="only run the bond-2 Gram slice leg with REPS timed calls per precision (profiling)")
+    p.add_argument("--slice-precisions", default="fp64,fp32,bf16", help="precisions of the slice leg")
     p.add_argument("--no-overlap", action="store_true",
                    help="build the evaluation plan after the decomposition instead of beside it")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
     p.add_argument("--roofline", default="auto",
                    help="kernel family for the roofline object ('auto': the one with the most time per step)")
+    p.add_argument("--stage", default=None, choices=["sparse", "decompose", "eval"],
+                   help="time one stage alone (for its profiler counters): 'sparse' runs only the sparse "
+                        "stage, 'decompose' the decomposition, 'eval' the plan, forward and backward on the "
+                        "decomposed tensor")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB MiB five times (profiler calibration)")
     return p.parse_args()
@@ -224,14 +231,15 @@ def _traffic(family, workload, method):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
     src = fields.get("source")
-    if not src or "traffic_bytes_per_launch" not in fields:
+    key = "traffic_bytes_per_launch" if "traffic_bytes_per_launch" in fields else "traffic_bytes_per_step"
+    if not src or key not in fields:
         return None
     if fields.get("workload") != workload or fields.get("method", "cps") != method:
         return None  # measured on another workload: other launch shapes
     with open(os.path.join(ROOT, src), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
             return None  # the kernel changed since the counters were taken
-    return float(fields["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return float(fields[key]), os.path.relpath(path, ROOT)
 
 
 def calibrate_copy(mib):
@@ -253,7 +261,66 @@ def calibrate_copy(mib):
                       "copies": 6, "ms_per_copy": ms, "copy_GBps": 2 * n * 8 / (ms / 1000.0) / 1e9}), flush=True)
 
 
-def c4_slice_leg(reps=3):
+def stage_only(args):
+    """One stage of the step alone, --warmup untimed and --steps timed repetitions, so that
+    profiler counters of its kernels are not mixed with the rest of the step.  Prints its
+    time per step and its algorithmic bytes per step (sparse: the formula of
+    sparse_alg_bytes; eval: the sum over the evaluation kernels' live timers)."""
+    import torch
+
+    import paper_1908_02721_amd as tts
+    from paper_1908_02721_amd import _lib, synth
+
+    idx, val, dims, eps = synth.workload(args.workload)
+    gi = torch.from_numpy(np.ascontiguousarray(idx)).cuda()
+    gv = torch.from_numpy(np.ascontiguousarray(val)).cuda()
+    out = {"stage": args.stage, "workload": args.workload, "steps": args.steps, "warmup": args.warmup}
+    if args.stage in ("sparse", "decompose"):
+        sparse_only = args.stage == "sparse"
+
+        def run():
+            return tts.decompose(gi, gv, dims, eps, sparse_only=sparse_only, precision=args.precision)
+    else:
+        tt = tts.decompose(gi, gv, dims, eps, precision=args.precision)
+        cores = tt.cores
+        gy = gv if cores[0].dtype == torch.float64 else gv.float()
+
+        def run():
+            plan = tts.EvalPlan(gi, dims)
+            plan.forward(cores, save=True)
+            plan.backward(cores, gy, use_saved=True)
+            return plan
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = run()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    out["ms_per_step"] = ms
+    if args.stage in ("sparse", "decompose"):
+        out["algo_bytes_per_step"] = sparse_alg_bytes(len(val), len(dims), r.level_sizes())
+        out["stage_ms"] = r.times_ms
+        if args.stage == "decompose":
+            out["ranks"] = r.ranks
+            out["note"] = "algo_bytes_per_step: the sparse stage's only"
+    else:
+        fam = {}
+        for f in ("eval_forward", "eval_up", "eval_grad"):
+            _lib.kernel_timer_start(f)
+            run()
+            torch.cuda.synchronize()
+            k_ms, k_n, k_bytes, k_flops = _lib.kernel_timer_read()
+            _lib.kernel_timer_start(None)
+            fam[f] = {"launches": k_n, "kernel_ms": k_ms, "algo_bytes": k_bytes, "algo_flops": k_flops}
+        out["families"] = fam
+        out["algo_bytes_per_step"] = sum(v["algo_bytes"] for v in fam.values())
+    out["algo_GBps"] = out["algo_bytes_per_step"] / (ms / 1000.0) / 1e9
+    print(json.dumps(out), flush=True)
+
+
+def c4_slice_leg(reps=3, precisions=("fp64", "fp32", "bf16")):
     """The bond-2 Gram slice (tt_sparse_gram_slice) on the 5-way 200^5 tensor with 10^7
     N(0,1) nonzeros, in the three precisions: whole-call nonzeros/s, stage times, the
     Gram kernel's FP64 MFMA rate from the live timer, and the error against the
@@ -270,7 +337,7 @@ def c4_slice_leg(reps=3):
     gi = torch.from_numpy(idx).cuda()
     gv = torch.from_numpy(val).cuda()
     out = {"workload": gold["workload"], "dims": list(dims), "nnz": len(val), "reps": reps}
-    for prec in ("fp64", "fp32", "bf16"):
+    for prec in precisions:
         gs = tts.gram_slice(gi, gv, dims, precision=prec)  # warm-up
         del gs
         torch.cuda.synchronize()
@@ -303,9 +370,12 @@ def c4_slice_leg(reps=3):
             "nnz_per_s": len(val) / (float(np.median(tot)) / 1000.0),
             "slice_ms": med,
             "gram_kernel": {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                            "frac": tf / FP64_PEAK_TFLOPS, "launches": k_n, "kernel_ms": k_ms / k_n,
-                            "algo_flops_per_launch": k_flops / k_n, "algo_bytes_per_launch": k_bytes / k_n},
+                            "frac": tf / FP64_PEAK_TFLOPS, "calls": k_n, "launches_per_call": 2,
+                            "kernel_ms_per_call": k_ms / k_n, "algo_flops_per_call": k_flops / k_n,
+                            "algo_bytes_per_call": k_bytes / k_n},
             "x2_dtype": "f64" if gs.x2_dtype == torch.float64 else "f32",
+            "gram_traffic_per_call": (_traffic("slice_gram", gold["workload"], "cps") or (None,))[0]
+            if prec == "fp64" else None,
             "error_vs_oracle": {"x2_max": float(np.max(ex)), "x2_median": float(np.median(ex)),
                                 "gram_max": float(np.max(eg)), "gram_median": float(np.median(eg)),
                                 "wnorm2_rel": abs(gs.wnorm2 - gold["norm2"]) / gold["norm2"],
@@ -325,6 +395,13 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU path is design-only.",
               file=sys.stderr)
         sys.exit(2)
+    if args.stage:
+        stage_only(args)
+        return
+    if args.slice_only:
+        print(json.dumps({"c4_slice": c4_slice_leg(args.slice_only, tuple(args.slice_precisions.split(",")))}),
+              flush=True)
+        return
     import torch
 
     import paper_1908_02721_amd as tts
@@ -500,8 +577,11 @@ def main():
                         "stage_ms": {k: float(np.median([st[k] for st in m_stage])) for k in m_stage[0]},
                         "ranks": mixed_tt.ranks,
                         "bf16": "not run: this workload's eps is below bfloat16's resolution (see c4_slice)"}
+        if eps < 1e-6:
+            out["mixed"]["eps_note"] = (f"eps = {eps:g} is below what FP32 contractions resolve: the FP32 result's "
+                                        "error is FP32 rounding (~1e-7 relative), see error_vs_oracle")
     if not args.no_slice and args.method == "cps":
-        out["c4_slice"] = c4_slice_leg()
+        out["c4_slice"] = c4_slice_leg(3, tuple(args.slice_precisions.split(",")))
     if not args.no_cpu_baseline:
         cores_host = [c.cpu().numpy() for c in tt.cores]
         out["cpu_baseline"], out["error_vs_oracle"], res = cpu_baseline(

@@ -51,10 +51,12 @@ typedef enum {
 
 typedef enum {
   TT_FP64 = 0,          /* every step in binary64 */
-  TT_FP32 = 1,          /* dense contractions in binary32 (MFMA, FP32 accumulate);
-                           R factors, Gram and SVD steps in binary64 */
-  TT_BF16_FP32ACC = 2   /* dense contractions with bfloat16 operands on MFMA,
-                           FP32 accumulate; R factors, Gram and SVD in binary64 */
+  TT_FP32 = 1,          /* dense contractions of the truncated SVD sweep in binary32
+                           (MFMA, FP32 accumulate); R factors, Gram and SVD steps in
+                           binary64.  The left-to-right QR sweep, whose certified
+                           deflation needs the exact rank deficiency of each
+                           unfolding, runs in binary64 in every precision. */
+  TT_BF16_FP32ACC = 2   /* as TT_FP32 with bfloat16 operands, FP32 accumulate */
 } tt_precision;
 
 typedef enum { TT_DTYPE_F64 = 0, TT_DTYPE_F32 = 1 } tt_dtype;
@@ -295,6 +297,18 @@ tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, co
    sizes[0] = number of unfolding columns (nnz_{k+1}, the entries of level k+1),
    sizes[1] = beta_k, sizes[2] = nnz(N_k).  TT_ERR_ARG for a fiber-trie result. */
 tt_status tt_get_level_sizes(tt_result r, int32_t k, int64_t* sizes);
+
+/*
+ * Device memory of the library.  Blocks that the library's calls release are kept in
+ * a cache, per stream and size class, and handed out again to later work on the
+ * same stream, without synchronisation; a result's blocks return there at tt_free.
+ * The cache holds them until tt_cache_trim, which waits for the device to finish all
+ * work and frees every cached block (*bytes_released, may be NULL, receives their
+ * total).  Streams are told apart by their handles: before destroying a stream the
+ * library used, synchronise it (ordinary practice), so that a later stream that
+ * receives the same handle cannot race with its work; or call tt_cache_trim.
+ */
+tt_status tt_cache_trim(uint64_t* bytes_released);
 
 /* Release a result (NULL is ignored). */
 void tt_free(tt_result r);

@@ -359,6 +359,14 @@ def gram_slice(idx: torch.Tensor, val: torch.Tensor, dims, precision: str = "fp6
     return GramSlice(h, dims)
 
 
+def cache_trim() -> int:
+    """Wait for the device and free every device block the library keeps cached; bytes freed."""
+    L = _lib.load()
+    b = ctypes.c_uint64()
+    _lib.check(L.tt_cache_trim(ctypes.byref(b)))
+    return int(b.value)
+
+
 def fasttt_select_p(idx: torch.Tensor, val: torch.Tensor, dims, stream=None):
     """Algorithm 9: (p, estimated cost of every p = 1..d)."""
     L = _lib.load()

@@ -55,7 +55,7 @@ EXPORTS = (
     "tt_options_default", "tt_sparse_decompose", "tt_get_ranks", "tt_get_core", "tt_get_info",
     "tt_get_sparse_ranks", "tt_get_sigma", "tt_get_bond_delta", "tt_get_times", "tt_matrix_to_tensor",
     "tt_fasttt_decompose", "tt_get_fasttt_info", "tt_sparse_gram_slice", "tt_get_slice_bond1", "tt_get_slice_x2",
-    "tt_get_slice_gram", "tt_fasttt_select_p", "tt_get_level", "tt_get_level_sizes", "tt_free",
+    "tt_get_slice_gram", "tt_fasttt_select_p", "tt_get_level", "tt_get_level_sizes", "tt_cache_trim", "tt_free",
     "tt_eval_entries", "tt_eval_entries_backward", "tt_eval_entries_noalloc", "tt_eval_plan_create", "tt_eval_plan_forward",
     "tt_eval_plan_backward", "tt_eval_plan_free", "tt_status_string", "tt_last_error",
     "tt_kernel_timer_start", "tt_kernel_timer_read",
@@ -109,6 +109,8 @@ def load():
         L.tt_get_times.restype = ctypes.c_int
         L.tt_get_level.argtypes = [vp, i32, P(i64), P(i64), P(vp), P(vp), P(vp), P(vp), P(vp), P(vp)]
         L.tt_get_level.restype = ctypes.c_int
+        L.tt_cache_trim.argtypes = [P(u64)]
+        L.tt_cache_trim.restype = ctypes.c_int
         L.tt_get_level_sizes.argtypes = [vp, i32, P(i64)]
         L.tt_get_level_sizes.restype = ctypes.c_int
         L.tt_free.argtypes = [vp]

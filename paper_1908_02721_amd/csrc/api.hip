@@ -140,6 +140,23 @@ void cached_free(void* p, size_t bytes, hipStream_t s) {
   c.free[{s, size_class(bytes)}].push_back(p);
 }
 
+// Releases every cached block (of every stream) after the device has finished all
+// work; returns the bytes released.
+uint64_t cache_trim() {
+  BlockCache& c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  TTS_HIP(hipDeviceSynchronize());
+  uint64_t bytes = 0;
+  for (auto& kv : c.free) {
+    for (void* p : kv.second) {
+      TTS_HIP(hipFree(p));
+      bytes += kv.first.second;
+    }
+  }
+  c.free.clear();
+  return bytes;
+}
+
 void* Allocator::get(size_t bytes) {
   if (budget && in_use + bytes > budget)
     fail(TT_ERR_NOMEM, "device_mem_budget exceeded (" + std::to_string(in_use + bytes) + " bytes needed)");
@@ -1009,6 +1026,17 @@ tt_status tt_get_level(tt_result r, int32_t k, int64_t* ncols, int64_t* beta, co
   if (n_row) *n_row = L.row.get();
   if (n_val) *n_val = L.val.get();
   return TT_OK;
+}
+
+tt_status tt_cache_trim(uint64_t* bytes_released) {
+  try {
+    const uint64_t b = cache_trim();
+    if (bytes_released) *bytes_released = b;
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  }
 }
 
 tt_status tt_get_level_sizes(tt_result r, int32_t k, int64_t* sizes) {

@@ -53,6 +53,7 @@ struct Allocator {
 // Stream-ordered block cache shared by every allocation of the library.
 void* cached_alloc(size_t bytes, hipStream_t s);
 void cached_free(void* p, size_t bytes, hipStream_t s);
+uint64_t cache_trim();  // frees every cached block after a device synchronisation
 
 template <class T>
 class DBuf {

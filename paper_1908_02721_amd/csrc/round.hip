@@ -256,9 +256,10 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   // exact sparse TT itself carries up to snap_rel ||A||_F of rounding (its canonical
   // values are rounded to key_bits fraction bits), so directions at that level are
   // dropped too, still within 1% of the bond's truncation threshold.  The residual
-  // measures what the basis leaves out, X - Q Q^T X, with Q^T X formed in FP64 in
-  // every precision, so the same threshold certifies the deflation in the reduced
-  // modes; their FP32/BF16 contraction of the carried factor adds its own rounding.
+  // measures what the basis leaves out, X - Q Q^T X.  The whole left-to-right sweep
+  // runs in FP64 in every precision (the basis, Q^T X and the carried factor), so
+  // the same threshold certifies the deflation in the reduced modes, whose FP32/BF16
+  // contractions start with the truncated SVD sweep.
   const double tau = std::min(1e-2 * in.delta, std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
   std::vector<int64_t> r(d + 1, 1);
   std::vector<DBuf<char>> cores(d);
@@ -298,7 +299,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   struct Pending {
     bool active = false;
     int k = 0, rows = 0, cols = 0;
-    DBuf<double> X, Q, e2, W64;
+    DBuf<double> X, Q, e2;
     DBuf<int32_t> ok;
   } pend;
   int32_t pok[4];
@@ -362,15 +363,11 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       gemm(A, true, false, rsel, rsel, rows, 1.0, Q1.get(), rows, Q1.get(), rows, 0.0, G2.get(), rsel, s);
       cholesky_upper(G2.get(), rsel, rsel, 10.0, ok.get() + 2, s);
       trsm_right_upper(Q1.get(), rows, rsel, rows, G2.get(), rsel, Q.get(), rows, ok.get() + 3, s, A);
-      gemm_prec(A, prec, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
-      // the certifying residual uses Q^T X in FP64 whatever the contraction precision
-      DBuf<double> W64;
+      // W' = Q^T X in FP64 in every precision: it is carried into the next bond, and a
+      // rounded W' would give the next unfolding full numerical rank at the rounding
+      // level, so that no deflation below that level could be certified
+      gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, Wn.get(), rsel, s);
       const double* Wres = Wn.get();
-      if (prec != TT_FP64) {
-        W64.reset(A, static_cast<size_t>(rsel) * cols);
-        gemm(A, true, false, rsel, cols, rows, 1.0, Q.get(), rows, X.get(), rows, 0.0, W64.get(), rsel, s);
-        Wres = W64.get();
-      }
       // residual of the basis, weighted by the right-part row norms (side stream)
       if (side) {
         TTS_HIP(hipEventRecord(ev.a, s));
@@ -397,7 +394,6 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       pend.Q = std::move(Q);
       pend.ok = std::move(ok);
       pend.e2 = std::move(e2);
-      pend.W64 = std::move(W64);  // read by the side-stream residual
     } else {
       exact_bond(k, X, rows, cols);
     }
@@ -415,7 +411,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     // last core: W (r_{d-1} x beta_{d-1}) times the exact last core (beta_{d-1} x n_d)
     const int nd = n[d - 1], bl = beta[d - 1];
     DBuf<double> C(A, static_cast<size_t>(rp) * nd);
-    gemm_prec(A, prec, false, true, rp, nd, bl, 1.0, W.get(), rp, in.last_core, nd, 0.0, C.get(), rp, s);
+    gemm(A, false, true, rp, nd, bl, 1.0, W.get(), rp, in.last_core, nd, 0.0, C.get(), rp, s);
     cores[d - 1].reset(A, sizeof(double) * static_cast<size_t>(rp) * nd);
     transpose(C.get(), rp, nd, rp, reinterpret_cast<double*>(cores[d - 1].get()), nd, s);
   }
