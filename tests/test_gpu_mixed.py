@@ -131,9 +131,9 @@ def test_fasttt_mixed_precision(oracle_mod, precision):
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_reduced_precision_deflation_is_certified(oracle_mod, precision):
     """A term at 2^-24 of the rest: the pivoted Cholesky drops its directions, and the
-    residual test, with Q^T X formed in FP64 whatever the contraction precision, must
-    reject every such deflation (threshold min(1e-2 delta, 1e-13 ||A||) in every mode),
-    so each bond is redone with an exact QR: the QR ranks are the oracle's."""
+    residual test (the left-to-right sweep is FP64 in every mode) must reject every
+    such deflation (threshold min(1e-2 delta, 1e-13 ||A||) in every mode), so each
+    bond is redone with an exact QR: the QR ranks are the oracle's."""
     import paper_1908_02721_amd as tts
 
     idx1, val1, dims = synth.kronecker_sum(6, 10, 5, 3, seed=11)
