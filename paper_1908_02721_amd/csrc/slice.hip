@@ -58,12 +58,16 @@ struct GramItem {
 };
 
 // Output tiles of a block are split over several items so that a wave holds at most
-// 11 accumulator tiles.  Off-diagonal blocks take all MT x MT tiles; diagonal blocks
-// (symmetric) only the MT (MT + 1) / 2 tiles on or above the diagonal, each mirrored.
+// 11 (off-diagonal) or 12 (diagonal) accumulator tiles: within the 256 registers of
+// two waves per SIMD, and enough for the 91 upper tiles of a diagonal block at
+// m = 208 to need no split.  Off-diagonal blocks take all MT x MT tiles; diagonal
+// blocks (symmetric) only the MT (MT + 1) / 2 tiles on or above the diagonal, each
+// mirrored.
 constexpr int kTilesPerWave = 11;
 __host__ __device__ constexpr int tiles_of(int mt, int kind) { return kind == 0 ? mt * (mt + 1) / 2 : mt * mt; }
+__host__ __device__ constexpr int tiles_per_wave(int kind) { return kind == 0 ? 12 : kTilesPerWave; }
 __host__ __device__ constexpr int gram_split(int mt, int kind) {
-  return (tiles_of(mt, kind) + kTilesPerWave * 8 - 1) / (kTilesPerWave * 8);
+  return (tiles_of(mt, kind) + tiles_per_wave(kind) * 8 - 1) / (tiles_per_wave(kind) * 8);
 }
 __host__ __device__ constexpr int tiles_per_item(int mt, int kind) {
   return (tiles_of(mt, kind) + gram_split(mt, kind) - 1) / gram_split(mt, kind);
@@ -296,29 +300,27 @@ __global__ __launch_bounds__(NT) void k_pair_emit(const int64_t* __restrict__ cp
 }
 
 // One k-step of NTPW accumulator tiles, starting at tile (tr, tc) of a wave's run:
-// the fragments are read first, then the MFMA chain runs.  Tiles past the wave's nt
-// live ones repeat its last live tile (valid addresses; never written back).
+// all fragments are read first, then the MFMA chain runs (reading each fragment just
+// one MFMA ahead measured 4% slower: the chain then waits on LDS latency).  Tiles past
+// the wave's nt live ones repeat its last live tile (valid addresses; never written
+// back).
 template <int MT, int NTPW>
 __device__ __forceinline__ void gram_kstep(const double* __restrict__ Ak, const double* __restrict__ Bk, dbl4* acc,
                                            int tr, int tc, int nt, bool diag) {
   // software pipeline of depth one: the next tile's fragments are read before this
   // tile's MFMA is issued
-  double a0 = Ak[tr * 16], b0 = Bk[tc * 16];
+  double fa[NTPW], fb[NTPW];
 #pragma unroll
   for (int u = 0; u < NTPW; ++u) {
-    double a1 = a0, b1 = b0;
-    if (u + 1 < NTPW) {
-      if (u + 1 < nt && ++tc == MT) {
-        ++tr;
-        tc = diag ? tr : 0;
-      }
-      a1 = Ak[tr * 16];
-      b1 = Bk[tc * 16];
+    fa[u] = Ak[tr * 16];
+    fb[u] = Bk[tc * 16];
+    if (u + 1 < nt && ++tc == MT) {
+      ++tr;
+      tc = diag ? tr : 0;
     }
-    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[u], 0, 0, 0);
-    a0 = a1;
-    b0 = b1;
   }
+#pragma unroll
+  for (int u = 0; u < NTPW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u], fb[u], acc[u], 0, 0, 0);
 }
 
 // One work item of the Gram per workgroup: the m x m block (padded to W = 16 MT)
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kGramThreads) void k_slice_gram(const GramItem* __r
   constexpr int W = 16 * MT;
   // accumulator tiles per wave; every item of a launch is of kind KIND
   constexpr int TPW = (tiles_per_item(MT, KIND) + kGramWaves - 1) / kGramWaves;
-  static_assert(TPW <= kTilesPerWave, "accumulator tiles per wave");
+  static_assert(TPW <= tiles_per_wave(KIND), "accumulator tiles per wave");
   extern __shared__ double lds[];
   double* SA = lds;                 // [2][kKC][W]
   double* SB = lds + 2 * kKC * W;   // [2][kKC][W]
@@ -598,6 +600,28 @@ void run_gram(Allocator* A, const SliceInput& in, SliceOut& o, const double* wbl
   const size_t ndiag = static_cast<size_t>(
       std::stable_partition(items.begin(), items.end(), [](const GramItem& x) { return x.kind == 0; }) -
       items.begin());
+  // XCD-aware order: the items that split one block's tiles read the same pairs.
+  // Workgroups are dispatched to the 8 XCDs round-robin by index, so within each
+  // window of 8 blocks the parts of block b are placed at b, b + 8, b + 16, ...:
+  // they run on one XCD at about the same time and the later ones find the pairs'
+  // vectors in that XCD's L2 instead of reading them from HBM again.
+  auto xcd_order = [&](size_t first, size_t cnt, int nsplit) {
+    if (nsplit <= 1 || cnt % nsplit) return;
+    for (size_t u = first; u < first + cnt; u += nsplit)
+      for (int sp = 1; sp < nsplit; ++sp)
+        if (items[u + sp].start != items[u].start || items[u + sp].dst != items[u].dst) return;
+    std::vector<GramItem> out(items.begin() + first, items.begin() + first + cnt);
+    const size_t nunit = cnt / nsplit;
+    for (size_t w0 = 0; w0 < nunit; w0 += 8) {
+      const size_t k = std::min<size_t>(8, nunit - w0);
+      for (size_t b = 0; b < k; ++b)
+        for (int sp = 0; sp < nsplit; ++sp)
+          out[w0 * nsplit + sp * k + b] = items[first + (w0 + b) * nsplit + sp];
+    }
+    std::copy(out.begin(), out.end(), items.begin() + first);
+  };
+  xcd_order(0, ndiag, gram_split(MT, 0));
+  xcd_order(ndiag, items.size() - ndiag, gram_split(MT, 1));
   if (!items.empty())
     TTS_HIP(hipMemcpyAsync(ditems.get(), items.data(), sizeof(GramItem) * items.size(), hipMemcpyHostToDevice, s));
   if (!items.empty()) {
