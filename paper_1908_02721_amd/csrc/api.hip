@@ -112,6 +112,54 @@ size_t size_class(size_t bytes) {
 }
 }  // namespace
 
+namespace {
+struct PinnedStage {
+  char* p = nullptr;
+  size_t cap = 0;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local PinnedStage g_stage;
+thread_local const Readback* g_stage_owner = nullptr;  // the Readback with pieces in flight
+}  // namespace
+
+Readback::~Readback() {
+  if (g_stage_owner == this) g_stage_owner = nullptr;
+}
+
+void Readback::add(void* host, const void* dev, size_t bytes) {
+  if (!bytes) return;
+  if (g_stage_owner && g_stage_owner != this) fail(TT_ERR_DEVICE, "internal: overlapping read-backs on one thread");
+  const size_t off = (off_ + 255) & ~static_cast<size_t>(255);
+  if (off + bytes > g_stage.cap) {
+    // grow: the pieces already enqueued land first
+    sync();
+    const size_t cap = std::max<size_t>(size_t(1) << 20, 2 * bytes);
+    if (g_stage.p) TTS_HIP(hipHostFree(g_stage.p));
+    g_stage.p = nullptr;
+    g_stage.cap = 0;
+    void* q = nullptr;
+    TTS_HIP(hipHostMalloc(&q, cap, hipHostMallocDefault));
+    g_stage.p = static_cast<char*>(q);
+    g_stage.cap = cap;
+    add(host, dev, bytes);
+    return;
+  }
+  g_stage_owner = this;
+  TTS_HIP(hipMemcpyAsync(g_stage.p + off, dev, bytes, hipMemcpyDeviceToHost, s_));
+  pend_.push_back(Piece{host, off, bytes});
+  off_ = off + bytes;
+}
+
+void Readback::sync() {
+  TTS_HIP(hipStreamSynchronize(s_));
+  for (const Piece& x : pend_) std::memcpy(x.host, g_stage.p + x.off, x.bytes);
+  pend_.clear();
+  off_ = 0;
+  if (g_stage_owner == this) g_stage_owner = nullptr;
+}
+
 void* cached_alloc(size_t bytes, hipStream_t s) {
   const size_t cls = size_class(bytes);
   {

@@ -1103,8 +1103,11 @@ bool build_trie(const EvalDesc& ed, int64_t m, const int32_t* idx, DevMem& mem, 
     prev = cur;
   }
   std::vector<uint32_t> hc(d + 1);
-  TTS_HIP(hipMemcpyAsync(hc.data(), counts, sizeof(uint32_t) * (d + 1), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(hc.data(), counts, sizeof(uint32_t) * (d + 1));
+    rb.sync();
+  }
   if (hc[0]) return false;
   for (int t = 1; t <= d; ++t) tr.P[t] = hc[t];
   tr.leaf = prev;
@@ -1123,6 +1126,7 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, DevMem& scratch, A
   uint64_t* vt = mem.get<uint64_t>(pmax);
   std::vector<std::vector<int64_t>>& hoff = tr.hoff;
   hoff.assign(d + 1, {});
+  Readback rb(s);
   for (int t = 1; t <= d; ++t) {
     const int nk = ed.n[t - 1];
     const int64_t P = tr.P[t];
@@ -1140,9 +1144,9 @@ void build_buckets(const EvalDesc& ed, Trie& tr, DevMem& mem, DevMem& scratch, A
     k_bucket_offsets<<<grid_for(nk + 1, NT), NT, 0, s>>>(key, P, nk, tr.boff[t]);
     TTS_LAUNCH_CHECK();
     hoff[t].resize(nk + 1);
-    TTS_HIP(hipMemcpyAsync(hoff[t].data(), tr.boff[t], sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToHost, s));
+    rb.add(hoff[t].data(), tr.boff[t], sizeof(int64_t) * (nk + 1));
   }
-  TTS_HIP(hipStreamSynchronize(s));
+  rb.sync();
   for (int t = 1; t <= d; ++t)
     for (int i = 0; i < ed.n[t - 1]; ++i) tr.bmax[t] = std::max(tr.bmax[t], hoff[t][i + 1] - hoff[t][i]);
 }
@@ -1359,8 +1363,11 @@ tt_status direct_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, void* y
   TTS_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
   if (m > 0) launch_left<T>(ed, m, idx, static_cast<T*>(y_out), nullptr, err, s);
   uint32_t h = 0;
-  TTS_HIP(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&h, err, sizeof(h));
+    rb.sync();
+  }
   if (h) {
     set_last_error("a coordinate is outside its mode range");
     return TT_ERR_INDEX;
@@ -1385,8 +1392,11 @@ tt_status direct_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T
     if (R) launch_right<T>(ed, m, idx, R, s);
   }
   uint32_t h = 0;
-  TTS_HIP(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&h, err, sizeof(h));
+    rb.sync();
+  }
   if (h) {
     set_last_error("a coordinate is outside its mode range");
     return TT_ERR_INDEX;
@@ -1417,8 +1427,11 @@ tt_status direct_grad(const EvalDesc& ed, int64_t m, const int32_t* idx, const T
     k_bucket_offsets<<<grid_for(nk + 1, NT), NT, 0, s>>>(key, m, nk, off);
     TTS_LAUNCH_CHECK();
     std::vector<int64_t> hoff(nk + 1);
-    TTS_HIP(hipMemcpyAsync(hoff.data(), off, sizeof(int64_t) * (nk + 1), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
+    {
+      Readback rb(s);
+      rb.add(hoff.data(), off, sizeof(int64_t) * (nk + 1));
+      rb.sync();
+    }
     const int tiles = ((r0 + 63) / 64) * ((r1 + 63) / 64);
     const ChunkList ch = make_chunk_list(off, hoff, grad_chunk_len(m, tiles, KC), mem, s);
     T* part = mem.get<T>(static_cast<size_t>(std::max<int64_t>(ch.n, 1)) * r0 * r1);
@@ -1624,8 +1637,11 @@ extern "C" tt_status tt_eval_plan_create(int32_t d, const int64_t* dims, int64_t
       k_check_coords<<<grid_for(m * d, NT), NT, 0, s>>>(c, m, ed, err);
       TTS_LAUNCH_CHECK();
       uint32_t h = 0;
-      TTS_HIP(hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, s));
-      TTS_HIP(hipStreamSynchronize(s));
+      {
+        Readback rb(s);
+        rb.add(&h, err, sizeof(h));
+        rb.sync();
+      }
       if (h) {
         set_last_error("a coordinate is outside its mode range");
         return TT_ERR_INDEX;
@@ -1758,8 +1774,11 @@ tt_status noalloc_eval(const EvalDesc& ed, int64_t m, const int32_t* idx, T* y, 
   TTS_LAUNCH_CHECK();
   if (m > 0) launch_left<T>(ed, m, idx, y, nullptr, flag, s);
   uint32_t h = 0;
-  TTS_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&h, flag, sizeof(h));
+    rb.sync();
+  }
   if (h) {
     set_last_error("a coordinate is outside its mode range");
     return TT_ERR_INDEX;

@@ -169,8 +169,11 @@ __global__ __launch_bounds__(FT) void k_ftt_sumsq(const uint32_t* __restrict__ l
 template <class T>
 T read1(const T* dev, hipStream_t s) {
   T h{};
-  TTS_HIP(hipMemcpyAsync(&h, dev, sizeof(T), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&h, dev, sizeof(T));
+    rb.sync();
+  }
   return h;
 }
 
@@ -191,8 +194,11 @@ void ftt_kept(Allocator* al, const int32_t* idx, const double* val, uint32_t nnz
   TTS_LAUNCH_CHECK();
   exclusive_scan_u32(al, keep.get(), pos.get(), nnz, st.get() + 1, s);
   uint32_t h[2];
-  TTS_HIP(hipMemcpyAsync(h, st.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(h, st.get(), sizeof(h));
+    rb.sync();
+  }
   if (h[0] & 1u) fail(TT_ERR_INDEX, "a coordinate lies outside [0, n_k)");
   if (h[0] & 2u) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");
   if (h[1] == 0) fail(TT_ERR_EMPTY, "no nonzero left after dropping explicit zeros");
@@ -237,8 +243,11 @@ void ftt_exact(Allocator* al, const int32_t* idx, const double* val, uint32_t nn
     k_ftt_sumsq<<<np, FT, 0, s>>>(kp.list.get(), val, m, part.get());
     TTS_LAUNCH_CHECK();
     std::vector<double> h(np);
-    TTS_HIP(hipMemcpyAsync(h.data(), part.get(), sizeof(double) * np, hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
+    {
+      Readback rb(s);
+      rb.add(h.data(), part.get(), sizeof(double) * np);
+      rb.sync();
+    }
     double ss = 0.0;
     for (double x : h) ss += x;
     out.norm = std::sqrt(ss);
@@ -420,8 +429,11 @@ void ftt_round(Allocator* al, const std::vector<int64_t>& dims, int p, double ep
       DBuf<int32_t> ok(al, 4);
       cholqr2_async(al, core(k), m, r0, reinterpret_cast<double*>(Q.get()), Rm.get(), ok.get(), s);
       int32_t h[4];
-      TTS_HIP(hipMemcpyAsync(h, ok.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-      TTS_HIP(hipStreamSynchronize(s));
+      {
+        Readback rb(s);
+        rb.add(h, ok.get(), sizeof(h));
+        rb.sync();
+      }
       done = h[0] && h[1] && h[2] && h[3];
     }
     if (!done) qr_explicit(al, core(k), m, r0, m, reinterpret_cast<double*>(Q.get()), m, Rm.get(), q, s);

@@ -2966,8 +2966,11 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
       k_bjacobi_round<<<nb / 2, NT, bshm, s>>>(A, rows, c, lda, V, ldv, nb, rd, flag);
       TTS_LAUNCH_CHECK();
     }
-    TTS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
+    {
+      Readback rb(s);
+      rb.add(&hflag, flag, sizeof(int32_t));
+      rb.sync();
+    }
     sweeps = sweep + 1;
   }
   cached_free(flag, sizeof(int32_t), s);

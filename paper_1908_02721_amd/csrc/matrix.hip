@@ -154,8 +154,11 @@ tt_status matrix_coords(int32_t d, const int64_t* row_dims, const int64_t* col_d
     TTS_LAUNCH_CHECK();
   }
   uint32_t h = 0;
-  TTS_HIP(hipMemcpyAsync(&h, err.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&h, err.get(), sizeof(h));
+    rb.sync();
+  }
   if (h) fail(TT_ERR_INDEX, "a row or column index lies outside the matrix");
   return TT_OK;
 }

@@ -49,8 +49,7 @@ __global__ void k_set_i32(int32_t* p, int n, int32_t v) {
 
 template <class T>
 void d2h(T* host, const T* dev, size_t n, hipStream_t s) {
-  TTS_HIP(hipMemcpyAsync(host, dev, sizeof(T) * n, hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  read_back(host, dev, n, s);
 }
 
 template <class T>
@@ -163,12 +162,13 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   DBuf<int32_t> dperm(A, cB), okq(A, 4), jinfo(A, 4);
   std::vector<double> sh(cB);
   alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
+  Readback rb(s);
   auto svd_of_bt = [&]() {
     jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s);
     k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
     TTS_LAUNCH_CHECK();
-    TTS_HIP(hipMemcpyAsync(sh.data(), sig.get(), sizeof(double) * cB, hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipMemcpyAsync(hinfo, jinfo.get(), sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    rb.add(sh.data(), sig.get(), sizeof(double) * cB);
+    rb.add(hinfo, jinfo.get(), sizeof(hinfo));
   };
   if (haveQ) {
     DBuf<double> R(A, static_cast<size_t>(c) * c);
@@ -176,18 +176,18 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     transpose(R.get(), c, c, c, Bt.get(), c, s);
     svd_of_bt();
     int32_t okh[4];
-    TTS_HIP(hipMemcpyAsync(okh, okq.get(), sizeof(okh), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
+    rb.add(okh, okq.get(), sizeof(okh));
+    rb.sync();
     if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
       qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
       transpose(R.get(), c, c, c, Bt.get(), c, s);
       svd_of_bt();
-      TTS_HIP(hipStreamSynchronize(s));
+      rb.sync();
     }
   } else {
     transpose(G, m, c, m, Bt.get(), c, s);
     svd_of_bt();
-    TTS_HIP(hipStreamSynchronize(s));
+    rb.sync();
   }
   svd_check(hinfo, sh.data(), cB, c);
   // the same stable non-ascending order as k_rank_desc
@@ -317,6 +317,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     DBuf<double> L;
     DBuf<int32_t> piv, cnt;
     int32_t rsel = 0;
+    Readback rb(s);
     if (tau > 0.0) {
       DBuf<double> Y(A, static_cast<size_t>(rows) * cols), G(A, static_cast<size_t>(cols) * cols);
       scale_cols_sqrt(X.get(), rows, cols, rows, w[k].get(), Y.get(), rows, s);
@@ -325,14 +326,14 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       piv.reset(A, rmax);
       cnt.reset(A, 1);
       pivoted_cholesky(G.get(), cols, cols, rmax, kTheta, L.get(), piv.get(), cnt.get(), s);
-      TTS_HIP(hipMemcpyAsync(&rsel, cnt.get(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      rb.add(&rsel, cnt.get(), sizeof(int32_t));
     }
     if (pend.active) {
       if (side) TTS_HIP(hipStreamWaitEvent(s, ev.b, 0));
-      TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
-      TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+      rb.add(pok, pend.ok.get(), sizeof(pok));
+      rb.add(&pe2, pend.e2.get(), sizeof(double));
     }
-    if (tau > 0.0 || pend.active) TTS_HIP(hipStreamSynchronize(s));
+    if (tau > 0.0 || pend.active) rb.sync();
     if (pend.active) {
       pend.active = false;
       logf("QR bond %d: deflation to rank %lld %s (residual %.3e ||A||, threshold %.3e ||A||)", pend.k,
@@ -401,9 +402,10 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   }
   if (pend.active) {  // the last bond's test
     if (side) TTS_HIP(hipStreamWaitEvent(s, ev.b, 0));
-    TTS_HIP(hipMemcpyAsync(pok, pend.ok.get(), sizeof(pok), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipMemcpyAsync(&pe2, pend.e2.get(), sizeof(double), hipMemcpyDeviceToHost, s));
-    TTS_HIP(hipStreamSynchronize(s));
+    Readback rb(s);
+    rb.add(pok, pend.ok.get(), sizeof(pok));
+    rb.add(&pe2, pend.e2.get(), sizeof(double));
+    rb.sync();
     pend.active = false;
     if (!pending_accepted()) exact_bond(pend.k, pend.X, pend.rows, pend.cols);
   }

@@ -500,8 +500,9 @@ int bits_of(uint64_t n) {  // bits to hold values 0..n-1
 template <class X>
 void to_host(std::vector<X>& h, const X* dev, size_t n, hipStream_t s) {
   h.resize(n);
-  if (n) TTS_HIP(hipMemcpyAsync(h.data(), dev, sizeof(X) * n, hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  Readback rb(s);
+  if (n) rb.add(h.data(), dev, sizeof(X) * n);
+  rb.sync();
 }
 
 struct StageEvents {
@@ -539,8 +540,11 @@ void fill_x2(Allocator* A, const SliceInput& in, SliceOut& o, const DBuf<int64_t
   }
   k_sum_ordered<<<1, NT, 0, s>>>(wpart.get(), static_cast<int>(grid * (NT / 64)), wsum.get());
   TTS_LAUNCH_CHECK();
-  TTS_HIP(hipMemcpyAsync(&o.wnorm2, wsum.get(), sizeof(double), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&o.wnorm2, wsum.get(), sizeof(double));
+    rb.sync();
+  }
 }
 
 template <typename T>
@@ -711,9 +715,12 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   cholqr2_async(A, G.get(), static_cast<int>(b1), n1, Qg.get(), Rg.get(), ok.get(), s);
   int32_t hok[4];
   int32_t nz = 0;
-  TTS_HIP(hipMemcpyAsync(hok, ok.get(), sizeof(hok), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipMemcpyAsync(&nz, rowflag.get() + n1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(hok, ok.get(), sizeof(hok));
+    rb.add(&nz, rowflag.get() + n1, sizeof(int32_t));
+    rb.sync();
+  }
   if (!(hok[0] && hok[1] && hok[2] && hok[3]))
     qr_explicit(A, G.get(), static_cast<int>(b1), n1, static_cast<int>(b1), Qg.get(), static_cast<int>(b1), Rg.get(),
                 n1, s);
@@ -724,9 +731,13 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   DBuf<int32_t> jinfo(A, 4);
   jacobi_svd(Rg.get(), n1, n1, n1, V.get(), n1, sig.get(), jinfo.get(), s);
   alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
-  TTS_HIP(hipMemcpyAsync(hinfo, jinfo.get(), sizeof(hinfo), hipMemcpyDeviceToHost, s));
-  std::vector<double> hs;
-  to_host(hs, sig.get(), n1, s);
+  std::vector<double> hs(n1);
+  {
+    Readback rb(s);
+    rb.add(hinfo, jinfo.get(), sizeof(hinfo));
+    rb.add(hs.data(), sig.get(), sizeof(double) * n1);
+    rb.sync();
+  }
   svd_check(hinfo, hs.data(), n1, n1);
   std::vector<int32_t> perm(n1);
   std::iota(perm.begin(), perm.end(), 0);
@@ -778,8 +789,11 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   TTS_LAUNCH_CHECK();
   exclusive_scan_u32(A, flag.get(), pos.get(), nnz2, cnt.get(), s);
   uint32_t nb = 0;
-  TTS_HIP(hipMemcpyAsync(&nb, cnt.get(), sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&nb, cnt.get(), sizeof(uint32_t));
+    rb.sync();
+  }
   o.nblocks = nb;
   DBuf<int64_t> bstart(A, static_cast<size_t>(nb) + 1);
   DBuf<int32_t> bslot(A, nb);
@@ -829,8 +843,11 @@ void gram_slice(Allocator& al, const SliceInput& in, SliceOut& o, hipStream_t s)
   k_pair_counts<<<grid_for(b2, NT), NT, 0, s>>>(cptr.get(), static_cast<int>(b2), pcnt.get(), ptot64.get());
   TTS_LAUNCH_CHECK();
   unsigned long long np64 = 0;
-  TTS_HIP(hipMemcpyAsync(&np64, ptot64.get(), sizeof(np64), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  {
+    Readback rb(s);
+    rb.add(&np64, ptot64.get(), sizeof(np64));
+    rb.sync();
+  }
   if (np64 >= (1ull << 31)) fail(TT_ERR_TOO_LARGE, "more than 2^31 slot pairs in the columns of N_2");
   exclusive_scan_u32(A, pcnt.get(), ppos.get(), static_cast<uint32_t>(b2), ptot.get(), s);
   const uint32_t np = static_cast<uint32_t>(np64);
