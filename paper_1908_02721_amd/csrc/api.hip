@@ -333,8 +333,8 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     DBuf<uint32_t> flag(al, nE), pos(al, nE), col_start(al, static_cast<size_t>(nE) + 1);
     DBuf<double> norm_part;
     if (level1) norm_part.reset(al, norm_partials_count(nE));
-    TTS_HIP(hipMemsetAsync(&st.get()->longcol, 0, sizeof(uint32_t), s));
-    launch_col_flags(ekey.get(), nE, sh, level1, !level1, evp, flag.get(), norm_part.get(), st.get(), s);
+    launch_col_flags(ekey.get(), nE, sh, level1, level1 ? -1 : k - 1, evp, flag.get(), norm_part.get(), st.get(),
+                     s);
     exclusive_scan_u32(al, flag.get(), pos.get(), nE, &st.get()->ncols, s);
     launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), st.get(), s);
     if (level1) launch_norm_final(norm_part.get(), norm_partials_count(nE), st.get(), s);
@@ -346,7 +346,8 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     }
     const uint32_t ncols = hs.ncols;
     bool sort_rows = !level1;
-    if (!level1 && hs.longcol) {
+    const bool longcol = !level1 && ((hs.longmask >> (k - 1)) & 1ull);
+    if (longcol) {
       // long columns: order entries by (column, rho) with one composite sort
       const uint64_t maxrho = static_cast<uint64_t>(R->betas[k - 1]) * mi.n[k - 1];
       const int rbits = static_cast<int>(bits_for(maxrho));
@@ -390,14 +391,16 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     ca.cols = cols.get();
     ca.colsuf = colsuf.get();
     ca.rmkey = rmkey.get();
-    // levels with long columns and few columns: a workgroup per column
-    launch_canon(ca, mi, st.get(), !level1 && hs.longcol && ncols <= 16384, s);
-    // a5: group
+    // a5's hash table, cleared by the canonicalisation kernel
     uint32_t tsize = 1;
     while (tsize < 2u * ncols + 2u) tsize <<= 1;
     DBuf<uint64_t> table(al, tsize), slotmin(al, tsize);
-    TTS_HIP(hipMemsetAsync(table.get(), 0, sizeof(uint64_t) * tsize, s));
-    TTS_HIP(hipMemsetAsync(slotmin.get(), 0xff, sizeof(uint64_t) * tsize, s));
+    ca.table = table.get();
+    ca.slotmin = slotmin.get();
+    ca.tsize = tsize;
+    // levels with long columns and few columns: a workgroup per column
+    launch_canon(ca, mi, st.get(), longcol && ncols <= 16384, s);
+    // a5: group
     DBuf<uint32_t> slot(al, ncols), isrep(al, ncols);
     launch_group(colhash.get(), crho.get(), cval.get(), col_start.get(), rmkey.get(), ncols, table.get(),
                  slotmin.get(), tsize - 1, slot.get(), isrep.get(), s);

@@ -47,15 +47,6 @@ __global__ void k_set_i32(int32_t* p, int n, int32_t v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-template <class T>
-void d2h(T* host, const T* dev, size_t n, hipStream_t s) {
-  read_back(host, dev, n, s);
-}
-
-template <class T>
-void h2d(T* dev, const T* host, size_t n, hipStream_t s) {
-  TTS_HIP(hipMemcpyAsync(dev, host, sizeof(T) * n, hipMemcpyHostToDevice, s));
-}
 
 // perm[rank(j)] = j for the stable non-ascending order of s[0..n): rank(j) = number of
 // i with s_i > s_j, or s_i == s_j and i < j.

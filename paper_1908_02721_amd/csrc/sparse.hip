@@ -66,7 +66,7 @@ __global__ __launch_bounds__(NT) void k_ingest(const int32_t* __restrict__ idx, 
 }
 
 __global__ __launch_bounds__(NT) void k_col_flags(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,
-                                                  int level1, int check_long, const double* __restrict__ ev,
+                                                  int level1, int long_bit, const double* __restrict__ ev,
                                                   uint32_t* __restrict__ flag, double* __restrict__ norm_part,
                                                   DevStatus* st) {
   __shared__ double red[NT / 64];
@@ -82,11 +82,11 @@ __global__ __launch_bounds__(NT) void k_col_flags(const uint64_t* __restrict__ e
       const double v = ev[e];
       sq = v * v;
     }
-    if (check_long && start) {
+    if (long_bit >= 0 && start) {
       uint32_t j = e + 1;
       const uint32_t lim = (nE - e > static_cast<uint32_t>(kMaxLocal) + 1) ? e + kMaxLocal + 1 : nE;
       while (j < lim && (ekey[j] >> sh) == col) ++j;
-      if (j - e > static_cast<uint32_t>(kMaxLocal)) atomicOr(&st->longcol, 1u);
+      if (j - e > static_cast<uint32_t>(kMaxLocal)) atomicOr(&st->longmask, 1ull << long_bit);
     }
   }
   if (level1) {
@@ -101,16 +101,28 @@ __global__ __launch_bounds__(NT) void k_col_flags(const uint64_t* __restrict__ e
   }
 }
 
-__global__ __launch_bounds__(NT) void k_norm_final(const double* __restrict__ part, uint32_t np, DevStatus* st) {
-  __shared__ double red[NT / 64];
-  double s = 0.0;
-  for (uint32_t i = threadIdx.x; i < np; i += NT) s += part[i];
-  s = wave_sum_f64(s);
+// Sum of the per-workgroup partials in a fixed order: 1024 threads, each with four
+// independent running sums over a strided quarter of its share (loads issued
+// together), then a wave sum and the 16 wave sums in order.
+constexpr int NF = 1024;
+__global__ __launch_bounds__(NF) void k_norm_final(const double* __restrict__ part, uint32_t np, DevStatus* st) {
+  __shared__ double red[NF / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * NF < np; i += 4 * NF) {
+    const double a = part[i], b = part[i + NF], c = part[i + 2 * NF], e = part[i + 3 * NF];
+    s0 += a;
+    s1 += b;
+    s2 += c;
+    s3 += e;
+  }
+  for (; i < np; i += NF) s0 += part[i];
+  double s = wave_sum_f64((s0 + s1) + (s2 + s3));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
-    for (int w = 0; w < NT / 64; ++w) t += red[w];
+    for (int w = 0; w < NF / 64; ++w) t += red[w];
     st->norm2 = t;
   }
 }
@@ -187,8 +199,17 @@ __device__ __forceinline__ void col_keys(const CanonArgs& a, const ModeInfo& mi,
   a.rmkey[c] = rm;
 }
 
+// Clears the grouping table: slots t, t + stride, ... (below tsize).
+__device__ __forceinline__ void clear_table(const CanonArgs& a, uint32_t t, uint32_t stride) {
+  for (uint32_t e = t; e < a.tsize; e += stride) {
+    a.table[e] = 0ull;
+    a.slotmin[e] = ~0ull;
+  }
+}
+
 __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
+  clear_table(a, c, gridDim.x * NT);
   const bool active = c < a.ncols;
   const uint32_t st = active ? a.col_start[c] : 0;
   const uint32_t m = active ? a.col_start[c + 1] - st : 0;
@@ -275,6 +296,7 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
 __global__ __launch_bounds__(NT) void k_canon_wide(CanonArgs a, ModeInfo mi) {
   __shared__ uint64_t red[NT / 64];
   const uint32_t c = blockIdx.x;
+  clear_table(a, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
   const uint32_t st = a.col_start[c], en = a.col_start[c + 1];
   const uint32_t m = en - st;
   const double s = a.ev[st];
@@ -419,13 +441,17 @@ __device__ __forceinline__ uint32_t global_probe(const uint64_t* __restrict__ co
 // then only one column per chunk-local group probes the global table, and the
 // group's minimum goes to memory once per chunk.  Same slots, representatives and
 // minima as k_group.
-constexpr int GL_CH = 2048, GL_TL = 4096, GL_PT = GL_CH / NT;
+// The chunk is GL_CH columns (a power of two, 256 to 2048), chosen per level so that
+// the grid has at least 256 workgroups where the level allows.
+template <int GL_CH>
 __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__ colhash,
                                                     const uint32_t* __restrict__ crho, const double* __restrict__ cval,
                                                     const uint32_t* __restrict__ col_start,
                                                     const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
                                                     uint64_t* slotmin, uint32_t tmask, uint32_t* __restrict__ slot,
                                                     uint32_t* __restrict__ isrep) {
+  constexpr int GL_TL = 2 * GL_CH, GL_PT = GL_CH / NT;
+  static_assert(GL_CH % NT == 0 && (GL_CH & (GL_CH - 1)) == 0, "chunk of whole thread rounds, a power of two");
   __shared__ uint32_t ltab[GL_TL];   // chunk-local representative + 1, 0 = empty
   __shared__ uint32_t lglob[GL_TL];  // global slot of the local group
   __shared__ uint32_t lrep[GL_TL];   // its representative is the global one
@@ -578,15 +604,14 @@ void launch_ingest(const int32_t* idx, const double* val, uint32_t nnz, const Mo
 
 uint32_t norm_partials_count(uint32_t nE) { return grid_for(nE, NT); }
 
-void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, bool check_long, const double* ev,
+void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, int long_bit, const double* ev,
                       uint32_t* flag, double* norm_part, DevStatus* st, hipStream_t s) {
-  k_col_flags<<<grid_for(nE, NT), NT, 0, s>>>(ekey, nE, sh, level1 ? 1 : 0, check_long ? 1 : 0, ev, flag,
-                                              norm_part, st);
+  k_col_flags<<<grid_for(nE, NT), NT, 0, s>>>(ekey, nE, sh, level1 ? 1 : 0, long_bit, ev, flag, norm_part, st);
   TTS_LAUNCH_CHECK();
 }
 
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s) {
-  k_norm_final<<<1, NT, 0, s>>>(part, np, st);
+  k_norm_final<<<1, NF, 0, s>>>(part, np, st);
   TTS_LAUNCH_CHECK();
 }
 
@@ -629,9 +654,20 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
   // per column: read hash, start and row-major key, write slot and flag
   KTimer kt("level_group", s, 32.0 * ncols, 0.0);
   if (ncols >= 16384) {
-    // large levels: chunk-local grouping first (see k_group_local)
-    k_group_local<<<(ncols + GL_CH - 1) / GL_CH, NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table,
-                                                             slotmin, tmask, slot, isrep);
+    // large levels: chunk-local grouping first (see k_group_local), with chunks small
+    // enough for at least 256 workgroups (down to 256 columns)
+#define TTS_GROUP_LOCAL(CH)                                                                                      \
+  k_group_local<CH><<<(ncols + (CH) - 1) / (CH), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, \
+                                                             slotmin, tmask, slot, isrep)
+    if (ncols >= 256u * 2048u)
+      TTS_GROUP_LOCAL(2048);
+    else if (ncols >= 256u * 1024u)
+      TTS_GROUP_LOCAL(1024);
+    else if (ncols >= 256u * 512u)
+      TTS_GROUP_LOCAL(512);
+    else
+      TTS_GROUP_LOCAL(256);
+#undef TTS_GROUP_LOCAL
   } else {
     k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
                                                slot, isrep, 0);

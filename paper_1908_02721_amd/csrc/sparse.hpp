@@ -18,12 +18,12 @@ struct ModeInfo {
 // Small device-side status block, read back once or twice per level.
 struct DevStatus {
   uint32_t err;       // bit 0: index out of range, bit 1: non-finite, bit 2: duplicate
-  uint32_t longcol;   // a level >= 2 column has more than kMaxLocal entries
+  uint32_t pad0;
   uint32_t ncols;     // columns of the current level
   uint32_t beta;      // groups of the current level
   uint32_t nnz_n;     // entries of N_k
   uint32_t dropped;   // explicit zeros among the input entries
-  uint32_t pad0, pad1;
+  unsigned long long longmask;  // bit k - 1: a level-k column has more than kMaxLocal entries
   double norm2;       // ||A||_F^2
 };
 
@@ -36,7 +36,9 @@ void launch_ingest(const int32_t* idx, const double* val, uint32_t nnz, const Mo
 
 // Column starts of a level: flag[e] = 1 where (ekey[e] >> sh) changes.  Level 1
 // also checks duplicates and accumulates ||A||^2 (fixed-order partial sums).
-void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, bool check_long,
+// long_bit >= 0: set bit long_bit of st->longmask if a column has more than kMaxLocal
+// entries (one bit per level, so that nothing needs clearing between levels).
+void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, int long_bit,
                       const double* ev, uint32_t* flag, double* norm_part, DevStatus* st, hipStream_t s);
 uint32_t norm_partials_count(uint32_t nE);
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s);
@@ -67,6 +69,11 @@ struct CanonArgs {
   double* cols;         // prefactor s
   uint64_t* colsuf;     // colex-packed suffix (lowest field = mode k)
   uint64_t* rmkey;      // row-major-ordered suffix key (numbering order)
+  // the grouping's hash table (tsize slots), cleared here for the next step: table to
+  // 0 (empty), slotmin to ~0 (no minimum yet)
+  uint64_t* table;
+  uint64_t* slotmin;
+  uint32_t tsize;
 };
 // a4: canonicalise every column by its entry of smallest row, key and hash it.
 // wide: one workgroup per column (for levels of few, long columns already in row
