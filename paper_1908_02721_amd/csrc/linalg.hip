@@ -2508,20 +2508,33 @@ __global__ __launch_bounds__(NT) void k_permute_cols(const double* __restrict__ 
 }
 
 // One wave per column: entry of largest magnitude (lowest index on ties) made positive.
+// Sign rule on columns of at most kSignRows rows: one workgroup per column finds the
+// entry of largest magnitude (lowest index on ties; each thread's loads issued together)
+// and, if it is negative, flips the column of U and the matching column of VS.
 __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int rows, int r, int ldu,
                                                  double* __restrict__ VS, int vrows, int ldv) {
-  const int j = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= r) return;
+  __shared__ double wb[NT / 64];
+  __shared__ int wi[NT / 64];
+  __shared__ int flip;
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* u = U + static_cast<size_t>(j) * ldu;
   double best = -1.0;
   int bi = rows;
-  for (int i = lane; i < rows; i += 64) {
-    const double a = fabs(u[i]);
-    if (a > best) {
-      best = a;
-      bi = i;
+  constexpr int PER = 4;
+  for (int i0 = threadIdx.x; i0 < rows; i0 += NT * PER) {
+    double a[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int i = i0 + t * NT;
+      a[t] = (i < rows) ? fabs(u[i]) : -1.0;
     }
+#pragma unroll
+    for (int t = 0; t < PER; ++t)
+      if (a[t] > best) {  // rows visited in increasing order per thread: ties keep the lower
+        best = a[t];
+        bi = i0 + t * NT;
+      }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const double ob = __shfl_xor(best, o, 64);
@@ -2531,10 +2544,26 @@ __global__ __launch_bounds__(NT) void k_sign_fix(double* __restrict__ U, int row
       bi = oi;
     }
   }
-  if (bi >= rows || u[bi] >= 0.0) return;
-  for (int i = lane; i < rows; i += 64) u[i] = -u[i];
+  if (lane == 0) {
+    wb[w] = best;
+    wi[w] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = wb[0];
+    int x = wi[0];
+    for (int v = 1; v < NT / 64; ++v)
+      if (wb[v] > b || (wb[v] == b && wi[v] < x)) {
+        b = wb[v];
+        x = wi[v];
+      }
+    flip = (x < rows && u[x] < 0.0) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!flip) return;
+  for (int i = threadIdx.x; i < rows; i += NT) u[i] = -u[i];
   double* v = VS + static_cast<size_t>(j) * ldv;
-  for (int i = lane; i < vrows; i += 64) v[i] = -v[i];
+  for (int i = threadIdx.x; i < vrows; i += NT) v[i] = -v[i];
 }
 
 // Tall columns: each workgroup finds the entry of largest magnitude (lowest index on
@@ -3004,7 +3033,7 @@ void permute_cols(const double* A, int rows, int lda, const int32_t* perm, const
 void sign_fix(double* U, int rows, int r, int ldu, double* VS, int vrows, int ldv, hipStream_t s) {
   if (r <= 0) return;
   if (rows <= kSignRows) {
-    k_sign_fix<<<(r + 3) / 4, NT, 0, s>>>(U, rows, r, ldu, VS, vrows, ldv);
+    k_sign_fix<<<r, NT, 0, s>>>(U, rows, r, ldu, VS, vrows, ldv);
     TTS_LAUNCH_CHECK();
     return;
   }
