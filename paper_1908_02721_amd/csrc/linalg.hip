@@ -2197,7 +2197,16 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
 // GW = 512 / NC lanes; a lane holds 64 / GW rows of a column as double2 pairs.
 // Padded columns are zero and never rotate.  Same rotation, stopping test and output
 // as k_jacobi64.
-template <int NC>
+//
+// ACCV = false is for a square lower-triangular input L (c x c, c = rows), such as
+// R^T from a QR: the rotations are not accumulated (a quarter of a round's work);
+// after convergence the accumulated rotation J = L^{-1} A_final is formed by forward
+// substitution, whose columns are orthonormal to about n u kappa(L).  That is used
+// only when the sweeps converged and sigma_max <= kNoVCond sigma_min; otherwise the
+// kernel writes nothing but info[1] = -1 and leaves A as it was, and the caller runs
+// the ACCV = true kernel.
+constexpr double kNoVCond = 100.0;
+template <int NC, bool ACCV>
 __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
                                                    double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
   __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
@@ -2205,8 +2214,9 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
   constexpr int NTH = 256, LD = 64, GW = 512 / NC, UP = 32 / GW;
   static_assert(NC == 32 || NC == 64, "32 or 64 columns");
   __shared__ double2 sA[NC * LD / 2];  // 64 x NC, column-major (rows >= `rows` zero)
-  __shared__ double2 sV[NC * LD / 2];  // 64 x NC (identity outside the leading c x c block)
+  __shared__ double2 sV[NC * LD / 2];  // 64 x NC: V (identity outside the leading c x c block), or L
   __shared__ int rotated;
+  __shared__ double smax_[NTH / 64], smin_[NTH / 64];
   double* A = reinterpret_cast<double*>(sA);
   double* V = reinterpret_cast<double*>(sV);
   {  // staging: each thread's loads are issued together (clamped addresses)
@@ -2221,7 +2231,8 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + NTH * u, i = e % LD, j = e / LD;
       A[e] = (i < rows && j < c) ? v[u] : 0.0;
-      V[e] = (i == j) ? 1.0 : 0.0;
+      // ACCV: V = I; otherwise a copy of the input (L) for the substitution
+      V[e] = ACCV ? ((i == j) ? 1.0 : 0.0) : A[e];
     }
   }
   __syncthreads();
@@ -2243,7 +2254,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           ka[u] = ap[GW * u];
-          kv[u] = vp[GW * u];
+          if (ACCV) kv[u] = vp[GW * u];
         }
       }
       int qi = i;  // (i + st) mod half, stepped without a division
@@ -2259,7 +2270,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           y[u] = aq[GW * u];
-          if (PRE_V) yv[u] = vq[GW * u];
+          if (ACCV && PRE_V) yv[u] = vq[GW * u];
         }
         double a = 0.0, b = 0.0, g = 0.0;
 #pragma unroll
@@ -2275,17 +2286,20 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
           double cs, sn;
           if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
           jacobi_rotation(a, b, g, &cs, &sn);
-          if (!PRE_V) {
+          if (ACCV && !PRE_V) {
 #pragma unroll
             for (int u = 0; u < UP; ++u) yv[u] = vq[GW * u];
           }
 #pragma unroll
           for (int u = 0; u < UP; ++u) {
-            const double2 x = ka[u], xv = kv[u];
+            const double2 x = ka[u];
             ka[u] = double2{cs * x.x - sn * y[u].x, cs * x.y - sn * y[u].y};
             aq[GW * u] = double2{sn * x.x + cs * y[u].x, sn * x.y + cs * y[u].y};
-            kv[u] = double2{cs * xv.x - sn * yv[u].x, cs * xv.y - sn * yv[u].y};
-            vq[GW * u] = double2{sn * xv.x + cs * yv[u].x, sn * xv.y + cs * yv[u].y};
+            if (ACCV) {
+              const double2 xv = kv[u];
+              kv[u] = double2{cs * xv.x - sn * yv[u].x, cs * xv.y - sn * yv[u].y};
+              vq[GW * u] = double2{sn * xv.x + cs * yv[u].x, sn * xv.y + cs * yv[u].y};
+            }
           }
           any = true;
         }
@@ -2297,7 +2311,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           ap[GW * u] = ka[u];
-          vp[GW * u] = kv[u];
+          if (ACCV) vp[GW * u] = kv[u];
         }
       }
       __syncthreads();
@@ -2310,18 +2324,73 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
     }
     __syncthreads();
   }
+  // column norms (sigma); without V also their extremes, for the condition test
+  double smax = 0.0, smin = HUGE_VAL;
   for (int j = grp; j < c; j += NTH / GW) {
     const double2* aj = sA + j * (LD / 2) + gl;
     double sacc = 0.0;
 #pragma unroll
     for (int u = 0; u < UP; ++u) sacc = fma(aj[GW * u].x, aj[GW * u].x, fma(aj[GW * u].y, aj[GW * u].y, sacc));
     sacc = group_sum<GW>(sacc);
-    if (gl == 0) sigma[j] = sqrt(sacc);
+    const double sj = sqrt(sacc);
+    if (gl == 0) sigma[j] = sj;
+    smax = fmax(smax, sj);
+    smin = fmin(smin, sj);
+  }
+  if (!ACCV) {
+    // every lane of a group holds its columns' values: the wave extremes cover them
+    for (int o = 32; o > 0; o >>= 1) {
+      smax = fmax(smax, __shfl_xor(smax, o, 64));
+      smin = fmin(smin, __shfl_xor(smin, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      smax_[threadIdx.x >> 6] = smax;
+      smin_[threadIdx.x >> 6] = smin;
+    }
+    __syncthreads();
+    double gmx = 0.0, gmn = HUGE_VAL;
+    for (int w = 0; w < NTH / 64; ++w) {
+      gmx = fmax(gmx, smax_[w]);
+      gmn = fmin(gmn, smin_[w]);
+    }
+    const bool use = conv_ && nsw_ > 0 && gmn > 0.0 && gmx <= kNoVCond * gmn;
+    if (!use) {  // uniform: the caller reruns with the rotations accumulated
+      if (threadIdx.x == 0 && info) {
+        info[0] = nsw_;
+        info[1] = -1;
+        *reinterpret_cast<double*>(info + 2) = 0.0;
+      }
+      return;
+    }
+    // J = L^{-1} A_final by forward substitution: 4 lanes per column j, lane `sub`
+    // keeps x_l for l = sub (mod 4) and sums those terms of each row's dot product
+    constexpr int SL = 4, XR = NC / SL;
+    const int j = threadIdx.x / SL, sub = threadIdx.x % SL;
+    if (j < NC) {  // NTH / SL = 64 >= NC column groups; groups past c idle
+      double x[XR];
+#pragma unroll
+      for (int u = 0; u < XR; ++u) x[u] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        if (i < c) {  // uniform
+          double sdot = 0.0;
+#pragma unroll
+          for (int u = 0; u < XR; ++u) {
+            const int l = sub + SL * u;
+            if (l < i) sdot = fma(V[i + LD * l], x[u], sdot);
+          }
+          sdot = group_sum<SL>(sdot);
+          const double xi = (j < c) ? (A[i + LD * j] - sdot) / V[i + LD * i] : 0.0;
+          if (sub == i % SL) x[i / SL] = xi;
+          if (sub == 0 && j < c) Vg[i + static_cast<size_t>(j) * ldv] = xi;
+        }
+      }
+    }
   }
   for (int e = threadIdx.x; e < LD * c; e += NTH) {
     const int i = e % LD, j = e / LD;
     if (i < rows) Ag[i + static_cast<size_t>(j) * lda] = A[e];
-    if (i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
+    if (ACCV && i < c) Vg[i + static_cast<size_t>(j) * ldv] = V[e];
   }
   __syncthreads();
   if (threadIdx.x == 0 && info) {  // sweeps run, whether the last one rotated nothing, its largest |g|
@@ -2908,23 +2977,33 @@ int jacobi_sweep_cap() {
 }
 }  // namespace
 
-void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s) {
+void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s,
+                bool lower_tri) {
   if (c <= 0) return;
   const int ms = jacobi_sweep_cap();
   const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
+  // rotations left unaccumulated (triangular input of 16 < c <= 64 columns)
+  const bool nov = lower_tri && rows == c && c > 16 && c <= 64 && info != nullptr;
   KTimer kt("jacobi", s, 8.0 * 2.0 * (static_cast<double>(rows) * c + static_cast<double>(c) * c),
-            // per sweep: c(c-1)/2 pairs x (3 dots + 2 column updates of A and V); the
-            // timer multiplies it by the sweeps the launch reports in info[0]
-            0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + 6.0 * c));
+            // per sweep: c(c-1)/2 pairs x (3 dots + 2 column updates of A, and of V when
+            // accumulated); the timer multiplies it by the sweeps the launch reports in
+            // info[0]
+            0.5 * static_cast<double>(c) * (c - 1) * (6.0 * rows + 6.0 * rows + (nov ? 0.0 : 6.0 * c)));
   kt.flops_per_count(info);
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
   if (c > 32 && c <= 64 && rows <= 64) {
-    k_jacobi64h<64><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+    if (nov)
+      k_jacobi64h<64, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+    else
+      k_jacobi64h<64, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }
   if (c > 16 && c <= 32 && rows <= 64) {
-    k_jacobi64h<32><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+    if (nov)
+      k_jacobi64h<32, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+    else
+      k_jacobi64h<32, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
     return;
   }

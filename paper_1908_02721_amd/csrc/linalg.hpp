@@ -78,8 +78,13 @@ void householder_extract_r(const double* A, int m, int n, int lda, double* R, in
 // 8-byte aligned, may be null) receives the sweeps run, 1 if the last sweep rotated
 // nothing (converged) or 0 if the sweep cap stopped it, and in info[2..3] the largest
 // |a_p^T a_q| rotated in the last sweep (a double; 0 when converged).
+// lower_tri: A is square and lower triangular (R^T of a QR).  For 16 < c <= 64 the
+// rotations may then be left unaccumulated and V formed afterwards as A^{-1} A_final,
+// when that is accurate (converged, sigma_max <= 100 sigma_min); otherwise info[1] is
+// set to -1, A, V and sigma are left unspecified, and the caller must call again
+// with lower_tri = false on the original matrix (A itself is left unchanged then).
 void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info,
-                hipStream_t s);
+                hipStream_t s, bool lower_tri = false);
 
 // Copy / transpose helpers.
 void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s);

@@ -154,30 +154,39 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   std::vector<double> sh(cB);
   alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
   Readback rb(s);
-  auto svd_of_bt = [&]() {
-    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s);
+  auto svd_of_bt = [&](bool lower_tri) {
+    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s, lower_tri);
     k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
     TTS_LAUNCH_CHECK();
     rb.add(sh.data(), sig.get(), sizeof(double) * cB);
     rb.add(hinfo, jinfo.get(), sizeof(hinfo));
   };
+  // Bt = R^T is lower triangular: the Jacobi may leave its rotations unaccumulated and
+  // form them afterwards; it says so (info[1] = -1) when that would not be accurate
+  auto svd_of_r = [&]() {
+    if (hinfo[1] == -1) {
+      svd_of_bt(false);
+      rb.sync();
+    }
+  };
   if (haveQ) {
     DBuf<double> R(A, static_cast<size_t>(c) * c);
     cholqr2_async(A, G, m, c, Qb.get(), R.get(), okq.get(), s);
     transpose(R.get(), c, c, c, Bt.get(), c, s);
-    svd_of_bt();
+    svd_of_bt(true);
     int32_t okh[4];
     rb.add(okh, okq.get(), sizeof(okh));
     rb.sync();
     if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
       qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
       transpose(R.get(), c, c, c, Bt.get(), c, s);
-      svd_of_bt();
+      svd_of_bt(true);
       rb.sync();
     }
+    svd_of_r();
   } else {
     transpose(G, m, c, m, Bt.get(), c, s);
-    svd_of_bt();
+    svd_of_bt(false);
     rb.sync();
   }
   svd_check(hinfo, sh.data(), cB, c);
