@@ -113,15 +113,33 @@ size_t size_class(size_t bytes) {
 }  // namespace
 
 namespace {
+// The staging buffer is pinned, mapped and coherent host memory: one small kernel
+// writes every pending piece into it (a copy engine transfer per piece costs a blit
+// launch each, about 4 us).
 struct PinnedStage {
-  char* p = nullptr;
+  char* p = nullptr;   // host address
+  char* dp = nullptr;  // the same memory as the device sees it
   size_t cap = 0;
   ~PinnedStage() {
     if (p) (void)hipHostFree(p);
   }
 };
 thread_local PinnedStage g_stage;
-thread_local const Readback* g_stage_owner = nullptr;  // the Readback with pieces in flight
+thread_local const Readback* g_stage_owner = nullptr;  // the Readback with pieces pending
+
+constexpr int kGatherPieces = 8;
+struct GatherList {
+  const uint32_t* src[kGatherPieces];
+  uint32_t off[kGatherPieces];    // in 4-byte words of the staging buffer
+  uint32_t words[kGatherPieces];  // 4-byte words of the piece
+  int n;
+};
+__global__ void k_gather_host(GatherList g, uint32_t* __restrict__ dst) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (int k = 0; k < g.n; ++k)
+    for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < g.words[k]; w += stride)
+      dst[g.off[k] + w] = g.src[k][w];
+}
 }  // namespace
 
 Readback::~Readback() {
@@ -131,28 +149,46 @@ Readback::~Readback() {
 void Readback::add(void* host, const void* dev, size_t bytes) {
   if (!bytes) return;
   if (g_stage_owner && g_stage_owner != this) fail(TT_ERR_DEVICE, "internal: overlapping read-backs on one thread");
+  if ((bytes & 3) || (reinterpret_cast<uintptr_t>(dev) & 3)) fail(TT_ERR_DEVICE, "internal: unaligned read-back");
   const size_t off = (off_ + 255) & ~static_cast<size_t>(255);
   if (off + bytes > g_stage.cap) {
-    // grow: the pieces already enqueued land first
+    // grow: the pieces already pending land first
     sync();
     const size_t cap = std::max<size_t>(size_t(1) << 20, 2 * bytes);
     if (g_stage.p) TTS_HIP(hipHostFree(g_stage.p));
-    g_stage.p = nullptr;
+    g_stage.p = g_stage.dp = nullptr;
     g_stage.cap = 0;
     void* q = nullptr;
-    TTS_HIP(hipHostMalloc(&q, cap, hipHostMallocDefault));
+    TTS_HIP(hipHostMalloc(&q, cap, hipHostMallocMapped | hipHostMallocCoherent));
+    void* dq = nullptr;
+    TTS_HIP(hipHostGetDevicePointer(&dq, q, 0));
     g_stage.p = static_cast<char*>(q);
+    g_stage.dp = static_cast<char*>(dq);
     g_stage.cap = cap;
     add(host, dev, bytes);
     return;
   }
   g_stage_owner = this;
-  TTS_HIP(hipMemcpyAsync(g_stage.p + off, dev, bytes, hipMemcpyDeviceToHost, s_));
-  pend_.push_back(Piece{host, off, bytes});
+  pend_.push_back(Piece{host, dev, off, bytes});
   off_ = off + bytes;
 }
 
 void Readback::sync() {
+  // one gather kernel per kGatherPieces pieces, then one wait
+  for (size_t i = 0; i < pend_.size(); i += kGatherPieces) {
+    GatherList g{};
+    size_t total = 0;
+    for (size_t k = i; k < std::min(pend_.size(), i + kGatherPieces); ++k) {
+      g.src[g.n] = static_cast<const uint32_t*>(pend_[k].dev);
+      g.off[g.n] = static_cast<uint32_t>(pend_[k].off / 4);
+      g.words[g.n] = static_cast<uint32_t>(pend_[k].bytes / 4);
+      total = std::max(total, pend_[k].bytes / 4);
+      ++g.n;
+    }
+    const unsigned blocks = static_cast<unsigned>(std::min<size_t>((total + 255) / 256, 64));
+    k_gather_host<<<std::max(1u, blocks), 256, 0, s_>>>(g, reinterpret_cast<uint32_t*>(g_stage.dp));
+    TTS_LAUNCH_CHECK();
+  }
   TTS_HIP(hipStreamSynchronize(s_));
   for (const Piece& x : pend_) std::memcpy(x.host, g_stage.p + x.off, x.bytes);
   pend_.clear();
@@ -278,9 +314,7 @@ struct Events {
 };
 
 void sync_status(DevStatus* d_st, hipStream_t s) {
-  DevStatus* h = host_status();
-  TTS_HIP(hipMemcpyAsync(h, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-  TTS_HIP(hipStreamSynchronize(s));
+  read_back(host_status(), d_st, 1, s);
 }
 
 // Exact sparse TT: ingest, sort, and parallel-vector rounding level by level.

@@ -59,8 +59,11 @@ uint64_t cache_trim();  // frees every cached block after a device synchronisati
 // Read-backs to the host go through a per-thread pinned buffer: a device-to-host copy
 // into pageable memory is staged by the runtime and costs about 8 us more per round
 // trip (measured: kernel + copy + synchronisation 22.8 us pageable, 14.7 us pinned).
-// add() enqueues a copy on the stream; sync() waits for the stream and then moves
-// every piece to its destination.  One Readback at a time per thread.
+// add() records a piece (device address 4-byte aligned, a multiple of 4 bytes);
+// sync() launches one small kernel on the stream that writes the pending pieces into
+// the buffer, waits for the stream and moves every piece to its destination.  The
+// values read are those the device holds after all work enqueued before sync().
+// One Readback at a time per thread.
 class Readback {
  public:
   explicit Readback(hipStream_t s) : s_(s) {}
@@ -73,6 +76,7 @@ class Readback {
  private:
   struct Piece {
     void* host;
+    const void* dev;
     size_t off, bytes;
   };
   hipStream_t s_;
