@@ -37,6 +37,9 @@ struct RoundOutput {
 // positive diagonal).  ok[0..3] (device) are set to 0 when a Cholesky factor breaks
 // down or is too ill-conditioned; nothing is read back.
 void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s);
+// One (passes = 1) or two CholeskyQR passes; the same flags as cholqr2_async.
+void cholqr_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, int passes,
+                  hipStream_t s);
 
 // Truncated SVD of a column-major m x c matrix (left singular vectors U, m x rank,
 // and V Sigma, c x rank, with the sign rule applied to both).

@@ -41,6 +41,9 @@ namespace {
 
 constexpr double kTheta = 1e-12;   // pivot threshold relative to the largest Gram diagonal
 constexpr double kTauRel = 1e-13;  // per-bond deflation budget relative to ||A||_F
+// largest condition number of a bond factor for which one CholeskyQR pass is kept
+// (orthogonality of Q about u kOnePassCond^2 = 2e-13)
+constexpr double kOnePassCond = 30.0;
 
 __global__ void k_set_f64(double* p, double v) { *p = v; }
 __global__ void k_set_i32(int32_t* p, int n, int32_t v) {
@@ -113,12 +116,24 @@ void svd_check(const int32_t info[4], const double* sigma, int n, int rows) {
 
 // CholeskyQR2 of the column-major m x c matrix G: Q (m x c), R (c x c upper).
 // ok[0..3] (device) are set to 0 when a Cholesky factor breaks down or is too
-// ill-conditioned; nothing is read back here.
+// ill-conditioned; nothing is read back here.  cholqr_async with passes = 1 stops
+// after the first pass: Q is then orthonormal only to about u kappa(G)^2.
 void cholqr2_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, hipStream_t s) {
-  DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
-      g2(al, static_cast<size_t>(c) * c);
+  cholqr_async(al, G, m, c, Q, R, ok, 2, s);
+}
+
+void cholqr_async(Allocator* al, const double* G, int m, int c, double* Q, double* R, int32_t* ok, int passes,
+                  hipStream_t s) {
   k_set_i32<<<1, 64, 0, s>>>(ok, 4, 1);
   TTS_LAUNCH_CHECK();
+  if (passes == 1) {  // Q = G R^{-1} straight into Q, R = chol(G^T G)
+    gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, R, c, s);
+    cholesky_upper(R, c, c, 1e7, ok + 0, s);
+    trsm_right_upper(G, m, c, m, R, c, Q, m, ok + 1, s, al);
+    return;
+  }
+  DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
+      g2(al, static_cast<size_t>(c) * c);
   gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, g1.get(), c, s);
   cholesky_upper(g1.get(), c, c, 1e7, ok + 0, s);
   trsm_right_upper(G, m, c, m, g1.get(), c, q1.get(), m, ok + 1, s, al);
@@ -171,17 +186,36 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   };
   if (haveQ) {
     DBuf<double> R(A, static_cast<size_t>(c) * c);
-    cholqr2_async(A, G, m, c, Qb.get(), R.get(), okq.get(), s);
+    // One CholeskyQR pass first: its Q is orthonormal to about u kappa(G)^2, enough
+    // when kappa(G) <= kOnePassCond.  The singular values read back with the Jacobi
+    // (those of R = those of G) decide; otherwise the bond is redone with CholeskyQR2.
+    cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 1, s);
     transpose(R.get(), c, c, c, Bt.get(), c, s);
     svd_of_bt(true);
     int32_t okh[4];
     rb.add(okh, okq.get(), sizeof(okh));
     rb.sync();
-    if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
-      qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
+    bool two = !(okh[0] && okh[1]) || hinfo[1] != 1;
+    if (!two) {
+      double smax = 0.0, smin = HUGE_VAL;
+      for (double x : sh) {
+        smax = std::max(smax, x);
+        smin = std::min(smin, x);
+      }
+      two = !(smin > 0.0 && smax <= kOnePassCond * smin);
+    }
+    if (two) {
+      cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 2, s);
       transpose(R.get(), c, c, c, Bt.get(), c, s);
       svd_of_bt(true);
+      rb.add(okh, okq.get(), sizeof(okh));
       rb.sync();
+      if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
+        qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
+        transpose(R.get(), c, c, c, Bt.get(), c, s);
+        svd_of_bt(true);
+        rb.sync();
+      }
     }
     svd_of_r();
   } else {
