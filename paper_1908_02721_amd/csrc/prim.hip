@@ -140,11 +140,17 @@ __device__ __forceinline__ uint64_t match_digit(unsigned dig) {
 
 // Per-tile digit histogram: LDS atomic adds (integer counts, so the order of the adds
 // does not matter), all of a thread's keys loaded before any add.  Written digit-major.
+// Per-tile digit counts.  Each wave counts into its own 256 bins, and a row of keys
+// whose digit is the same in every lane of the wave (common in the high digits of
+// structured keys, where per-lane atomics on one bin would serialise) is counted by
+// one lane; the bins are summed per digit at the end.
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
                                                    uint32_t* __restrict__ counts, uint32_t ntiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  __shared__ uint32_t h[RS_NW][256];
+#pragma unroll
+  for (int w = 0; w < RS_NW; ++w) h[w][threadIdx.x] = 0;
   __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t base = static_cast<size_t>(blockIdx.x) * RS_TILE;
   unsigned dig[RS_IPT];
 #pragma unroll
@@ -153,10 +159,19 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* __restrict__ 
     dig[r] = (i < n) ? static_cast<unsigned>((keys[i] >> shift) & 255u) : 256u;
   }
 #pragma unroll
-  for (int r = 0; r < RS_IPT; ++r)
-    if (dig[r] < 256u) atomicAdd(&h[dig[r]], 1u);
+  for (int r = 0; r < RS_IPT; ++r) {
+    const unsigned d0 = __builtin_amdgcn_readfirstlane(dig[r]);
+    if (__ballot(dig[r] != d0) == 0ull) {  // uniform over the wave
+      if (lane == 0 && d0 < 256u) atomicAdd(&h[wv][d0], 64u);
+    } else if (dig[r] < 256u) {
+      atomicAdd(&h[wv][dig[r]], 1u);
+    }
+  }
   __syncthreads();
-  counts[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
+  uint32_t t = 0;
+#pragma unroll
+  for (int w = 0; w < RS_NW; ++w) t += h[w][threadIdx.x];
+  counts[static_cast<size_t>(threadIdx.x) * ntiles + blockIdx.x] = t;
 }
 
 // Exclusive scan of one digit's row of per-tile counts (one workgroup per digit),
