@@ -304,25 +304,29 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* __restrict
 // LDS with coalesced loads, each of the 1024 threads scans a contiguous run, and the
 // runs are combined with a workgroup scan.
 constexpr uint32_t SMALL_SCAN = 16384;
+// One workgroup: thread t scans a contiguous run of `per` elements.  The LDS copy has
+// one padding word per 32, so that the runs of neighbouring threads (a power-of-two
+// stride apart) fall into different banks.
+__device__ __forceinline__ uint32_t scan_pad(uint32_t i) { return i + (i >> 5); }
 __global__ __launch_bounds__(1024) void k_scan_single(const uint32_t* in, uint32_t* out, uint32_t n,
                                                       uint32_t* __restrict__ d_total) {
-  __shared__ uint32_t buf[SMALL_SCAN];
+  __shared__ uint32_t buf[SMALL_SCAN + SMALL_SCAN / 32];
   __shared__ uint32_t lds[1024 / 64];
-  for (uint32_t i = threadIdx.x; i < n; i += 1024) buf[i] = in[i];
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) buf[scan_pad(i)] = in[i];
   __syncthreads();
   const uint32_t per = (n + 1023) / 1024;
   const uint32_t b = min(n, threadIdx.x * per), e = min(n, b + per);
   uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += buf[i];
+  for (uint32_t i = b; i < e; ++i) sum += buf[scan_pad(i)];
   uint32_t tot;
   uint32_t run = block_excl_scan_u32<1024>(sum, lds, &tot);
   for (uint32_t i = b; i < e; ++i) {
-    const uint32_t v = buf[i];
-    buf[i] = run;
+    const uint32_t v = buf[scan_pad(i)];
+    buf[scan_pad(i)] = run;
     run += v;
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += 1024) out[i] = buf[i];
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) out[i] = buf[scan_pad(i)];
   if (threadIdx.x == 0 && d_total) *d_total = tot;
 }
 
