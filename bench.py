@@ -13,7 +13,8 @@ as it needs only the coordinates; --no-overlap builds it afterwards):
   tt_eval_plan_forward  the TT at every nonzero coordinate (left products kept)
   tt_eval_plan_backward gradient of sum_n val[n] * TT(i_n) w.r.t. every core
 The FP64 run also times the FP32 form of the same step ("mixed"), the sparse stage
-against HBM ("roofline.sparse_hbm") and the bond-2 Gram slice on the 5-way 200^5
+against HBM ("roofline.sparse_hbm"; inside the step, and with the decomposition run
+by itself after the timed steps, "t_ms_alone" / "stage_ms_alone") and the bond-2 Gram slice on the 5-way 200^5
 tensor with 10^7 nonzeros in FP64/FP32/BF16 ("c4_slice": its Gram kernel against the
 FP64 matrix-core peak, errors against oracle values stored in tests/golden).
 With --matrix-input (the Laplacian workload) the step starts from the sparse matrix
@@ -560,9 +561,26 @@ def main():
         t_sparse = stage_med["ingest"] + stage_med["sort"] + stage_med["sparse_levels"]
         gbps = b_alg / (t_sparse / 1000.0) / 1e9
         cp = copy_gbps()
+        # the same decomposition alone, without the plan's sort and trie beside it on
+        # the GPU: what the stage itself takes
+        alone = []
+        for _ in range(args.steps):
+            tta = tts.decompose(gi, gv, dims, eps, precision=args.precision, dynamic_delta=args.dynamic_delta,
+                                key_bits=args.key_bits)
+            alone.append(tta.times_ms)
+            del tta
+        alone_med = {k: float(np.median([st[k] for st in alone])) for k in alone[0]}
+        t_alone = alone_med["ingest"] + alone_med["sort"] + alone_med["sparse_levels"]
+        gbps_alone = b_alg / (t_alone / 1000.0) / 1e9
+        out["decompose_alone_ms_median"] = alone_med["total"]
+        out["stage_ms_alone"] = alone_med
         out.setdefault("roofline", {})["sparse_hbm"] = {
             "bound": "hbm", "algo_bytes": b_alg, "t_ms": t_sparse, "achieved": gbps, "unit": "GB/s",
             "peak": HBM_PEAK_GBS, "frac": gbps / HBM_PEAK_GBS, "copy_GBps": cp, "frac_of_copy": gbps / cp,
+            "t_ms_alone": t_alone, "achieved_alone": gbps_alone, "frac_alone": gbps_alone / HBM_PEAK_GBS,
+            "frac_of_copy_alone": gbps_alone / cp,
+            "note": "t_ms: inside the step, with the evaluation plan built beside it on a second stream; "
+                    "t_ms_alone: the decomposition run by itself",
             "level_sizes": tt.level_sizes()}
     mixed_tt = None
     if args.precision == "fp64" and not args.no_mixed:

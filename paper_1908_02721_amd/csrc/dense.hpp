@@ -49,6 +49,12 @@ struct SvdPart {
   std::vector<double> sigma;   // c singular values, non-ascending
   double tail = 0.0;           // discarded sum of sigma^2
   int rank = 0;
+  // the path taken: CholeskyQR passes of the final R (0: no QR, m <= c; 3: Householder
+  // after CholeskyQR2 broke down), Jacobi runs, and whether the final one formed V by
+  // substitution instead of accumulating the rotations
+  int qr_passes = 0;
+  int jacobi_runs = 0;
+  bool v_substituted = false;
 };
 void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,
                    hipStream_t s);

@@ -2202,10 +2202,9 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
 // R^T from a QR: the rotations are not accumulated (a quarter of a round's work);
 // after convergence the accumulated rotation J = L^{-1} A_final is formed by forward
 // substitution, whose columns are orthonormal to about n u kappa(L).  That is used
-// only when the sweeps converged and sigma_max <= kNoVCond sigma_min; otherwise the
-// kernel writes nothing but info[1] = -1 and leaves A as it was, and the caller runs
-// the ACCV = true kernel.
-constexpr double kNoVCond = 100.0;
+// only when the sweeps converged and sigma_max <= kJacobiNoVCond sigma_min; otherwise
+// the kernel writes only sigma and info (info[1] = -1), leaves A as it was, and the
+// caller runs the ACCV = true kernel.
 template <int NC, bool ACCV>
 __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
                                                    double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
@@ -2353,7 +2352,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
       gmx = fmax(gmx, smax_[w]);
       gmn = fmin(gmn, smin_[w]);
     }
-    const bool use = conv_ && nsw_ > 0 && gmn > 0.0 && gmx <= kNoVCond * gmn;
+    const bool use = conv_ && nsw_ > 0 && gmn > 0.0 && gmx <= kJacobiNoVCond * gmn;
     if (!use) {  // uniform: the caller reruns with the rotations accumulated
       if (threadIdx.x == 0 && info) {
         info[0] = nsw_;
@@ -2977,9 +2976,9 @@ int jacobi_sweep_cap() {
 }
 }  // namespace
 
-void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s,
+bool jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s,
                 bool lower_tri) {
-  if (c <= 0) return;
+  if (c <= 0) return false;
   const int ms = jacobi_sweep_cap();
   const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
   // rotations left unaccumulated (triangular input of 16 < c <= 64 columns)
@@ -2997,7 +2996,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     else
       k_jacobi64h<64, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return nov;
   }
   if (c > 16 && c <= 32 && rows <= 64) {
     if (nov)
@@ -3005,13 +3004,13 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     else
       k_jacobi64h<32, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return nov;
   }
   if (c <= 64 && rows <= 64) {
     k_jacobi64<<<1, 256, sizeof(double) * 128 * static_cast<size_t>(c), s>>>(A, rows, c, lda, V, ldv, sigma, ms,
                                                                                info);
     TTS_LAUNCH_CHECK();
-    return;
+    return false;
   }
   if (shm_odd <= 150 * 1024 && c <= 64 && rows <= 256) {
     if (rows <= 128)
@@ -3019,7 +3018,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     else
       k_jacobi_reg<32, 8><<<1, 1024, shm_odd, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return false;
   }
   // A and V in registers: 64 < c <= 128 columns of at most 128 rows
   if (c > 64 && c <= 128 && rows <= 128) {
@@ -3027,7 +3026,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     k_jacobi_oe<8><<<1, 1024, sizeof(double) * 2 * 8 * 16 * static_cast<size_t>(H), s>>>(A, rows, c, lda, V, ldv,
                                                                                          sigma, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return false;
   }
   // A in LDS with the rotations logged, then V in LDS: up to 138 columns
   if (shm > 150 * 1024 && c <= 138 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
@@ -3041,20 +3040,20 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
                                                       std::min(ms, kMaxSweeps), info);
     TTS_LAUNCH_CHECK();
     cached_free(lg, lbytes, s);
-    return;
+    return false;
   }
   // A in LDS, V in global memory: up to 160 columns
   if (shm > 150 * 1024 && c <= 160 && rows <= 160 && sizeof(double) * static_cast<size_t>(rows) * c <= 150 * 1024) {
     k_jacobi_lv<1024, 16, 10><<<1, 1024, sizeof(double) * static_cast<size_t>(rows) * c, s>>>(A, rows, c, lda, V,
                                                                                              ldv, sigma, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return false;
   }
   if (shm <= 150 * 1024 || c <= 2 * BJ_B) {
     const int use_lds = shm <= 150 * 1024;
     k_jacobi<BT, 16><<<1, BT, use_lds ? shm : 0, s>>>(A, rows, c, lda, V, ldv, sigma, use_lds, ms, info);
     TTS_LAUNCH_CHECK();
-    return;
+    return false;
   }
   // wide: block Jacobi, one launch per round of block pairs
   const size_t bshm = sizeof(double) * 2 * BJ_B * (static_cast<size_t>(rows) + c);
@@ -3088,6 +3087,7 @@ void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
     k_set_info<<<1, 1, 0, s>>>(info, sweeps, hflag ? 0 : 1);
     TTS_LAUNCH_CHECK();
   }
+  return false;
 }
 
 void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s) {

@@ -6,6 +6,11 @@
 
 namespace tts {
 
+// Largest sigma_max / sigma_min for which the Jacobi SVD of a triangular factor forms
+// V by substitution instead of accumulating the rotations (V orthonormal to about
+// n u kappa).
+constexpr double kJacobiNoVCond = 100.0;
+
 // C = alpha * op(A) * op(B) + beta * C;  op(A) is m x k, op(B) is k x n.
 // Split-K with a fixed-order reduction when the output is small (deterministic).
 void gemm(Allocator* al, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
@@ -80,10 +85,12 @@ void householder_extract_r(const double* A, int m, int n, int lda, double* R, in
 // |a_p^T a_q| rotated in the last sweep (a double; 0 when converged).
 // lower_tri: A is square and lower triangular (R^T of a QR).  For 16 < c <= 64 the
 // rotations may then be left unaccumulated and V formed afterwards as A^{-1} A_final,
-// when that is accurate (converged, sigma_max <= 100 sigma_min); otherwise info[1] is
-// set to -1, A, V and sigma are left unspecified, and the caller must call again
-// with lower_tri = false on the original matrix (A itself is left unchanged then).
-void jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info,
+// when that is accurate (converged, sigma_max <= kJacobiNoVCond sigma_min); otherwise
+// info[1] is set to -1, V is left unspecified, sigma holds the column norms the
+// sweeps reached (the singular values when they converged), and the caller must call
+// again with lower_tri = false on the original matrix (A is left unchanged then).
+// Returns whether the launch left the rotations unaccumulated (lower_tri honoured).
+bool jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info,
                 hipStream_t s, bool lower_tri = false);
 
 // Copy / transpose helpers.

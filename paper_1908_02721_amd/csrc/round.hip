@@ -41,6 +41,7 @@ namespace {
 
 constexpr double kTheta = 1e-12;   // pivot threshold relative to the largest Gram diagonal
 constexpr double kTauRel = 1e-13;  // per-bond deflation budget relative to ||A||_F
+constexpr double kUnitRoundoff = 0x1p-53;
 // largest condition number of a bond factor for which one CholeskyQR pass is kept
 // (orthogonality of Q about u kOnePassCond^2 = 2e-13)
 constexpr double kOnePassCond = 30.0;
@@ -169,8 +170,10 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   std::vector<double> sh(cB);
   alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
   Readback rb(s);
+  bool last_tri = false;
   auto svd_of_bt = [&](bool lower_tri) {
-    jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s, lower_tri);
+    last_tri = jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s, lower_tri);
+    ++o.jacobi_runs;
     k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
     TTS_LAUNCH_CHECK();
     rb.add(sh.data(), sig.get(), sizeof(double) * cB);
@@ -188,32 +191,37 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     DBuf<double> R(A, static_cast<size_t>(c) * c);
     // One CholeskyQR pass first: its Q is orthonormal to about u kappa(G)^2, enough
     // when kappa(G) <= kOnePassCond.  The singular values read back with the Jacobi
-    // (those of R = those of G) decide; otherwise the bond is redone with CholeskyQR2.
+    // (those of R = those of G; written also when the Jacobi declined to form V)
+    // decide; otherwise the bond is redone with CholeskyQR2, and beyond
+    // kJacobiNoVCond its Jacobi accumulates the rotations at once.
     cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 1, s);
+    o.qr_passes = 1;
     transpose(R.get(), c, c, c, Bt.get(), c, s);
     svd_of_bt(true);
     int32_t okh[4];
     rb.add(okh, okq.get(), sizeof(okh));
     rb.sync();
-    bool two = !(okh[0] && okh[1]) || hinfo[1] != 1;
-    if (!two) {
-      double smax = 0.0, smin = HUGE_VAL;
-      for (double x : sh) {
-        smax = std::max(smax, x);
-        smin = std::min(smin, x);
-      }
-      two = !(smin > 0.0 && smax <= kOnePassCond * smin);
+    double smax = 0.0, smin = HUGE_VAL;
+    for (double x : sh) {
+      smax = std::max(smax, x);
+      smin = std::min(smin, x);
     }
+    // false for non-finite values of a broken-down first pass
+    const bool finite = okh[0] && okh[1] && smin > 0.0 && smax < HUGE_VAL;
+    const bool two = !(finite && hinfo[1] == 1 && smax <= kOnePassCond * smin);
     if (two) {
+      const bool tri = finite && smax <= kJacobiNoVCond * smin;
       cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 2, s);
+      o.qr_passes = 2;
       transpose(R.get(), c, c, c, Bt.get(), c, s);
-      svd_of_bt(true);
+      svd_of_bt(tri);
       rb.add(okh, okq.get(), sizeof(okh));
       rb.sync();
       if (!(okh[0] && okh[1] && okh[2] && okh[3])) {
         qr_explicit(A, G, m, c, m, Qb.get(), m, R.get(), c, s);
+        o.qr_passes = 3;
         transpose(R.get(), c, c, c, Bt.get(), c, s);
-        svd_of_bt(true);
+        svd_of_bt(tri);
         rb.sync();
       }
     }
@@ -224,6 +232,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     rb.sync();
   }
   svd_check(hinfo, sh.data(), cB, c);
+  o.v_substituted = last_tri && hinfo[1] == 1;
   // the same stable non-ascending order as k_rank_desc
   std::vector<int32_t> perm(cB);
   std::iota(perm.begin(), perm.end(), 0);
@@ -295,6 +304,18 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   // the same threshold certifies the deflation in the reduced modes, whose FP32/BF16
   // contractions start with the truncated SVD sweep.
   const double tau = std::min(1e-2 * in.delta, std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
+  // At very small eps, 1% of delta can lie below what the residual of any FP64 basis
+  // reads, the exact QR's included: about sqrt(r) u ||A||_F for a basis of r columns
+  // (rounding of Q^T X and Q W').  A basis of r columns is then also accepted at
+  // min(4 sqrt(r) u ||A||_F, delta / 4), which drops at most 1/16 of the bond's
+  // truncation budget delta^2, so that such bonds keep their numerical rank instead
+  // of taking the exact QR's full rank into the SVD sweep.
+  auto tau_for = [&](int rsel) {
+    if (!(tau > 0.0)) return tau;
+    const double fl = std::min(4.0 * std::sqrt(static_cast<double>(rsel)) * kUnitRoundoff * in.norm,
+                                  0.25 * in.delta);
+    return std::min(std::max(tau, fl), std::max(kTauRel, 4.0 * in.snap_rel) * in.norm);
+  };
   std::vector<int64_t> r(d + 1, 1);
   std::vector<DBuf<char>> cores(d);
 
@@ -333,12 +354,13 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
   struct Pending {
     bool active = false;
     int k = 0, rows = 0, cols = 0;
+    double tau = 0.0;  // acceptance threshold of its basis
     DBuf<double> X, Q, e2;
     DBuf<int32_t> ok;
   } pend;
   int32_t pok[4];
   double pe2 = 0.0;
-  auto pending_accepted = [&]() { return pok[1] && pok[2] && pok[3] && pe2 <= tau * tau; };
+  auto pending_accepted = [&]() { return pok[1] && pok[2] && pok[3] && pe2 <= pend.tau * pend.tau; };
   int k = 1;
   double t_bond = host_ms();
   while (k <= d - 1) {
@@ -372,7 +394,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       pend.active = false;
       logf("QR bond %d: deflation to rank %lld %s (residual %.3e ||A||, threshold %.3e ||A||)", pend.k,
            static_cast<long long>(r[pend.k]), pending_accepted() ? "accepted" : "rejected, exact QR",
-           std::sqrt(pe2) / in.norm, tau / in.norm);
+           std::sqrt(pe2) / in.norm, pend.tau / in.norm);
       if (!pending_accepted()) {
         exact_bond(pend.k, pend.X, pend.rows, pend.cols);
         k = pend.k + 1;  // this bond again, from the exact factor
@@ -423,6 +445,7 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
       r[k] = rsel;
       pend.active = true;
       pend.k = k;
+      pend.tau = tau_for(rsel);
       pend.rows = rows;
       pend.cols = cols;
       pend.X = std::move(X);
@@ -471,8 +494,10 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     out.bond_delta[k - 2] = std::sqrt(delta2);
     SvdPart sv;
     truncated_svd(A, prec, reinterpret_cast<const double*>(cores[k - 1].get()), m, rl, delta2, in.max_rank, sv, s);
-    logf("SVD bond %d: %d x %d, rank %d, discarded sum of sigma^2 %.3e ||A||^2 (threshold^2 %.3e), %.3f ms (host)",
-         k - 1, m, rl, sv.rank, sv.tail / (in.norm * in.norm), delta2 / (in.norm * in.norm), host_ms() - t_bond);
+    logf("SVD bond %d: %d x %d, rank %d, discarded sum of sigma^2 %.3e ||A||^2 (threshold^2 %.3e), "
+         "QR passes %d, Jacobi runs %d, V %s, %.3f ms (host)",
+         k - 1, m, rl, sv.rank, sv.tail / (in.norm * in.norm), delta2 / (in.norm * in.norm), sv.qr_passes,
+         sv.jacobi_runs, sv.v_substituted ? "by substitution" : "accumulated", host_ms() - t_bond);
     t_bond = host_ms();
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;

@@ -15,6 +15,8 @@ Workloads (sizes are those of the sparse-tensor experiments the method targets):
   has ``q`` nonzeros drawn from the dyadic grid {16..48}/32, so products of d <= 8
   factors and their sums are exact in binary64 and parallel columns stay exactly
   parallel (heavy parallel-column structure).
+* ``orthogonal_terms`` -- rank-1 terms with disjoint supports and geometrically
+  spaced weights: every unfolding has a known spectrum of a chosen condition number.
 * ``laplacian_qtt``  -- the 2D Dirichlet 5-point Laplacian on a 2^L x 2^L grid as a
   2L-way tensor with modes of size 4 (quantized TT / matrix-in-TT layout: row and
   column bits interleaved, x bits first, most significant bit first).
@@ -32,6 +34,7 @@ __all__ = [
     "random_sparse",
     "kronecker_sum",
     "noisy_kronecker",
+    "orthogonal_terms",
     "laplacian_matrix",
     "laplacian_qtt",
     "fdm3d_matrix",
@@ -103,6 +106,31 @@ def kronecker_sum(d: int, n: int, terms: int, q: int, seed: int, continuous: boo
     acc = np.zeros(uniq.size, dtype=np.float64)
     np.add.at(acc, inv, v)
     return unravel(uniq, dims), acc, dims
+
+
+def orthogonal_terms(d: int, terms: int, q: int, kappa: float, seed: int):
+    """Sum of ``terms`` rank-1 terms with pairwise disjoint supports in every mode.
+
+    Mode size ``terms * q``; each factor is ``q`` ones on its own block of indices
+    (blocks scattered by a random permutation per mode); term t carries the weight
+    w_t = kappa^(t / (terms - 1)), the weights shuffled over the terms.  Every
+    unfolding then has exactly the singular values w_t q^(d/2) (the terms are
+    orthogonal in every unfolding), so its condition number is ``kappa``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = terms * q
+    dims = (n,) * d
+    perms = [rng.permutation(n) for _ in range(d)]
+    w = kappa ** (np.arange(terms) / max(terms - 1, 1))
+    w = w[rng.permutation(terms)]
+    local = np.stack(np.meshgrid(*([np.arange(q)] * d), indexing="ij"), -1).reshape(-1, d)
+    idx = np.concatenate([_perms_apply(perms, t * q + local) for t in range(terms)]).astype(np.int32)
+    val = np.repeat(w, q ** d).astype(np.float64)
+    return idx, val, dims
+
+
+def _perms_apply(perms, idx):
+    return np.stack([perms[k][idx[:, k]] for k in range(idx.shape[1])], 1)
 
 
 def noisy_kronecker(seed: int, noise: float, d: int = 4, n: int = 6, terms: int = 5, q: int = 3):

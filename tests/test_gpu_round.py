@@ -126,6 +126,45 @@ def test_fdm_random_table2(oracle_mod):
     assert tt.ranks == [1, 28, 28, 1]
 
 
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("n,rank", [(20, 58), (30, 88)])
+def test_fdm_random_at_the_rounding_floor(oracle_mod, n, rank):
+    """Table 2's random FDM matrices at eps = 1e-14: 1% of delta lies below what the
+    residual of any FP64 basis reads, so the deflation is accepted at the rounding
+    floor (4 sqrt(r) u ||A||_F, at most delta / 4) and the bonds keep their numerical
+    ranks instead of the exact QR's full ones.  Parity with the oracle's exact QR."""
+    idx, val, dims = synth.fdm3d_mpo(n, "random", seed=1)
+    tt, res = check_round(oracle_mod, idx, val, dims, 1e-14, f"fdm n={n} random")
+    print(f"[round parity] qr ranks gpu {tt.qr_ranks} oracle {res.qr_ranks}", flush=True)
+    assert tt.ranks == [1, rank, rank, 1]
+    assert tt.qr_ranks == [1, rank, rank, 1]
+
+
+@pytest.mark.timeout(400)
+def test_fdm_n40_random_against_fiber_trie_oracle(oracle_mod):
+    """The largest random FDM case of Table 2 (438,400 nonzeros, modes of 1600) on the
+    column-parallel path, against the fiber-trie oracle (the same TT-SVD ranks and
+    singular values at small eps, the remark after Algorithm 7): ranks, singular
+    values and the represented tensor within 1e-12 ||A||_F."""
+    from oracle import ftt as oftt
+
+    tts = _tt()
+    idx, val, dims = synth.fdm3d_mpo(40, "random", seed=1)
+    print("[round parity] fdm n=40 random, column-parallel vs fiber-trie oracle", flush=True)
+    res = oftt.decompose(idx, val, dims, 1e-14, p=2)
+    gi, gv = _gpu(idx, val)
+    tt = tts.decompose(gi, gv, dims, 1e-14)
+    nrm = res.norm
+    assert tt.ranks == res.ranks == [1, 118, 118, 1]
+    for b in (1, 2):
+        sg, so = tt.sigma(b)[0], res.sigma[b - 1]
+        m = min(len(sg), len(so))
+        assert np.max(np.abs(sg[:m] - so[:m])) <= TOL * nrm, b
+    cores = [c.cpu().numpy() for c in tt.cores]
+    diff = oracle_mod.tt_diff_norm(cores, [np.ascontiguousarray(c) for c in res.cores])
+    assert diff <= TOL * nrm, f"||B_gpu - B_oracle|| = {diff / nrm:.3e} ||A||"
+
+
 def test_random4d_n20_nnz1k(oracle_mod):
     idx, val, dims, eps = synth.workload("random4d_n20_nnz1k")
     tt, res = check_round(oracle_mod, idx, val, dims, eps, "random4d_n20_nnz1k", dense=True)
@@ -298,3 +337,80 @@ def test_progress_log():
         assert f"[ttsparse] level {k}:" in r.stderr
         assert f"[ttsparse] SVD bond {k}:" in r.stderr
         assert f"[ttsparse] QR bond {k}:" in r.stderr
+
+
+# ---- truncated-SVD paths by condition number ----
+#
+# Rank-1 terms with disjoint supports: every bond of the SVD sweep gets a factor of
+# known condition number kappa (the weights' spread), c = terms columns, m > c rows.
+# The truncated SVD takes one CholeskyQR pass when kappa <= 30, CholeskyQR2 above;
+# the Jacobi on R^T forms V by substitution when kappa <= 100 (for 16 < c <= 64),
+# and accumulates the rotations above; when CholeskyQR breaks down, Householder.
+SVD_PATHS = [
+    # (terms, kappa, QR passes, Jacobi runs, V by substitution); None: not asserted
+    (40, 10.0, 1, 1, True),
+    (40, 60.0, 2, 2, True),
+    (40, 1000.0, 2, 2, False),
+    (24, 10.0, 1, 1, True),
+    (24, 60.0, 2, 2, True),
+    (24, 1000.0, 2, 2, False),
+    (40, 1e9, None, None, False),
+]
+
+
+@pytest.mark.parametrize("terms,kappa,passes,runs,subst", SVD_PATHS)
+@pytest.mark.parametrize("eps", [1e-12, 0.05])
+def test_svd_paths_by_condition_number(oracle_mod, terms, kappa, passes, runs, subst, eps):
+    d, q = 4, 2
+    idx, val, dims = synth.orthogonal_terms(d, terms, q, kappa, seed=terms)
+    tt, _ = check_round(oracle_mod, idx, val, dims, eps, f"orthogonal terms T={terms} kappa={kappa:g}")
+    if eps < 1e-10:
+        # nothing is truncated: every bond keeps all terms, with the closed-form spectrum
+        assert tt.ranks == [1] + [terms] * (d - 1) + [1]
+        expect = np.sort(kappa ** (np.arange(terms) / (terms - 1)))[::-1] * q ** (d / 2)
+        nrm = float(np.sqrt(np.sum(expect ** 2)))
+        for b in range(1, d):
+            assert np.max(np.abs(tt.sigma(b)[0][:terms] - expect)) <= TOL * nrm, b
+
+
+def test_svd_path_log():
+    # The progress log (TTSPARSE_LOG=1, read once per process, hence one child
+    # process for all cases) names the path each bond took: the cases above must take
+    # the one their condition number selects.
+    import os
+    import re
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cases = [(t, k) for t, k, _, _, _ in SVD_PATHS]
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch\n"
+        "import paper_1908_02721_amd as tts\n"
+        "from paper_1908_02721_amd import synth\n"
+        "for i, (t, k) in enumerate(%r):\n"
+        "    idx, val, dims = synth.orthogonal_terms(4, t, 2, k, seed=t)\n"
+        "    print('CASE', i, file=sys.stderr, flush=True)\n"
+        "    tts.decompose(torch.from_numpy(idx).cuda(), torch.from_numpy(val).cuda(), dims, 1e-12)\n"
+        "print('CASE end', file=sys.stderr, flush=True)\n" % (root, cases))
+    env = dict(os.environ, TTSPARSE_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    blocks = r.stderr.split("CASE ")[1:]
+    assert len(blocks) == len(cases) + 1, r.stderr[-3000:]
+    pat = re.compile(r"SVD bond (\d+): (\d+) x (\d+), .*QR passes (\d+), Jacobi runs (\d+), V (by substitution|"
+                     r"accumulated)")
+    for (terms, kappa, passes, runs, subst), blk in zip(SVD_PATHS, blocks):
+        found = pat.findall(blk)
+        print(f"[svd path] T={terms} kappa={kappa:g}: {found}", flush=True)
+        assert len(found) == 3
+        for bond, m, c, p, j, v in found:
+            assert int(c) == terms and int(m) > terms
+            if passes is not None:
+                assert int(p) == passes, (terms, kappa, bond, p)
+            else:
+                assert int(p) >= 2, (terms, kappa, bond, p)
+            if runs is not None:
+                assert int(j) == runs, (terms, kappa, bond, j)
+            assert (v == "by substitution") == subst, (terms, kappa, bond, v)

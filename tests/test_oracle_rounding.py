@@ -195,3 +195,20 @@ def test_dynamic_delta_two_modes_is_static(oracle_mod):
         assert st.ranks == dy.ranks
         for a, b in zip(st.cores, dy.cores):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kappa", [10.0, 60.0, 1000.0, 1e9])
+def test_known_spectrum_of_orthogonal_terms(oracle_mod, kappa):
+    # Rank-1 terms with pairwise disjoint supports in every mode are orthogonal in
+    # every unfolding: bond b has exactly the singular values w_t q^(d/2) (Sec. 3.3:
+    # TT-ranks are the unfolding ranks), whatever the spread of the weights.
+    d, T, q = 4, 12, 2
+    idx, val, dims = synth.orthogonal_terms(d, T, q, kappa, seed=3)
+    res = oracle_mod.decompose(idx, val, dims, 1e-14)
+    expect = np.sort(kappa ** (np.arange(T) / (T - 1)))[::-1] * q ** (d / 2)
+    assert abs(res.norm - np.sqrt(np.sum(expect ** 2))) <= 1e-14 * res.norm
+    assert res.ranks == [1] + [T] * (d - 1) + [1]
+    for b in range(d - 1):
+        s = np.asarray(res.sigma[b])
+        assert np.max(np.abs(s[:T] - expect)) <= 1e-14 * res.norm, b
+        assert np.all(s[T:] <= 1e-14 * res.norm)
