@@ -860,6 +860,278 @@ __global__ __launch_bounds__(NTH) void k_pivchol_lds(const double* __restrict__ 
   if (threadIdx.x == 0) *d_r = r;
 }
 
+// Blocked left-looking pivoted Cholesky by one PB_NTH-thread workgroup.  A round takes
+// up to PB_KB candidates at once: the live column of largest Schur diagonal d_max
+// (lowest index on ties) and, in index order, the other live columns with
+// d_j >= PB_GAMMA d_max.  One wave factors the candidates' Schur block in that order,
+// accepting a candidate only while its updated diagonal is still above the threshold
+// and >= PB_GAMMA d_max, and every other column's new entries follow from one
+// triangular solve with the accepted pivots' factor.  So each pivot's diagonal is
+// within PB_GAMMA of the largest Schur diagonal at its step (threshold pivoting;
+// greedy pivoting is PB_GAMMA = 1), with five barriers a round instead of two per
+// pivot.  Same threshold, stopping rule and output layout as k_pivoted_cholesky
+// (L is n x r with leading dimension n, piv[t] the column of pivot t); the pivots may
+// come in another order.  Dynamic LDS: the Schur diagonal (n doubles) and the
+// candidates' rows of L (PB_KB x rmax doubles).
+constexpr int PB_NTH = 512, PB_KB = 8;  // KB * KB = one wave
+constexpr int PB_QT = 2;                 // 16-row tiles a wave takes at a time
+constexpr int PB_KS = 4;                // matrix-core steps (of 4 columns) per load batch
+constexpr double PB_GAMMA = 0.25;
+__global__ __launch_bounds__(PB_NTH) void k_pivchol_block(const double* __restrict__ G, int n, int ldg, int rmax,
+                                                          double theta, double* __restrict__ L,
+                                                          int32_t* __restrict__ piv, int32_t* __restrict__ d_r) {
+  constexpr int NTH = PB_NTH, NW = NTH / 64, KB = PB_KB, SQ = NTH / (KB * KB);
+  static_assert(KB * KB == 64 && SQ >= 1 && SQ <= 16, "one wave holds the candidates' block");
+  extern __shared__ double sm[];
+  double* dg = sm;         // n: Schur diagonal, -1 once pivoted
+  double* crow = sm + n;   // KB x rmax: the candidates' rows of L (entries l < t)
+  __shared__ double S[KB][KB];    // the candidates' Schur block (lower part)
+  __shared__ double Lpp[KB][KB];  // factor of the accepted pivots, in acceptance order
+  __shared__ double rdg[KB];      // 1 / Lpp[i][i]
+  __shared__ double Ht[NW][16 * PB_QT][KB + 1];  // each wave's products, padded
+  __shared__ int cand[KB], pcand[KB], pcol[KB];  // candidates; accepted i -> candidate, column
+  __shared__ int nctl[2];                        // candidates, accepted
+  __shared__ double slotv[NW];
+  __shared__ int sloti[NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the diagonal of G, its largest entry and column (lowest index on ties), every thread
+  auto block_argmax = [&](double* pv, int* pi) {
+    double v = -1.0;
+    int idx = n;
+    for (int j = threadIdx.x; j < n; j += NTH) {
+      const double x = G[j + static_cast<size_t>(j) * ldg];
+      dg[j] = x;
+      if (x > v) {
+        v = x;
+        idx = j;
+      }
+    }
+    double wv;
+    int wl;
+    wave_argmax_lane(v, &wv, &wl);
+    int widx = __builtin_amdgcn_readlane(idx, wl);
+    if (n > NTH) {  // a lower lane may hold a later index with the same value
+      int c = (v == wv) ? idx : n;
+      for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o, 64));
+      widx = c;
+    }
+    if (lane == 0) {
+      slotv[w] = wv;
+      sloti[w] = widx;
+    }
+    __syncthreads();
+    slot_argmax<NW>(slotv, sloti, pv, pi);
+  };
+  double dmax;
+  int am;
+  block_argmax(&dmax, &am);
+  const double thr = theta * dmax;
+  int t = 0;
+  for (;;) {
+    if (t > 0) slot_argmax<NW>(slotv, sloti, &dmax, &am);  // written by the last round
+    if (!(dmax > thr) || t >= rmax) break;  // uniform
+    const int cap = min(KB, rmax - t);
+    // candidates: the largest first, then the others >= PB_GAMMA d_max in index order
+    if (w == 0) {
+      int cnt = 1;
+      for (int j0 = 0; j0 < n && cnt < cap; j0 += 64) {
+        const int j = j0 + lane;
+        const double x = (j < n) ? dg[j] : -1.0;
+        const bool c = j != am && x > thr && x >= PB_GAMMA * dmax;
+        const uint64_t m = __ballot(c);
+        const int pos = cnt + __popcll(m & lanemask_lt());
+        if (c && pos < cap) cand[pos] = j;
+        cnt = min(cap, cnt + __popcll(m));
+      }
+      if (lane == 0) {
+        cand[0] = am;
+        nctl[0] = cnt;
+      }
+    }
+    __syncthreads();
+    const int nc = nctl[0];
+    // their rows of L so far
+    for (int e = threadIdx.x; e < nc * t; e += NTH) {
+      const int a = e / t, l = e - a * t;
+      crow[a * rmax + l] = L[cand[a] + static_cast<size_t>(l) * n];
+    }
+    __syncthreads();
+    {  // their Schur block, SQ lanes an entry
+      const int e = threadIdx.x / SQ, q = threadIdx.x % SQ, a = e / KB, b = e % KB;
+      const bool ok = a < nc && b < nc;
+      const double g = ok ? G[cand[a] + static_cast<size_t>(cand[b]) * ldg] : 0.0;
+      double acc = 0.0;
+      if (ok)
+        for (int l = q; l < t; l += SQ) acc = fma(crow[a * rmax + l], crow[b * rmax + l], acc);
+      acc = group_sum<SQ>(acc);
+      if (q == 0) S[a][b] = ok ? g - acc : 0.0;
+    }
+    __syncthreads();
+    if (w == 0) {
+      // lane (a, c) = (lane / KB, lane % KB) holds entry (a, c) of the candidates' Schur
+      // block, factored in candidate order; a candidate is accepted while its diagonal
+      // qualifies.  At step p lane (a, p) keeps l_a = S[a][p] / sqrt(S[p][p]).
+      const int a = lane / KB, c = lane % KB;
+      double sv = S[a][c], myl = 0.0, myinv = 0.0;
+      int na = 0;
+      uint32_t accm = 0;
+#pragma unroll
+      for (int p = 0; p < KB; ++p) {
+        if (p < nc) {
+          const double spp = readlane_f64(sv, p * KB + p);
+          if (spp > thr && spp >= PB_GAMMA * dmax && na < cap) {
+            double sq, inv;
+            sqrt_and_rsqrt(spp, &sq, &inv);
+            const double la = __shfl(sv, a * KB + p, 64) * inv;
+            const double lc = __shfl(sv, c * KB + p, 64) * inv;
+            if (c == p) {
+              myl = sv * inv;
+              myinv = inv;
+            }
+            sv = fma(-la, lc, sv);
+            if (lane == 0) {
+              pcand[na] = p;
+              pcol[na] = cand[p];
+            }
+            accm |= 1u << p;
+            ++na;
+          }
+        }
+      }
+      // the accepted rows of the factor, in acceptance order, zero elsewhere (above
+      // the diagonal and in the rows and columns of unused slots)
+      Lpp[a][c] = 0.0;
+      if (lane < KB) rdg[lane] = 0.0;
+      if (((accm >> a) & 1u) && ((accm >> c) & 1u)) {
+        const int ia = __popc(accm & ((1u << a) - 1u)), ic = __popc(accm & ((1u << c) - 1u));
+        Lpp[ia][ic] = (ic <= ia) ? myl : 0.0;
+        if (a == c) rdg[ia] = myinv;
+      }
+      if (lane == 0) nctl[1] = na;
+    }
+    __syncthreads();
+    const int b = nctl[1];
+    if (b == 0) break;  // uniform: no candidate qualified after rounding
+    // The new entries t .. t + b - 1 of every row j: H[j][i] = sum_{l < t} L[j, l]
+    // L[p_i, l] on the FP64 matrix cores, a wave taking PB_QT tiles of 16 rows at a
+    // time (A = rows of L from memory, B = the accepted pivots' rows, zero past slot
+    // b), then each lane solves one of those rows: x = (G[j, P] - H[j]) Lpp^-T.  Slots
+    // i >= b meet zero rows and columns of Lpp and so give zero.  The lanes also
+    // track the largest new Schur diagonal of their rows for the next round.
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      const double* crb = crow + pcand[min(li, b - 1)] * rmax;
+      const bool bok = li < b;
+      int pc[KB];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) pc[i] = pcol[min(i, b - 1)];
+      double bestv = -1.0;
+      int besti = n;
+      for (int p0 = 0; p0 < n; p0 += NW * PB_QT * 16) {
+        const int wr0 = p0 + w * PB_QT * 16;  // this wave's first row in this pass
+        if (wr0 >= n) break;                   // uniform within the wave
+        const int nq = min(PB_QT, (n - wr0 + 15) / 16);
+        const int j = wr0 + lane;  // the row this lane solves
+        const bool solver = lane < 16 * nq && j < n;
+        const double dj = solver ? dg[j] : -1.0;
+        int pr = -1;
+#pragma unroll
+        for (int i = 0; i < KB; ++i)
+          if (i < b && pc[i] == j) pr = i;
+        const bool live = solver && pr < 0 && dj >= 0.0;
+        double gv[KB];  // requested first, so that their latency overlaps the products
+#pragma unroll
+        for (int i = 0; i < KB; ++i) gv[i] = live ? G[j + static_cast<size_t>(pc[i]) * ldg] : 0.0;
+        dbl4 acc[PB_QT];
+#pragma unroll
+        for (int q = 0; q < PB_QT; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+        // PB_KS steps of four at a time, all their loads issued together (the loads'
+        // latency, not the products, bounds this phase)
+        for (int k0 = 0; k0 < t; k0 += 4 * PB_KS) {
+          double av[PB_QT][PB_KS], bv[PB_KS];
+#pragma unroll
+          for (int u = 0; u < PB_KS; ++u) {
+            const int l = k0 + 4 * u + lk, lc = min(l, t - 1);
+            const double bb = crb[lc];
+            bv[u] = (l < t && bok) ? bb : 0.0;
+#pragma unroll
+            for (int q = 0; q < PB_QT; ++q) {
+              const int ar = min(wr0 + 16 * q + li, n - 1);  // clamped: computed, not used
+              const double a = (q < nq) ? L[ar + static_cast<size_t>(lc) * n] : 0.0;
+              av[q][u] = (l < t) ? a : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PB_KS; ++u)
+            if (k0 + 4 * u < t)
+#pragma unroll
+              for (int q = 0; q < PB_QT; ++q)
+                if (q < nq) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q][u], bv[u], acc[q], 0, 0, 0);
+        }
+        // accumulator v of lane (li, lk) in tile q is H[wr0 + 16q + 4v + lk][li]: through
+        // LDS to the solving lanes (the wave's own buffer: LDS keeps a wave's order)
+        if (li < KB) {
+#pragma unroll
+          for (int q = 0; q < PB_QT; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ht[w][16 * q + 4 * v + lk][li] = acc[q][v];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (solver) {
+          double x[KB];
+          if (pr >= 0) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i) x[i] = Lpp[pr][i];
+          } else if (live) {
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+              double r = gv[i] - Ht[w][lane][i];
+#pragma unroll
+              for (int k = 0; k < i; ++k) r = fma(-x[k], Lpp[i][k], r);
+              x[i] = r * rdg[i];
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < KB; ++i) x[i] = 0.0;  // pivoted earlier, or negative by rounding
+          }
+          double dn = dj;
+#pragma unroll
+          for (int i = 0; i < KB; ++i) {
+            if (i < b) L[j + static_cast<size_t>(t + i) * n] = x[i];
+            dn = fma(-x[i], x[i], dn);
+          }
+          const double dnew = (pr >= 0) ? -1.0 : (live ? dn : dj);
+          dg[j] = dnew;
+          if (dnew > bestv) {  // rows of later passes have higher indices
+            bestv = dnew;
+            besti = j;
+          }
+        }
+        // the tile buffer is reused by the next pass
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      // this wave's largest new diagonal (lowest index on ties) for the next round
+      double wv;
+      int wl;
+      wave_argmax_lane(bestv, &wv, &wl);
+      int c = (bestv == wv) ? besti : n;
+      for (int o = 32; o > 0; o >>= 1) c = min(c, __shfl_xor(c, o, 64));
+      if (lane == 0) {
+        slotv[w] = wv;
+        sloti[w] = c;
+      }
+    }
+    if (threadIdx.x < b) piv[t + threadIdx.x] = pcol[threadIdx.x];
+    t += b;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *d_r = t;
+}
+
 __global__ __launch_bounds__(NT) void k_pivot_factor(const double* __restrict__ L, int n,
                                                      const int32_t* __restrict__ piv, int r, double* __restrict__ U) {
   const int e = blockIdx.x * NT + threadIdx.x;
@@ -2812,7 +3084,10 @@ void pivoted_cholesky(const double* G, int n, int ldg, int rmax, double theta, d
   // as many leading columns of L as fit are kept in LDS
   const int tl = static_cast<int>(std::min<size_t>(rmax, (cap - base) / (sizeof(double) * n)));
   const size_t shm = base + sizeof(double) * static_cast<size_t>(n) * tl;
-  if (n <= 64) {
+  const size_t shm_block = sizeof(double) * (static_cast<size_t>(n) + static_cast<size_t>(PB_KB) * rmax);
+  if (n > 32 && shm_block <= cap) {
+    k_pivchol_block<<<1, PB_NTH, shm_block, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
+  } else if (n <= 64) {
     k_pivchol_lds<8, 8, 512><<<1, 512, sizeof(double) * n * n, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
   } else if (n <= 128) {
     k_pivchol_lds<4, 32, 512><<<1, 512, sizeof(double) * n * n, s>>>(G, n, ldg, rmax, theta, L, piv, d_r);
