@@ -54,6 +54,7 @@ struct SvdPart {
   // substitution instead of accumulating the rotations
   int qr_passes = 0;
   int jacobi_runs = 0;
+  int jacobi_sweeps = 0;  // sweeps of the final Jacobi run
   bool v_substituted = false;
 };
 void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,

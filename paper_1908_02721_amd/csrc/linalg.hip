@@ -296,27 +296,6 @@ __global__ __launch_bounds__(NT) void k_to_f32(const double* __restrict__ x, siz
   if (e < n) y[e] = static_cast<float>(x[e]);
 }
 
-__global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const double* __restrict__ part,
-                                                    double alpha, double beta, double* __restrict__ C, int ldc) {
-  const size_t e = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
-  const size_t mn = static_cast<size_t>(m) * n;
-  if (e >= mn) return;
-  // four interleaved partial sums (a fixed order) keep four loads in flight
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int z = 0;
-  for (; z + 3 < ns; z += 4) {
-    s0 += part[static_cast<size_t>(z) * mn + e];
-    s1 += part[static_cast<size_t>(z + 1) * mn + e];
-    s2 += part[static_cast<size_t>(z + 2) * mn + e];
-    s3 += part[static_cast<size_t>(z + 3) * mn + e];
-  }
-  for (; z < ns; ++z) s0 += part[static_cast<size_t>(z) * mn + e];
-  const double s = (s0 + s1) + (s2 + s3);
-  const int i = static_cast<int>(e % m), j = static_cast<int>(e / m);
-  double* cp = &C[i + static_cast<size_t>(j) * ldc];
-  *cp = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * (*cp));
-}
-
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_spmm_left(const double* __restrict__ W, int r, int ldw,
                                                   const int64_t* __restrict__ colptr, const int32_t* __restrict__ row,
@@ -440,6 +419,36 @@ __device__ __forceinline__ double group_sum(double x) {
   return x;
 }
 __device__ __forceinline__ double group8_sum(double x) { return group_sum<8>(x); }
+
+// G lanes per output: lane q sums the partials z = q (mod G) with four interleaved
+// running sums, and the G lane sums are added by a DPP group sum (a fixed order), so
+// that 4 G loads per output are in flight at once.
+template <int G>
+__global__ __launch_bounds__(NT) void k_gemm_reduce(int m, int n, int ns, const double* __restrict__ part,
+                                                    double alpha, double beta, double* __restrict__ C, int ldc) {
+  const size_t g = static_cast<size_t>(blockIdx.x) * NT + threadIdx.x;
+  const size_t e = g / G;
+  const int q = static_cast<int>(g % G);
+  const size_t mn = static_cast<size_t>(m) * n;
+  const bool ok = e < mn;  // the whole group of G lanes agrees
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (ok) {
+    int z = q;
+    for (; z + 3 * G < ns; z += 4 * G) {
+      s0 += part[static_cast<size_t>(z) * mn + e];
+      s1 += part[static_cast<size_t>(z + G) * mn + e];
+      s2 += part[static_cast<size_t>(z + 2 * G) * mn + e];
+      s3 += part[static_cast<size_t>(z + 3 * G) * mn + e];
+    }
+    for (; z < ns; z += G) s0 += part[static_cast<size_t>(z) * mn + e];
+  }
+  const double s = group_sum<G>((s0 + s1) + (s2 + s3));
+  if (!ok || q != 0) return;
+  const int i = static_cast<int>(e % m), j = static_cast<int>(e / m);
+  double* cp = &C[i + static_cast<size_t>(j) * ldc];
+  *cp = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * (*cp));
+}
+
 // Three group sums at once, their moves interleaved so that they overlap.
 template <int G>
 __device__ __forceinline__ void group_sum3(double& a, double& b, double& c) {
@@ -1200,26 +1209,33 @@ __global__ __launch_bounds__(256) void k_cholesky_mfma(double* __restrict__ Ag, 
   for (int J = 0; J < NB; ++J) {
     const int b = 16 * J;
     if (w == 0) {
+      // the diagonal block in registers: lane (li, lk) holds rows lk + 4u (u < 4) of its
+      // column li; row jj of the factor reaches the other lanes by cross-lane permutes
+      double e[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] = a[b + lk + 4 * u][b + li];
+#pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
-        const double d = a[b + jj][b + jj];
+        const int uj = jj >> 2, kj = jj & 3;
+        const double d = readlane_f64(e[uj], jj + 16 * kj);
         const bool pos = d > 0.0;
         if (!pos && lane == 0) bad = 1;
         double piv, ip;
         sqrt_and_rsqrt(pos ? d : 1.0, &piv, &ip);
-        __builtin_amdgcn_wave_barrier();
-        if (lane == jj) {
-          a[b + jj][b + jj] = piv;
-          rdiag[b + jj] = ip;
-        }
-        if (lane > jj && lane < 16) a[b + jj][b + lane] *= ip;
-        __builtin_amdgcn_wave_barrier();
+        if (lk == kj) e[uj] = (li == jj) ? piv : (li > jj ? e[uj] * ip : e[uj]);
+        if (lane == jj + 16 * kj) rdiag[b + jj] = ip;
+        const double ujc = __shfl(e[uj], li + 16 * kj, 64);  // factor entry (jj, li)
+        double uji[4];                                        // factor entries (jj, lk + 4u)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) uji[u] = __shfl(e[uj], lk + 4 * u + 16 * kj, 64);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = lane + 64 * u, i = e >> 4, c = e & 15;
-          if (i > jj && c >= i) a[b + i][b + c] = fma(-a[b + jj][b + i], a[b + jj][b + c], a[b + i][b + c]);
+          const int i = lk + 4 * u;
+          if (i > jj && li >= i) e[u] = fma(-uji[u], ujc, e[u]);
         }
-        __builtin_amdgcn_wave_barrier();
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[b + lk + 4 * u][b + li] = e[u];
     }
     __syncthreads();
     const int rest = R - b - 16;
@@ -2457,6 +2473,58 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
   }
 }
 
+// Convergence test of a one-sided Jacobi on the 64 x NC matrix A in LDS (column-major,
+// leading dimension 64), by all 256 threads: true when no pair (p, q) would rotate,
+// i.e. g^2 <= tol^2 a b for a = |a_p|^2, b = |a_q|^2, g = a_p^T a_q (the sweep's own
+// test), which is what a further sweep would find before its first rotation.  The
+// Gram matrix comes from the FP64 matrix cores on a padded copy T (NC x 65) and the
+// squared norms nrm (NC), both LDS scratch.  Three barriers.
+template <int NC>
+__device__ bool jacobi_gram_converged(const double* A, double tol, double* T, double* nrm, int* viol) {
+  constexpr int NTH = 256, TP = 65, NB = NC / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < NC * 64; e += NTH) T[(e >> 6) * TP + (e & 63)] = A[e];
+  if (tid == 0) *viol = 0;
+  {  // squared column norms, NTH / NC lanes a column, in the order of the sweep's sums
+    constexpr int LPC = NTH / NC, RPL = 64 / LPC;
+    const int j = tid / LPC, q = tid % LPC;
+    double sacc = 0.0;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const double x = A[j * 64 + q * RPL + u];
+      sacc = fma(x, x, sacc);
+    }
+    sacc = group_sum<LPC>(sacc);
+    if (q == 0) nrm[j] = sacc;
+  }
+  __syncthreads();
+  int t = 0;
+  for (int P = 0; P < NB; ++P)
+    for (int Q = P; Q < NB; ++Q, ++t) {
+      if (t % (NTH / 64) != w) continue;  // uniform within the wave
+      dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < 64; k0 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[(16 * P + li) * TP + k0 + lk], T[(16 * Q + li) * TP + k0 + lk],
+                                                   acc, 0, 0, 0);
+      bool bad = false;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pp = 16 * P + 4 * v + lk, qq = 16 * Q + li;
+        if (pp < qq) {
+          const double a = nrm[pp], b = nrm[qq], g = acc[v], ab = a * b;
+          const bool rot = (ab > 1e-280 && ab < 1e280) ? (g * g > tol * tol * ab) : (fabs(g) > tol * sqrt(a) * sqrt(b));
+          bad = bad || (a != 0.0 && b != 0.0 && rot);
+        }
+      }
+      if (bad) *viol = 1;
+    }
+  __syncthreads();
+  const bool ok = *viol == 0;
+  __syncthreads();
+  return ok;
+}
+
 // One-sided Jacobi for NC/2 < c <= NC columns (NC = 32 or 64) of at most 64 rows,
 // padded to 64 x NC, with a hierarchical parallel ordering that keeps one column of
 // each pair in registers.  A sweep has log2(NC) phases: in phase h the NC columns form
@@ -2468,7 +2536,9 @@ __global__ __launch_bounds__(256) void k_jacobi64(double* __restrict__ Ag, int r
 // LDS traffic of an ordering in which both columns move.  Groups are
 // GW = 512 / NC lanes; a lane holds 64 / GW rows of a column as double2 pairs.
 // Padded columns are zero and never rotate.  Same rotation, stopping test and output
-// as k_jacobi64.
+// as k_jacobi64, except that after a sweep whose rotated pairs all had g^2 <= 1e-12 a b
+// the next sweep is replaced by jacobi_gram_converged (the stopping test on every pair
+// of the Gram matrix), and run only if some pair fails it.
 //
 // ACCV = false is for a square lower-triangular input L (c x c, c = rows), such as
 // R^T from a QR: the rotations are not accumulated (a quarter of a round's work);
@@ -2481,13 +2551,20 @@ template <int NC, bool ACCV>
 __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
                                                    double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
   __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
-  if (threadIdx.x == 0) gmax_ = 0ull;
+  // set when the current sweep rotates a pair with g^2 > 1e-12 a b
+  __shared__ int bigrot;
+  if (threadIdx.x == 0) {
+    gmax_ = 0ull;
+    bigrot = 0;
+  }
   constexpr int NTH = 256, LD = 64, GW = 512 / NC, UP = 32 / GW;
   static_assert(NC == 32 || NC == 64, "32 or 64 columns");
   __shared__ double2 sA[NC * LD / 2];  // 64 x NC, column-major (rows >= `rows` zero)
   __shared__ double2 sV[NC * LD / 2];  // 64 x NC: V (identity outside the leading c x c block), or L
   __shared__ int rotated;
   __shared__ double smax_[NTH / 64], smin_[NTH / 64];
+  __shared__ double gT[NC * 65], gnrm[NC];  // scratch of the Gram convergence test
+  __shared__ int gviol;
   double* A = reinterpret_cast<double*>(sA);
   double* V = reinterpret_cast<double*>(sV);
   {  // staging: each thread's loads are issued together (clamped addresses)
@@ -2512,7 +2589,9 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
   int nsw_ = 0, conv_ = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     nsw_ = sweep + 1;
-    if (threadIdx.x == 0) rotated = 0;
+    if (threadIdx.x == 0) {
+      rotated = 0;
+    }
     bool any = false;
     for (int lh = (NC == 64 ? 5 : 4); lh >= 0; --lh) {
       const int half = 1 << lh;
@@ -2556,6 +2635,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
         if (a != 0.0 && b != 0.0 && rot) {  // uniform within the group
           double cs, sn;
           if (sweep == max_sweeps - 1) atomicMax(&gmax_, static_cast<unsigned long long>(__double_as_longlong(fabs(g))));
+          if (gl == 0 && !(g * g <= 1e-12 * ab)) bigrot = 1;
           jacobi_rotation(a, b, g, &cs, &sn);
           if (ACCV && !PRE_V) {
 #pragma unroll
@@ -2593,7 +2673,17 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
       conv_ = 1;
       break;
     }
+    // Jacobi converges quadratically: once every pair a sweep rotated had g^2 <= 1e-12
+    // a b, the next sweep is expected to rotate nothing.  Instead of running it, the
+    // Gram matrix tells whether it would (the same test on every pair).
+    const bool small = bigrot == 0;
     __syncthreads();
+    if (threadIdx.x == 0) bigrot = 0;  // for the next sweep, before its first round
+    __syncthreads();
+    if (small && sweep + 1 < max_sweeps && jacobi_gram_converged<NC>(A, tol, gT, gnrm, &gviol)) {
+      conv_ = 1;
+      break;
+    }
   }
   // column norms (sigma); without V also their extremes, for the condition test
   double smax = 0.0, smin = HUGE_VAL;
@@ -2991,8 +3081,14 @@ void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, d
   const int tiles = sym ? tm * (tm + 1) / 2 : tm * tn;
   int ns = 1;
   // split K until about 1024 workgroups (a few per CU, so that the k-stage latency
-  // of one overlaps another's) with at least 128 rows of K each
-  if (tiles < 256 && k > 128) ns = std::min({(k + 127) / 128, std::max(1, 1024 / tiles), 256});
+  // of one overlaps another's) with at least 32 rows of K each: a workgroup's k-stages
+  // each wait for memory, so a short chunk finishes sooner.  The partial sums are kept
+  // to at most 2^21 values (16 MB, a few microseconds for the reduction to read).
+  if (tiles < 256 && k > 32) {
+    const int64_t mn = static_cast<int64_t>(m) * n;
+    const int cap_part = static_cast<int>(std::max<int64_t>(1, (int64_t(1) << 21) / mn));
+    ns = std::min({(k + 31) / 32, std::max(1, 1024 / tiles), 256, cap_part});
+  }
   int kchunk = (k + ns - 1) / ns;
   kchunk = ((kchunk + kstep - 1) / kstep) * kstep;
   if (kchunk == 0) kchunk = kstep;
@@ -3017,7 +3113,12 @@ void gemm_prec(Allocator* al, int prec, bool ta, bool tb, int m, int n, int k, d
   TTS_LAUNCH_CHECK();
   if (ns > 1) {
     const size_t mn = static_cast<size_t>(m) * n;
-    k_gemm_reduce<<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+    if (ns >= 32)
+      k_gemm_reduce<8><<<grid_for(mn * 8, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+    else if (ns >= 8)
+      k_gemm_reduce<2><<<grid_for(mn * 2, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
+    else
+      k_gemm_reduce<1><<<grid_for(mn, NT), NT, 0, s>>>(m, n, ns, part.get(), alpha, beta, C, ldc);
     TTS_LAUNCH_CHECK();
   }
 }

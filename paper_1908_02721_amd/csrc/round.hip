@@ -233,6 +233,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   }
   svd_check(hinfo, sh.data(), cB, c);
   o.v_substituted = last_tri && hinfo[1] == 1;
+  o.jacobi_sweeps = hinfo[0];
   // the same stable non-ascending order as k_rank_desc
   std::vector<int32_t> perm(cB);
   std::iota(perm.begin(), perm.end(), 0);
@@ -495,9 +496,9 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     SvdPart sv;
     truncated_svd(A, prec, reinterpret_cast<const double*>(cores[k - 1].get()), m, rl, delta2, in.max_rank, sv, s);
     logf("SVD bond %d: %d x %d, rank %d, discarded sum of sigma^2 %.3e ||A||^2 (threshold^2 %.3e), "
-         "QR passes %d, Jacobi runs %d, V %s, %.3f ms (host)",
+         "QR passes %d, Jacobi runs %d (last %d sweeps), V %s, %.3f ms (host)",
          k - 1, m, rl, sv.rank, sv.tail / (in.norm * in.norm), delta2 / (in.norm * in.norm), sv.qr_passes,
-         sv.jacobi_runs, sv.v_substituted ? "by substitution" : "accumulated", host_ms() - t_bond);
+         sv.jacobi_runs, sv.jacobi_sweeps, sv.v_substituted ? "by substitution" : "accumulated", host_ms() - t_bond);
     t_bond = host_ms();
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;

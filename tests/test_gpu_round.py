@@ -399,8 +399,8 @@ def test_svd_path_log():
     assert r.returncode == 0, r.stderr[-3000:]
     blocks = r.stderr.split("CASE ")[1:]
     assert len(blocks) == len(cases) + 1, r.stderr[-3000:]
-    pat = re.compile(r"SVD bond (\d+): (\d+) x (\d+), .*QR passes (\d+), Jacobi runs (\d+), V (by substitution|"
-                     r"accumulated)")
+    pat = re.compile(r"SVD bond (\d+): (\d+) x (\d+), .*QR passes (\d+), Jacobi runs (\d+) \(last \d+ sweeps\), "
+                     r"V (by substitution|accumulated)")
     for (terms, kappa, passes, runs, subst), blk in zip(SVD_PATHS, blocks):
         found = pat.findall(blk)
         print(f"[svd path] T={terms} kappa={kappa:g}: {found}", flush=True)
