@@ -318,8 +318,19 @@ void sync_status(DevStatus* d_st, hipStream_t s) {
 }
 
 // Exact sparse TT: ingest, sort, and parallel-vector rounding level by level.
-void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
-                  int total_bits, bool keep, int key_bits, hipStream_t s, Events& ev) {
+//
+// A level's host-side sizes are its column count, its group count beta and nnz(N_k).
+// The careful pass reads them back as the level goes (up to two read-backs a level).
+// The speculative pass reads every level's column count once, right after the sort
+// (distinct suffixes of the sorted keys, k_level_counts), and sizes the rest by upper
+// bounds (beta <= columns, nnz(N_k) <= entries), on the assumptions that no column is
+// longer than kMaxLocal entries and that beta fits the device-count leader sort
+// (kSmallSortMax) where the column count does not already guarantee it.  Its kernels
+// read the counts from the device and stay in bounds when an assumption fails; one
+// read-back at the end checks them, and the stage is then redone carefully.  Returns
+// false in that case.
+bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
+                       int total_bits, bool keep, int key_bits, hipStream_t s, Events& ev, bool spec) {
   Allocator* al = &R->al;
   const int d = mi.d;
   DBuf<DevStatus> st(al, 1);
@@ -350,37 +361,62 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
   }
   TTS_HIP(hipEventRecord(ev.e[2], s));
 
+  // every level's column count at once (speculative pass)
+  std::vector<uint32_t> ncols_h(d + 1, 0);
+  DBuf<uint32_t> lv(al, 4 * static_cast<size_t>(d));  // per level: columns, beta, nnz(N_k)
+  if (spec) {
+    DBuf<uint32_t> cnt(al, static_cast<size_t>(d) + 1);
+    TTS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(uint32_t) * (d + 1), s));
+    launch_level_counts(keys.get(), kept, mi, cnt.get(), st.get(), s);
+    Readback rb(s);
+    rb.add(ncols_h.data(), cnt.get(), sizeof(uint32_t) * (d + 1));
+    rb.add(host_status(), st.get(), sizeof(DevStatus));
+    rb.sync();
+    if (host_status()->err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
+  }
+
   // a3..a7: levels
   DBuf<uint64_t> ekey = std::move(keys);
   DBuf<uint32_t> erho;
   DBuf<double> evals;
   const double* evp = reinterpret_cast<const double*>(vals.get());
   uint32_t nE = kept;
+  R->lev.clear();
   R->lev.resize(d - 1);
   R->betas.assign(d + 1, 1);
-  logf("sparse stage: %u nonzeros kept of %u, %d modes", kept, nnz, d);
+  std::vector<uint32_t> caps(d, 0);
+  logf("sparse stage: %u nonzeros kept of %u, %d modes%s", kept, nnz, d, spec ? " (sizes read once)" : "");
   for (int k = 1; k <= d - 1; ++k) {
     const double t_level = host_ms();
     const int kidx = k;           // first suffix mode, 0-based
     const int sh = static_cast<int>(mi.bits[k - 1]);
     const bool level1 = (k == 1);
+    uint32_t* d_ncols = spec ? lv.get() + 4 * k - 4 : &st.get()->ncols;
+    uint32_t* d_beta = spec ? lv.get() + 4 * k - 3 : &st.get()->beta;
+    uint32_t* d_nnz = spec ? lv.get() + 4 * k - 2 : &st.get()->nnz_n;
     DBuf<uint32_t> flag(al, nE), pos(al, nE), col_start(al, static_cast<size_t>(nE) + 1);
     DBuf<double> norm_part;
     if (level1) norm_part.reset(al, norm_partials_count(nE));
     launch_col_flags(ekey.get(), nE, sh, level1, level1 ? -1 : k - 1, evp, flag.get(), norm_part.get(), st.get(),
                      s);
-    exclusive_scan_u32(al, flag.get(), pos.get(), nE, &st.get()->ncols, s);
-    launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), st.get(), s);
+    exclusive_scan_u32(al, flag.get(), pos.get(), nE, d_ncols, s);
+    launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), d_ncols, s);
     if (level1) launch_norm_final(norm_part.get(), norm_partials_count(nE), st.get(), s);
-    sync_status(st.get(), s);
-    const DevStatus hs = *host_status();
-    if (level1) {
-      if (hs.err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
-      R->norm = std::sqrt(hs.norm2);
+    uint32_t ncols;
+    bool longcol = false;
+    if (!spec) {
+      sync_status(st.get(), s);
+      const DevStatus hs = *host_status();
+      if (level1) {
+        if (hs.err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
+        R->norm = std::sqrt(hs.norm2);
+      }
+      ncols = hs.ncols;
+      longcol = !level1 && ((hs.longmask >> (k - 1)) & 1ull);
+    } else {
+      ncols = ncols_h[k];
     }
-    const uint32_t ncols = hs.ncols;
     bool sort_rows = !level1;
-    const bool longcol = !level1 && ((hs.longmask >> (k - 1)) & 1ull);
     if (longcol) {
       // long columns: order entries by (column, rho) with one composite sort
       const uint64_t maxrho = static_cast<uint64_t>(R->betas[k - 1]) * mi.n[k - 1];
@@ -408,6 +444,11 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     DBuf<uint32_t> crho(al, nE);
     DBuf<double> cval(al, nE), cols(al, ncols);
     DBuf<uint64_t> colhash(al, ncols), colsuf(al, ncols), rmkey(al, ncols);
+    // a5's hash table and group ids, cleared by the canonicalisation kernel
+    uint32_t tsize = 1;
+    while (tsize < 2u * ncols + 2u) tsize <<= 1;
+    DBuf<uint64_t> table(al, tsize), slotmin(al, tsize);
+    DBuf<uint32_t> slot_gid(al, tsize);
     CanonArgs ca{};
     ca.ekey = ekey.get();
     ca.erho = level1 ? nullptr : erho.get();
@@ -425,13 +466,10 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     ca.cols = cols.get();
     ca.colsuf = colsuf.get();
     ca.rmkey = rmkey.get();
-    // a5's hash table, cleared by the canonicalisation kernel
-    uint32_t tsize = 1;
-    while (tsize < 2u * ncols + 2u) tsize <<= 1;
-    DBuf<uint64_t> table(al, tsize), slotmin(al, tsize);
     ca.table = table.get();
     ca.slotmin = slotmin.get();
     ca.tsize = tsize;
+    ca.slot_gid = slot_gid.get();
     // levels with long columns and few columns: a workgroup per column
     launch_canon(ca, mi, st.get(), longcol && ncols <= 16384, s);
     // a5: group
@@ -439,7 +477,7 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     launch_group(colhash.get(), crho.get(), cval.get(), col_start.get(), rmkey.get(), ncols, table.get(),
                  slotmin.get(), tsize - 1, slot.get(), isrep.get(), s);
     DBuf<uint32_t> reppos(al, ncols);
-    exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, &st.get()->beta, s);
+    exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, d_beta, s);
     int rm_bits = 0;
     for (int j = kidx; j < d; ++j) rm_bits += static_cast<int>(mi.bits[j]);
     // Up to kSmallSortMax groups (the common case) the leaders are ordered without
@@ -447,35 +485,43 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     // device, and beta and nnz(N_k) come back in one read-back.  Beyond that the
     // leaders are sorted again with the device-wide radix sort.
     const uint32_t cap = std::min<uint32_t>(ncols, kSmallSortMax);
+    caps[k] = cap;
     DBuf<uint64_t> lkey(al, cap), lslot(al, cap), lks(al, cap), lss(al, cap);
-    DBuf<uint32_t> slot_gid(al, tsize), nlen(al, cap), npos(al, cap);
+    DBuf<uint32_t> nlen(al, cap), npos(al, cap);
     launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, cap, lkey.get(), lslot.get(), s);
-    sort_small_device_count(lkey.get(), lslot.get(), &st.get()->beta, cap, rm_bits, lks.get(), lss.get(), s);
-    launch_group_ids(lss.get(), 0, &st.get()->beta, cap, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
-    exclusive_scan_u32(al, nlen.get(), npos.get(), cap, &st.get()->nnz_n, s);
-    sync_status(st.get(), s);
-    const uint32_t beta = host_status()->beta;
-    if (static_cast<uint64_t>(beta) * (k < d ? mi.n[k] : 1) > static_cast<uint64_t>(INT32_MAX))
-      fail(TT_ERR_TOO_LARGE, "rank times mode size exceeds 2^31");
-    if (beta > cap) {
-      lkey.reset(al, beta);
-      lslot.reset(al, beta);
-      launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, beta, lkey.get(), lslot.get(), s);
-      {
-        DBuf<uint64_t> kt(al, beta), vt(al, beta);
-        if (radix_sort_pairs_pp(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s)) {
-          lkey.swap(kt);
-          lslot.swap(vt);
-        }
-      }
-      lss = std::move(lslot);
-      nlen.reset(al, beta);
-      npos.reset(al, beta);
-      launch_group_ids(lss.get(), beta, nullptr, beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
-      exclusive_scan_u32(al, nlen.get(), npos.get(), beta, &st.get()->nnz_n, s);
+    sort_small_device_count(lkey.get(), lslot.get(), d_beta, cap, rm_bits, lks.get(), lss.get(), s);
+    launch_group_ids(lss.get(), 0, d_beta, cap, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
+    exclusive_scan_u32(al, nlen.get(), npos.get(), cap, d_nnz, s);
+    // beta, nnz(N_k): exact (careful pass) or upper bounds (speculative pass: checked
+    // at the end, beta <= cap assumed)
+    uint32_t beta = cap, nnz_n = nE;
+    if (!spec) {
       sync_status(st.get(), s);
+      beta = host_status()->beta;
+      if (static_cast<uint64_t>(beta) * (k < d ? mi.n[k] : 1) > static_cast<uint64_t>(INT32_MAX))
+        fail(TT_ERR_TOO_LARGE, "rank times mode size exceeds 2^31");
+      if (beta > cap) {
+        lkey.reset(al, beta);
+        lslot.reset(al, beta);
+        launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, beta, lkey.get(), lslot.get(),
+                        s);
+        {
+          DBuf<uint64_t> kt(al, beta), vt(al, beta);
+          if (radix_sort_pairs_pp(al, lkey.get(), lslot.get(), kt.get(), vt.get(), beta, rm_bits, s)) {
+            lkey.swap(kt);
+            lslot.swap(vt);
+          }
+        }
+        lss = std::move(lslot);
+        nlen.reset(al, beta);
+        npos.reset(al, beta);
+        launch_group_ids(lss.get(), beta, nullptr, beta, table.get(), col_start.get(), slot_gid.get(), nlen.get(),
+                         s);
+        exclusive_scan_u32(al, nlen.get(), npos.get(), beta, d_nnz, s);
+        sync_status(st.get(), s);
+      }
+      nnz_n = host_status()->nnz_n;
     }
-    const uint32_t nnz_n = host_status()->nnz_n;
     LevelData& L = R->lev[k - 1];
     L.ncols = ncols;
     L.beta = beta;
@@ -485,8 +531,8 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
     L.colptr.reset(al, static_cast<size_t>(beta) + 1);
     L.row.reset(al, nnz_n);
     L.val.reset(al, nnz_n);
-    launch_emit_n(lss.get(), beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
-                  L.colptr.get(), L.row.get(), L.val.get(), st.get(), s);
+    launch_emit_n(lss.get(), beta, d_beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
+                  L.colptr.get(), L.row.get(), L.val.get(), d_nnz, s);
     // a7: next level (or the last core)
     EmitArgs ea{};
     ea.ncols = ncols;
@@ -521,8 +567,9 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
       ea.last_core = R->last_exact.get();
     }
     launch_emit_next(ea, mi, s);
-    logf("level %d: %u entries, %u columns, beta %u, nnz(N_k) %u, %.3f ms (host)", k, nE, ncols, beta, nnz_n,
-         host_ms() - t_level);
+    if (!spec)
+      logf("level %d: %u entries, %u columns, beta %u, nnz(N_k) %u, %.3f ms (host)", k, nE, ncols, beta, nnz_n,
+           host_ms() - t_level);
     if (!ea.last) {
       ekey = std::move(nk);
       erho = std::move(nr);
@@ -532,7 +579,48 @@ void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_
       nE = ncols;
     }
   }
+  if (spec) {
+    // one read-back for every level's counts; the assumptions are checked here
+    std::vector<uint32_t> lh(4 * static_cast<size_t>(d), 0);
+    Readback rb(s);
+    rb.add(lh.data(), lv.get(), sizeof(uint32_t) * 4 * d);
+    rb.add(host_status(), st.get(), sizeof(DevStatus));
+    rb.sync();
+    const DevStatus hs = *host_status();
+    bool ok = true;
+    uint32_t ne = kept;
+    for (int k = 1; k <= d - 1; ++k) {
+      const uint32_t nc = lh[4 * k - 4], beta = lh[4 * k - 3], nz = lh[4 * k - 2];
+      const bool fits = nc == ncols_h[k] && beta >= 1 && beta <= caps[k] && nz <= ne &&
+                        !(k >= 2 && ((hs.longmask >> (k - 1)) & 1ull)) &&
+                        static_cast<uint64_t>(beta) * (k < d ? mi.n[k] : 1) <= static_cast<uint64_t>(INT32_MAX);
+      if (!fits) {
+        ok = false;
+        logf("level %d: speculative sizes do not hold (columns %u / %u, beta %u, cap %u); redone carefully", k, nc,
+             ncols_h[k], beta, caps[k]);
+        break;
+      }
+      LevelData& L = R->lev[k - 1];
+      L.beta = beta;
+      L.nnz_n = nz;
+      R->betas[k] = beta;
+      logf("level %d: %u entries, %u columns, beta %u, nnz(N_k) %u", k, ne, nc, beta, nz);
+      ne = nc;
+    }
+    if (!ok) return false;
+    R->norm = std::sqrt(hs.norm2);
+  }
   TTS_HIP(hipEventRecord(ev.e[3], s));
+  return true;
+}
+
+void sparse_stage(tt_result_s* R, const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
+                  int total_bits, bool keep, int key_bits, hipStream_t s, Events& ev) {
+  // speculate only when the allocations are the library's own and unbudgeted (the
+  // upper bounds hold more memory for the duration of the call)
+  const bool spec = R->al.budget == 0 && !R->al.hook_alloc;
+  if (!sparse_stage_pass(R, idx, val, nnz, mi, total_bits, keep, key_bits, s, ev, spec))
+    sparse_stage_pass(R, idx, val, nnz, mi, total_bits, keep, key_bits, s, ev, false);
 }
 
 }  // namespace

@@ -19,6 +19,7 @@
 //                          (rho' = g * n_{k+1} + i_{k+1}, value s)
 #include "sparse.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace tts {
@@ -129,10 +130,55 @@ __global__ __launch_bounds__(NF) void k_norm_final(const double* __restrict__ pa
 
 __global__ __launch_bounds__(NT) void k_col_starts(const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos,
                                                    uint32_t nE, uint32_t* __restrict__ col_start,
-                                                   const DevStatus* st) {
+                                                   const uint32_t* __restrict__ d_ncols) {
   const uint32_t e = blockIdx.x * NT + threadIdx.x;
   if (e < nE && flag[e]) col_start[pos[e]] = e;
-  if (e == 0) col_start[st->ncols] = nE;
+  if (e == 0) col_start[*d_ncols] = nE;
+}
+
+// Column counts of every level from the globally sorted kept keys.  A level-k column
+// (k = 1 .. d-1) is a distinct suffix key >> off[k] (modes k .. d-1), so its count is
+// the number of positions where that suffix differs from the previous key's (the first
+// position counts for every level).  Row y of the grid takes levels 1 + LC_PER y ..;
+// per-workgroup sums go to counts[k] with one atomic each.  Also flags a duplicate
+// (equal neighbouring keys).
+constexpr int LC_PER = 8;
+__device__ __forceinline__ uint64_t suffix_of(uint64_t key, uint32_t off) { return off >= 64 ? 0ull : key >> off; }
+__global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict__ keys, uint32_t n, ModeInfo mi,
+                                                     uint32_t* __restrict__ counts, DevStatus* st) {
+  __shared__ uint32_t red[NT / 64][LC_PER];
+  const int k0 = 1 + LC_PER * static_cast<int>(blockIdx.y);
+  uint32_t cnt[LC_PER];
+#pragma unroll
+  for (int j = 0; j < LC_PER; ++j) cnt[j] = 0u;
+  bool dup = false;
+  for (uint32_t e = blockIdx.x * NT + threadIdx.x; e < n; e += gridDim.x * NT) {
+    const uint64_t key = keys[e];
+    const uint64_t prev = (e > 0) ? keys[e - 1] : ~key;  // differs from key in every bit
+    dup = dup || (e > 0 && prev == key);
+#pragma unroll
+    for (int j = 0; j < LC_PER; ++j) {
+      const int k = k0 + j;
+      if (k < mi.d) cnt[j] += (suffix_of(key, mi.off[k]) != suffix_of(prev, mi.off[k])) ? 1u : 0u;
+    }
+  }
+  if (dup && blockIdx.y == 0) atomicOr(&st->err, kErrDuplicate);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < LC_PER; ++j) {
+    uint32_t v = cnt[j];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[w][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < LC_PER) {
+    const int k = k0 + static_cast<int>(threadIdx.x);
+    if (k < mi.d) {
+      uint32_t t = 0;
+      for (int q = 0; q < NT / 64; ++q) t += red[q][threadIdx.x];
+      atomicAdd(&counts[k], t);
+    }
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_make_composite(const uint32_t* __restrict__ flag,
@@ -204,6 +250,7 @@ __device__ __forceinline__ void clear_table(const CanonArgs& a, uint32_t t, uint
   for (uint32_t e = t; e < a.tsize; e += stride) {
     a.table[e] = 0ull;
     a.slotmin[e] = ~0ull;
+    if (a.slot_gid) a.slot_gid[e] = 0u;
   }
 }
 
@@ -548,14 +595,19 @@ __global__ __launch_bounds__(NT) void k_group_ids(const uint64_t* __restrict__ l
   nlen[j] = col_start[r + 1] - col_start[r];
 }
 
-__global__ __launch_bounds__(NT) void k_emit_n(const uint64_t* __restrict__ lslot, uint32_t beta,
+__global__ __launch_bounds__(NT) void k_emit_n(const uint64_t* __restrict__ lslot, uint32_t bmax,
+                                               const uint32_t* __restrict__ d_beta,
                                                const uint64_t* __restrict__ table, const uint32_t* __restrict__ col_start,
                                                const uint32_t* __restrict__ npos, const uint32_t* __restrict__ crho,
                                                const double* __restrict__ cval, int64_t* __restrict__ colptr,
                                                int32_t* __restrict__ nrow, double* __restrict__ nval,
-                                               const DevStatus* st) {
+                                               const uint32_t* __restrict__ d_nnz) {
   const uint32_t j = blockIdx.x * NT + threadIdx.x;
-  if (j == 0) colptr[beta] = st->nnz_n;
+  // more groups than the launch covers (a speculative pass whose leader list was
+  // capped): nothing is written, the pass is redone
+  if (*d_beta > bmax) return;
+  const uint32_t beta = *d_beta;
+  if (j == 0) colptr[beta] = *d_nnz;
   if (j >= beta) return;
   const uint32_t p = static_cast<uint32_t>(lslot[j]);
   const uint32_t r = static_cast<uint32_t>(table[p] - 1);
@@ -616,8 +668,16 @@ void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream
 }
 
 void launch_col_starts(const uint32_t* flag, const uint32_t* pos, uint32_t nE, uint32_t* col_start,
-                       const DevStatus* st, hipStream_t s) {
-  k_col_starts<<<grid_for(nE, NT), NT, 0, s>>>(flag, pos, nE, col_start, st);
+                       const uint32_t* d_ncols, hipStream_t s) {
+  k_col_starts<<<grid_for(nE, NT), NT, 0, s>>>(flag, pos, nE, col_start, d_ncols);
+  TTS_LAUNCH_CHECK();
+}
+
+void launch_level_counts(const uint64_t* keys, uint32_t n, const ModeInfo& mi, uint32_t* counts, DevStatus* st,
+                         hipStream_t s) {
+  if (n == 0 || mi.d < 2) return;
+  const dim3 grid(std::min<unsigned>(grid_for(n, NT), 1024u), static_cast<unsigned>((mi.d - 2) / LC_PER + 1));
+  k_level_counts<<<grid, NT, 0, s>>>(keys, n, mi, counts, st);
   TTS_LAUNCH_CHECK();
 }
 
@@ -690,11 +750,11 @@ void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_
   TTS_LAUNCH_CHECK();
 }
 
-void launch_emit_n(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
-                   const uint32_t* npos, const uint32_t* crho, const double* cval, int64_t* colptr, int32_t* nrow,
-                   double* nval, const DevStatus* st, hipStream_t s) {
-  k_emit_n<<<grid_for(beta, NT), NT, 0, s>>>(lslot_sorted, beta, table, col_start, npos, crho, cval, colptr, nrow,
-                                             nval, st);
+void launch_emit_n(const uint64_t* lslot_sorted, uint32_t bmax, const uint32_t* d_beta, const uint64_t* table,
+                   const uint32_t* col_start, const uint32_t* npos, const uint32_t* crho, const double* cval,
+                   int64_t* colptr, int32_t* nrow, double* nval, const uint32_t* d_nnz, hipStream_t s) {
+  k_emit_n<<<grid_for(bmax, NT), NT, 0, s>>>(lslot_sorted, bmax, d_beta, table, col_start, npos, crho, cval, colptr,
+                                             nrow, nval, d_nnz);
   TTS_LAUNCH_CHECK();
 }
 

@@ -43,7 +43,11 @@ void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, in
 uint32_t norm_partials_count(uint32_t nE);
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s);
 void launch_col_starts(const uint32_t* flag, const uint32_t* pos, uint32_t nE, uint32_t* col_start,
-                       const DevStatus* st, hipStream_t s);
+                       const uint32_t* d_ncols, hipStream_t s);
+// Column counts of every level (counts[k], k = 1 .. d-1, zeroed beforehand) from the
+// sorted kept keys, and the duplicate flag; see k_level_counts.
+void launch_level_counts(const uint64_t* keys, uint32_t n, const ModeInfo& mi, uint32_t* counts, DevStatus* st,
+                         hipStream_t s);
 
 // Long-column path: composite sort keys (column << rbits | rho) and a permutation.
 void launch_make_composite(const uint32_t* flag, const uint32_t* pos, const uint32_t* erho, uint32_t nE,
@@ -74,6 +78,7 @@ struct CanonArgs {
   uint64_t* table;
   uint64_t* slotmin;
   uint32_t tsize;
+  uint32_t* slot_gid;  // tsize group ids, cleared to 0 here too (may be null)
 };
 // a4: canonicalise every column by its entry of smallest row, key and hash it.
 // wide: one workgroup per column (for levels of few, long columns already in row
@@ -95,10 +100,11 @@ void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_
                       const uint64_t* table, const uint32_t* col_start, uint32_t* slot_gid, uint32_t* nlen,
                       hipStream_t s);
 
-// a6: N_k in CSC (one canonical column per group, in group order).
-void launch_emit_n(const uint64_t* lslot_sorted, uint32_t beta, const uint64_t* table, const uint32_t* col_start,
-                   const uint32_t* npos, const uint32_t* crho, const double* cval, int64_t* colptr,
-                   int32_t* nrow, double* nval, const DevStatus* st, hipStream_t s);
+// a6: N_k in CSC (one canonical column per group, in group order); beta = *d_beta,
+// nnz(N_k) = *d_nnz; the launch covers bmax groups and writes nothing if beta > bmax.
+void launch_emit_n(const uint64_t* lslot_sorted, uint32_t bmax, const uint32_t* d_beta, const uint64_t* table,
+                   const uint32_t* col_start, const uint32_t* npos, const uint32_t* crho, const double* cval,
+                   int64_t* colptr, int32_t* nrow, double* nval, const uint32_t* d_nnz, hipStream_t s);
 
 struct EmitArgs {
   uint32_t ncols;

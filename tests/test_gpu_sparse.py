@@ -95,6 +95,44 @@ def test_long_columns_path(oracle_mod):
     check_sparse_parity(oracle_mod, synth.unravel(lin, dims), val, dims, "long columns")
 
 
+def test_speculative_sizes_and_careful_redo():
+    """Level sizes are read once per call when its assumptions hold (no column longer
+    than 32 entries, at most 2048 groups where the column count allows more); inputs
+    that break them are redone with per-level read-backs.  The progress log
+    (TTSPARSE_LOG=1, read once per process, hence a child process) says which."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import numpy as np, torch\n"
+        "import paper_1908_02721_amd as tts\n"
+        "from paper_1908_02721_amd import synth\n"
+        "def run(idx, val, dims, label):\n"
+        "    print('CASE', label, file=sys.stderr, flush=True)\n"
+        "    tts.decompose(torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda(),\n"
+        "                  torch.from_numpy(np.ascontiguousarray(val)).cuda(), dims, 1e-10, sparse_only=True)\n"
+        "idx, val, dims = synth.kronecker_sum(6, 10, 6, 3, seed=4)\n"
+        "run(idx, val, dims, 'kron')\n"
+        "rng = np.random.Generator(np.random.PCG64(17))\n"
+        "dims = (3, 48, 4)\n"
+        "lin = rng.choice(int(np.prod(dims)), int(np.prod(dims)) // 2, replace=False)\n"
+        "run(synth.unravel(lin, dims), rng.integers(1, 3, lin.size).astype(float), dims, 'long')\n"
+        "idx, val, dims = synth.random_sparse((30, 100, 100), 60000, 3)\n"
+        "run(idx, val, dims, 'many groups')\n"
+        "print('CASE end', file=sys.stderr, flush=True)\n" % root)
+    env = dict(os.environ, TTSPARSE_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    blocks = dict(b.split("\n", 1) for b in r.stderr.split("CASE ")[1:] if "\n" in b)
+    print({k: v[-600:] for k, v in blocks.items()}, flush=True)
+    assert "(sizes read once)" in blocks["kron"] and "redone carefully" not in blocks["kron"]
+    assert "redone carefully" in blocks["long"]
+    assert "redone carefully" in blocks["many groups"]
+
+
 def test_wide_mode_and_unit_modes(oracle_mod):
     idx, val, dims = synth.random_sparse((1, 300, 1, 7, 2), 500, 33)
     check_sparse_parity(oracle_mod, idx, val, dims, "unit modes")
