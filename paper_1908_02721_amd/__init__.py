@@ -32,14 +32,27 @@ def _stream_handle(stream=None) -> ctypes.c_void_p:
 
 
 class _CAI:
-    """A borrowed device buffer exposed through __cuda_array_interface__."""
+    """A borrowed device buffer exposed through __cuda_array_interface__.  ``owner``
+    (the result that holds the buffer) stays alive as long as this object, which a
+    tensor made from it keeps."""
 
-    def __init__(self, ptr: int, shape, typestr: str):
+    def __init__(self, ptr: int, shape, typestr: str, owner=None):
         self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(int(x) for x in shape),
                                          "typestr": typestr, "version": 2, "strides": None}
+        self._owner = owner
 
 
 _TYPESTR = {torch.float64: "<f8", torch.float32: "<f4", torch.int64: "<i8", torch.int32: "<i4"}
+
+
+def _view_of_device(ptr: int, shape, dtype, owner) -> torch.Tensor:
+    """Zero-copy torch view of a library-owned device buffer that keeps ``owner`` alive."""
+    n = 1
+    for x in shape:
+        n *= int(x)
+    if n == 0 or not ptr:
+        return torch.empty(tuple(shape), dtype=dtype, device="cuda")
+    return torch.as_tensor(_CAI(ptr, shape, _TYPESTR[dtype], owner), device="cuda")
 
 
 def _copy_from_device(ptr: int, shape, dtype) -> torch.Tensor:
@@ -77,7 +90,6 @@ class TT:
         t = (ctypes.c_double * _lib.NUM_STAGES)()
         _lib.check(L.tt_get_times(self._h, t))
         self.times_ms = dict(zip(STAGES, (float(x) for x in t)))
-        self._cores = None
         self.row_dims = self.col_dims = None  # set for a matrix decomposed as an MPO
 
     def __del__(self):
@@ -91,19 +103,19 @@ class TT:
 
     @property
     def cores(self):
-        """Owning torch copies of the cores, [r_{k-1}, n_k, r_k] each."""
-        if self._cores is None:
-            L = _lib.load()
-            out = []
-            for k in range(1, self.d + 1):
-                p = ctypes.c_void_p()
-                dt = ctypes.c_int32()
-                _lib.check(L.tt_get_core(self._h, k, ctypes.byref(p), ctypes.byref(dt)))
-                dtype = torch.float64 if dt.value == _lib.DTYPE_F64 else torch.float32
-                shape = (self.ranks[k - 1], self.dims[k - 1], self.ranks[k])
-                out.append(_copy_from_device(p.value, shape, dtype))
-            self._cores = out
-        return self._cores
+        """The cores, [r_{k-1}, n_k, r_k] each: torch views of this result's device
+        memory, made without a copy (ordered on the stream the decomposition ran on).
+        Each view keeps the result alive; writing to one changes the result's core."""
+        L = _lib.load()
+        out = []
+        for k in range(1, self.d + 1):
+            p = ctypes.c_void_p()
+            dt = ctypes.c_int32()
+            _lib.check(L.tt_get_core(self._h, k, ctypes.byref(p), ctypes.byref(dt)))
+            dtype = torch.float64 if dt.value == _lib.DTYPE_F64 else torch.float32
+            shape = (self.ranks[k - 1], self.dims[k - 1], self.ranks[k])
+            out.append(_view_of_device(p.value, shape, dtype, self))
+        return out
 
     def sigma(self, b: int):
         """Singular values at bond b (1..d-1) and the discarded sum of squares."""

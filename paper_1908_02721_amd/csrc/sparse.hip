@@ -152,9 +152,16 @@ __global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict_
 #pragma unroll
   for (int j = 0; j < LC_PER; ++j) cnt[j] = 0u;
   bool dup = false;
-  for (uint32_t e = blockIdx.x * NT + threadIdx.x; e < n; e += gridDim.x * NT) {
-    const uint64_t key = keys[e];
-    const uint64_t prev = (e > 0) ? keys[e - 1] : ~key;  // differs from key in every bit
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // a wave takes 64 consecutive keys at a time (uniform loop): each lane's predecessor
+  // comes from the lane below, the first lane's from memory
+  for (uint32_t base = blockIdx.x * NT + w * 64; base < n; base += gridDim.x * NT) {
+    const uint32_t e = base + lane;
+    const bool valid = e < n;
+    const uint64_t key = valid ? keys[e] : 0ull;
+    uint64_t prev = __shfl_up(key, 1, 64);
+    if (lane == 0) prev = (e > 0) ? keys[e - 1] : ~key;  // ~key differs from key in every bit
+    if (!valid) continue;
     dup = dup || (e > 0 && prev == key);
 #pragma unroll
     for (int j = 0; j < LC_PER; ++j) {
@@ -163,7 +170,6 @@ __global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict_
     }
   }
   if (dup && blockIdx.y == 0) atomicOr(&st->err, kErrDuplicate);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < LC_PER; ++j) {
     uint32_t v = cnt[j];

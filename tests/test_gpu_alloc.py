@@ -60,6 +60,7 @@ def test_allocator_hooks_give_the_same_result(case):
     for a, b in zip(tt.cores, ref.cores):
         assert torch.equal(a, b)
     assert len(hooks.live) > 0  # the result's cores
+    del a, b  # views of the cores keep their result alive
     del tt
     gc.collect()
     assert hooks.live == {}

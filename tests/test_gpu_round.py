@@ -194,6 +194,26 @@ def test_determinism():
         assert torch.equal(x, y)
 
 
+def test_core_views_keep_the_result_alive():
+    """tt.cores are views of the result's device memory: they keep it alive after the
+    result object itself is gone, while later calls reuse the library's freed blocks."""
+    import gc
+
+    tts = _tt()
+    idx, val, dims = synth.random_sparse((6, 5, 4, 6), 200, 1)
+    tt = tts.decompose(*_gpu(idx, val), dims, 1e-10)
+    cores = tt.cores
+    before = [c.clone() for c in cores]
+    del tt
+    gc.collect()
+    for seed in range(3):
+        i2, v2, d2 = synth.random_sparse((6, 5, 4, 6), 200, 10 + seed)
+        tts.decompose(*_gpu(i2, v2), d2, 1e-10)
+    torch.cuda.synchronize()
+    for a, b in zip(cores, before):
+        assert torch.equal(a, b)
+
+
 def test_deflation_rejected_and_redone(oracle_mod):
     """A term at 2^-24 of the rest: pivoted Cholesky (threshold 1e-12 on squared
     norms) drops its directions, the residual test (1e-13 ||A||) rejects the deflated
