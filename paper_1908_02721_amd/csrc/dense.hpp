@@ -56,6 +56,7 @@ struct SvdPart {
   int jacobi_runs = 0;
   int jacobi_sweeps = 0;  // sweeps of the final Jacobi run
   bool v_substituted = false;
+  bool u_direct = false;  // U = G Bt_final Sigma^-2: neither Q nor V formed
 };
 void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double delta2, int max_rank, SvdPart& o,
                    hipStream_t s);

@@ -2546,10 +2546,13 @@ __device__ bool jacobi_gram_converged(const double* A, double tol, double* T, do
 // substitution, whose columns are orthonormal to about n u kappa(L).  That is used
 // only when the sweeps converged and sigma_max <= kJacobiNoVCond sigma_min; otherwise
 // the kernel writes only sigma and info (info[1] = -1), leaves A as it was, and the
-// caller runs the ACCV = true kernel.
+// caller runs the ACCV = true kernel.  With want_v = 0 (ACCV = false) no V is formed
+// at all: A_final, sigma and info only, for callers that need the left singular
+// vectors of the triangular factor's product and not the rotations.
 template <int NC, bool ACCV>
 __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int rows, int c, int lda,
-                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info) {
+                                                   double* __restrict__ Vg, int ldv, double* __restrict__ sigma, int max_sweeps, int32_t* __restrict__ info,
+                                                   int want_v) {
   __shared__ unsigned long long gmax_;  // bits of the largest |a_p^T a_q| rotated in the last sweep
   // set when the current sweep rotates a pair with g^2 > 1e-12 a b
   __shared__ int bigrot;
@@ -2698,7 +2701,7 @@ __global__ __launch_bounds__(256) void k_jacobi64h(double* __restrict__ Ag, int 
     smax = fmax(smax, sj);
     smin = fmin(smin, sj);
   }
-  if (!ACCV) {
+  if (!ACCV && want_v) {
     // every lane of a group holds its columns' values: the wave extremes cover them
     for (int o = 32; o > 0; o >>= 1) {
       smax = fmax(smax, __shfl_xor(smax, o, 64));
@@ -3353,7 +3356,7 @@ int jacobi_sweep_cap() {
 }  // namespace
 
 bool jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info, hipStream_t s,
-                bool lower_tri) {
+                bool lower_tri, bool want_v) {
   if (c <= 0) return false;
   const int ms = jacobi_sweep_cap();
   const size_t shm = sizeof(double) * (static_cast<size_t>(rows) * c + static_cast<size_t>(c) * c);
@@ -3368,17 +3371,17 @@ bool jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double*
   const size_t shm_odd = sizeof(double) * (static_cast<size_t>(rows | 1) * c + static_cast<size_t>(c | 1) * c);
   if (c > 32 && c <= 64 && rows <= 64) {
     if (nov)
-      k_jacobi64h<64, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+      k_jacobi64h<64, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info, want_v ? 1 : 0);
     else
-      k_jacobi64h<64, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+      k_jacobi64h<64, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info, 1);
     TTS_LAUNCH_CHECK();
     return nov;
   }
   if (c > 16 && c <= 32 && rows <= 64) {
     if (nov)
-      k_jacobi64h<32, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+      k_jacobi64h<32, false><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info, want_v ? 1 : 0);
     else
-      k_jacobi64h<32, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info);
+      k_jacobi64h<32, true><<<1, 256, 0, s>>>(A, rows, c, lda, V, ldv, sigma, ms, info, 1);
     TTS_LAUNCH_CHECK();
     return nov;
   }

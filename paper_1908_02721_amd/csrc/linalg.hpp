@@ -89,9 +89,11 @@ void householder_extract_r(const double* A, int m, int n, int lda, double* R, in
 // info[1] is set to -1, V is left unspecified, sigma holds the column norms the
 // sweeps reached (the singular values when they converged), and the caller must call
 // again with lower_tri = false on the original matrix (A is left unchanged then).
+// want_v = false (with lower_tri): V is not needed, the 16 < c <= 64 kernels form none
+// (info[1] = 1 when converged); other widths still return it.
 // Returns whether the launch left the rotations unaccumulated (lower_tri honoured).
 bool jacobi_svd(double* A, int rows, int c, int lda, double* V, int ldv, double* sigma, int32_t* info,
-                hipStream_t s, bool lower_tri = false);
+                hipStream_t s, bool lower_tri = false, bool want_v = true);
 
 // Copy / transpose helpers.
 void copy_matrix(const double* A, int rows, int cols, int lda, double* B, int ldb, hipStream_t s);

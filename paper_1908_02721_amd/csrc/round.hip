@@ -54,7 +54,10 @@ __global__ void k_set_i32(int32_t* p, int n, int32_t v) {
 
 // perm[rank(j)] = j for the stable non-ascending order of s[0..n): rank(j) = number of
 // i with s_i > s_j, or s_i == s_j and i < j.
-__global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv, int n, int32_t* __restrict__ perm) {
+// perm[r] = the index of the r-th largest sv (stable), and inv_sq[r] = 1 / sv^2 of it
+// (when given)
+__global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv, int n, int32_t* __restrict__ perm,
+                                                   double* __restrict__ inv_sq) {
   for (int j = threadIdx.x; j < n; j += 256) {
     const double x = sv[j];
     int r = 0;
@@ -63,6 +66,7 @@ __global__ __launch_bounds__(256) void k_rank_desc(const double* __restrict__ sv
       r += (y > x || (y == x && i < j)) ? 1 : 0;
     }
     perm[r] = j;
+    if (inv_sq) inv_sq[r] = 1.0 / (x * x);
   }
 }
 
@@ -127,10 +131,10 @@ void cholqr_async(Allocator* al, const double* G, int m, int c, double* Q, doubl
                   hipStream_t s) {
   k_set_i32<<<1, 64, 0, s>>>(ok, 4, 1);
   TTS_LAUNCH_CHECK();
-  if (passes == 1) {  // Q = G R^{-1} straight into Q, R = chol(G^T G)
+  if (passes == 1) {  // R = chol(G^T G), and Q = G R^{-1} straight into Q when given
     gemm(al, true, false, c, c, m, 1.0, G, m, G, m, 0.0, R, c, s);
     cholesky_upper(R, c, c, 1e7, ok + 0, s);
-    trsm_right_upper(G, m, c, m, R, c, Q, m, ok + 1, s, al);
+    if (Q) trsm_right_upper(G, m, c, m, R, c, Q, m, ok + 1, s, al);
     return;
   }
   DBuf<double> g1(al, static_cast<size_t>(c) * c), q1(al, static_cast<size_t>(m) * c),
@@ -165,16 +169,16 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     haveQ = true;
     Qb.reset(A, static_cast<size_t>(m) * c);
   }
-  DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB);
+  DBuf<double> V(A, static_cast<size_t>(cB) * cB), sig(A, cB), isq(A, cB);
   DBuf<int32_t> dperm(A, cB), okq(A, 4), jinfo(A, 4);
   std::vector<double> sh(cB);
   alignas(8) int32_t hinfo[4] = {0, 0, 0, 0};
   Readback rb(s);
-  bool last_tri = false;
-  auto svd_of_bt = [&](bool lower_tri) {
-    last_tri = jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s, lower_tri);
+  bool last_tri = false, direct = false;
+  auto svd_of_bt = [&](bool lower_tri, bool want_v = true) {
+    last_tri = jacobi_svd(Bt.get(), c, cB, c, V.get(), cB, sig.get(), jinfo.get(), s, lower_tri, want_v) && want_v;
     ++o.jacobi_runs;
-    k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get());
+    k_rank_desc<<<1, 256, 0, s>>>(sig.get(), cB, dperm.get(), isq.get());
     TTS_LAUNCH_CHECK();
     rb.add(sh.data(), sig.get(), sizeof(double) * cB);
     rb.add(hinfo, jinfo.get(), sizeof(hinfo));
@@ -189,15 +193,20 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   };
   if (haveQ) {
     DBuf<double> R(A, static_cast<size_t>(c) * c);
-    // One CholeskyQR pass first: its Q is orthonormal to about u kappa(G)^2, enough
-    // when kappa(G) <= kOnePassCond.  The singular values read back with the Jacobi
-    // (those of R = those of G; written also when the Jacobi declined to form V)
+    // One CholeskyQR pass first, whose Q would be orthonormal to about u kappa(G)^2,
+    // enough when kappa(G) <= kOnePassCond.  The singular values read back with the
+    // Jacobi (those of R = those of G; written also when the Jacobi declined to form V)
     // decide; otherwise the bond is redone with CholeskyQR2, and beyond
     // kJacobiNoVCond its Jacobi accumulates the rotations at once.
-    cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 1, s);
+    // In FP64 the accepted pass needs neither Q nor the rotations: with Bt = R^T and
+    // Bt_final = U_t Sigma the Jacobi's rotated columns, G = (Q J) Sigma U_t^T gives
+    // U = Q J = G R^{-1} J = G U_t Sigma^{-1} = G Bt_final Sigma^{-2}, one product
+    // accurate to about kappa(G) u (the reduced modes keep their rounded Q J).
+    const bool direct_ok = prec == TT_FP64;
+    cholqr_async(A, G, m, c, direct_ok ? nullptr : Qb.get(), R.get(), okq.get(), 1, s);
     o.qr_passes = 1;
     transpose(R.get(), c, c, c, Bt.get(), c, s);
-    svd_of_bt(true);
+    svd_of_bt(true, !direct_ok);
     int32_t okh[4];
     rb.add(okh, okq.get(), sizeof(okh));
     rb.sync();
@@ -209,6 +218,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
     // false for non-finite values of a broken-down first pass
     const bool finite = okh[0] && okh[1] && smin > 0.0 && smax < HUGE_VAL;
     const bool two = !(finite && hinfo[1] == 1 && smax <= kOnePassCond * smin);
+    direct = direct_ok && !two;
     if (two) {
       const bool tri = finite && smax <= kJacobiNoVCond * smin;
       cholqr_async(A, G, m, c, Qb.get(), R.get(), okq.get(), 2, s);
@@ -225,7 +235,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
         rb.sync();
       }
     }
-    svd_of_r();
+    if (!direct) svd_of_r();
   } else {
     transpose(G, m, c, m, Bt.get(), c, s);
     svd_of_bt(false);
@@ -233,6 +243,7 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   }
   svd_check(hinfo, sh.data(), cB, c);
   o.v_substituted = last_tri && hinfo[1] == 1;
+  o.u_direct = direct;
   o.jacobi_sweeps = hinfo[0];
   // the same stable non-ascending order as k_rank_desc
   std::vector<int32_t> perm(cB);
@@ -261,11 +272,15 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   o.rank = rk;
   DBuf<double> UR(A, static_cast<size_t>(cB) * rk);
   o.VS.reset(A, static_cast<size_t>(c) * rk);
-  permute_cols(V.get(), cB, cB, dperm.get(), nullptr, rk, UR.get(), cB, s);
+  // direct: UR = the rotated columns scaled by 1 / sigma^2, U = G UR; otherwise UR = J
+  permute_cols(direct ? Bt.get() : V.get(), direct ? c : cB, direct ? c : cB, dperm.get(), direct ? isq.get() : nullptr,
+               rk, UR.get(), cB, s);
   permute_cols(Bt.get(), c, c, dperm.get(), nullptr, rk, o.VS.get(), c, s);
   o.U.reset(A, sizeof(double) * static_cast<size_t>(m) * rk);
   double* U = reinterpret_cast<double*>(o.U.get());
-  if (haveQ)
+  if (direct)
+    gemm(A, false, false, m, rk, c, 1.0, G, m, UR.get(), c, 0.0, U, m, s);
+  else if (haveQ)
     gemm_prec(A, prec, false, false, m, rk, c, 1.0, Qb.get(), m, UR.get(), c, 0.0, U, m, s);
   else
     copy_matrix(UR.get(), m, rk, m, U, m, s);
@@ -498,7 +513,9 @@ void round_tt(Allocator& al, const RoundInput& in, RoundOutput& out, hipStream_t
     logf("SVD bond %d: %d x %d, rank %d, discarded sum of sigma^2 %.3e ||A||^2 (threshold^2 %.3e), "
          "QR passes %d, Jacobi runs %d (last %d sweeps), V %s, %.3f ms (host)",
          k - 1, m, rl, sv.rank, sv.tail / (in.norm * in.norm), delta2 / (in.norm * in.norm), sv.qr_passes,
-         sv.jacobi_runs, sv.jacobi_sweeps, sv.v_substituted ? "by substitution" : "accumulated", host_ms() - t_bond);
+         sv.jacobi_runs, sv.jacobi_sweeps,
+         sv.u_direct ? "not formed (U from G)" : (sv.v_substituted ? "by substitution" : "accumulated"),
+         host_ms() - t_bond);
     t_bond = host_ms();
     out.sigma[k - 2] = std::move(sv.sigma);
     out.tail[k - 2] = sv.tail;

@@ -363,24 +363,25 @@ def test_progress_log():
 #
 # Rank-1 terms with disjoint supports: every bond of the SVD sweep gets a factor of
 # known condition number kappa (the weights' spread), c = terms columns, m > c rows.
-# The truncated SVD takes one CholeskyQR pass when kappa <= 30, CholeskyQR2 above;
-# the Jacobi on R^T forms V by substitution when kappa <= 100 (for 16 < c <= 64),
-# and accumulates the rotations above; when CholeskyQR breaks down, Householder.
+# The truncated SVD takes one CholeskyQR pass when kappa <= 30, and then forms U from
+# G and the rotated columns (neither Q nor V); CholeskyQR2 above, where the Jacobi on
+# R^T forms V by substitution when kappa <= 100 (for 16 < c <= 64) and accumulates the
+# rotations above; when CholeskyQR breaks down, Householder.
 SVD_PATHS = [
-    # (terms, kappa, QR passes, Jacobi runs, V by substitution); None: not asserted
-    (40, 10.0, 1, 1, True),
-    (40, 60.0, 2, 2, True),
-    (40, 1000.0, 2, 2, False),
-    (24, 10.0, 1, 1, True),
-    (24, 60.0, 2, 2, True),
-    (24, 1000.0, 2, 2, False),
-    (40, 1e9, None, None, False),
+    # (terms, kappa, QR passes, Jacobi runs, V); None: not asserted
+    (40, 10.0, 1, 1, "not formed"),
+    (40, 60.0, 2, 2, "by substitution"),
+    (40, 1000.0, 2, 2, "accumulated"),
+    (24, 10.0, 1, 1, "not formed"),
+    (24, 60.0, 2, 2, "by substitution"),
+    (24, 1000.0, 2, 2, "accumulated"),
+    (40, 1e9, None, None, "accumulated"),
 ]
 
 
-@pytest.mark.parametrize("terms,kappa,passes,runs,subst", SVD_PATHS)
+@pytest.mark.parametrize("terms,kappa,passes,runs,vmode", SVD_PATHS)
 @pytest.mark.parametrize("eps", [1e-12, 0.05])
-def test_svd_paths_by_condition_number(oracle_mod, terms, kappa, passes, runs, subst, eps):
+def test_svd_paths_by_condition_number(oracle_mod, terms, kappa, passes, runs, vmode, eps):
     d, q = 4, 2
     idx, val, dims = synth.orthogonal_terms(d, terms, q, kappa, seed=terms)
     tt, _ = check_round(oracle_mod, idx, val, dims, eps, f"orthogonal terms T={terms} kappa={kappa:g}")
@@ -420,8 +421,8 @@ def test_svd_path_log():
     blocks = r.stderr.split("CASE ")[1:]
     assert len(blocks) == len(cases) + 1, r.stderr[-3000:]
     pat = re.compile(r"SVD bond (\d+): (\d+) x (\d+), .*QR passes (\d+), Jacobi runs (\d+) \(last \d+ sweeps\), "
-                     r"V (by substitution|accumulated)")
-    for (terms, kappa, passes, runs, subst), blk in zip(SVD_PATHS, blocks):
+                     r"V (by substitution|accumulated|not formed)")
+    for (terms, kappa, passes, runs, vmode), blk in zip(SVD_PATHS, blocks):
         found = pat.findall(blk)
         print(f"[svd path] T={terms} kappa={kappa:g}: {found}", flush=True)
         assert len(found) == 3
@@ -433,4 +434,4 @@ def test_svd_path_log():
                 assert int(p) >= 2, (terms, kappa, bond, p)
             if runs is not None:
                 assert int(j) == runs, (terms, kappa, bond, j)
-            assert (v == "by substitution") == subst, (terms, kappa, bond, v)
+            assert v == vmode, (terms, kappa, bond, v)
