@@ -148,7 +148,7 @@ void cholqr_async(Allocator* al, const double* G, int m, int c, double* Q, doubl
   gemm(al, false, false, c, c, c, 1.0, g2.get(), c, g1.get(), c, 0.0, R, c, s);
 }
 
-// Truncated SVD of the column-major m x c matrix G (read only): G = Q R (m > c) or G
+// Truncated SVD of the column-major m x c matrix G (read only): G = Q R (m >= c) or G
 // itself; one-sided Jacobi then runs on the transpose, Bt = R^T or G^T (c x cB):
 // Bt U_R = V_R Sigma, so the accumulated rotations are the left singular vectors of
 // R (resp. G) and the rotated columns are V Sigma, both without a division by sigma.
@@ -164,7 +164,9 @@ void truncated_svd(Allocator* A, int prec, const double* G, int m, int c, double
   bool haveQ = false;
   int cB = m;
   Bt.reset(A, static_cast<size_t>(c) * std::min(m, c));
-  if (m > c) {
+  // a square G takes the QR too: the Jacobi on a triangular factor needs fewer sweeps
+  // and, with the one-pass QR accepted, no rotations
+  if (m >= c) {
     cB = c;
     haveQ = true;
     Qb.reset(A, static_cast<size_t>(m) * c);
