@@ -95,6 +95,9 @@ def _parse():
     p.add_argument("--slice-only", type=int, default=0, metavar="REPS",
                    help="only run the bond-2 Gram slice leg with REPS timed calls per precision (profiling)")
     p.add_argument("--slice-precisions", default="fp64,fp32,bf16", help="precisions of the slice leg")
+    p.add_argument("--no-hbm", action="store_true",
+                   help="skip roofline.sparse_hbm (its device-copy calibration and the decomposition "
+                        "run alone): for profiling runs whose kernel tables must hold only the steps")
     p.add_argument("--no-overlap", action="store_true",
                    help="build the evaluation plan after the decomposition instead of beside it")
     p.add_argument("--cpu-sample", type=int, default=20000, help="entries of the oracle's eval/backward sample")
@@ -554,7 +557,7 @@ def main():
         if family in SINGLE_WORKGROUP:
             out["roofline"]["single_workgroup"] = True
             out["roofline"]["frac_of_one_cu"] = achieved / (peak / NUM_CU)
-    if args.method == "cps":
+    if args.method == "cps" and not args.no_hbm:
         # the sparse stage (ingest, sort, every level) against HBM: algorithmic bytes over
         # its time, against the spec and against a device copy measured here
         b_alg = sparse_alg_bytes(nnz, len(dims), tt.level_sizes())

@@ -119,8 +119,13 @@ void tt_options_default(tt_options* opt);
  *   opt   : NULL for the defaults
  *   out   : receives the result handle; release it with tt_free
  * All work is enqueued on `stream`; the call waits for its own small device-to-
- * host counts (two per level, three for a level of more than 2048 groups, and one
- * per bond) and returns when the result is complete.
+ * host counts and returns when the result is complete.  With the library's own
+ * allocator and no budget, the sparse stage reads its sizes twice in all (every
+ * level's column count after the sort, then every level's group and entry counts),
+ * and is redone with per-level reads (two per level, three for a level of more than
+ * 2048 groups) when a level has a column of more than 32 entries or more than 2048
+ * groups; with allocator hooks or a budget it always reads per level.  The rounding
+ * reads back once per bond (twice when a bond's QR or SVD is redone).
  */
 tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,
                               const double* val, double eps, const tt_options* opt, void* stream,
