@@ -120,11 +120,12 @@ void tt_options_default(tt_options* opt);
  *   out   : receives the result handle; release it with tt_free
  * All work is enqueued on `stream`; the call waits for its own small device-to-
  * host counts and returns when the result is complete.  With the library's own
- * allocator and no budget, the sparse stage reads its sizes twice in all (every
- * level's column count after the sort, then every level's group and entry counts),
- * and is redone with per-level reads (two per level, three for a level of more than
- * 2048 groups) when a level has a column of more than 32 entries or more than 2048
- * groups; with allocator hooks or a budget it always reads per level.  The rounding
+ * allocator and no budget, the sparse stage reads back twice in all (the input
+ * checks and every level's column count after the sort, then every level's group and
+ * entry counts), and is redone with a read-back after the ingest and per-level reads
+ * (two per level, three for a level of more than 2048 groups) when the input holds
+ * explicit zeros or a level has a column of more than 32 entries or more than 2048
+ * groups; with allocator hooks or a budget it always reads that way.  The rounding
  * reads back once per bond (twice when a bond's QR or SVD is redone).
  */
 tt_status tt_sparse_decompose(int32_t d, const int64_t* dims, int64_t nnz, const int32_t* idx,

@@ -323,9 +323,10 @@ void sync_status(DevStatus* d_st, hipStream_t s) {
 // The careful pass reads them back as the level goes (up to two read-backs a level).
 // The speculative pass reads every level's column count once, right after the sort
 // (distinct suffixes of the sorted keys, k_level_counts), and sizes the rest by upper
-// bounds (beta <= columns, nnz(N_k) <= entries), on the assumptions that no column is
-// longer than kMaxLocal entries and that beta fits the device-count leader sort
-// (kSmallSortMax) where the column count does not already guarantee it.  Its kernels
+// bounds (beta <= columns, nnz(N_k) <= entries), on the assumptions that no input
+// value is an explicit zero, that no column is longer than kMaxLocal entries, and that
+// beta fits the device-count leader sort (kSmallSortMax) where the column count does
+// not already guarantee it (the grouping table then sized for that many).  Its kernels
 // read the counts from the device and stay in bounds when an assumption fails; one
 // read-back at the end checks them, and the stage is then redone carefully.  Returns
 // false in that case.
@@ -339,9 +340,12 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
   // a1: ingest
   DBuf<uint64_t> keys(al, nnz), vals(al, nnz);
   launch_ingest(idx, val, nnz, mi, keys.get(), vals.get(), st.get(), s);
-  sync_status(st.get(), s);
-  const uint32_t kept = nnz - host_status()->dropped;
-  {
+  // the careful pass reads the status back here; the speculative one assumes no
+  // explicit zeros and checks the status with its first read-back
+  uint32_t kept = nnz;
+  if (!spec) {
+    sync_status(st.get(), s);
+    kept = nnz - host_status()->dropped;
     const DevStatus* h = host_status();
     if (h->err & kErrIndex) fail(TT_ERR_INDEX, "a coordinate is outside its mode range");
     if (h->err & kErrNonfinite) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");
@@ -372,7 +376,14 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     rb.add(ncols_h.data(), cnt.get(), sizeof(uint32_t) * (d + 1));
     rb.add(host_status(), st.get(), sizeof(DevStatus));
     rb.sync();
-    if (host_status()->err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
+    const DevStatus* h = host_status();
+    if (h->err & kErrIndex) fail(TT_ERR_INDEX, "a coordinate is outside its mode range");
+    if (h->err & kErrNonfinite) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");
+    if (h->dropped) {
+      logf("speculative sizes do not hold (%u explicit zeros among the nonzeros); redone carefully", h->dropped);
+      return false;
+    }
+    if (h->err & kErrDuplicate) fail(TT_ERR_DUPLICATE, "a coordinate appears twice among the nonzeros");
   }
 
   // a3..a7: levels
@@ -394,14 +405,21 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     uint32_t* d_ncols = spec ? lv.get() + 4 * k - 4 : &st.get()->ncols;
     uint32_t* d_beta = spec ? lv.get() + 4 * k - 3 : &st.get()->beta;
     uint32_t* d_nnz = spec ? lv.get() + 4 * k - 2 : &st.get()->nnz_n;
-    DBuf<uint32_t> flag(al, nE), pos(al, nE), col_start(al, static_cast<size_t>(nE) + 1);
-    DBuf<double> norm_part;
-    if (level1) norm_part.reset(al, norm_partials_count(nE));
-    launch_col_flags(ekey.get(), nE, sh, level1, level1 ? -1 : k - 1, evp, flag.get(), norm_part.get(), st.get(),
-                     s);
-    exclusive_scan_u32(al, flag.get(), pos.get(), nE, d_ncols, s);
-    launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), d_ncols, s);
-    if (level1) launch_norm_final(norm_part.get(), norm_partials_count(nE), st.get(), s);
+    DBuf<uint32_t> flag, pos, col_start(al, static_cast<size_t>(nE) + 1);
+    if (spec && !level1 && nE <= kColsSmallMax) {
+      // small level of a speculative pass (never the long-column path): one workgroup
+      launch_columns_small(ekey.get(), nE, sh, k - 1, col_start.get(), d_ncols, st.get(), s);
+    } else {
+      flag.reset(al, nE);
+      pos.reset(al, nE);
+      DBuf<double> norm_part;
+      if (level1) norm_part.reset(al, norm_partials_count(nE));
+      launch_col_flags(ekey.get(), nE, sh, level1, level1 ? -1 : k - 1, evp, flag.get(), norm_part.get(),
+                       st.get(), s);
+      exclusive_scan_u32(al, flag.get(), pos.get(), nE, d_ncols, s);
+      launch_col_starts(flag.get(), pos.get(), nE, col_start.get(), d_ncols, s);
+      if (level1) launch_norm_final(norm_part.get(), norm_partials_count(nE), st.get(), s);
+    }
     uint32_t ncols;
     bool longcol = false;
     if (!spec) {
@@ -444,9 +462,14 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     DBuf<uint32_t> crho(al, nE);
     DBuf<double> cval(al, nE), cols(al, ncols);
     DBuf<uint64_t> colhash(al, ncols), colsuf(al, ncols), rmkey(al, ncols);
-    // a5's hash table and group ids, cleared by the canonicalisation kernel
+    // a5's hash table and group ids, cleared by the canonicalisation kernel, with at
+    // least twice as many slots as groups: twice the columns, or on a speculative pass
+    // twice the most groups it allows (kSmallSortMax), probes then bounded by
+    // kSpecMaxProbe (an overflow fails the speculation)
+    const bool small_table = spec && ncols > kSmallSortMax;
+    const uint32_t tcols = small_table ? kSmallSortMax : ncols;
     uint32_t tsize = 1;
-    while (tsize < 2u * ncols + 2u) tsize <<= 1;
+    while (tsize < 2u * tcols + 2u) tsize <<= 1;
     DBuf<uint64_t> table(al, tsize), slotmin(al, tsize);
     DBuf<uint32_t> slot_gid(al, tsize);
     CanonArgs ca{};
@@ -475,23 +498,51 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     // a5: group
     DBuf<uint32_t> slot(al, ncols), isrep(al, ncols);
     launch_group(colhash.get(), crho.get(), cval.get(), col_start.get(), rmkey.get(), ncols, table.get(),
-                 slotmin.get(), tsize - 1, slot.get(), isrep.get(), s);
+                 slotmin.get(), tsize - 1, small_table ? kSpecMaxProbe : tsize,
+                 small_table ? &st.get()->table_over : nullptr, slot.get(), isrep.get(), s);
     DBuf<uint32_t> reppos(al, ncols);
-    exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, d_beta, s);
     int rm_bits = 0;
     for (int j = kidx; j < d; ++j) rm_bits += static_cast<int>(mi.bits[j]);
     // Up to kSmallSortMax groups (the common case) the leaders are ordered without
-    // knowing beta on the host: the group count is read by the kernels from the
-    // device, and beta and nnz(N_k) come back in one read-back.  Beyond that the
-    // leaders are sorted again with the device-wide radix sort.
+    // knowing beta on the host, in one workgroup that counts and lists the groups
+    // itself (on a speculative pass from the grouping table, on a careful one from the
+    // columns' flags up to kLeaderListMax columns) or reads the count from the device;
+    // beta and nnz(N_k) come back in one read-back.
+    // Beyond that the leaders are sorted again with the device-wide radix sort.
     const uint32_t cap = std::min<uint32_t>(ncols, kSmallSortMax);
     caps[k] = cap;
-    DBuf<uint64_t> lkey(al, cap), lslot(al, cap), lks(al, cap), lss(al, cap);
-    DBuf<uint32_t> nlen(al, cap), npos(al, cap);
-    launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, cap, lkey.get(), lslot.get(), s);
-    sort_small_device_count(lkey.get(), lslot.get(), d_beta, cap, rm_bits, lks.get(), lss.get(), s);
-    launch_group_ids(lss.get(), 0, d_beta, cap, table.get(), col_start.get(), slot_gid.get(), nlen.get(), s);
-    exclusive_scan_u32(al, nlen.get(), npos.get(), cap, d_nnz, s);
+    DBuf<uint64_t> lkey, lslot, lss(al, cap);
+    DBuf<uint32_t> nlen, npos(al, cap);
+    LeaderArgs la{};
+    if (spec && tsize <= kLeaderTableMax) {
+      // every group owns one slot of the (small) table: the list comes from there
+      la.tscan = 1;
+      la.tsize = tsize;
+      la.slotmin = slotmin.get();
+    } else if (ncols <= kLeaderListMax) {
+      la.isrep = isrep.get();
+      la.reppos = reppos.get();
+      la.slot = slot.get();
+      la.slotmin = slotmin.get();
+      la.ncols = ncols;
+    } else {
+      exclusive_scan_u32(al, isrep.get(), reppos.get(), ncols, d_beta, s);
+      lkey.reset(al, cap);
+      lslot.reset(al, cap);
+      launch_rep_list(isrep.get(), reppos.get(), slot.get(), slotmin.get(), ncols, cap, lkey.get(), lslot.get(), s);
+      la.lkey = lkey.get();
+      la.lslot = lslot.get();
+    }
+    la.d_beta = d_beta;
+    la.cap = cap;
+    la.nbits = rm_bits;
+    la.table = table.get();
+    la.col_start = col_start.get();
+    la.lss = lss.get();
+    la.slot_gid = slot_gid.get();
+    la.npos = npos.get();
+    la.d_nnz = d_nnz;
+    launch_leaders(la, s);
     // beta, nnz(N_k): exact (careful pass) or upper bounds (speculative pass: checked
     // at the end, beta <= cap assumed)
     uint32_t beta = cap, nnz_n = nE;
@@ -531,10 +582,20 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     L.colptr.reset(al, static_cast<size_t>(beta) + 1);
     L.row.reset(al, nnz_n);
     L.val.reset(al, nnz_n);
-    launch_emit_n(lss.get(), beta, d_beta, table.get(), col_start.get(), npos.get(), crho.get(), cval.get(),
-                  L.colptr.get(), L.row.get(), L.val.get(), d_nnz, s);
-    // a7: next level (or the last core)
+    // a7: next level (or the last core), in the same launch
     EmitArgs ea{};
+    ea.lss = lss.get();
+    ea.bmax = beta;
+    ea.d_beta = d_beta;
+    ea.d_nnz = d_nnz;
+    ea.table = table.get();
+    ea.col_start = col_start.get();
+    ea.npos = npos.get();
+    ea.crho = crho.get();
+    ea.cval = cval.get();
+    ea.colptr = L.colptr.get();
+    ea.nrow = L.row.get();
+    ea.nval = L.val.get();
     ea.ncols = ncols;
     ea.slot = slot.get();
     ea.slot_gid = slot_gid.get();
@@ -566,7 +627,7 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
       TTS_HIP(hipMemsetAsync(R->last_exact.get(), 0, sizeof(double) * sz, s));
       ea.last_core = R->last_exact.get();
     }
-    launch_emit_next(ea, mi, s);
+    launch_emit(ea, mi, s);
     if (!spec)
       logf("level %d: %u entries, %u columns, beta %u, nnz(N_k) %u, %.3f ms (host)", k, nE, ncols, beta, nnz_n,
            host_ms() - t_level);
@@ -588,6 +649,10 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     rb.sync();
     const DevStatus hs = *host_status();
     bool ok = true;
+    if (hs.table_over) {
+      logf("speculative sizes do not hold (a grouping table overflowed); redone carefully");
+      return false;
+    }
     uint32_t ne = kept;
     for (int k = 1; k <= d - 1; ++k) {
       const uint32_t nc = lh[4 * k - 4], beta = lh[4 * k - 3], nz = lh[4 * k - 2];

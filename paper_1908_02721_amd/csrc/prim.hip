@@ -475,14 +475,6 @@ bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t
   return ki != keys;
 }
 
-void sort_small_device_count(const uint64_t* keys, const uint64_t* vals, const uint32_t* d_n, uint32_t cap,
-                             int nbits, uint64_t* kout, uint64_t* vout, hipStream_t s) {
-  if (cap == 0) return;
-  if (cap > SMALL_SORT) fail(TT_ERR_TOO_LARGE, "device-count small sort beyond its capacity");
-  k_sort_small<<<1, 1024, 0, s>>>(keys, vals, 0, nbits, kout, vout, d_n, cap);
-  TTS_LAUNCH_CHECK();
-}
-
 void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp, uint64_t* vtmp,
                       uint32_t n, int nbits, hipStream_t s) {
   if (radix_sort_pairs_pp(al, keys, vals, ktmp, vtmp, n, nbits, s)) {

@@ -19,11 +19,8 @@ void radix_sort_pairs(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* k
 // (ktmp, vtmp) (an odd number of passes), false when they are in (keys, vals).
 bool radix_sort_pairs_pp(Allocator* al, uint64_t* keys, uint64_t* vals, uint64_t* ktmp,
                          uint64_t* vtmp, uint32_t n, int nbits, hipStream_t s);
-// Stable one-workgroup sort of the first *d_n pairs (count read on the device) into
-// (kout, vout), for counts up to cap <= kSmallSortMax; a larger count sorts nothing
-// (the caller sees the count after its next read-back and sorts otherwise).
+// Most pairs a one-workgroup rank sort takes (the sort itself for small counts, and
+// the sparse stage's leader phase).
 constexpr uint32_t kSmallSortMax = 2048;
-void sort_small_device_count(const uint64_t* keys, const uint64_t* vals, const uint32_t* d_n, uint32_t cap,
-                             int nbits, uint64_t* kout, uint64_t* vout, hipStream_t s);
 
 }  // namespace tts

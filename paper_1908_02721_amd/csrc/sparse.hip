@@ -4,8 +4,10 @@
 //
 // Data flow of one level k (entries of M_k sorted so that every column -- a suffix
 // (i_{k+1},...,i_d) -- is one contiguous segment):
-//   col_flags/col_starts : segment boundaries -> column start offsets
-//   canon                : one thread per column: order its entries by row rho,
+//   col_flags/col_starts : segment boundaries -> column start offsets (columns_small:
+//                          the same in one workgroup for small levels)
+//   canon                : one thread (canon_wave: one wave) per column: order its
+//                          entries by row rho,
 //                          s = value at the smallest row, c_j = v_j / s (IEEE
 //                          binary64 division, optionally rounded to fewer fraction
 //                          bits: the tolerant test), 64-bit hash of (m, rho_j, bits(c_j))
@@ -13,11 +15,13 @@
 //                          finds an occupied slot compares its full canonical key
 //                          with the slot's representative column; the smallest
 //                          row-major suffix key of each group is its leader
-//   rep_list + sort      : leaders sorted by row-major suffix key -> group ids
-//                          (first occurrence in row-major column order)
-//   emit_n / emit_next   : N_k (CSC) and the next level's entries
+//   leaders              : leaders sorted by row-major suffix key -> group ids
+//                          (first occurrence in row-major column order), N_k's
+//                          column places
+//   emit                 : N_k (CSC) and the next level's entries
 //                          (rho' = g * n_{k+1} + i_{k+1}, value s)
 #include "sparse.hpp"
+#include "prim.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -32,7 +36,7 @@ __device__ __forceinline__ uint64_t fmask(uint32_t b) { return (b >= 64) ? ~0ull
 
 __global__ __launch_bounds__(NT) void k_ingest(const int32_t* __restrict__ idx, const double* __restrict__ val,
                                                uint32_t nnz, ModeInfo mi, uint64_t* __restrict__ keys,
-                                               uint64_t* __restrict__ vbits, DevStatus* st) {
+                                               uint64_t* __restrict__ vbits, DevStatus* st, int vec4) {
   const uint32_t e = blockIdx.x * NT + threadIdx.x;
   bool zero = false;
   if (e < nnz) {
@@ -40,11 +44,19 @@ __global__ __launch_bounds__(NT) void k_ingest(const int32_t* __restrict__ idx, 
     const double v = val[e];
     uint64_t key = 0;
     bool bad = false;
-    // the coordinates eight at a time, each group's loads issued together
+    // the coordinates eight at a time, each group's loads issued together (as two
+    // 16-byte loads when every row is 16-byte aligned)
     for (int j0 = 0; j0 < mi.d; j0 += 8) {
       int32_t x[8];
+      if (vec4) {
+        const int4 a = *reinterpret_cast<const int4*>(c + j0);
+        const int4 b = (j0 + 4 < mi.d) ? *reinterpret_cast<const int4*>(c + j0 + 4) : make_int4(0, 0, 0, 0);
+        x[0] = a.x, x[1] = a.y, x[2] = a.z, x[3] = a.w;
+        x[4] = b.x, x[5] = b.y, x[6] = b.z, x[7] = b.w;
+      } else {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = c[(j0 + u < mi.d) ? j0 + u : 0];
+        for (int u = 0; u < 8; ++u) x[u] = c[(j0 + u < mi.d) ? j0 + u : 0];
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int j = j0 + u;
@@ -83,12 +95,11 @@ __global__ __launch_bounds__(NT) void k_col_flags(const uint64_t* __restrict__ e
       const double v = ev[e];
       sq = v * v;
     }
-    if (long_bit >= 0 && start) {
-      uint32_t j = e + 1;
-      const uint32_t lim = (nE - e > static_cast<uint32_t>(kMaxLocal) + 1) ? e + kMaxLocal + 1 : nE;
-      while (j < lim && (ekey[j] >> sh) == col) ++j;
-      if (j - e > static_cast<uint32_t>(kMaxLocal)) atomicOr(&st->longmask, 1ull << long_bit);
-    }
+    // columns are contiguous runs of the sorted entries: the one starting at e is
+    // longer than kMaxLocal exactly when entry e + kMaxLocal still belongs to it
+    if (long_bit >= 0 && start && nE - e > static_cast<uint32_t>(kMaxLocal) &&
+        (ekey[e + kMaxLocal] >> sh) == col)
+      atomicOr(&st->longmask, 1ull << long_bit);
   }
   if (level1) {
     sq = wave_sum_f64(sq);
@@ -136,6 +147,62 @@ __global__ __launch_bounds__(NT) void k_col_starts(const uint32_t* __restrict__ 
   if (e == 0) col_start[*d_ncols] = nE;
 }
 
+// a3 for a level k >= 2 of at most kColsSmallMax entries in one workgroup: thread t
+// takes a contiguous run of at most CS_PER entries (held in registers), counts the
+// column starts in it (an entry whose suffix differs from its predecessor's), and
+// after a workgroup scan writes each start's column place, and flags a column
+// longer than kMaxLocal entries.  Same col_start, *d_ncols and long-column bit as
+// k_col_flags, the scan and k_col_starts.
+constexpr int CS_NT = 1024;
+constexpr int CS_PER = static_cast<int>(kColsSmallMax / CS_NT);
+__device__ __forceinline__ void columns_small_block(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,
+                                                    int long_bit, uint32_t* __restrict__ col_start,
+                                                    uint32_t* __restrict__ d_ncols, DevStatus* st) {
+  __shared__ uint32_t red[CS_NT / 64];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (nE + CS_NT - 1) / CS_NT;
+  const uint32_t b = min(nE, t * per), e1 = min(nE, b + per);
+  uint64_t col[CS_PER];
+#pragma unroll
+  for (int u = 0; u < CS_PER; ++u) {
+    const uint32_t e = b + u;
+    col[u] = e < e1 ? (ekey[e] >> sh) : 0ull;
+  }
+  const uint64_t before = (b > 0 && b < e1) ? (ekey[b - 1] >> sh) : 0ull;
+  uint32_t starts = 0;  // bit u: entry b + u starts a column
+#pragma unroll
+  for (int u = 0; u < CS_PER; ++u) {
+    const uint32_t e = b + u;
+    const bool st_u = e < e1 && (e == 0 || (u == 0 ? before : col[u > 0 ? u - 1 : 0]) != col[u]);
+    starts |= st_u ? (1u << u) : 0u;
+  }
+  uint32_t tot;
+  uint32_t pos = block_excl_scan_u32<CS_NT>(static_cast<uint32_t>(__popc(starts)), red, &tot);
+#pragma unroll
+  for (int u = 0; u < CS_PER; ++u)
+    if ((starts >> u) & 1u) col_start[pos++] = b + u;
+  if (t == 0) {
+    col_start[tot] = nE;
+    *d_ncols = tot;
+  }
+  if (long_bit < 0) return;
+  // a column is longer than kMaxLocal exactly when the entry kMaxLocal past its start
+  // still belongs to it (columns are contiguous runs of the sorted entries)
+  bool lng = false;
+#pragma unroll
+  for (int u = 0; u < CS_PER; ++u) {
+    const uint32_t e = b + u;
+    if (((starts >> u) & 1u) && nE - e > static_cast<uint32_t>(kMaxLocal))
+      lng = lng || (ekey[e + kMaxLocal] >> sh) == col[u];
+  }
+  if (lng) atomicOr(&st->longmask, 1ull << long_bit);
+}
+__global__ __launch_bounds__(CS_NT) void k_columns_small(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,
+                                                         int long_bit, uint32_t* __restrict__ col_start,
+                                                         uint32_t* __restrict__ d_ncols, DevStatus* st) {
+  columns_small_block(ekey, nE, sh, long_bit, col_start, d_ncols, st);
+}
+
 // Column counts of every level from the globally sorted kept keys.  A level-k column
 // (k = 1 .. d-1) is a distinct suffix key >> off[k] (modes k .. d-1), so its count is
 // the number of positions where that suffix differs from the previous key's (the first
@@ -143,6 +210,7 @@ __global__ __launch_bounds__(NT) void k_col_starts(const uint32_t* __restrict__ 
 // per-workgroup sums go to counts[k] with one atomic each.  Also flags a duplicate
 // (equal neighbouring keys).
 constexpr int LC_PER = 8;
+constexpr int LC_U = 8;  // runs of 64 keys per wave and loop trip
 __device__ __forceinline__ uint64_t suffix_of(uint64_t key, uint32_t off) { return off >= 64 ? 0ull : key >> off; }
 __global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict__ keys, uint32_t n, ModeInfo mi,
                                                      uint32_t* __restrict__ counts, DevStatus* st) {
@@ -153,20 +221,31 @@ __global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict_
   for (int j = 0; j < LC_PER; ++j) cnt[j] = 0u;
   bool dup = false;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // a wave takes 64 consecutive keys at a time (uniform loop): each lane's predecessor
-  // comes from the lane below, the first lane's from memory
-  for (uint32_t base = blockIdx.x * NT + w * 64; base < n; base += gridDim.x * NT) {
-    const uint32_t e = base + lane;
-    const bool valid = e < n;
-    const uint64_t key = valid ? keys[e] : 0ull;
-    uint64_t prev = __shfl_up(key, 1, 64);
-    if (lane == 0) prev = (e > 0) ? keys[e - 1] : ~key;  // ~key differs from key in every bit
-    if (!valid) continue;
-    dup = dup || (e > 0 && prev == key);
+  // a wave takes 64 consecutive keys at a time (uniform loop), LC_U such runs with
+  // all their loads issued together: each lane's predecessor comes from the lane
+  // below, the first lane's from memory
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * NT;
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * NT + w * 64; base < n; base += LC_U * stride) {
+    uint64_t kk[LC_U], pk[LC_U];
 #pragma unroll
-    for (int j = 0; j < LC_PER; ++j) {
-      const int k = k0 + j;
-      if (k < mi.d) cnt[j] += (suffix_of(key, mi.off[k]) != suffix_of(prev, mi.off[k])) ? 1u : 0u;
+    for (int u = 0; u < LC_U; ++u) {
+      const uint64_t e = base + u * stride + lane;
+      kk[u] = e < n ? keys[e] : 0ull;
+      pk[u] = (lane == 0 && e > 0 && e < n) ? keys[e - 1] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < LC_U; ++u) {
+      const uint64_t e = base + u * stride + lane;
+      const uint64_t key = kk[u];
+      uint64_t prev = __shfl_up(key, 1, 64);
+      if (lane == 0) prev = (e > 0) ? pk[u] : ~key;  // ~key differs from key in every bit
+      if (e >= n) continue;
+      dup = dup || (e > 0 && prev == key);
+#pragma unroll
+      for (int j = 0; j < LC_PER; ++j) {
+        const int k = k0 + j;
+        if (k < mi.d) cnt[j] += (suffix_of(key, mi.off[k]) != suffix_of(prev, mi.off[k])) ? 1u : 0u;
+      }
     }
   }
   if (dup && blockIdx.y == 0) atomicOr(&st->err, kErrDuplicate);
@@ -260,6 +339,49 @@ __device__ __forceinline__ void clear_table(const CanonArgs& a, uint32_t t, uint
   }
 }
 
+// One column of at most CAP entries whose rows are not yet ordered: all its entries
+// are loaded at once (clamped addresses), the places beyond the column padded with
+// the largest row (rows are below 2^31).  The rows of a column are distinct, so an
+// entry's place in row order is the number of smaller rows: one compare-and-add per
+// pair, with no further condition.  s is the value at the smallest row, hs the
+// column's hash sum.
+template <int CAP>
+__device__ __forceinline__ void canon_rows(const CanonArgs& a, bool active, uint32_t st, uint32_t m, double* s,
+                                           uint64_t* hs) {
+  uint32_t rr[CAP];
+  double vv[CAP];
+#pragma unroll
+  for (int j = 0; j < CAP; ++j) {
+    const uint32_t e = st + min(static_cast<uint32_t>(j), m > 0 ? m - 1 : 0u);
+    const uint32_t r = active ? a.erho[e] : 0xffffffffu;
+    rr[j] = static_cast<uint32_t>(j) < m ? r : 0xffffffffu;
+    vv[j] = active ? a.ev[e] : 0.0;
+  }
+  uint32_t rmin = 0xffffffffu;
+  double sv = 0.0;
+#pragma unroll
+  for (int j = 0; j < CAP; ++j) {
+    const bool lt = rr[j] < rmin;
+    rmin = lt ? rr[j] : rmin;
+    sv = lt ? vv[j] : sv;
+  }
+  uint64_t h = 0;
+#pragma unroll
+  for (int j = 0; j < CAP; ++j) {
+    uint32_t rank = 0;
+#pragma unroll
+    for (int l = 0; l < CAP; ++l) rank += rr[l] < rr[j] ? 1u : 0u;
+    if (static_cast<uint32_t>(j) < m) {
+      const double cv = canon_value(vv[j], sv, a.snap);
+      a.crho[st + rank] = rr[j];
+      a.cval[st + rank] = cv;
+      h += col_hash_term(rank, rr[j], cv);
+    }
+  }
+  *s = sv;
+  *hs = h;
+}
+
 __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
   clear_table(a, c, gridDim.x * NT);
@@ -295,53 +417,63 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
       }
     }
   } else {
-    // at most kMaxLocal entries (checked by the host), all loaded at once; the rows
-    // of a column are distinct, so an entry's place in row order is the number of
-    // smaller rows.  Loops run to the wave's longest column, with fixed register
-    // indices throughout.
+    // at most kMaxLocal entries (checked by the host); the wave's longest column picks
+    // the register arrays' size, so short columns cost no more than their length
     uint32_t mw = m;
     for (int o = 32; o > 0; o >>= 1) mw = max(mw, static_cast<uint32_t>(__shfl_xor(mw, o, 64)));
-    uint32_t rr[kMaxLocal];
-    double vv[kMaxLocal];
-#pragma unroll
-    for (int j = 0; j < kMaxLocal; ++j) {
-      if (static_cast<uint32_t>(j) < mw) {
-        const uint32_t e = st + min(static_cast<uint32_t>(j), m > 0 ? m - 1 : 0u);
-        rr[j] = active ? a.erho[e] : 0u;
-        vv[j] = active ? a.ev[e] : 0.0;
-      } else {
-        rr[j] = 0u;
-        vv[j] = 0.0;
-      }
-    }
-    // value at the smallest row
-    uint32_t rmin = 0xffffffffu;
-#pragma unroll
-    for (int j = 0; j < kMaxLocal; ++j)
-      if (static_cast<uint32_t>(j) < m && rr[j] < rmin) {
-        rmin = rr[j];
-        s = vv[j];
-      }
-#pragma unroll
-    for (int j = 0; j < kMaxLocal; ++j) {
-      if (static_cast<uint32_t>(j) < mw) {
-        uint32_t rank = 0;
-#pragma unroll
-        for (int l = 0; l < kMaxLocal; ++l)
-          if (static_cast<uint32_t>(l) < mw) rank += (static_cast<uint32_t>(l) < m && rr[l] < rr[j]) ? 1u : 0u;
-        if (static_cast<uint32_t>(j) < m) {
-          const double cv = canon_value(vv[j], s, a.snap);
-          a.crho[st + rank] = rr[j];
-          a.cval[st + rank] = cv;
-          hs += col_hash_term(rank, rr[j], cv);
-        }
-      }
-    }
+    const uint32_t mwu = __builtin_amdgcn_readfirstlane(mw);
+    if (mwu <= 4)
+      canon_rows<4>(a, active, st, m, &s, &hs);
+    else if (mwu <= 8)
+      canon_rows<8>(a, active, st, m, &s, &hs);
+    else if (mwu <= 16)
+      canon_rows<16>(a, active, st, m, &s, &hs);
+    else
+      canon_rows<kMaxLocal>(a, active, st, m, &s, &hs);
   }
   if (!active) return;
   a.colhash[c] = col_hash_final(m, hs);
   a.cols[c] = s;
   col_keys(a, mi, c, st);
+}
+
+// The same for levels of few columns whose rows are not yet ordered (at most
+// kMaxLocal entries each, where one lane per column would leave most of the chip
+// idle): one wave per column, one lane per entry.  An entry's place is the number of
+// smaller rows among the column's (read lane by lane: the column length is uniform
+// over the wave); the value at the smallest row comes from the lane of place 0, and
+// the hash terms are summed over the wave.  The same results as k_canon.
+constexpr int CW_COLS = NT / 64;  // columns per workgroup
+__device__ __forceinline__ void canon_wave_col(const CanonArgs& a, const ModeInfo& mi, uint32_t c, uint32_t lane) {
+  const uint32_t st = a.col_start[c];
+  const uint32_t m = a.col_start[c + 1] - st;
+  const uint32_t mw = min(m, 64u);
+  const bool act = lane < mw;
+  const uint32_t r = act ? a.erho[st + lane] : 0xffffffffu;
+  const double v = act ? a.ev[st + lane] : 0.0;
+  uint32_t rank = 0;
+  for (uint32_t l = 0; l < mw; ++l)
+    rank += static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(r), static_cast<int>(l))) < r ? 1u : 0u;
+  const int first = __ffsll(static_cast<unsigned long long>(__ballot(act && rank == 0))) - 1;
+  const double s = __shfl(v, first, 64);
+  uint64_t h = 0;
+  if (act) {
+    const double cv = canon_value(v, s, a.snap);
+    a.crho[st + rank] = r;
+    a.cval[st + rank] = cv;
+    h = col_hash_term(rank, r, cv);
+  }
+  for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o, 64);
+  if (lane == 0) {
+    a.colhash[c] = col_hash_final(m, h);
+    a.cols[c] = s;
+    col_keys(a, mi, c, st);
+  }
+}
+__global__ __launch_bounds__(NT) void k_canon_wave(CanonArgs a, ModeInfo mi) {
+  clear_table(a, blockIdx.x * NT + threadIdx.x, gridDim.x * NT);
+  const uint32_t c = blockIdx.x * CW_COLS + (threadIdx.x >> 6);
+  if (c < a.ncols) canon_wave_col(a, mi, c, threadIdx.x & 63);  // the same for the whole wave
 }
 
 // The same for levels whose columns are already in row order and include long ones:
@@ -399,7 +531,8 @@ __device__ __forceinline__ bool same_column(const uint32_t* __restrict__ crho, c
 __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colhash, const uint32_t* __restrict__ crho,
                                               const double* __restrict__ cval, const uint32_t* __restrict__ col_start,
                                               const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
-                                              uint64_t* slotmin, uint32_t tmask, uint32_t* __restrict__ slot,
+                                              uint64_t* slotmin, uint32_t tmask, uint32_t max_probe,
+                                              uint32_t* over, uint32_t* __restrict__ slot,
                                               uint32_t* __restrict__ isrep, int aggregate) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
   const bool active = c < ncols;
@@ -408,8 +541,11 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
   const uint32_t m = active ? col_start[c + 1] - st : 0;
   uint32_t p = static_cast<uint32_t>(h) & tmask;
   uint32_t rep = 0;
-  // The table has more slots than columns, so an empty slot is always reached.
-  for (uint32_t probe = 0; active && probe <= tmask; ++probe) {
+  // A table with more slots than columns always has an empty slot within reach
+  // (max_probe = its size); a smaller one (speculative pass) may not, and a column
+  // that finds neither its group nor an empty slot within max_probe probes flags it.
+  uint32_t probe = 0;
+  for (; active && probe < max_probe; ++probe) {
     uint64_t cur = __hip_atomic_load(&table[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cur == 0) {
       const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&table[p]), 0ull,
@@ -427,6 +563,7 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
     }
     p = (p + 1) & tmask;
   }
+  if (active && probe == max_probe && over) atomicOr(over, 1u);
   if (active) {
     slot[c] = p;
     isrep[c] = rep;
@@ -464,10 +601,11 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
 __device__ __forceinline__ uint32_t global_probe(const uint64_t* __restrict__ colhash, const uint32_t* __restrict__ crho,
                                                  const double* __restrict__ cval,
                                                  const uint32_t* __restrict__ col_start, uint64_t* table, uint32_t tmask,
-                                                 uint32_t c, uint64_t h, uint32_t st, uint32_t m, uint32_t* rep) {
+                                                 uint32_t max_probe, uint32_t* over, uint32_t c, uint64_t h,
+                                                 uint32_t st, uint32_t m, uint32_t* rep) {
   uint32_t p = static_cast<uint32_t>(h) & tmask;
   *rep = 0;
-  for (uint32_t probe = 0; probe <= tmask; ++probe) {
+  for (uint32_t probe = 0; probe < max_probe; ++probe) {
     uint64_t cur = __hip_atomic_load(&table[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cur == 0) {
       const uint64_t old = atomicCAS(reinterpret_cast<unsigned long long*>(&table[p]), 0ull,
@@ -485,6 +623,7 @@ __device__ __forceinline__ uint32_t global_probe(const uint64_t* __restrict__ co
     }
     p = (p + 1) & tmask;
   }
+  if (over) atomicOr(over, 1u);
   return p;
 }
 
@@ -501,7 +640,8 @@ __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__
                                                     const uint32_t* __restrict__ crho, const double* __restrict__ cval,
                                                     const uint32_t* __restrict__ col_start,
                                                     const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
-                                                    uint64_t* slotmin, uint32_t tmask, uint32_t* __restrict__ slot,
+                                                    uint64_t* slotmin, uint32_t tmask, uint32_t max_probe,
+                                                    uint32_t* over, uint32_t* __restrict__ slot,
                                                     uint32_t* __restrict__ isrep) {
   constexpr int GL_TL = 2 * GL_CH, GL_PT = GL_CH / NT;
   static_assert(GL_CH % NT == 0 && (GL_CH & (GL_CH - 1)) == 0, "chunk of whole thread rounds, a power of two");
@@ -551,7 +691,7 @@ __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__
     const uint32_t st = col_start[c];
     const uint32_t m = col_start[c + 1] - st;
     uint32_t rep;
-    const uint32_t p = global_probe(colhash, crho, cval, col_start, table, tmask, c, h, st, m, &rep);
+    const uint32_t p = global_probe(colhash, crho, cval, col_start, table, tmask, max_probe, over, c, h, st, m, &rep);
     lglob[ls[u]] = p;
     lrep[ls[u]] = rep;
     const unsigned long long v = lmin[ls[u]];
@@ -601,34 +741,172 @@ __global__ __launch_bounds__(NT) void k_group_ids(const uint64_t* __restrict__ l
   nlen[j] = col_start[r + 1] - col_start[r];
 }
 
-__global__ __launch_bounds__(NT) void k_emit_n(const uint64_t* __restrict__ lslot, uint32_t bmax,
-                                               const uint32_t* __restrict__ d_beta,
-                                               const uint64_t* __restrict__ table, const uint32_t* __restrict__ col_start,
-                                               const uint32_t* __restrict__ npos, const uint32_t* __restrict__ crho,
-                                               const double* __restrict__ cval, int64_t* __restrict__ colptr,
-                                               int32_t* __restrict__ nrow, double* __restrict__ nval,
-                                               const uint32_t* __restrict__ d_nnz) {
-  const uint32_t j = blockIdx.x * NT + threadIdx.x;
+// The leader phase of a level in one workgroup (see launch_leaders).  The rank sort:
+// an element's place is the number of smaller keys, or equal ones at a lower index;
+// up to 53 key bits the key and the index share one word (key << 11 | index), so one
+// comparison decides.  Up to LD_NT leaders, P = 2^k threads share an element, each
+// counting over a part of the keys (LDS broadcasts), the parts added by LDS atomics.
+constexpr int LD_NT = 1024;
+constexpr int LD_PER = static_cast<int>(kLeaderListMax / LD_NT);  // columns per thread
+constexpr int LD_TPER = static_cast<int>(kLeaderTableMax / LD_NT);  // table slots per thread
+__device__ __forceinline__ void leaders_block(const LeaderArgs& a) {
+  __shared__ uint64_t ks[kSmallSortMax];
+  __shared__ uint32_t sl[kSmallSortMax];
+  __shared__ uint32_t rk[kSmallSortMax];
+  __shared__ uint32_t ln[kSmallSortMax];
+  __shared__ uint32_t red[LD_NT / 64];
+  const uint32_t t = threadIdx.x;
+  const uint64_t mask = (a.nbits >= 64) ? ~0ull : ((1ull << a.nbits) - 1ull);
+  const bool packed = a.nbits <= 53;
+  uint32_t n;
+  if (a.tscan) {
+    // thread t takes a contiguous run of at most LD_TPER slots, their entries and
+    // minima loaded together; the sort below orders the groups, so the list may
+    // follow slot order
+    const uint32_t per = (a.tsize + LD_NT - 1) / LD_NT;
+    const uint32_t b = min(a.tsize, t * per), e = min(a.tsize, b + per);
+    uint64_t tv[LD_TPER], mk[LD_TPER];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < LD_TPER; ++u) {
+      tv[u] = (b + u < e) ? a.table[b + u] : 0ull;
+      mk[u] = (b + u < e) ? a.slotmin[b + u] : 0ull;
+      cnt += tv[u] ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t pos = block_excl_scan_u32<LD_NT>(cnt, red, &tot);
+#pragma unroll
+    for (int u = 0; u < LD_TPER; ++u) {
+      if (!tv[u]) continue;
+      if (pos < a.cap) {
+        ks[pos] = mk[u] & mask;
+        sl[pos] = b + u;
+      }
+      ++pos;
+    }
+    n = tot;
+    if (t == 0) *a.d_beta = n;
+  } else if (a.isrep) {
+    // thread t takes a contiguous run of at most LD_PER columns, each step's loads
+    // for the whole run issued together (flags, then slots, then slot minima)
+    const uint32_t per = (a.ncols + LD_NT - 1) / LD_NT;
+    const uint32_t b = min(a.ncols, t * per), e = min(a.ncols, b + per);
+    uint32_t fl[LD_PER], sp[LD_PER];
+    uint64_t mk[LD_PER];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < LD_PER; ++u) {
+      fl[u] = (b + u < e) ? a.isrep[b + u] : 0u;
+      cnt += fl[u] ? 1u : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < LD_PER; ++u) sp[u] = fl[u] ? a.slot[b + u] : 0u;
+#pragma unroll
+    for (int u = 0; u < LD_PER; ++u) mk[u] = fl[u] ? a.slotmin[sp[u]] : 0ull;
+    uint32_t tot;
+    uint32_t pos = block_excl_scan_u32<LD_NT>(cnt, red, &tot);
+#pragma unroll
+    for (int u = 0; u < LD_PER; ++u) {
+      if (!fl[u]) continue;
+      a.reppos[b + u] = pos;
+      if (pos < a.cap) {
+        ks[pos] = mk[u] & mask;
+        sl[pos] = sp[u];
+      }
+      ++pos;
+    }
+    n = tot;
+    if (t == 0) *a.d_beta = n;
+  } else {
+    n = *a.d_beta;
+    const uint32_t nl = min(n, a.cap);
+    for (uint32_t i = t; i < nl; i += LD_NT) {
+      ks[i] = a.lkey[i] & mask;
+      sl[i] = static_cast<uint32_t>(a.lslot[i]);
+    }
+  }
+  if (n == 0 || n > a.cap) return;  // the same for every thread
+  __syncthreads();
+  for (uint32_t i = t; i < n; i += LD_NT) {
+    if (packed) ks[i] = (ks[i] << 11) | i;
+    rk[i] = 0u;
+  }
+  __syncthreads();
+  if (n <= static_cast<uint32_t>(LD_NT)) {
+    uint32_t P = 1;
+    while (P < static_cast<uint32_t>(LD_NT) && n * P * 2 <= static_cast<uint32_t>(LD_NT)) P *= 2;
+    const uint32_t i = t / P, part = t % P;
+    if (i < n) {
+      const uint32_t len = (n + P - 1) / P, j0 = min(n, part * len), j1 = min(n, j0 + len);
+      const uint64_t ki = ks[i];
+      uint32_t r = 0;
+#pragma unroll 8
+      for (uint32_t j = j0; j < j1; ++j) {
+        const uint64_t kj = ks[j];
+        r += (kj < ki || (!packed && kj == ki && j < i)) ? 1u : 0u;
+      }
+      if (P == 1)
+        rk[i] = r;
+      else if (r)
+        atomicAdd(&rk[i], r);
+    }
+  } else {
+    const uint32_t i0 = t, i1 = t + LD_NT;
+    const uint64_t k0 = ks[i0], k1 = i1 < n ? ks[i1] : ~0ull;
+    uint32_t r0 = 0, r1 = 0;
+#pragma unroll 8
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint64_t kj = ks[j];
+      r0 += (kj < k0 || (!packed && kj == k0 && j < i0)) ? 1u : 0u;
+      r1 += (kj < k1 || (!packed && kj == k1 && j < i1)) ? 1u : 0u;
+    }
+    rk[i0] = r0;
+    if (i1 < n) rk[i1] = r1;
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < n; i += LD_NT) {
+    const uint32_t r = rk[i], p = sl[i];
+    a.lss[r] = p;
+    a.slot_gid[p] = r;
+    const uint32_t rep = static_cast<uint32_t>(a.table[p] - 1);
+    ln[r] = a.col_start[rep + 1] - a.col_start[rep];
+  }
+  __syncthreads();
+  const uint32_t per = (n + LD_NT - 1) / LD_NT;
+  const uint32_t b = min(n, t * per), e = min(n, b + per);
+  uint32_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += ln[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan_u32<LD_NT>(sum, red, &tot);
+  for (uint32_t i = b; i < e; ++i) {
+    a.npos[i] = run;
+    run += ln[i];
+  }
+  if (t == 0) *a.d_nnz = tot;
+}
+__global__ __launch_bounds__(LD_NT) void k_leaders(LeaderArgs a) { leaders_block(a); }
+
+// N_k's column of group j.
+__device__ __forceinline__ void emit_n_group(const EmitArgs& a, uint32_t j) {
   // more groups than the launch covers (a speculative pass whose leader list was
   // capped): nothing is written, the pass is redone
-  if (*d_beta > bmax) return;
-  const uint32_t beta = *d_beta;
-  if (j == 0) colptr[beta] = *d_nnz;
+  if (*a.d_beta > a.bmax) return;
+  const uint32_t beta = *a.d_beta;
+  if (j == 0) a.colptr[beta] = *a.d_nnz;
   if (j >= beta) return;
-  const uint32_t p = static_cast<uint32_t>(lslot[j]);
-  const uint32_t r = static_cast<uint32_t>(table[p] - 1);
-  const uint32_t s0 = col_start[r], m = col_start[r + 1] - s0;
-  const uint32_t o = npos[j];
-  colptr[j] = o;
+  const uint32_t p = static_cast<uint32_t>(a.lss[j]);
+  const uint32_t r = static_cast<uint32_t>(a.table[p] - 1);
+  const uint32_t s0 = a.col_start[r], m = a.col_start[r + 1] - s0;
+  const uint32_t o = a.npos[j];
+  a.colptr[j] = o;
   for (uint32_t t = 0; t < m; ++t) {
-    nrow[o + t] = static_cast<int32_t>(crho[s0 + t]);
-    nval[o + t] = cval[s0 + t];
+    a.nrow[o + t] = static_cast<int32_t>(a.crho[s0 + t]);
+    a.nval[o + t] = a.cval[s0 + t];
   }
 }
 
-__global__ __launch_bounds__(NT) void k_emit_next(EmitArgs a, ModeInfo mi) {
-  const uint32_t c = blockIdx.x * NT + threadIdx.x;
-  if (c >= a.ncols) return;
+// Column c's entry of the next level (or of the last core).
+__device__ __forceinline__ void emit_next_col(const EmitArgs& a, const ModeInfo& mi, uint32_t c) {
   const uint32_t g = a.slot_gid[a.slot[c]];
   const uint64_t suf = a.colsuf[c];
   const double s = a.cols[c];
@@ -651,12 +929,23 @@ __global__ __launch_bounds__(NT) void k_emit_next(EmitArgs a, ModeInfo mi) {
   }
 }
 
+// The first nb_next workgroups take the columns (next level), the rest the groups (N_k).
+__global__ __launch_bounds__(NT) void k_emit(EmitArgs a, ModeInfo mi, uint32_t nb_next) {
+  if (blockIdx.x >= nb_next) {
+    emit_n_group(a, (blockIdx.x - nb_next) * NT + threadIdx.x);
+    return;
+  }
+  const uint32_t c = blockIdx.x * NT + threadIdx.x;
+  if (c < a.ncols) emit_next_col(a, mi, c);
+}
+
 }  // namespace
 
 void launch_ingest(const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi, uint64_t* keys,
                    uint64_t* vbits, DevStatus* st, hipStream_t s) {
   if (!nnz) return;
-  k_ingest<<<grid_for(nnz, NT), NT, 0, s>>>(idx, val, nnz, mi, keys, vbits, st);
+  const int vec4 = (mi.d % 4 == 0) && (reinterpret_cast<uintptr_t>(idx) % 16 == 0);
+  k_ingest<<<grid_for(nnz, NT), NT, 0, s>>>(idx, val, nnz, mi, keys, vbits, st, vec4);
   TTS_LAUNCH_CHECK();
 }
 
@@ -670,6 +959,13 @@ void launch_col_flags(const uint64_t* ekey, uint32_t nE, int sh, bool level1, in
 
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s) {
   k_norm_final<<<1, NF, 0, s>>>(part, np, st);
+  TTS_LAUNCH_CHECK();
+}
+
+void launch_columns_small(const uint64_t* ekey, uint32_t nE, int sh, int long_bit, uint32_t* col_start,
+                          uint32_t* d_ncols, DevStatus* st, hipStream_t s) {
+  if (nE == 0 || nE > kColsSmallMax) fail(TT_ERR_TOO_LARGE, "one-workgroup column pass beyond its capacity");
+  k_columns_small<<<1, CS_NT, 0, s>>>(ekey, nE, sh, long_bit, col_start, d_ncols, st);
   TTS_LAUNCH_CHECK();
 }
 
@@ -708,6 +1004,8 @@ void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, bool wide,
   KTimer kt("level_canon", s, 56.0 * a.ncols, 0.0);
   if (wide && !a.sort_rows)
     k_canon_wide<<<a.ncols, NT, 0, s>>>(a, mi);
+  else if (a.sort_rows && a.ncols <= kCanonWaveMax)
+    k_canon_wave<<<grid_for(a.ncols, CW_COLS), NT, 0, s>>>(a, mi);
   else
     k_canon<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
   TTS_LAUNCH_CHECK();
@@ -715,7 +1013,7 @@ void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, bool wide,
 
 void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* cval, const uint32_t* col_start,
                   const uint64_t* rmkey, uint32_t ncols, uint64_t* table, uint64_t* slotmin, uint32_t tmask,
-                  uint32_t* slot, uint32_t* isrep, hipStream_t s) {
+                  uint32_t max_probe, uint32_t* over, uint32_t* slot, uint32_t* isrep, hipStream_t s) {
   if (!ncols) return;
   // per column: read hash, start and row-major key, write slot and flag
   KTimer kt("level_group", s, 32.0 * ncols, 0.0);
@@ -724,7 +1022,7 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
     // enough for at least 256 workgroups (down to 256 columns)
 #define TTS_GROUP_LOCAL(CH)                                                                                      \
   k_group_local<CH><<<(ncols + (CH) - 1) / (CH), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, \
-                                                             slotmin, tmask, slot, isrep)
+                                                             slotmin, tmask, max_probe, over, slot, isrep)
     if (ncols >= 256u * 2048u)
       TTS_GROUP_LOCAL(2048);
     else if (ncols >= 256u * 1024u)
@@ -736,7 +1034,7 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
 #undef TTS_GROUP_LOCAL
   } else {
     k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
-                                               slot, isrep, 0);
+                                               max_probe, over, slot, isrep, 0);
   }
   TTS_LAUNCH_CHECK();
 }
@@ -756,17 +1054,17 @@ void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_
   TTS_LAUNCH_CHECK();
 }
 
-void launch_emit_n(const uint64_t* lslot_sorted, uint32_t bmax, const uint32_t* d_beta, const uint64_t* table,
-                   const uint32_t* col_start, const uint32_t* npos, const uint32_t* crho, const double* cval,
-                   int64_t* colptr, int32_t* nrow, double* nval, const uint32_t* d_nnz, hipStream_t s) {
-  k_emit_n<<<grid_for(bmax, NT), NT, 0, s>>>(lslot_sorted, bmax, d_beta, table, col_start, npos, crho, cval, colptr,
-                                             nrow, nval, d_nnz);
+void launch_leaders(const LeaderArgs& a, hipStream_t s) {
+  if (a.cap == 0) return;
+  if (a.cap > kSmallSortMax || (a.tscan && a.tsize > kLeaderTableMax) || (a.isrep && a.ncols > kLeaderListMax))
+    fail(TT_ERR_TOO_LARGE, "leader phase beyond its one-workgroup capacity");
+  k_leaders<<<1, LD_NT, 0, s>>>(a);
   TTS_LAUNCH_CHECK();
 }
 
-void launch_emit_next(const EmitArgs& a, const ModeInfo& mi, hipStream_t s) {
-  if (!a.ncols) return;
-  k_emit_next<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
+void launch_emit(const EmitArgs& a, const ModeInfo& mi, hipStream_t s) {
+  const uint32_t nb_next = a.ncols ? grid_for(a.ncols, NT) : 0u;
+  k_emit<<<nb_next + grid_for(a.bmax, NT), NT, 0, s>>>(a, mi, nb_next);
   TTS_LAUNCH_CHECK();
 }
 

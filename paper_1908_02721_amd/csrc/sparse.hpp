@@ -18,7 +18,7 @@ struct ModeInfo {
 // Small device-side status block, read back once or twice per level.
 struct DevStatus {
   uint32_t err;       // bit 0: index out of range, bit 1: non-finite, bit 2: duplicate
-  uint32_t pad0;
+  uint32_t table_over;  // a grouping table too small for its level (speculative pass)
   uint32_t ncols;     // columns of the current level
   uint32_t beta;      // groups of the current level
   uint32_t nnz_n;     // entries of N_k
@@ -29,6 +29,11 @@ struct DevStatus {
 
 constexpr uint32_t kErrIndex = 1u, kErrNonfinite = 2u, kErrDuplicate = 4u;
 constexpr int kMaxLocal = 32;  // longest column canonicalised from registers
+// levels of at most this many columns (rows not yet ordered) take one wave per column
+constexpr uint32_t kCanonWaveMax = 4096;
+// probes per column in a speculative pass's grouping table (at most a quarter full
+// while the speculation holds)
+constexpr uint32_t kSpecMaxProbe = 32;
 
 // a1: validate, drop zeros (key := ~0), pack keys; values copied as raw bits.
 void launch_ingest(const int32_t* idx, const double* val, uint32_t nnz, const ModeInfo& mi,
@@ -44,6 +49,11 @@ uint32_t norm_partials_count(uint32_t nE);
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s);
 void launch_col_starts(const uint32_t* flag, const uint32_t* pos, uint32_t nE, uint32_t* col_start,
                        const uint32_t* d_ncols, hipStream_t s);
+// The same three steps (flags, scan, starts) for a level k >= 2 of 1 .. kColsSmallMax
+// entries in one workgroup; the flags and places themselves are not kept.
+constexpr uint32_t kColsSmallMax = 16384;
+void launch_columns_small(const uint64_t* ekey, uint32_t nE, int sh, int long_bit, uint32_t* col_start,
+                          uint32_t* d_ncols, DevStatus* st, hipStream_t s);
 // Column counts of every level (counts[k], k = 1 .. d-1, zeroed beforehand) from the
 // sorted kept keys, and the duplicate flag; see k_level_counts.
 void launch_level_counts(const uint64_t* keys, uint32_t n, const ModeInfo& mi, uint32_t* counts, DevStatus* st,
@@ -85,11 +95,14 @@ struct CanonArgs {
 // order); otherwise one lane per column.
 void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus* st, bool wide, hipStream_t s);
 
-// a5: group identical canonical columns (open-addressing table with full-key
-// verification), leader = smallest row-major suffix key of each group.
+// a5: group identical canonical columns (open-addressing table of tmask + 1 slots with
+// full-key verification), leader = smallest row-major suffix key of each group.  A
+// column probes at most max_probe slots; one that finds neither its group nor an
+// empty slot sets *over (when given) and is left without a group.  A table with more
+// slots than columns and max_probe = its size never overflows.
 void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* cval, const uint32_t* col_start,
                   const uint64_t* rmkey, uint32_t ncols, uint64_t* table, uint64_t* slotmin, uint32_t tmask,
-                  uint32_t* slot, uint32_t* isrep, hipStream_t s);
+                  uint32_t max_probe, uint32_t* over, uint32_t* slot, uint32_t* isrep, hipStream_t s);
 // the leaders' (row-major key, slot) pairs at their group positions below cap
 void launch_rep_list(const uint32_t* isrep, const uint32_t* reppos, const uint32_t* slot, const uint64_t* slotmin,
                      uint32_t ncols, uint32_t cap, uint64_t* lkey, uint64_t* lslot, hipStream_t s);
@@ -100,11 +113,39 @@ void launch_group_ids(const uint64_t* lslot_sorted, uint32_t beta, const uint32_
                       const uint64_t* table, const uint32_t* col_start, uint32_t* slot_gid, uint32_t* nlen,
                       hipStream_t s);
 
-// a6: N_k in CSC (one canonical column per group, in group order); beta = *d_beta,
-// nnz(N_k) = *d_nnz; the launch covers bmax groups and writes nothing if beta > bmax.
-void launch_emit_n(const uint64_t* lslot_sorted, uint32_t bmax, const uint32_t* d_beta, const uint64_t* table,
-                   const uint32_t* col_start, const uint32_t* npos, const uint32_t* crho, const double* cval,
-                   int64_t* colptr, int32_t* nrow, double* nval, const uint32_t* d_nnz, hipStream_t s);
+// The leaders of at most cap (<= kSmallSortMax) groups in one workgroup: ordered by
+// row-major key (stable rank sort), numbered (slot_gid of each slot = its leader's
+// rank), and the lengths of their columns scanned into npos with the total in *d_nnz;
+// lss = the slots in group order.  The list is either given (lkey, lslot: beta =
+// *d_beta entries, as launch_rep_list writes them), or built here: from a table of
+// at most kLeaderTableMax slots (tscan: an occupied slot is a group, its minimum the
+// leader's key; the list in slot order, *d_beta written), or for at most
+// kLeaderListMax columns (isrep non-null) from the columns' flags, slots and slot
+// minima, with *d_beta and each representative's place reppos written too.  More
+// than cap groups: nothing written beyond *d_beta and reppos.
+constexpr uint32_t kLeaderListMax = 16384;
+constexpr uint32_t kLeaderTableMax = 8192;
+struct LeaderArgs {
+  int tscan;       // build the list from the table (tsize slots)
+  uint32_t tsize;
+  const uint32_t* isrep;  // non-null: build the list from the columns
+  uint32_t* reppos;
+  const uint32_t* slot;
+  const uint64_t* slotmin;
+  uint32_t ncols;
+  const uint64_t* lkey;  // else: the given list
+  const uint64_t* lslot;
+  uint32_t* d_beta;
+  uint32_t cap;
+  int nbits;  // key bits compared
+  const uint64_t* table;
+  const uint32_t* col_start;
+  uint64_t* lss;
+  uint32_t* slot_gid;
+  uint32_t* npos;
+  uint32_t* d_nnz;
+};
+void launch_leaders(const LeaderArgs& a, hipStream_t s);
 
 struct EmitArgs {
   uint32_t ncols;
@@ -124,8 +165,24 @@ struct EmitArgs {
   double* next_v;
   // last level: dense G^(d) [beta][n_d], zero-filled beforehand
   double* last_core;
+  // N_k: the groups' slots in group order (lss), their columns' places (npos)
+  const uint64_t* lss;
+  uint32_t bmax;  // groups the launch covers
+  const uint32_t* d_beta;
+  const uint32_t* d_nnz;
+  const uint64_t* table;
+  const uint32_t* col_start;
+  const uint32_t* npos;
+  const uint32_t* crho;
+  const double* cval;
+  int64_t* colptr;
+  int32_t* nrow;
+  double* nval;
 };
-// a7: transfer matrix -> next level's entries (or the last core).
-void launch_emit_next(const EmitArgs& a, const ModeInfo& mi, hipStream_t s);
+// a6 + a7 in one launch: N_k in CSC (one canonical column per group, in group order;
+// beta = *d_beta, nnz(N_k) = *d_nnz; nothing written if beta > bmax), and the
+// transfer matrix -> next level's entries (or the last core).
+void launch_emit(const EmitArgs& a, const ModeInfo& mi, hipStream_t s);
+
 
 }  // namespace tts

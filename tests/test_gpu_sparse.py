@@ -96,9 +96,9 @@ def test_long_columns_path(oracle_mod):
 
 
 def test_speculative_sizes_and_careful_redo():
-    """Level sizes are read once per call when its assumptions hold (no column longer
-    than 32 entries, at most 2048 groups where the column count allows more); inputs
-    that break them are redone with per-level read-backs.  The progress log
+    """Level sizes are read once per call when its assumptions hold (no explicit zero,
+    no column longer than 32 entries, at most 2048 groups where the column count allows
+    more); inputs that break them are redone with per-level read-backs.  The progress log
     (TTSPARSE_LOG=1, read once per process, hence a child process) says which."""
     import os
     import subprocess
@@ -122,6 +122,9 @@ def test_speculative_sizes_and_careful_redo():
         "run(synth.unravel(lin, dims), rng.integers(1, 3, lin.size).astype(float), dims, 'long')\n"
         "idx, val, dims = synth.random_sparse((30, 100, 100), 60000, 3)\n"
         "run(idx, val, dims, 'many groups')\n"
+        "idx, val, dims = synth.kronecker_sum(6, 10, 6, 3, seed=4)\n"
+        "val = val.copy(); val[::7] = 0.0\n"
+        "run(idx, val, dims, 'zeros')\n"
         "print('CASE end', file=sys.stderr, flush=True)\n" % root)
     env = dict(os.environ, TTSPARSE_LOG="1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
@@ -131,6 +134,9 @@ def test_speculative_sizes_and_careful_redo():
     assert "(sizes read once)" in blocks["kron"] and "redone carefully" not in blocks["kron"]
     assert "redone carefully" in blocks["long"]
     assert "redone carefully" in blocks["many groups"]
+    # about 10^4 groups on level 1: more than the speculative grouping table's slots
+    assert "grouping table overflowed" in blocks["many groups"]
+    assert "explicit zeros among the nonzeros); redone carefully" in blocks["zeros"]
 
 
 def test_wide_mode_and_unit_modes(oracle_mod):
