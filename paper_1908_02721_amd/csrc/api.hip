@@ -409,6 +409,16 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
     if (spec && !level1 && nE <= kColsSmallMax) {
       // small level of a speculative pass (never the long-column path): one workgroup
       launch_columns_small(ekey.get(), nE, sh, k - 1, col_start.get(), d_ncols, st.get(), s);
+    } else if (spec && starts_tiles(nE) <= kStartsMaxTiles) {
+      // a speculative pass needs no flag arrays (the long-column path is the careful
+      // pass's)
+      const uint32_t nt = starts_tiles(nE);
+      DBuf<uint32_t> part(al, nt);
+      DBuf<double> norm_part;
+      if (level1) norm_part.reset(al, nt);
+      launch_starts(ekey.get(), nE, sh, level1, level1 ? -1 : k - 1, evp, part.get(), norm_part.get(),
+                    col_start.get(), d_ncols, st.get(), s);
+      if (level1) launch_norm_final(norm_part.get(), nt, st.get(), s);
     } else {
       flag.reset(al, nE);
       pos.reset(al, nE);

@@ -203,6 +203,116 @@ __global__ __launch_bounds__(CS_NT) void k_columns_small(const uint64_t* __restr
   columns_small_block(ekey, nE, sh, long_bit, col_start, d_ncols, st);
 }
 
+// a3 without flag arrays (speculative pass): two launches over tiles of ST_TILE
+// entries, thread t of a tile owning ST_IPT consecutive entries.  The first counts
+// each tile's column starts (an entry whose suffix differs from its predecessor's;
+// on level 1 also the duplicate check and a fixed-order sum of squares per tile, on
+// later levels the long-column probe); the second recomputes the starts, adds the
+// counts of the tiles before its own (at most kStartsMaxTiles of them, each tile
+// summing them itself) and writes every start's column place.  Same col_start,
+// *d_ncols, duplicate and long-column flags as k_col_flags, the scan and k_col_starts.
+constexpr int ST_IPT = 16;
+constexpr uint32_t ST_TILE = NT * ST_IPT;
+static_assert(kStartsMaxTiles % NT == 0, "whole thread rounds of tile counts");
+// the suffixes of entries b .. b + ST_IPT - 1 (clamped loads) and of entry b - 1
+__device__ __forceinline__ void tile_suffixes(const uint64_t* __restrict__ ekey, uint32_t nE, int sh, uint32_t b,
+                                              uint64_t key[ST_IPT], uint64_t* before) {
+#pragma unroll
+  for (int u = 0; u < ST_IPT; ++u) key[u] = ekey[min(b + u, nE - 1)];
+  *before = b > 0 ? ekey[b - 1] : 0ull;
+}
+__device__ __forceinline__ uint32_t tile_starts(const uint64_t key[ST_IPT], uint64_t before, uint32_t b, uint32_t nE,
+                                                int sh) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int u = 0; u < ST_IPT; ++u) {
+    const uint64_t prev = u == 0 ? before : key[u > 0 ? u - 1 : 0];
+    const bool st = b + u < nE && (b + u == 0 || (prev >> sh) != (key[u] >> sh));
+    m |= st ? (1u << u) : 0u;
+  }
+  return m;
+}
+__global__ __launch_bounds__(NT) void k_starts_count(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,
+                                                     int level1, int long_bit, const double* __restrict__ ev,
+                                                     uint32_t* __restrict__ part, double* __restrict__ norm_part,
+                                                     DevStatus* st) {
+  __shared__ uint32_t red[NT / 64];
+  __shared__ double dred[NT / 64];
+  const uint32_t b = blockIdx.x * ST_TILE + threadIdx.x * ST_IPT;
+  uint64_t key[ST_IPT], before;
+  uint32_t m = 0;
+  double sq = 0.0;
+  if (b < nE) {
+    tile_suffixes(ekey, nE, sh, b, key, &before);
+    m = tile_starts(key, before, b, nE, sh);
+    if (level1) {
+      bool dup = false;
+#pragma unroll
+      for (int u = 0; u < ST_IPT; ++u) {
+        const uint64_t prev = u == 0 ? before : key[u > 0 ? u - 1 : 0];
+        dup = dup || (b + u < nE && b + u > 0 && prev == key[u]);
+        const double v = (b + u < nE) ? ev[b + u] : 0.0;
+        sq += v * v;
+      }
+      if (dup) atomicOr(&st->err, kErrDuplicate);
+    }
+    if (long_bit >= 0) {
+      // the column starting at e is longer than kMaxLocal exactly when entry
+      // e + kMaxLocal still belongs to it
+      bool lng = false;
+#pragma unroll
+      for (int u = 0; u < ST_IPT; ++u)
+        if (((m >> u) & 1u) && nE - (b + u) > static_cast<uint32_t>(kMaxLocal))
+          lng = lng || (ekey[b + u + kMaxLocal] >> sh) == (key[u] >> sh);
+      if (lng) atomicOr(&st->longmask, 1ull << long_bit);
+    }
+  }
+  uint32_t tot;
+  block_excl_scan_u32<NT>(static_cast<uint32_t>(__popc(m)), red, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (level1) {
+    sq = wave_sum_f64(sq);
+    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += dred[w];
+      norm_part[blockIdx.x] = s;
+    }
+  }
+}
+__global__ __launch_bounds__(NT) void k_starts_place(const uint64_t* __restrict__ ekey, uint32_t nE, int sh,
+                                                     const uint32_t* __restrict__ part, uint32_t* __restrict__ col_start,
+                                                     uint32_t* __restrict__ d_ncols) {
+  __shared__ uint32_t red[NT / 64];
+  const uint32_t tile = blockIdx.x;
+  constexpr int R = static_cast<int>(kStartsMaxTiles / NT);
+  uint32_t q = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t j = threadIdx.x + r * NT;
+    q += j < tile ? part[j] : 0u;
+  }
+  uint32_t prefix;
+  block_excl_scan_u32<NT>(q, red, &prefix);
+  const uint32_t b = tile * ST_TILE + threadIdx.x * ST_IPT;
+  uint32_t m = 0;
+  if (b < nE) {
+    uint64_t key[ST_IPT], before;
+    tile_suffixes(ekey, nE, sh, b, key, &before);
+    m = tile_starts(key, before, b, nE, sh);
+  }
+  uint32_t tot;
+  uint32_t run = prefix + block_excl_scan_u32<NT>(static_cast<uint32_t>(__popc(m)), red, &tot);
+#pragma unroll
+  for (int u = 0; u < ST_IPT; ++u)
+    if ((m >> u) & 1u) col_start[run++] = b + u;
+  if (threadIdx.x == 0 && tile == gridDim.x - 1) {
+    col_start[prefix + tot] = nE;
+    *d_ncols = prefix + tot;
+  }
+}
+
 // Column counts of every level from the globally sorted kept keys.  A level-k column
 // (k = 1 .. d-1) is a distinct suffix key >> off[k] (modes k .. d-1), so its count is
 // the number of positions where that suffix differs from the previous key's (the first
@@ -966,6 +1076,19 @@ void launch_columns_small(const uint64_t* ekey, uint32_t nE, int sh, int long_bi
                           uint32_t* d_ncols, DevStatus* st, hipStream_t s) {
   if (nE == 0 || nE > kColsSmallMax) fail(TT_ERR_TOO_LARGE, "one-workgroup column pass beyond its capacity");
   k_columns_small<<<1, CS_NT, 0, s>>>(ekey, nE, sh, long_bit, col_start, d_ncols, st);
+  TTS_LAUNCH_CHECK();
+}
+
+uint32_t starts_tiles(uint32_t nE) { return (nE + ST_TILE - 1) / ST_TILE; }
+
+void launch_starts(const uint64_t* ekey, uint32_t nE, int sh, bool level1, int long_bit, const double* ev,
+                   uint32_t* part, double* norm_part, uint32_t* col_start, uint32_t* d_ncols, DevStatus* st,
+                   hipStream_t s) {
+  const uint32_t nt = starts_tiles(nE);
+  if (nE == 0 || nt > kStartsMaxTiles) fail(TT_ERR_TOO_LARGE, "column pass beyond its tile count");
+  k_starts_count<<<nt, NT, 0, s>>>(ekey, nE, sh, level1 ? 1 : 0, long_bit, ev, part, norm_part, st);
+  TTS_LAUNCH_CHECK();
+  k_starts_place<<<nt, NT, 0, s>>>(ekey, nE, sh, part, col_start, d_ncols);
   TTS_LAUNCH_CHECK();
 }
 

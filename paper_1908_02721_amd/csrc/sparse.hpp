@@ -49,6 +49,15 @@ uint32_t norm_partials_count(uint32_t nE);
 void launch_norm_final(const double* part, uint32_t np, DevStatus* st, hipStream_t s);
 void launch_col_starts(const uint32_t* flag, const uint32_t* pos, uint32_t nE, uint32_t* col_start,
                        const uint32_t* d_ncols, hipStream_t s);
+// The same three steps in two launches without flag arrays (tiles of 4096 entries, at
+// most kStartsMaxTiles of them), with level 1's duplicate check and per-tile sums of
+// squares into norm_part[starts_tiles(nE)] (level1), or the long-column bit
+// (long_bit >= 0); part holds starts_tiles(nE) words.
+constexpr uint32_t kStartsMaxTiles = 4096;
+uint32_t starts_tiles(uint32_t nE);
+void launch_starts(const uint64_t* ekey, uint32_t nE, int sh, bool level1, int long_bit, const double* ev,
+                   uint32_t* part, double* norm_part, uint32_t* col_start, uint32_t* d_ncols, DevStatus* st,
+                   hipStream_t s);
 // The same three steps (flags, scan, starts) for a level k >= 2 of 1 .. kColsSmallMax
 // entries in one workgroup; the flags and places themselves are not kept.
 constexpr uint32_t kColsSmallMax = 16384;
