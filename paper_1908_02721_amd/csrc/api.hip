@@ -369,13 +369,17 @@ bool sparse_stage_pass(tt_result_s* R, const int32_t* idx, const double* val, ui
   std::vector<uint32_t> ncols_h(d + 1, 0);
   DBuf<uint32_t> lv(al, 4 * static_cast<size_t>(d));  // per level: columns, beta, nnz(N_k)
   if (spec) {
-    DBuf<uint32_t> cnt(al, static_cast<size_t>(d) + 1);
-    TTS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(uint32_t) * (d + 1), s));
+    const size_t nc = (static_cast<size_t>(d) + 1) * kLevelCountCopies;
+    DBuf<uint32_t> cnt(al, nc);
+    TTS_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(uint32_t) * nc, s));
     launch_level_counts(keys.get(), kept, mi, cnt.get(), st.get(), s);
+    std::vector<uint32_t> cnt_h(nc, 0);
     Readback rb(s);
-    rb.add(ncols_h.data(), cnt.get(), sizeof(uint32_t) * (d + 1));
+    rb.add(cnt_h.data(), cnt.get(), sizeof(uint32_t) * nc);
     rb.add(host_status(), st.get(), sizeof(DevStatus));
     rb.sync();
+    for (int k = 0; k <= d; ++k)
+      for (uint32_t c = 0; c < kLevelCountCopies; ++c) ncols_h[k] += cnt_h[k * kLevelCountCopies + c];
     const DevStatus* h = host_status();
     if (h->err & kErrIndex) fail(TT_ERR_INDEX, "a coordinate is outside its mode range");
     if (h->err & kErrNonfinite) fail(TT_ERR_NONFINITE, "a value is NaN or infinite");

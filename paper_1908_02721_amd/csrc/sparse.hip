@@ -371,7 +371,9 @@ __global__ __launch_bounds__(NT) void k_level_counts(const uint64_t* __restrict_
     if (k < mi.d) {
       uint32_t t = 0;
       for (int q = 0; q < NT / 64; ++q) t += red[q][threadIdx.x];
-      atomicAdd(&counts[k], t);
+      // kLevelCountCopies copies of each count, so that the workgroups' adds do not
+      // all queue on one address
+      atomicAdd(&counts[static_cast<size_t>(k) * kLevelCountCopies + blockIdx.x % kLevelCountCopies], t);
     }
   }
 }
@@ -864,6 +866,7 @@ __device__ __forceinline__ void leaders_block(const LeaderArgs& a) {
   __shared__ uint32_t sl[kSmallSortMax];
   __shared__ uint32_t rk[kSmallSortMax];
   __shared__ uint32_t ln[kSmallSortMax];
+  __shared__ uint32_t rp[kSmallSortMax];  // representative column (list from the table)
   __shared__ uint32_t red[LD_NT / 64];
   const uint32_t t = threadIdx.x;
   const uint64_t mask = (a.nbits >= 64) ? ~0ull : ((1ull << a.nbits) - 1ull);
@@ -891,6 +894,7 @@ __device__ __forceinline__ void leaders_block(const LeaderArgs& a) {
       if (pos < a.cap) {
         ks[pos] = mk[u] & mask;
         sl[pos] = b + u;
+        rp[pos] = static_cast<uint32_t>(tv[u] - 1);
       }
       ++pos;
     }
@@ -978,7 +982,7 @@ __device__ __forceinline__ void leaders_block(const LeaderArgs& a) {
     const uint32_t r = rk[i], p = sl[i];
     a.lss[r] = p;
     a.slot_gid[p] = r;
-    const uint32_t rep = static_cast<uint32_t>(a.table[p] - 1);
+    const uint32_t rep = a.tscan ? rp[i] : static_cast<uint32_t>(a.table[p] - 1);
     ln[r] = a.col_start[rep + 1] - a.col_start[rep];
   }
   __syncthreads();

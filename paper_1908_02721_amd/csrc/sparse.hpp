@@ -63,8 +63,11 @@ void launch_starts(const uint64_t* ekey, uint32_t nE, int sh, bool level1, int l
 constexpr uint32_t kColsSmallMax = 16384;
 void launch_columns_small(const uint64_t* ekey, uint32_t nE, int sh, int long_bit, uint32_t* col_start,
                           uint32_t* d_ncols, DevStatus* st, hipStream_t s);
-// Column counts of every level (counts[k], k = 1 .. d-1, zeroed beforehand) from the
-// sorted kept keys, and the duplicate flag; see k_level_counts.
+// Column counts of every level from the sorted kept keys, and the duplicate flag; see
+// k_level_counts.  Level k's count is the sum of counts[k * kLevelCountCopies + c],
+// c < kLevelCountCopies (k = 1 .. d-1, all (d + 1) * kLevelCountCopies words zeroed
+// beforehand).
+constexpr uint32_t kLevelCountCopies = 32;
 void launch_level_counts(const uint64_t* keys, uint32_t n, const ModeInfo& mi, uint32_t* counts, DevStatus* st,
                          hipStream_t s);
 
