@@ -746,22 +746,24 @@ __device__ __forceinline__ uint32_t global_probe(const uint64_t* __restrict__ co
 // group's minimum goes to memory once per chunk.  Same slots, representatives and
 // minima as k_group.
 // The chunk is GL_CH columns (a power of two, 256 to 2048), chosen per level so that
-// the grid has at least 256 workgroups where the level allows.
-template <int GL_CH>
-__global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__ colhash,
+// the grid has at least 256 workgroups where the level allows, taken by GL_NT threads
+// (up to 1024): a thread's columns are handled one after another, each a chain of
+// dependent loads, so the more threads the shorter the chain.
+template <int GL_CH, int GL_NT>
+__global__ __launch_bounds__(GL_NT) void k_group_local(const uint64_t* __restrict__ colhash,
                                                     const uint32_t* __restrict__ crho, const double* __restrict__ cval,
                                                     const uint32_t* __restrict__ col_start,
                                                     const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
                                                     uint64_t* slotmin, uint32_t tmask, uint32_t max_probe,
                                                     uint32_t* over, uint32_t* __restrict__ slot,
                                                     uint32_t* __restrict__ isrep) {
-  constexpr int GL_TL = 2 * GL_CH, GL_PT = GL_CH / NT;
-  static_assert(GL_CH % NT == 0 && (GL_CH & (GL_CH - 1)) == 0, "chunk of whole thread rounds, a power of two");
+  constexpr int GL_TL = 2 * GL_CH, GL_PT = GL_CH / GL_NT;
+  static_assert(GL_CH % GL_NT == 0 && (GL_CH & (GL_CH - 1)) == 0, "chunk of whole thread rounds, a power of two");
   __shared__ uint32_t ltab[GL_TL];   // chunk-local representative + 1, 0 = empty
   __shared__ uint32_t lglob[GL_TL];  // global slot of the local group
   __shared__ uint32_t lrep[GL_TL];   // its representative is the global one
   __shared__ unsigned long long lmin[GL_TL];
-  for (int e = threadIdx.x; e < GL_TL; e += NT) {
+  for (int e = threadIdx.x; e < GL_TL; e += GL_NT) {
     ltab[e] = 0u;
     lmin[e] = ~0ull;
   }
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__
   uint32_t ls[GL_PT];
   // local grouping
   for (int u = 0; u < GL_PT; ++u) {
-    const uint32_t c = c0 + threadIdx.x + u * NT;
+    const uint32_t c = c0 + threadIdx.x + u * GL_NT;
     ls[u] = 0xffffffffu;
     if (c >= ncols) continue;
     const uint64_t h = colhash[c];
@@ -797,7 +799,7 @@ __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__
   __syncthreads();
   // one global probe per chunk-local group (by its local representative)
   for (int u = 0; u < GL_PT; ++u) {
-    const uint32_t c = c0 + threadIdx.x + u * NT;
+    const uint32_t c = c0 + threadIdx.x + u * GL_NT;
     if (ls[u] == 0xffffffffu || ltab[ls[u]] != c + 1u) continue;
     const uint64_t h = colhash[c];
     const uint32_t st = col_start[c];
@@ -812,7 +814,7 @@ __global__ __launch_bounds__(NT) void k_group_local(const uint64_t* __restrict__
   }
   __syncthreads();
   for (int u = 0; u < GL_PT; ++u) {
-    const uint32_t c = c0 + threadIdx.x + u * NT;
+    const uint32_t c = c0 + threadIdx.x + u * GL_NT;
     if (ls[u] == 0xffffffffu) continue;
     slot[c] = lglob[ls[u]];
     isrep[c] = (ltab[ls[u]] == c + 1u) ? lrep[ls[u]] : 0u;
@@ -1147,9 +1149,9 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
   if (ncols >= 16384) {
     // large levels: chunk-local grouping first (see k_group_local), with chunks small
     // enough for at least 256 workgroups (down to 256 columns)
-#define TTS_GROUP_LOCAL(CH)                                                                                      \
-  k_group_local<CH><<<(ncols + (CH) - 1) / (CH), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, \
-                                                             slotmin, tmask, max_probe, over, slot, isrep)
+#define TTS_GROUP_LOCAL(CH)                                                                                    \
+  k_group_local<CH, ((CH) < 1024 ? (CH) : 1024)><<<(ncols + (CH) - 1) / (CH), ((CH) < 1024 ? (CH) : 1024), 0, s>>>( \
+      colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask, max_probe, over, slot, isrep)
     if (ncols >= 256u * 2048u)
       TTS_GROUP_LOCAL(2048);
     else if (ncols >= 256u * 1024u)
