@@ -494,6 +494,9 @@ __device__ __forceinline__ void canon_rows(const CanonArgs& a, bool active, uint
   *hs = h;
 }
 
+// SORT: the rows of a column are not yet ordered (a.sort_rows); the two forms are
+// separate kernels so that the ordered one keeps few registers (more waves per CU).
+template <bool SORT>
 __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
   clear_table(a, c, gridDim.x * NT);
@@ -502,7 +505,7 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   const uint32_t m = active ? a.col_start[c + 1] - st : 0;
   uint64_t hs = 0;
   double s = 0.0;
-  if (!a.sort_rows) {
+  if constexpr (!SORT) {
     // rows already ascending: eight entries at a time, each group's loads issued
     // together (clamped addresses)
     if (active) {
@@ -1135,8 +1138,10 @@ void launch_canon(const CanonArgs& a, const ModeInfo& mi, DevStatus*, bool wide,
     k_canon_wide<<<a.ncols, NT, 0, s>>>(a, mi);
   else if (a.sort_rows && a.ncols <= kCanonWaveMax)
     k_canon_wave<<<grid_for(a.ncols, CW_COLS), NT, 0, s>>>(a, mi);
+  else if (a.sort_rows)
+    k_canon<true><<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
   else
-    k_canon<<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
+    k_canon<false><<<grid_for(a.ncols, NT), NT, 0, s>>>(a, mi);
   TTS_LAUNCH_CHECK();
 }
 
