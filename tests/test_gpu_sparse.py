@@ -125,6 +125,10 @@ def test_speculative_sizes_and_careful_redo():
         "idx, val, dims = synth.kronecker_sum(6, 10, 6, 3, seed=4)\n"
         "val = val.copy(); val[::7] = 0.0\n"
         "run(idx, val, dims, 'zeros')\n"
+        "rng = np.random.Generator(np.random.PCG64(23))\n"
+        "dims = (2, 64, 300)\n"
+        "lin = rng.choice(int(np.prod(dims)), 30000, replace=False)\n"
+        "run(synth.unravel(lin, dims), np.ones(lin.size), dims, 'long large')\n"
         "print('CASE end', file=sys.stderr, flush=True)\n" % root)
     env = dict(os.environ, TTSPARSE_LOG="1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
@@ -137,6 +141,18 @@ def test_speculative_sizes_and_careful_redo():
     # about 10^4 groups on level 1: more than the speculative grouping table's slots
     assert "grouping table overflowed" in blocks["many groups"]
     assert "explicit zeros among the nonzeros); redone carefully" in blocks["zeros"]
+    # level 2 of more than 16384 entries (the tiled column pass) with columns of ~60
+    assert "redone carefully" in blocks["long large"] and "overflowed" not in blocks["long large"]
+
+
+def test_long_columns_on_a_large_level(oracle_mod):
+    # level 2 holds more than 16384 entries (the speculative pass's tiled column pass)
+    # and columns of about 60 entries, with few groups on level 1 (equal values): the
+    # long columns are found there and the level is redone carefully, bit-exact
+    rng = np.random.Generator(np.random.PCG64(23))
+    dims = (2, 64, 300)
+    lin = rng.choice(int(np.prod(dims)), 30000, replace=False)
+    check_sparse_parity(oracle_mod, synth.unravel(lin, dims), np.ones(lin.size), dims, "long columns, large level")
 
 
 def test_wide_mode_and_unit_modes(oracle_mod):
