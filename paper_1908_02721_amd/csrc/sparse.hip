@@ -494,6 +494,7 @@ __device__ __forceinline__ void canon_rows(const CanonArgs& a, bool active, uint
   *hs = h;
 }
 
+constexpr uint32_t CN_STAGE = 512;  // entries of a wave's columns staged in LDS
 // SORT: the rows of a column are not yet ordered (a.sort_rows); the two forms are
 // separate kernels so that the ordered one keeps few registers (more waves per CU).
 template <bool SORT>
@@ -506,9 +507,43 @@ __global__ __launch_bounds__(NT) void k_canon(CanonArgs a, ModeInfo mi) {
   uint64_t hs = 0;
   double s = 0.0;
   if constexpr (!SORT) {
-    // rows already ascending: eight entries at a time, each group's loads issued
-    // together (clamped addresses)
-    if (active) {
+    // Rows already ascending.  A wave's 64 columns are consecutive, so their entries
+    // are one contiguous range: when every wave's range of the workgroup fits
+    // CN_STAGE entries it is staged through LDS (coalesced loads, each lane then
+    // works on its own column there, coalesced stores); otherwise each lane reads its
+    // column eight entries at a time (clamped addresses, loads issued together).
+    __shared__ uint32_t srho[NT / 64][CN_STAGE];
+    __shared__ double sval[NT / 64][CN_STAGE];
+    __shared__ int fits;
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t cw0 = min(blockIdx.x * NT + w * 64, a.ncols), cw1 = min(cw0 + 64, a.ncols);
+    const uint32_t e0 = cw0 < cw1 ? a.col_start[cw0] : 0u, e1 = cw0 < cw1 ? a.col_start[cw1] : 0u;
+    if (threadIdx.x == 0) fits = 1;
+    __syncthreads();
+    if (lane == 0 && e1 - e0 > CN_STAGE) fits = 0;
+    __syncthreads();
+    if (fits) {
+      for (uint32_t j = lane; j < e1 - e0; j += 64) {
+        const uint32_t e = e0 + j;
+        srho[w][j] = a.erho ? a.erho[e] : static_cast<uint32_t>(a.ekey[e] & a.rho_mask);
+        sval[w][j] = a.ev[e];
+      }
+      __syncthreads();
+      if (active) {
+        const uint32_t o = st - e0;
+        s = sval[w][o];
+        for (uint32_t j = 0; j < m; ++j) {
+          const double cv = canon_value(sval[w][o + j], s, a.snap);
+          sval[w][o + j] = cv;  // this lane's own entries
+          hs += col_hash_term(j, srho[w][o + j], cv);
+        }
+      }
+      __syncthreads();
+      for (uint32_t j = lane; j < e1 - e0; j += 64) {
+        a.crho[e0 + j] = srho[w][j];
+        a.cval[e0 + j] = sval[w][j];
+      }
+    } else if (active) {
       s = a.ev[st];
       for (uint32_t j0 = 0; j0 < m; j0 += 8) {
         uint32_t rr[8];
