@@ -1053,9 +1053,23 @@ __device__ __forceinline__ void emit_n_group(const EmitArgs& a, uint32_t j) {
   const uint32_t s0 = a.col_start[r], m = a.col_start[r + 1] - s0;
   const uint32_t o = a.npos[j];
   a.colptr[j] = o;
-  for (uint32_t t = 0; t < m; ++t) {
-    a.nrow[o + t] = static_cast<int32_t>(a.crho[s0 + t]);
-    a.nval[o + t] = a.cval[s0 + t];
+  // eight entries at a time, each group's loads issued together (clamped addresses;
+  // a column has at least one entry)
+  for (uint32_t t0 = 0; t0 < m; t0 += 8) {
+    uint32_t rr[8];
+    double vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t t = min(t0 + u, m - 1);
+      rr[u] = a.crho[s0 + t];
+      vv[u] = a.cval[s0 + t];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (t0 + u < m) {
+        a.nrow[o + t0 + u] = static_cast<int32_t>(rr[u]);
+        a.nval[o + t0 + u] = vv[u];
+      }
   }
 }
 
