@@ -683,7 +683,7 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
                                               const uint64_t* __restrict__ rmkey, uint32_t ncols, uint64_t* table,
                                               uint64_t* slotmin, uint32_t tmask, uint32_t max_probe,
                                               uint32_t* over, uint32_t* __restrict__ slot,
-                                              uint32_t* __restrict__ isrep, int aggregate) {
+                                              uint32_t* __restrict__ isrep) {
   const uint32_t c = blockIdx.x * NT + threadIdx.x;
   const bool active = c < ncols;
   const uint64_t h = active ? colhash[c] : 0;
@@ -718,32 +718,12 @@ __global__ __launch_bounds__(NT) void k_group(const uint64_t* __restrict__ colha
     slot[c] = p;
     isrep[c] = rep;
   }
-  // Group leader = smallest row-major key.  On large levels parallel columns share a
-  // few slots (a level can put 10^4 columns into one group), so the lanes of a wave
-  // first take the minimum per slot among themselves and one lane per slot updates
-  // memory; on small levels every lane updates its own slot.
+  // Group leader = smallest row-major key (this kernel serves the levels of fewer
+  // than 16384 columns; larger ones take k_group_local, which takes the minimum per
+  // chunk first)
   const uint64_t rk = active ? rmkey[c] : ~0ull;
-  if (!aggregate) {
-    if (active && rk < __hip_atomic_load(&slotmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p]), static_cast<unsigned long long>(rk));
-    return;
-  }
-  const unsigned lane = threadIdx.x & 63;
-  uint64_t todo = __ballot(active);
-  while (todo) {
-    const int lead = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-    const uint32_t p0 = __shfl(p, lead, 64);
-    const bool mine = active && p == p0;
-    todo &= ~__ballot(mine);
-    uint64_t v = mine ? rk : ~0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint64_t w = __shfl_xor(v, o, 64);
-      v = w < v ? w : v;
-    }
-    if (static_cast<int>(lane) == lead &&
-        v < __hip_atomic_load(&slotmin[p0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p0]), static_cast<unsigned long long>(v));
-  }
+  if (active && rk < __hip_atomic_load(&slotmin[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMin(reinterpret_cast<unsigned long long*>(&slotmin[p]), static_cast<unsigned long long>(rk));
 }
 
 // Probe of the global table for column c (hash h, m entries from st): returns the
@@ -1217,7 +1197,7 @@ void launch_group(const uint64_t* colhash, const uint32_t* crho, const double* c
 #undef TTS_GROUP_LOCAL
   } else {
     k_group<<<grid_for(ncols, NT), NT, 0, s>>>(colhash, crho, cval, col_start, rmkey, ncols, table, slotmin, tmask,
-                                               max_probe, over, slot, isrep, 0);
+                                               max_probe, over, slot, isrep);
   }
   TTS_LAUNCH_CHECK();
 }
