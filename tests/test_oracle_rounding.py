@@ -212,3 +212,21 @@ def test_known_spectrum_of_orthogonal_terms(oracle_mod, kappa):
         s = np.asarray(res.sigma[b])
         assert np.max(np.abs(s[:T] - expect)) <= 1e-14 * res.norm, b
         assert np.all(s[T:] <= 1e-14 * res.norm)
+
+
+@pytest.mark.parametrize("case", ["kron", "random"])
+def test_sign_rule_gauge_of_the_rounded_cores(oracle_mod, case):
+    # The right-to-left SVD sweep leaves core k (k >= 2) as U^T of its bond's SVD, so
+    # the rows of unfold_1(core k) are the kept left singular vectors: orthonormal, and
+    # each with its entry of largest magnitude positive (the SVD gauge; it pins the
+    # sign choice, which the represented tensor does not see).
+    if case == "kron":
+        idx, val, dims = synth.kronecker_sum(5, 8, 6, 3, seed=2)
+    else:
+        idx, val, dims = synth.random_sparse((6, 7, 5, 6), 400, 11)
+    res = oracle_mod.decompose(idx, val, dims, 1e-10)
+    for k, core in enumerate(res.cores[1:], start=2):
+        u = core.reshape(core.shape[0], -1)
+        assert np.allclose(u @ u.T, np.eye(u.shape[0]), atol=1e-12), k
+        top = u[np.arange(u.shape[0]), np.argmax(np.abs(u), axis=1)]
+        assert np.all(top > 0), (k, top)
