@@ -161,3 +161,37 @@ def test_dynamic_thresholds_at_p_d_match_dense_ttsvd(dims, nnz, seed):
         dy = ftt.decompose(idx, val, dims, eps, p=len(dims), dynamic_delta=True)
         ranks, _ = _brute.tt_svd_right_to_left(A, eps, dynamic=True)
         assert dy.ranks == ranks
+
+
+def test_exact_tt_numbering_worked_example():
+    # Alg 5 keeps each nonzero row of a quasi-permutation matrix once, numbered by
+    # increasing row index: a prefix's bond index is its rank among the distinct
+    # prefixes (lexicographic), a suffix's its rank among the distinct suffixes with
+    # its first mode most significant.  Three nonzeros of a 2 x 3 x 3 tensor, the
+    # expected cores written out by hand from that rule.
+    idx = np.array([[0, 1, 2], [1, 0, 0], [0, 2, 2]], dtype=np.int32)
+    val = np.array([3.0, -5.0, 7.0])
+    dims = (2, 3, 3)
+    # p = 2: prefixes (i_1) = {0, 1} -> ids 0, 1; suffixes (i_3) = {0, 2} -> ids 0, 1
+    ex = ftt.exact_tt(idx, val, dims, 2)
+    assert ex.ranks == [1, 2, 2, 1]
+    g1 = np.zeros((1, 2, 2)); g1[0, 0, 0] = g1[0, 1, 1] = 1.0
+    g2 = np.zeros((2, 3, 2)); g2[0, 1, 1] = 3.0; g2[1, 0, 0] = -5.0; g2[0, 2, 1] = 7.0
+    g3 = np.zeros((2, 3, 1)); g3[0, 0, 0] = g3[1, 2, 0] = 1.0
+    for got, want in zip(ex.cores, (g1, g2, g3)):
+        assert np.array_equal(got, want)
+    # p = 3: prefixes (i_1, i_2) = (0,1), (0,2), (1,0) -> ids 0, 1, 2
+    ex = ftt.exact_tt(idx, val, dims, 3)
+    assert ex.ranks == [1, 2, 3, 1]
+    g2 = np.zeros((2, 3, 3)); g2[0, 1, 0] = g2[0, 2, 1] = g2[1, 0, 2] = 1.0
+    g3 = np.zeros((3, 3, 1)); g3[0, 2, 0] = 3.0; g3[1, 2, 0] = 7.0; g3[2, 0, 0] = -5.0
+    for got, want in zip(ex.cores, (g1, g2, g3)):
+        assert np.array_equal(got, want)
+    # p = 1: suffixes (i_2, i_3) = (0,0), (1,2), (2,2) -> ids 0, 1, 2; (i_3) as above
+    ex = ftt.exact_tt(idx, val, dims, 1)
+    assert ex.ranks == [1, 3, 2, 1]
+    h1 = np.zeros((1, 2, 3)); h1[0, 0, 1] = 3.0; h1[0, 1, 0] = -5.0; h1[0, 0, 2] = 7.0
+    h2 = np.zeros((3, 3, 2)); h2[0, 0, 0] = h2[1, 1, 1] = h2[2, 2, 1] = 1.0
+    h3 = np.zeros((2, 3, 1)); h3[0, 0, 0] = h3[1, 2, 0] = 1.0
+    for got, want in zip(ex.cores, (h1, h2, h3)):
+        assert np.array_equal(got, want)
